@@ -1,0 +1,260 @@
+"""Serial FP64 reference (oracle) for the batched LHEVI column solve.
+
+TEST INFRASTRUCTURE ONLY: the tests, ``__graft_entry__.smoke()`` and the CPU
+baseline leg of ``bench.py`` are the only callers.  The product path
+(``paper_2311_11425_amd``) never imports this package, and this package imports
+nothing from the product.
+
+The arithmetic lives in ``hevi_oracle.c`` (plain C, built with gcc into
+``libhevi_oracle.so`` next to this file); this module only marshals numpy
+arrays.  Array layout matches the batched convention used throughout: a per-node
+field is ``[k][c]`` (column index fastest), a state vector ``[v][k][c]`` with
+``v = (rho, rho u, rho v, rho w, rho theta)``, ``grad(zeta)`` is ``[m][k][c]``.
+
+Parity status per function is documented in ``hevi_oracle.c``; every function
+has at least one pin in ``tests/test_oracle_pins.py``.  The ARK tableaux in
+``oracle/tableaux.py`` are pinned only by their order conditions and the
+observed convergence order (the coefficients of the third-order method are not
+printed in the paper): "parity unpinned" by the paper itself for those numbers.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "hevi_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "libhevi_oracle.so")
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, no BLAS) into libhevi_oracle.so."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-shared", "-fPIC", "-pthread",
+               _SRC, "-o", tmp, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB_PATH)
+        lib.ho_gll.argtypes = [ctypes.c_int, _dp, _dp, _dp]
+        lib.ho_gll.restype = ctypes.c_int
+        lib.ho_reference.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double, _dp, _dp]
+        lib.ho_reference.restype = None
+        lib.ho_assemble_L.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp, _dp,
+                                      _dp, _dp, ctypes.c_int, ctypes.c_int, _dp]
+        lib.ho_assemble_L.restype = ctypes.c_int
+        lib.ho_bc_project.argtypes = [ctypes.c_int, _dp, _dp]
+        lib.ho_bc_project.restype = None
+        lib.ho_form_A.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp]
+        lib.ho_form_A.restype = None
+        lib.ho_lu_factor.argtypes = [ctypes.c_int, _dp, ctypes.POINTER(ctypes.c_int)]
+        lib.ho_lu_factor.restype = ctypes.c_int
+        lib.ho_lu_solve.argtypes = [ctypes.c_int, _dp, ctypes.POINTER(ctypes.c_int), _dp, _dp]
+        lib.ho_lu_solve.restype = None
+        lib.ho_solve_refined.argtypes = [ctypes.c_int, _dp, _dp, ctypes.POINTER(ctypes.c_int),
+                                         _dp, _dp, ctypes.c_int, _dp]
+        lib.ho_solve_refined.restype = None
+        common = [ctypes.c_int, ctypes.c_int, ctypes.c_long, ctypes.c_int, _dp, _dp, _dp, _dp, _dp,
+                  _dp]
+        lib.ho_solve_batch.argtypes = common + [ctypes.c_double, _dp, _dp, ctypes.c_int,
+                                                ctypes.c_int, ctypes.POINTER(ctypes.c_long)]
+        lib.ho_solve_batch.restype = ctypes.c_int
+        lib.ho_apply_batch.argtypes = common + [_dp, _dp, _dp, ctypes.c_int,
+                                                ctypes.POINTER(ctypes.c_long)]
+        lib.ho_apply_batch.restype = ctypes.c_int
+        lib.ho_ark_step_batch.argtypes = common + [ctypes.c_int, _dp, _dp, _dp, ctypes.c_double,
+                                                   ctypes.c_double, _dp, _dp, _dp, _dp, _dp,
+                                                   ctypes.c_int,
+                                                   ctypes.c_int, ctypes.POINTER(ctypes.c_long)]
+        lib.ho_ark_step_batch.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(_dp) if a is not None else None
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# --------------------------------------------------------------------------
+# small per-column building blocks (Sec. 3, Appendix A)
+
+def gll(N: int):
+    """GLL nodes, weights and D[i, j] = h_j'(xi_i) for order N."""
+    lib = _load()
+    xi = np.zeros(N + 1)
+    w = np.zeros(N + 1)
+    D = np.zeros((N + 1, N + 1))
+    if lib.ho_gll(N, _p(xi), _p(w), _p(D)) != 0:
+        raise ValueError("order out of range")
+    return xi, w, D
+
+
+def reference(rho0, Theta0, consts):
+    """theta0 and c_Theta = dP/dTheta from the set-2C equation of state."""
+    lib = _load()
+    rho0 = _f64(rho0)
+    Theta0 = _f64(Theta0)
+    th = np.zeros_like(rho0)
+    cT = np.zeros_like(rho0)
+    R, cp, g, pA = consts
+    lib.ho_reference(rho0.size, _p(rho0), _p(Theta0), R, cp, pA, _p(th), _p(cT))
+    return th, cT
+
+
+def assemble_L(N, Ne, g, z, J, gz_k3, theta0, cTheta, rho_weak=True, theta_weak=False):
+    """Dense L_z of ONE column.  gz_k3 is [k][3]; returns (5nz x 5nz)."""
+    lib = _load()
+    nz = Ne * N + 1
+    L = np.zeros((5 * nz, 5 * nz))
+    args = [_f64(a) for a in (z, J, gz_k3, theta0, cTheta)]
+    rc = lib.ho_assemble_L(N, Ne, g, *[_p(a) for a in args], int(rho_weak), int(theta_weak),
+                           _p(L))
+    if rc:
+        raise ValueError("assemble failed")
+    return L
+
+
+def column_L(N, Ne, consts, z, J, gz_k3, rho0, Theta0, rho_weak=True, theta_weak=False):
+    th, cT = reference(rho0, Theta0, consts)
+    return assemble_L(N, Ne, consts[2], z, J, gz_k3, th, cT, rho_weak, theta_weak)
+
+
+def bc_project(nz, gz_k3, b):
+    lib = _load()
+    b = _f64(b).copy()
+    lib.ho_bc_project(nz, _p(_f64(gz_k3)), _p(b))
+    return b
+
+
+def form_A(L, lam):
+    lib = _load()
+    L = _f64(L)
+    A = np.zeros_like(L)
+    lib.ho_form_A(L.shape[0], lam, _p(L), _p(A))
+    return A
+
+
+def lu_solve_dense(A, b, refine=0):
+    """x = A^{-1} b by the oracle's GEPP (+ long-double refinement steps)."""
+    lib = _load()
+    A = _f64(A)
+    n = A.shape[0]
+    LU = A.copy()
+    piv = np.zeros(n, dtype=np.int32)
+    rc = lib.ho_lu_factor(n, _p(LU), piv.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+    if rc:
+        raise ZeroDivisionError(f"zero pivot at step {rc - 1}")
+    x = np.zeros(n)
+    work = np.zeros(n)
+    lib.ho_solve_refined(n, _p(A), _p(LU), piv.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                         _p(_f64(b)), _p(x), refine, _p(work))
+    return x
+
+
+# --------------------------------------------------------------------------
+# batched drivers (columns stored column-fastest)
+
+def _geom_args(col):
+    return [_f64(col[k]) for k in ("z", "J", "gz", "rho0", "Theta0")]
+
+
+def solve_batch(col, lam, b, refine=1, rho_weak=True, nthreads=None):
+    """x = (I - lam L_z)^{-1} P(b) for every column of the batch ``col``."""
+    lib = _load()
+    N, Ne = col["N"], col["Ne"]
+    ncols = col["z"].shape[1]
+    g = _geom_args(col)
+    b = _f64(b)
+    x = np.zeros_like(b)
+    bad = ctypes.c_long(-1)
+    consts = _f64(col["consts"])
+    rc = lib.ho_solve_batch(N, Ne, ncols, nthreads or os.cpu_count() or 1, _p(consts),
+                            *[_p(a) for a in g], lam, _p(b), _p(x), refine, int(rho_weak),
+                            ctypes.byref(bad))
+    if rc:
+        raise RuntimeError(f"oracle solve failed ({rc}) at column {bad.value}")
+    return x
+
+
+def apply_batch(col, x, xref=None, rho_weak=True, nthreads=None):
+    """y = L_z (x - xref) for every column."""
+    lib = _load()
+    N, Ne = col["N"], col["Ne"]
+    ncols = col["z"].shape[1]
+    g = _geom_args(col)
+    x = _f64(x)
+    xr = _f64(xref) if xref is not None else None
+    y = np.zeros_like(x)
+    bad = ctypes.c_long(-1)
+    consts = _f64(col["consts"])
+    rc = lib.ho_apply_batch(N, Ne, ncols, nthreads or os.cpu_count() or 1, _p(consts),
+                            *[_p(a) for a in g], _p(x), _p(xr), _p(y), int(rho_weak),
+                            ctypes.byref(bad))
+    if rc:
+        raise RuntimeError(f"oracle apply failed ({rc}) at column {bad.value}")
+    return y
+
+
+def ark_step_batch(col, tab, dt, qn, qref, refine=1, rho_weak=True, nthreads=None,
+                   want_stages=False, omega=0.0):
+    """One LHEVI ARK step.  ``tab`` holds float arrays Aexp, Aimp (s x s), b (s).
+
+    ``omega`` adds the explicit Coriolis term -2 omega n x U (time-convergence
+    studies only).  Returns q^{n+1} and, if requested, the stage values Q and tendencies S as
+    arrays [s][v][k][c]."""
+    lib = _load()
+    N, Ne = col["N"], col["Ne"]
+    ncols = col["z"].shape[1]
+    g = _geom_args(col)
+    Aexp = _f64(tab["Aexp"])
+    Aimp = _f64(tab["Aimp"])
+    bw = _f64(tab["b"])
+    s = bw.size
+    qn = _f64(qn)
+    qref = _f64(qref)
+    qnp1 = np.zeros_like(qn)
+    Q = np.zeros((s,) + qn.shape) if want_stages else None
+    S = np.zeros((s,) + qn.shape) if want_stages else None
+    bad = ctypes.c_long(-1)
+    consts = _f64(col["consts"])
+    rc = lib.ho_ark_step_batch(N, Ne, ncols, nthreads or os.cpu_count() or 1, _p(consts),
+                               *[_p(a) for a in g], s, _p(Aexp), _p(Aimp), _p(bw), dt, omega,
+                               _p(qn),
+                               _p(qref), _p(qnp1), _p(Q), _p(S), refine, int(rho_weak),
+                               ctypes.byref(bad))
+    if rc:
+        raise RuntimeError(f"oracle ARK step failed ({rc}) at column {bad.value}")
+    if want_stages:
+        return qnp1, Q, S
+    return qnp1
+
+
+def column_of(col, c):
+    """Per-column arrays of column c: z, J, gz [k][3], rho0, Theta0."""
+    gz = np.ascontiguousarray(col["gz"][:, :, c].T)
+    return (np.ascontiguousarray(col["z"][:, c]), np.ascontiguousarray(col["J"][:, c]), gz,
+            np.ascontiguousarray(col["rho0"][:, c]), np.ascontiguousarray(col["Theta0"][:, c]))
+
+
+def vec_of(v, c):
+    """Column c of a batched state [v][k][c] as the interleaved vector (5k+v)."""
+    return np.ascontiguousarray(v[:, :, c].T).reshape(-1)

@@ -1,0 +1,549 @@
+/*
+ * hevi_oracle.c -- plain, slow, serial FP64 reference for the LHEVI column solve.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU-baseline
+ * leg of the benchmark may load this library.  The product path (the HIP library
+ * under paper_2311_11425_amd/) never calls, links or includes anything here, and
+ * this file includes nothing from it.
+ *
+ * What it computes, per vertical column (Giraldo et al., arXiv 2311.11425):
+ *   - 1D Gauss-Lobatto-Legendre nodes, weights and differentiation matrix
+ *     (Sec. 3, basis and collocated Lobatto quadrature);
+ *   - the reference coefficients theta0 = Theta0/rho0 and c_Theta = dP/dTheta
+ *     from the set-2C equation of state (Appendix A.1, eq. set2c_pressure);
+ *   - the dense vertical operator L_z: the set-2C vertical operator V
+ *     (Appendix A.2) linearised about a reference state at rest, discretised with
+ *     the strong/weak differentiation matrices of Appendix A.3, multiplied by the
+ *     quadrature weight w_i J_i, direct-stiffness-summed along the column and
+ *     divided by the lumped mass (Sec. 3 eq. mass matrix, Sec. 4.2.2 global
+ *     assembly), with rigid-lid rows at the bottom and top nodes;
+ *   - x = (I - Lambda L_z)^{-1} b by dense Gaussian elimination with partial
+ *     pivoting (Sec. 4.3 eq. lhevi-ark-final-2), optionally followed by
+ *     iterative refinement with the residual accumulated in long double;
+ *   - the LHEVI ARK stage recipe (Sec. 4.1 stage/update formulas and Sec. 4.3
+ *     eq. lhevi-ark-final-3) for one time step of a batch of columns.
+ *
+ * Parity status of each function is recorded in the header comment of the
+ * function.  Everything here is double precision except the optional
+ * long-double residual of the refinement step.
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------- */
+/* Legendre polynomial P_N and its first derivative by the three-term
+ * recurrence (n+1) P_{n+1} = (2n+1) x P_n - n P_{n-1}; the derivative from
+ * (1 - x^2) P_N' = N (P_{N-1} - x P_N) away from x = +-1. */
+static void legendre(int N, double x, double *p, double *dp) {
+  double p0 = 1.0, p1 = x;
+  if (N == 0) { *p = 1.0; *dp = 0.0; return; }
+  for (int n = 1; n < N; ++n) {
+    double p2 = ((2.0 * n + 1.0) * x * p1 - n * p0) / (n + 1.0);
+    p0 = p1; p1 = p2;
+  }
+  *p = p1;
+  if (fabs(1.0 - x * x) < 1e-300) {
+    /* P_N'(+-1) = (+-1)^{N+1} N(N+1)/2 */
+    double s = (x > 0 || (N % 2 == 1)) ? 1.0 : -1.0;
+    *dp = s * 0.5 * N * (N + 1.0);
+  } else {
+    *dp = N * (p0 - x * p1) / (1.0 - x * x);
+  }
+}
+
+/* GLL nodes xi (ascending, xi_0=-1, xi_N=1; interior nodes are the roots of
+ * P_N'), weights w_i = 2/(N(N+1) P_N(xi_i)^2), and the collocation derivative
+ * D[i*(N+1)+j] = h_j'(xi_i) (derivative at node i of the Lagrange basis function
+ * of node j), from the textbook closed form
+ *   D_ij = P_N(xi_i) / (P_N(xi_j) (xi_i - xi_j)),  i != j,
+ *   D_00 = -N(N+1)/4,  D_NN = N(N+1)/4,  other diagonal entries 0.
+ * Sec. 3 (Lobatto points used for interpolation and integration; 1D
+ * differentiation matrices).  Interior roots by Newton's method on P_N' with
+ * P_N'' from Legendre's equation (1-x^2)P'' = 2x P' - N(N+1) P.
+ * Parity pinned: closed-form nodes/weights for N<=4, quadrature exactness to
+ * degree 2N-1 and derivative exactness to degree N (tests). */
+int ho_gll(int N, double *xi, double *w, double *D) {
+  if (N < 1 || N > 16) return 1;
+  xi[0] = -1.0; xi[N] = 1.0;
+  for (int j = 1; j < N; ++j) {
+    /* initial guess: Chebyshev-Gauss-Lobatto point, ascending */
+    double x = -cos(M_PI * j / N);
+    for (int it = 0; it < 100; ++it) {
+      double p, dp;
+      legendre(N, x, &p, &dp);
+      double d2p = (2.0 * x * dp - N * (N + 1.0) * p) / (1.0 - x * x);
+      double dx = dp / d2p;
+      x -= dx;
+      if (fabs(dx) < 1e-16) break;
+    }
+    xi[j] = x;
+  }
+  double PN[17];
+  for (int i = 0; i <= N; ++i) {
+    double p, dp;
+    legendre(N, xi[i], &p, &dp);
+    PN[i] = p;
+    w[i] = 2.0 / (N * (N + 1.0) * p * p);
+  }
+  for (int i = 0; i <= N; ++i)
+    for (int j = 0; j <= N; ++j) {
+      double v = 0.0;
+      if (i != j) v = PN[i] / (PN[j] * (xi[i] - xi[j]));
+      D[i * (N + 1) + j] = v;
+    }
+  D[0] = -0.25 * N * (N + 1.0);
+  D[N * (N + 1) + N] = 0.25 * N * (N + 1.0);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Reference coefficients from the set-2C equation of state
+ * P = P_A (R Theta / P_A)^gamma, gamma = c_p / (c_p - R) (Appendix A.1,
+ * eq. set2c_pressure; P_A = 1e5 Pa in Sec. 2.1).  theta0 = Theta0/rho0 and
+ * c_Theta = dP/dTheta = gamma P0 / Theta0.  (dP/drho = 0 in set 2C.)
+ * Parity pinned: mpmath evaluation of the same closed form (tests). */
+void ho_reference(int nz, const double *rho0, const double *Theta0, double R,
+                  double cp, double pA, double *theta0, double *cTheta) {
+  double gam = cp / (cp - R);
+  for (int k = 0; k < nz; ++k) {
+    double P0 = pA * pow(R * Theta0[k] / pA, gam);
+    theta0[k] = Theta0[k] / rho0[k];
+    cTheta[k] = gam * P0 / Theta0[k];
+  }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Dense vertical operator L_z (n x n, row-major, n = 5 nz) of one column.
+ * Unknown (node k, variable v) sits at 5k+v, v = (rho, rho u, rho v, rho w,
+ * rho theta).  Inputs per node k: height z[k], metric Jacobian J[k],
+ * contravariant metric grad(zeta) gz[3k+m], theta0[k], cTheta[k]; gravity g.
+ *
+ * The set-2C vertical fluxes F_rho = U.gz, F_U = (UU/rho + P I).gz,
+ * F_Theta = Theta U.gz / rho (Appendix A.2) linearised about a state at rest
+ * (U0 = 0) give the flux Jacobian K_j with nonzeros
+ *   K[rho][U_m] = gz_m,  K[U_m][Theta] = gz_m c_Theta,  K[Theta][U_m] = gz_m theta0
+ * (Appendix A.3, eq. set2c_jacobian, evaluated at U = 0 and with dP/dTheta in
+ * place of the garbled dP/dE entry), and the gravity term rho dPhi/dzeta gz
+ * (Appendix A.2) is linear in rho, so it enters the rho column of the momentum
+ * rows, with Phi = g z (Sec. 2.1).
+ *
+ * Per element e (nodes k = eN+i), multiplied by the quadrature weight w_i J_i
+ * (Sec. 4.2.2, "applying numerical integration ... and DSS"):
+ *   strong form (Appendix A.3 eq. differentiation_matrix/strong):
+ *     B[(k_i,a),(k_j,b)] += w_i D_ij J_{k_j} K_{k_j}[a][b]
+ *   weak form (eq. differentiation_matrix/weak):
+ *     B[(k_i,a),(k_j,b)] += -w_j D_ji J_{k_j} K_{k_j}[a][b]
+ *   gravity: B[(k_i,U_m),(k_i,rho)] += w_i J_{k_i} (dPhi/dzeta)_i gz_m(k_i),
+ *     (dPhi/dzeta)_i = g sum_j D_ij z_{k_j} within the element;
+ *   mass M_k += w_i J_k (Sec. 3, lumped mass and DSS).
+ * L_z = -M^{-1} B.  rho row weak (the continuity choice of Sec. 4.2.2) unless
+ * rho_weak == 0; Theta row strong unless theta_weak != 0; momentum rows strong.
+ * Rigid lid: momentum rows of the bottom (k=0) and top (k=nz-1) nodes are zero.
+ * Parity pinned: closed-form isothermal acoustic-gravity eigenvalues, mass and
+ * rho-theta conservation, weak/strong equivalence, tangential momentum,
+ * hydrostatic null vectors, rotation equivariance, exact rational brute force
+ * (tests). */
+int ho_assemble_L(int N, int Ne, double g, const double *z, const double *J,
+                  const double *gz, const double *theta0, const double *cTheta,
+                  int rho_weak, int theta_weak, double *L) {
+  if (N < 1 || N > 16 || Ne < 1) return 1;
+  int nz = Ne * N + 1, n = 5 * nz, np1 = N + 1;
+  double xi[17], w[17], D[17 * 17];
+  if (ho_gll(N, xi, w, D)) return 1;
+  double *M = (double *)calloc((size_t)nz, sizeof(double));
+  if (!M) return 2;
+  memset(L, 0, sizeof(double) * (size_t)n * (size_t)n);
+  for (int e = 0; e < Ne; ++e) {
+    for (int i = 0; i <= N; ++i) {
+      int ki = e * N + i;
+      double dphi = 0.0;
+      for (int j = 0; j <= N; ++j) dphi += D[i * np1 + j] * z[e * N + j];
+      dphi *= g;
+      M[ki] += w[i] * J[ki];
+      for (int m = 0; m < 3; ++m)
+        L[(size_t)(5 * ki + 1 + m) * n + 5 * ki + 0] += w[i] * J[ki] * dphi * gz[3 * ki + m];
+      for (int j = 0; j <= N; ++j) {
+        int kj = e * N + j;
+        double strong = w[i] * D[i * np1 + j] * J[kj];
+        double weak = -w[j] * D[j * np1 + i] * J[kj];
+        for (int m = 0; m < 3; ++m) {
+          double zm = gz[3 * kj + m];
+          L[(size_t)(5 * ki + 0) * n + 5 * kj + 1 + m] += (rho_weak ? weak : strong) * zm;
+          L[(size_t)(5 * ki + 1 + m) * n + 5 * kj + 4] += strong * zm * cTheta[kj];
+          L[(size_t)(5 * ki + 4) * n + 5 * kj + 1 + m] += (theta_weak ? weak : strong) * zm * theta0[kj];
+        }
+      }
+    }
+  }
+  /* L = -M^{-1} B */
+  for (int r = 0; r < n; ++r) {
+    double s = -1.0 / M[r / 5];
+    for (int c = 0; c < n; ++c) L[(size_t)r * n + c] *= s;
+  }
+  /* rigid lid: no momentum tendency at the bottom and top nodes */
+  int ends[2] = {0, nz - 1};
+  for (int t = 0; t < 2; ++t)
+    for (int m = 0; m < 3; ++m)
+      memset(&L[(size_t)(5 * ends[t] + 1 + m) * n], 0, sizeof(double) * (size_t)n);
+  free(M);
+  return 0;
+}
+
+/* Rigid-lid projection of a right-hand side: at the bottom and top nodes the
+ * momentum loses its component along n = gz/|gz| (no flux through the lid). */
+void ho_bc_project(int nz, const double *gz, double *b) {
+  int ends[2] = {0, nz - 1};
+  for (int t = 0; t < 2; ++t) {
+    int k = ends[t];
+    const double *a = &gz[3 * k];
+    double nn = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+    double nh[3] = {a[0] / nn, a[1] / nn, a[2] / nn};
+    double *u = &b[5 * k + 1];
+    double d = nh[0] * u[0] + nh[1] * u[1] + nh[2] * u[2];
+    for (int m = 0; m < 3; ++m) u[m] -= nh[m] * d;
+  }
+}
+
+/* A = I - Lambda L with the rigid-lid momentum rows of the end nodes replaced
+ * by identity rows (their rows of L are already zero, so this is automatic). */
+void ho_form_A(int n, double lambda, const double *L, double *A) {
+  for (int r = 0; r < n; ++r)
+    for (int c = 0; c < n; ++c)
+      A[(size_t)r * n + c] = (r == c ? 1.0 : 0.0) - lambda * L[(size_t)r * n + c];
+}
+
+/* ------------------------------------------------------------------------- */
+/* Dense LU with partial pivoting, in place (row-major n x n).  At step k the
+ * pivot is the row i >= k of largest |a_ik|, the lowest such row on ties; the
+ * multipliers overwrite the strictly lower part.  Returns 0, or 1 + k for an
+ * exactly zero pivot at step k.  Plain Gaussian elimination as used by the
+ * LU-based HEVI solvers (Sec. 4.2.2; LHEVI reuses it, Sec. 4.3).
+ * Parity pinned: exact rational brute force, scipy LAPACK band solve, mpmath. */
+int ho_lu_factor(int n, double *A, int *piv) {
+  for (int k = 0; k < n; ++k) {
+    int p = k;
+    double best = fabs(A[(size_t)k * n + k]);
+    for (int i = k + 1; i < n; ++i) {
+      double v = fabs(A[(size_t)i * n + k]);
+      if (v > best) { best = v; p = i; }
+    }
+    piv[k] = p;
+    if (best == 0.0) return 1 + k;
+    if (p != k)
+      for (int c = 0; c < n; ++c) {
+        double t = A[(size_t)k * n + c];
+        A[(size_t)k * n + c] = A[(size_t)p * n + c];
+        A[(size_t)p * n + c] = t;
+      }
+    double inv = 1.0 / A[(size_t)k * n + k];
+    for (int i = k + 1; i < n; ++i) {
+      double l = A[(size_t)i * n + k] * inv;
+      A[(size_t)i * n + k] = l;
+      if (l != 0.0)
+        for (int c = k + 1; c < n; ++c) A[(size_t)i * n + c] -= l * A[(size_t)k * n + c];
+    }
+  }
+  return 0;
+}
+
+/* Solve with the factors of ho_lu_factor: row swaps, unit-lower forward
+ * substitution, upper back substitution.  x may alias b. */
+void ho_lu_solve(int n, const double *LU, const int *piv, const double *b, double *x) {
+  if (x != b) memcpy(x, b, sizeof(double) * (size_t)n);
+  for (int k = 0; k < n; ++k) {
+    int p = piv[k];
+    if (p != k) { double t = x[k]; x[k] = x[p]; x[p] = t; }
+  }
+  for (int i = 0; i < n; ++i) {
+    double s = x[i];
+    for (int c = 0; c < i; ++c) s -= LU[(size_t)i * n + c] * x[c];
+    x[i] = s;
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double s = x[i];
+    for (int c = i + 1; c < n; ++c) s -= LU[(size_t)i * n + c] * x[c];
+    x[i] = s / LU[(size_t)i * n + i];
+  }
+}
+
+/* Solve A x = b with the factors, then `refine` steps of iterative refinement
+ * whose residual r = b - A x is accumulated in long double (the extended
+ * "oracle+" mode: it certifies the oracle where A is ill conditioned). */
+void ho_solve_refined(int n, const double *A, const double *LU, const int *piv,
+                      const double *b, double *x, int refine, double *work) {
+  ho_lu_solve(n, LU, piv, b, x);
+  for (int it = 0; it < refine; ++it) {
+    for (int r = 0; r < n; ++r) {
+      long double s = (long double)b[r];
+      for (int c = 0; c < n; ++c) s -= (long double)A[(size_t)r * n + c] * (long double)x[c];
+      work[r] = (double)s;
+    }
+    ho_lu_solve(n, LU, piv, work, work);
+    for (int r = 0; r < n; ++r) x[r] += work[r];
+  }
+}
+
+/* y = L x, dense */
+void ho_matvec(int n, const double *L, const double *x, double *y) {
+  for (int r = 0; r < n; ++r) {
+    double s = 0.0;
+    for (int c = 0; c < n; ++c) s += L[(size_t)r * n + c] * x[c];
+    y[r] = s;
+  }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Batched drivers over columns stored column-fastest: a per-node field f of
+ * column c at node k is f[k * ncols + c]; vectors [v][k][c]; grad(zeta)
+ * [m][k][c].  Columns are independent (Sec. 4.2.1: each column is solved
+ * independently), so they are split over plain POSIX threads. */
+
+typedef struct {
+  int N, Ne;
+  long ncols, c0, c1;
+  double R, cp, g, pA;
+  const double *z, *J, *gz, *rho0, *Theta0;
+  /* mode 0: solve, 1: apply, 2: ARK step */
+  int mode;
+  int rho_weak, refine;
+  double lambda;
+  const double *in; /* solve: b; apply: x */
+  const double *in_ref; /* apply: optional x_ref subtracted first */
+  double *out;      /* solve: x; apply: y */
+  /* ARK */
+  int s;
+  const double *Aexp, *Aimp, *bw;
+  double dt, omega;
+  const double *qn, *qref;
+  double *qnp1, *Qout, *Sout;
+  int status;
+  long bad_col;
+} job_t;
+
+static void gather_col(const job_t *jb, long c, double *z, double *J, double *gz,
+                       double *rho0, double *Th0) {
+  int nz = jb->Ne * jb->N + 1;
+  for (int k = 0; k < nz; ++k) {
+    z[k] = jb->z[k * jb->ncols + c];
+    J[k] = jb->J[k * jb->ncols + c];
+    rho0[k] = jb->rho0[k * jb->ncols + c];
+    Th0[k] = jb->Theta0[k * jb->ncols + c];
+    for (int m = 0; m < 3; ++m) gz[3 * k + m] = jb->gz[((long)m * nz + k) * jb->ncols + c];
+  }
+}
+
+static void get_vec(const double *src, long ncols, int nz, long c, double *dst) {
+  for (int v = 0; v < 5; ++v)
+    for (int k = 0; k < nz; ++k) dst[5 * k + v] = src[((long)v * nz + k) * ncols + c];
+}
+
+static void put_vec(double *dst, long ncols, int nz, long c, const double *src) {
+  for (int v = 0; v < 5; ++v)
+    for (int k = 0; k < nz; ++k) dst[((long)v * nz + k) * ncols + c] = src[5 * k + v];
+}
+
+/* Optional extra explicit term for time-convergence studies: the Coriolis
+ * force -2 Omega n x U of the set-2C momentum equation (Appendix A.1), with the
+ * rotation vector along the column's radial direction n = gz/|gz|.  It only
+ * rotates the tangential momentum, so it respects the rigid lid. */
+static void add_coriolis(int nz, const double *gz, double omega, const double *q, double *S) {
+  for (int k = 0; k < nz; ++k) {
+    const double *a = &gz[3 * k];
+    double nn = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+    double n0 = a[0] / nn, n1 = a[1] / nn, n2 = a[2] / nn;
+    const double *u = &q[5 * k + 1];
+    S[5 * k + 1] += -2.0 * omega * (n1 * u[2] - n2 * u[1]);
+    S[5 * k + 2] += -2.0 * omega * (n2 * u[0] - n0 * u[2]);
+    S[5 * k + 3] += -2.0 * omega * (n0 * u[1] - n1 * u[0]);
+  }
+}
+
+static void *worker(void *arg) {
+  job_t *jb = (job_t *)arg;
+  int nz = jb->Ne * jb->N + 1, n = 5 * nz, s = jb->s;
+  size_t nn = (size_t)n * n;
+  double *L = malloc(sizeof(double) * nn), *A = malloc(sizeof(double) * nn),
+         *LU = malloc(sizeof(double) * nn);
+  int *piv = malloc(sizeof(int) * n);
+  double *z = malloc(sizeof(double) * nz), *J = malloc(sizeof(double) * nz),
+         *gz = malloc(sizeof(double) * 3 * nz), *rho0 = malloc(sizeof(double) * nz),
+         *Th0 = malloc(sizeof(double) * nz), *th0 = malloc(sizeof(double) * nz),
+         *cT = malloc(sizeof(double) * nz);
+  int nv = 8 + 2 * (s > 0 ? s : 1);
+  double *vb = malloc(sizeof(double) * n * nv);
+  double *b = vb, *x = vb + n, *work = vb + 2 * n, *qn = vb + 3 * n, *qref = vb + 4 * n,
+         *tmp = vb + 5 * n, *qE = vb + 6 * n, *qhat = vb + 7 * n;
+  double *Q = vb + 8 * n, *S = Q + (size_t)n * (s > 0 ? s : 1);
+  jb->status = 0;
+  jb->bad_col = -1;
+  for (long c = jb->c0; c < jb->c1; ++c) {
+    gather_col(jb, c, z, J, gz, rho0, Th0);
+    ho_reference(nz, rho0, Th0, jb->R, jb->cp, jb->pA, th0, cT);
+    if (ho_assemble_L(jb->N, jb->Ne, jb->g, z, J, gz, th0, cT, jb->rho_weak, 0, L)) {
+      jb->status = 1; jb->bad_col = c; break;
+    }
+    if (jb->mode == 1) {
+      get_vec(jb->in, jb->ncols, nz, c, x);
+      if (jb->in_ref) {
+        get_vec(jb->in_ref, jb->ncols, nz, c, tmp);
+        for (int r = 0; r < n; ++r) x[r] -= tmp[r];
+      }
+      ho_matvec(n, L, x, b);
+      put_vec(jb->out, jb->ncols, nz, c, b);
+      continue;
+    }
+    if (jb->mode == 0) {
+      ho_form_A(n, jb->lambda, L, A);
+      memcpy(LU, A, sizeof(double) * nn);
+      if (ho_lu_factor(n, LU, piv)) { jb->status = 5; jb->bad_col = c; break; }
+      get_vec(jb->in, jb->ncols, nz, c, b);
+      ho_bc_project(nz, gz, b);
+      ho_solve_refined(n, A, LU, piv, b, x, jb->refine, work);
+      put_vec(jb->out, jb->ncols, nz, c, x);
+      continue;
+    }
+    /* mode 2: one LHEVI ARK step (Sec. 4.1 and eq. lhevi-ark-final-3).
+     * ESDIRK: first stage explicit, constant diagonal a~_ii, so one
+     * factorisation of I - a~_ii dt L serves every implicit stage. */
+    double lambda = jb->Aimp[1 * s + 1] * jb->dt;
+    ho_form_A(n, lambda, L, A);
+    memcpy(LU, A, sizeof(double) * nn);
+    if (ho_lu_factor(n, LU, piv)) { jb->status = 5; jb->bad_col = c; break; }
+    get_vec(jb->qn, jb->ncols, nz, c, qn);
+    get_vec(jb->qref, jb->ncols, nz, c, qref);
+    /* Q_1 = q^n, S_1 = S(Q_1) with the synthetic explicit operator
+     * S(q) = L_z (q - q_ref) */
+    memcpy(&Q[0], qn, sizeof(double) * n);
+    for (int r = 0; r < n; ++r) tmp[r] = qn[r] - qref[r];
+    ho_matvec(n, L, tmp, &S[0]);
+    if (jb->omega != 0.0) add_coriolis(nz, gz, jb->omega, tmp, &S[0]);
+    for (int i = 1; i < s; ++i) {
+      double aii = jb->Aimp[i * s + i];
+      /* q^E = q^n + dt sum_{j<i} a_ij S(Q_j) */
+      for (int r = 0; r < n; ++r) {
+        double v = qn[r];
+        for (int j = 0; j < i; ++j) v += jb->dt * jb->Aexp[i * s + j] * S[(size_t)j * n + r];
+        qE[r] = v;
+      }
+      /* q^ = q^E + sum_j c_j Q_j, c_j = (a~_ij - a_ij) / a~_ii */
+      for (int r = 0; r < n; ++r) {
+        double v = qE[r];
+        for (int j = 0; j < i; ++j) {
+          double cj = (jb->Aimp[i * s + j] - jb->Aexp[i * s + j]) / aii;
+          v += cj * Q[(size_t)j * n + r];
+        }
+        qhat[r] = v;
+      }
+      /* (I - Lambda L) q_tt = q^ ; Q_i = q_tt - sum_j c_j Q_j */
+      memcpy(b, qhat, sizeof(double) * n);
+      ho_bc_project(nz, gz, b);
+      ho_solve_refined(n, A, LU, piv, b, x, jb->refine, work);
+      for (int r = 0; r < n; ++r) {
+        double v = x[r];
+        for (int j = 0; j < i; ++j) {
+          double cj = (jb->Aimp[i * s + j] - jb->Aexp[i * s + j]) / aii;
+          v -= cj * Q[(size_t)j * n + r];
+        }
+        Q[(size_t)i * n + r] = v;
+      }
+      for (int r = 0; r < n; ++r) tmp[r] = Q[(size_t)i * n + r] - qref[r];
+      ho_matvec(n, L, tmp, &S[(size_t)i * n]);
+      if (jb->omega != 0.0) add_coriolis(nz, gz, jb->omega, tmp, &S[(size_t)i * n]);
+    }
+    /* q^{n+1} = q^n + dt sum_i b_i S(Q_i)  (b = b~) */
+    for (int r = 0; r < n; ++r) {
+      double v = qn[r];
+      for (int i = 0; i < s; ++i) v += jb->dt * jb->bw[i] * S[(size_t)i * n + r];
+      x[r] = v;
+    }
+    put_vec(jb->qnp1, jb->ncols, nz, c, x);
+    if (jb->Qout)
+      for (int i = 0; i < s; ++i)
+        put_vec(jb->Qout + (size_t)i * 5 * nz * jb->ncols, jb->ncols, nz, c, &Q[(size_t)i * n]);
+    if (jb->Sout)
+      for (int i = 0; i < s; ++i)
+        put_vec(jb->Sout + (size_t)i * 5 * nz * jb->ncols, jb->ncols, nz, c, &S[(size_t)i * n]);
+  }
+  free(L); free(A); free(LU); free(piv); free(z); free(J); free(gz); free(rho0);
+  free(Th0); free(th0); free(cT); free(vb);
+  return NULL;
+}
+
+static int run_jobs(job_t *proto, int nthreads, long *bad_col) {
+  if (nthreads < 1) nthreads = 1;
+  if (nthreads > proto->ncols) nthreads = (int)(proto->ncols > 0 ? proto->ncols : 1);
+  job_t *jobs = calloc((size_t)nthreads, sizeof(job_t));
+  pthread_t *th = calloc((size_t)nthreads, sizeof(pthread_t));
+  long per = (proto->ncols + nthreads - 1) / nthreads;
+  for (int t = 0; t < nthreads; ++t) {
+    jobs[t] = *proto;
+    jobs[t].c0 = t * per;
+    jobs[t].c1 = (t + 1) * per < proto->ncols ? (t + 1) * per : proto->ncols;
+    if (jobs[t].c0 > jobs[t].c1) jobs[t].c0 = jobs[t].c1;
+    pthread_create(&th[t], NULL, worker, &jobs[t]);
+  }
+  int status = 0;
+  *bad_col = -1;
+  for (int t = 0; t < nthreads; ++t) {
+    pthread_join(th[t], NULL);
+    if (jobs[t].status && !status) { status = jobs[t].status; *bad_col = jobs[t].bad_col; }
+  }
+  free(jobs); free(th);
+  return status;
+}
+
+static void fill_common(job_t *jb, int N, int Ne, long ncols, const double *consts,
+                        const double *z, const double *J, const double *gz,
+                        const double *rho0, const double *Theta0) {
+  memset(jb, 0, sizeof(*jb));
+  jb->N = N; jb->Ne = Ne; jb->ncols = ncols;
+  jb->R = consts[0]; jb->cp = consts[1]; jb->g = consts[2]; jb->pA = consts[3];
+  jb->z = z; jb->J = J; jb->gz = gz; jb->rho0 = rho0; jb->Theta0 = Theta0;
+}
+
+/* x = (I - lambda L_z)^{-1} P(b) per column, P the rigid-lid projection.
+ * consts = {R, c_p, g, P_A}.  Returns 0 or an error code; *bad_col names the
+ * first failing column. */
+int ho_solve_batch(int N, int Ne, long ncols, int nthreads, const double *consts,
+                   const double *z, const double *J, const double *gz, const double *rho0,
+                   const double *Theta0, double lambda, const double *b, double *x,
+                   int refine, int rho_weak, long *bad_col) {
+  job_t jb;
+  fill_common(&jb, N, Ne, ncols, consts, z, J, gz, rho0, Theta0);
+  jb.mode = 0; jb.lambda = lambda; jb.in = b; jb.out = x; jb.refine = refine;
+  jb.rho_weak = rho_weak;
+  return run_jobs(&jb, nthreads, bad_col);
+}
+
+/* y = L_z (x - x_ref) per column (x_ref may be NULL). */
+int ho_apply_batch(int N, int Ne, long ncols, int nthreads, const double *consts,
+                   const double *z, const double *J, const double *gz, const double *rho0,
+                   const double *Theta0, const double *x, const double *xref, double *y,
+                   int rho_weak, long *bad_col) {
+  job_t jb;
+  fill_common(&jb, N, Ne, ncols, consts, z, J, gz, rho0, Theta0);
+  jb.mode = 1; jb.in = x; jb.in_ref = xref; jb.out = y; jb.rho_weak = rho_weak;
+  return run_jobs(&jb, nthreads, bad_col);
+}
+
+/* One LHEVI ARK step of every column with the s-stage tableau (Aexp, Aimp row-
+ * major s x s, weights bw), explicit operator S(q) = L_z (q - q_ref), plus the
+ * Coriolis term when omega != 0.
+ * Qout / Sout (nullable) receive every stage value / tendency, [i][v][k][c]. */
+int ho_ark_step_batch(int N, int Ne, long ncols, int nthreads, const double *consts,
+                      const double *z, const double *J, const double *gz, const double *rho0,
+                      const double *Theta0, int s, const double *Aexp, const double *Aimp,
+                      const double *bw, double dt, double omega, const double *qn,
+                      const double *qref, double *qnp1, double *Qout, double *Sout, int refine,
+                      int rho_weak, long *bad_col) {
+  if (s < 2) return 1;
+  job_t jb;
+  fill_common(&jb, N, Ne, ncols, consts, z, J, gz, rho0, Theta0);
+  jb.mode = 2; jb.s = s; jb.Aexp = Aexp; jb.Aimp = Aimp; jb.bw = bw; jb.dt = dt;
+  jb.omega = omega;
+  jb.qn = qn; jb.qref = qref; jb.qnp1 = qnp1; jb.Qout = Qout; jb.Sout = Sout;
+  jb.refine = refine; jb.rho_weak = rho_weak;
+  return run_jobs(&jb, nthreads, bad_col);
+}
