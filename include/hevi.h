@@ -1,0 +1,214 @@
+/*
+ * hevi.h -- C ABI of the batched LHEVI vertical column solver for MI355X (gfx950).
+ *
+ * The library solves, for many independent vertical columns at once, the
+ * linear implicit problem of the LHEVI additive Runge-Kutta method of
+ * Giraldo et al. (arXiv 2311.11425):
+ *
+ *     (I - Lambda L_z) q_tt = q^,   Lambda = a~_ii dt          (Sec. 4.3,
+ *                                                       eq. lhevi-ark-final-2)
+ *
+ * where L_z is the set-2C vertical operator (Appendix A.2) linearised about a
+ * hydrostatic reference state at rest and discretised on the Gauss-Lobatto-
+ * Legendre points of each column (Sec. 3; Appendix A.3), with a rigid lid at
+ * the bottom and top nodes.  The matrix is factored once and the factors are
+ * reused by every implicit stage (Sec. 4.4: the forward reduction is paid when
+ * the operator is rebuilt, the back-substitution once per stage).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Shapes.   order_N = polynomial order of the vertical elements (1..8),
+ *           n_elem = number of vertical elements (>= 1),
+ *           n_z = n_elem * order_N + 1 unique GLL nodes per column,
+ *           n_cols = number of columns (>= 0).
+ * Layout.   All device arrays owned by the caller are FP64, struct-of-arrays,
+ *           column index fastest:  a per-node field f is f[k * n_cols + c];
+ *           grad(zeta) is gz[(m * n_z + k) * n_cols + c], m = x, y, z;
+ *           a state vector q (rho, rho u, rho v, rho w, rho theta) is
+ *           q[(v * n_z + k) * n_cols + c].  8-byte alignment is required,
+ *           256-byte alignment gives the best coalescing.
+ * Ownership. d_* pointers are caller-owned device memory; the library never
+ *           frees them and keeps no reference to them after the call's work
+ *           has run on the stream.  hevi_ops / hevi_factors / hevi_server are
+ *           library-owned, freed only by the matching *_free / *_destroy;
+ *           ops must outlive every factor object built from them.
+ * Streams.  Work is enqueued on the caller's HIP stream and returns
+ *           immediately unless stated otherwise; inputs must stay valid until
+ *           the stream reaches the call.  A NULL stream is the default stream.
+ * Errors.   The return value reports synchronous validation (bad arguments,
+ *           shapes, allocation failures).  Problems found by a kernel (zero
+ *           pivot, non-finite value, refinement not converged) are reported
+ *           through hevi_info, which is filled only when the caller passes a
+ *           non-NULL hevi_info (that makes the call wait for its stream).  On a
+ *           synchronous error no device work is enqueued and outputs are
+ *           untouched; outputs of columns flagged by a kernel are unspecified.
+ * Threads.  A context may be used by one host thread at a time; distinct
+ *           contexts are independent.  The server API is thread-safe.
+ */
+#ifndef HEVI_H
+#define HEVI_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HEVI_OK = 0,
+  HEVI_E_INVALID = 1,       /* bad argument value (NULL pointer, NaN constant ...) */
+  HEVI_E_SHAPE = 2,         /* unsupported or inconsistent shape                   */
+  HEVI_E_NOMEM = 3,         /* device or host allocation failed / over budget      */
+  HEVI_E_DEVICE = 4,        /* HIP runtime error                                   */
+  HEVI_E_SINGULAR = 5,      /* exactly zero pivot in some column                   */
+  HEVI_E_NOT_CONVERGED = 6, /* mixed path: refinement target not reached           */
+  HEVI_E_BUSY = 7,          /* server: no slot or memory free right now            */
+  HEVI_E_CLOSED = 8,        /* server: shut down or unknown id                     */
+  HEVI_E_NONFINITE = 9      /* a kernel produced or read a non-finite value        */
+} hevi_status;
+
+typedef enum {
+  HEVI_FP64 = 0,        /* factors and solve in FP64                                  */
+  HEVI_FP32_REFINE = 1  /* FP32-stored factors, FP64 right-hand side, FP64 residual
+                           of the reduced system, iterative refinement               */
+} hevi_precision;
+
+/* Physical constants: gas constant R, specific heat c_p, gravity g, reference
+ * pressure P_A of the equation of state P = P_A (R Theta / P_A)^gamma,
+ * gamma = c_p / (c_p - R) (Appendix A.1; P_A = 1e5 Pa in Sec. 2.1). */
+typedef struct { double R, cp, g, p_A; } hevi_consts;
+
+typedef struct { int32_t order_N, n_elem; int64_t n_cols; } hevi_shape;
+
+/* Refinement controls of a stage solve.
+ * max_sweeps / rel_residual_target: FP32-factor path only -- sweeps of
+ *   iterative refinement of the reduced system (FP64 residual r - S u applied
+ *   matrix-free, correction d from the FP32 factors, u += d) until the last
+ *   correction satisfies ||d|| <= rel_residual_target ||u||.
+ * full_sweeps: either precision -- sweeps of iterative refinement of the full
+ *   system with the FP64 residual q^ - A q_tt formed on offset-free vectors.  A
+ *   plain FP64 solve of a right-hand side ~100x larger than its solution (the
+ *   later ARK stages) loses about two digits in any FP64 factorisation; one
+ *   full sweep restores them. */
+typedef struct { int32_t max_sweeps; double rel_residual_target; int32_t full_sweeps; } hevi_refine;
+
+typedef struct {
+  int32_t status;            /* worst kernel-detected hevi_status of the call       */
+  int32_t max_sweeps_used;   /* refinement sweeps of the worst column (mixed path)  */
+  int64_t first_bad_col;     /* lowest flagged column, -1 if none                   */
+  int64_t n_bad_cols;        /* number of flagged columns                           */
+  double max_rel_correction; /* max over columns of the last ||d|| / ||u|| (FP32)    */
+} hevi_info;
+
+typedef struct hevi_ctx hevi_ctx;
+typedef struct hevi_ops hevi_ops;
+typedef struct hevi_factors hevi_factors;
+typedef struct hevi_server hevi_server;
+
+/* ---- context ----------------------------------------------------------- */
+/* Create a context on HIP device `device` (makes it current for the calling
+ * thread).  Returns HEVI_E_DEVICE if the device does not exist or is not a
+ * gfx950 part. */
+hevi_status hevi_create(int device, hevi_ctx **out);
+void hevi_destroy(hevi_ctx *ctx);
+const char *hevi_status_str(hevi_status s);
+
+/* ---- column operators (a1/a2) -------------------------------------------
+ * Column set-up of Sec. 3 and Appendix A: GLL nodes, weights and
+ * differentiation matrix of order N; per node the lumped mass M_k (quadrature
+ * weight times J, direct-stiffness-summed along the column), theta0 =
+ * Theta0/rho0 and c_Theta = dP/dTheta = gamma P0/Theta0 from the set-2C
+ * equation of state, and the gravity coefficient dPhi/dzeta with Phi = g z
+ * (Sec. 2.1), integrated and summed like every other term.
+ * Inputs (per node, [k][c]): height d_z, metric Jacobian d_J (> 0), reference
+ * density d_rho0 (> 0) and density potential temperature d_Theta0 (> 0);
+ * d_gz = grad(zeta) ([m][k][c], nonzero).  The result is a library-owned
+ * compact per-node operator (8 FP64 per node).  Invalid per-node values are
+ * reported by hevi_ops_check. */
+hevi_status hevi_build_column_ops(hevi_ctx *ctx, const hevi_shape *shape,
+                                  const hevi_consts *consts, const double *d_z,
+                                  const double *d_J, const double *d_gz,
+                                  const double *d_rho0, const double *d_Theta0,
+                                  hevi_ops **out, hipStream_t stream);
+/* Waits for `stream` and reports the first column whose inputs were invalid
+ * (non-positive J/rho0/Theta0, zero grad(zeta), non-finite values). */
+hevi_status hevi_ops_check(hevi_ctx *ctx, const hevi_ops *ops, int64_t *first_bad_col,
+                           hipStream_t stream);
+void hevi_ops_free(hevi_ops *ops);
+
+/* ---- operator application (a0) ------------------------------------------
+ * y = L_z (x - x_ref) for every column (x_ref may be NULL), with the rigid-lid
+ * rows of the end nodes zero.  This is the discrete vertical operator of
+ * Appendix A.2 linearised at rest; it serves as the synthetic explicit
+ * tendency S(q) = L_z (q - q_ref) of the benchmark.  Vectors [v][k][c].  y must
+ * not alias x or x_ref. */
+hevi_status hevi_apply_op(hevi_ctx *ctx, const hevi_ops *ops, const double *d_x,
+                          const double *d_xref, double *d_y, hipStream_t stream);
+
+/* ---- factorisation (a3) ---------------------------------------------------
+ * Factor A = I - lambda L_z (with rigid-lid identity rows) for every column.
+ * Representation: the exact block elimination of rho, Theta and the tangential
+ * momentum (their diagonal blocks are identities) leaves a band system of
+ * half-bandwidth 2N in the contravariant vertical momentum u = grad(zeta).U;
+ * that system is LU-factored with partial pivoting (largest magnitude in the
+ * pivot column, lowest row on ties), the same band LU the paper uses through
+ * LAPACK (Sec. 4.2.2) applied to the reduced matrix.  Factors are FP64, or
+ * FP32 for HEVI_FP32_REFINE (elimination in FP64, then rounded).  lambda >= 0.
+ * hevi_factor allocates; hevi_refactor reuses the storage of `f` for a new
+ * lambda (no allocation).  A zero pivot is reported as HEVI_E_SINGULAR by
+ * hevi_factors_check. */
+hevi_status hevi_factor(hevi_ctx *ctx, const hevi_ops *ops, double lambda,
+                        hevi_precision prec, hevi_factors **out, hipStream_t stream);
+hevi_status hevi_refactor(hevi_ctx *ctx, hevi_factors *f, double lambda, hipStream_t stream);
+hevi_status hevi_factors_check(hevi_ctx *ctx, const hevi_factors *f, hevi_info *info,
+                               hipStream_t stream);
+void hevi_factors_free(hevi_factors *f);
+
+/* ---- stage solve (a4 + a5 + a6) -------------------------------------------
+ * One implicit LHEVI stage for every column (Sec. 4.3, eq. lhevi-ark-final-3):
+ *     q^E = sum_t e[t] E_t            (e.g. E = {q^n, S(Q_1), ...},
+ *                                      e = {1, dt a_i1, ...})
+ *     q^  = q^E + sum_j c[j] Q_j      (c_j = (a~_ij - a_ij) / a~_ii)
+ *     q_tt = (I - lambda L_z)^{-1} q^  (rigid-lid projection of q^ first)
+ *     Q_i  = q_tt - sum_j c[j] Q_j
+ * h_dE / h_dQprev are HOST arrays of n_e / n_prev DEVICE pointers to state
+ * vectors [v][k][c]; h_e / h_c are host coefficient arrays.  n_e in [1, 16],
+ * n_prev in [0, 16]; n_prev = 0 with n_e = 1, e = {1} solves A x = b directly.
+ * d_Qi must not alias any input.  `refine` (NULL = {4, 1e-13, 0}) is described
+ * at hevi_refine; max_sweeps is ignored for FP64 factors.
+ * If h_info != NULL the call waits for the stream and fills it. */
+hevi_status hevi_stage_solve(hevi_ctx *ctx, const hevi_factors *f, int32_t n_e,
+                             const double *const *h_dE, const double *h_e, int32_t n_prev,
+                             const double *const *h_dQprev, const double *h_c, double *d_Qi,
+                             const hevi_refine *refine, hevi_info *h_info, hipStream_t stream);
+
+/* ---- linear combination (end of step, a6) ---------------------------------
+ * out = sum_t coef[t] V_t over n_v state vectors (n_v in [1, 16]), e.g. the
+ * update q^{n+1} = q^n + dt sum_i b_i S(Q_i) (Sec. 4.1, with b = b~). */
+hevi_status hevi_combine(hevi_ctx *ctx, const hevi_ops *ops, int32_t n_v,
+                         const double *const *h_dV, const double *h_coef, double *d_out,
+                         hipStream_t stream);
+
+/* ---- tableaux ---------------------------------------------------------------
+ * IMEX ARK tableaux of the paper's integrators (Sec. 5): "ARK2" / "ARK2b" =
+ * ARK(2,3,2) with a_32 = 1/2, "ARK2a" with a_32 = (3 + 2 sqrt 2)/6 (Sec. 4.1),
+ * "ARK3" = ARK3(2)4L[2]SA of Kennedy and Carpenter.  Writes s and the
+ * row-major s x s explicit / implicit matrices and weights (capacity 8 stages).
+ * Returns HEVI_E_INVALID for an unknown name. */
+hevi_status hevi_tableau(const char *name, int32_t *s, double *a_exp, double *a_imp,
+                         double *b);
+
+/* ---- introspection ---------------------------------------------------------- */
+/* Bytes of the compact operator and of the factors actually stored per column
+ * (FP64 or FP32 factors incl. pivots), and the bytes the paper's LAPACK band
+ * layout would need (ldab = 3 * 5 (N+1) - 2 rows of 8-byte entries per
+ * unknown plus a 4-byte pivot). */
+hevi_status hevi_sizes(const hevi_shape *shape, hevi_precision prec, size_t *ops_bytes_per_col,
+                       size_t *factor_bytes_per_col, size_t *paper_band_bytes_per_col);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HEVI_H */

@@ -1,0 +1,458 @@
+// hevi_api.cpp -- C ABI of the batched LHEVI column solver (see include/hevi.h).
+//
+// Host side only: argument validation, ownership of device buffers, the 1D
+// GLL tables of order N, the ARK tableaux, and kernel launches on the caller's
+// stream.  The arithmetic of the method runs in hevi_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <new>
+
+#include "hevi.h"
+#include "hevi_internal.h"
+
+struct hevi_ctx {
+  int device;
+};
+
+struct hevi_ops {
+  hevi_ctx* ctx;
+  hevi_shape shape;
+  hevi_consts consts;
+  HeviShapeDev sh;
+  HeviTab tab;
+  double* d_ops;
+  HeviDevInfo* d_info;
+};
+
+struct hevi_factors {
+  const hevi_ops* ops;
+  double lambda;
+  hevi_precision prec;
+  void* U;
+  void* L;
+  uint8_t* piv;
+  double* sbuf;  // FP64 assembly buffer (aliases U for FP64 factors)
+  double* ws;    // per-node FP64 scratch of the stage solve
+  HeviDevInfo* d_info;
+};
+
+namespace {
+
+bool ok(hipError_t e) { return e == hipSuccess; }
+
+// ---- 1D Gauss-Lobatto-Legendre tables (Sec. 3) ------------------------------
+// The interior nodes are the roots of q(x) = P_{N+1}(x) - P_{N-1}(x) (which
+// also vanishes at +-1), found by Newton's method with q'(x) = (2N+1) P_N(x);
+// weights w_i = 2 / (N (N+1) P_N(x_i)^2); the derivative matrix from the
+// barycentric form D_ij = (b_j / b_i) / (x_i - x_j), D_ii = -sum_{j!=i} D_ij,
+// b_j = 1 / prod_{k!=j} (x_j - x_k).
+void legendre3(int N, double x, double* pm1, double* p, double* pp1) {
+  double a = 1.0, b = x;  // P_0, P_1
+  if (N == 0) { *pm1 = 0.0; *p = 1.0; *pp1 = x; return; }
+  for (int n = 1; n < N; ++n) {
+    double c = ((2 * n + 1) * x * b - n * a) / (n + 1);
+    a = b; b = c;
+  }
+  *pm1 = a; *p = b;
+  *pp1 = ((2 * N + 1) * x * b - N * a) / (N + 1);
+}
+
+void gll_tables(int N, HeviTab* tab, double* xi_out) {
+  double x[HEVI_MAXN + 1];
+  x[0] = -1.0; x[N] = 1.0;
+  for (int j = 1; j < N; ++j) {
+    double t = -std::cos(M_PI * j / N);
+    for (int it = 0; it < 200; ++it) {
+      double pm1, p, pp1;
+      legendre3(N, t, &pm1, &p, &pp1);
+      const double dt = (pp1 - pm1) / ((2 * N + 1) * p);
+      t -= dt;
+      if (std::fabs(dt) <= 1e-17) break;
+    }
+    x[j] = t;
+  }
+  std::memset(tab, 0, sizeof(*tab));
+  for (int i = 0; i <= N; ++i) {
+    double pm1, p, pp1;
+    legendre3(N, x[i], &pm1, &p, &pp1);
+    tab->w[i] = 2.0 / (N * (N + 1.0) * p * p);
+  }
+  double bw[HEVI_MAXN + 1];
+  for (int j = 0; j <= N; ++j) {
+    double prod = 1.0;
+    for (int k = 0; k <= N; ++k)
+      if (k != j) prod *= (x[j] - x[k]);
+    bw[j] = 1.0 / prod;
+  }
+  for (int i = 0; i <= N; ++i) {
+    double diag = 0.0;
+    for (int j = 0; j <= N; ++j) {
+      if (i == j) continue;
+      const double d = (bw[j] / bw[i]) / (x[i] - x[j]);
+      tab->D[i * (N + 1) + j] = d;
+      diag -= d;
+    }
+    tab->D[i * (N + 1) + i] = diag;
+  }
+  if (xi_out)
+    for (int i = 0; i <= N; ++i) xi_out[i] = x[i];
+}
+
+HeviShapeDev dev_shape(const hevi_shape& s) {
+  HeviShapeDev d;
+  d.N = s.order_N;
+  d.Ne = s.n_elem;
+  d.nz = s.n_elem * s.order_N + 1;
+  d.ncols = s.n_cols;
+  d.ntiles = (s.n_cols + HEVI_TILE - 1) / HEVI_TILE;
+  return d;
+}
+
+hevi_status check_shape(const hevi_shape* s) {
+  if (!s) return HEVI_E_INVALID;
+  if (s->order_N < 1 || s->order_N > HEVI_MAXN) return HEVI_E_SHAPE;
+  if (s->n_elem < 1 || s->n_elem > 4096) return HEVI_E_SHAPE;
+  if (s->n_cols < 0) return HEVI_E_SHAPE;
+  const int64_t nz = (int64_t)s->n_elem * s->order_N + 1;
+  if (nz > 32768) return HEVI_E_SHAPE;
+  // grid dimension limit: one 64-column tile per block
+  if ((s->n_cols + HEVI_TILE - 1) / HEVI_TILE > (int64_t)INT32_MAX) return HEVI_E_SHAPE;
+  return HEVI_OK;
+}
+
+template <typename P>
+hevi_status dev_alloc(P** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 256;
+  void* v = nullptr;
+  if (!ok(hipMalloc(&v, bytes))) return HEVI_E_NOMEM;
+  *p = (P*)v;
+  return HEVI_OK;
+}
+
+size_t tiles_nodes(const HeviShapeDev& sh) { return (size_t)sh.ntiles * (size_t)sh.nz * HEVI_TILE; }
+
+hevi_status read_info(HeviDevInfo* d_info, hipStream_t st, hevi_info* out, bool reset) {
+  HeviDevInfo h;
+  if (!ok(hipMemcpyAsync(&h, d_info, sizeof(h), hipMemcpyDeviceToHost, st))) return HEVI_E_DEVICE;
+  if (!ok(hipStreamSynchronize(st))) return HEVI_E_DEVICE;
+  if (reset && !ok(hevi_launch_info_reset(d_info, st))) return HEVI_E_DEVICE;
+  if (out) {
+    out->status = h.status;
+    out->max_sweeps_used = h.max_sweeps;
+    out->first_bad_col = h.first_bad == INT64_MAX ? -1 : h.first_bad;
+    out->n_bad_cols = h.n_bad;
+    double r;
+    std::memcpy(&r, &h.max_res_bits, sizeof(r));
+    out->max_rel_correction = r;
+  }
+  return (hevi_status)h.status;
+}
+
+hevi_status terms(int32_t n, const double* const* v, const double* coef, int lo, bool empty,
+                  HeviTerms* t) {
+  // empty: the batch has no columns, so NULL device pointers are acceptable
+  if (n < lo || n > HEVI_MAXTERMS) return HEVI_E_INVALID;
+  if (n > 0 && (!v || !coef)) return HEVI_E_INVALID;
+  t->n = n;
+  for (int i = 0; i < n; ++i) {
+    if ((!v[i] && !empty) || !std::isfinite(coef[i])) return HEVI_E_INVALID;
+    t->v[i] = v[i];
+    t->coef[i] = coef[i];
+  }
+  for (int i = n; i < HEVI_MAXTERMS; ++i) { t->v[i] = nullptr; t->coef[i] = 0.0; }
+  return HEVI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hevi_status_str(hevi_status s) {
+  switch (s) {
+    case HEVI_OK: return "ok";
+    case HEVI_E_INVALID: return "invalid argument";
+    case HEVI_E_SHAPE: return "unsupported shape";
+    case HEVI_E_NOMEM: return "out of memory";
+    case HEVI_E_DEVICE: return "HIP device error";
+    case HEVI_E_SINGULAR: return "zero pivot";
+    case HEVI_E_NOT_CONVERGED: return "refinement did not converge";
+    case HEVI_E_BUSY: return "busy";
+    case HEVI_E_CLOSED: return "closed";
+    case HEVI_E_NONFINITE: return "non-finite value";
+  }
+  return "unknown status";
+}
+
+hevi_status hevi_create(int device, hevi_ctx** out) {
+  if (!out) return HEVI_E_INVALID;
+  *out = nullptr;
+  int n = 0;
+  if (!ok(hipGetDeviceCount(&n)) || device < 0 || device >= n) return HEVI_E_DEVICE;
+  hipDeviceProp_t prop;
+  if (!ok(hipGetDeviceProperties(&prop, device))) return HEVI_E_DEVICE;
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return HEVI_E_DEVICE;
+  if (!ok(hipSetDevice(device))) return HEVI_E_DEVICE;
+  hevi_ctx* c = new (std::nothrow) hevi_ctx;
+  if (!c) return HEVI_E_NOMEM;
+  c->device = device;
+  *out = c;
+  return HEVI_OK;
+}
+
+void hevi_destroy(hevi_ctx* ctx) { delete ctx; }
+
+hevi_status hevi_build_column_ops(hevi_ctx* ctx, const hevi_shape* shape, const hevi_consts* k,
+                                  const double* d_z, const double* d_J, const double* d_gz,
+                                  const double* d_rho0, const double* d_Theta0, hevi_ops** out,
+                                  hipStream_t stream) {
+  if (!ctx || !out || !k) return HEVI_E_INVALID;
+  *out = nullptr;
+  hevi_status s = check_shape(shape);
+  if (s) return s;
+  if (!(k->R > 0) || !(k->cp > k->R) || !(k->g >= 0) || !(k->p_A > 0) || !std::isfinite(k->R) ||
+      !std::isfinite(k->cp) || !std::isfinite(k->g) || !std::isfinite(k->p_A))
+    return HEVI_E_INVALID;
+  if (shape->n_cols > 0 && (!d_z || !d_J || !d_gz || !d_rho0 || !d_Theta0)) return HEVI_E_INVALID;
+  if (!ok(hipSetDevice(ctx->device))) return HEVI_E_DEVICE;
+  hevi_ops* o = new (std::nothrow) hevi_ops;
+  if (!o) return HEVI_E_NOMEM;
+  o->ctx = ctx;
+  o->shape = *shape;
+  o->consts = *k;
+  o->sh = dev_shape(*shape);
+  gll_tables(shape->order_N, &o->tab, nullptr);
+  o->d_ops = nullptr;
+  o->d_info = nullptr;
+  if ((s = dev_alloc(&o->d_ops, tiles_nodes(o->sh) * HEVI_NOPS * sizeof(double))) ||
+      (s = dev_alloc(&o->d_info, sizeof(HeviDevInfo)))) {
+    hevi_ops_free(o);
+    return s;
+  }
+  if (!ok(hevi_launch_info_reset(o->d_info, stream)) ||
+      !ok(hevi_launch_build_ops(o->sh, o->tab, k->R, k->cp, k->g, k->p_A, d_z, d_J, d_gz, d_rho0,
+                                d_Theta0, o->d_ops, o->d_info, stream))) {
+    hevi_ops_free(o);
+    return HEVI_E_DEVICE;
+  }
+  *out = o;
+  return HEVI_OK;
+}
+
+hevi_status hevi_ops_check(hevi_ctx* ctx, const hevi_ops* ops, int64_t* first_bad_col,
+                           hipStream_t stream) {
+  if (!ctx || !ops) return HEVI_E_INVALID;
+  hevi_info inf;
+  hevi_status s = read_info(ops->d_info, stream, &inf, false);
+  if (first_bad_col) *first_bad_col = inf.first_bad_col;
+  return s;
+}
+
+void hevi_ops_free(hevi_ops* ops) {
+  if (!ops) return;
+  if (ops->d_ops) (void)hipFree(ops->d_ops);
+  if (ops->d_info) (void)hipFree(ops->d_info);
+  delete ops;
+}
+
+hevi_status hevi_apply_op(hevi_ctx* ctx, const hevi_ops* ops, const double* d_x,
+                          const double* d_xref, double* d_y, hipStream_t stream) {
+  if (!ctx || !ops) return HEVI_E_INVALID;
+  if (ops->sh.ncols > 0) {
+    if (!d_x || !d_y) return HEVI_E_INVALID;
+    if (d_y == d_x || (d_xref && d_y == d_xref)) return HEVI_E_INVALID;
+  }
+  if (!ok(hipSetDevice(ctx->device))) return HEVI_E_DEVICE;
+  if (!ok(hevi_launch_apply(ops->sh, ops->tab, ops->d_ops, d_x, d_xref, d_y, stream)))
+    return HEVI_E_DEVICE;
+  return HEVI_OK;
+}
+
+hevi_status hevi_factor(hevi_ctx* ctx, const hevi_ops* ops, double lambda, hevi_precision prec,
+                        hevi_factors** out, hipStream_t stream) {
+  if (!ctx || !ops || !out) return HEVI_E_INVALID;
+  *out = nullptr;
+  if (prec != HEVI_FP64 && prec != HEVI_FP32_REFINE) return HEVI_E_INVALID;
+  if (!(lambda >= 0.0) || !std::isfinite(lambda)) return HEVI_E_INVALID;
+  if (!ok(hipSetDevice(ctx->device))) return HEVI_E_DEVICE;
+  hevi_factors* f = new (std::nothrow) hevi_factors;
+  if (!f) return HEVI_E_NOMEM;
+  std::memset(f, 0, sizeof(*f));
+  f->ops = ops;
+  f->prec = prec;
+  const HeviShapeDev& sh = ops->sh;
+  const size_t tn = tiles_nodes(sh);
+  const size_t fs = prec == HEVI_FP64 ? sizeof(double) : sizeof(float);
+  const int N = sh.N;
+  hevi_status s;
+  if ((s = dev_alloc(&f->U, tn * (4 * N + 1) * fs)) || (s = dev_alloc(&f->L, tn * 2 * N * fs)) ||
+      (s = dev_alloc(&f->piv, tn)) || (s = dev_alloc(&f->ws, tn * HEVI_NWS * sizeof(double))) ||
+      (s = dev_alloc(&f->d_info, sizeof(HeviDevInfo)))) {
+    hevi_factors_free(f);
+    return s;
+  }
+  if (prec == HEVI_FP64) {
+    f->sbuf = (double*)f->U;
+  } else if ((s = dev_alloc(&f->sbuf, tn * (4 * N + 1) * sizeof(double)))) {
+    hevi_factors_free(f);
+    return s;
+  }
+  if (!ok(hevi_launch_info_reset(f->d_info, stream))) {
+    hevi_factors_free(f);
+    return HEVI_E_DEVICE;
+  }
+  if ((s = hevi_refactor(ctx, f, lambda, stream))) {
+    hevi_factors_free(f);
+    return s;
+  }
+  *out = f;
+  return HEVI_OK;
+}
+
+hevi_status hevi_refactor(hevi_ctx* ctx, hevi_factors* f, double lambda, hipStream_t stream) {
+  if (!ctx || !f) return HEVI_E_INVALID;
+  if (!(lambda >= 0.0) || !std::isfinite(lambda)) return HEVI_E_INVALID;
+  if (!ok(hipSetDevice(ctx->device))) return HEVI_E_DEVICE;
+  f->lambda = lambda;
+  const hevi_ops* o = f->ops;
+  if (!ok(hevi_launch_factor(o->sh, o->tab, lambda, f->prec == HEVI_FP32_REFINE, o->d_ops,
+                             f->sbuf, f->U, f->L, f->piv, f->d_info, stream)))
+    return HEVI_E_DEVICE;
+  return HEVI_OK;
+}
+
+hevi_status hevi_factors_check(hevi_ctx* ctx, const hevi_factors* f, hevi_info* info,
+                               hipStream_t stream) {
+  if (!ctx || !f) return HEVI_E_INVALID;
+  return read_info(f->d_info, stream, info, true);
+}
+
+void hevi_factors_free(hevi_factors* f) {
+  if (!f) return;
+  if (f->sbuf && f->sbuf != (double*)f->U) (void)hipFree(f->sbuf);
+  if (f->U) (void)hipFree(f->U);
+  if (f->L) (void)hipFree(f->L);
+  if (f->piv) (void)hipFree(f->piv);
+  if (f->ws) (void)hipFree(f->ws);
+  if (f->d_info) (void)hipFree(f->d_info);
+  delete f;
+}
+
+hevi_status hevi_stage_solve(hevi_ctx* ctx, const hevi_factors* f, int32_t n_e,
+                             const double* const* h_dE, const double* h_e, int32_t n_prev,
+                             const double* const* h_dQprev, const double* h_c, double* d_Qi,
+                             const hevi_refine* refine, hevi_info* h_info, hipStream_t stream) {
+  if (!ctx || !f) return HEVI_E_INVALID;
+  const hevi_ops* o = f->ops;
+  HeviTerms E, Q;
+  hevi_status s;
+  const bool empty = o->sh.ncols == 0;
+  if ((s = terms(n_e, h_dE, h_e, 1, empty, &E))) return s;
+  if ((s = terms(n_prev, h_dQprev, h_c, 0, empty, &Q))) return s;
+  if (!empty) {
+    if (!d_Qi) return HEVI_E_INVALID;
+    for (int i = 0; i < E.n; ++i)
+      if (E.v[i] == d_Qi) return HEVI_E_INVALID;
+    for (int i = 0; i < Q.n; ++i)
+      if (Q.v[i] == d_Qi) return HEVI_E_INVALID;
+  }
+  int sweeps = 4, full = 0;
+  double target = 1e-13;
+  if (refine) {
+    if (refine->max_sweeps < 0 || refine->max_sweeps > 64 || !(refine->rel_residual_target >= 0) ||
+        refine->full_sweeps < 0 || refine->full_sweeps > 8)
+      return HEVI_E_INVALID;
+    sweeps = refine->max_sweeps;
+    target = refine->rel_residual_target;
+    full = refine->full_sweeps;
+  }
+  if (f->prec == HEVI_FP64) sweeps = 0;
+  if (!ok(hipSetDevice(ctx->device))) return HEVI_E_DEVICE;
+  if (h_info && !ok(hevi_launch_info_reset(f->d_info, stream))) return HEVI_E_DEVICE;
+  if (!ok(hevi_launch_stage_solve(o->sh, o->tab, f->lambda, f->prec == HEVI_FP32_REFINE, o->d_ops,
+                                  f->U, f->L, f->piv, f->ws, E, Q, d_Qi, sweeps, target, full,
+                                  f->d_info, stream)))
+    return HEVI_E_DEVICE;
+  if (h_info) {
+    std::memset(h_info, 0, sizeof(*h_info));
+    hevi_status r = read_info(f->d_info, stream, h_info, true);
+    if (r == HEVI_E_DEVICE) return r;
+  }
+  return HEVI_OK;
+}
+
+hevi_status hevi_combine(hevi_ctx* ctx, const hevi_ops* ops, int32_t n_v,
+                         const double* const* h_dV, const double* h_coef, double* d_out,
+                         hipStream_t stream) {
+  if (!ctx || !ops) return HEVI_E_INVALID;
+  HeviTerms V;
+  hevi_status s;
+  if ((s = terms(n_v, h_dV, h_coef, 1, ops->sh.ncols == 0, &V))) return s;
+  if (ops->sh.ncols > 0 && !d_out) return HEVI_E_INVALID;
+  if (!ok(hipSetDevice(ctx->device))) return HEVI_E_DEVICE;
+  const int64_t n = 5 * (int64_t)ops->sh.nz * ops->sh.ncols;
+  if (!ok(hevi_launch_combine(n, V, d_out, stream))) return HEVI_E_DEVICE;
+  return HEVI_OK;
+}
+
+// ---- ARK tableaux (Sec. 5) ---------------------------------------------------
+hevi_status hevi_tableau(const char* name, int32_t* s, double* a_exp, double* a_imp, double* b) {
+  if (!name || !s || !a_exp || !a_imp || !b) return HEVI_E_INVALID;
+  if (!std::strcmp(name, "ARK2") || !std::strcmp(name, "ARK2b") || !std::strcmp(name, "ARK2a")) {
+    // ARK(2,3,2): gamma = 1 - 1/sqrt2, delta = 1/(2 sqrt2), free a_32
+    const double r2 = std::sqrt(2.0);
+    const double gm = 1.0 - 1.0 / r2, dl = 1.0 / (2.0 * r2);
+    const double a32 = !std::strcmp(name, "ARK2a") ? (3.0 + 2.0 * r2) / 6.0 : 0.5;
+    const double E[9] = {0, 0, 0, 2 * gm, 0, 0, 1 - a32, a32, 0};
+    const double I[9] = {0, 0, 0, gm, gm, 0, dl, dl, gm};
+    *s = 3;
+    std::memcpy(a_exp, E, sizeof(E));
+    std::memcpy(a_imp, I, sizeof(I));
+    b[0] = dl; b[1] = dl; b[2] = gm;
+    return HEVI_OK;
+  }
+  if (!std::strcmp(name, "ARK3")) {
+    // ARK3(2)4L[2]SA (Kennedy and Carpenter, 2003)
+    const double g = 1767732205903.0 / 4055673282236.0;
+    const double E[16] = {0, 0, 0, 0,
+                          1767732205903.0 / 2027836641118.0, 0, 0, 0,
+                          5535828885825.0 / 10492691773637.0, 788022342437.0 / 10882634858940.0, 0, 0,
+                          6485989280629.0 / 16251701735622.0, -4246266847089.0 / 9704473918619.0,
+                          10755448449292.0 / 10357097424841.0, 0};
+    const double I[16] = {0, 0, 0, 0,
+                          g, g, 0, 0,
+                          2746238789719.0 / 10658868560708.0, -640167445237.0 / 6845629431997.0, g, 0,
+                          1471266399579.0 / 7840856788654.0, -4482444167858.0 / 7529755066697.0,
+                          11266239266428.0 / 11593286722821.0, g};
+    *s = 4;
+    std::memcpy(a_exp, E, sizeof(E));
+    std::memcpy(a_imp, I, sizeof(I));
+    for (int i = 0; i < 4; ++i) b[i] = I[12 + i];
+    return HEVI_OK;
+  }
+  return HEVI_E_INVALID;
+}
+
+hevi_status hevi_sizes(const hevi_shape* shape, hevi_precision prec, size_t* ops_bytes,
+                       size_t* factor_bytes, size_t* paper_bytes) {
+  hevi_status s = check_shape(shape);
+  if (s) return s;
+  if (prec != HEVI_FP64 && prec != HEVI_FP32_REFINE) return HEVI_E_INVALID;
+  const int N = shape->order_N;
+  const size_t nz = (size_t)shape->n_elem * N + 1;
+  const size_t fsz = prec == HEVI_FP64 ? 8 : 4;
+  if (ops_bytes) *ops_bytes = nz * HEVI_NOPS * sizeof(double);
+  if (factor_bytes) *factor_bytes = nz * ((4 * N + 1) + 2 * N) * fsz + nz;
+  if (paper_bytes) {
+    const size_t n = 5 * nz;
+    const size_t ldab = 3 * 5 * (N + 1) - 2;
+    *paper_bytes = n * ldab * 8 + n * 4;
+  }
+  return HEVI_OK;
+}
+
+}  // extern "C"

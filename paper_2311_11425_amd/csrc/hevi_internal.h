@@ -1,0 +1,66 @@
+// hevi_internal.h -- launch interface between the C ABI layer (hevi_api.cpp)
+// and the gfx950 kernels (hevi_kernels.hip).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#define HEVI_MAXN 8       // highest supported polynomial order
+#define HEVI_TILE 64      // columns per wavefront: one lane per column
+#define HEVI_NOPS 8       // compact per-node operator fields
+#define HEVI_NWS 21       // per-node FP64 scratch fields of a stage solve
+#define HEVI_MAXTERMS 16  // max vectors in a linear combination
+
+// compact per-node operator fields (tile-interleaved, see hevi_kernels.hip)
+enum { OP_MINV = 0, OP_J = 1, OP_JTH = 2, OP_JCT = 3, OP_GX = 4, OP_GY = 5, OP_GZ = 6, OP_PHI = 7 };
+
+// 1D GLL weights and differentiation matrix D[i*(N+1)+j] = h_j'(xi_i)
+struct HeviTab {
+  double w[HEVI_MAXN + 1];
+  double D[(HEVI_MAXN + 1) * (HEVI_MAXN + 1)];
+};
+
+// kernel-side report of a call, reduced with device atomics
+struct HeviDevInfo {
+  int32_t status;          // worst status code seen
+  int32_t max_sweeps;      // refinement sweeps of the worst column
+  int64_t first_bad;       // lowest flagged column (INT64_MAX if none)
+  int64_t n_bad;           // number of flagged columns
+  uint64_t max_res_bits;   // bit pattern of the max (non-negative) relative residual
+};
+
+struct HeviTerms {         // sum_t coef[t] * v[t] over state vectors
+  int32_t n;
+  const double* v[HEVI_MAXTERMS];
+  double coef[HEVI_MAXTERMS];
+};
+
+struct HeviShapeDev {
+  int32_t N, Ne, nz;
+  int64_t ncols, ntiles;
+};
+
+hipError_t hevi_launch_build_ops(const HeviShapeDev& sh, const HeviTab& tab, double R, double cp,
+                                 double g, double pA, const double* z, const double* J,
+                                 const double* gz, const double* rho0, const double* Th0,
+                                 double* ops, HeviDevInfo* info, hipStream_t st);
+
+hipError_t hevi_launch_apply(const HeviShapeDev& sh, const HeviTab& tab, const double* ops,
+                             const double* x, const double* xref, double* y, hipStream_t st);
+
+// fp32 != 0 selects FP32 factor storage.  sbuf: FP64 assembly buffer of
+// (4N+1) entries per node (may alias Ub when FP64).
+hipError_t hevi_launch_factor(const HeviShapeDev& sh, const HeviTab& tab, double lambda, int fp32,
+                              const double* ops, double* sbuf, void* Ub, void* Lb, uint8_t* piv,
+                              HeviDevInfo* info, hipStream_t st);
+
+hipError_t hevi_launch_stage_solve(const HeviShapeDev& sh, const HeviTab& tab, double lambda,
+                                   int fp32, const double* ops, const void* Ub, const void* Lb,
+                                   const uint8_t* piv, double* ws, const HeviTerms& E,
+                                   const HeviTerms& Q, double* Qi, int max_sweeps,
+                                   double rel_target, int full_sweeps, HeviDevInfo* info,
+                                   hipStream_t st);
+
+hipError_t hevi_launch_combine(int64_t n, const HeviTerms& V, double* out, hipStream_t st);
+
+hipError_t hevi_launch_info_reset(HeviDevInfo* info, hipStream_t st);

@@ -1,0 +1,85 @@
+"""Device-resident column batches and the LHEVI ARK step as a sequence of C-ABI calls.
+
+Orchestration only: every arithmetic step runs in libhevi.so kernels
+(hevi_apply_op, hevi_factor / hevi_refactor, hevi_stage_solve, hevi_combine).
+The step follows the LHEVI ARK recipe (Sec. 4.1 stage and update formulas,
+Sec. 4.3 eq. lhevi-ark-final-3) with the explicit tendency
+S(q) = L_z (q - q_ref):
+
+    Q_1 = q^n;  for i >= 2:  c_j = (a~_ij - a_ij) / a~_ii,
+    Q_i = stage_solve(E = {q^n, S_1..S_{i-1}}, e = {1, dt a_i1, ...},
+                      Qprev = {Q_1..Q_{i-1}}, c),   S_i = L_z (Q_i - q_ref)
+    q^{n+1} = q^n + dt sum_i b_i S_i.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import hevi
+
+
+def to_dev(a, device="cuda"):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(device)
+
+
+class ColumnBatch:
+    """Device copies of one batch of columns and its compact operator."""
+
+    def __init__(self, ctx: hevi.Context, col: dict, device="cuda", stream=None):
+        self.ctx = ctx
+        self.N, self.Ne = int(col["N"]), int(col["Ne"])
+        self.nz = self.N * self.Ne + 1
+        self.ncols = int(col["z"].shape[1])
+        self.consts = tuple(float(v) for v in col["consts"])
+        self.z = to_dev(col["z"], device)
+        self.J = to_dev(col["J"], device)
+        self.gz = to_dev(col["gz"], device)
+        self.rho0 = to_dev(col["rho0"], device)
+        self.Theta0 = to_dev(col["Theta0"], device)
+        self.ops = ctx.build_column_ops(self.N, self.Ne, self.ncols, self.consts, self.z, self.J,
+                                        self.gz, self.rho0, self.Theta0, stream=stream)
+        self.device = device
+
+    def empty_state(self):
+        return torch.empty((5, self.nz, self.ncols), dtype=torch.float64, device=self.device)
+
+
+class ArkStepper:
+    """One LHEVI ARK time step per call, factors reused across stages."""
+
+    def __init__(self, ctx: hevi.Context, batch: ColumnBatch, tableau="ARK3", dt=300.0,
+                 precision=hevi.HEVI_FP64, refine=(4, 1e-13, 0), stream=None):
+        self.ctx, self.batch = ctx, batch
+        tab = hevi.tableau(tableau)
+        self.s = tab["s"]
+        self.Aexp, self.Aimp, self.b = tab["Aexp"], tab["Aimp"], tab["b"]
+        self.dt = float(dt)
+        self.lam = self.Aimp[1][1] * self.dt
+        self.precision = precision
+        self.refine = refine
+        self.Q = [batch.empty_state() for _ in range(self.s)]
+        self.S = [batch.empty_state() for _ in range(self.s)]
+        self.factors = ctx.factor(batch.ops, self.lam, precision, stream=stream)
+
+    def coeffs(self, i):
+        aii = self.Aimp[i][i]
+        return [(self.Aimp[i][j] - self.Aexp[i][j]) / aii for j in range(i)]
+
+    def step(self, qn, qref, out, refactor=True, info=False, stream=None):
+        ctx, ops = self.ctx, self.batch.ops
+        if refactor:
+            ctx.refactor(self.factors, self.lam, stream=stream)
+        infos = []
+        self.Q[0] = qn
+        ctx.apply_op(ops, qn, self.S[0], xref=qref, stream=stream)
+        for i in range(1, self.s):
+            E = [qn] + self.S[:i]
+            e = [1.0] + [self.dt * self.Aexp[i][j] for j in range(i)]
+            inf = ctx.stage_solve(self.factors, E, e, self.Q[:i], self.coeffs(i), self.Q[i],
+                                  refine=self.refine, info=info, stream=stream)
+            infos.append(inf)
+            ctx.apply_op(ops, self.Q[i], self.S[i], xref=qref, stream=stream)
+        ctx.combine(ops, [qn] + self.S, [1.0] + [self.dt * bi for bi in self.b], out,
+                    stream=stream)
+        return infos

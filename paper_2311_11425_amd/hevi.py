@@ -1,0 +1,266 @@
+"""Thin ctypes binding of the C ABI in include/hevi.h.
+
+Argument marshalling only: every step of the solve runs in the HIP kernels of
+libhevi.so.  Device buffers are torch tensors on a ROCm device (torch is used
+for device memory and streams only).  If the library is missing the import of
+this module fails loudly; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhevi.so")
+
+HEVI_FP64 = 0
+HEVI_FP32_REFINE = 1
+
+STATUS = {0: "HEVI_OK", 1: "HEVI_E_INVALID", 2: "HEVI_E_SHAPE", 3: "HEVI_E_NOMEM",
+          4: "HEVI_E_DEVICE", 5: "HEVI_E_SINGULAR", 6: "HEVI_E_NOT_CONVERGED", 7: "HEVI_E_BUSY",
+          8: "HEVI_E_CLOSED", 9: "HEVI_E_NONFINITE"}
+
+# every symbol include/hevi.h declares
+EXPORTS = ["hevi_create", "hevi_destroy", "hevi_status_str", "hevi_build_column_ops",
+           "hevi_ops_check", "hevi_ops_free", "hevi_apply_op", "hevi_factor", "hevi_refactor",
+           "hevi_factors_check", "hevi_factors_free", "hevi_stage_solve", "hevi_combine",
+           "hevi_tableau", "hevi_sizes"]
+
+
+class HeviError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: {STATUS.get(code, code)}")
+        self.code = code
+
+
+class Shape(ctypes.Structure):
+    _fields_ = [("order_N", ctypes.c_int32), ("n_elem", ctypes.c_int32), ("n_cols", ctypes.c_int64)]
+
+
+class Consts(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_double), ("cp", ctypes.c_double), ("g", ctypes.c_double),
+                ("p_A", ctypes.c_double)]
+
+
+class Refine(ctypes.Structure):
+    _fields_ = [("max_sweeps", ctypes.c_int32), ("rel_residual_target", ctypes.c_double),
+                ("full_sweeps", ctypes.c_int32)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("max_sweeps_used", ctypes.c_int32),
+                ("first_bad_col", ctypes.c_int64), ("n_bad_cols", ctypes.c_int64),
+                ("max_rel_correction", ctypes.c_double)]
+
+    def as_dict(self):
+        return {"status": STATUS.get(self.status, self.status), "max_sweeps_used": self.max_sweeps_used,
+                "first_bad_col": self.first_bad_col, "n_bad_cols": self.n_bad_cols,
+                "max_rel_correction": self.max_rel_correction}
+
+
+_vp = ctypes.c_void_p
+_lib = None
+
+
+def load():
+    """Load libhevi.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    # torch ships its own HIP runtime; load it first so that libhevi.so binds to
+    # the same runtime instance (one address space for device pointers)
+    import torch  # noqa: F401
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2311_11425_amd/build.py "
+                           "(no CPU fallback exists)")
+    lib = ctypes.CDLL(LIB_PATH)
+    i32, i64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    pp = ctypes.POINTER(_vp)
+    pd = ctypes.POINTER(dbl)
+    sig = {
+        "hevi_create": ([ctypes.c_int, pp], ctypes.c_int),
+        "hevi_destroy": ([_vp], None),
+        "hevi_status_str": ([ctypes.c_int], ctypes.c_char_p),
+        "hevi_build_column_ops": ([_vp, ctypes.POINTER(Shape), ctypes.POINTER(Consts), _vp, _vp, _vp,
+                                   _vp, _vp, pp, _vp], ctypes.c_int),
+        "hevi_ops_check": ([_vp, _vp, ctypes.POINTER(i64), _vp], ctypes.c_int),
+        "hevi_ops_free": ([_vp], None),
+        "hevi_apply_op": ([_vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+        "hevi_factor": ([_vp, _vp, dbl, ctypes.c_int, pp, _vp], ctypes.c_int),
+        "hevi_refactor": ([_vp, _vp, dbl, _vp], ctypes.c_int),
+        "hevi_factors_check": ([_vp, _vp, ctypes.POINTER(Info), _vp], ctypes.c_int),
+        "hevi_factors_free": ([_vp], None),
+        "hevi_stage_solve": ([_vp, _vp, i32, pp, pd, i32, pp, pd, _vp, ctypes.POINTER(Refine),
+                              ctypes.POINTER(Info), _vp], ctypes.c_int),
+        "hevi_combine": ([_vp, _vp, i32, pp, pd, _vp, _vp], ctypes.c_int),
+        "hevi_tableau": ([ctypes.c_char_p, ctypes.POINTER(i32), pd, pd, pd], ctypes.c_int),
+        "hevi_sizes": ([ctypes.POINTER(Shape), ctypes.c_int, ctypes.POINTER(ctypes.c_size_t),
+                        ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)],
+                       ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(code, what):
+    if code != 0:
+        raise HeviError(code, what)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr_array(ts):
+    arr = (_vp * max(1, len(ts)))()
+    for i, t in enumerate(ts):
+        arr[i] = t.data_ptr()
+    return arr
+
+
+def _dbl_array(vals):
+    arr = (ctypes.c_double * max(1, len(vals)))()
+    for i, v in enumerate(vals):
+        arr[i] = float(v)
+    return arr
+
+
+def tableau(name):
+    lib = load()
+    s = ctypes.c_int32(0)
+    a = (ctypes.c_double * 64)()
+    ai = (ctypes.c_double * 64)()
+    b = (ctypes.c_double * 8)()
+    _check(lib.hevi_tableau(name.encode(), ctypes.byref(s), a, ai, b), f"tableau {name}")
+    n = s.value
+    return {"name": name, "s": n,
+            "Aexp": [[a[i * n + j] for j in range(n)] for i in range(n)],
+            "Aimp": [[ai[i * n + j] for j in range(n)] for i in range(n)],
+            "b": [b[i] for i in range(n)]}
+
+
+def sizes(N, Ne, ncols=1, precision=HEVI_FP64):
+    lib = load()
+    sh = Shape(N, Ne, ncols)
+    o, f, p = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib.hevi_sizes(ctypes.byref(sh), precision, ctypes.byref(o), ctypes.byref(f),
+                          ctypes.byref(p)), "sizes")
+    return {"ops": o.value, "factors": f.value, "paper_band": p.value}
+
+
+class Ops:
+    def __init__(self, ctx, handle, shape, keep):
+        self.ctx, self.handle, self.shape, self._keep = ctx, handle, shape, keep
+
+    def check(self, stream=None):
+        bad = ctypes.c_int64(-1)
+        code = load().hevi_ops_check(self.ctx.handle, self.handle, ctypes.byref(bad), _stream(stream))
+        return code, bad.value
+
+    def free(self):
+        if self.handle:
+            load().hevi_ops_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Factors:
+    def __init__(self, ctx, handle, ops, precision, lam):
+        self.ctx, self.handle, self.ops, self.precision, self.lam = ctx, handle, ops, precision, lam
+
+    def check(self, stream=None):
+        inf = Info()
+        code = load().hevi_factors_check(self.ctx.handle, self.handle, ctypes.byref(inf),
+                                         _stream(stream))
+        return code, inf.as_dict()
+
+    def free(self):
+        if self.handle:
+            load().hevi_factors_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Context:
+    """One library context on one HIP device."""
+
+    def __init__(self, device=0):
+        self.lib = load()
+        h = ctypes.c_void_p()
+        _check(self.lib.hevi_create(device, ctypes.byref(h)), "hevi_create")
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            self.lib.hevi_destroy(self.handle)
+            self.handle = None
+
+    def build_column_ops(self, N, Ne, ncols, consts, z, J, gz, rho0, Theta0, stream=None):
+        sh = Shape(N, Ne, ncols)
+        k = Consts(*consts)
+        out = ctypes.c_void_p()
+        _check(self.lib.hevi_build_column_ops(self.handle, ctypes.byref(sh), ctypes.byref(k), _ptr(z),
+                                              _ptr(J), _ptr(gz), _ptr(rho0), _ptr(Theta0),
+                                              ctypes.byref(out), _stream(stream)),
+               "hevi_build_column_ops")
+        return Ops(self, out, (N, Ne, ncols), None)
+
+    def apply_op(self, ops, x, y, xref=None, stream=None):
+        _check(self.lib.hevi_apply_op(self.handle, ops.handle, _ptr(x), _ptr(xref), _ptr(y),
+                                      _stream(stream)), "hevi_apply_op")
+
+    def factor(self, ops, lam, precision=HEVI_FP64, stream=None):
+        out = ctypes.c_void_p()
+        _check(self.lib.hevi_factor(self.handle, ops.handle, float(lam), precision,
+                                    ctypes.byref(out), _stream(stream)), "hevi_factor")
+        return Factors(self, out, ops, precision, lam)
+
+    def refactor(self, f, lam, stream=None):
+        _check(self.lib.hevi_refactor(self.handle, f.handle, float(lam), _stream(stream)),
+               "hevi_refactor")
+        f.lam = lam
+
+    def stage_solve(self, f, E, e, Qprev, c, Qi, refine=None, info=False, stream=None):
+        """Qi <- one LHEVI stage (see include/hevi.h); returns the info dict if requested.
+
+        refine = (max_sweeps, rel_residual_target[, full_sweeps])."""
+        Ep, ep = _ptr_array(E), _dbl_array(e)
+        Qp, cp = _ptr_array(Qprev), _dbl_array(c)
+        ref = None
+        if refine is not None:
+            r = tuple(refine) + (0,) * (3 - len(refine))
+            ref = Refine(int(r[0]), float(r[1]), int(r[2]))
+        inf = Info() if info else None
+        _check(self.lib.hevi_stage_solve(self.handle, f.handle, len(E), Ep, ep, len(Qprev), Qp, cp,
+                                         _ptr(Qi), ctypes.byref(ref) if ref else None,
+                                         ctypes.byref(inf) if inf else None, _stream(stream)),
+               "hevi_stage_solve")
+        return inf.as_dict() if inf else None
+
+    def combine(self, ops, V, coef, out, stream=None):
+        _check(self.lib.hevi_combine(self.handle, ops.handle, len(V), _ptr_array(V), _dbl_array(coef),
+                                     _ptr(out), _stream(stream)), "hevi_combine")

@@ -1,0 +1,80 @@
+"""CPU-side checks of the C ABI: the library loads, exports every declared symbol,
+validates arguments without a GPU, and its tableaux/sizes agree with independent
+definitions.  No kernel is launched."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import tableaux as otab
+from paper_2311_11425_amd import hevi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "hevi.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hevi_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = hevi.load()
+    decl = declared_symbols()
+    assert len(decl) >= 15
+    for name in decl:
+        assert hasattr(lib, name), name
+    assert sorted(hevi.EXPORTS) == decl
+
+
+def test_status_strings():
+    lib = hevi.load()
+    for code in range(10):
+        s = lib.hevi_status_str(code)
+        assert s and s != b"unknown status"
+    assert lib.hevi_status_str(99) == b"unknown status"
+
+
+def test_create_rejects_missing_device():
+    lib = hevi.load()
+    h = ctypes.c_void_p()
+    code = lib.hevi_create(1000, ctypes.byref(h))
+    assert code == 4 and not h.value
+    assert lib.hevi_create(0, None) == 1
+
+
+@pytest.mark.parametrize("name,ref", [("ARK2", otab.ark2("b")), ("ARK2b", otab.ark2("b")),
+                                      ("ARK2a", otab.ark2("a")), ("ARK3", otab.ark3())])
+def test_tableau_matches_independent_transcription(name, ref):
+    t = hevi.tableau(name)
+    r = otab.as_float(ref)
+    assert t["s"] == len(r["b"])
+    assert np.allclose(t["Aexp"], r["Aexp"], rtol=0, atol=2e-16)
+    assert np.allclose(t["Aimp"], r["Aimp"], rtol=0, atol=2e-16)
+    assert np.allclose(t["b"], r["b"], rtol=0, atol=2e-16)
+
+
+def test_tableau_unknown():
+    with pytest.raises(hevi.HeviError):
+        hevi.tableau("RK4")
+
+
+def test_sizes():
+    s = hevi.sizes(4, 10)
+    nz = 41
+    assert s["ops"] == nz * 8 * 8
+    assert s["factors"] == nz * (17 + 8) * 8 + nz
+    assert hevi.sizes(4, 10, precision=1)["factors"] == nz * 25 * 4 + nz
+    # paper layout: LAPACK band with kl = ku = 5(N+1)-1, ldab = 2kl+ku+1 rows
+    n = 5 * nz
+    kl = 5 * 5 - 1
+    assert s["paper_band"] == n * (2 * kl + kl + 1) * 8 + 4 * n
+
+
+@pytest.mark.parametrize("N,Ne,nc", [(0, 4, 1), (9, 4, 1), (4, 0, 1), (4, 5000, 1), (4, 4, -1)])
+def test_sizes_rejects_bad_shapes(N, Ne, nc):
+    with pytest.raises(hevi.HeviError) as e:
+        hevi.sizes(N, Ne, nc)
+    assert e.value.code == 2
