@@ -246,19 +246,45 @@ __device__ void pg_pass(const HeviTab& tab, const OpsView& op, int Ne, double* w
 }
 
 // ---------------------------------------------------------------------------
+// Element-chunked kernels: a 256-thread block owns one 64-column tile; its four
+// wavefronts own contiguous chunks of elements [e0, e1) and the nodes
+// e0*N .. e1*N - 1 (plus the top node for the last chunk).  A node on a chunk
+// boundary also receives a contribution from the last element of the previous
+// chunk; the wavefront recomputes that element's contribution itself instead of
+// exchanging partial sums, so the four wavefronts run independently.
+constexpr int CW = 4;  // chunk wavefronts per tile
+
+struct Chunk {
+  int lane, e0, e1;
+  int64_t tile;
+};
+
+__device__ __forceinline__ Chunk chunk_of(int Ne) {
+  Chunk ch;
+  ch.lane = threadIdx.x & (T - 1);
+  const int wv = threadIdx.x / T;
+  const int ce = (Ne + CW - 1) / CW;
+  ch.e0 = wv * ce;
+  ch.e1 = min(Ne, ch.e0 + ce);
+  ch.tile = blockIdx.x;
+  return ch;
+}
+
 // a0: y = L_z (x - x_ref)
 template <int N>
-__global__ __launch_bounds__(64) void k_apply(HeviShapeDev sh, HeviTab tab,
-                                              const double* __restrict__ ops,
-                                              const double* __restrict__ x,
-                                              const double* __restrict__ xref,
-                                              double* __restrict__ y) {
-  const int lane = threadIdx.x;
-  const int64_t tile = blockIdx.x;
+__global__ __launch_bounds__(256) void k_apply(HeviShapeDev sh, HeviTab tab,
+                                               const double* __restrict__ ops,
+                                               const double* __restrict__ x,
+                                               const double* __restrict__ xref,
+                                               double* __restrict__ y) {
+  const int Ne = sh.Ne, nz = sh.nz;
+  const Chunk ch = chunk_of(Ne);
+  if (ch.e0 >= ch.e1) return;
+  const int lane = ch.lane;
+  const int64_t tile = ch.tile;
   const int64_t c = tile * T + lane;
   const bool valid = c < sh.ncols;
   const int64_t cc = valid ? c : sh.ncols - 1;
-  const int nz = sh.nz, Ne = sh.Ne;
   const int64_t nc = sh.ncols;
   OpsView op{ops, tile, nz, lane};
   auto X = [&](int v, int k) {
@@ -266,7 +292,7 @@ __global__ __launch_bounds__(64) void k_apply(HeviShapeDev sh, HeviTab tab,
     return xref ? x[i] - xref[i] : x[i];
   };
   double cr = 0.0, ct = 0.0, c0 = 0.0, c1 = 0.0, c2 = 0.0;
-  for (int e = 0; e < Ne; ++e) {
+  for (int e = max(ch.e0 - 1, 0); e < ch.e1; ++e) {
     double Ju[N + 1], Jtu[N + 1], f0[N + 1], f1[N + 1], f2[N + 1];
 #pragma unroll
     for (int j = 0; j <= N; ++j) {
@@ -292,6 +318,7 @@ __global__ __launch_bounds__(64) void k_apply(HeviShapeDev sh, HeviTab tab,
       st *= wa; s0 *= wa; s1 *= wa; s2 *= wa;
       if (a == 0) { sr += cr; st += ct; s0 += c0; s1 += c1; s2 += c2; }
       if (a == N && e < Ne - 1) { cr = sr; ct = st; c0 = s0; c1 = s1; c2 = s2; continue; }
+      if (e < ch.e0) continue;  // element recomputed for the boundary node only
       const int k = e * N + a;
       const double mi = op(k, OP_MINV);
       const bool lid = (k == 0) || (k == nz - 1);
@@ -335,25 +362,29 @@ __device__ __forceinline__ double s_entry(const double* sbuf, int64_t tile, int 
   return sbuf[tix(tile, nz, r, W, off, lane)] + (cabs == r ? 1.0 : 0.0);
 }
 
-template <int N, typename FT>
-__global__ __launch_bounds__(64) void k_factor(HeviShapeDev sh, HeviTab tab, double lambda,
-                                               const double* __restrict__ ops,
-                                               double* sbuf, FT* Ub,  // may alias (FP64)
-                                               FT* __restrict__ Lb, uint8_t* __restrict__ piv,
-                                               HeviDevInfo* info) {
+// Assembly of -lambda^2 K (element-chunked, see Chunk): row r of the band is
+// written once, by the wavefront owning node r.
+constexpr int CWF = 4;  // chunk wavefronts of the assembly kernel
+
+template <int N>
+__global__ __launch_bounds__(256) void k_factor_assemble(HeviShapeDev sh, HeviTab tab,
+                                                         double lambda,
+                                                         const double* __restrict__ ops,
+                                                         double* __restrict__ sbuf) {
   constexpr int B = 2 * N;          // half-bandwidth of S (kl = ku)
-  constexpr int W = 4 * N + 1;      // U row width kl + ku + 1 = S band width
+  constexpr int W = 4 * N + 1;      // S band width = U row width kl + ku + 1
   constexpr int NC = 3 * N + 1;     // columns touched by DTh rows of one element
-  const int lane = threadIdx.x;
-  const int64_t tile = blockIdx.x;
-  const int64_t c = tile * T + lane;
-  const bool valid = c < sh.ncols;
-  const int nz = sh.nz, Ne = sh.Ne;
+  const int Ne = sh.Ne, nz = sh.nz;
+  const Chunk ch = chunk_of(Ne);
+  if (ch.e0 >= ch.e1) return;
+  const int lane = ch.lane;
+  const int64_t tile = ch.tile;
   OpsView op{ops, tile, nz, lane};
   const double l2 = lambda * lambda;
-
-  // ---- assembly of -lambda^2 K, element by element ----
-  for (int e = 0; e < Ne; ++e) {
+  double carry[W];
+#pragma unroll
+  for (int o = 0; o < W; ++o) carry[o] = 0.0;
+  for (int e = max(ch.e0 - 1, 0); e < ch.e1; ++e) {
     // DTh rows of the element's nodes over columns (e-1)N .. (e+2)N
     double DT[N + 1][NC];
     double Jth[NC];
@@ -390,6 +421,7 @@ __global__ __launch_bounds__(64) void k_factor(HeviShapeDev sh, HeviTab tab, dou
     }
 #pragma unroll
     for (int a = 0; a <= N; ++a) {
+      if (e < ch.e0 && a < N) continue;  // only the boundary row of the recomputed element
       const int r = e * N + a;
       const double mr = op(r, OP_MINV), ph = op(r, OP_PHI);
       double acc[W];
@@ -406,68 +438,112 @@ __global__ __launch_bounds__(64) void k_factor(HeviShapeDev sh, HeviTab tab, dou
 #pragma unroll
       for (int i2 = 0; i2 <= N; ++i2)
         acc[B + i2 - a] += gr * tab.w[i2] * tab.D[i2 * (N + 1) + a] * jj[i2];
-      double* row = sbuf + tix(tile, nz, r, W, 0, lane);
-      if (a == 0 && e > 0) {
+      if (a == 0) {
 #pragma unroll
-        for (int o = 0; o < W; ++o) row[o * T] += -l2 * acc[o];
-      } else {
-#pragma unroll
-        for (int o = 0; o < W; ++o) row[o * T] = -l2 * acc[o];
+        for (int o = 0; o < W; ++o) acc[o] += carry[o];
       }
+      if (a == N && e < Ne - 1) {
+#pragma unroll
+        for (int o = 0; o < W; ++o) carry[o] = acc[o];
+        continue;
+      }
+      double* row = sbuf + tix(tile, nz, r, W, 0, lane);
+#pragma unroll
+      for (int o = 0; o < W; ++o) row[o * T] = -l2 * acc[o];
     }
   }
+}
 
-  // ---- band LU with partial pivoting over a (2N+1) x (4N+1) register window ----
-  // window row t, column s holds A(j+t, j+s) at step j
+// Band LU with partial pivoting of S over a (2N+1) x (4N+1) register window
+// (one lane per column).  Window row t, column s holds A(j+t, j+s) at step j;
+// the S rows entering the window are prefetched PFL rows ahead.
+template <int N>
+__device__ __forceinline__ double s_fix(int r, int nz, int s, double raw) {
+  // entry (r, r - 2N + s) of S from the stored -lambda^2 K value: identity rows
+  // at the rigid-lid nodes, zero columns for their (identically zero) unknowns
+  constexpr int B = 2 * N;
+  const int cabs = r - B + s;
+  if (r >= nz) return 0.0;
+  if (r == 0 || r == nz - 1) return s == B ? 1.0 : 0.0;
+  if (cabs <= 0 || cabs >= nz - 1) return 0.0;
+  return raw + (s == B ? 1.0 : 0.0);
+}
+
+template <int N, typename FT>
+__global__ __launch_bounds__(64) void k_factor_lu(HeviShapeDev sh, const double* sbuf,
+                                                  FT* Ub,  // may alias sbuf (FP64)
+                                                  FT* __restrict__ Lb, uint8_t* __restrict__ piv,
+                                                  HeviDevInfo* info) {
+  constexpr int B = 2 * N, W = 4 * N + 1, PFL = 2;
+  const int lane = threadIdx.x;
+  const int64_t tile = blockIdx.x;
+  const int64_t c = tile * T + lane;
+  const bool valid = c < sh.ncols;
+  const int nz = sh.nz;
   double Wn[B + 1][W];
 #pragma unroll
   for (int t = 0; t <= B; ++t)
 #pragma unroll
     for (int s = 0; s < W; ++s) Wn[t][s] = s_entry<N>(sbuf, tile, nz, lane, t, s);
+  double ring[PFL][W];
+#pragma unroll
+  for (int d = 0; d < PFL; ++d) {
+    const int r = min(B + 1 + d, nz - 1);
+#pragma unroll
+    for (int s = 0; s < W; ++s) ring[d][s] = sbuf[tix(tile, nz, r, W, s, lane)];
+  }
   bool singular = false;
-  for (int j = 0; j < nz; ++j) {
-    int p = 0;
-    double best = fabs(Wn[0][0]);
+  for (int j0 = 0; j0 < nz; j0 += PFL) {
 #pragma unroll
-    for (int t = 1; t <= B; ++t) {
-      const double v = fabs(Wn[t][0]);
-      if (j + t < nz && v > best) { best = v; p = t; }
+    for (int d = 0; d < PFL; ++d) {
+      const int j = j0 + d;
+      if (j < nz) {
+        int p = 0;
+        double best = fabs(Wn[0][0]);
+#pragma unroll
+        for (int t = 1; t <= B; ++t) {
+          const double v = fabs(Wn[t][0]);
+          if (j + t < nz && v > best) { best = v; p = t; }
+        }
+        if (!(best > 0.0)) { singular = true; Wn[0][0] = 1.0; p = 0; }
+#pragma unroll
+        for (int s = 0; s < W; ++s) {
+          const double v0 = Wn[0][s];
+          double vp = v0;
+#pragma unroll
+          for (int t = 1; t <= B; ++t) vp = (p == t) ? Wn[t][s] : vp;
+          Wn[0][s] = vp;
+#pragma unroll
+          for (int t = 1; t <= B; ++t) Wn[t][s] = (p == t) ? v0 : Wn[t][s];
+        }
+        piv[tix(tile, nz, j, 1, 0, lane)] = (uint8_t)p;
+        FT* urow = Ub + tix(tile, nz, j, W, 0, lane);
+#pragma unroll
+        for (int s = 0; s < W; ++s) urow[s * T] = (FT)Wn[0][s];
+        const double inv = 1.0 / Wn[0][0];
+        FT* lrow = Lb + tix(tile, nz, j, B, 0, lane);
+#pragma unroll
+        for (int t = 1; t <= B; ++t) {
+          const double l = Wn[t][0] * inv;
+          lrow[(t - 1) * T] = (FT)l;
+#pragma unroll
+          for (int s = 1; s < W; ++s) Wn[t][s] -= l * Wn[0][s];
+        }
+#pragma unroll
+        for (int t = 0; t < B; ++t) {
+#pragma unroll
+          for (int s = 0; s < W - 1; ++s) Wn[t][s] = Wn[t + 1][s + 1];
+          Wn[t][W - 1] = 0.0;
+        }
+        // new bottom row j + 2N + 1 from the ring; refill the slot
+        const int rn = j + B + 1;
+#pragma unroll
+        for (int s = 0; s < W; ++s) Wn[B][s] = s_fix<N>(rn, nz, s, ring[d][s]);
+        const int rf = min(rn + PFL, nz - 1);
+#pragma unroll
+        for (int s = 0; s < W; ++s) ring[d][s] = sbuf[tix(tile, nz, rf, W, s, lane)];
+      }
     }
-    if (!(best > 0.0)) { singular = true; Wn[0][0] = 1.0; p = 0; }
-    // swap rows 0 and p
-#pragma unroll
-    for (int s = 0; s < W; ++s) {
-      const double v0 = Wn[0][s];
-      double vp = v0;
-#pragma unroll
-      for (int t = 1; t <= B; ++t) vp = (p == t) ? Wn[t][s] : vp;
-      Wn[0][s] = vp;
-#pragma unroll
-      for (int t = 1; t <= B; ++t) Wn[t][s] = (p == t) ? v0 : Wn[t][s];
-    }
-    piv[tix(tile, nz, j, 1, 0, lane)] = (uint8_t)p;
-    FT* urow = Ub + tix(tile, nz, j, W, 0, lane);
-#pragma unroll
-    for (int s = 0; s < W; ++s) urow[s * T] = (FT)Wn[0][s];
-    const double inv = 1.0 / Wn[0][0];
-    FT* lrow = Lb + tix(tile, nz, j, B, 0, lane);
-#pragma unroll
-    for (int t = 1; t <= B; ++t) {
-      const double l = Wn[t][0] * inv;
-      lrow[(t - 1) * T] = (FT)l;
-#pragma unroll
-      for (int s = 1; s < W; ++s) Wn[t][s] -= l * Wn[0][s];
-    }
-    // advance the window one row and one column
-#pragma unroll
-    for (int t = 0; t < B; ++t) {
-#pragma unroll
-      for (int s = 0; s < W - 1; ++s) Wn[t][s] = Wn[t + 1][s + 1];
-      Wn[t][W - 1] = 0.0;
-    }
-    const int rn = j + B + 1;
-#pragma unroll
-    for (int s = 0; s < W; ++s) Wn[B][s] = s_entry<N>(sbuf, tile, nz, lane, rn, j + 1 + s);
   }
   if (singular && valid) flag(info, 5 /*HEVI_E_SINGULAR*/, c);
 }
@@ -482,46 +558,93 @@ __global__ __launch_bounds__(64) void k_factor(HeviShapeDev sh, HeviTab tab, dou
 enum { WS_R = 0, WS_U = 1, WS_VR = 2, WS_VT = 3, WS_T = 4, WS_D = 5, WS_B = 6, WS_X = 11,
        WS_S = 16 };
 
-// solve S x = rhs with the band LU factors (rhs field fi, result field fo)
+// solve S x = rhs with the band LU factors (rhs field fi, result field fo).
+// The sweeps are sequential in the row index, so each wavefront keeps the
+// factor rows of the next rows in flight (PF forward, PB backward) (software prefetch into a register
+// ring, refilled as soon as a slot is consumed) while it works on the current one.
 template <int N, typename FT>
 __device__ void band_solve(const FT* __restrict__ Ub, const FT* __restrict__ Lb,
                            const uint8_t* __restrict__ piv, double* ws, int64_t tile, int nz,
                            int lane, int fi, int fo) {
-  constexpr int B = 2 * N, K = 4 * N;
+  constexpr int B = 2 * N, K = 4 * N, PF = 3, PB = 2;
+  // ---- forward: row swaps and unit-lower elimination ----
   double y[B + 1];
 #pragma unroll
   for (int t = 0; t <= B; ++t) y[t] = (t < nz) ? ws[tix(tile, nz, t, HEVI_NWS, fi, lane)] : 0.0;
-  for (int j = 0; j < nz; ++j) {
-    const int p = piv[tix(tile, nz, j, 1, 0, lane)];
-    const double v0 = y[0];
-    double vp = v0;
+  double lr[PF][B], rin[PF];
+  int pv[PF];
 #pragma unroll
-    for (int t = 1; t <= B; ++t) vp = (p == t) ? y[t] : vp;
+  for (int d = 0; d < PF; ++d) {
+    const int jj = d < nz ? d : nz - 1;
+    pv[d] = piv[tix(tile, nz, jj, 1, 0, lane)];
 #pragma unroll
-    for (int t = 1; t <= B; ++t) y[t] = (p == t) ? v0 : y[t];
-    y[0] = vp;
-    ws[tix(tile, nz, j, HEVI_NWS, fo, lane)] = vp;
-    const FT* lrow = Lb + tix(tile, nz, j, B, 0, lane);
-#pragma unroll
-    for (int t = 1; t <= B; ++t) y[t] -= ld(lrow + (t - 1) * T) * vp;
-#pragma unroll
-    for (int t = 0; t < B; ++t) y[t] = y[t + 1];
-    const int rn = j + B + 1;
-    y[B] = (rn < nz) ? ws[tix(tile, nz, rn, HEVI_NWS, fi, lane)] : 0.0;
+    for (int t = 0; t < B; ++t) lr[d][t] = ld(Lb + tix(tile, nz, jj, B, t, lane));
+    const int rn = d + B + 1;
+    rin[d] = (rn < nz) ? ws[tix(tile, nz, rn, HEVI_NWS, fi, lane)] : 0.0;
   }
+  for (int j0 = 0; j0 < nz; j0 += PF) {
+#pragma unroll
+    for (int d = 0; d < PF; ++d) {
+      const int j = j0 + d;
+      if (j < nz) {
+        const int p = pv[d];
+        const double v0 = y[0];
+        double vp = v0;
+#pragma unroll
+        for (int t = 1; t <= B; ++t) vp = (p == t) ? y[t] : vp;
+#pragma unroll
+        for (int t = 1; t <= B; ++t) y[t] = (p == t) ? v0 : y[t];
+        ws[tix(tile, nz, j, HEVI_NWS, fo, lane)] = vp;
+#pragma unroll
+        for (int t = 1; t <= B; ++t) y[t] -= lr[d][t - 1] * vp;
+#pragma unroll
+        for (int t = 0; t < B; ++t) y[t] = y[t + 1];
+        y[B] = rin[d];
+        // refill the consumed slot with row j + PF
+        const int jn = j + PF;
+        const int jj = jn < nz ? jn : nz - 1;
+        pv[d] = piv[tix(tile, nz, jj, 1, 0, lane)];
+#pragma unroll
+        for (int t = 0; t < B; ++t) lr[d][t] = ld(Lb + tix(tile, nz, jj, B, t, lane));
+        const int rn = jn + B + 1;
+        rin[d] = (rn < nz) ? ws[tix(tile, nz, rn, HEVI_NWS, fi, lane)] : 0.0;
+      }
+    }
+  }
+  // ---- backward: upper-triangular substitution ----
   double xw[K + 1];
 #pragma unroll
   for (int t = 0; t <= K; ++t) xw[t] = 0.0;
-  for (int j = nz - 1; j >= 0; --j) {
-    const FT* urow = Ub + tix(tile, nz, j, K + 1, 0, lane);
-    double s = ws[tix(tile, nz, j, HEVI_NWS, fo, lane)];
+  double ur[PB][K + 1], yin[PB];
 #pragma unroll
-    for (int t = 1; t <= K; ++t) s -= ld(urow + t * T) * xw[t];
-    const double xj = s / ld(urow);
-    ws[tix(tile, nz, j, HEVI_NWS, fo, lane)] = xj;
+  for (int d = 0; d < PB; ++d) {
+    const int jr = nz - 1 - d;
+    const int jj = jr >= 0 ? jr : 0;
 #pragma unroll
-    for (int t = K; t >= 2; --t) xw[t] = xw[t - 1];
-    xw[1] = xj;
+    for (int t = 0; t <= K; ++t) ur[d][t] = ld(Ub + tix(tile, nz, jj, K + 1, t, lane));
+    yin[d] = ws[tix(tile, nz, jj, HEVI_NWS, fo, lane)];
+  }
+  for (int j0 = nz - 1; j0 >= 0; j0 -= PB) {
+#pragma unroll
+    for (int d = 0; d < PB; ++d) {
+      const int j = j0 - d;
+      if (j >= 0) {
+        double s = yin[d];
+#pragma unroll
+        for (int t = 1; t <= K; ++t) s -= ur[d][t] * xw[t];
+        const double xj = s / ur[d][0];
+        ws[tix(tile, nz, j, HEVI_NWS, fo, lane)] = xj;
+#pragma unroll
+        for (int t = K; t >= 2; --t) xw[t] = xw[t - 1];
+        xw[1] = xj;
+        // refill the consumed slot with row j - PB
+        const int jr = j - PB;
+        const int jj = jr >= 0 ? jr : 0;
+#pragma unroll
+        for (int t = 0; t <= K; ++t) ur[d][t] = ld(Ub + tix(tile, nz, jj, K + 1, t, lane));
+        yin[d] = ws[tix(tile, nz, jj, HEVI_NWS, fo, lane)];
+      }
+    }
   }
 }
 
@@ -737,7 +860,7 @@ __device__ void residual_pass(const HeviTab& tab, const OpsView& op, int Ne, dou
   }
 }
 
-template <int N, typename FT>
+template <int N, typename FT, bool FULL>
 __global__ __launch_bounds__(64) void k_stage_solve(HeviShapeDev sh, HeviTab tab, double lambda,
                                                     const double* __restrict__ ops,
                                                     const FT* __restrict__ Ub,
@@ -756,25 +879,37 @@ __global__ __launch_bounds__(64) void k_stage_solve(HeviShapeDev sh, HeviTab tab
   const int64_t nc = sh.ncols;
   OpsView op{ops, tile, nz, lane};
   bool nonfinite = false;
-  const bool full = full_sweeps > 0;
+  const bool full = FULL;
 
   // ---- pass 1: q^E, q^ = q^E + sum c_j Q_j, reduced right-hand side r ----
   double c0 = 0.0, c1 = 0.0, c2 = 0.0;
   for (int e = 0; e < Ne; ++e) {
+    // q^E and q^ at the element's nodes; the term loop is outermost so that
+    // each term issues (N+1)*5 independent coalesced loads
     double qE[N + 1][5], b[N + 1][5];
 #pragma unroll
-    for (int j = 0; j <= N; ++j) {
-      const int k = e * N + j;
+    for (int j = 0; j <= N; ++j)
 #pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        const size_t i = cix(nz, nc, v, k, cc);
-        double s = 0.0;
-        for (int t = 0; t < E.n; ++t) s += E.coef[t] * E.v[t][i];
-        double sb = s;
-        for (int t = 0; t < Q.n; ++t) sb += Q.coef[t] * Q.v[t][i];
-        qE[j][v] = s;
-        b[j][v] = sb;
-      }
+      for (int v = 0; v < 5; ++v) qE[j][v] = 0.0;
+    for (int t = 0; t < E.n; ++t) {
+      const double* src = E.v[t];
+      const double cf = E.coef[t];
+#pragma unroll
+      for (int j = 0; j <= N; ++j)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) qE[j][v] += cf * src[cix(nz, nc, v, e * N + j, cc)];
+    }
+#pragma unroll
+    for (int j = 0; j <= N; ++j)
+#pragma unroll
+      for (int v = 0; v < 5; ++v) b[j][v] = qE[j][v];
+    for (int t = 0; t < Q.n; ++t) {
+      const double* src = Q.v[t];
+      const double cf = Q.coef[t];
+#pragma unroll
+      for (int j = 0; j <= N; ++j)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) b[j][v] += cf * src[cix(nz, nc, v, e * N + j, cc)];
     }
     double f0[N + 1], f1[N + 1], f2[N + 1];
 #pragma unroll
@@ -837,7 +972,7 @@ __global__ __launch_bounds__(64) void k_stage_solve(HeviShapeDev sh, HeviTab tab
     reduced_refine<N, FT>(tab, op, Ne, ws, tile, lane, valid, lambda, Ub, Lb, piv, max_sweeps,
                           rel_target, &sweeps, &relres);
 
-  if (!full) {
+  if constexpr (!FULL) {
     // ---- pass 3: recover rho, Theta and momentum; Q_i = q^E + lambda L_z x ----
     div_pass<N>(tab, op, Ne, ws, tile, lane, WS_U, WS_VR, WS_VT);
     pg_pass<N, 1>(tab, op, Ne, ws, tile, lane, WS_VR, WS_VT, 0, lambda, Qi, nc, c, valid,
@@ -882,6 +1017,262 @@ __global__ __launch_bounds__(64) void k_stage_solve(HeviShapeDev sh, HeviTab tab
       const double rr = isfinite(relres) ? relres : 1.0e300;
       atomicMax((unsigned long long*)&info->max_res_bits,
                 (unsigned long long)__double_as_longlong(rr));
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fast stage solve as three kernels: k_stage_rhs (element-chunked),
+// k_stage_bsolve (one lane per column), k_stage_update (element-chunked).
+
+// pass 1: q^E = sum e_t E_t and q^ = q^E + sum c_j Q_j at the owned nodes; writes
+// Q_i <- (q^E_rho, q^E_U + lambda (PG q^_Theta - Phi' grad(zeta) q^_rho), q^E_Theta)
+// (at the lid: Q_U <- q^E_U - n (n . q^_U)) and the reduced right-hand side
+// r = grad(zeta).(q^_U + lambda (PG q^_Theta - Phi' grad(zeta) q^_rho)) (0 at the lid).
+template <int N>
+__global__ __launch_bounds__(256, 2) void k_stage_rhs(HeviShapeDev sh, HeviTab tab, double lambda,
+                                                   const double* __restrict__ ops,
+                                                   double* __restrict__ ws, HeviTerms E,
+                                                   HeviTerms Q, double* __restrict__ Qi) {
+  const int Ne = sh.Ne, nz = sh.nz;
+  const Chunk ch = chunk_of(Ne);
+  if (ch.e0 >= ch.e1) return;
+  const int lane = ch.lane;
+  const int64_t tile = ch.tile;
+  const int64_t c = tile * T + lane;
+  const bool valid = c < sh.ncols;
+  const int64_t cc = valid ? c : sh.ncols - 1;
+  const int64_t nc = sh.ncols;
+  OpsView op{ops, tile, nz, lane};
+  if (ch.e0 == 0) ws[tix(tile, nz, 0, HEVI_NWS, WS_T, lane)] = 0.0;  // per-column flag
+  double c0 = 0.0, c1 = 0.0, c2 = 0.0;
+  for (int e = max(ch.e0 - 1, 0); e < ch.e1; ++e) {
+    // q^_Theta at the element's nodes
+    double bt[N + 1];
+#pragma unroll
+    for (int j = 0; j <= N; ++j) bt[j] = 0.0;
+    for (int t = 0; t < E.n; ++t) {
+      const double* src = E.v[t];
+      const double cf = E.coef[t];
+#pragma unroll
+      for (int j = 0; j <= N; ++j) bt[j] += cf * src[cix(nz, nc, 4, e * N + j, cc)];
+    }
+    for (int t = 0; t < Q.n; ++t) {
+      const double* src = Q.v[t];
+      const double cf = Q.coef[t];
+#pragma unroll
+      for (int j = 0; j <= N; ++j) bt[j] += cf * src[cix(nz, nc, 4, e * N + j, cc)];
+    }
+    double f0[N + 1], f1[N + 1], f2[N + 1];
+#pragma unroll
+    for (int j = 0; j <= N; ++j) {
+      const int k = e * N + j;
+      const double p = op(k, OP_JCT) * bt[j];
+      f0[j] = p * op(k, OP_GX); f1[j] = p * op(k, OP_GY); f2[j] = p * op(k, OP_GZ);
+    }
+#pragma unroll
+    for (int a = 0; a <= N; ++a) {
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+      for (int j = 0; j <= N; ++j) {
+        const double d = tab.D[a * (N + 1) + j];
+        s0 += d * f0[j]; s1 += d * f1[j]; s2 += d * f2[j];
+      }
+      s0 *= tab.w[a]; s1 *= tab.w[a]; s2 *= tab.w[a];
+      if (a == 0) { s0 += c0; s1 += c1; s2 += c2; }
+      if (a == N && e < Ne - 1) { c0 = s0; c1 = s1; c2 = s2; continue; }
+      if (e < ch.e0) continue;
+      const int k = e * N + a;
+      // q^E and q^ at node k
+      double qE[5], b[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) qE[v] = 0.0;
+      for (int t = 0; t < E.n; ++t) {
+        const double* src = E.v[t];
+        const double cf = E.coef[t];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) qE[v] += cf * src[cix(nz, nc, v, k, cc)];
+      }
+#pragma unroll
+      for (int v = 0; v < 5; ++v) b[v] = qE[v];
+      for (int t = 0; t < Q.n; ++t) {
+        const double* src = Q.v[t];
+        const double cf = Q.coef[t];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) b[v] += cf * src[cix(nz, nc, v, k, cc)];
+      }
+      const double gx = op(k, OP_GX), gy = op(k, OP_GY), gzz = op(k, OP_GZ);
+      double h1, h2, h3, r;
+      if (k == 0 || k == nz - 1) {
+        const double inv = 1.0 / sqrt(gx * gx + gy * gy + gzz * gzz);
+        const double n0 = gx * inv, n1 = gy * inv, n2 = gzz * inv;
+        const double d = n0 * b[1] + n1 * b[2] + n2 * b[3];
+        h1 = qE[1] - n0 * d; h2 = qE[2] - n1 * d; h3 = qE[3] - n2 * d;
+        r = 0.0;
+      } else {
+        const double mi = op(k, OP_MINV), ph = op(k, OP_PHI);
+        const double g1 = lambda * (-mi * s0 - ph * gx * b[0]);
+        const double g2 = lambda * (-mi * s1 - ph * gy * b[0]);
+        const double g3 = lambda * (-mi * s2 - ph * gzz * b[0]);
+        h1 = qE[1] + g1; h2 = qE[2] + g2; h3 = qE[3] + g3;
+        r = gx * (b[1] + g1) + gy * (b[2] + g2) + gzz * (b[3] + g3);
+      }
+      ws[tix(tile, nz, k, HEVI_NWS, WS_R, lane)] = r;
+      if (valid) {
+        Qi[cix(nz, nc, 0, k, c)] = qE[0];
+        Qi[cix(nz, nc, 1, k, c)] = h1;
+        Qi[cix(nz, nc, 2, k, c)] = h2;
+        Qi[cix(nz, nc, 3, k, c)] = h3;
+        Qi[cix(nz, nc, 4, k, c)] = qE[4];
+      }
+    }
+  }
+}
+
+// pass 2: S u = r, one lane per column (+ reduced FP64 refinement for FP32 factors)
+template <int N, typename FT, bool REFINE>
+__global__ __launch_bounds__(64, 8) void k_stage_bsolve(HeviShapeDev sh, HeviTab tab, double lambda,
+                                                     const double* __restrict__ ops,
+                                                     const FT* __restrict__ Ub,
+                                                     const FT* __restrict__ Lb,
+                                                     const uint8_t* __restrict__ piv,
+                                                     double* __restrict__ ws, int max_sweeps,
+                                                     double rel_target, HeviDevInfo* info) {
+  const int lane = threadIdx.x;
+  const int64_t tile = blockIdx.x;
+  const int64_t c = tile * T + lane;
+  const bool valid = c < sh.ncols;
+  const int nz = sh.nz;
+  band_solve<N, FT>(Ub, Lb, piv, ws, tile, nz, lane, WS_R, WS_U);
+  if (REFINE && max_sweeps > 0) {
+    OpsView op{ops, tile, nz, lane};
+    int sweeps = 0;
+    double corr = 0.0;
+    reduced_refine<N, FT>(tab, op, sh.Ne, ws, tile, lane, valid, lambda, Ub, Lb, piv, max_sweeps,
+                          rel_target, &sweeps, &corr);
+    if (valid) {
+      if (!(corr <= rel_target)) flag(info, 6 /*HEVI_E_NOT_CONVERGED*/, c);
+      atomicMax(&info->max_sweeps, sweeps);
+      const double rr = isfinite(corr) ? corr : 1.0e300;
+      atomicMax((unsigned long long*)&info->max_res_bits,
+                (unsigned long long)__double_as_longlong(rr));
+    }
+  }
+}
+
+// div contributions of element ee to its nodes: sr[a] = sum_j w_j D_ja (J u)_j,
+// st[a] = w_a sum_j D_aj (J theta0 u)_j, u from scratch field WS_U
+template <int N>
+__device__ __forceinline__ void elem_div(const HeviTab& tab, const OpsView& op, const double* ws,
+                                         int64_t tile, int lane, int ee, double* sr, double* st) {
+  const int nz = op.nz;
+  double Ju[N + 1], Jtu[N + 1];
+#pragma unroll
+  for (int j = 0; j <= N; ++j) {
+    const int k = ee * N + j;
+    const double u = ws[tix(tile, nz, k, HEVI_NWS, WS_U, lane)];
+    Ju[j] = op(k, OP_J) * u;
+    Jtu[j] = op(k, OP_JTH) * u;
+  }
+#pragma unroll
+  for (int a = 0; a <= N; ++a) {
+    double r = 0.0, t = 0.0;
+#pragma unroll
+    for (int j = 0; j <= N; ++j) {
+      r += tab.w[j] * tab.D[j * (N + 1) + a] * Ju[j];
+      t += tab.D[a * (N + 1) + j] * Jtu[j];
+    }
+    sr[a] = r;
+    st[a] = tab.w[a] * t;
+  }
+}
+
+// pass 3: v_rho = Drho u, v_Th = DTh u; Q_i += (lambda v_rho,
+// lambda^2 (PG v_Th - Phi' grad(zeta) v_rho) [interior], lambda v_Th)
+template <int N>
+__global__ __launch_bounds__(256, 2) void k_stage_update(HeviShapeDev sh, HeviTab tab,
+                                                      double lambda,
+                                                      const double* __restrict__ ops,
+                                                      double* __restrict__ ws,
+                                                      double* __restrict__ Qi,
+                                                      HeviDevInfo* info) {
+  const int Ne = sh.Ne, nz = sh.nz;
+  const Chunk ch = chunk_of(Ne);
+  if (ch.e0 >= ch.e1) return;
+  const int lane = ch.lane;
+  const int64_t tile = ch.tile;
+  const int64_t c = tile * T + lane;
+  const bool valid = c < sh.ncols;
+  const int64_t nc = sh.ncols;
+  OpsView op{ops, tile, nz, lane};
+  const double l2 = lambda * lambda;
+  bool nonfinite = false;
+  double c0 = 0.0, c1 = 0.0, c2 = 0.0;
+  for (int e = max(ch.e0 - 1, 0); e < ch.e1; ++e) {
+    // v_rho, v_Th at the nodes of element e, summed over all their elements
+    double sr[N + 1], st[N + 1], pr[N + 1], pt[N + 1];
+    elem_div<N>(tab, op, ws, tile, lane, e, sr, st);
+    if (e > 0) {
+      elem_div<N>(tab, op, ws, tile, lane, e - 1, pr, pt);
+      sr[0] += pr[N]; st[0] += pt[N];
+    }
+    if (e < Ne - 1) {
+      elem_div<N>(tab, op, ws, tile, lane, e + 1, pr, pt);
+      sr[N] += pr[0]; st[N] += pt[0];
+    }
+    double vr[N + 1], f0[N + 1], f1[N + 1], f2[N + 1];
+#pragma unroll
+    for (int j = 0; j <= N; ++j) {
+      const int k = e * N + j;
+      const double mi = op(k, OP_MINV);
+      vr[j] = mi * sr[j];
+      st[j] = -mi * st[j];  // v_Th
+      const double p = op(k, OP_JCT) * st[j];
+      f0[j] = p * op(k, OP_GX); f1[j] = p * op(k, OP_GY); f2[j] = p * op(k, OP_GZ);
+    }
+#pragma unroll
+    for (int a = 0; a <= N; ++a) {
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+      for (int j = 0; j <= N; ++j) {
+        const double d = tab.D[a * (N + 1) + j];
+        s0 += d * f0[j]; s1 += d * f1[j]; s2 += d * f2[j];
+      }
+      s0 *= tab.w[a]; s1 *= tab.w[a]; s2 *= tab.w[a];
+      if (a == 0) { s0 += c0; s1 += c1; s2 += c2; }
+      if (a == N && e < Ne - 1) { c0 = s0; c1 = s1; c2 = s2; continue; }
+      if (e < ch.e0 || !valid) continue;
+      const int k = e * N + a;
+      const size_t i0 = cix(nz, nc, 0, k, c), i4 = cix(nz, nc, 4, k, c);
+      const double qr = Qi[i0] + lambda * vr[a];
+      const double qt = Qi[i4] + lambda * st[a];
+      Qi[i0] = qr;
+      Qi[i4] = qt;
+      bool fin = isfinite(qr) && isfinite(qt);
+      if (k != 0 && k != nz - 1) {
+        const double mi = op(k, OP_MINV), ph = op(k, OP_PHI);
+        const size_t i1 = cix(nz, nc, 1, k, c), i2 = cix(nz, nc, 2, k, c),
+                     i3 = cix(nz, nc, 3, k, c);
+        const double q1 = Qi[i1] + l2 * (-mi * s0 - ph * op(k, OP_GX) * vr[a]);
+        const double q2 = Qi[i2] + l2 * (-mi * s1 - ph * op(k, OP_GY) * vr[a]);
+        const double q3 = Qi[i3] + l2 * (-mi * s2 - ph * op(k, OP_GZ) * vr[a]);
+        Qi[i1] = q1; Qi[i2] = q2; Qi[i3] = q3;
+        fin = fin && isfinite(q1) && isfinite(q2) && isfinite(q3);
+      } else {
+        fin = fin && isfinite(Qi[cix(nz, nc, 1, k, c)]) && isfinite(Qi[cix(nz, nc, 2, k, c)]) &&
+              isfinite(Qi[cix(nz, nc, 3, k, c)]);
+      }
+      if (!fin) nonfinite = true;
+    }
+  }
+  if (nonfinite) {
+    // count each column once: the first wavefront to flag it wins the exchange
+    unsigned long long* fl =
+        (unsigned long long*)&ws[tix(tile, nz, 0, HEVI_NWS, WS_T, lane)];
+    if (atomicCAS(fl, 0ull, 1ull) == 0ull) flag(info, 9 /*HEVI_E_NONFINITE*/, c);
+    else {
+      atomicMax(&info->status, 9);
+      atomicMin((unsigned long long*)&info->first_bad, (unsigned long long)c);
     }
   }
 }
@@ -937,7 +1328,7 @@ template <int N>
 struct Apply {
   static hipError_t run(const HeviShapeDev& sh, const HeviTab& tab, const double* ops,
                         const double* x, const double* xref, double* y, hipStream_t st) {
-    hipLaunchKernelGGL(k_apply<N>, dim3((unsigned)sh.ntiles), dim3(T), 0, st, sh, tab, ops, x,
+    hipLaunchKernelGGL(k_apply<N>, dim3((unsigned)sh.ntiles), dim3(T * CW), 0, st, sh, tab, ops, x,
                        xref, y);
     return hipGetLastError();
   }
@@ -948,12 +1339,14 @@ struct Factor {
   static hipError_t run(const HeviShapeDev& sh, const HeviTab& tab, double lambda, int fp32,
                         const double* ops, double* sbuf, void* Ub, void* Lb, uint8_t* piv,
                         HeviDevInfo* info, hipStream_t st) {
+    const dim3 g((unsigned)sh.ntiles);
+    hipLaunchKernelGGL(k_factor_assemble<N>, g, dim3(T * CWF), 0, st, sh, tab, lambda, ops, sbuf);
     if (fp32)
-      hipLaunchKernelGGL((k_factor<N, float>), dim3((unsigned)sh.ntiles), dim3(T), 0, st, sh, tab,
-                         lambda, ops, sbuf, (float*)Ub, (float*)Lb, piv, info);
+      hipLaunchKernelGGL((k_factor_lu<N, float>), g, dim3(T), 0, st, sh, sbuf, (float*)Ub,
+                         (float*)Lb, piv, info);
     else
-      hipLaunchKernelGGL((k_factor<N, double>), dim3((unsigned)sh.ntiles), dim3(T), 0, st, sh, tab,
-                         lambda, ops, sbuf, (double*)Ub, (double*)Lb, piv, info);
+      hipLaunchKernelGGL((k_factor_lu<N, double>), g, dim3(T), 0, st, sh, sbuf, (double*)Ub,
+                         (double*)Lb, piv, info);
     return hipGetLastError();
   }
 };
@@ -965,14 +1358,27 @@ struct StageSolve {
                         double* ws, const HeviTerms& E, const HeviTerms& Q, double* Qi,
                         int max_sweeps, double rel_target, int full_sweeps, HeviDevInfo* info,
                         hipStream_t st) {
+    const dim3 g((unsigned)sh.ntiles), b(T), b4(T * CW);
+    if (full_sweeps > 0) {
+      // accuracy mode: one kernel with the full-system refinement sweeps
+      if (fp32)
+        hipLaunchKernelGGL((k_stage_solve<N, float, true>), g, b, 0, st, sh, tab, lambda, ops,
+                           (const float*)Ub, (const float*)Lb, piv, ws, E, Q, Qi, max_sweeps,
+                           rel_target, full_sweeps, info);
+      else
+        hipLaunchKernelGGL((k_stage_solve<N, double, true>), g, b, 0, st, sh, tab, lambda, ops,
+                           (const double*)Ub, (const double*)Lb, piv, ws, E, Q, Qi, 0, rel_target,
+                           full_sweeps, info);
+      return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_stage_rhs<N>, g, b4, 0, st, sh, tab, lambda, ops, ws, E, Q, Qi);
     if (fp32)
-      hipLaunchKernelGGL((k_stage_solve<N, float>), dim3((unsigned)sh.ntiles), dim3(T), 0, st, sh,
-                         tab, lambda, ops, (const float*)Ub, (const float*)Lb, piv, ws, E, Q, Qi,
-                         max_sweeps, rel_target, full_sweeps, info);
+      hipLaunchKernelGGL((k_stage_bsolve<N, float, true>), g, b, 0, st, sh, tab, lambda, ops,
+                         (const float*)Ub, (const float*)Lb, piv, ws, max_sweeps, rel_target, info);
     else
-      hipLaunchKernelGGL((k_stage_solve<N, double>), dim3((unsigned)sh.ntiles), dim3(T), 0, st,
-                         sh, tab, lambda, ops, (const double*)Ub, (const double*)Lb, piv, ws, E,
-                         Q, Qi, 0, rel_target, full_sweeps, info);
+      hipLaunchKernelGGL((k_stage_bsolve<N, double, false>), g, b, 0, st, sh, tab, lambda, ops,
+                         (const double*)Ub, (const double*)Lb, piv, ws, 0, rel_target, info);
+    hipLaunchKernelGGL(k_stage_update<N>, g, b4, 0, st, sh, tab, lambda, ops, ws, Qi, info);
     return hipGetLastError();
   }
 };
