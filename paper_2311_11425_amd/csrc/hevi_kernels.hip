@@ -252,7 +252,7 @@ __device__ void pg_pass(const HeviTab& tab, const OpsView& op, int Ne, double* w
 // boundary also receives a contribution from the last element of the previous
 // chunk; the wavefront recomputes that element's contribution itself instead of
 // exchanging partial sums, so the four wavefronts run independently.
-constexpr int CW = 4;  // chunk wavefronts per tile
+constexpr int CW = 1;  // chunk wavefronts per tile
 
 struct Chunk {
   int lane, e0, e1;
@@ -270,9 +270,11 @@ __device__ __forceinline__ Chunk chunk_of(int Ne) {
   return ch;
 }
 
-// a0: y = L_z (x - x_ref)
-template <int N>
-__global__ __launch_bounds__(256) void k_apply(HeviShapeDev sh, HeviTab tab,
+// a0: y = L_z (x - x_ref).  Each element iteration loads everything it needs
+// unconditionally (clamped indices), computes, then stores the owned nodes, so
+// the loads of an element are in flight together.
+template <int N, bool HAS_REF>
+__global__ __launch_bounds__(64) void k_apply(HeviShapeDev sh, HeviTab tab,
                                                const double* __restrict__ ops,
                                                const double* __restrict__ x,
                                                const double* __restrict__ xref,
@@ -289,21 +291,34 @@ __global__ __launch_bounds__(256) void k_apply(HeviShapeDev sh, HeviTab tab,
   OpsView op{ops, tile, nz, lane};
   auto X = [&](int v, int k) {
     const size_t i = cix(nz, nc, v, k, cc);
-    return xref ? x[i] - xref[i] : x[i];
+    if constexpr (HAS_REF) return x[i] - xref[i];
+    else return x[i];
   };
   double cr = 0.0, ct = 0.0, c0 = 0.0, c1 = 0.0, c2 = 0.0;
   for (int e = max(ch.e0 - 1, 0); e < ch.e1; ++e) {
-    double Ju[N + 1], Jtu[N + 1], f0[N + 1], f1[N + 1], f2[N + 1];
+    // ---- loads ----
+    double g0[N + 1], g1[N + 1], g2[N + 1], Jn[N + 1], Jt[N + 1], Jc[N + 1], mi[N + 1], ph[N + 1];
+    double xr[N + 1], xu[N + 1][3], xt[N + 1];
 #pragma unroll
     for (int j = 0; j <= N; ++j) {
       const int k = e * N + j;
-      const double gx = op(k, OP_GX), gy = op(k, OP_GY), gzz = op(k, OP_GZ);
-      const double u = gx * X(1, k) + gy * X(2, k) + gzz * X(3, k);
-      Ju[j] = op(k, OP_J) * u;
-      Jtu[j] = op(k, OP_JTH) * u;
-      const double p = op(k, OP_JCT) * X(4, k);
-      f0[j] = p * gx; f1[j] = p * gy; f2[j] = p * gzz;
+      g0[j] = op(k, OP_GX); g1[j] = op(k, OP_GY); g2[j] = op(k, OP_GZ);
+      Jn[j] = op(k, OP_J); Jt[j] = op(k, OP_JTH); Jc[j] = op(k, OP_JCT);
+      mi[j] = op(k, OP_MINV); ph[j] = op(k, OP_PHI);
+      xr[j] = X(0, k); xu[j][0] = X(1, k); xu[j][1] = X(2, k); xu[j][2] = X(3, k);
+      xt[j] = X(4, k);
     }
+    // ---- element sums ----
+    double Ju[N + 1], Jtu[N + 1], f0[N + 1], f1[N + 1], f2[N + 1];
+#pragma unroll
+    for (int j = 0; j <= N; ++j) {
+      const double u = g0[j] * xu[j][0] + g1[j] * xu[j][1] + g2[j] * xu[j][2];
+      Ju[j] = Jn[j] * u;
+      Jtu[j] = Jt[j] * u;
+      const double p = Jc[j] * xt[j];
+      f0[j] = p * g0[j]; f1[j] = p * g1[j]; f2[j] = p * g2[j];
+    }
+    double yo[N + 1][5];
 #pragma unroll
     for (int a = 0; a <= N; ++a) {
       double sr = 0.0, st = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
@@ -317,23 +332,23 @@ __global__ __launch_bounds__(256) void k_apply(HeviShapeDev sh, HeviTab tab,
       const double wa = tab.w[a];
       st *= wa; s0 *= wa; s1 *= wa; s2 *= wa;
       if (a == 0) { sr += cr; st += ct; s0 += c0; s1 += c1; s2 += c2; }
-      if (a == N && e < Ne - 1) { cr = sr; ct = st; c0 = s0; c1 = s1; c2 = s2; continue; }
-      if (e < ch.e0) continue;  // element recomputed for the boundary node only
+      if (a == N) { cr = sr; ct = st; c0 = s0; c1 = s1; c2 = s2; }
       const int k = e * N + a;
-      const double mi = op(k, OP_MINV);
       const bool lid = (k == 0) || (k == nz - 1);
-      if (valid) {
-        y[cix(nz, nc, 0, k, c)] = mi * sr;
-        y[cix(nz, nc, 4, k, c)] = -mi * st;
-        if (lid) {
-          y[cix(nz, nc, 1, k, c)] = 0.0;
-          y[cix(nz, nc, 2, k, c)] = 0.0;
-          y[cix(nz, nc, 3, k, c)] = 0.0;
-        } else {
-          const double ph = op(k, OP_PHI), r = X(0, k);
-          y[cix(nz, nc, 1, k, c)] = -mi * s0 - ph * op(k, OP_GX) * r;
-          y[cix(nz, nc, 2, k, c)] = -mi * s1 - ph * op(k, OP_GY) * r;
-          y[cix(nz, nc, 3, k, c)] = -mi * s2 - ph * op(k, OP_GZ) * r;
+      yo[a][0] = mi[a] * sr;
+      yo[a][4] = -mi[a] * st;
+      yo[a][1] = lid ? 0.0 : -mi[a] * s0 - ph[a] * g0[a] * xr[a];
+      yo[a][2] = lid ? 0.0 : -mi[a] * s1 - ph[a] * g1[a] * xr[a];
+      yo[a][3] = lid ? 0.0 : -mi[a] * s2 - ph[a] * g2[a] * xr[a];
+    }
+    // ---- stores of the owned nodes ----
+    if (e >= ch.e0 && valid) {
+      const int amax = (e == Ne - 1) ? N : N - 1;
+#pragma unroll
+      for (int a = 0; a <= N; ++a) {
+        if (a <= amax) {
+#pragma unroll
+          for (int v = 0; v < 5; ++v) y[cix(nz, nc, v, e * N + a, c)] = yo[a][v];
         }
       }
     }
@@ -364,10 +379,10 @@ __device__ __forceinline__ double s_entry(const double* sbuf, int64_t tile, int 
 
 // Assembly of -lambda^2 K (element-chunked, see Chunk): row r of the band is
 // written once, by the wavefront owning node r.
-constexpr int CWF = 4;  // chunk wavefronts of the assembly kernel
+constexpr int CWF = 1;  // chunk wavefronts of the assembly kernel
 
 template <int N>
-__global__ __launch_bounds__(256) void k_factor_assemble(HeviShapeDev sh, HeviTab tab,
+__global__ __launch_bounds__(64) void k_factor_assemble(HeviShapeDev sh, HeviTab tab,
                                                          double lambda,
                                                          const double* __restrict__ ops,
                                                          double* __restrict__ sbuf) {
@@ -391,7 +406,8 @@ __global__ __launch_bounds__(256) void k_factor_assemble(HeviShapeDev sh, HeviTa
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
       const int k = (e - 1) * N + q;
-      Jth[q] = (k >= 0 && k < nz) ? op(k, OP_JTH) : 0.0;
+      const double v = op(min(max(k, 0), nz - 1), OP_JTH);
+      Jth[q] = (k >= 0 && k < nz) ? v : 0.0;
     }
 #pragma unroll
     for (int i = 0; i <= N; ++i) {
@@ -563,14 +579,17 @@ enum { WS_R = 0, WS_U = 1, WS_VR = 2, WS_VT = 3, WS_T = 4, WS_D = 5, WS_B = 6, W
 // factor rows of the next rows in flight (PF forward, PB backward) (software prefetch into a register
 // ring, refilled as soon as a slot is consumed) while it works on the current one.
 template <int N, typename FT>
-__device__ void band_solve(const FT* __restrict__ Ub, const FT* __restrict__ Lb,
+__device__ __forceinline__ void band_solve(const FT* __restrict__ Ub, const FT* __restrict__ Lb,
                            const uint8_t* __restrict__ piv, double* ws, int64_t tile, int nz,
                            int lane, int fi, int fo) {
   constexpr int B = 2 * N, K = 4 * N, PF = 3, PB = 2;
   // ---- forward: row swaps and unit-lower elimination ----
   double y[B + 1];
 #pragma unroll
-  for (int t = 0; t <= B; ++t) y[t] = (t < nz) ? ws[tix(tile, nz, t, HEVI_NWS, fi, lane)] : 0.0;
+  for (int t = 0; t <= B; ++t) {
+    const double v = ws[tix(tile, nz, min(t, nz - 1), HEVI_NWS, fi, lane)];
+    y[t] = (t < nz) ? v : 0.0;
+  }
   double lr[PF][B], rin[PF];
   int pv[PF];
 #pragma unroll
@@ -580,7 +599,8 @@ __device__ void band_solve(const FT* __restrict__ Ub, const FT* __restrict__ Lb,
 #pragma unroll
     for (int t = 0; t < B; ++t) lr[d][t] = ld(Lb + tix(tile, nz, jj, B, t, lane));
     const int rn = d + B + 1;
-    rin[d] = (rn < nz) ? ws[tix(tile, nz, rn, HEVI_NWS, fi, lane)] : 0.0;
+    const double rv = ws[tix(tile, nz, min(rn, nz - 1), HEVI_NWS, fi, lane)];
+    rin[d] = (rn < nz) ? rv : 0.0;
   }
   for (int j0 = 0; j0 < nz; j0 += PF) {
 #pragma unroll
@@ -607,7 +627,8 @@ __device__ void band_solve(const FT* __restrict__ Ub, const FT* __restrict__ Lb,
 #pragma unroll
         for (int t = 0; t < B; ++t) lr[d][t] = ld(Lb + tix(tile, nz, jj, B, t, lane));
         const int rn = jn + B + 1;
-        rin[d] = (rn < nz) ? ws[tix(tile, nz, rn, HEVI_NWS, fi, lane)] : 0.0;
+        const double rv = ws[tix(tile, nz, min(rn, nz - 1), HEVI_NWS, fi, lane)];
+        rin[d] = (rn < nz) ? rv : 0.0;
       }
     }
   }
@@ -1029,8 +1050,9 @@ __global__ __launch_bounds__(64) void k_stage_solve(HeviShapeDev sh, HeviTab tab
 // Q_i <- (q^E_rho, q^E_U + lambda (PG q^_Theta - Phi' grad(zeta) q^_rho), q^E_Theta)
 // (at the lid: Q_U <- q^E_U - n (n . q^_U)) and the reduced right-hand side
 // r = grad(zeta).(q^_U + lambda (PG q^_Theta - Phi' grad(zeta) q^_rho)) (0 at the lid).
+// The term loop is outermost so that each term issues (N+1)*5 independent loads.
 template <int N>
-__global__ __launch_bounds__(256, 2) void k_stage_rhs(HeviShapeDev sh, HeviTab tab, double lambda,
+__global__ __launch_bounds__(64, 2) void k_stage_rhs(HeviShapeDev sh, HeviTab tab, double lambda,
                                                    const double* __restrict__ ops,
                                                    double* __restrict__ ws, HeviTerms E,
                                                    HeviTerms Q, double* __restrict__ Qi) {
@@ -1047,29 +1069,43 @@ __global__ __launch_bounds__(256, 2) void k_stage_rhs(HeviShapeDev sh, HeviTab t
   if (ch.e0 == 0) ws[tix(tile, nz, 0, HEVI_NWS, WS_T, lane)] = 0.0;  // per-column flag
   double c0 = 0.0, c1 = 0.0, c2 = 0.0;
   for (int e = max(ch.e0 - 1, 0); e < ch.e1; ++e) {
-    // q^_Theta at the element's nodes
-    double bt[N + 1];
+    double qE[N + 1][5], b[N + 1][5];
 #pragma unroll
-    for (int j = 0; j <= N; ++j) bt[j] = 0.0;
+    for (int j = 0; j <= N; ++j)
+#pragma unroll
+      for (int v = 0; v < 5; ++v) qE[j][v] = 0.0;
+#pragma unroll 2
     for (int t = 0; t < E.n; ++t) {
       const double* src = E.v[t];
       const double cf = E.coef[t];
 #pragma unroll
-      for (int j = 0; j <= N; ++j) bt[j] += cf * src[cix(nz, nc, 4, e * N + j, cc)];
+      for (int j = 0; j <= N; ++j)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) qE[j][v] += cf * src[cix(nz, nc, v, e * N + j, cc)];
     }
+#pragma unroll
+    for (int j = 0; j <= N; ++j)
+#pragma unroll
+      for (int v = 0; v < 5; ++v) b[j][v] = qE[j][v];
+#pragma unroll 2
     for (int t = 0; t < Q.n; ++t) {
       const double* src = Q.v[t];
       const double cf = Q.coef[t];
 #pragma unroll
-      for (int j = 0; j <= N; ++j) bt[j] += cf * src[cix(nz, nc, 4, e * N + j, cc)];
+      for (int j = 0; j <= N; ++j)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) b[j][v] += cf * src[cix(nz, nc, v, e * N + j, cc)];
     }
-    double f0[N + 1], f1[N + 1], f2[N + 1];
+    double g0[N + 1], g1[N + 1], g2[N + 1], mi[N + 1], ph[N + 1], f0[N + 1], f1[N + 1], f2[N + 1];
 #pragma unroll
     for (int j = 0; j <= N; ++j) {
       const int k = e * N + j;
-      const double p = op(k, OP_JCT) * bt[j];
-      f0[j] = p * op(k, OP_GX); f1[j] = p * op(k, OP_GY); f2[j] = p * op(k, OP_GZ);
+      g0[j] = op(k, OP_GX); g1[j] = op(k, OP_GY); g2[j] = op(k, OP_GZ);
+      mi[j] = op(k, OP_MINV); ph[j] = op(k, OP_PHI);
+      const double p = op(k, OP_JCT) * b[j][4];
+      f0[j] = p * g0[j]; f1[j] = p * g1[j]; f2[j] = p * g2[j];
     }
+    double ro[N + 1], ho[N + 1][3];
 #pragma unroll
     for (int a = 0; a <= N; ++a) {
       double s0 = 0.0, s1 = 0.0, s2 = 0.0;
@@ -1080,50 +1116,38 @@ __global__ __launch_bounds__(256, 2) void k_stage_rhs(HeviShapeDev sh, HeviTab t
       }
       s0 *= tab.w[a]; s1 *= tab.w[a]; s2 *= tab.w[a];
       if (a == 0) { s0 += c0; s1 += c1; s2 += c2; }
-      if (a == N && e < Ne - 1) { c0 = s0; c1 = s1; c2 = s2; continue; }
-      if (e < ch.e0) continue;
+      if (a == N) { c0 = s0; c1 = s1; c2 = s2; }
       const int k = e * N + a;
-      // q^E and q^ at node k
-      double qE[5], b[5];
-#pragma unroll
-      for (int v = 0; v < 5; ++v) qE[v] = 0.0;
-      for (int t = 0; t < E.n; ++t) {
-        const double* src = E.v[t];
-        const double cf = E.coef[t];
-#pragma unroll
-        for (int v = 0; v < 5; ++v) qE[v] += cf * src[cix(nz, nc, v, k, cc)];
-      }
-#pragma unroll
-      for (int v = 0; v < 5; ++v) b[v] = qE[v];
-      for (int t = 0; t < Q.n; ++t) {
-        const double* src = Q.v[t];
-        const double cf = Q.coef[t];
-#pragma unroll
-        for (int v = 0; v < 5; ++v) b[v] += cf * src[cix(nz, nc, v, k, cc)];
-      }
-      const double gx = op(k, OP_GX), gy = op(k, OP_GY), gzz = op(k, OP_GZ);
-      double h1, h2, h3, r;
+      const double gx = g0[a], gy = g1[a], gzz = g2[a];
       if (k == 0 || k == nz - 1) {
         const double inv = 1.0 / sqrt(gx * gx + gy * gy + gzz * gzz);
         const double n0 = gx * inv, n1 = gy * inv, n2 = gzz * inv;
-        const double d = n0 * b[1] + n1 * b[2] + n2 * b[3];
-        h1 = qE[1] - n0 * d; h2 = qE[2] - n1 * d; h3 = qE[3] - n2 * d;
-        r = 0.0;
+        const double d = n0 * b[a][1] + n1 * b[a][2] + n2 * b[a][3];
+        ho[a][0] = qE[a][1] - n0 * d; ho[a][1] = qE[a][2] - n1 * d; ho[a][2] = qE[a][3] - n2 * d;
+        ro[a] = 0.0;
       } else {
-        const double mi = op(k, OP_MINV), ph = op(k, OP_PHI);
-        const double g1 = lambda * (-mi * s0 - ph * gx * b[0]);
-        const double g2 = lambda * (-mi * s1 - ph * gy * b[0]);
-        const double g3 = lambda * (-mi * s2 - ph * gzz * b[0]);
-        h1 = qE[1] + g1; h2 = qE[2] + g2; h3 = qE[3] + g3;
-        r = gx * (b[1] + g1) + gy * (b[2] + g2) + gzz * (b[3] + g3);
+        const double q1 = lambda * (-mi[a] * s0 - ph[a] * gx * b[a][0]);
+        const double q2 = lambda * (-mi[a] * s1 - ph[a] * gy * b[a][0]);
+        const double q3 = lambda * (-mi[a] * s2 - ph[a] * gzz * b[a][0]);
+        ho[a][0] = qE[a][1] + q1; ho[a][1] = qE[a][2] + q2; ho[a][2] = qE[a][3] + q3;
+        ro[a] = gx * (b[a][1] + q1) + gy * (b[a][2] + q2) + gzz * (b[a][3] + q3);
       }
-      ws[tix(tile, nz, k, HEVI_NWS, WS_R, lane)] = r;
-      if (valid) {
-        Qi[cix(nz, nc, 0, k, c)] = qE[0];
-        Qi[cix(nz, nc, 1, k, c)] = h1;
-        Qi[cix(nz, nc, 2, k, c)] = h2;
-        Qi[cix(nz, nc, 3, k, c)] = h3;
-        Qi[cix(nz, nc, 4, k, c)] = qE[4];
+    }
+    if (e >= ch.e0) {
+      const int amax = (e == Ne - 1) ? N : N - 1;
+#pragma unroll
+      for (int a = 0; a <= N; ++a) {
+        if (a <= amax) {
+          const int k = e * N + a;
+          ws[tix(tile, nz, k, HEVI_NWS, WS_R, lane)] = ro[a];
+          if (valid) {
+            Qi[cix(nz, nc, 0, k, c)] = qE[a][0];
+            Qi[cix(nz, nc, 1, k, c)] = ho[a][0];
+            Qi[cix(nz, nc, 2, k, c)] = ho[a][1];
+            Qi[cix(nz, nc, 3, k, c)] = ho[a][2];
+            Qi[cix(nz, nc, 4, k, c)] = qE[a][4];
+          }
+        }
       }
     }
   }
@@ -1131,7 +1155,7 @@ __global__ __launch_bounds__(256, 2) void k_stage_rhs(HeviShapeDev sh, HeviTab t
 
 // pass 2: S u = r, one lane per column (+ reduced FP64 refinement for FP32 factors)
 template <int N, typename FT, bool REFINE>
-__global__ __launch_bounds__(64, 8) void k_stage_bsolve(HeviShapeDev sh, HeviTab tab, double lambda,
+__global__ __launch_bounds__(64, 2) void k_stage_bsolve(HeviShapeDev sh, HeviTab tab, double lambda,
                                                      const double* __restrict__ ops,
                                                      const FT* __restrict__ Ub,
                                                      const FT* __restrict__ Lb,
@@ -1160,42 +1184,18 @@ __global__ __launch_bounds__(64, 8) void k_stage_bsolve(HeviShapeDev sh, HeviTab
   }
 }
 
-// div contributions of element ee to its nodes: sr[a] = sum_j w_j D_ja (J u)_j,
-// st[a] = w_a sum_j D_aj (J theta0 u)_j, u from scratch field WS_U
-template <int N>
-__device__ __forceinline__ void elem_div(const HeviTab& tab, const OpsView& op, const double* ws,
-                                         int64_t tile, int lane, int ee, double* sr, double* st) {
-  const int nz = op.nz;
-  double Ju[N + 1], Jtu[N + 1];
-#pragma unroll
-  for (int j = 0; j <= N; ++j) {
-    const int k = ee * N + j;
-    const double u = ws[tix(tile, nz, k, HEVI_NWS, WS_U, lane)];
-    Ju[j] = op(k, OP_J) * u;
-    Jtu[j] = op(k, OP_JTH) * u;
-  }
-#pragma unroll
-  for (int a = 0; a <= N; ++a) {
-    double r = 0.0, t = 0.0;
-#pragma unroll
-    for (int j = 0; j <= N; ++j) {
-      r += tab.w[j] * tab.D[j * (N + 1) + a] * Ju[j];
-      t += tab.D[a * (N + 1) + j] * Jtu[j];
-    }
-    sr[a] = r;
-    st[a] = tab.w[a] * t;
-  }
-}
-
 // pass 3: v_rho = Drho u, v_Th = DTh u; Q_i += (lambda v_rho,
-// lambda^2 (PG v_Th - Phi' grad(zeta) v_rho) [interior], lambda v_Th)
+// lambda^2 (PG v_Th - Phi' grad(zeta) v_rho) [interior], lambda v_Th).
+// An element needs u on its neighbours too (the DSS of Drho u, DTh u at its end
+// nodes), so each iteration loads u and the operator on nodes (e-1)N .. (e+2)N.
 template <int N>
-__global__ __launch_bounds__(256, 2) void k_stage_update(HeviShapeDev sh, HeviTab tab,
+__global__ __launch_bounds__(64) void k_stage_update(HeviShapeDev sh, HeviTab tab,
                                                       double lambda,
                                                       const double* __restrict__ ops,
                                                       double* __restrict__ ws,
                                                       double* __restrict__ Qi,
                                                       HeviDevInfo* info) {
+  constexpr int NC = 3 * N + 1;
   const int Ne = sh.Ne, nz = sh.nz;
   const Chunk ch = chunk_of(Ne);
   if (ch.e0 >= ch.e1) return;
@@ -1203,33 +1203,68 @@ __global__ __launch_bounds__(256, 2) void k_stage_update(HeviShapeDev sh, HeviTa
   const int64_t tile = ch.tile;
   const int64_t c = tile * T + lane;
   const bool valid = c < sh.ncols;
+  const int64_t cc = valid ? c : sh.ncols - 1;
   const int64_t nc = sh.ncols;
   OpsView op{ops, tile, nz, lane};
   const double l2 = lambda * lambda;
   bool nonfinite = false;
   double c0 = 0.0, c1 = 0.0, c2 = 0.0;
   for (int e = max(ch.e0 - 1, 0); e < ch.e1; ++e) {
-    // v_rho, v_Th at the nodes of element e, summed over all their elements
-    double sr[N + 1], st[N + 1], pr[N + 1], pt[N + 1];
-    elem_div<N>(tab, op, ws, tile, lane, e, sr, st);
-    if (e > 0) {
-      elem_div<N>(tab, op, ws, tile, lane, e - 1, pr, pt);
-      sr[0] += pr[N]; st[0] += pt[N];
+    // ---- loads: u, J, J theta0 on nodes (e-1)N .. (e+2)N; operator and Q_i on the element
+    double Ju[NC], Jtu[NC];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      const int k = (e - 1) * N + q;
+      const int kk = min(max(k, 0), nz - 1);
+      const double u = ws[tix(tile, nz, kk, HEVI_NWS, WS_U, lane)];
+      const double in = (k >= 0 && k < nz) ? 1.0 : 0.0;
+      Ju[q] = in * op(kk, OP_J) * u;
+      Jtu[q] = in * op(kk, OP_JTH) * u;
     }
-    if (e < Ne - 1) {
-      elem_div<N>(tab, op, ws, tile, lane, e + 1, pr, pt);
-      sr[N] += pr[0]; st[N] += pt[0];
-    }
-    double vr[N + 1], f0[N + 1], f1[N + 1], f2[N + 1];
+    double g0[N + 1], g1[N + 1], g2[N + 1], mi[N + 1], ph[N + 1], jc[N + 1], q[N + 1][5];
 #pragma unroll
     for (int j = 0; j <= N; ++j) {
       const int k = e * N + j;
-      const double mi = op(k, OP_MINV);
-      vr[j] = mi * sr[j];
-      st[j] = -mi * st[j];  // v_Th
-      const double p = op(k, OP_JCT) * st[j];
-      f0[j] = p * op(k, OP_GX); f1[j] = p * op(k, OP_GY); f2[j] = p * op(k, OP_GZ);
+      g0[j] = op(k, OP_GX); g1[j] = op(k, OP_GY); g2[j] = op(k, OP_GZ);
+      mi[j] = op(k, OP_MINV); ph[j] = op(k, OP_PHI); jc[j] = op(k, OP_JCT);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) q[j][v] = Qi[cix(nz, nc, v, k, cc)];
     }
+    // ---- v_rho, v_Th at the element's nodes (contributions of elements e-1, e, e+1)
+    double sr[N + 1], st[N + 1];
+#pragma unroll
+    for (int a = 0; a <= N; ++a) {
+      double r = 0.0, t = 0.0;
+#pragma unroll
+      for (int j = 0; j <= N; ++j) {
+        r += tab.w[j] * tab.D[j * (N + 1) + a] * Ju[N + j];
+        t += tab.D[a * (N + 1) + j] * Jtu[N + j];
+      }
+      sr[a] = r;
+      st[a] = tab.w[a] * t;
+    }
+    {
+      // element e-1 into node 0 (its node N), element e+1 into node N (its node 0)
+      double r0 = 0.0, t0 = 0.0, rN = 0.0, tN = 0.0;
+#pragma unroll
+      for (int j = 0; j <= N; ++j) {
+        r0 += tab.w[j] * tab.D[j * (N + 1) + N] * Ju[j];
+        t0 += tab.D[N * (N + 1) + j] * Jtu[j];
+        rN += tab.w[j] * tab.D[j * (N + 1) + 0] * Ju[2 * N + j];
+        tN += tab.D[0 * (N + 1) + j] * Jtu[2 * N + j];
+      }
+      sr[0] += r0; st[0] += tab.w[N] * t0;
+      sr[N] += rN; st[N] += tab.w[0] * tN;
+    }
+    double vr[N + 1], vt[N + 1], f0[N + 1], f1[N + 1], f2[N + 1];
+#pragma unroll
+    for (int j = 0; j <= N; ++j) {
+      vr[j] = mi[j] * sr[j];
+      vt[j] = -mi[j] * st[j];
+      const double p = jc[j] * vt[j];
+      f0[j] = p * g0[j]; f1[j] = p * g1[j]; f2[j] = p * g2[j];
+    }
+    // ---- pressure gradient and gravity, stage update
 #pragma unroll
     for (int a = 0; a <= N; ++a) {
       double s0 = 0.0, s1 = 0.0, s2 = 0.0;
@@ -1240,29 +1275,29 @@ __global__ __launch_bounds__(256, 2) void k_stage_update(HeviShapeDev sh, HeviTa
       }
       s0 *= tab.w[a]; s1 *= tab.w[a]; s2 *= tab.w[a];
       if (a == 0) { s0 += c0; s1 += c1; s2 += c2; }
-      if (a == N && e < Ne - 1) { c0 = s0; c1 = s1; c2 = s2; continue; }
-      if (e < ch.e0 || !valid) continue;
+      if (a == N) { c0 = s0; c1 = s1; c2 = s2; }
       const int k = e * N + a;
-      const size_t i0 = cix(nz, nc, 0, k, c), i4 = cix(nz, nc, 4, k, c);
-      const double qr = Qi[i0] + lambda * vr[a];
-      const double qt = Qi[i4] + lambda * st[a];
-      Qi[i0] = qr;
-      Qi[i4] = qt;
-      bool fin = isfinite(qr) && isfinite(qt);
-      if (k != 0 && k != nz - 1) {
-        const double mi = op(k, OP_MINV), ph = op(k, OP_PHI);
-        const size_t i1 = cix(nz, nc, 1, k, c), i2 = cix(nz, nc, 2, k, c),
-                     i3 = cix(nz, nc, 3, k, c);
-        const double q1 = Qi[i1] + l2 * (-mi * s0 - ph * op(k, OP_GX) * vr[a]);
-        const double q2 = Qi[i2] + l2 * (-mi * s1 - ph * op(k, OP_GY) * vr[a]);
-        const double q3 = Qi[i3] + l2 * (-mi * s2 - ph * op(k, OP_GZ) * vr[a]);
-        Qi[i1] = q1; Qi[i2] = q2; Qi[i3] = q3;
-        fin = fin && isfinite(q1) && isfinite(q2) && isfinite(q3);
-      } else {
-        fin = fin && isfinite(Qi[cix(nz, nc, 1, k, c)]) && isfinite(Qi[cix(nz, nc, 2, k, c)]) &&
-              isfinite(Qi[cix(nz, nc, 3, k, c)]);
+      const bool lid = (k == 0) || (k == nz - 1);
+      q[a][0] += lambda * vr[a];
+      q[a][4] += lambda * vt[a];
+      if (!lid) {
+        q[a][1] += l2 * (-mi[a] * s0 - ph[a] * g0[a] * vr[a]);
+        q[a][2] += l2 * (-mi[a] * s1 - ph[a] * g1[a] * vr[a]);
+        q[a][3] += l2 * (-mi[a] * s2 - ph[a] * g2[a] * vr[a]);
       }
-      if (!fin) nonfinite = true;
+    }
+    if (e >= ch.e0 && valid) {
+      const int amax = (e == Ne - 1) ? N : N - 1;
+#pragma unroll
+      for (int a = 0; a <= N; ++a) {
+        if (a <= amax) {
+#pragma unroll
+          for (int v = 0; v < 5; ++v) {
+            Qi[cix(nz, nc, v, e * N + a, c)] = q[a][v];
+            if (!isfinite(q[a][v])) nonfinite = true;
+          }
+        }
+      }
     }
   }
   if (nonfinite) {
@@ -1328,8 +1363,12 @@ template <int N>
 struct Apply {
   static hipError_t run(const HeviShapeDev& sh, const HeviTab& tab, const double* ops,
                         const double* x, const double* xref, double* y, hipStream_t st) {
-    hipLaunchKernelGGL(k_apply<N>, dim3((unsigned)sh.ntiles), dim3(T * CW), 0, st, sh, tab, ops, x,
-                       xref, y);
+    if (xref)
+      hipLaunchKernelGGL((k_apply<N, true>), dim3((unsigned)sh.ntiles), dim3(T * CW), 0, st, sh,
+                         tab, ops, x, xref, y);
+    else
+      hipLaunchKernelGGL((k_apply<N, false>), dim3((unsigned)sh.ntiles), dim3(T * CW), 0, st, sh,
+                         tab, ops, x, xref, y);
     return hipGetLastError();
   }
 };
