@@ -4,17 +4,20 @@
 Workload: the ne=30 production shape -- 86,402 columns (6 (30*4)^2 + 2), 10
 vertical elements of order 4 (41 GLL points, 205 unknowns per column), lapse-
 rate hydrostatic reference (310 K surface, 6.5 K/km), 30 km top, ARK3
-(ARK3(2)4L[2]SA), dt = 300 s, synthetic seeded perturbations of relative size
-1e-3.  One step = the whole hot path: refactor I - a~_ii dt L_z, S(Q_1), three
-implicit stage solves each followed by S(Q_i), and the final update.
-A column-solve is one implicit stage solve of one column (3 per column-step).
+(ARK3(2)4L[2]SA), dt = 300 s, seeded synthetic perturbations of relative size
+1e-3.  One step = the whole path: refactor I - a~_ii dt L_z, the synthetic
+explicit tendency S(Q_1) = L_z (Q_1 - q_ref), three implicit stage solves each
+followed by S(Q_i), and the final update.  A column-solve is one implicit stage
+solve of one column (3 per column and step).
 
-Prints ONE JSON line (rank 0).  `value` is column-solves/s of whole steps (factor
-included) with inputs resident in HBM.
+Prints ONE JSON line.  `value` is column-solves/s of whole steps (factor and
+explicit tendency included) with all inputs resident in HBM, for the path
+selected by --precision (FP64 by default); the other paths are reported beside it.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,26 +29,53 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0       # MI355X HBM3E, published
-PEAK_FP64_TFLOPS = 78.6     # MI355X FP64 vector/matrix, published
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage_solve_ne30_traffic.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_2311_11425_amd", "csrc", "hevi_kernels.hip")
+
+PATHS = {  # name: (precision, refine=(max_sweeps, rel_target, full_sweeps))
+    "fp64": (0, (0, 1e-13, 0)),
+    "mixed": (1, (4, 1e-13, 0)),
+    "fp64_full1": (0, (0, 1e-13, 1)),
+}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def percentile(v, p):
+def pct(v, p):
     return float(np.percentile(np.asarray(v), p)) if len(v) else float("nan")
 
 
+def kernel_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(path):
+    """HBM bytes per stage-solve launch from the committed counter summary, only if
+    it was taken on the current kernel source (else None)."""
+    try:
+        txt = open(TRAFFIC_FILE).read().split("\n")
+    except OSError:
+        return None
+    kv = dict(line.split("=", 1) for line in txt if "=" in line and not line.startswith("#"))
+    if kv.get("kernel_sha256_16") != kernel_hash():
+        return None
+    v = kv.get(f"bytes_per_stage_solve_{path}")
+    return float(v) if v else None
+
+
 def oracle_rate(col, qn, qref, budget_cpu_s=15.0):
+    """The oracle's ARK3 step on a bounded sample of the same columns, on the host
+    cores; column-solves/s (sampling by column is exact: columns are independent)."""
     import oracle
     from oracle import tableaux
     tab = tableaux.as_float(tableaux.ark3())
-    threads = os.cpu_count() or 1
     try:
         threads = len(os.sched_getaffinity(0))
     except AttributeError:
-        pass
+        threads = os.cpu_count() or 1
     threads = max(1, min(threads, 16))
 
     def sample(n):
@@ -56,45 +86,122 @@ def oracle_rate(col, qn, qref, budget_cpu_s=15.0):
         sc["gz"] = np.ascontiguousarray(col["gz"][:, :, idx])
         return sc, np.ascontiguousarray(qn[..., idx]), np.ascontiguousarray(qref[..., idx])
 
-    # calibrate on a small sample, then size the timed sample to the CPU budget
-    sc, q0, r0 = sample(threads * 2)
+    n0 = threads * 16
+    sc, q0, r0 = sample(n0)
     t = time.perf_counter()
     oracle.ark_step_batch(sc, tab, 300.0, q0, r0, refine=1, nthreads=threads)
-    per_col_cpu = (time.perf_counter() - t) * threads / (threads * 2)
-    n = int(max(threads * 2, min(col["z"].shape[1], budget_cpu_s / max(per_col_cpu, 1e-6))))
-    n = (n // threads) * threads or threads
+    per_col_cpu = (time.perf_counter() - t) * threads / n0
+    n = int(min(col["z"].shape[1], max(n0, budget_cpu_s / max(per_col_cpu, 1e-6))))
+    n = max(threads, (n // threads) * threads)
     sc, q0, r0 = sample(n)
     t = time.perf_counter()
     oracle.ark_step_batch(sc, tab, 300.0, q0, r0, refine=1, nthreads=threads)
     wall = time.perf_counter() - t
-    rate = n * 3 / wall
-    return {"value": rate, "unit": "column-solves/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n} of {col['z'].shape[1]} columns, one ARK3 step each (dense GEPP "
-                      f"factor + 3 stage solves + one long-double refinement step per solve), "
-                      f"{wall:.2f} s wall on {threads} threads"}
+    return {"value": n * 3 / wall, "unit": "column-solves/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} of {col['z'].shape[1]} columns (evenly spaced), one ARK3 step each: "
+                      f"dense 205x205 GEPP factor, 3 stage solves with one long-double "
+                      f"refinement step, 4 dense operator applications; {wall:.2f} s wall, "
+                      f"{wall * threads:.1f} CPU-s on {threads} threads"}
+
+
+def stage_errors(st, col, qn, idx):
+    """Max relative L2 error per (column, variable) of each stage solve on sampled
+    columns: q^ rebuilt from the GPU's own Q_j, S_j and solved by the oracle."""
+    import torch
+    import oracle
+    qs = np.ascontiguousarray(qn[..., idx])
+    sc = dict(col)
+    for k in ("z", "J", "rho0", "Theta0"):
+        sc[k] = np.ascontiguousarray(col[k][:, idx])
+    sc["gz"] = np.ascontiguousarray(col["gz"][:, :, idx])
+    torch.cuda.synchronize()
+    Q = [t.cpu().numpy()[..., idx] for t in st.Q]
+    S = [t.cpu().numpy()[..., idx] for t in st.S]
+    out = []
+    for i in range(1, st.s):
+        c = st.coeffs(i)
+        qE = qs + sum(st.dt * st.Aexp[i][j] * S[j] for j in range(i))
+        P = sum(c[j] * Q[j] for j in range(i))
+        xo = oracle.solve_batch(sc, st.lam, qE + P, refine=1)
+        xg = Q[i] + P
+        num = np.sqrt(((xg - xo) ** 2).sum(axis=1))
+        den = np.sqrt((xo ** 2).sum(axis=1))
+        out.append(float((num / np.where(den > 0, den, 1.0)).max()))
+    return out
+
+
+def run_path(ctx, B, name, qd, qrd, steps, warmup):
+    import torch
+    from paper_2311_11425_amd.driver import ArkStepper
+    prec, refine = PATHS[name]
+    st = ArkStepper(ctx, B, "ARK3", 300.0, precision=prec, refine=refine)
+    out = B.empty_state()
+    for inf in st.step(qd, qrd, out, info=True):
+        if inf["status"] != "HEVI_OK":
+            raise SystemExit(f"{name}: stage solve reported {inf}")
+    for _ in range(warmup):
+        st.step(qd, qrd, out)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    marks = {"stage_solve": [], "refactor": [], "apply_op": []}
+    orig = {k: getattr(ctx, k) for k in marks}
+
+    def wrap(k):
+        def f(*a, **kw):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            r = orig[k](*a, **kw)
+            e1.record(stream)
+            marks[k].append((e0, e1))
+            return r
+        return f
+
+    for k in marks:
+        setattr(ctx, k, wrap(k))
+    step_ev = []
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        st.step(qd, qrd, out)
+        b.record(stream)
+        step_ev.append((a, b))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    for k in marks:
+        setattr(ctx, k, orig[k])
+    ms = {k: [a.elapsed_time(b) for a, b in v] for k, v in marks.items()}
+    step_ms = [a.elapsed_time(b) for a, b in step_ev]
+    return st, {"wall_s": wall, "step_ms": step_ms, "stage_ms": ms["stage_solve"],
+                "factor_ms": ms["refactor"], "apply_ms": ms["apply_op"]}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--ncols", type=int, default=86402)
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--precision", choices=list(PATHS), default="fp64")
+    ap.add_argument("--only", action="store_true", help="time only the selected path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-error-check", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="CPU-seconds for the oracle")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a plain 1 GiB device copy (for HBM counter scaling)")
+                    help="also run plain 1 GiB device copies (scale for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU; --gpus {args.gpus} is not "
-              "supported (columns shard across GPUs with no exchange; see DESIGN.md)",
+              "supported (columns shard across GPUs with no exchange step; see DESIGN.md)",
               file=sys.stderr)
         sys.exit(2)
 
     import torch
     from paper_2311_11425_amd import hevi, inputs
-    from paper_2311_11425_amd.driver import ArkStepper, ColumnBatch
+    from paper_2311_11425_amd.driver import ColumnBatch
 
     t0 = time.perf_counter()
     col = inputs.config2(ncols=args.ncols)
@@ -102,117 +209,91 @@ def main():
     log(f"inputs ready in {time.perf_counter() - t0:.1f} s")
     ctx = hevi.Context(0)
     B = ColumnBatch(ctx, col)
-    prec = hevi.HEVI_FP64 if args.precision == "fp64" else hevi.HEVI_FP32_REFINE
-    st = ArkStepper(ctx, B, "ARK3", 300.0, precision=prec, refine=(4, 1e-13, 0))
-    q = torch.from_numpy(qn).cuda()
-    qr = torch.from_numpy(qref).cuda()
-    out = B.empty_state()
+    qd = torch.from_numpy(qn).cuda()
+    qrd = torch.from_numpy(qref).cuda()
     torch.cuda.synchronize()
-    log("device state resident")
-
-    # stage-solve timing with events on the stream the kernels are launched on
-    stream = torch.cuda.current_stream()
-    orig = ctx.stage_solve
-    ev = []
-
-    def timed_stage_solve(*a, **k):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        r = orig(*a, **k)
-        e1.record(stream)
-        ev.append((e0, e1))
-        return r
-
-    infos = st.step(q, qr, out, info=True)
-    for inf in infos:
-        if inf["status"] != "HEVI_OK":
-            raise SystemExit(f"stage solve reported {inf}")
-    for _ in range(args.warmup):
-        st.step(q, qr, out)
-    torch.cuda.synchronize()
-    log("warmup done")
-
-    ctx.stage_solve = timed_stage_solve
-    step_ev = []
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    for _ in range(args.steps):
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        st.step(q, qr, out)
-        b.record(stream)
-        step_ev.append((a, b))
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t
-    ctx.stage_solve = orig
-    log(f"timed {args.steps} steps in {wall:.3f} s")
-
-    step_ms = [a.elapsed_time(b) for a, b in step_ev]
-    solve_ms = [a.elapsed_time(b) for a, b in ev]
-    ncols = col["z"].shape[1]
-    nz = col["nz"]
+    ncols, nz = col["z"].shape[1], col["nz"]
     n_unk = 5 * nz
-    solves_per_step = 3 * ncols
-    ms_per_step = wall * 1e3 / args.steps
-    value = solves_per_step / (ms_per_step * 1e-3)
-    stage_avg_ms = float(np.mean(solve_ms))
+    rng = np.random.default_rng(5)
+    nsamp = min(ncols, 64)
+    idx = np.unique(np.concatenate([rng.choice(ncols, nsamp - 3, replace=False),
+                                    [0, ncols - 1, min(64, ncols - 1)]]))
 
-    # algorithmic bytes of one stage-solve launch, averaged over the 3 stages
-    sz = hevi.sizes(4, 10, precision=prec)
-    vec = 5 * nz * 8
-    per_col = []
-    for i in (1, 2, 3):
-        n_e, n_prev = 1 + i, i
-        per_col.append((n_e + n_prev + 1) * vec + sz["factors"] + sz["ops"])
-    bytes_per_col = float(np.mean(per_col))
-    bytes_launch = bytes_per_col * ncols
-    achieved = bytes_launch / (stage_avg_ms * 1e-3) / 1e9
+    order = [args.precision] + ([] if args.only else [p for p in PATHS if p != args.precision])
+    res_paths = {}
+    for name in order:
+        st, r = run_path(ctx, B, name, qd, qrd, args.steps, args.warmup)
+        ms_step = r["wall_s"] * 1e3 / args.steps
+        stage_ms = float(np.mean(r["stage_ms"]))
+        fac_ms = float(np.mean(r["factor_ms"]))
+        app_ms = float(np.mean(r["apply_ms"]))
+        d = {"ms_per_step": ms_step,
+             "column_solves_per_s": 3 * ncols / (ms_step * 1e-3),
+             "latency_ms_per_step": {"p50": pct(r["step_ms"], 50), "p99": pct(r["step_ms"], 99)},
+             "stage_solve_ms": {"avg": stage_ms, "p50": pct(r["stage_ms"], 50),
+                                "p99": pct(r["stage_ms"], 99)},
+             "stage_only_column_solves_per_s": ncols / (stage_ms * 1e-3),
+             "factor_ms": fac_ms, "apply_op_ms": app_ms,
+             "factor_plus_stages_column_solves_per_s": 3 * ncols / ((fac_ms + 3 * stage_ms) * 1e-3)}
+        if not args.no_error_check:
+            d["stage_rel_err_vs_oracle"] = stage_errors(st, col, qn, idx)
+        res_paths[name] = d
+        log(f"{name}: {ms_step:.3f} ms/step, stage solve {stage_ms:.3f} ms, factor {fac_ms:.3f} ms")
 
-    res = {
-        "metric": "column-solves/s & unknowns/s at <=1e-10 rel err vs FP64 oracle; "
-                  "p50/p99 latency",
-        "value": value,
-        "unit": "column-solves/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if prec == hevi.HEVI_FP64 else "f32-factors+f64-refine",
-        "data": "synthetic",
-        "config": {"workload": "LHEVI ARK3 step, ne=30 cubed-sphere column count 86402, "
-                               "10 elements x order 4 (41 pts, 205 unknowns), lapse-rate "
-                               "reference, dt=300 s",
-                   "columns": ncols, "unknowns_per_column": n_unk, "precision": args.precision,
-                   "stages_per_step": 3, "factor_per_step": True},
-        "unknowns_per_s": value * n_unk,
-        "latency_ms_per_step": {"p50": percentile(step_ms, 50), "p99": percentile(step_ms, 99)},
-        "stage_solve": {"avg_ms": stage_avg_ms, "p50_ms": percentile(solve_ms, 50),
-                        "p99_ms": percentile(solve_ms, 99),
-                        "column_solves_per_s": ncols / (stage_avg_ms * 1e-3),
-                        "unknowns_per_s": ncols * n_unk / (stage_avg_ms * 1e-3)},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
-                     "kernel": "k_stage_solve<4>", "algorithmic_bytes_per_column": bytes_per_col,
-                     "paper_band_factor_bytes_per_column": sz["paper_band"]},
-    }
     if args.copy_calibration:
         src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-        res["copy_calibration_bytes"] = 2 * src.numel() * 8
+        del src, dst
+    main_path = res_paths[args.precision]
+    prec = PATHS[args.precision][0]
+    sz = hevi.sizes(4, 10, precision=prec)
+    vec = 5 * nz * 8
+    # algorithmic bytes of one stage solve, averaged over the 3 stages: the input
+    # vectors (q^n, S_1..S_{i-1}, Q_1..Q_{i-1}), the output Q_i, the factors and
+    # the compact operator, each once
+    per_col = float(np.mean([(2 * i + 1 + 1) * vec + sz["factors"] + sz["ops"] for i in (1, 2, 3)]))
+    stage_s = main_path["stage_solve_ms"]["avg"] * 1e-3
+    achieved = per_col * ncols / stage_s / 1e9
+    traffic = measured_traffic(args.precision)
+    res = {
+        "metric": "column-solves/s & unknowns/s at <=1e-10 rel err vs FP64 oracle; "
+                  "p50/p99 latency",
+        "value": main_path["column_solves_per_s"],
+        "unit": "column-solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_path["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == 0 else "f32-factors+f64-refinement",
+        "data": "synthetic",
+        "config": {"workload": "LHEVI ARK3 step at the ne=30 cubed-sphere column count: 86402 "
+                               "columns x 10 elements x order 4 (41 GLL points, 205 unknowns), "
+                               "lapse-rate hydrostatic reference, dt=300 s",
+                   "columns": ncols, "unknowns_per_column": n_unk, "path": args.precision,
+                   "implicit_stages_per_step": 3, "factor_per_step": True},
+        "unknowns_per_s": main_path["column_solves_per_s"] * n_unk,
+        "latency_ms_per_step": main_path["latency_ms_per_step"],
+        "paths": res_paths,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                     "kernel": "hevi_stage_solve (k_stage_rhs + k_stage_bsolve + k_stage_update)",
+                     "algorithmic_bytes_per_column": per_col,
+                     "launch_columns": ncols,
+                     "paper_layout_band_factor_bytes_per_column": sz["paper_band"],
+                     "factor_bytes_per_column": sz["factors"]},
+    }
     if not args.no_cpu_baseline:
         log("oracle CPU baseline ...")
         res["cpu_baseline"] = oracle_rate(col, qn, qref, args.cpu_budget)
     res["paper_context"] = {
         "note": "whole-model 10-day baroclinic-instability time-to-solution on 512 AMD EPYC "
-                "Rome cores (CPU, FP64 implied); context only",
+                "Rome cores (CPU); context only, not this metric",
         "LHEVI_ARK2_s": 163, "NHEVI_LU_ARK2_s": 502, "NHEVI_GMRES_ARK2_s": 1793}
     ctx.close()
     print(json.dumps(res), flush=True)
