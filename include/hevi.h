@@ -208,6 +208,85 @@ hevi_status hevi_tableau(const char *name, int32_t *s, double *a_exp, double *a_
 hevi_status hevi_sizes(const hevi_shape *shape, hevi_precision prec, size_t *ops_bytes_per_col,
                        size_t *factor_bytes_per_col, size_t *paper_band_bytes_per_col);
 
+/* ---- groups: one ARK step for many column batches ---------------------------
+ * A group advances n member problems -- column batches with their own
+ * operator, of any order N, element count and column count -- by one LHEVI ARK
+ * step each, with one tableau and dt for all (Sec. 4.1; Sec. 4.3 eqs.
+ * lhevi-ark-final-2/3):
+ *     refactor A = I - a~_ii dt L_z                        (if requested)
+ *     S_1 = L_z (q^n - q_ref)
+ *     for i = 2..s:  Q_i = stage solve of hevi_stage_solve with
+ *                        E = {q^n, S_1..S_{i-1}}, e = {1, dt a_i1, ..},
+ *                        Qprev = {Q_1 = q^n, Q_2..Q_{i-1}}, c_j = (a~_ij - a_ij)/a~_ii
+ *                    S_i = L_z (Q_i - q_ref)
+ *     q^{n+1} = q^n + dt sum_i b_i S_i
+ * Each phase of the step is one persistent launch over the 64-column tiles of
+ * all members (HEVI_LAUNCH_ONE), one per distinct order (HEVI_LAUNCH_PER_ORDER)
+ * or one plain launch per member (HEVI_LAUNCH_PER_MEMBER); the tiles are handed
+ * out most expensive first.  Results do not depend on the plan.
+ * Buffers: per member, caller-owned device state vectors [v][k][c] of the
+ * member's shape.  d_Q[1..s-1] receive Q_2..Q_s (d_Q[0] is ignored: Q_1 = q^n),
+ * d_S[0..s-1] receive S_1..S_s, d_out receives q^{n+1}; none may alias another
+ * or q^n / q_ref.  The buffers are bound at creation and must stay valid until
+ * hevi_group_free.  Factors (FP64 or FP32 by `prec`) and scratch are owned by
+ * the group.  Steps of one group must not overlap in time (one stream, or
+ * synchronised streams): the launches share the group's work counters. */
+#define HEVI_MAX_STAGES 8
+typedef struct hevi_group hevi_group;
+
+typedef struct {
+  const hevi_ops *ops;
+  const double *d_qn;
+  const double *d_qref;
+  double *d_out;
+  double *d_Q[HEVI_MAX_STAGES];
+  double *d_S[HEVI_MAX_STAGES];
+} hevi_group_member;
+
+typedef enum {
+  HEVI_LAUNCH_ONE = 0,        /* one launch per phase over every member             */
+  HEVI_LAUNCH_PER_ORDER = 1,  /* one launch per phase and distinct order N          */
+  HEVI_LAUNCH_PER_MEMBER = 2  /* one single-problem launch per phase and member     */
+} hevi_launch_mode;
+
+typedef struct {
+  int32_t mode;       /* hevi_launch_mode                                          */
+  int32_t grid;       /* workgroups (one wavefront each) per persistent launch;
+                         0 = one per tile.  Ignored for HEVI_LAUNCH_PER_MEMBER.     */
+  int32_t use_graph;  /* replay the step from a captured HIP graph                 */
+} hevi_group_plan;
+
+typedef struct {
+  hevi_group_plan plan;
+  double ms_per_step; /* mean over the timed steps                                */
+} hevi_tune_result;
+
+/* Create a group of n >= 1 members (tableau as hevi_tableau; dt > 0) and factor
+ * every member once (enqueued on `stream`).  refine: NULL = {4, 1e-13, 0};
+ * full_sweeps must be 0.  The initial plan is {HEVI_LAUNCH_ONE, 0, 0}. */
+hevi_status hevi_group_create(hevi_ctx *ctx, int32_t n, const hevi_group_member *members,
+                              const char *tableau, double dt, hevi_precision prec,
+                              const hevi_refine *refine, hevi_group **out, hipStream_t stream);
+hevi_status hevi_group_set_plan(hevi_ctx *ctx, hevi_group *g, const hevi_group_plan *plan);
+hevi_status hevi_group_get_plan(const hevi_group *g, hevi_group_plan *plan);
+/* One ARK step of every member, enqueued on `stream` (refactor != 0: factor
+ * A = I - a~_ii dt L_z first).  With use_graph the first call of each refactor
+ * flag captures the step into a HIP graph; later calls launch the graph. */
+hevi_status hevi_group_step(hevi_ctx *ctx, hevi_group *g, int32_t refactor, hipStream_t stream);
+/* Wait for `stream` and report, per member, the worst kernel-detected problem
+ * of every step since the previous check (h_infos: n entries); then reset. */
+hevi_status hevi_group_check(hevi_ctx *ctx, hevi_group *g, hevi_info *h_infos,
+                             hipStream_t stream);
+/* Autotuner: time `reps` steps (after one untimed step) of each candidate plan
+ * -- launch modes x persistent grid sizes x graph on/off -- keep the fastest
+ * as the group's plan and write up to `cap` results (n_results = candidates
+ * timed).  It runs real steps: the members' d_out, d_Q and d_S are
+ * overwritten (q^n is not), and the factors are refreshed. */
+hevi_status hevi_group_autotune(hevi_ctx *ctx, hevi_group *g, int32_t reps,
+                                hevi_tune_result *results, int32_t cap, int32_t *n_results,
+                                hipStream_t stream);
+void hevi_group_free(hevi_group *g);
+
 #ifdef __cplusplus
 }
 #endif

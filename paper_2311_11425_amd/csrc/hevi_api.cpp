@@ -13,36 +13,10 @@
 
 #include "hevi.h"
 #include "hevi_internal.h"
-
-struct hevi_ctx {
-  int device;
-};
-
-struct hevi_ops {
-  hevi_ctx* ctx;
-  hevi_shape shape;
-  hevi_consts consts;
-  HeviShapeDev sh;
-  HeviTab tab;
-  double* d_ops;
-  HeviDevInfo* d_info;
-};
-
-struct hevi_factors {
-  const hevi_ops* ops;
-  double lambda;
-  hevi_precision prec;
-  void* U;
-  void* L;
-  uint8_t* piv;
-  double* sbuf;  // FP64 assembly buffer (aliases U for FP64 factors)
-  double* ws;    // per-node FP64 scratch of the stage solve
-  HeviDevInfo* d_info;
-};
+#include "hevi_objects.h"
 
 namespace {
-
-bool ok(hipError_t e) { return e == hipSuccess; }
+using namespace hevi_host;
 
 // ---- 1D Gauss-Lobatto-Legendre tables (Sec. 3) ------------------------------
 // The interior nodes are the roots of q(x) = P_{N+1}(x) - P_{N-1}(x) (which
@@ -102,6 +76,10 @@ void gll_tables(int N, HeviTab* tab, double* xi_out) {
     for (int i = 0; i <= N; ++i) xi_out[i] = x[i];
 }
 
+}  // namespace
+
+namespace hevi_host {
+
 HeviShapeDev dev_shape(const hevi_shape& s) {
   HeviShapeDev d;
   d.N = s.order_N;
@@ -124,33 +102,33 @@ hevi_status check_shape(const hevi_shape* s) {
   return HEVI_OK;
 }
 
-template <typename P>
-hevi_status dev_alloc(P** p, size_t bytes) {
-  *p = nullptr;
-  if (bytes == 0) bytes = 256;
-  void* v = nullptr;
-  if (!ok(hipMalloc(&v, bytes))) return HEVI_E_NOMEM;
-  *p = (P*)v;
-  return HEVI_OK;
-}
-
 size_t tiles_nodes(const HeviShapeDev& sh) { return (size_t)sh.ntiles * (size_t)sh.nz * HEVI_TILE; }
+
+void info_to_host(const HeviDevInfo& h, hevi_info* out) {
+  out->status = h.status;
+  out->max_sweeps_used = h.max_sweeps;
+  out->first_bad_col = h.first_bad == INT64_MAX ? -1 : h.first_bad;
+  out->n_bad_cols = h.n_bad;
+  double r;
+  std::memcpy(&r, &h.max_res_bits, sizeof(r));
+  out->max_rel_correction = r;
+}
 
 hevi_status read_info(HeviDevInfo* d_info, hipStream_t st, hevi_info* out, bool reset) {
   HeviDevInfo h;
   if (!ok(hipMemcpyAsync(&h, d_info, sizeof(h), hipMemcpyDeviceToHost, st))) return HEVI_E_DEVICE;
   if (!ok(hipStreamSynchronize(st))) return HEVI_E_DEVICE;
   if (reset && !ok(hevi_launch_info_reset(d_info, st))) return HEVI_E_DEVICE;
-  if (out) {
-    out->status = h.status;
-    out->max_sweeps_used = h.max_sweeps;
-    out->first_bad_col = h.first_bad == INT64_MAX ? -1 : h.first_bad;
-    out->n_bad_cols = h.n_bad;
-    double r;
-    std::memcpy(&r, &h.max_res_bits, sizeof(r));
-    out->max_rel_correction = r;
-  }
+  if (out) info_to_host(h, out);
   return (hevi_status)h.status;
+}
+
+size_t factor_storage_bytes(const HeviShapeDev& sh, hevi_precision prec) {
+  const size_t tn = tiles_nodes(sh);
+  const size_t fs = prec == HEVI_FP64 ? sizeof(double) : sizeof(float);
+  size_t b = tn * (4 * sh.N + 1) * fs + tn * 2 * sh.N * fs + tn + tn * HEVI_NWS * sizeof(double);
+  if (prec != HEVI_FP64) b += tn * (4 * sh.N + 1) * sizeof(double);
+  return b;
 }
 
 hevi_status terms(int32_t n, const double* const* v, const double* coef, int lo, bool empty,
@@ -168,7 +146,9 @@ hevi_status terms(int32_t n, const double* const* v, const double* coef, int lo,
   return HEVI_OK;
 }
 
-}  // namespace
+}  // namespace hevi_host
+
+using namespace hevi_host;
 
 extern "C" {
 

@@ -10,6 +10,7 @@
 #define HEVI_NOPS 8       // compact per-node operator fields
 #define HEVI_NWS 21       // per-node FP64 scratch fields of a stage solve
 #define HEVI_MAXTERMS 16  // max vectors in a linear combination
+#define HEVI_MAXSTAGES 8  // max stages of an ARK tableau in a group step
 
 // compact per-node operator fields (tile-interleaved, see hevi_kernels.hip)
 enum { OP_MINV = 0, OP_J = 1, OP_JTH = 2, OP_JCT = 3, OP_GX = 4, OP_GY = 5, OP_GZ = 6, OP_PHI = 7 };
@@ -64,3 +65,64 @@ hipError_t hevi_launch_stage_solve(const HeviShapeDev& sh, const HeviTab& tab, d
 hipError_t hevi_launch_combine(int64_t n, const HeviTerms& V, double* out, hipStream_t st);
 
 hipError_t hevi_launch_info_reset(HeviDevInfo* info, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Multi-problem persistent launches (hevi_group.hip).  A launch covers several
+// problems (column batches of possibly different order N, element count and
+// column count); its work items are the 64-column tiles of all of them.
+
+// one problem: shape, tables, operator and factor storage (device-resident table)
+struct HeviProbDev {
+  HeviTab tab;
+  HeviShapeDev sh;
+  int32_t fp32;           // factors stored in FP32
+  double lambda;
+  const double* ops;
+  double* sbuf;           // FP64 assembly buffer (aliases U for FP64 factors)
+  void* U;
+  void* L;
+  uint8_t* piv;
+  double* ws;             // stage-solve scratch
+  HeviDevInfo* info;      // per-problem report
+};
+
+// operands of one call for one problem
+struct HeviCallDev {
+  HeviTerms E;            // stage solve: q^E terms; combine: the terms
+  HeviTerms Q;            // stage solve: previous stage values and c_j
+  const double* x;        // apply: x
+  const double* xref;     // apply: x_ref (required)
+  double* out;            // apply: y; stage solve: Q_i; combine: output
+};
+
+// work list of one launch: segment j is problem plist[j] with items
+// pstart[j] .. pstart[j+1]-1 (its tiles in order)
+struct HeviSched {
+  const int32_t* plist;
+  const int64_t* pstart;  // m + 1 entries, pstart[0] = 0, pstart[m] = total
+  int32_t m;
+  int64_t total;
+  uint32_t* ctr;          // {next item, finished workgroups}; zero before a launch, zero after it
+};
+
+enum HeviPhase {
+  HEVI_PH_APPLY = 0,
+  HEVI_PH_FACTOR_ASSEMBLE = 1,
+  HEVI_PH_FACTOR_LU = 2,
+  HEVI_PH_STAGE_RHS = 3,
+  HEVI_PH_STAGE_BSOLVE = 4,
+  HEVI_PH_STAGE_UPDATE = 5,
+  HEVI_PH_COMBINE = 6,
+  HEVI_NPHASES = 7
+};
+
+// One persistent launch of `phase` with `grid` workgroups of one wavefront.
+// nlo..nhi: the orders the kernel is compiled for ((n, n) for n = 1..8, or
+// (1, HEVI_MAXN)); every problem in the schedule must have nlo <= N <= nhi.
+// fp32 / refine select the factor type and the reduced refinement of the
+// stage solve (max_sweeps, rel_target).
+hipError_t hevi_launch_multi(int phase, int nlo, int nhi, int fp32, const HeviProbDev* probs,
+                             const HeviCallDev* calls, const HeviSched& s, int grid,
+                             int max_sweeps, double rel_target, hipStream_t st);
+
+hipError_t hevi_launch_info_reset_n(HeviDevInfo* info, int n, hipStream_t st);

@@ -1,63 +1,9 @@
-// hevi_kernels.hip -- gfx950 kernels of the batched LHEVI column solver.
-//
-// Mapping.  One lane owns one vertical column; a 64-lane wavefront owns a tile
-// of 64 consecutive columns.  The caller's arrays are column-fastest
-// struct-of-arrays, so every per-node access of a wavefront is one coalesced
-// 512-byte FP64 request.  Library-owned arrays (compact operator, factors,
-// scratch) are tile-interleaved: element (tile, node k, field f, lane) sits at
-// ((tile * nz + k) * F + f) * 64 + lane, so a wavefront streams one contiguous
-// region per tile.
-//
-// Method (Giraldo et al., arXiv 2311.11425).  L_z is the set-2C vertical
-// operator (Appendix A.2) linearised about a state at rest and discretised as
-// in Sec. 3 / Appendix A.3: per element, strong derivative w_i D_ij J_j f_j for
-// the momentum and rho-theta rows, weak derivative -w_j D_ji J_j f_j for the
-// continuity row, direct-stiffness summation along the column, division by the
-// lumped mass; gravity rho dPhi/dzeta grad(zeta) in the momentum rows; the
-// momentum rows of the bottom and top nodes are replaced by the rigid lid.
-// With u = grad(zeta).U (contravariant vertical momentum):
-//   (L x)_rho   = Drho u      = M^-1 sum_e sum_j w_j D_ji J_j u_j
-//   (L x)_Theta = DTh u       = -M^-1 sum_e w_i sum_j D_ij (J theta0)_j u_j
-//   (L x)_U     = PG(Theta) - Phi' grad(zeta) rho
-//               = -M^-1 sum_e w_i sum_j D_ij (J c_Theta grad(zeta))_j Theta_j
-//                 - Phi'_k grad(zeta)_k rho_k                 (interior nodes)
-// The rho-rho and Theta-Theta blocks of A = I - Lambda L_z are identities, so
-// eliminating rho, Theta and the tangential momentum exactly leaves
-//   S u = r,  S = I - Lambda^2 grad(zeta).(PG DTh + Phi' grad(zeta) Drho),
-//   r = grad(zeta).(b_U + Lambda (PG b_Theta - Phi' grad(zeta) b_rho)),
-// a band matrix of half-bandwidth 2N in u (identity rows at the rigid-lid
-// nodes, where u = 0).  Back-substitution recovers
-//   x_rho = b_rho + Lambda Drho u,  x_Theta = b_Theta + Lambda DTh u,
-//   x_U   = b_U + Lambda (PG x_Theta - Phi' grad(zeta) x_rho).
-// S is LU-factored with partial pivoting (band LU, the paper's LAPACK scheme
-// of Sec. 4.2.2 applied to the reduced matrix).
-#include <hip/hip_runtime.h>
-#include <math.h>
-#include <stdint.h>
-
-#include "hevi_internal.h"
+// hevi_kernels.hip -- single-problem gfx950 kernels of the batched LHEVI column
+// solver (one workgroup = one wavefront = one 64-column tile) and their launchers.
+// The per-tile bodies and the method are described in hevi_device.h.
+#include "hevi_device.h"
 
 namespace {
-
-constexpr int T = HEVI_TILE;
-
-__device__ __forceinline__ size_t tix(int64_t tile, int nz, int k, int nf, int f, int lane) {
-  return ((size_t)(tile * nz + k) * nf + f) * T + lane;
-}
-
-// caller layout: field f (or vector component) v, node k, column c
-__device__ __forceinline__ size_t cix(int nz, int64_t ncols, int v, int k, int64_t c) {
-  return ((size_t)v * nz + k) * (size_t)ncols + (size_t)c;
-}
-
-__device__ __forceinline__ void flag(HeviDevInfo* info, int code, int64_t col) {
-  atomicMax(&info->status, code);
-  atomicMin((unsigned long long*)&info->first_bad, (unsigned long long)col);
-  atomicAdd((unsigned long long*)&info->n_bad, 1ull);
-}
-
-template <typename FT>
-__device__ __forceinline__ double ld(const FT* p) { return (double)*p; }
 
 // ---------------------------------------------------------------------------
 // a1: compact per-node operator
@@ -128,361 +74,23 @@ __global__ __launch_bounds__(64) void k_build_ops(HeviShapeDev sh, HeviTab tab, 
 }
 
 // ---------------------------------------------------------------------------
-// Element-streaming helpers.  Node eN is shared by elements e-1 and e; a sum
-// over elements is finished for node eN after element e, so each helper
-// carries the partial sum of the last node of an element into the next.
+// Single-problem kernels: tile = blockIdx.x
 
-struct OpsView {
-  const double* ops;
-  int64_t tile;
-  int nz, lane;
-  __device__ __forceinline__ double operator()(int k, int f) const {
-    return ops[tix(tile, nz, k, HEVI_NOPS, f, lane)];
-  }
-};
-
-// v_rho = Drho u and v_Th = DTh u for all nodes; u read from scratch field
-// fu, results written to fields fr, ft.
-template <int N>
-__device__ void div_pass(const HeviTab& tab, const OpsView& op, int Ne, double* ws, int64_t tile,
-                         int lane, int fu, int fr, int ft) {
-  const int nz = op.nz;
-  double cr = 0.0, ct = 0.0;
-  for (int e = 0; e < Ne; ++e) {
-    double Ju[N + 1], Jtu[N + 1];
-#pragma unroll
-    for (int j = 0; j <= N; ++j) {
-      const int k = e * N + j;
-      const double u = ws[tix(tile, nz, k, HEVI_NWS, fu, lane)];
-      Ju[j] = op(k, OP_J) * u;
-      Jtu[j] = op(k, OP_JTH) * u;
-    }
-#pragma unroll
-    for (int a = 0; a <= N; ++a) {
-      double sr = 0.0, st = 0.0;
-#pragma unroll
-      for (int j = 0; j <= N; ++j) {
-        sr += tab.w[j] * tab.D[j * (N + 1) + a] * Ju[j];
-        st += tab.D[a * (N + 1) + j] * Jtu[j];
-      }
-      st *= tab.w[a];
-      if (a == 0) { sr += cr; st += ct; }
-      if (a == N && e < Ne - 1) { cr = sr; ct = st; continue; }
-      const int k = e * N + a;
-      const double mi = op(k, OP_MINV);
-      ws[tix(tile, nz, k, HEVI_NWS, fr, lane)] = mi * sr;
-      ws[tix(tile, nz, k, HEVI_NWS, ft, lane)] = -mi * st;
-    }
-  }
-}
-
-// Pressure gradient + gravity of (v_rho, v_Th) (fields fr, ft):
-//   G_k = -M^-1 sum_e w_i sum_j D_ij (J c_Theta grad zeta)_j v_Th,j - Phi'_k grad(zeta)_k v_rho,k
-// MODE 0: write grad(zeta)_k . G_k into field fo (zero at the rigid-lid nodes).
-// MODE 1: final stage update Q_i = stored + lambda v (rho, Theta) and
-//         Q_U = stored + lambda^2 G (interior nodes) in the caller's Qi.
-template <int N, int MODE>
-__device__ void pg_pass(const HeviTab& tab, const OpsView& op, int Ne, double* ws, int64_t tile,
-                        int lane, int fr, int ft, int fo, double lambda, double* Qi,
-                        int64_t ncols, int64_t c, bool valid, bool* nonfinite) {
-  const int nz = op.nz;
-  double c0 = 0.0, c1 = 0.0, c2 = 0.0;
-  for (int e = 0; e < Ne; ++e) {
-    double f0[N + 1], f1[N + 1], f2[N + 1];
-#pragma unroll
-    for (int j = 0; j <= N; ++j) {
-      const int k = e * N + j;
-      const double v = op(k, OP_JCT) * ws[tix(tile, nz, k, HEVI_NWS, ft, lane)];
-      f0[j] = v * op(k, OP_GX);
-      f1[j] = v * op(k, OP_GY);
-      f2[j] = v * op(k, OP_GZ);
-    }
-#pragma unroll
-    for (int a = 0; a <= N; ++a) {
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-#pragma unroll
-      for (int j = 0; j <= N; ++j) {
-        const double d = tab.D[a * (N + 1) + j];
-        s0 += d * f0[j];
-        s1 += d * f1[j];
-        s2 += d * f2[j];
-      }
-      s0 *= tab.w[a]; s1 *= tab.w[a]; s2 *= tab.w[a];
-      if (a == 0) { s0 += c0; s1 += c1; s2 += c2; }
-      if (a == N && e < Ne - 1) { c0 = s0; c1 = s1; c2 = s2; continue; }
-      const int k = e * N + a;
-      const bool lid = (k == 0) || (k == nz - 1);
-      const double mi = op(k, OP_MINV), ph = op(k, OP_PHI);
-      const double gx = op(k, OP_GX), gy = op(k, OP_GY), gzz = op(k, OP_GZ);
-      const double vr = ws[tix(tile, nz, k, HEVI_NWS, fr, lane)];
-      const double G0 = -mi * s0 - ph * gx * vr;
-      const double G1 = -mi * s1 - ph * gy * vr;
-      const double G2 = -mi * s2 - ph * gzz * vr;
-      if (MODE == 0) {
-        ws[tix(tile, nz, k, HEVI_NWS, fo, lane)] = lid ? 0.0 : gx * G0 + gy * G1 + gzz * G2;
-      } else {
-        const double vt = ws[tix(tile, nz, k, HEVI_NWS, ft, lane)];
-        if (valid) {
-          double* q = Qi;
-          const size_t i0 = cix(nz, ncols, 0, k, c), i4 = cix(nz, ncols, 4, k, c);
-          const double qr = q[i0] + lambda * vr;
-          const double qt = q[i4] + lambda * vt;
-          q[i0] = qr;
-          q[i4] = qt;
-          bool fin = isfinite(qr) && isfinite(qt);
-          if (!lid) {
-            const double l2 = lambda * lambda;
-            const size_t i1 = cix(nz, ncols, 1, k, c), i2 = cix(nz, ncols, 2, k, c),
-                         i3 = cix(nz, ncols, 3, k, c);
-            const double q1 = q[i1] + l2 * G0, q2 = q[i2] + l2 * G1, q3 = q[i3] + l2 * G2;
-            q[i1] = q1; q[i2] = q2; q[i3] = q3;
-            fin = fin && isfinite(q1) && isfinite(q2) && isfinite(q3);
-          }
-          if (!fin) *nonfinite = true;
-        }
-      }
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Element-chunked kernels: a 256-thread block owns one 64-column tile; its four
-// wavefronts own contiguous chunks of elements [e0, e1) and the nodes
-// e0*N .. e1*N - 1 (plus the top node for the last chunk).  A node on a chunk
-// boundary also receives a contribution from the last element of the previous
-// chunk; the wavefront recomputes that element's contribution itself instead of
-// exchanging partial sums, so the four wavefronts run independently.
-constexpr int CW = 1;  // chunk wavefronts per tile
-
-struct Chunk {
-  int lane, e0, e1;
-  int64_t tile;
-};
-
-__device__ __forceinline__ Chunk chunk_of(int Ne) {
-  Chunk ch;
-  ch.lane = threadIdx.x & (T - 1);
-  const int wv = threadIdx.x / T;
-  const int ce = (Ne + CW - 1) / CW;
-  ch.e0 = wv * ce;
-  ch.e1 = min(Ne, ch.e0 + ce);
-  ch.tile = blockIdx.x;
-  return ch;
-}
-
-// a0: y = L_z (x - x_ref).  Each element iteration loads everything it needs
-// unconditionally (clamped indices), computes, then stores the owned nodes, so
-// the loads of an element are in flight together.
 template <int N, bool HAS_REF>
 __global__ __launch_bounds__(64) void k_apply(HeviShapeDev sh, HeviTab tab,
                                                const double* __restrict__ ops,
                                                const double* __restrict__ x,
                                                const double* __restrict__ xref,
                                                double* __restrict__ y) {
-  const int Ne = sh.Ne, nz = sh.nz;
-  const Chunk ch = chunk_of(Ne);
-  if (ch.e0 >= ch.e1) return;
-  const int lane = ch.lane;
-  const int64_t tile = ch.tile;
-  const int64_t c = tile * T + lane;
-  const bool valid = c < sh.ncols;
-  const int64_t cc = valid ? c : sh.ncols - 1;
-  const int64_t nc = sh.ncols;
-  OpsView op{ops, tile, nz, lane};
-  auto X = [&](int v, int k) {
-    const size_t i = cix(nz, nc, v, k, cc);
-    if constexpr (HAS_REF) return x[i] - xref[i];
-    else return x[i];
-  };
-  double cr = 0.0, ct = 0.0, c0 = 0.0, c1 = 0.0, c2 = 0.0;
-  for (int e = max(ch.e0 - 1, 0); e < ch.e1; ++e) {
-    // ---- loads ----
-    double g0[N + 1], g1[N + 1], g2[N + 1], Jn[N + 1], Jt[N + 1], Jc[N + 1], mi[N + 1], ph[N + 1];
-    double xr[N + 1], xu[N + 1][3], xt[N + 1];
-#pragma unroll
-    for (int j = 0; j <= N; ++j) {
-      const int k = e * N + j;
-      g0[j] = op(k, OP_GX); g1[j] = op(k, OP_GY); g2[j] = op(k, OP_GZ);
-      Jn[j] = op(k, OP_J); Jt[j] = op(k, OP_JTH); Jc[j] = op(k, OP_JCT);
-      mi[j] = op(k, OP_MINV); ph[j] = op(k, OP_PHI);
-      xr[j] = X(0, k); xu[j][0] = X(1, k); xu[j][1] = X(2, k); xu[j][2] = X(3, k);
-      xt[j] = X(4, k);
-    }
-    // ---- element sums ----
-    double Ju[N + 1], Jtu[N + 1], f0[N + 1], f1[N + 1], f2[N + 1];
-#pragma unroll
-    for (int j = 0; j <= N; ++j) {
-      const double u = g0[j] * xu[j][0] + g1[j] * xu[j][1] + g2[j] * xu[j][2];
-      Ju[j] = Jn[j] * u;
-      Jtu[j] = Jt[j] * u;
-      const double p = Jc[j] * xt[j];
-      f0[j] = p * g0[j]; f1[j] = p * g1[j]; f2[j] = p * g2[j];
-    }
-    double yo[N + 1][5];
-#pragma unroll
-    for (int a = 0; a <= N; ++a) {
-      double sr = 0.0, st = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
-#pragma unroll
-      for (int j = 0; j <= N; ++j) {
-        const double d = tab.D[a * (N + 1) + j];
-        sr += tab.w[j] * tab.D[j * (N + 1) + a] * Ju[j];
-        st += d * Jtu[j];
-        s0 += d * f0[j]; s1 += d * f1[j]; s2 += d * f2[j];
-      }
-      const double wa = tab.w[a];
-      st *= wa; s0 *= wa; s1 *= wa; s2 *= wa;
-      if (a == 0) { sr += cr; st += ct; s0 += c0; s1 += c1; s2 += c2; }
-      if (a == N) { cr = sr; ct = st; c0 = s0; c1 = s1; c2 = s2; }
-      const int k = e * N + a;
-      const bool lid = (k == 0) || (k == nz - 1);
-      yo[a][0] = mi[a] * sr;
-      yo[a][4] = -mi[a] * st;
-      yo[a][1] = lid ? 0.0 : -mi[a] * s0 - ph[a] * g0[a] * xr[a];
-      yo[a][2] = lid ? 0.0 : -mi[a] * s1 - ph[a] * g1[a] * xr[a];
-      yo[a][3] = lid ? 0.0 : -mi[a] * s2 - ph[a] * g2[a] * xr[a];
-    }
-    // ---- stores of the owned nodes ----
-    if (e >= ch.e0 && valid) {
-      const int amax = (e == Ne - 1) ? N : N - 1;
-#pragma unroll
-      for (int a = 0; a <= N; ++a) {
-        if (a <= amax) {
-#pragma unroll
-          for (int v = 0; v < 5; ++v) y[cix(nz, nc, v, e * N + a, c)] = yo[a][v];
-        }
-      }
-    }
-  }
+  b_apply<N, HAS_REF>((int64_t)blockIdx.x, sh, tab, ops, x, xref, y);
 }
-
-// ---------------------------------------------------------------------------
-// a2 + a3: assemble S = I - lambda^2 K and factor it (band LU, partial pivoting)
-//
-// Storage per node j (tile-interleaved): U row j, entries (j, j+t) for
-// t = 0..4N (zero beyond the last column); L multipliers of step j for rows
-// j+1..j+2N; pivot offset p in 0..2N (row j was swapped with row j+p).
-// sbuf holds, during assembly, row r of -lambda^2 K at band offset c - r + 2N.
-
-template <int N>
-__device__ __forceinline__ double s_entry(const double* sbuf, int64_t tile, int nz, int lane, int r,
-                                          int cabs) {
-  // entry (r, cabs) of S with identity rows at the rigid-lid nodes and zero
-  // columns for their (identically zero) unknowns
-  constexpr int B = 2 * N, W = 4 * N + 1;
-  if (r < 0 || r >= nz || cabs < 0 || cabs >= nz) return 0.0;
-  if (r == 0 || r == nz - 1) return cabs == r ? 1.0 : 0.0;
-  if (cabs == 0 || cabs == nz - 1) return 0.0;
-  const int off = cabs - r + B;
-  if (off < 0 || off >= W) return 0.0;
-  return sbuf[tix(tile, nz, r, W, off, lane)] + (cabs == r ? 1.0 : 0.0);
-}
-
-// Assembly of -lambda^2 K (element-chunked, see Chunk): row r of the band is
-// written once, by the wavefront owning node r.
-constexpr int CWF = 1;  // chunk wavefronts of the assembly kernel
 
 template <int N>
 __global__ __launch_bounds__(64) void k_factor_assemble(HeviShapeDev sh, HeviTab tab,
                                                          double lambda,
                                                          const double* __restrict__ ops,
                                                          double* __restrict__ sbuf) {
-  constexpr int B = 2 * N;          // half-bandwidth of S (kl = ku)
-  constexpr int W = 4 * N + 1;      // S band width = U row width kl + ku + 1
-  constexpr int NC = 3 * N + 1;     // columns touched by DTh rows of one element
-  const int Ne = sh.Ne, nz = sh.nz;
-  const Chunk ch = chunk_of(Ne);
-  if (ch.e0 >= ch.e1) return;
-  const int lane = ch.lane;
-  const int64_t tile = ch.tile;
-  OpsView op{ops, tile, nz, lane};
-  const double l2 = lambda * lambda;
-  double carry[W];
-#pragma unroll
-  for (int o = 0; o < W; ++o) carry[o] = 0.0;
-  for (int e = max(ch.e0 - 1, 0); e < ch.e1; ++e) {
-    // DTh rows of the element's nodes over columns (e-1)N .. (e+2)N
-    double DT[N + 1][NC];
-    double Jth[NC];
-#pragma unroll
-    for (int q = 0; q < NC; ++q) {
-      const int k = (e - 1) * N + q;
-      const double v = op(min(max(k, 0), nz - 1), OP_JTH);
-      Jth[q] = (k >= 0 && k < nz) ? v : 0.0;
-    }
-#pragma unroll
-    for (int i = 0; i <= N; ++i) {
-#pragma unroll
-      for (int q = 0; q < NC; ++q) DT[i][q] = 0.0;
-#pragma unroll
-      for (int i2 = 0; i2 <= N; ++i2) DT[i][N + i2] += tab.w[i] * tab.D[i * (N + 1) + i2] * Jth[N + i2];
-      if (i == 0 && e > 0) {
-#pragma unroll
-        for (int i2 = 0; i2 <= N; ++i2) DT[0][i2] += tab.w[N] * tab.D[N * (N + 1) + i2] * Jth[i2];
-      }
-      if (i == N && e < Ne - 1) {
-#pragma unroll
-        for (int i2 = 0; i2 <= N; ++i2)
-          DT[N][2 * N + i2] += tab.w[0] * tab.D[0 * (N + 1) + i2] * Jth[2 * N + i2];
-      }
-      const double mi = op(e * N + i, OP_MINV);
-#pragma unroll
-      for (int q = 0; q < NC; ++q) DT[i][q] *= -mi;
-    }
-    double gxj[N + 1], gyj[N + 1], gzj[N + 1], jct[N + 1], jj[N + 1];
-#pragma unroll
-    for (int i = 0; i <= N; ++i) {
-      const int k = e * N + i;
-      gxj[i] = op(k, OP_GX); gyj[i] = op(k, OP_GY); gzj[i] = op(k, OP_GZ);
-      jct[i] = op(k, OP_JCT); jj[i] = op(k, OP_J);
-    }
-#pragma unroll
-    for (int a = 0; a <= N; ++a) {
-      if (e < ch.e0 && a < N) continue;  // only the boundary row of the recomputed element
-      const int r = e * N + a;
-      const double mr = op(r, OP_MINV), ph = op(r, OP_PHI);
-      double acc[W];
-#pragma unroll
-      for (int o = 0; o < W; ++o) acc[o] = 0.0;
-#pragma unroll
-      for (int i = 0; i <= N; ++i) {
-        const double dot = gxj[a] * gxj[i] + gyj[a] * gyj[i] + gzj[a] * gzj[i];
-        const double P = -mr * tab.w[a] * tab.D[a * (N + 1) + i] * jct[i] * dot;
-#pragma unroll
-        for (int q = 0; q < NC; ++q) acc[q + N - a] += P * DT[i][q];
-      }
-      const double gr = -ph * (gxj[a] * gxj[a] + gyj[a] * gyj[a] + gzj[a] * gzj[a]) * mr;
-#pragma unroll
-      for (int i2 = 0; i2 <= N; ++i2)
-        acc[B + i2 - a] += gr * tab.w[i2] * tab.D[i2 * (N + 1) + a] * jj[i2];
-      if (a == 0) {
-#pragma unroll
-        for (int o = 0; o < W; ++o) acc[o] += carry[o];
-      }
-      if (a == N && e < Ne - 1) {
-#pragma unroll
-        for (int o = 0; o < W; ++o) carry[o] = acc[o];
-        continue;
-      }
-      double* row = sbuf + tix(tile, nz, r, W, 0, lane);
-#pragma unroll
-      for (int o = 0; o < W; ++o) row[o * T] = -l2 * acc[o];
-    }
-  }
-}
-
-// Band LU with partial pivoting of S over a (2N+1) x (4N+1) register window
-// (one lane per column).  Window row t, column s holds A(j+t, j+s) at step j;
-// the S rows entering the window are prefetched PFL rows ahead.
-template <int N>
-__device__ __forceinline__ double s_fix(int r, int nz, int s, double raw) {
-  // entry (r, r - 2N + s) of S from the stored -lambda^2 K value: identity rows
-  // at the rigid-lid nodes, zero columns for their (identically zero) unknowns
-  constexpr int B = 2 * N;
-  const int cabs = r - B + s;
-  if (r >= nz) return 0.0;
-  if (r == 0 || r == nz - 1) return s == B ? 1.0 : 0.0;
-  if (cabs <= 0 || cabs >= nz - 1) return 0.0;
-  return raw + (s == B ? 1.0 : 0.0);
+  b_factor_assemble<N>((int64_t)blockIdx.x, sh, tab, lambda, ops, sbuf);
 }
 
 template <int N, typename FT>
@@ -490,395 +98,7 @@ __global__ __launch_bounds__(64) void k_factor_lu(HeviShapeDev sh, const double*
                                                   FT* Ub,  // may alias sbuf (FP64)
                                                   FT* __restrict__ Lb, uint8_t* __restrict__ piv,
                                                   HeviDevInfo* info) {
-  constexpr int B = 2 * N, W = 4 * N + 1, PFL = 2;
-  const int lane = threadIdx.x;
-  const int64_t tile = blockIdx.x;
-  const int64_t c = tile * T + lane;
-  const bool valid = c < sh.ncols;
-  const int nz = sh.nz;
-  double Wn[B + 1][W];
-#pragma unroll
-  for (int t = 0; t <= B; ++t)
-#pragma unroll
-    for (int s = 0; s < W; ++s) Wn[t][s] = s_entry<N>(sbuf, tile, nz, lane, t, s);
-  double ring[PFL][W];
-#pragma unroll
-  for (int d = 0; d < PFL; ++d) {
-    const int r = min(B + 1 + d, nz - 1);
-#pragma unroll
-    for (int s = 0; s < W; ++s) ring[d][s] = sbuf[tix(tile, nz, r, W, s, lane)];
-  }
-  bool singular = false;
-  for (int j0 = 0; j0 < nz; j0 += PFL) {
-#pragma unroll
-    for (int d = 0; d < PFL; ++d) {
-      const int j = j0 + d;
-      if (j < nz) {
-        int p = 0;
-        double best = fabs(Wn[0][0]);
-#pragma unroll
-        for (int t = 1; t <= B; ++t) {
-          const double v = fabs(Wn[t][0]);
-          if (j + t < nz && v > best) { best = v; p = t; }
-        }
-        if (!(best > 0.0)) { singular = true; Wn[0][0] = 1.0; p = 0; }
-#pragma unroll
-        for (int s = 0; s < W; ++s) {
-          const double v0 = Wn[0][s];
-          double vp = v0;
-#pragma unroll
-          for (int t = 1; t <= B; ++t) vp = (p == t) ? Wn[t][s] : vp;
-          Wn[0][s] = vp;
-#pragma unroll
-          for (int t = 1; t <= B; ++t) Wn[t][s] = (p == t) ? v0 : Wn[t][s];
-        }
-        piv[tix(tile, nz, j, 1, 0, lane)] = (uint8_t)p;
-        FT* urow = Ub + tix(tile, nz, j, W, 0, lane);
-#pragma unroll
-        for (int s = 0; s < W; ++s) urow[s * T] = (FT)Wn[0][s];
-        const double inv = 1.0 / Wn[0][0];
-        FT* lrow = Lb + tix(tile, nz, j, B, 0, lane);
-#pragma unroll
-        for (int t = 1; t <= B; ++t) {
-          const double l = Wn[t][0] * inv;
-          lrow[(t - 1) * T] = (FT)l;
-#pragma unroll
-          for (int s = 1; s < W; ++s) Wn[t][s] -= l * Wn[0][s];
-        }
-#pragma unroll
-        for (int t = 0; t < B; ++t) {
-#pragma unroll
-          for (int s = 0; s < W - 1; ++s) Wn[t][s] = Wn[t + 1][s + 1];
-          Wn[t][W - 1] = 0.0;
-        }
-        // new bottom row j + 2N + 1 from the ring; refill the slot
-        const int rn = j + B + 1;
-#pragma unroll
-        for (int s = 0; s < W; ++s) Wn[B][s] = s_fix<N>(rn, nz, s, ring[d][s]);
-        const int rf = min(rn + PFL, nz - 1);
-#pragma unroll
-        for (int s = 0; s < W; ++s) ring[d][s] = sbuf[tix(tile, nz, rf, W, s, lane)];
-      }
-    }
-  }
-  if (singular && valid) flag(info, 5 /*HEVI_E_SINGULAR*/, c);
-}
-
-// ---------------------------------------------------------------------------
-// a4 + a5 + a6: one stage solve
-//
-// scratch fields per node
-// R: reduced right-hand side, U: reduced solution u, VR/VT: Drho u / DTh u,
-// T/D: reduced residual / correction; B, X, S: 5-field vectors (rho, U, Theta)
-// of the full-residual refinement (right-hand side, solution, residual)
-enum { WS_R = 0, WS_U = 1, WS_VR = 2, WS_VT = 3, WS_T = 4, WS_D = 5, WS_B = 6, WS_X = 11,
-       WS_S = 16 };
-
-// solve S x = rhs with the band LU factors (rhs field fi, result field fo).
-// The sweeps are sequential in the row index, so each wavefront keeps the
-// factor rows of the next rows in flight (PF forward, PB backward) (software prefetch into a register
-// ring, refilled as soon as a slot is consumed) while it works on the current one.
-template <int N, typename FT>
-__device__ __forceinline__ void band_solve(const FT* __restrict__ Ub, const FT* __restrict__ Lb,
-                           const uint8_t* __restrict__ piv, double* ws, int64_t tile, int nz,
-                           int lane, int fi, int fo) {
-  constexpr int B = 2 * N, K = 4 * N, PF = 3, PB = 2;
-  // ---- forward: row swaps and unit-lower elimination ----
-  double y[B + 1];
-#pragma unroll
-  for (int t = 0; t <= B; ++t) {
-    const double v = ws[tix(tile, nz, min(t, nz - 1), HEVI_NWS, fi, lane)];
-    y[t] = (t < nz) ? v : 0.0;
-  }
-  double lr[PF][B], rin[PF];
-  int pv[PF];
-#pragma unroll
-  for (int d = 0; d < PF; ++d) {
-    const int jj = d < nz ? d : nz - 1;
-    pv[d] = piv[tix(tile, nz, jj, 1, 0, lane)];
-#pragma unroll
-    for (int t = 0; t < B; ++t) lr[d][t] = ld(Lb + tix(tile, nz, jj, B, t, lane));
-    const int rn = d + B + 1;
-    const double rv = ws[tix(tile, nz, min(rn, nz - 1), HEVI_NWS, fi, lane)];
-    rin[d] = (rn < nz) ? rv : 0.0;
-  }
-  for (int j0 = 0; j0 < nz; j0 += PF) {
-#pragma unroll
-    for (int d = 0; d < PF; ++d) {
-      const int j = j0 + d;
-      if (j < nz) {
-        const int p = pv[d];
-        const double v0 = y[0];
-        double vp = v0;
-#pragma unroll
-        for (int t = 1; t <= B; ++t) vp = (p == t) ? y[t] : vp;
-#pragma unroll
-        for (int t = 1; t <= B; ++t) y[t] = (p == t) ? v0 : y[t];
-        ws[tix(tile, nz, j, HEVI_NWS, fo, lane)] = vp;
-#pragma unroll
-        for (int t = 1; t <= B; ++t) y[t] -= lr[d][t - 1] * vp;
-#pragma unroll
-        for (int t = 0; t < B; ++t) y[t] = y[t + 1];
-        y[B] = rin[d];
-        // refill the consumed slot with row j + PF
-        const int jn = j + PF;
-        const int jj = jn < nz ? jn : nz - 1;
-        pv[d] = piv[tix(tile, nz, jj, 1, 0, lane)];
-#pragma unroll
-        for (int t = 0; t < B; ++t) lr[d][t] = ld(Lb + tix(tile, nz, jj, B, t, lane));
-        const int rn = jn + B + 1;
-        const double rv = ws[tix(tile, nz, min(rn, nz - 1), HEVI_NWS, fi, lane)];
-        rin[d] = (rn < nz) ? rv : 0.0;
-      }
-    }
-  }
-  // ---- backward: upper-triangular substitution ----
-  double xw[K + 1];
-#pragma unroll
-  for (int t = 0; t <= K; ++t) xw[t] = 0.0;
-  double ur[PB][K + 1], yin[PB];
-#pragma unroll
-  for (int d = 0; d < PB; ++d) {
-    const int jr = nz - 1 - d;
-    const int jj = jr >= 0 ? jr : 0;
-#pragma unroll
-    for (int t = 0; t <= K; ++t) ur[d][t] = ld(Ub + tix(tile, nz, jj, K + 1, t, lane));
-    yin[d] = ws[tix(tile, nz, jj, HEVI_NWS, fo, lane)];
-  }
-  for (int j0 = nz - 1; j0 >= 0; j0 -= PB) {
-#pragma unroll
-    for (int d = 0; d < PB; ++d) {
-      const int j = j0 - d;
-      if (j >= 0) {
-        double s = yin[d];
-#pragma unroll
-        for (int t = 1; t <= K; ++t) s -= ur[d][t] * xw[t];
-        const double xj = s / ur[d][0];
-        ws[tix(tile, nz, j, HEVI_NWS, fo, lane)] = xj;
-#pragma unroll
-        for (int t = K; t >= 2; --t) xw[t] = xw[t - 1];
-        xw[1] = xj;
-        // refill the consumed slot with row j - PB
-        const int jr = j - PB;
-        const int jj = jr >= 0 ? jr : 0;
-#pragma unroll
-        for (int t = 0; t <= K; ++t) ur[d][t] = ld(Ub + tix(tile, nz, jj, K + 1, t, lane));
-        yin[d] = ws[tix(tile, nz, jj, HEVI_NWS, fo, lane)];
-      }
-    }
-  }
-}
-
-// Reduced refinement for FP32-stored factors: d = r - S u with S applied
-// matrix-free in FP64, correction delta from the factors, u += delta, until the
-// correction is small, ||delta|| <= target ||u|| (a residual test would stop
-// early: ||u_err|| can exceed ||d|| / ||r|| by the condition number of S), or
-// max_sweeps.  Per column; the wavefront sweeps while any column needs one.
-template <int N, typename FT>
-__device__ void reduced_refine(const HeviTab& tab, const OpsView& op, int Ne, double* ws,
-                               int64_t tile, int lane, bool valid, double lambda,
-                               const FT* __restrict__ Ub, const FT* __restrict__ Lb,
-                               const uint8_t* __restrict__ piv, int max_sweeps, double rel_target,
-                               int* sweeps_out, double* corr_out) {
-  const int nz = op.nz;
-  int sweeps = 0;
-  double corr = INFINITY;
-  for (;;) {
-    const bool need = !(corr <= rel_target) && sweeps < max_sweeps;
-    if (!__any(valid && need)) break;
-    div_pass<N>(tab, op, Ne, ws, tile, lane, WS_U, WS_VR, WS_VT);
-    bool dummy = false;
-    pg_pass<N, 0>(tab, op, Ne, ws, tile, lane, WS_VR, WS_VT, WS_T, 0.0, nullptr, 0, 0, false,
-                  &dummy);
-    const double l2 = lambda * lambda;
-    for (int k = 0; k < nz; ++k) {
-      const double u = ws[tix(tile, nz, k, HEVI_NWS, WS_U, lane)];
-      const double Ku = ws[tix(tile, nz, k, HEVI_NWS, WS_T, lane)];
-      const double Su = (k == 0 || k == nz - 1) ? u : u - l2 * Ku;
-      ws[tix(tile, nz, k, HEVI_NWS, WS_T, lane)] = ws[tix(tile, nz, k, HEVI_NWS, WS_R, lane)] - Su;
-    }
-    band_solve<N, FT>(Ub, Lb, piv, ws, tile, nz, lane, WS_T, WS_D);
-    if (need) {
-      double d2 = 0.0, u2 = 0.0;
-      for (int k = 0; k < nz; ++k) {
-        const size_t iu = tix(tile, nz, k, HEVI_NWS, WS_U, lane);
-        const double d = ws[tix(tile, nz, k, HEVI_NWS, WS_D, lane)];
-        const double u = ws[iu] + d;
-        ws[iu] = u;
-        d2 += d * d;
-        u2 += u * u;
-      }
-      corr = u2 > 0.0 ? sqrt(d2 / u2) : (d2 > 0.0 ? INFINITY : 0.0);
-      ++sweeps;
-    }
-  }
-  *sweeps_out = sweeps;
-  *corr_out = corr;
-}
-
-// Reduced right-hand side r = grad(zeta).(b_U + lambda (PG b_Theta - Phi' grad(zeta) b_rho))
-// of a 5-field vector b stored in scratch fields fb..fb+4 (zero at the lid nodes).
-template <int N>
-__device__ double reduced_rhs_pass(const HeviTab& tab, const OpsView& op, int Ne, double* ws,
-                                   int64_t tile, int lane, double lambda, int fb) {
-  const int nz = op.nz;
-  double c0 = 0.0, c1 = 0.0, c2 = 0.0, rn2 = 0.0;
-  for (int e = 0; e < Ne; ++e) {
-    double f0[N + 1], f1[N + 1], f2[N + 1];
-#pragma unroll
-    for (int j = 0; j <= N; ++j) {
-      const int k = e * N + j;
-      const double p = op(k, OP_JCT) * ws[tix(tile, nz, k, HEVI_NWS, fb + 4, lane)];
-      f0[j] = p * op(k, OP_GX); f1[j] = p * op(k, OP_GY); f2[j] = p * op(k, OP_GZ);
-    }
-#pragma unroll
-    for (int a = 0; a <= N; ++a) {
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-#pragma unroll
-      for (int j = 0; j <= N; ++j) {
-        const double d = tab.D[a * (N + 1) + j];
-        s0 += d * f0[j]; s1 += d * f1[j]; s2 += d * f2[j];
-      }
-      s0 *= tab.w[a]; s1 *= tab.w[a]; s2 *= tab.w[a];
-      if (a == 0) { s0 += c0; s1 += c1; s2 += c2; }
-      if (a == N && e < Ne - 1) { c0 = s0; c1 = s1; c2 = s2; continue; }
-      const int k = e * N + a;
-      double r = 0.0;
-      if (k != 0 && k != nz - 1) {
-        const double gx = op(k, OP_GX), gy = op(k, OP_GY), gzz = op(k, OP_GZ);
-        const double mi = op(k, OP_MINV), ph = op(k, OP_PHI);
-        const double br = ws[tix(tile, nz, k, HEVI_NWS, fb + 0, lane)];
-        const double g1 = lambda * (-mi * s0 - ph * gx * br);
-        const double g2 = lambda * (-mi * s1 - ph * gy * br);
-        const double g3 = lambda * (-mi * s2 - ph * gzz * br);
-        r = gx * (ws[tix(tile, nz, k, HEVI_NWS, fb + 1, lane)] + g1) +
-            gy * (ws[tix(tile, nz, k, HEVI_NWS, fb + 2, lane)] + g2) +
-            gzz * (ws[tix(tile, nz, k, HEVI_NWS, fb + 3, lane)] + g3);
-      }
-      rn2 += r * r;
-      ws[tix(tile, nz, k, HEVI_NWS, WS_R, lane)] = r;
-    }
-  }
-  return rn2;
-}
-
-// Back-substitution of the block elimination: with u (field WS_U) and the
-// right-hand side b (fields fb..), d_rho = b_rho + lambda Drho u,
-// d_Th = b_Th + lambda DTh u, d_U = b_U + lambda (PG d_Th - Phi' grad(zeta) d_rho)
-// (interior), d_U = P(b_U) at the lid (P removes the normal component).
-// Writes d into fields fx.. or adds it to them (accumulate).
-template <int N>
-__device__ void recover_pass(const HeviTab& tab, const OpsView& op, int Ne, double* ws,
-                             int64_t tile, int lane, double lambda, int fb, int fx,
-                             bool accumulate) {
-  const int nz = op.nz;
-  div_pass<N>(tab, op, Ne, ws, tile, lane, WS_U, WS_VR, WS_VT);
-  auto W = [&](int k, int f) -> double& { return ws[tix(tile, nz, k, HEVI_NWS, f, lane)]; };
-  double c0 = 0.0, c1 = 0.0, c2 = 0.0;
-  for (int e = 0; e < Ne; ++e) {
-    double f0[N + 1], f1[N + 1], f2[N + 1];
-#pragma unroll
-    for (int j = 0; j <= N; ++j) {
-      const int k = e * N + j;
-      const double dth = W(k, fb + 4) + lambda * W(k, WS_VT);
-      const double p = op(k, OP_JCT) * dth;
-      f0[j] = p * op(k, OP_GX); f1[j] = p * op(k, OP_GY); f2[j] = p * op(k, OP_GZ);
-    }
-#pragma unroll
-    for (int a = 0; a <= N; ++a) {
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-#pragma unroll
-      for (int j = 0; j <= N; ++j) {
-        const double d = tab.D[a * (N + 1) + j];
-        s0 += d * f0[j]; s1 += d * f1[j]; s2 += d * f2[j];
-      }
-      s0 *= tab.w[a]; s1 *= tab.w[a]; s2 *= tab.w[a];
-      if (a == 0) { s0 += c0; s1 += c1; s2 += c2; }
-      if (a == N && e < Ne - 1) { c0 = s0; c1 = s1; c2 = s2; continue; }
-      const int k = e * N + a;
-      const double gx = op(k, OP_GX), gy = op(k, OP_GY), gzz = op(k, OP_GZ);
-      const double dr = W(k, fb + 0) + lambda * W(k, WS_VR);
-      const double dt = W(k, fb + 4) + lambda * W(k, WS_VT);
-      double d1, d2, d3;
-      const double b1 = W(k, fb + 1), b2 = W(k, fb + 2), b3 = W(k, fb + 3);
-      if (k == 0 || k == nz - 1) {
-        const double inv = 1.0 / sqrt(gx * gx + gy * gy + gzz * gzz);
-        const double n0 = gx * inv, n1 = gy * inv, n2 = gzz * inv;
-        const double dd = n0 * b1 + n1 * b2 + n2 * b3;
-        d1 = b1 - n0 * dd; d2 = b2 - n1 * dd; d3 = b3 - n2 * dd;
-      } else {
-        const double mi = op(k, OP_MINV), ph = op(k, OP_PHI);
-        d1 = b1 + lambda * (-mi * s0 - ph * gx * dr);
-        d2 = b2 + lambda * (-mi * s1 - ph * gy * dr);
-        d3 = b3 + lambda * (-mi * s2 - ph * gzz * dr);
-      }
-      if (accumulate) {
-        W(k, fx + 0) += dr; W(k, fx + 1) += d1; W(k, fx + 2) += d2; W(k, fx + 3) += d3;
-        W(k, fx + 4) += dt;
-      } else {
-        W(k, fx + 0) = dr; W(k, fx + 1) = d1; W(k, fx + 2) = d2; W(k, fx + 3) = d3;
-        W(k, fx + 4) = dt;
-      }
-    }
-  }
-}
-
-// Full-system residual s = P(b) - A x = P(b) - x + lambda L_z x in FP64 for the
-// vectors b (fields fb..) and x (fields fx..); rigid-lid momentum rows of A are
-// identity rows, so there s_U = P(b_U) - x_U.  Writes fields fs..
-template <int N>
-__device__ void residual_pass(const HeviTab& tab, const OpsView& op, int Ne, double* ws,
-                              int64_t tile, int lane, double lambda, int fb, int fx, int fs) {
-  const int nz = op.nz;
-  auto W = [&](int k, int f) -> double& { return ws[tix(tile, nz, k, HEVI_NWS, f, lane)]; };
-  double cr = 0.0, ct = 0.0, c0 = 0.0, c1 = 0.0, c2 = 0.0;
-  for (int e = 0; e < Ne; ++e) {
-    double Ju[N + 1], Jtu[N + 1], f0[N + 1], f1[N + 1], f2[N + 1];
-#pragma unroll
-    for (int j = 0; j <= N; ++j) {
-      const int k = e * N + j;
-      const double gx = op(k, OP_GX), gy = op(k, OP_GY), gzz = op(k, OP_GZ);
-      const double u = gx * W(k, fx + 1) + gy * W(k, fx + 2) + gzz * W(k, fx + 3);
-      Ju[j] = op(k, OP_J) * u;
-      Jtu[j] = op(k, OP_JTH) * u;
-      const double p = op(k, OP_JCT) * W(k, fx + 4);
-      f0[j] = p * gx; f1[j] = p * gy; f2[j] = p * gzz;
-    }
-#pragma unroll
-    for (int a = 0; a <= N; ++a) {
-      double sr = 0.0, st = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
-#pragma unroll
-      for (int j = 0; j <= N; ++j) {
-        const double d = tab.D[a * (N + 1) + j];
-        sr += tab.w[j] * tab.D[j * (N + 1) + a] * Ju[j];
-        st += d * Jtu[j];
-        s0 += d * f0[j]; s1 += d * f1[j]; s2 += d * f2[j];
-      }
-      const double wa = tab.w[a];
-      st *= wa; s0 *= wa; s1 *= wa; s2 *= wa;
-      if (a == 0) { sr += cr; st += ct; s0 += c0; s1 += c1; s2 += c2; }
-      if (a == N && e < Ne - 1) { cr = sr; ct = st; c0 = s0; c1 = s1; c2 = s2; continue; }
-      const int k = e * N + a;
-      const double mi = op(k, OP_MINV);
-      const double gx = op(k, OP_GX), gy = op(k, OP_GY), gzz = op(k, OP_GZ);
-      W(k, fs + 0) = W(k, fb + 0) - W(k, fx + 0) + lambda * (mi * sr);
-      W(k, fs + 4) = W(k, fb + 4) - W(k, fx + 4) + lambda * (-mi * st);
-      const double b1 = W(k, fb + 1), b2 = W(k, fb + 2), b3 = W(k, fb + 3);
-      if (k == 0 || k == nz - 1) {
-        const double inv = 1.0 / sqrt(gx * gx + gy * gy + gzz * gzz);
-        const double n0 = gx * inv, n1 = gy * inv, n2 = gzz * inv;
-        const double dd = n0 * b1 + n1 * b2 + n2 * b3;
-        W(k, fs + 1) = b1 - n0 * dd - W(k, fx + 1);
-        W(k, fs + 2) = b2 - n1 * dd - W(k, fx + 2);
-        W(k, fs + 3) = b3 - n2 * dd - W(k, fx + 3);
-      } else {
-        const double ph = op(k, OP_PHI), xr = W(k, fx + 0);
-        W(k, fs + 1) = b1 - W(k, fx + 1) + lambda * (-mi * s0 - ph * gx * xr);
-        W(k, fs + 2) = b2 - W(k, fx + 2) + lambda * (-mi * s1 - ph * gy * xr);
-        W(k, fs + 3) = b3 - W(k, fx + 3) + lambda * (-mi * s2 - ph * gzz * xr);
-      }
-    }
-  }
+  b_factor_lu<N, FT>((int64_t)blockIdx.x, sh, sbuf, Ub, Lb, piv, info);
 }
 
 template <int N, typename FT, bool FULL>
@@ -891,269 +111,18 @@ __global__ __launch_bounds__(64) void k_stage_solve(HeviShapeDev sh, HeviTab tab
                                                     HeviTerms Q, double* __restrict__ Qi,
                                                     int max_sweeps, double rel_target,
                                                     int full_sweeps, HeviDevInfo* info) {
-  const int lane = threadIdx.x;
-  const int64_t tile = blockIdx.x;
-  const int64_t c = tile * T + lane;
-  const bool valid = c < sh.ncols;
-  const int64_t cc = valid ? c : sh.ncols - 1;
-  const int nz = sh.nz, Ne = sh.Ne;
-  const int64_t nc = sh.ncols;
-  OpsView op{ops, tile, nz, lane};
-  bool nonfinite = false;
-  const bool full = FULL;
-
-  // ---- pass 1: q^E, q^ = q^E + sum c_j Q_j, reduced right-hand side r ----
-  double c0 = 0.0, c1 = 0.0, c2 = 0.0;
-  for (int e = 0; e < Ne; ++e) {
-    // q^E and q^ at the element's nodes; the term loop is outermost so that
-    // each term issues (N+1)*5 independent coalesced loads
-    double qE[N + 1][5], b[N + 1][5];
-#pragma unroll
-    for (int j = 0; j <= N; ++j)
-#pragma unroll
-      for (int v = 0; v < 5; ++v) qE[j][v] = 0.0;
-    for (int t = 0; t < E.n; ++t) {
-      const double* src = E.v[t];
-      const double cf = E.coef[t];
-#pragma unroll
-      for (int j = 0; j <= N; ++j)
-#pragma unroll
-        for (int v = 0; v < 5; ++v) qE[j][v] += cf * src[cix(nz, nc, v, e * N + j, cc)];
-    }
-#pragma unroll
-    for (int j = 0; j <= N; ++j)
-#pragma unroll
-      for (int v = 0; v < 5; ++v) b[j][v] = qE[j][v];
-    for (int t = 0; t < Q.n; ++t) {
-      const double* src = Q.v[t];
-      const double cf = Q.coef[t];
-#pragma unroll
-      for (int j = 0; j <= N; ++j)
-#pragma unroll
-        for (int v = 0; v < 5; ++v) b[j][v] += cf * src[cix(nz, nc, v, e * N + j, cc)];
-    }
-    double f0[N + 1], f1[N + 1], f2[N + 1];
-#pragma unroll
-    for (int j = 0; j <= N; ++j) {
-      const int k = e * N + j;
-      const double p = op(k, OP_JCT) * b[j][4];
-      f0[j] = p * op(k, OP_GX); f1[j] = p * op(k, OP_GY); f2[j] = p * op(k, OP_GZ);
-    }
-#pragma unroll
-    for (int a = 0; a <= N; ++a) {
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-#pragma unroll
-      for (int j = 0; j <= N; ++j) {
-        const double d = tab.D[a * (N + 1) + j];
-        s0 += d * f0[j]; s1 += d * f1[j]; s2 += d * f2[j];
-      }
-      s0 *= tab.w[a]; s1 *= tab.w[a]; s2 *= tab.w[a];
-      if (a == 0) { s0 += c0; s1 += c1; s2 += c2; }
-      if (a == N && e < Ne - 1) { c0 = s0; c1 = s1; c2 = s2; continue; }
-      const int k = e * N + a;
-      const double gx = op(k, OP_GX), gy = op(k, OP_GY), gzz = op(k, OP_GZ);
-      double h1, h2, h3, r;
-      if (k == 0 || k == nz - 1) {
-        // rigid lid: Q_U = q^E_U - n (n . b_U), u = 0
-        const double inv = 1.0 / sqrt(gx * gx + gy * gy + gzz * gzz);
-        const double n0 = gx * inv, n1 = gy * inv, n2 = gzz * inv;
-        const double d = n0 * b[a][1] + n1 * b[a][2] + n2 * b[a][3];
-        h1 = qE[a][1] - n0 * d; h2 = qE[a][2] - n1 * d; h3 = qE[a][3] - n2 * d;
-        r = 0.0;
-      } else {
-        const double mi = op(k, OP_MINV), ph = op(k, OP_PHI);
-        const double g1 = lambda * (-mi * s0 - ph * gx * b[a][0]);
-        const double g2 = lambda * (-mi * s1 - ph * gy * b[a][0]);
-        const double g3 = lambda * (-mi * s2 - ph * gzz * b[a][0]);
-        h1 = qE[a][1] + g1; h2 = qE[a][2] + g2; h3 = qE[a][3] + g3;
-        r = gx * (b[a][1] + g1) + gy * (b[a][2] + g2) + gzz * (b[a][3] + g3);
-      }
-      ws[tix(tile, nz, k, HEVI_NWS, WS_R, lane)] = r;
-      if (full) {
-        // keep q^ (offset-free) for the full-system residual; Q_i holds q^E
-#pragma unroll
-        for (int v = 0; v < 5; ++v) ws[tix(tile, nz, k, HEVI_NWS, WS_B + v, lane)] = b[a][v];
-        h1 = qE[a][1]; h2 = qE[a][2]; h3 = qE[a][3];
-      }
-      if (valid) {
-        Qi[cix(nz, nc, 0, k, c)] = qE[a][0];
-        Qi[cix(nz, nc, 1, k, c)] = h1;
-        Qi[cix(nz, nc, 2, k, c)] = h2;
-        Qi[cix(nz, nc, 3, k, c)] = h3;
-        Qi[cix(nz, nc, 4, k, c)] = qE[a][4];
-      }
-    }
-  }
-
-  // ---- pass 2: S u = r (+ reduced FP64 refinement when the factors are FP32) ----
-  band_solve<N, FT>(Ub, Lb, piv, ws, tile, nz, lane, WS_R, WS_U);
-  int sweeps = 0;
-  double relres = 0.0;
-  if (max_sweeps > 0)
-    reduced_refine<N, FT>(tab, op, Ne, ws, tile, lane, valid, lambda, Ub, Lb, piv, max_sweeps,
-                          rel_target, &sweeps, &relres);
-
-  if constexpr (!FULL) {
-    // ---- pass 3: recover rho, Theta and momentum; Q_i = q^E + lambda L_z x ----
-    div_pass<N>(tab, op, Ne, ws, tile, lane, WS_U, WS_VR, WS_VT);
-    pg_pass<N, 1>(tab, op, Ne, ws, tile, lane, WS_VR, WS_VT, 0, lambda, Qi, nc, c, valid,
-                  &nonfinite);
-  } else {
-    // ---- full-system FP64 iterative refinement on x = q_tt (offset-free) ----
-    recover_pass<N>(tab, op, Ne, ws, tile, lane, lambda, WS_B, WS_X, false);
-    for (int it = 0; it < full_sweeps; ++it) {
-      residual_pass<N>(tab, op, Ne, ws, tile, lane, lambda, WS_B, WS_X, WS_S);
-      reduced_rhs_pass<N>(tab, op, Ne, ws, tile, lane, lambda, WS_S);
-      band_solve<N, FT>(Ub, Lb, piv, ws, tile, nz, lane, WS_R, WS_U);
-      if (max_sweeps > 0) {
-        // the correction only needs the accuracy of the outer sweep
-        int sw = 0;
-        double cr = 0.0;
-        reduced_refine<N, FT>(tab, op, Ne, ws, tile, lane, valid, lambda, Ub, Lb, piv, 1,
-                              rel_target, &sw, &cr);
-        sweeps += sw;
-      }
-      recover_pass<N>(tab, op, Ne, ws, tile, lane, lambda, WS_S, WS_X, true);
-    }
-    // Q_i = q_tt - sum_j c_j Q_j = q^E + x - q^
-    if (valid) {
-      for (int k = 0; k < nz; ++k) {
-#pragma unroll
-        for (int v = 0; v < 5; ++v) {
-          const size_t i = cix(nz, nc, v, k, c);
-          const double q = Qi[i] + ws[tix(tile, nz, k, HEVI_NWS, WS_X + v, lane)] -
-                           ws[tix(tile, nz, k, HEVI_NWS, WS_B + v, lane)];
-          Qi[i] = q;
-          if (!isfinite(q)) nonfinite = true;
-        }
-      }
-    }
-  }
-
-  if (valid) {
-    if (nonfinite) flag(info, 9 /*HEVI_E_NONFINITE*/, c);
-    if (max_sweeps > 0) {
-      if (!(relres <= rel_target)) flag(info, 6 /*HEVI_E_NOT_CONVERGED*/, c);
-      atomicMax(&info->max_sweeps, sweeps);
-      const double rr = isfinite(relres) ? relres : 1.0e300;
-      atomicMax((unsigned long long*)&info->max_res_bits,
-                (unsigned long long)__double_as_longlong(rr));
-    }
-  }
+  b_stage_solve<N, FT, FULL>((int64_t)blockIdx.x,
+      sh, tab, lambda, ops, Ub, Lb, piv, ws, E, Q, Qi, max_sweeps, rel_target, full_sweeps, info);
 }
 
-// ---------------------------------------------------------------------------
-// Fast stage solve as three kernels: k_stage_rhs (element-chunked),
-// k_stage_bsolve (one lane per column), k_stage_update (element-chunked).
-
-// pass 1: q^E = sum e_t E_t and q^ = q^E + sum c_j Q_j at the owned nodes; writes
-// Q_i <- (q^E_rho, q^E_U + lambda (PG q^_Theta - Phi' grad(zeta) q^_rho), q^E_Theta)
-// (at the lid: Q_U <- q^E_U - n (n . q^_U)) and the reduced right-hand side
-// r = grad(zeta).(q^_U + lambda (PG q^_Theta - Phi' grad(zeta) q^_rho)) (0 at the lid).
-// The term loop is outermost so that each term issues (N+1)*5 independent loads.
 template <int N>
 __global__ __launch_bounds__(64, 2) void k_stage_rhs(HeviShapeDev sh, HeviTab tab, double lambda,
                                                    const double* __restrict__ ops,
                                                    double* __restrict__ ws, HeviTerms E,
                                                    HeviTerms Q, double* __restrict__ Qi) {
-  const int Ne = sh.Ne, nz = sh.nz;
-  const Chunk ch = chunk_of(Ne);
-  if (ch.e0 >= ch.e1) return;
-  const int lane = ch.lane;
-  const int64_t tile = ch.tile;
-  const int64_t c = tile * T + lane;
-  const bool valid = c < sh.ncols;
-  const int64_t cc = valid ? c : sh.ncols - 1;
-  const int64_t nc = sh.ncols;
-  OpsView op{ops, tile, nz, lane};
-  if (ch.e0 == 0) ws[tix(tile, nz, 0, HEVI_NWS, WS_T, lane)] = 0.0;  // per-column flag
-  double c0 = 0.0, c1 = 0.0, c2 = 0.0;
-  for (int e = max(ch.e0 - 1, 0); e < ch.e1; ++e) {
-    double qE[N + 1][5], b[N + 1][5];
-#pragma unroll
-    for (int j = 0; j <= N; ++j)
-#pragma unroll
-      for (int v = 0; v < 5; ++v) qE[j][v] = 0.0;
-#pragma unroll 2
-    for (int t = 0; t < E.n; ++t) {
-      const double* src = E.v[t];
-      const double cf = E.coef[t];
-#pragma unroll
-      for (int j = 0; j <= N; ++j)
-#pragma unroll
-        for (int v = 0; v < 5; ++v) qE[j][v] += cf * src[cix(nz, nc, v, e * N + j, cc)];
-    }
-#pragma unroll
-    for (int j = 0; j <= N; ++j)
-#pragma unroll
-      for (int v = 0; v < 5; ++v) b[j][v] = qE[j][v];
-#pragma unroll 2
-    for (int t = 0; t < Q.n; ++t) {
-      const double* src = Q.v[t];
-      const double cf = Q.coef[t];
-#pragma unroll
-      for (int j = 0; j <= N; ++j)
-#pragma unroll
-        for (int v = 0; v < 5; ++v) b[j][v] += cf * src[cix(nz, nc, v, e * N + j, cc)];
-    }
-    double g0[N + 1], g1[N + 1], g2[N + 1], mi[N + 1], ph[N + 1], f0[N + 1], f1[N + 1], f2[N + 1];
-#pragma unroll
-    for (int j = 0; j <= N; ++j) {
-      const int k = e * N + j;
-      g0[j] = op(k, OP_GX); g1[j] = op(k, OP_GY); g2[j] = op(k, OP_GZ);
-      mi[j] = op(k, OP_MINV); ph[j] = op(k, OP_PHI);
-      const double p = op(k, OP_JCT) * b[j][4];
-      f0[j] = p * g0[j]; f1[j] = p * g1[j]; f2[j] = p * g2[j];
-    }
-    double ro[N + 1], ho[N + 1][3];
-#pragma unroll
-    for (int a = 0; a <= N; ++a) {
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-#pragma unroll
-      for (int j = 0; j <= N; ++j) {
-        const double d = tab.D[a * (N + 1) + j];
-        s0 += d * f0[j]; s1 += d * f1[j]; s2 += d * f2[j];
-      }
-      s0 *= tab.w[a]; s1 *= tab.w[a]; s2 *= tab.w[a];
-      if (a == 0) { s0 += c0; s1 += c1; s2 += c2; }
-      if (a == N) { c0 = s0; c1 = s1; c2 = s2; }
-      const int k = e * N + a;
-      const double gx = g0[a], gy = g1[a], gzz = g2[a];
-      if (k == 0 || k == nz - 1) {
-        const double inv = 1.0 / sqrt(gx * gx + gy * gy + gzz * gzz);
-        const double n0 = gx * inv, n1 = gy * inv, n2 = gzz * inv;
-        const double d = n0 * b[a][1] + n1 * b[a][2] + n2 * b[a][3];
-        ho[a][0] = qE[a][1] - n0 * d; ho[a][1] = qE[a][2] - n1 * d; ho[a][2] = qE[a][3] - n2 * d;
-        ro[a] = 0.0;
-      } else {
-        const double q1 = lambda * (-mi[a] * s0 - ph[a] * gx * b[a][0]);
-        const double q2 = lambda * (-mi[a] * s1 - ph[a] * gy * b[a][0]);
-        const double q3 = lambda * (-mi[a] * s2 - ph[a] * gzz * b[a][0]);
-        ho[a][0] = qE[a][1] + q1; ho[a][1] = qE[a][2] + q2; ho[a][2] = qE[a][3] + q3;
-        ro[a] = gx * (b[a][1] + q1) + gy * (b[a][2] + q2) + gzz * (b[a][3] + q3);
-      }
-    }
-    if (e >= ch.e0) {
-      const int amax = (e == Ne - 1) ? N : N - 1;
-#pragma unroll
-      for (int a = 0; a <= N; ++a) {
-        if (a <= amax) {
-          const int k = e * N + a;
-          ws[tix(tile, nz, k, HEVI_NWS, WS_R, lane)] = ro[a];
-          if (valid) {
-            Qi[cix(nz, nc, 0, k, c)] = qE[a][0];
-            Qi[cix(nz, nc, 1, k, c)] = ho[a][0];
-            Qi[cix(nz, nc, 2, k, c)] = ho[a][1];
-            Qi[cix(nz, nc, 3, k, c)] = ho[a][2];
-            Qi[cix(nz, nc, 4, k, c)] = qE[a][4];
-          }
-        }
-      }
-    }
-  }
+  b_stage_rhs<N>((int64_t)blockIdx.x, sh, tab, lambda, ops, ws, E, Q, Qi);
 }
 
-// pass 2: S u = r, one lane per column (+ reduced FP64 refinement for FP32 factors)
 template <int N, typename FT, bool REFINE>
 __global__ __launch_bounds__(64, 2) void k_stage_bsolve(HeviShapeDev sh, HeviTab tab, double lambda,
                                                      const double* __restrict__ ops,
@@ -1162,32 +131,10 @@ __global__ __launch_bounds__(64, 2) void k_stage_bsolve(HeviShapeDev sh, HeviTab
                                                      const uint8_t* __restrict__ piv,
                                                      double* __restrict__ ws, int max_sweeps,
                                                      double rel_target, HeviDevInfo* info) {
-  const int lane = threadIdx.x;
-  const int64_t tile = blockIdx.x;
-  const int64_t c = tile * T + lane;
-  const bool valid = c < sh.ncols;
-  const int nz = sh.nz;
-  band_solve<N, FT>(Ub, Lb, piv, ws, tile, nz, lane, WS_R, WS_U);
-  if (REFINE && max_sweeps > 0) {
-    OpsView op{ops, tile, nz, lane};
-    int sweeps = 0;
-    double corr = 0.0;
-    reduced_refine<N, FT>(tab, op, sh.Ne, ws, tile, lane, valid, lambda, Ub, Lb, piv, max_sweeps,
-                          rel_target, &sweeps, &corr);
-    if (valid) {
-      if (!(corr <= rel_target)) flag(info, 6 /*HEVI_E_NOT_CONVERGED*/, c);
-      atomicMax(&info->max_sweeps, sweeps);
-      const double rr = isfinite(corr) ? corr : 1.0e300;
-      atomicMax((unsigned long long*)&info->max_res_bits,
-                (unsigned long long)__double_as_longlong(rr));
-    }
-  }
+  b_stage_bsolve<N, FT, REFINE>((int64_t)blockIdx.x,
+      sh, tab, lambda, ops, Ub, Lb, piv, ws, max_sweeps, rel_target, info);
 }
 
-// pass 3: v_rho = Drho u, v_Th = DTh u; Q_i += (lambda v_rho,
-// lambda^2 (PG v_Th - Phi' grad(zeta) v_rho) [interior], lambda v_Th).
-// An element needs u on its neighbours too (the DSS of Drho u, DTh u at its end
-// nodes), so each iteration loads u and the operator on nodes (e-1)N .. (e+2)N.
 template <int N>
 __global__ __launch_bounds__(64) void k_stage_update(HeviShapeDev sh, HeviTab tab,
                                                       double lambda,
@@ -1195,121 +142,7 @@ __global__ __launch_bounds__(64) void k_stage_update(HeviShapeDev sh, HeviTab ta
                                                       double* __restrict__ ws,
                                                       double* __restrict__ Qi,
                                                       HeviDevInfo* info) {
-  constexpr int NC = 3 * N + 1;
-  const int Ne = sh.Ne, nz = sh.nz;
-  const Chunk ch = chunk_of(Ne);
-  if (ch.e0 >= ch.e1) return;
-  const int lane = ch.lane;
-  const int64_t tile = ch.tile;
-  const int64_t c = tile * T + lane;
-  const bool valid = c < sh.ncols;
-  const int64_t cc = valid ? c : sh.ncols - 1;
-  const int64_t nc = sh.ncols;
-  OpsView op{ops, tile, nz, lane};
-  const double l2 = lambda * lambda;
-  bool nonfinite = false;
-  double c0 = 0.0, c1 = 0.0, c2 = 0.0;
-  for (int e = max(ch.e0 - 1, 0); e < ch.e1; ++e) {
-    // ---- loads: u, J, J theta0 on nodes (e-1)N .. (e+2)N; operator and Q_i on the element
-    double Ju[NC], Jtu[NC];
-#pragma unroll
-    for (int q = 0; q < NC; ++q) {
-      const int k = (e - 1) * N + q;
-      const int kk = min(max(k, 0), nz - 1);
-      const double u = ws[tix(tile, nz, kk, HEVI_NWS, WS_U, lane)];
-      const double in = (k >= 0 && k < nz) ? 1.0 : 0.0;
-      Ju[q] = in * op(kk, OP_J) * u;
-      Jtu[q] = in * op(kk, OP_JTH) * u;
-    }
-    double g0[N + 1], g1[N + 1], g2[N + 1], mi[N + 1], ph[N + 1], jc[N + 1], q[N + 1][5];
-#pragma unroll
-    for (int j = 0; j <= N; ++j) {
-      const int k = e * N + j;
-      g0[j] = op(k, OP_GX); g1[j] = op(k, OP_GY); g2[j] = op(k, OP_GZ);
-      mi[j] = op(k, OP_MINV); ph[j] = op(k, OP_PHI); jc[j] = op(k, OP_JCT);
-#pragma unroll
-      for (int v = 0; v < 5; ++v) q[j][v] = Qi[cix(nz, nc, v, k, cc)];
-    }
-    // ---- v_rho, v_Th at the element's nodes (contributions of elements e-1, e, e+1)
-    double sr[N + 1], st[N + 1];
-#pragma unroll
-    for (int a = 0; a <= N; ++a) {
-      double r = 0.0, t = 0.0;
-#pragma unroll
-      for (int j = 0; j <= N; ++j) {
-        r += tab.w[j] * tab.D[j * (N + 1) + a] * Ju[N + j];
-        t += tab.D[a * (N + 1) + j] * Jtu[N + j];
-      }
-      sr[a] = r;
-      st[a] = tab.w[a] * t;
-    }
-    {
-      // element e-1 into node 0 (its node N), element e+1 into node N (its node 0)
-      double r0 = 0.0, t0 = 0.0, rN = 0.0, tN = 0.0;
-#pragma unroll
-      for (int j = 0; j <= N; ++j) {
-        r0 += tab.w[j] * tab.D[j * (N + 1) + N] * Ju[j];
-        t0 += tab.D[N * (N + 1) + j] * Jtu[j];
-        rN += tab.w[j] * tab.D[j * (N + 1) + 0] * Ju[2 * N + j];
-        tN += tab.D[0 * (N + 1) + j] * Jtu[2 * N + j];
-      }
-      sr[0] += r0; st[0] += tab.w[N] * t0;
-      sr[N] += rN; st[N] += tab.w[0] * tN;
-    }
-    double vr[N + 1], vt[N + 1], f0[N + 1], f1[N + 1], f2[N + 1];
-#pragma unroll
-    for (int j = 0; j <= N; ++j) {
-      vr[j] = mi[j] * sr[j];
-      vt[j] = -mi[j] * st[j];
-      const double p = jc[j] * vt[j];
-      f0[j] = p * g0[j]; f1[j] = p * g1[j]; f2[j] = p * g2[j];
-    }
-    // ---- pressure gradient and gravity, stage update
-#pragma unroll
-    for (int a = 0; a <= N; ++a) {
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-#pragma unroll
-      for (int j = 0; j <= N; ++j) {
-        const double d = tab.D[a * (N + 1) + j];
-        s0 += d * f0[j]; s1 += d * f1[j]; s2 += d * f2[j];
-      }
-      s0 *= tab.w[a]; s1 *= tab.w[a]; s2 *= tab.w[a];
-      if (a == 0) { s0 += c0; s1 += c1; s2 += c2; }
-      if (a == N) { c0 = s0; c1 = s1; c2 = s2; }
-      const int k = e * N + a;
-      const bool lid = (k == 0) || (k == nz - 1);
-      q[a][0] += lambda * vr[a];
-      q[a][4] += lambda * vt[a];
-      if (!lid) {
-        q[a][1] += l2 * (-mi[a] * s0 - ph[a] * g0[a] * vr[a]);
-        q[a][2] += l2 * (-mi[a] * s1 - ph[a] * g1[a] * vr[a]);
-        q[a][3] += l2 * (-mi[a] * s2 - ph[a] * g2[a] * vr[a]);
-      }
-    }
-    if (e >= ch.e0 && valid) {
-      const int amax = (e == Ne - 1) ? N : N - 1;
-#pragma unroll
-      for (int a = 0; a <= N; ++a) {
-        if (a <= amax) {
-#pragma unroll
-          for (int v = 0; v < 5; ++v) {
-            Qi[cix(nz, nc, v, e * N + a, c)] = q[a][v];
-            if (!isfinite(q[a][v])) nonfinite = true;
-          }
-        }
-      }
-    }
-  }
-  if (nonfinite) {
-    // count each column once: the first wavefront to flag it wins the exchange
-    unsigned long long* fl =
-        (unsigned long long*)&ws[tix(tile, nz, 0, HEVI_NWS, WS_T, lane)];
-    if (atomicCAS(fl, 0ull, 1ull) == 0ull) flag(info, 9 /*HEVI_E_NONFINITE*/, c);
-    else {
-      atomicMax(&info->status, 9);
-      atomicMin((unsigned long long*)&info->first_bad, (unsigned long long)c);
-    }
-  }
+  b_stage_update<N>((int64_t)blockIdx.x, sh, tab, lambda, ops, ws, Qi, info);
 }
 
 // ---------------------------------------------------------------------------

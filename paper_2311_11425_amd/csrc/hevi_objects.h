@@ -1,0 +1,65 @@
+// hevi_objects.h -- host-side objects of the C ABI and helpers shared by the
+// ABI implementation files (hevi_api.cpp, hevi_group_api.cpp, hevi_serve.cpp).
+// Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "hevi.h"
+#include "hevi_internal.h"
+
+struct hevi_ctx {
+  int device;
+};
+
+struct hevi_ops {
+  hevi_ctx* ctx;
+  hevi_shape shape;
+  hevi_consts consts;
+  HeviShapeDev sh;
+  HeviTab tab;
+  double* d_ops;
+  HeviDevInfo* d_info;
+};
+
+struct hevi_factors {
+  const hevi_ops* ops;
+  double lambda;
+  hevi_precision prec;
+  void* U;
+  void* L;
+  uint8_t* piv;
+  double* sbuf;  // FP64 assembly buffer (aliases U for FP64 factors)
+  double* ws;    // per-node FP64 scratch of the stage solve
+  HeviDevInfo* d_info;
+};
+
+namespace hevi_host {
+
+inline bool ok(hipError_t e) { return e == hipSuccess; }
+
+template <typename P>
+hevi_status dev_alloc(P** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 256;
+  void* v = nullptr;
+  if (!ok(hipMalloc(&v, bytes))) return HEVI_E_NOMEM;
+  *p = (P*)v;
+  return HEVI_OK;
+}
+
+HeviShapeDev dev_shape(const hevi_shape& s);
+hevi_status check_shape(const hevi_shape* s);
+size_t tiles_nodes(const HeviShapeDev& sh);
+// copy a device report to the host (waits for the stream); optionally reset it
+hevi_status read_info(HeviDevInfo* d_info, hipStream_t st, hevi_info* out, bool reset);
+void info_to_host(const HeviDevInfo& h, hevi_info* out);
+// validated linear-combination terms (lo = minimum count; empty = no columns)
+hevi_status terms(int32_t n, const double* const* v, const double* coef, int lo, bool empty,
+                  HeviTerms* t);
+// bytes of the library-owned storage of one factor object
+size_t factor_storage_bytes(const HeviShapeDev& sh, hevi_precision prec);
+
+}  // namespace hevi_host

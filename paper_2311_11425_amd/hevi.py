@@ -24,7 +24,12 @@ STATUS = {0: "HEVI_OK", 1: "HEVI_E_INVALID", 2: "HEVI_E_SHAPE", 3: "HEVI_E_NOMEM
 EXPORTS = ["hevi_create", "hevi_destroy", "hevi_status_str", "hevi_build_column_ops",
            "hevi_ops_check", "hevi_ops_free", "hevi_apply_op", "hevi_factor", "hevi_refactor",
            "hevi_factors_check", "hevi_factors_free", "hevi_stage_solve", "hevi_combine",
-           "hevi_tableau", "hevi_sizes"]
+           "hevi_tableau", "hevi_sizes", "hevi_group_create", "hevi_group_set_plan",
+           "hevi_group_get_plan", "hevi_group_step", "hevi_group_check", "hevi_group_autotune",
+           "hevi_group_free"]
+
+HEVI_MAX_STAGES = 8
+LAUNCH_MODES = {"one": 0, "per_order": 1, "per_member": 2}
 
 
 class HeviError(RuntimeError):
@@ -56,6 +61,24 @@ class Info(ctypes.Structure):
         return {"status": STATUS.get(self.status, self.status), "max_sweeps_used": self.max_sweeps_used,
                 "first_bad_col": self.first_bad_col, "n_bad_cols": self.n_bad_cols,
                 "max_rel_correction": self.max_rel_correction}
+
+
+class GroupMember(ctypes.Structure):
+    _fields_ = [("ops", ctypes.c_void_p), ("d_qn", ctypes.c_void_p), ("d_qref", ctypes.c_void_p),
+                ("d_out", ctypes.c_void_p), ("d_Q", ctypes.c_void_p * HEVI_MAX_STAGES),
+                ("d_S", ctypes.c_void_p * HEVI_MAX_STAGES)]
+
+
+class GroupPlan(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("grid", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+
+    def as_dict(self):
+        mode = {v: k for k, v in LAUNCH_MODES.items()}.get(self.mode, self.mode)
+        return {"mode": mode, "grid": self.grid, "use_graph": bool(self.use_graph)}
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("plan", GroupPlan), ("ms_per_step", ctypes.c_double)]
 
 
 _vp = ctypes.c_void_p
@@ -97,6 +120,15 @@ def load():
         "hevi_sizes": ([ctypes.POINTER(Shape), ctypes.c_int, ctypes.POINTER(ctypes.c_size_t),
                         ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)],
                        ctypes.c_int),
+        "hevi_group_create": ([_vp, i32, ctypes.POINTER(GroupMember), ctypes.c_char_p, dbl,
+                               ctypes.c_int, ctypes.POINTER(Refine), pp, _vp], ctypes.c_int),
+        "hevi_group_set_plan": ([_vp, _vp, ctypes.POINTER(GroupPlan)], ctypes.c_int),
+        "hevi_group_get_plan": ([_vp, ctypes.POINTER(GroupPlan)], ctypes.c_int),
+        "hevi_group_step": ([_vp, _vp, i32, _vp], ctypes.c_int),
+        "hevi_group_check": ([_vp, _vp, ctypes.POINTER(Info), _vp], ctypes.c_int),
+        "hevi_group_autotune": ([_vp, _vp, i32, ctypes.POINTER(TuneResult), i32,
+                                 ctypes.POINTER(i32), _vp], ctypes.c_int),
+        "hevi_group_free": ([_vp], None),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -264,3 +296,82 @@ class Context:
     def combine(self, ops, V, coef, out, stream=None):
         _check(self.lib.hevi_combine(self.handle, ops.handle, len(V), _ptr_array(V), _dbl_array(coef),
                                      _ptr(out), _stream(stream)), "hevi_combine")
+
+
+class Group:
+    """Members advanced together by hevi_group_step (see include/hevi.h).
+
+    members: list of dicts with keys ops (Ops), qn, qref, out, Q (list of s
+    tensors; Q[0] is ignored), S (list of s tensors)."""
+
+    def __init__(self, ctx, members, tableau="ARK3", dt=300.0, precision=HEVI_FP64, refine=None,
+                 stream=None):
+        self.ctx = ctx
+        self.lib = load()
+        self.members = members  # keep tensors alive
+        n = len(members)
+        arr = (GroupMember * max(1, n))()
+        for i, m in enumerate(members):
+            gm = arr[i]
+            gm.ops = m["ops"].handle.value if isinstance(m["ops"].handle, ctypes.c_void_p) else m["ops"].handle
+            gm.d_qn = m["qn"].data_ptr()
+            gm.d_qref = m["qref"].data_ptr()
+            gm.d_out = m["out"].data_ptr()
+            for j, t in enumerate(m["Q"]):
+                if t is not None:
+                    gm.d_Q[j] = t.data_ptr()
+            for j, t in enumerate(m["S"]):
+                gm.d_S[j] = t.data_ptr()
+        ref = None
+        if refine is not None:
+            r = tuple(refine) + (0,) * (3 - len(refine))
+            ref = Refine(int(r[0]), float(r[1]), int(r[2]))
+        h = ctypes.c_void_p()
+        _check(self.lib.hevi_group_create(ctx.handle, n, arr, tableau.encode(), float(dt), precision,
+                                          ctypes.byref(ref) if ref else None, ctypes.byref(h),
+                                          _stream(stream)), "hevi_group_create")
+        self.handle = h
+        self.n = n
+
+    def set_plan(self, mode="one", grid=0, use_graph=False):
+        p = GroupPlan(LAUNCH_MODES[mode] if isinstance(mode, str) else int(mode), int(grid),
+                      int(bool(use_graph)))
+        _check(self.lib.hevi_group_set_plan(self.ctx.handle, self.handle, ctypes.byref(p)),
+               "hevi_group_set_plan")
+
+    def plan(self):
+        p = GroupPlan()
+        _check(self.lib.hevi_group_get_plan(self.handle, ctypes.byref(p)), "hevi_group_get_plan")
+        return p.as_dict()
+
+    def step(self, refactor=True, stream=None):
+        _check(self.lib.hevi_group_step(self.ctx.handle, self.handle, int(bool(refactor)),
+                                        _stream(stream)), "hevi_group_step")
+
+    def check(self, stream=None):
+        infos = (Info * max(1, self.n))()
+        code = self.lib.hevi_group_check(self.ctx.handle, self.handle, infos, _stream(stream))
+        if code == 4:
+            raise HeviError(code, "hevi_group_check")
+        return code, [infos[i].as_dict() for i in range(self.n)]
+
+    def autotune(self, reps=3, stream=None):
+        cap = 64
+        res = (TuneResult * cap)()
+        nr = ctypes.c_int32(0)
+        _check(self.lib.hevi_group_autotune(self.ctx.handle, self.handle, int(reps), res, cap,
+                                            ctypes.byref(nr), _stream(stream)),
+               "hevi_group_autotune")
+        return [dict(res[i].plan.as_dict(), ms_per_step=res[i].ms_per_step)
+                for i in range(min(cap, nr.value))]
+
+    def free(self):
+        if self.handle:
+            self.lib.hevi_group_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

@@ -213,3 +213,11 @@ def serving_simulations(n_sims=16, seed=50, scale=1.0):
         out.append({"N": 4, "Ne": Ne, "ncols": max(nc, 1), "z_top": top, "profile": prof,
                     "seed": seed * 1000 + s})
     return out
+
+
+def spec_columns(spec):
+    """The column batch of one problem spec from uneven_problems or
+    serving_simulations (isothermal 300 K and a 30 km top unless the spec says
+    otherwise)."""
+    return make_columns(spec["N"], spec["Ne"], spec["ncols"], z_top=spec.get("z_top", 30.0e3),
+                        profile=spec.get("profile", "isothermal"), seed=spec["seed"])
