@@ -130,6 +130,252 @@ def stage_errors(st, col, qn, idx):
     return out
 
 
+def relerr_max(a, ref):
+    """Max over (variable, column) of ||a - ref||_2 / ||ref||_2 over nodes ([v][k][c])."""
+    num = np.sqrt(((a - ref) ** 2).sum(axis=1))
+    den = np.sqrt((ref ** 2).sum(axis=1))
+    den = np.where(den > 0, den, 1.0)
+    return float((num / den).max()) if num.size else 0.0
+
+
+def cfg1_leg(ctx, steps=200):
+    """Config 1 shape (256 columns, N=4, Ne=8, isothermal, ARK2, dt=30 s): per-stage
+    and end-of-step error of the mixed (FP32 factors + FP64 refinement) and FP64
+    paths against the oracle, and the step time (the batch fits in the caches)."""
+    import torch
+    import oracle
+    from oracle import tableaux
+    from paper_2311_11425_amd import inputs
+    from paper_2311_11425_amd.driver import ArkStepper, ColumnBatch
+    col = inputs.config1()
+    qn, qref = inputs.perturbed_state(col)
+    B = ColumnBatch(ctx, col)
+    qd, qrd = torch.from_numpy(qn).cuda(), torch.from_numpy(qref).cuda()
+    qo, Qo, _ = oracle.ark_step_batch(col, tableaux.as_float(tableaux.ark2()), 30.0, qn, qref,
+                                      refine=1, want_stages=True)
+    out = {}
+    for name, prec, refine in (("mixed", 1, (4, 1e-13, 0)), ("fp64", 0, (0, 1e-13, 0))):
+        st = ArkStepper(ctx, B, "ARK2", 30.0, precision=prec, refine=refine)
+        o = B.empty_state()
+        infos = st.step(qd, qrd, o, info=True)
+        Q = [t.cpu().numpy() for t in st.Q]
+        res = {"stage_solve_rel_err": stage_errors(st, col, qn, np.arange(col["ncols"])),
+               "increment_rel_err": {
+                   "Q2": relerr_max(Q[1] - qn, Qo[1] - qn),
+                   "Q3": relerr_max(Q[2] - qn, Qo[2] - qn),
+                   "q_next": relerr_max(o.cpu().numpy() - qn, qo - qn)},
+               "max_refinement_sweeps": max(i["max_sweeps_used"] for i in infos)}
+        for _ in range(10):
+            st.step(qd, qrd, o)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            st.step(qd, qrd, o)
+        torch.cuda.synchronize()
+        res["ms_per_step"] = (time.perf_counter() - t) * 1e3 / steps
+        out[name] = res
+    out["note"] = ("increments q - q^n are compared (the state is the reference plus a 1e-3 "
+                   "perturbation); stage_solve_rel_err is the solve of each stage's q^ rebuilt "
+                   "from the GPU's own Q_j, S_j")
+    return out
+
+
+def uneven_leg(ctx, scale=1.0, steps=5, reps=2):
+    """Uneven batch: 64 problems, N ~ U{3..7}, Ne ~ U{8..16}, 1k-50k columns each
+    (seed 40), isothermal 300 K, 30 km; one ARK3 step (dt = 300 s) of every problem
+    per group step, each phase one persistent launch; autotuned plan."""
+    import torch
+    import oracle
+    from paper_2311_11425_amd import hevi, inputs
+    from paper_2311_11425_amd.driver import ColumnBatch
+    specs = inputs.uneven_problems(scale=scale)
+    members, host_q = [], {}
+    worst = max(range(len(specs)), key=lambda p: (specs[p]["N"], specs[p]["Ne"]))
+    check = sorted({0, worst, len(specs) // 2, len(specs) - 1})
+    t0 = time.perf_counter()
+    for p, sp in enumerate(specs):
+        col = inputs.spec_columns(sp)
+        qn, qref = inputs.perturbed_state(col, seed=sp["seed"] + 7)
+        B = ColumnBatch(ctx, col)
+        m = {"batch": B, "ops": B.ops, "qn": torch.from_numpy(qn).cuda(),
+             "qref": torch.from_numpy(qref).cuda(), "out": B.empty_state(),
+             "Q": [None] + [B.empty_state() for _ in range(3)],
+             "S": [B.empty_state() for _ in range(4)]}
+        members.append(m)
+        if p in check:
+            idx = np.unique(np.linspace(0, col["ncols"] - 1, 12).astype(np.int64))
+            host_q[p] = (col, qn, idx)
+        del qn, qref
+    torch.cuda.synchronize()
+    log(f"uneven: {len(specs)} problems uploaded in {time.perf_counter() - t0:.1f} s")
+    ncols = sum(sp["ncols"] for sp in specs)
+    unknowns = sum(sp["ncols"] * 5 * (sp["Ne"] * sp["N"] + 1) for sp in specs)
+    res = {"problems": len(specs), "columns": ncols, "unknowns": unknowns,
+           "orders": sorted({sp["N"] for sp in specs}), "tableau": "ARK3", "dt": 300.0}
+    stream = torch.cuda.current_stream()
+    for name, prec in (("mixed", 1), ("fp64", 0)):
+        # FP32 factors of the higher orders contract more slowly: allow 8 sweeps
+        g = hevi.Group(ctx, members, "ARK3", 300.0, precision=prec, refine=(8, 1e-13, 0))
+        tune = g.autotune(reps=reps)
+        best = g.plan()
+        g.step()
+        code, infos = g.check()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(steps):
+            g.step()
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        per_member = min(r["ms_per_step"] for r in tune if r["mode"] == "per_member")
+        d = {"plan": best, "ms_per_step": ms, "column_solves_per_s": 3 * ncols / (ms * 1e-3),
+             "unknowns_per_s": 3 * unknowns / (ms * 1e-3),
+             "per_member_launches_ms_per_step": per_member,
+             "speedup_vs_per_member": per_member / ms,
+             "status": hevi.STATUS.get(code, code),
+             "max_refinement_sweeps": max(i["max_sweeps_used"] for i in infos),
+             "max_rel_correction": max(i["max_rel_correction"] for i in infos),
+             "autotune": tune}
+        # stage solves of sampled columns of 4 members against the oracle
+        errs = []
+        tab = hevi.tableau("ARK3")
+        for p, (col, qn, idx) in host_q.items():
+            m = members[p]
+            sc = dict(col)
+            for k in ("z", "J", "rho0", "Theta0"):
+                sc[k] = np.ascontiguousarray(col[k][:, idx])
+            sc["gz"] = np.ascontiguousarray(col["gz"][:, :, idx])
+            qs = np.ascontiguousarray(qn[..., idx])
+            Q = [qs] + [t.cpu().numpy()[..., idx] for t in m["Q"][1:]]
+            S = [t.cpu().numpy()[..., idx] for t in m["S"]]
+            lam = tab["Aimp"][1][1] * 300.0
+            for i in range(1, 4):
+                c = [(tab["Aimp"][i][j] - tab["Aexp"][i][j]) / tab["Aimp"][i][i] for j in range(i)]
+                qE = qs + sum(300.0 * tab["Aexp"][i][j] * S[j] for j in range(i))
+                P = sum(c[j] * Q[j] for j in range(i))
+                xo = oracle.solve_batch(sc, lam, qE + P, refine=1)
+                errs.append(relerr_max(Q[i] + P, xo))
+        d["stage_rel_err_vs_oracle_max"] = max(errs)
+        d["oracle_sample"] = f"{len(host_q)} members (incl. the highest order) x 12 columns x 3 stages"
+        res[name] = d
+        log(f"uneven {name}: {ms:.2f} ms/step, plan {best}, per-member {per_member:.2f} ms")
+        g.free()
+    return res
+
+
+def serve_leg(ctx, rates=(0.25, 0.5, 0.75, 1.0, 1.2), per_rate=300, scale=1.0, seed=9):
+    """Serving: 16 simulations (tops 30/60/120 km, Ne ~ U{10..40}, N = 4, 5k-86,402
+    columns, seed 50) registered with a server; each request is the ARK3
+    second-stage solve of one simulation (FP64).  Saturation = completed
+    requests/s of a burst of 8 requests per simulation; then Poisson arrivals of
+    uniformly chosen simulations at fractions of it, latency p50/p99 from the
+    server's submit-to-completion clock."""
+    import threading
+    import ctypes
+    import torch
+    from paper_2311_11425_amd import hevi, inputs
+    from paper_2311_11425_amd.driver import ColumnBatch
+    tab = hevi.tableau("ARK3")
+    dt = 300.0
+    lam = tab["Aimp"][1][1] * dt
+    specs = inputs.serving_simulations(scale=scale)
+    budget = 0
+    sims = []
+    t0 = time.perf_counter()
+    for sp in specs:
+        col = inputs.spec_columns(sp)
+        qn, qref = inputs.perturbed_state(col, seed=sp["seed"] + 3)
+        B = ColumnBatch(ctx, col)
+        qd, qrd = torch.from_numpy(qn).cuda(), torch.from_numpy(qref).cuda()
+        S1 = B.empty_state()
+        ctx.apply_op(B.ops, qd, S1, xref=qrd)
+        Qi = B.empty_state()
+        sims.append({"B": B, "qn": qd, "S1": S1, "Qi": Qi, "ncols": sp["ncols"],
+                     "Ep": hevi._ptr_array([qd, S1]),
+                     "ep": hevi._dbl_array([1.0, dt * tab["Aexp"][1][0]]),
+                     "Qp": hevi._ptr_array([qd]), "cp": hevi._dbl_array([-1.0]),
+                     "out": ctypes.c_void_p(Qi.data_ptr())})
+        budget += hevi.sizes(4, sp["Ne"], sp["ncols"])["factors"] * sp["ncols"]
+    torch.cuda.synchronize()
+    log(f"serve: {len(specs)} simulations ready in {time.perf_counter() - t0:.1f} s")
+    srv = hevi.Server(ctx, 1 << 40, max_inflight=1 << 16)
+    for sm in sims:
+        sm["id"] = srv.register(sm["B"].ops, lam)
+    torch.cuda.synchronize()
+
+    def submit(k):
+        sm = sims[k]
+        while True:
+            code, t = srv.submit_raw(sm["id"], sm["Ep"], sm["ep"], 2, sm["Qp"], sm["cp"], 1,
+                                     sm["out"])
+            if code == 0:
+                return t
+            if code != 7:
+                raise hevi.HeviError(code, "hevi_serve_submit")
+
+    # warm up, then saturation from a burst
+    for t in [submit(k) for k in range(len(sims))]:
+        srv.wait(t)
+    burst = [k for _ in range(8) for k in range(len(sims))]
+    t = time.perf_counter()
+    tickets = [submit(k) for k in burst]
+    for tk in tickets:
+        srv.wait(tk)
+    sat_s = time.perf_counter() - t
+    sat = len(burst) / sat_s
+    cols_per_req = float(np.mean([sm["ncols"] for sm in sims]))
+    out = {"simulations": len(sims), "columns": [sm["ncols"] for sm in sims],
+           "saturation_requests_per_s": sat,
+           "saturation_column_solves_per_s": sum(sims[k]["ncols"] for k in burst) / sat_s,
+           "rates": []}
+    rng = np.random.default_rng(seed)
+    for frac in rates:
+        rate = frac * sat
+        gaps = rng.exponential(1.0 / rate, per_rate)
+        which = rng.integers(0, len(sims), per_rate)
+        tickets = [None] * per_rate
+        ready = threading.Semaphore(0)
+
+        def producer():
+            t_next = time.perf_counter()
+            for i in range(per_rate):
+                t_next += gaps[i]
+                while True:
+                    d = t_next - time.perf_counter()
+                    if d <= 0:
+                        break
+                    if d > 0.002:
+                        time.sleep(d - 0.001)
+                tickets[i] = submit(int(which[i]))
+                ready.release()
+
+        lat = []
+        th = threading.Thread(target=producer)
+        t = time.perf_counter()
+        th.start()
+        for i in range(per_rate):
+            ready.acquire()
+            inf, l = srv.wait(tickets[i])
+            if inf["status"] != "HEVI_OK":
+                raise SystemExit(f"serve: request reported {inf}")
+            lat.append(l)
+        th.join()
+        wall = time.perf_counter() - t
+        done_cols = float(sum(sims[int(k)]["ncols"] for k in which))
+        out["rates"].append({"offered_fraction_of_saturation": frac,
+                             "offered_requests_per_s": rate,
+                             "achieved_requests_per_s": per_rate / wall,
+                             "column_solves_per_s": done_cols / wall,
+                             "latency_ms": {"p50": 1e3 * pct(lat, 50), "p99": 1e3 * pct(lat, 99),
+                                            "mean": 1e3 * float(np.mean(lat))}})
+        log(f"serve {frac:.2f}x: p50 {1e3 * pct(lat, 50):.2f} ms, p99 {1e3 * pct(lat, 99):.2f} ms")
+    out["mean_columns_per_request"] = cols_per_req
+    out["requests_per_rate"] = per_rate
+    srv.close()
+    return out
+
+
 def run_path(ctx, B, name, qd, qrd, steps, warmup):
     import torch
     from paper_2311_11425_amd.driver import ArkStepper
@@ -182,14 +428,18 @@ def run_path(ctx, B, name, qd, qrd, steps, warmup):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--ncols", type=int, default=86402)
     ap.add_argument("--precision", choices=list(PATHS), default="fp64")
     ap.add_argument("--only", action="store_true", help="time only the selected path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-error-check", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="CPU-seconds for the oracle")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the config-1 accuracy, uneven-batch and serving legs")
+    ap.add_argument("--uneven-scale", type=float, default=1.0)
+    ap.add_argument("--serve-scale", type=float, default=1.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run plain 1 GiB device copies (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -291,6 +541,17 @@ def main():
     if not args.no_cpu_baseline:
         log("oracle CPU baseline ...")
         res["cpu_baseline"] = oracle_rate(col, qn, qref, args.cpu_budget)
+    if not args.no_extra:
+        del B, st
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        log("config-1 accuracy leg ...")
+        res["config1_ark2_accuracy"] = cfg1_leg(ctx)
+        log("uneven-batch leg ...")
+        res["uneven_batch"] = uneven_leg(ctx, scale=args.uneven_scale)
+        torch.cuda.empty_cache()
+        log("serving leg ...")
+        res["serving"] = serve_leg(ctx, scale=args.serve_scale)
     res["paper_context"] = {
         "note": "whole-model 10-day baroclinic-instability time-to-solution on 512 AMD EPYC "
                 "Rome cores (CPU); context only, not this metric",

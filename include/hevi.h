@@ -287,6 +287,54 @@ hevi_status hevi_group_autotune(hevi_ctx *ctx, hevi_group *g, int32_t reps,
                                 hipStream_t stream);
 void hevi_group_free(hevi_group *g);
 
+/* ---- serving: continuous batching of stage solves over resident factors -----
+ * A server keeps the factors of registered simulations resident in HBM and
+ * runs stage-solve requests (each exactly hevi_stage_solve of one simulation,
+ * Sec. 4.3 eq. lhevi-ark-final-3) from any host thread.  A worker thread
+ * gathers the queued requests into batches -- at most one request per
+ * simulation per batch, first come first served -- and runs each batch as
+ * one persistent launch per kernel phase over the tiles of all its requests
+ * (FP64 and FP32-factor simulations in separate launches), on the server's own
+ * stream, with up to 3 batches in flight.  Requests of one simulation run in
+ * submission order.  FP32-factor simulations use the refinement {4, 1e-13}.
+ *
+ * hevi_serve_create: hbm_budget_bytes bounds the library-owned memory of all
+ *   registered simulations (factors and scratch); max_inflight bounds the
+ *   requests submitted and not yet completed.
+ * hevi_serve_register: factor A = I - lambda L_z of `ops` (enqueued on the
+ *   server's stream) and return a simulation id.  HEVI_E_NOMEM: not admitted
+ *   now (the budget is used up; release a simulation and retry).  `ops` must
+ *   stay valid until hevi_serve_release.
+ * hevi_serve_submit: queue one stage solve of simulation sim_id (arguments as
+ *   in hevi_stage_solve).  The device buffers must stay valid and unchanged
+ *   until the ticket completes; the stage-solve operands are read when the
+ *   batch runs.  HEVI_E_BUSY: max_inflight requests are pending (retry later);
+ *   HEVI_E_CLOSED: unknown or released simulation, or server shut down.
+ * hevi_serve_poll / hevi_serve_wait: report a ticket's completion (poll: *done
+ *   = 0 or 1; wait: blocks).  On completion the ticket's kernel report and the
+ *   latency in seconds from submit to observed completion (latency_s may be
+ *   NULL) are written, and the ticket is retired: a second poll or wait of it
+ *   returns HEVI_E_CLOSED, as does an unknown ticket.
+ * hevi_serve_release: wait for the simulation's requests, then free its
+ *   factors and return its budget.  hevi_serve_destroy: finish every queued
+ *   request, stop the worker and free everything.
+ * All server calls are thread-safe.  If the device fails, pending and later
+ * tickets complete with status HEVI_E_DEVICE. */
+hevi_status hevi_serve_create(hevi_ctx *ctx, size_t hbm_budget_bytes, int32_t max_inflight,
+                              hevi_server **out);
+hevi_status hevi_serve_register(hevi_server *srv, const hevi_ops *ops, double lambda,
+                                hevi_precision prec, int32_t *sim_id);
+hevi_status hevi_serve_submit(hevi_server *srv, int32_t sim_id, int32_t n_e,
+                              const double *const *h_dE, const double *h_e, int32_t n_prev,
+                              const double *const *h_dQprev, const double *h_c, double *d_Qi,
+                              uint64_t *ticket);
+hevi_status hevi_serve_poll(hevi_server *srv, uint64_t ticket, int32_t *done, hevi_info *info,
+                            double *latency_s);
+hevi_status hevi_serve_wait(hevi_server *srv, uint64_t ticket, hevi_info *info,
+                            double *latency_s);
+hevi_status hevi_serve_release(hevi_server *srv, int32_t sim_id);
+void hevi_serve_destroy(hevi_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,7 +26,8 @@ EXPORTS = ["hevi_create", "hevi_destroy", "hevi_status_str", "hevi_build_column_
            "hevi_factors_check", "hevi_factors_free", "hevi_stage_solve", "hevi_combine",
            "hevi_tableau", "hevi_sizes", "hevi_group_create", "hevi_group_set_plan",
            "hevi_group_get_plan", "hevi_group_step", "hevi_group_check", "hevi_group_autotune",
-           "hevi_group_free"]
+           "hevi_group_free", "hevi_serve_create", "hevi_serve_register", "hevi_serve_submit",
+           "hevi_serve_poll", "hevi_serve_wait", "hevi_serve_release", "hevi_serve_destroy"]
 
 HEVI_MAX_STAGES = 8
 LAUNCH_MODES = {"one": 0, "per_order": 1, "per_member": 2}
@@ -129,6 +130,15 @@ def load():
         "hevi_group_autotune": ([_vp, _vp, i32, ctypes.POINTER(TuneResult), i32,
                                  ctypes.POINTER(i32), _vp], ctypes.c_int),
         "hevi_group_free": ([_vp], None),
+        "hevi_serve_create": ([_vp, ctypes.c_size_t, i32, pp], ctypes.c_int),
+        "hevi_serve_register": ([_vp, _vp, dbl, ctypes.c_int, ctypes.POINTER(i32)], ctypes.c_int),
+        "hevi_serve_submit": ([_vp, i32, i32, pp, pd, i32, pp, pd, _vp,
+                               ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+        "hevi_serve_poll": ([_vp, ctypes.c_uint64, ctypes.POINTER(i32), ctypes.POINTER(Info), pd],
+                            ctypes.c_int),
+        "hevi_serve_wait": ([_vp, ctypes.c_uint64, ctypes.POINTER(Info), pd], ctypes.c_int),
+        "hevi_serve_release": ([_vp, i32], ctypes.c_int),
+        "hevi_serve_destroy": ([_vp], None),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -373,5 +383,68 @@ class Group:
     def __del__(self):
         try:
             self.free()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching stage-solve server (hevi_serve_*, see include/hevi.h).
+    Calls are thread-safe; ctypes releases the GIL while the library waits."""
+
+    def __init__(self, ctx, hbm_budget_bytes, max_inflight=1024):
+        self.ctx = ctx
+        self.lib = load()
+        h = ctypes.c_void_p()
+        _check(self.lib.hevi_serve_create(ctx.handle, int(hbm_budget_bytes), int(max_inflight),
+                                          ctypes.byref(h)), "hevi_serve_create")
+        self.handle = h
+
+    def register(self, ops, lam, precision=HEVI_FP64):
+        """Simulation id, or raises HeviError (code 3 = not admitted within the budget)."""
+        sid = ctypes.c_int32(-1)
+        _check(self.lib.hevi_serve_register(self.handle, ops.handle, float(lam), precision,
+                                            ctypes.byref(sid)), "hevi_serve_register")
+        return sid.value
+
+    def submit_raw(self, sim, Ep, ep, ne, Qp, cp, nq, Qi_ptr):
+        """Submit with prepared ctypes arrays (no per-call marshalling); returns
+        (status, ticket)."""
+        t = ctypes.c_uint64(0)
+        code = self.lib.hevi_serve_submit(self.handle, sim, ne, Ep, ep, nq, Qp, cp, Qi_ptr,
+                                          ctypes.byref(t))
+        return code, t.value
+
+    def submit(self, sim, E, e, Qprev, c, Qi):
+        code, t = self.submit_raw(sim, _ptr_array(E), _dbl_array(e), len(E), _ptr_array(Qprev),
+                                  _dbl_array(c), len(Qprev), _ptr(Qi))
+        _check(code, "hevi_serve_submit")
+        return t
+
+    def poll(self, ticket):
+        done = ctypes.c_int32(0)
+        inf = Info()
+        lat = ctypes.c_double(0.0)
+        _check(self.lib.hevi_serve_poll(self.handle, ticket, ctypes.byref(done), ctypes.byref(inf),
+                                        ctypes.byref(lat)), "hevi_serve_poll")
+        return (inf.as_dict(), lat.value) if done.value else None
+
+    def wait(self, ticket):
+        inf = Info()
+        lat = ctypes.c_double(0.0)
+        _check(self.lib.hevi_serve_wait(self.handle, ticket, ctypes.byref(inf), ctypes.byref(lat)),
+               "hevi_serve_wait")
+        return inf.as_dict(), lat.value
+
+    def release(self, sim):
+        _check(self.lib.hevi_serve_release(self.handle, int(sim)), "hevi_serve_release")
+
+    def close(self):
+        if self.handle:
+            self.lib.hevi_serve_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
         except Exception:
             pass

@@ -78,3 +78,26 @@ def test_sizes_rejects_bad_shapes(N, Ne, nc):
     with pytest.raises(hevi.HeviError) as e:
         hevi.sizes(N, Ne, nc)
     assert e.value.code == 2
+
+
+def test_serve_and_group_reject_null_handles():
+    """Failure handling that needs no device: NULL handles and bad arguments are
+    rejected synchronously (HEVI_E_INVALID), destroy/free accept NULL."""
+    import ctypes
+    lib = hevi.load()
+    out = ctypes.c_void_p()
+    assert lib.hevi_serve_create(None, 1 << 20, 4, ctypes.byref(out)) == 1
+    sid = ctypes.c_int32(0)
+    assert lib.hevi_serve_register(None, None, 1.0, 0, ctypes.byref(sid)) == 1
+    t = ctypes.c_uint64(0)
+    assert lib.hevi_serve_submit(None, 0, 1, None, None, 0, None, None, None, ctypes.byref(t)) == 1
+    done = ctypes.c_int32(0)
+    assert lib.hevi_serve_poll(None, 1, ctypes.byref(done), None, None) == 1
+    assert lib.hevi_serve_wait(None, 1, None, None) == 1
+    assert lib.hevi_serve_release(None, 0) == 1
+    lib.hevi_serve_destroy(None)
+    assert lib.hevi_group_create(None, 1, None, b"ARK3", 1.0, 0, None, ctypes.byref(out),
+                                 None) == 1
+    assert lib.hevi_group_step(None, None, 1, None) == 1
+    assert lib.hevi_group_set_plan(None, None, None) == 1
+    lib.hevi_group_free(None)

@@ -1,0 +1,196 @@
+"""The continuous-batching server (hevi_serve_*) through the C ABI.
+
+* A request's result is bit-identical to hevi_stage_solve of the same operands,
+  whether it runs alone or batched with requests of other simulations, and it
+  matches the FP64 oracle.
+* Admission within the HBM budget, backpressure (HEVI_E_BUSY), unknown and
+  retired ids (HEVI_E_CLOSED), release, and submits from several threads.
+"""
+import threading
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2311_11425_amd import inputs
+from parity_util import relerr_cols, stage_floor
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DT = 300.0
+GAMMA = 1767732205903.0 / 4055673282236.0  # ARK3 diagonal
+LAM = GAMMA * DT
+A21 = 1767732205903.0 / 2027836641118.0    # ARK3 explicit a_21
+
+SPECS = [
+    {"N": 4, "Ne": 12, "ncols": 300, "seed": 501, "z_top": 60e3, "profile": "lapse_capped"},
+    {"N": 4, "Ne": 20, "ncols": 65, "seed": 502},
+    {"N": 3, "Ne": 9, "ncols": 130, "seed": 503},
+    {"N": 4, "Ne": 10, "ncols": 1, "seed": 504, "z_top": 120e3, "profile": "lapse_capped"},
+]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2311_11425_amd import hevi
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    c = hevi.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+class SimData:
+    """One simulation: columns, ops, and the operands of an ARK3 second-stage solve."""
+
+    def __init__(self, ctx, spec):
+        from paper_2311_11425_amd.driver import ColumnBatch
+        self.col = inputs.spec_columns(spec)
+        self.B = ColumnBatch(ctx, self.col)
+        qn, qref = inputs.perturbed_state(self.col, seed=spec["seed"] + 3)
+        self.qn_h, self.qref_h = qn, qref
+        self.qn, self.qref = dev(qn), dev(qref)
+        self.S1 = self.B.empty_state()
+        ctx.apply_op(self.B.ops, self.qn, self.S1, xref=self.qref)
+        self.E, self.e = [self.qn, self.S1], [1.0, DT * A21]
+        self.Qp, self.c = [self.qn], [-1.0]
+
+    def out(self):
+        return torch.full_like(self.qn, float("nan"))
+
+
+def reference(ctx, sd, prec):
+    f = ctx.factor(sd.B.ops, LAM, prec)
+    x = sd.out()
+    ctx.stage_solve(f, sd.E, sd.e, sd.Qp, sd.c, x, refine=(4, 1e-13, 0))
+    torch.cuda.synchronize()
+    f.free()
+    return x.cpu()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_serve_alone_and_mixed_match_stage_solve(ctx, prec):
+    from paper_2311_11425_amd import hevi
+    sims = [SimData(ctx, sp) for sp in SPECS]
+    ref = [reference(ctx, sd, prec) for sd in sims]
+    srv = hevi.Server(ctx, 1 << 34, max_inflight=64)
+    ids = [srv.register(sd.B.ops, LAM, prec) for sd in sims]
+    # alone: one request at a time
+    for sd, sid, r in zip(sims, ids, ref):
+        x = sd.out()
+        inf, lat = srv.wait(srv.submit(sid, sd.E, sd.e, sd.Qp, sd.c, x))
+        assert inf["status"] == "HEVI_OK", inf
+        assert lat > 0
+        torch.cuda.synchronize()
+        assert torch.equal(x.cpu(), r)
+    # mixed: every simulation twice, submitted together (separate outputs)
+    outs = [[sd.out(), sd.out()] for sd in sims]
+    tickets = [srv.submit(sid, sd.E, sd.e, sd.Qp, sd.c, o)
+               for rep in range(2) for sd, sid, o in zip(sims, ids, [oo[rep] for oo in outs])]
+    for t in tickets:
+        inf, _ = srv.wait(t)
+        assert inf["status"] == "HEVI_OK", inf
+    torch.cuda.synchronize()
+    for oo, r in zip(outs, ref):
+        for o in oo:
+            assert torch.equal(o.cpu(), r)
+    # the oracle on every simulation: q^ = q^E - Q_1 with Q_1 = q^n, q_tt = Q_2 + Q_1
+    for sd, r in zip(sims, ref):
+        qE = sd.qn_h + DT * A21 * sd.S1.cpu().numpy()
+        P = -sd.qn_h
+        x_or = oracle.solve_batch(sd.col, LAM, qE + P, refine=1)
+        err = relerr_cols(r.numpy() + P, x_or)
+        tol = max(1e-12 if prec == 0 else 1e-10,
+                  4 * stage_floor(oracle, sd.col, LAM, qE, P, r.numpy(), x_or))
+        if prec == 0:
+            tol = max(tol, 10 * relerr_cols(oracle.solve_batch(sd.col, LAM, qE + P, refine=0),
+                                            x_or))
+        print(f"N={sd.col['N']} Ne={sd.col['Ne']}: {err:.2e} (tol {tol:.2e})", flush=True)
+        assert err < tol
+    for sid in ids:
+        srv.release(sid)
+    srv.close()
+
+
+def test_serve_admission_busy_closed(ctx):
+    from paper_2311_11425_amd import hevi
+    a, b = SimData(ctx, SPECS[0]), SimData(ctx, SPECS[1])
+    sz_a = hevi.sizes(4, 12, 300)
+    srv = hevi.Server(ctx, 1, max_inflight=2)  # a 1-byte budget admits nothing
+    with pytest.raises(hevi.HeviError) as e:
+        srv.register(a.B.ops, LAM)
+    assert e.value.code == 3
+    srv.close()
+    # budget for one simulation: the second waits for a release
+    srv = hevi.Server(ctx, 64 << 20, max_inflight=2)
+    sa = srv.register(a.B.ops, LAM)
+    try:
+        srv.register(b.B.ops, LAM)
+        admitted_both = True
+    except hevi.HeviError as err:
+        assert err.code == 3
+        admitted_both = False
+    assert sz_a["factors"] > 0
+    # backpressure: a burst beyond max_inflight sees HEVI_E_BUSY
+    outs = [a.out() for _ in range(40)]
+    tickets, busy = [], 0
+    for o in outs:
+        try:
+            tickets.append(srv.submit(sa, a.E, a.e, a.Qp, a.c, o))
+        except hevi.HeviError as err:
+            assert err.code == 7
+            busy += 1
+    for t in tickets:
+        srv.wait(t)
+    assert busy > 0 and len(tickets) >= 2
+    # retired and unknown tickets / ids
+    with pytest.raises(hevi.HeviError) as e:
+        srv.wait(tickets[0])
+    assert e.value.code == 8
+    with pytest.raises(hevi.HeviError) as e:
+        srv.submit(12345, a.E, a.e, a.Qp, a.c, outs[0])
+    assert e.value.code == 8
+    srv.release(sa)
+    with pytest.raises(hevi.HeviError) as e:
+        srv.submit(sa, a.E, a.e, a.Qp, a.c, outs[0])
+    assert e.value.code == 8
+    if not admitted_both:
+        sb = srv.register(b.B.ops, LAM)  # fits after the release
+        srv.release(sb)
+    srv.close()
+
+
+def test_serve_threads(ctx):
+    """Four host threads submit and wait concurrently; every result is the reference."""
+    from paper_2311_11425_amd import hevi
+    sims = [SimData(ctx, sp) for sp in SPECS[:3]]
+    ref = [reference(ctx, sd, 0) for sd in sims]
+    srv = hevi.Server(ctx, 1 << 34, max_inflight=256)
+    ids = [srv.register(sd.B.ops, LAM) for sd in sims]
+    errors = []
+
+    def client(k):
+        try:
+            for rep in range(6):
+                j = (k + rep) % len(sims)
+                o = sims[j].out()
+                t = srv.submit(ids[j], sims[j].E, sims[j].e, sims[j].Qp, sims[j].c, o)
+                inf, _ = srv.wait(t)
+                assert inf["status"] == "HEVI_OK"
+                torch.cuda.synchronize()
+                assert torch.equal(o.cpu(), ref[j])
+        except Exception as ex:  # reported in the main thread
+            errors.append(repr(ex))
+
+    th = [threading.Thread(target=client, args=(k,)) for k in range(4)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errors, errors
+    srv.close()
