@@ -389,40 +389,39 @@ def run_path(ctx, B, name, qd, qrd, steps, warmup):
         st.step(qd, qrd, out)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    marks = {"stage_solve": [], "refactor": [], "apply_op": []}
-    orig = {k: getattr(ctx, k) for k in marks}
-
-    def wrap(k):
-        def f(*a, **kw):
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            r = orig[k](*a, **kw)
-            e1.record(stream)
-            marks[k].append((e0, e1))
-            return r
-        return f
-
-    for k in marks:
-        setattr(ctx, k, wrap(k))
-    step_ev = []
+    # headline pass: whole steps, events pre-created, nothing else in the loop
+    step_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(steps)]
     torch.cuda.synchronize()
     t = time.perf_counter()
-    for _ in range(steps):
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
+    for a, b in step_ev:
         a.record(stream)
         st.step(qd, qrd, out)
         b.record(stream)
-        step_ev.append((a, b))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t
-    for k in marks:
-        setattr(ctx, k, orig[k])
-    ms = {k: [a.elapsed_time(b) for a, b in v] for k, v in marks.items()}
     step_ms = [a.elapsed_time(b) for a, b in step_ev]
+    # breakdown pass: HIP events around every C-ABI call of a step
+    nb = min(steps, 20)
+    seq = st.calls(qd, qrd, out)
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in seq] for _ in range(nb)]
+    torch.cuda.synchronize()
+    for r in range(nb):
+        for (name, fn, args), (a, b) in zip(seq, ev[r]):
+            a.record(stream)
+            code = fn(*args)
+            b.record(stream)
+            if code != 0:
+                raise SystemExit(f"{name} returned {code}")
+    torch.cuda.synchronize()
+    ms = {"stage_solve": [], "refactor": [], "apply_op": [], "combine": []}
+    for r in range(nb):
+        for (name, _, _), (a, b) in zip(seq, ev[r]):
+            ms[name].append(a.elapsed_time(b))
     return st, {"wall_s": wall, "step_ms": step_ms, "stage_ms": ms["stage_solve"],
-                "factor_ms": ms["refactor"], "apply_ms": ms["apply_op"]}
+                "factor_ms": ms["refactor"], "apply_ms": ms["apply_op"],
+                "combine_ms": ms["combine"]}
 
 
 def main():
@@ -484,6 +483,7 @@ def main():
                                 "p99": pct(r["stage_ms"], 99)},
              "stage_only_column_solves_per_s": ncols / (stage_ms * 1e-3),
              "factor_ms": fac_ms, "apply_op_ms": app_ms,
+             "combine_ms": float(np.mean(r["combine_ms"])),
              "factor_plus_stages_column_solves_per_s": 3 * ncols / ((fac_ms + 3 * stage_ms) * 1e-3)}
         if not args.no_error_check:
             d["stage_rel_err_vs_oracle"] = stage_errors(st, col, qn, idx)

@@ -1,8 +1,8 @@
 // hevi_api.cpp -- C ABI of the batched LHEVI column solver (see include/hevi.h).
 //
-// Host side only: argument validation, ownership of device buffers, the 1D
-// GLL tables of order N, the ARK tableaux, and kernel launches on the caller's
-// stream.  The arithmetic of the method runs in hevi_kernels.hip.
+// Host side only: argument validation, ownership of device buffers, the ARK
+// tableaux, and kernel launches on the caller's stream.  The arithmetic of the
+// method runs in hevi_kernels.hip (GLL tables: compile-time constants, hevi_gll.h).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -14,69 +14,6 @@
 #include "hevi.h"
 #include "hevi_internal.h"
 #include "hevi_objects.h"
-
-namespace {
-using namespace hevi_host;
-
-// ---- 1D Gauss-Lobatto-Legendre tables (Sec. 3) ------------------------------
-// The interior nodes are the roots of q(x) = P_{N+1}(x) - P_{N-1}(x) (which
-// also vanishes at +-1), found by Newton's method with q'(x) = (2N+1) P_N(x);
-// weights w_i = 2 / (N (N+1) P_N(x_i)^2); the derivative matrix from the
-// barycentric form D_ij = (b_j / b_i) / (x_i - x_j), D_ii = -sum_{j!=i} D_ij,
-// b_j = 1 / prod_{k!=j} (x_j - x_k).
-void legendre3(int N, double x, double* pm1, double* p, double* pp1) {
-  double a = 1.0, b = x;  // P_0, P_1
-  if (N == 0) { *pm1 = 0.0; *p = 1.0; *pp1 = x; return; }
-  for (int n = 1; n < N; ++n) {
-    double c = ((2 * n + 1) * x * b - n * a) / (n + 1);
-    a = b; b = c;
-  }
-  *pm1 = a; *p = b;
-  *pp1 = ((2 * N + 1) * x * b - N * a) / (N + 1);
-}
-
-void gll_tables(int N, HeviTab* tab, double* xi_out) {
-  double x[HEVI_MAXN + 1];
-  x[0] = -1.0; x[N] = 1.0;
-  for (int j = 1; j < N; ++j) {
-    double t = -std::cos(M_PI * j / N);
-    for (int it = 0; it < 200; ++it) {
-      double pm1, p, pp1;
-      legendre3(N, t, &pm1, &p, &pp1);
-      const double dt = (pp1 - pm1) / ((2 * N + 1) * p);
-      t -= dt;
-      if (std::fabs(dt) <= 1e-17) break;
-    }
-    x[j] = t;
-  }
-  std::memset(tab, 0, sizeof(*tab));
-  for (int i = 0; i <= N; ++i) {
-    double pm1, p, pp1;
-    legendre3(N, x[i], &pm1, &p, &pp1);
-    tab->w[i] = 2.0 / (N * (N + 1.0) * p * p);
-  }
-  double bw[HEVI_MAXN + 1];
-  for (int j = 0; j <= N; ++j) {
-    double prod = 1.0;
-    for (int k = 0; k <= N; ++k)
-      if (k != j) prod *= (x[j] - x[k]);
-    bw[j] = 1.0 / prod;
-  }
-  for (int i = 0; i <= N; ++i) {
-    double diag = 0.0;
-    for (int j = 0; j <= N; ++j) {
-      if (i == j) continue;
-      const double d = (bw[j] / bw[i]) / (x[i] - x[j]);
-      tab->D[i * (N + 1) + j] = d;
-      diag -= d;
-    }
-    tab->D[i * (N + 1) + i] = diag;
-  }
-  if (xi_out)
-    for (int i = 0; i <= N; ++i) xi_out[i] = x[i];
-}
-
-}  // namespace
 
 namespace hevi_host {
 
@@ -205,7 +142,6 @@ hevi_status hevi_build_column_ops(hevi_ctx* ctx, const hevi_shape* shape, const 
   o->shape = *shape;
   o->consts = *k;
   o->sh = dev_shape(*shape);
-  gll_tables(shape->order_N, &o->tab, nullptr);
   o->d_ops = nullptr;
   o->d_info = nullptr;
   if ((s = dev_alloc(&o->d_ops, tiles_nodes(o->sh) * HEVI_NOPS * sizeof(double))) ||
@@ -214,7 +150,7 @@ hevi_status hevi_build_column_ops(hevi_ctx* ctx, const hevi_shape* shape, const 
     return s;
   }
   if (!ok(hevi_launch_info_reset(o->d_info, stream)) ||
-      !ok(hevi_launch_build_ops(o->sh, o->tab, k->R, k->cp, k->g, k->p_A, d_z, d_J, d_gz, d_rho0,
+      !ok(hevi_launch_build_ops(o->sh, k->R, k->cp, k->g, k->p_A, d_z, d_J, d_gz, d_rho0,
                                 d_Theta0, o->d_ops, o->d_info, stream))) {
     hevi_ops_free(o);
     return HEVI_E_DEVICE;
@@ -247,7 +183,7 @@ hevi_status hevi_apply_op(hevi_ctx* ctx, const hevi_ops* ops, const double* d_x,
     if (d_y == d_x || (d_xref && d_y == d_xref)) return HEVI_E_INVALID;
   }
   if (!ok(hipSetDevice(ctx->device))) return HEVI_E_DEVICE;
-  if (!ok(hevi_launch_apply(ops->sh, ops->tab, ops->d_ops, d_x, d_xref, d_y, stream)))
+  if (!ok(hevi_launch_apply(ops->sh, ops->d_ops, d_x, d_xref, d_y, stream)))
     return HEVI_E_DEVICE;
   return HEVI_OK;
 }
@@ -299,7 +235,7 @@ hevi_status hevi_refactor(hevi_ctx* ctx, hevi_factors* f, double lambda, hipStre
   if (!ok(hipSetDevice(ctx->device))) return HEVI_E_DEVICE;
   f->lambda = lambda;
   const hevi_ops* o = f->ops;
-  if (!ok(hevi_launch_factor(o->sh, o->tab, lambda, f->prec == HEVI_FP32_REFINE, o->d_ops,
+  if (!ok(hevi_launch_factor(o->sh, lambda, f->prec == HEVI_FP32_REFINE, o->d_ops,
                              f->sbuf, f->U, f->L, f->piv, f->d_info, stream)))
     return HEVI_E_DEVICE;
   return HEVI_OK;
@@ -353,7 +289,7 @@ hevi_status hevi_stage_solve(hevi_ctx* ctx, const hevi_factors* f, int32_t n_e,
   if (f->prec == HEVI_FP64) sweeps = 0;
   if (!ok(hipSetDevice(ctx->device))) return HEVI_E_DEVICE;
   if (h_info && !ok(hevi_launch_info_reset(f->d_info, stream))) return HEVI_E_DEVICE;
-  if (!ok(hevi_launch_stage_solve(o->sh, o->tab, f->lambda, f->prec == HEVI_FP32_REFINE, o->d_ops,
+  if (!ok(hevi_launch_stage_solve(o->sh, f->lambda, f->prec == HEVI_FP32_REFINE, o->d_ops,
                                   f->U, f->L, f->piv, f->ws, E, Q, d_Qi, sweeps, target, full,
                                   f->d_info, stream)))
     return HEVI_E_DEVICE;

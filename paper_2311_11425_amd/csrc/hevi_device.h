@@ -39,6 +39,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include "hevi_gll.h"
 #include "hevi_internal.h"
 
 namespace {
@@ -80,7 +81,7 @@ struct OpsView {
 // v_rho = Drho u and v_Th = DTh u for all nodes; u read from scratch field
 // fu, results written to fields fr, ft.
 template <int N>
-__device__ void div_pass(const HeviTab& tab, const OpsView& op, int Ne, double* ws, int64_t tile,
+__device__ void div_pass(Gll<N> tab, const OpsView& op, int Ne, double* ws, int64_t tile,
                          int lane, int fu, int fr, int ft) {
   const int nz = op.nz;
   double cr = 0.0, ct = 0.0;
@@ -118,7 +119,7 @@ __device__ void div_pass(const HeviTab& tab, const OpsView& op, int Ne, double* 
 // MODE 1: final stage update Q_i = stored + lambda v (rho, Theta) and
 //         Q_U = stored + lambda^2 G (interior nodes) in the caller's Qi.
 template <int N, int MODE>
-__device__ void pg_pass(const HeviTab& tab, const OpsView& op, int Ne, double* ws, int64_t tile,
+__device__ void pg_pass(Gll<N> tab, const OpsView& op, int Ne, double* ws, int64_t tile,
                         int lane, int fr, int ft, int fo, double lambda, double* Qi,
                         int64_t ncols, int64_t c, bool valid, bool* nonfinite) {
   const int nz = op.nz;
@@ -210,7 +211,7 @@ __device__ __forceinline__ Chunk chunk_of(int Ne, int64_t tile) {
 // unconditionally (clamped indices), computes, then stores the owned nodes, so
 // the loads of an element are in flight together.
 template <int N, bool HAS_REF>
-__device__ __forceinline__ void b_apply(int64_t tile_, HeviShapeDev sh, const HeviTab& tab,
+__device__ __forceinline__ void b_apply(int64_t tile_, HeviShapeDev sh, Gll<N> tab,
                                         const double* __restrict__ ops,
                                         const double* __restrict__ x,
                                         const double* __restrict__ xref, double* __restrict__ y) {
@@ -298,27 +299,13 @@ __device__ __forceinline__ void b_apply(int64_t tile_, HeviShapeDev sh, const He
 // j+1..j+2N; pivot offset p in 0..2N (row j was swapped with row j+p).
 // sbuf holds, during assembly, row r of -lambda^2 K at band offset c - r + 2N.
 
-template <int N>
-__device__ __forceinline__ double s_entry(const double* sbuf, int64_t tile, int nz, int lane, int r,
-                                          int cabs) {
-  // entry (r, cabs) of S with identity rows at the rigid-lid nodes and zero
-  // columns for their (identically zero) unknowns
-  constexpr int B = 2 * N, W = 4 * N + 1;
-  if (r < 0 || r >= nz || cabs < 0 || cabs >= nz) return 0.0;
-  if (r == 0 || r == nz - 1) return cabs == r ? 1.0 : 0.0;
-  if (cabs == 0 || cabs == nz - 1) return 0.0;
-  const int off = cabs - r + B;
-  if (off < 0 || off >= W) return 0.0;
-  return sbuf[tix(tile, nz, r, W, off, lane)] + (cabs == r ? 1.0 : 0.0);
-}
-
 // Assembly of -lambda^2 K (element-chunked, see Chunk): row r of the band is
 // written once, by the wavefront owning node r.
 constexpr int CWF = 1;  // chunk wavefronts of the assembly kernel
 
 template <int N>
 __device__ __forceinline__ void b_factor_assemble(int64_t tile_, HeviShapeDev sh,
-                                                  const HeviTab& tab, double lambda,
+                                                  Gll<N> tab, double lambda,
                                                   const double* __restrict__ ops,
                                                   double* __restrict__ sbuf) {
   constexpr int B = 2 * N;          // half-bandwidth of S (kl = ku)
@@ -431,54 +418,65 @@ __device__ __forceinline__ void b_factor_lu(int64_t tile_, HeviShapeDev sh, cons
   const int64_t c = tile * T + lane;
   const bool valid = c < sh.ncols;
   const int nz = sh.nz;
+  // active window: Wn[t][s] = entry (j + t, j + s) of the partly eliminated S.
+  // It starts empty at j = -(2N+1); the first 2N+1 steps only shift rows
+  // 0..2N in through the prefetch ring (the loads of a row are in flight
+  // together), the elimination starts at j = 0.
   double Wn[B + 1][W];
 #pragma unroll
   for (int t = 0; t <= B; ++t)
 #pragma unroll
-    for (int s = 0; s < W; ++s) Wn[t][s] = s_entry<N>(sbuf, tile, nz, lane, t, s);
+    for (int s = 0; s < W; ++s) Wn[t][s] = 0.0;
   double ring[PFL][W];
 #pragma unroll
   for (int d = 0; d < PFL; ++d) {
-    const int r = min(B + 1 + d, nz - 1);
+    const int r = min(d, nz - 1);
 #pragma unroll
     for (int s = 0; s < W; ++s) ring[d][s] = sbuf[tix(tile, nz, r, W, s, lane)];
   }
   bool singular = false;
-  for (int j0 = 0; j0 < nz; j0 += PFL) {
+  for (int j0 = -(B + 1); j0 < nz; j0 += PFL) {
 #pragma unroll
     for (int d = 0; d < PFL; ++d) {
       const int j = j0 + d;
       if (j < nz) {
-        int p = 0;
-        double best = fabs(Wn[0][0]);
+        if (j >= 0) {  // elimination step j (rows 0..2N are only shifted in)
+          int p = 0;
+          double best = fabs(Wn[0][0]);
 #pragma unroll
-        for (int t = 1; t <= B; ++t) {
-          const double v = fabs(Wn[t][0]);
-          if (j + t < nz && v > best) { best = v; p = t; }
-        }
-        if (!(best > 0.0)) { singular = true; Wn[0][0] = 1.0; p = 0; }
+          for (int t = 1; t <= B; ++t) {
+            const double v = fabs(Wn[t][0]);
+            if (j + t < nz && v > best) { best = v; p = t; }
+          }
+          if (!(best > 0.0)) { singular = true; Wn[0][0] = 1.0; p = 0; }
+          // Most rows need no exchange in any column of the tile: skip the
+          // selects then (a wave-uniform branch); otherwise each lane selects
+          // its own pivot row.
+          if (__ballot(p != 0) != 0) {
 #pragma unroll
-        for (int s = 0; s < W; ++s) {
-          const double v0 = Wn[0][s];
-          double vp = v0;
+            for (int s = 0; s < W; ++s) {
+              const double v0 = Wn[0][s];
+              double vp = v0;
 #pragma unroll
-          for (int t = 1; t <= B; ++t) vp = (p == t) ? Wn[t][s] : vp;
-          Wn[0][s] = vp;
+              for (int t = 1; t <= B; ++t) vp = (p == t) ? Wn[t][s] : vp;
+              Wn[0][s] = vp;
 #pragma unroll
-          for (int t = 1; t <= B; ++t) Wn[t][s] = (p == t) ? v0 : Wn[t][s];
-        }
-        piv[tix(tile, nz, j, 1, 0, lane)] = (uint8_t)p;
-        FT* urow = Ub + tix(tile, nz, j, W, 0, lane);
+              for (int t = 1; t <= B; ++t) Wn[t][s] = (p == t) ? v0 : Wn[t][s];
+            }
+          }
+          piv[tix(tile, nz, j, 1, 0, lane)] = (uint8_t)p;
+          FT* urow = Ub + tix(tile, nz, j, W, 0, lane);
 #pragma unroll
-        for (int s = 0; s < W; ++s) urow[s * T] = (FT)Wn[0][s];
-        const double inv = 1.0 / Wn[0][0];
-        FT* lrow = Lb + tix(tile, nz, j, B, 0, lane);
+          for (int s = 0; s < W; ++s) urow[s * T] = (FT)Wn[0][s];
+          const double inv = 1.0 / Wn[0][0];
+          FT* lrow = Lb + tix(tile, nz, j, B, 0, lane);
 #pragma unroll
-        for (int t = 1; t <= B; ++t) {
-          const double l = Wn[t][0] * inv;
-          lrow[(t - 1) * T] = (FT)l;
+          for (int t = 1; t <= B; ++t) {
+            const double l = Wn[t][0] * inv;
+            lrow[(t - 1) * T] = (FT)l;
 #pragma unroll
-          for (int s = 1; s < W; ++s) Wn[t][s] -= l * Wn[0][s];
+            for (int s = 1; s < W; ++s) Wn[t][s] -= l * Wn[0][s];
+          }
         }
 #pragma unroll
         for (int t = 0; t < B; ++t) {
@@ -610,7 +608,7 @@ __device__ __forceinline__ void band_solve(const FT* __restrict__ Ub, const FT* 
 // early: ||u_err|| can exceed ||d|| / ||r|| by the condition number of S), or
 // max_sweeps.  Per column; the wavefront sweeps while any column needs one.
 template <int N, typename FT>
-__device__ void reduced_refine(const HeviTab& tab, const OpsView& op, int Ne, double* ws,
+__device__ void reduced_refine(Gll<N> tab, const OpsView& op, int Ne, double* ws,
                                int64_t tile, int lane, bool valid, double lambda,
                                const FT* __restrict__ Ub, const FT* __restrict__ Lb,
                                const uint8_t* __restrict__ piv, int max_sweeps, double rel_target,
@@ -654,7 +652,7 @@ __device__ void reduced_refine(const HeviTab& tab, const OpsView& op, int Ne, do
 // Reduced right-hand side r = grad(zeta).(b_U + lambda (PG b_Theta - Phi' grad(zeta) b_rho))
 // of a 5-field vector b stored in scratch fields fb..fb+4 (zero at the lid nodes).
 template <int N>
-__device__ double reduced_rhs_pass(const HeviTab& tab, const OpsView& op, int Ne, double* ws,
+__device__ double reduced_rhs_pass(Gll<N> tab, const OpsView& op, int Ne, double* ws,
                                    int64_t tile, int lane, double lambda, int fb) {
   const int nz = op.nz;
   double c0 = 0.0, c1 = 0.0, c2 = 0.0, rn2 = 0.0;
@@ -703,7 +701,7 @@ __device__ double reduced_rhs_pass(const HeviTab& tab, const OpsView& op, int Ne
 // (interior), d_U = P(b_U) at the lid (P removes the normal component).
 // Writes d into fields fx.. or adds it to them (accumulate).
 template <int N>
-__device__ void recover_pass(const HeviTab& tab, const OpsView& op, int Ne, double* ws,
+__device__ void recover_pass(Gll<N> tab, const OpsView& op, int Ne, double* ws,
                              int64_t tile, int lane, double lambda, int fb, int fx,
                              bool accumulate) {
   const int nz = op.nz;
@@ -762,7 +760,7 @@ __device__ void recover_pass(const HeviTab& tab, const OpsView& op, int Ne, doub
 // vectors b (fields fb..) and x (fields fx..); rigid-lid momentum rows of A are
 // identity rows, so there s_U = P(b_U) - x_U.  Writes fields fs..
 template <int N>
-__device__ void residual_pass(const HeviTab& tab, const OpsView& op, int Ne, double* ws,
+__device__ void residual_pass(Gll<N> tab, const OpsView& op, int Ne, double* ws,
                               int64_t tile, int lane, double lambda, int fb, int fx, int fs) {
   const int nz = op.nz;
   auto W = [&](int k, int f) -> double& { return ws[tix(tile, nz, k, HEVI_NWS, f, lane)]; };
@@ -817,7 +815,7 @@ __device__ void residual_pass(const HeviTab& tab, const OpsView& op, int Ne, dou
 }
 
 template <int N, typename FT, bool FULL>
-__device__ __forceinline__ void b_stage_solve(int64_t tile_, HeviShapeDev sh, const HeviTab& tab,
+__device__ __forceinline__ void b_stage_solve(int64_t tile_, HeviShapeDev sh, Gll<N> tab,
                                               double lambda, const double* __restrict__ ops,
                                               const FT* __restrict__ Ub, const FT* __restrict__ Lb,
                                               const uint8_t* __restrict__ piv,
@@ -986,7 +984,7 @@ __device__ __forceinline__ void b_stage_solve(int64_t tile_, HeviShapeDev sh, co
 // r = grad(zeta).(q^_U + lambda (PG q^_Theta - Phi' grad(zeta) q^_rho)) (0 at the lid).
 // The term loop is outermost so that each term issues (N+1)*5 independent loads.
 template <int N>
-__device__ __forceinline__ void b_stage_rhs(int64_t tile_, HeviShapeDev sh, const HeviTab& tab,
+__device__ __forceinline__ void b_stage_rhs(int64_t tile_, HeviShapeDev sh, Gll<N> tab,
                                             double lambda, const double* __restrict__ ops,
                                             double* __restrict__ ws, const HeviTerms& E,
                                             const HeviTerms& Q, double* __restrict__ Qi) {
@@ -1089,7 +1087,7 @@ __device__ __forceinline__ void b_stage_rhs(int64_t tile_, HeviShapeDev sh, cons
 
 // pass 2: S u = r, one lane per column (+ reduced FP64 refinement for FP32 factors)
 template <int N, typename FT, bool REFINE>
-__device__ __forceinline__ void b_stage_bsolve(int64_t tile_, HeviShapeDev sh, const HeviTab& tab,
+__device__ __forceinline__ void b_stage_bsolve(int64_t tile_, HeviShapeDev sh, Gll<N> tab,
                                                double lambda, const double* __restrict__ ops,
                                                const FT* __restrict__ Ub, const FT* __restrict__ Lb,
                                                const uint8_t* __restrict__ piv,
@@ -1122,7 +1120,7 @@ __device__ __forceinline__ void b_stage_bsolve(int64_t tile_, HeviShapeDev sh, c
 // An element needs u on its neighbours too (the DSS of Drho u, DTh u at its end
 // nodes), so each iteration loads u and the operator on nodes (e-1)N .. (e+2)N.
 template <int N>
-__device__ __forceinline__ void b_stage_update(int64_t tile_, HeviShapeDev sh, const HeviTab& tab,
+__device__ __forceinline__ void b_stage_update(int64_t tile_, HeviShapeDev sh, Gll<N> tab,
                                                double lambda, const double* __restrict__ ops,
                                                double* __restrict__ ws, double* __restrict__ Qi,
                                                HeviDevInfo* info) {

@@ -77,7 +77,8 @@ __global__ __launch_bounds__(64) void km_apply(const HeviProbDev* __restrict__ p
     const HeviProbDev& P = probs[p];
     const HeviCallDev& C = calls[p];
     switch_N<NLO, NHI>(P.sh.N, [&](auto n) {
-      b_apply<decltype(n)::value, true>(tile, P.sh, P.tab, P.ops, C.x, C.xref, C.out);
+      constexpr int NN = decltype(n)::value;
+      b_apply<NN, true>(tile, P.sh, Gll<NN>{}, P.ops, C.x, C.xref, C.out);
     });
   });
 }
@@ -88,7 +89,8 @@ __global__ __launch_bounds__(64) void km_factor_assemble(const HeviProbDev* __re
   persist(s, [&](int p, int64_t tile) {
     const HeviProbDev& P = probs[p];
     switch_N<NLO, NHI>(P.sh.N, [&](auto n) {
-      b_factor_assemble<decltype(n)::value>(tile, P.sh, P.tab, P.lambda, P.ops, P.sbuf);
+      constexpr int NN = decltype(n)::value;
+      b_factor_assemble<NN>(tile, P.sh, Gll<NN>{}, P.lambda, P.ops, P.sbuf);
     });
   });
 }
@@ -99,7 +101,8 @@ __global__ __launch_bounds__(64) void km_factor_lu(const HeviProbDev* __restrict
   persist(s, [&](int p, int64_t tile) {
     const HeviProbDev& P = probs[p];
     switch_N<NLO, NHI>(P.sh.N, [&](auto n) {
-      b_factor_lu<decltype(n)::value, FT>(tile, P.sh, P.sbuf, (FT*)P.U, (FT*)P.L, P.piv, P.info);
+      constexpr int NN = decltype(n)::value;
+      b_factor_lu<NN, FT>(tile, P.sh, P.sbuf, (FT*)P.U, (FT*)P.L, P.piv, P.info);
     });
   });
 }
@@ -112,7 +115,8 @@ __global__ __launch_bounds__(64) void km_stage_rhs(const HeviProbDev* __restrict
     const HeviProbDev& P = probs[p];
     const HeviCallDev& C = calls[p];
     switch_N<NLO, NHI>(P.sh.N, [&](auto n) {
-      b_stage_rhs<decltype(n)::value>(tile, P.sh, P.tab, P.lambda, P.ops, P.ws, C.E, C.Q, C.out);
+      constexpr int NN = decltype(n)::value;
+      b_stage_rhs<NN>(tile, P.sh, Gll<NN>{}, P.lambda, P.ops, P.ws, C.E, C.Q, C.out);
     });
   });
 }
@@ -124,9 +128,10 @@ __global__ __launch_bounds__(64) void km_stage_bsolve(const HeviProbDev* __restr
   persist(s, [&](int p, int64_t tile) {
     const HeviProbDev& P = probs[p];
     switch_N<NLO, NHI>(P.sh.N, [&](auto n) {
-      b_stage_bsolve<decltype(n)::value, FT, REFINE>(tile, P.sh, P.tab, P.lambda, P.ops,
-                                                     (const FT*)P.U, (const FT*)P.L, P.piv, P.ws,
-                                                     max_sweeps, rel_target, P.info);
+      constexpr int NN = decltype(n)::value;
+      b_stage_bsolve<NN, FT, REFINE>(tile, P.sh, Gll<NN>{}, P.lambda, P.ops, (const FT*)P.U,
+                                     (const FT*)P.L, P.piv, P.ws, max_sweeps, rel_target,
+                                     P.info);
     });
   });
 }
@@ -139,7 +144,8 @@ __global__ __launch_bounds__(64) void km_stage_update(const HeviProbDev* __restr
     const HeviProbDev& P = probs[p];
     const HeviCallDev& C = calls[p];
     switch_N<NLO, NHI>(P.sh.N, [&](auto n) {
-      b_stage_update<decltype(n)::value>(tile, P.sh, P.tab, P.lambda, P.ops, P.ws, C.out, P.info);
+      constexpr int NN = decltype(n)::value;
+      b_stage_update<NN>(tile, P.sh, Gll<NN>{}, P.lambda, P.ops, P.ws, C.out, P.info);
     });
   });
 }

@@ -134,14 +134,14 @@ hipError_t phase(hevi_group* g, int ph, int slot, hipStream_t st) {
       const HeviCallDev* C = slot >= 0 ? &g->calls[(size_t)slot * g->n + p] : nullptr;
       switch (ph) {
         case HEVI_PH_APPLY:
-          e = hevi_launch_apply(P.sh, P.tab, P.ops, C->x, C->xref, C->out, st);
+          e = hevi_launch_apply(P.sh, P.ops, C->x, C->xref, C->out, st);
           break;
         case HEVI_PH_FACTOR_ASSEMBLE:
-          e = hevi_launch_factor(P.sh, P.tab, P.lambda, fp32, P.ops, P.sbuf, P.U, P.L, P.piv,
+          e = hevi_launch_factor(P.sh, P.lambda, fp32, P.ops, P.sbuf, P.U, P.L, P.piv,
                                  P.info, st);
           break;
         case HEVI_PH_STAGE_RHS:
-          e = hevi_launch_stage_solve(P.sh, P.tab, P.lambda, fp32, P.ops, P.U, P.L, P.piv, P.ws,
+          e = hevi_launch_stage_solve(P.sh, P.lambda, fp32, P.ops, P.U, P.L, P.piv, P.ws,
                                       C->E, C->Q, C->out, fp32 ? g->sweeps : 0, g->target, 0,
                                       P.info, st);
           break;
@@ -269,7 +269,6 @@ hevi_status hevi_group_create(hevi_ctx* ctx, int32_t n, const hevi_group_member*
     const hevi_factors* f = g->fac[p];
     HeviProbDev& P = g->probs[p];
     std::memset(&P, 0, sizeof(P));
-    P.tab = o->tab;
     P.sh = o->sh;
     P.fp32 = prec == HEVI_FP32_REFINE;
     P.lambda = g->lambda;

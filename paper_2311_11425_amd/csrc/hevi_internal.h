@@ -15,12 +15,6 @@
 // compact per-node operator fields (tile-interleaved, see hevi_kernels.hip)
 enum { OP_MINV = 0, OP_J = 1, OP_JTH = 2, OP_JCT = 3, OP_GX = 4, OP_GY = 5, OP_GZ = 6, OP_PHI = 7 };
 
-// 1D GLL weights and differentiation matrix D[i*(N+1)+j] = h_j'(xi_i)
-struct HeviTab {
-  double w[HEVI_MAXN + 1];
-  double D[(HEVI_MAXN + 1) * (HEVI_MAXN + 1)];
-};
-
 // kernel-side report of a call, reduced with device atomics
 struct HeviDevInfo {
   int32_t status;          // worst status code seen
@@ -41,21 +35,21 @@ struct HeviShapeDev {
   int64_t ncols, ntiles;
 };
 
-hipError_t hevi_launch_build_ops(const HeviShapeDev& sh, const HeviTab& tab, double R, double cp,
+hipError_t hevi_launch_build_ops(const HeviShapeDev& sh, double R, double cp,
                                  double g, double pA, const double* z, const double* J,
                                  const double* gz, const double* rho0, const double* Th0,
                                  double* ops, HeviDevInfo* info, hipStream_t st);
 
-hipError_t hevi_launch_apply(const HeviShapeDev& sh, const HeviTab& tab, const double* ops,
+hipError_t hevi_launch_apply(const HeviShapeDev& sh, const double* ops,
                              const double* x, const double* xref, double* y, hipStream_t st);
 
 // fp32 != 0 selects FP32 factor storage.  sbuf: FP64 assembly buffer of
 // (4N+1) entries per node (may alias Ub when FP64).
-hipError_t hevi_launch_factor(const HeviShapeDev& sh, const HeviTab& tab, double lambda, int fp32,
+hipError_t hevi_launch_factor(const HeviShapeDev& sh, double lambda, int fp32,
                               const double* ops, double* sbuf, void* Ub, void* Lb, uint8_t* piv,
                               HeviDevInfo* info, hipStream_t st);
 
-hipError_t hevi_launch_stage_solve(const HeviShapeDev& sh, const HeviTab& tab, double lambda,
+hipError_t hevi_launch_stage_solve(const HeviShapeDev& sh, double lambda,
                                    int fp32, const double* ops, const void* Ub, const void* Lb,
                                    const uint8_t* piv, double* ws, const HeviTerms& E,
                                    const HeviTerms& Q, double* Qi, int max_sweeps,
@@ -71,9 +65,8 @@ hipError_t hevi_launch_info_reset(HeviDevInfo* info, hipStream_t st);
 // problems (column batches of possibly different order N, element count and
 // column count); its work items are the 64-column tiles of all of them.
 
-// one problem: shape, tables, operator and factor storage (device-resident table)
+// one problem: shape, operator and factor storage (device-resident table)
 struct HeviProbDev {
-  HeviTab tab;
   HeviShapeDev sh;
   int32_t fp32;           // factors stored in FP32
   double lambda;

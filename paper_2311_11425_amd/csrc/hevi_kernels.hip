@@ -8,14 +8,14 @@ namespace {
 // ---------------------------------------------------------------------------
 // a1: compact per-node operator
 template <int N>
-__global__ __launch_bounds__(64) void k_build_ops(HeviShapeDev sh, HeviTab tab, double R, double cp,
-                                                  double g, double pA,
-                                                  const double* __restrict__ z,
+__global__ __launch_bounds__(64) void k_build_ops(HeviShapeDev sh, double R, double cp, double g,
+                                                  double pA, const double* __restrict__ z,
                                                   const double* __restrict__ J,
                                                   const double* __restrict__ gzeta,
                                                   const double* __restrict__ rho0,
                                                   const double* __restrict__ Th0,
                                                   double* __restrict__ ops, HeviDevInfo* info) {
+  const Gll<N> tab{};
   const int lane = threadIdx.x;
   const int64_t tile = blockIdx.x;
   const int64_t c = tile * T + lane;
@@ -77,20 +77,18 @@ __global__ __launch_bounds__(64) void k_build_ops(HeviShapeDev sh, HeviTab tab, 
 // Single-problem kernels: tile = blockIdx.x
 
 template <int N, bool HAS_REF>
-__global__ __launch_bounds__(64) void k_apply(HeviShapeDev sh, HeviTab tab,
-                                               const double* __restrict__ ops,
-                                               const double* __restrict__ x,
-                                               const double* __restrict__ xref,
-                                               double* __restrict__ y) {
-  b_apply<N, HAS_REF>((int64_t)blockIdx.x, sh, tab, ops, x, xref, y);
+__global__ __launch_bounds__(64, 2) void k_apply(HeviShapeDev sh, const double* __restrict__ ops,
+                                              const double* __restrict__ x,
+                                              const double* __restrict__ xref,
+                                              double* __restrict__ y) {
+  b_apply<N, HAS_REF>((int64_t)blockIdx.x, sh, Gll<N>{}, ops, x, xref, y);
 }
 
 template <int N>
-__global__ __launch_bounds__(64) void k_factor_assemble(HeviShapeDev sh, HeviTab tab,
-                                                         double lambda,
-                                                         const double* __restrict__ ops,
-                                                         double* __restrict__ sbuf) {
-  b_factor_assemble<N>((int64_t)blockIdx.x, sh, tab, lambda, ops, sbuf);
+__global__ __launch_bounds__(64) void k_factor_assemble(HeviShapeDev sh, double lambda,
+                                                        const double* __restrict__ ops,
+                                                        double* __restrict__ sbuf) {
+  b_factor_assemble<N>((int64_t)blockIdx.x, sh, Gll<N>{}, lambda, ops, sbuf);
 }
 
 template <int N, typename FT>
@@ -102,7 +100,7 @@ __global__ __launch_bounds__(64) void k_factor_lu(HeviShapeDev sh, const double*
 }
 
 template <int N, typename FT, bool FULL>
-__global__ __launch_bounds__(64) void k_stage_solve(HeviShapeDev sh, HeviTab tab, double lambda,
+__global__ __launch_bounds__(64) void k_stage_solve(HeviShapeDev sh, double lambda,
                                                     const double* __restrict__ ops,
                                                     const FT* __restrict__ Ub,
                                                     const FT* __restrict__ Lb,
@@ -112,37 +110,35 @@ __global__ __launch_bounds__(64) void k_stage_solve(HeviShapeDev sh, HeviTab tab
                                                     int max_sweeps, double rel_target,
                                                     int full_sweeps, HeviDevInfo* info) {
   b_stage_solve<N, FT, FULL>((int64_t)blockIdx.x,
-      sh, tab, lambda, ops, Ub, Lb, piv, ws, E, Q, Qi, max_sweeps, rel_target, full_sweeps, info);
+      sh, Gll<N>{}, lambda, ops, Ub, Lb, piv, ws, E, Q, Qi, max_sweeps, rel_target, full_sweeps, info);
 }
 
 template <int N>
-__global__ __launch_bounds__(64, 2) void k_stage_rhs(HeviShapeDev sh, HeviTab tab, double lambda,
-                                                   const double* __restrict__ ops,
-                                                   double* __restrict__ ws, HeviTerms E,
-                                                   HeviTerms Q, double* __restrict__ Qi) {
-  b_stage_rhs<N>((int64_t)blockIdx.x, sh, tab, lambda, ops, ws, E, Q, Qi);
+__global__ __launch_bounds__(64, 2) void k_stage_rhs(HeviShapeDev sh, double lambda,
+                                                     const double* __restrict__ ops,
+                                                     double* __restrict__ ws, HeviTerms E,
+                                                     HeviTerms Q, double* __restrict__ Qi) {
+  b_stage_rhs<N>((int64_t)blockIdx.x, sh, Gll<N>{}, lambda, ops, ws, E, Q, Qi);
 }
 
 template <int N, typename FT, bool REFINE>
-__global__ __launch_bounds__(64, 2) void k_stage_bsolve(HeviShapeDev sh, HeviTab tab, double lambda,
-                                                     const double* __restrict__ ops,
-                                                     const FT* __restrict__ Ub,
-                                                     const FT* __restrict__ Lb,
-                                                     const uint8_t* __restrict__ piv,
-                                                     double* __restrict__ ws, int max_sweeps,
-                                                     double rel_target, HeviDevInfo* info) {
+__global__ __launch_bounds__(64, 2) void k_stage_bsolve(HeviShapeDev sh, double lambda,
+                                                        const double* __restrict__ ops,
+                                                        const FT* __restrict__ Ub,
+                                                        const FT* __restrict__ Lb,
+                                                        const uint8_t* __restrict__ piv,
+                                                        double* __restrict__ ws, int max_sweeps,
+                                                        double rel_target, HeviDevInfo* info) {
   b_stage_bsolve<N, FT, REFINE>((int64_t)blockIdx.x,
-      sh, tab, lambda, ops, Ub, Lb, piv, ws, max_sweeps, rel_target, info);
+      sh, Gll<N>{}, lambda, ops, Ub, Lb, piv, ws, max_sweeps, rel_target, info);
 }
 
 template <int N>
-__global__ __launch_bounds__(64) void k_stage_update(HeviShapeDev sh, HeviTab tab,
-                                                      double lambda,
-                                                      const double* __restrict__ ops,
-                                                      double* __restrict__ ws,
-                                                      double* __restrict__ Qi,
-                                                      HeviDevInfo* info) {
-  b_stage_update<N>((int64_t)blockIdx.x, sh, tab, lambda, ops, ws, Qi, info);
+__global__ __launch_bounds__(64, 2) void k_stage_update(HeviShapeDev sh, double lambda,
+                                                     const double* __restrict__ ops,
+                                                     double* __restrict__ ws,
+                                                     double* __restrict__ Qi, HeviDevInfo* info) {
+  b_stage_update<N>((int64_t)blockIdx.x, sh, Gll<N>{}, lambda, ops, ws, Qi, info);
 }
 
 // ---------------------------------------------------------------------------
@@ -182,11 +178,11 @@ hipError_t dispatch_N(int N, A&&... a) {
 
 template <int N>
 struct BuildOps {
-  static hipError_t run(const HeviShapeDev& sh, const HeviTab& tab, double R, double cp, double g,
+  static hipError_t run(const HeviShapeDev& sh, double R, double cp, double g,
                         double pA, const double* z, const double* J, const double* gz,
                         const double* rho0, const double* Th0, double* ops, HeviDevInfo* info,
                         hipStream_t st) {
-    hipLaunchKernelGGL(k_build_ops<N>, dim3((unsigned)sh.ntiles), dim3(T), 0, st, sh, tab, R, cp,
+    hipLaunchKernelGGL(k_build_ops<N>, dim3((unsigned)sh.ntiles), dim3(T), 0, st, sh, R, cp,
                        g, pA, z, J, gz, rho0, Th0, ops, info);
     return hipGetLastError();
   }
@@ -194,25 +190,23 @@ struct BuildOps {
 
 template <int N>
 struct Apply {
-  static hipError_t run(const HeviShapeDev& sh, const HeviTab& tab, const double* ops,
+  static hipError_t run(const HeviShapeDev& sh, const double* ops,
                         const double* x, const double* xref, double* y, hipStream_t st) {
     if (xref)
-      hipLaunchKernelGGL((k_apply<N, true>), dim3((unsigned)sh.ntiles), dim3(T * CW), 0, st, sh,
-                         tab, ops, x, xref, y);
+      hipLaunchKernelGGL((k_apply<N, true>), dim3((unsigned)sh.ntiles), dim3(T * CW), 0, st, sh, ops, x, xref, y);
     else
-      hipLaunchKernelGGL((k_apply<N, false>), dim3((unsigned)sh.ntiles), dim3(T * CW), 0, st, sh,
-                         tab, ops, x, xref, y);
+      hipLaunchKernelGGL((k_apply<N, false>), dim3((unsigned)sh.ntiles), dim3(T * CW), 0, st, sh, ops, x, xref, y);
     return hipGetLastError();
   }
 };
 
 template <int N>
 struct Factor {
-  static hipError_t run(const HeviShapeDev& sh, const HeviTab& tab, double lambda, int fp32,
+  static hipError_t run(const HeviShapeDev& sh, double lambda, int fp32,
                         const double* ops, double* sbuf, void* Ub, void* Lb, uint8_t* piv,
                         HeviDevInfo* info, hipStream_t st) {
     const dim3 g((unsigned)sh.ntiles);
-    hipLaunchKernelGGL(k_factor_assemble<N>, g, dim3(T * CWF), 0, st, sh, tab, lambda, ops, sbuf);
+    hipLaunchKernelGGL(k_factor_assemble<N>, g, dim3(T * CWF), 0, st, sh, lambda, ops, sbuf);
     if (fp32)
       hipLaunchKernelGGL((k_factor_lu<N, float>), g, dim3(T), 0, st, sh, sbuf, (float*)Ub,
                          (float*)Lb, piv, info);
@@ -225,7 +219,7 @@ struct Factor {
 
 template <int N>
 struct StageSolve {
-  static hipError_t run(const HeviShapeDev& sh, const HeviTab& tab, double lambda, int fp32,
+  static hipError_t run(const HeviShapeDev& sh, double lambda, int fp32,
                         const double* ops, const void* Ub, const void* Lb, const uint8_t* piv,
                         double* ws, const HeviTerms& E, const HeviTerms& Q, double* Qi,
                         int max_sweeps, double rel_target, int full_sweeps, HeviDevInfo* info,
@@ -234,58 +228,58 @@ struct StageSolve {
     if (full_sweeps > 0) {
       // accuracy mode: one kernel with the full-system refinement sweeps
       if (fp32)
-        hipLaunchKernelGGL((k_stage_solve<N, float, true>), g, b, 0, st, sh, tab, lambda, ops,
+        hipLaunchKernelGGL((k_stage_solve<N, float, true>), g, b, 0, st, sh, lambda, ops,
                            (const float*)Ub, (const float*)Lb, piv, ws, E, Q, Qi, max_sweeps,
                            rel_target, full_sweeps, info);
       else
-        hipLaunchKernelGGL((k_stage_solve<N, double, true>), g, b, 0, st, sh, tab, lambda, ops,
+        hipLaunchKernelGGL((k_stage_solve<N, double, true>), g, b, 0, st, sh, lambda, ops,
                            (const double*)Ub, (const double*)Lb, piv, ws, E, Q, Qi, 0, rel_target,
                            full_sweeps, info);
       return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_stage_rhs<N>, g, b4, 0, st, sh, tab, lambda, ops, ws, E, Q, Qi);
+    hipLaunchKernelGGL(k_stage_rhs<N>, g, b4, 0, st, sh, lambda, ops, ws, E, Q, Qi);
     if (fp32)
-      hipLaunchKernelGGL((k_stage_bsolve<N, float, true>), g, b, 0, st, sh, tab, lambda, ops,
+      hipLaunchKernelGGL((k_stage_bsolve<N, float, true>), g, b, 0, st, sh, lambda, ops,
                          (const float*)Ub, (const float*)Lb, piv, ws, max_sweeps, rel_target, info);
     else
-      hipLaunchKernelGGL((k_stage_bsolve<N, double, false>), g, b, 0, st, sh, tab, lambda, ops,
+      hipLaunchKernelGGL((k_stage_bsolve<N, double, false>), g, b, 0, st, sh, lambda, ops,
                          (const double*)Ub, (const double*)Lb, piv, ws, 0, rel_target, info);
-    hipLaunchKernelGGL(k_stage_update<N>, g, b4, 0, st, sh, tab, lambda, ops, ws, Qi, info);
+    hipLaunchKernelGGL(k_stage_update<N>, g, b4, 0, st, sh, lambda, ops, ws, Qi, info);
     return hipGetLastError();
   }
 };
 
 }  // namespace
 
-hipError_t hevi_launch_build_ops(const HeviShapeDev& sh, const HeviTab& tab, double R, double cp,
+hipError_t hevi_launch_build_ops(const HeviShapeDev& sh, double R, double cp,
                                  double g, double pA, const double* z, const double* J,
                                  const double* gz, const double* rho0, const double* Th0,
                                  double* ops, HeviDevInfo* info, hipStream_t st) {
   if (sh.ntiles == 0) return hipSuccess;
-  return dispatch_N<BuildOps>(sh.N, sh, tab, R, cp, g, pA, z, J, gz, rho0, Th0, ops, info, st);
+  return dispatch_N<BuildOps>(sh.N, sh, R, cp, g, pA, z, J, gz, rho0, Th0, ops, info, st);
 }
 
-hipError_t hevi_launch_apply(const HeviShapeDev& sh, const HeviTab& tab, const double* ops,
+hipError_t hevi_launch_apply(const HeviShapeDev& sh, const double* ops,
                              const double* x, const double* xref, double* y, hipStream_t st) {
   if (sh.ntiles == 0) return hipSuccess;
-  return dispatch_N<Apply>(sh.N, sh, tab, ops, x, xref, y, st);
+  return dispatch_N<Apply>(sh.N, sh, ops, x, xref, y, st);
 }
 
-hipError_t hevi_launch_factor(const HeviShapeDev& sh, const HeviTab& tab, double lambda, int fp32,
+hipError_t hevi_launch_factor(const HeviShapeDev& sh, double lambda, int fp32,
                               const double* ops, double* sbuf, void* Ub, void* Lb, uint8_t* piv,
                               HeviDevInfo* info, hipStream_t st) {
   if (sh.ntiles == 0) return hipSuccess;
-  return dispatch_N<Factor>(sh.N, sh, tab, lambda, fp32, ops, sbuf, Ub, Lb, piv, info, st);
+  return dispatch_N<Factor>(sh.N, sh, lambda, fp32, ops, sbuf, Ub, Lb, piv, info, st);
 }
 
-hipError_t hevi_launch_stage_solve(const HeviShapeDev& sh, const HeviTab& tab, double lambda,
+hipError_t hevi_launch_stage_solve(const HeviShapeDev& sh, double lambda,
                                    int fp32, const double* ops, const void* Ub, const void* Lb,
                                    const uint8_t* piv, double* ws, const HeviTerms& E,
                                    const HeviTerms& Q, double* Qi, int max_sweeps,
                                    double rel_target, int full_sweeps, HeviDevInfo* info,
                                    hipStream_t st) {
   if (sh.ntiles == 0) return hipSuccess;
-  return dispatch_N<StageSolve>(sh.N, sh, tab, lambda, fp32, ops, Ub, Lb, piv, ws, E, Q, Qi,
+  return dispatch_N<StageSolve>(sh.N, sh, lambda, fp32, ops, Ub, Lb, piv, ws, E, Q, Qi,
                                 max_sweeps, rel_target, full_sweeps, info, st);
 }
 

@@ -19,7 +19,6 @@ struct hevi_ops {
   hevi_shape shape;
   hevi_consts consts;
   HeviShapeDev sh;
-  HeviTab tab;
   double* d_ops;
   HeviDevInfo* d_info;
 };

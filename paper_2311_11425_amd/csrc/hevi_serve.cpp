@@ -352,7 +352,6 @@ hevi_status hevi_serve_register(hevi_server* S, const hevi_ops* ops, double lamb
   sim.fac = f;
   sim.bytes = bytes;
   std::memset(&sim.desc, 0, sizeof(sim.desc));
-  sim.desc.tab = ops->tab;
   sim.desc.sh = ops->sh;
   sim.desc.fp32 = prec == HEVI_FP32_REFINE;
   sim.desc.lambda = lambda;

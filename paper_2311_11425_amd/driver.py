@@ -13,6 +13,8 @@ S(q) = L_z (q - q_ref):
 """
 from __future__ import annotations
 
+import ctypes
+
 import numpy as np
 import torch
 
@@ -66,7 +68,51 @@ class ArkStepper:
         aii = self.Aimp[i][i]
         return [(self.Aimp[i][j] - self.Aexp[i][j]) / aii for j in range(i)]
 
+    def calls(self, qn, qref, out, stream=None):
+        """The C-ABI calls of one step, marshalled once: a list of (name, function,
+        arguments) for fixed buffers (cached per buffer set and stream)."""
+        key = (qn.data_ptr(), qref.data_ptr(), out.data_ptr(), stream)
+        if getattr(self, "_calls_key", None) == key:
+            return self._calls
+        lib, ctx, ops, f = self.ctx.lib, self.ctx, self.batch.ops, self.factors
+        st = hevi._stream(stream)
+        P = hevi._ptr
+        ref = hevi.Refine(*(tuple(self.refine) + (0,) * (3 - len(self.refine))))
+        keep = [ref]
+        self.Q[0] = qn
+        seq = [("refactor", lib.hevi_refactor, (ctx.handle, f.handle, ctypes.c_double(self.lam), st)),
+               ("apply_op", lib.hevi_apply_op, (ctx.handle, ops.handle, P(qn), P(qref),
+                                                P(self.S[0]), st))]
+        for i in range(1, self.s):
+            E = [qn] + self.S[:i]
+            e = [1.0] + [self.dt * self.Aexp[i][j] for j in range(i)]
+            Ep, ep = hevi._ptr_array(E), hevi._dbl_array(e)
+            Qp, cp = hevi._ptr_array(self.Q[:i]), hevi._dbl_array(self.coeffs(i))
+            keep += [Ep, ep, Qp, cp]
+            seq.append(("stage_solve", lib.hevi_stage_solve,
+                        (ctx.handle, f.handle, len(E), Ep, ep, i, Qp, cp, P(self.Q[i]),
+                         ctypes.byref(ref), None, st)))
+            seq.append(("apply_op", lib.hevi_apply_op, (ctx.handle, ops.handle, P(self.Q[i]),
+                                                        P(qref), P(self.S[i]), st)))
+        V = [qn] + self.S
+        Vp, vc = hevi._ptr_array(V), hevi._dbl_array([1.0] + [self.dt * bi for bi in self.b])
+        keep += [Vp, vc]
+        seq.append(("combine", lib.hevi_combine, (ctx.handle, ops.handle, len(V), Vp, vc, P(out),
+                                                  st)))
+        self._calls, self._calls_key, self._keep = seq, key, keep
+        return seq
+
     def step(self, qn, qref, out, refactor=True, info=False, stream=None):
+        """One ARK step.  info=True waits after every stage solve and returns its
+        report (one dict per implicit stage)."""
+        if not info:
+            for name, fn, args in self.calls(qn, qref, out, stream):
+                if name == "refactor" and not refactor:
+                    continue
+                code = fn(*args)
+                if code != 0:
+                    raise hevi.HeviError(code, name)
+            return []
         ctx, ops = self.ctx, self.batch.ops
         if refactor:
             ctx.refactor(self.factors, self.lam, stream=stream)
@@ -77,7 +123,7 @@ class ArkStepper:
             E = [qn] + self.S[:i]
             e = [1.0] + [self.dt * self.Aexp[i][j] for j in range(i)]
             inf = ctx.stage_solve(self.factors, E, e, self.Q[:i], self.coeffs(i), self.Q[i],
-                                  refine=self.refine, info=info, stream=stream)
+                                  refine=self.refine, info=True, stream=stream)
             infos.append(inf)
             ctx.apply_op(ops, self.Q[i], self.S[i], xref=qref, stream=stream)
         ctx.combine(ops, [qn] + self.S, [1.0] + [self.dt * bi for bi in self.b], out,
