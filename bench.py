@@ -30,7 +30,8 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0       # MI355X HBM3E, published
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage_solve_ne30_traffic.txt")
-KERNEL_SRC = os.path.join(ROOT, "paper_2311_11425_amd", "csrc", "hevi_kernels.hip")
+KERNEL_SRC = [os.path.join(ROOT, "paper_2311_11425_amd", "csrc", f)
+              for f in ("hevi_kernels.hip", "hevi_device.h", "hevi_gll.h")]
 
 PATHS = {  # name: (precision, refine=(max_sweeps, rel_target, full_sweeps))
     "fp64": (0, (0, 1e-13, 0)),
@@ -48,8 +49,12 @@ def pct(v, p):
 
 
 def kernel_hash():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """sha256[:16] of the single-problem kernel sources (kernels, bodies, tables)."""
+    h = hashlib.sha256()
+    for path in KERNEL_SRC:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(path):
@@ -437,6 +442,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="CPU-seconds for the oracle")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the config-1 accuracy, uneven-batch and serving legs")
+    ap.add_argument("--leg", choices=["config1", "uneven", "serve"],
+                    help="run only this extra leg (for profiling) and print its JSON")
     ap.add_argument("--uneven-scale", type=float, default=1.0)
     ap.add_argument("--serve-scale", type=float, default=1.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -452,6 +459,15 @@ def main():
     from paper_2311_11425_amd import hevi, inputs
     from paper_2311_11425_amd.driver import ColumnBatch
 
+    if args.leg:
+        ctx = hevi.Context(0)
+        leg = {"config1": lambda: cfg1_leg(ctx),
+               "uneven": lambda: uneven_leg(ctx, scale=args.uneven_scale),
+               "serve": lambda: serve_leg(ctx, scale=args.serve_scale)}[args.leg]()
+        torch.cuda.synchronize()
+        ctx.close()
+        print(json.dumps({"leg": args.leg, "result": leg}), flush=True)
+        return
     t0 = time.perf_counter()
     col = inputs.config2(ncols=args.ncols)
     qn, qref = inputs.perturbed_state(col)
