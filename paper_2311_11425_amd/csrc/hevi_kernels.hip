@@ -99,6 +99,17 @@ __global__ __launch_bounds__(64) void k_factor_lu(HeviShapeDev sh, const double*
   b_factor_lu<N, FT>((int64_t)blockIdx.x, sh, sbuf, Ub, Lb, piv, info);
 }
 
+template <int N, typename FT>
+__global__ __launch_bounds__(64) void k_factor_lu_lds(HeviShapeDev sh, const double* sbuf, FT* Ub,
+                                                      FT* __restrict__ Lb,
+                                                      uint8_t* __restrict__ piv,
+                                                      HeviDevInfo* info) {
+  __shared__ double lds[LuLdsShape<N>::LDS];
+  constexpr int P = 64 / LuLdsShape<N>::CPW;  // workgroups per tile
+  b_factor_lu_lds<N, FT>((int64_t)(blockIdx.x / P), (int)(blockIdx.x % P), sh, sbuf, Ub, Lb, piv,
+                         info, lds);
+}
+
 template <int N, typename FT, bool FULL>
 __global__ __launch_bounds__(64) void k_stage_solve(HeviShapeDev sh, double lambda,
                                                     const double* __restrict__ ops,
@@ -207,12 +218,22 @@ struct Factor {
                         HeviDevInfo* info, hipStream_t st) {
     const dim3 g((unsigned)sh.ntiles);
     hipLaunchKernelGGL(k_factor_assemble<N>, g, dim3(T * CWF), 0, st, sh, lambda, ops, sbuf);
-    if (fp32)
+    if (N >= kLuLdsMinN) {
+      // the window does not fit in registers: LDS window, 64 / CPW workgroups per tile
+      const dim3 gl((unsigned)(sh.ntiles * (64 / LuLdsShape<N>::CPW)));
+      if (fp32)
+        hipLaunchKernelGGL((k_factor_lu_lds<N, float>), gl, dim3(T), 0, st, sh, sbuf, (float*)Ub,
+                           (float*)Lb, piv, info);
+      else
+        hipLaunchKernelGGL((k_factor_lu_lds<N, double>), gl, dim3(T), 0, st, sh, sbuf,
+                           (double*)Ub, (double*)Lb, piv, info);
+    } else if (fp32) {
       hipLaunchKernelGGL((k_factor_lu<N, float>), g, dim3(T), 0, st, sh, sbuf, (float*)Ub,
                          (float*)Lb, piv, info);
-    else
+    } else {
       hipLaunchKernelGGL((k_factor_lu<N, double>), g, dim3(T), 0, st, sh, sbuf, (double*)Ub,
                          (double*)Lb, piv, info);
+    }
     return hipGetLastError();
   }
 };
