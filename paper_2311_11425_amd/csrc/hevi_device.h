@@ -39,6 +39,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "hevi_gll.h"
 #include "hevi_internal.h"
 
@@ -231,12 +233,23 @@ __device__ __forceinline__ void b_apply(int64_t tile_, HeviShapeDev sh, Gll<N> t
     else return x[i];
   };
   double cr = 0.0, ct = 0.0, c0 = 0.0, c1 = 0.0, c2 = 0.0;
-  for (int e = max(ch.e0 - 1, 0); e < ch.e1; ++e) {
+  // node eN is shared by elements e-1 and e: its loaded values are carried
+  // over instead of being loaded again (the first element loads all N+1 nodes)
+  double kg0 = 0.0, kg1 = 0.0, kg2 = 0.0, kJn = 0.0, kJt = 0.0, kJc = 0.0, kmi = 0.0, kph = 0.0;
+  double kxr = 0.0, kxu0 = 0.0, kxu1 = 0.0, kxu2 = 0.0, kxt = 0.0;
+  auto element = [&](const int e, auto first) {
+    constexpr bool FIRST = decltype(first)::value;
     // ---- loads ----
     double g0[N + 1], g1[N + 1], g2[N + 1], Jn[N + 1], Jt[N + 1], Jc[N + 1], mi[N + 1], ph[N + 1];
     double xr[N + 1], xu[N + 1][3], xt[N + 1];
 #pragma unroll
     for (int j = 0; j <= N; ++j) {
+      if (!FIRST && j == 0) {
+        g0[0] = kg0; g1[0] = kg1; g2[0] = kg2; Jn[0] = kJn; Jt[0] = kJt; Jc[0] = kJc;
+        mi[0] = kmi; ph[0] = kph;
+        xr[0] = kxr; xu[0][0] = kxu0; xu[0][1] = kxu1; xu[0][2] = kxu2; xt[0] = kxt;
+        continue;
+      }
       const int k = e * N + j;
       g0[j] = op(k, OP_GX); g1[j] = op(k, OP_GY); g2[j] = op(k, OP_GZ);
       Jn[j] = op(k, OP_J); Jt[j] = op(k, OP_JTH); Jc[j] = op(k, OP_JCT);
@@ -288,7 +301,13 @@ __device__ __forceinline__ void b_apply(int64_t tile_, HeviShapeDev sh, Gll<N> t
         }
       }
     }
-  }
+    kg0 = g0[N]; kg1 = g1[N]; kg2 = g2[N]; kJn = Jn[N]; kJt = Jt[N]; kJc = Jc[N];
+    kmi = mi[N]; kph = ph[N];
+    kxr = xr[N]; kxu0 = xu[N][0]; kxu1 = xu[N][1]; kxu2 = xu[N][2]; kxt = xt[N];
+  };
+  int e = max(ch.e0 - 1, 0);
+  element(e, std::true_type{});
+  for (++e; e < ch.e1; ++e) element(e, std::false_type{});
 }
 
 // ---------------------------------------------------------------------------
@@ -1152,37 +1171,47 @@ __device__ __forceinline__ void b_stage_rhs(int64_t tile_, HeviShapeDev sh, Gll<
   OpsView op{ops, tile, nz, lane};
   if (ch.e0 == 0) ws[tix(tile, nz, 0, HEVI_NWS, WS_T, lane)] = 0.0;  // per-column flag
   double c0 = 0.0, c1 = 0.0, c2 = 0.0;
-  for (int e = max(ch.e0 - 1, 0); e < ch.e1; ++e) {
+  // node eN is shared by elements e-1 and e: its sums and operator values are
+  // carried over instead of being loaded again (the first element loads all)
+  double kqE[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, kb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  double kg0 = 0.0, kg1 = 0.0, kg2 = 0.0, kmi = 0.0, kph = 0.0, kf0 = 0.0, kf1 = 0.0, kf2 = 0.0;
+  auto element = [&](const int e, auto first) {
+    constexpr bool FIRST = decltype(first)::value;
     double qE[N + 1][5], b[N + 1][5];
 #pragma unroll
     for (int j = 0; j <= N; ++j)
 #pragma unroll
-      for (int v = 0; v < 5; ++v) qE[j][v] = 0.0;
+      for (int v = 0; v < 5; ++v) qE[j][v] = (!FIRST && j == 0) ? kqE[v] : 0.0;
 #pragma unroll 2
     for (int t = 0; t < E.n; ++t) {
       const double* src = E.v[t];
       const double cf = E.coef[t];
 #pragma unroll
-      for (int j = 0; j <= N; ++j)
+      for (int j = FIRST ? 0 : 1; j <= N; ++j)
 #pragma unroll
         for (int v = 0; v < 5; ++v) qE[j][v] += cf * src[cix(nz, nc, v, e * N + j, cc)];
     }
 #pragma unroll
     for (int j = 0; j <= N; ++j)
 #pragma unroll
-      for (int v = 0; v < 5; ++v) b[j][v] = qE[j][v];
+      for (int v = 0; v < 5; ++v) b[j][v] = (!FIRST && j == 0) ? kb[v] : qE[j][v];
 #pragma unroll 2
     for (int t = 0; t < Q.n; ++t) {
       const double* src = Q.v[t];
       const double cf = Q.coef[t];
 #pragma unroll
-      for (int j = 0; j <= N; ++j)
+      for (int j = FIRST ? 0 : 1; j <= N; ++j)
 #pragma unroll
         for (int v = 0; v < 5; ++v) b[j][v] += cf * src[cix(nz, nc, v, e * N + j, cc)];
     }
     double g0[N + 1], g1[N + 1], g2[N + 1], mi[N + 1], ph[N + 1], f0[N + 1], f1[N + 1], f2[N + 1];
 #pragma unroll
     for (int j = 0; j <= N; ++j) {
+      if (!FIRST && j == 0) {
+        g0[0] = kg0; g1[0] = kg1; g2[0] = kg2; mi[0] = kmi; ph[0] = kph;
+        f0[0] = kf0; f1[0] = kf1; f2[0] = kf2;
+        continue;
+      }
       const int k = e * N + j;
       g0[j] = op(k, OP_GX); g1[j] = op(k, OP_GY); g2[j] = op(k, OP_GZ);
       mi[j] = op(k, OP_MINV); ph[j] = op(k, OP_PHI);
@@ -1234,7 +1263,14 @@ __device__ __forceinline__ void b_stage_rhs(int64_t tile_, HeviShapeDev sh, Gll<
         }
       }
     }
-  }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) { kqE[v] = qE[N][v]; kb[v] = b[N][v]; }
+    kg0 = g0[N]; kg1 = g1[N]; kg2 = g2[N]; kmi = mi[N]; kph = ph[N];
+    kf0 = f0[N]; kf1 = f1[N]; kf2 = f2[N];
+  };
+  int e = max(ch.e0 - 1, 0);
+  element(e, std::true_type{});
+  for (++e; e < ch.e1; ++e) element(e, std::false_type{});
 }
 
 // pass 2: S u = r, one lane per column (+ reduced FP64 refinement for FP32 factors)
