@@ -1326,11 +1326,21 @@ __device__ __forceinline__ void b_stage_update(int64_t tile_, HeviShapeDev sh, G
   const double l2 = lambda * lambda;
   bool nonfinite = false;
   double c0 = 0.0, c1 = 0.0, c2 = 0.0;
-  for (int e = max(ch.e0 - 1, 0); e < ch.e1; ++e) {
+  // consecutive elements share nodes eN .. (e+2)N of the u window and node eN of
+  // the operator and Q_i: those values are carried over instead of loaded again
+  double kJu[2 * N + 1], kJtu[2 * N + 1], kq[5];
+  double kg0 = 0.0, kg1 = 0.0, kg2 = 0.0, kmi = 0.0, kph = 0.0, kjc = 0.0;
+  auto element = [&](const int e, auto first) {
+    constexpr bool FIRST = decltype(first)::value;
     // ---- loads: u, J, J theta0 on nodes (e-1)N .. (e+2)N; operator and Q_i on the element
     double Ju[NC], Jtu[NC];
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
+      if (!FIRST && q <= 2 * N) {
+        Ju[q] = kJu[q];
+        Jtu[q] = kJtu[q];
+        continue;
+      }
       const int k = (e - 1) * N + q;
       const int kk = min(max(k, 0), nz - 1);
       const double u = ws[tix(tile, nz, kk, HEVI_NWS, WS_U, lane)];
@@ -1341,12 +1351,24 @@ __device__ __forceinline__ void b_stage_update(int64_t tile_, HeviShapeDev sh, G
     double g0[N + 1], g1[N + 1], g2[N + 1], mi[N + 1], ph[N + 1], jc[N + 1], q[N + 1][5];
 #pragma unroll
     for (int j = 0; j <= N; ++j) {
+      if (!FIRST && j == 0) {
+        g0[0] = kg0; g1[0] = kg1; g2[0] = kg2; mi[0] = kmi; ph[0] = kph; jc[0] = kjc;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) q[0][v] = kq[v];
+        continue;
+      }
       const int k = e * N + j;
       g0[j] = op(k, OP_GX); g1[j] = op(k, OP_GY); g2[j] = op(k, OP_GZ);
       mi[j] = op(k, OP_MINV); ph[j] = op(k, OP_PHI); jc[j] = op(k, OP_JCT);
 #pragma unroll
       for (int v = 0; v < 5; ++v) q[j][v] = Qi[cix(nz, nc, v, k, cc)];
     }
+    // node N as loaded (before this element's update) is node 0 of the next
+#pragma unroll
+    for (int v = 0; v < 5; ++v) kq[v] = q[N][v];
+    kg0 = g0[N]; kg1 = g1[N]; kg2 = g2[N]; kmi = mi[N]; kph = ph[N]; kjc = jc[N];
+#pragma unroll
+    for (int t = 0; t <= 2 * N; ++t) { kJu[t] = Ju[N + t]; kJtu[t] = Jtu[N + t]; }
     // ---- v_rho, v_Th at the element's nodes (contributions of elements e-1, e, e+1)
     double sr[N + 1], st[N + 1];
 #pragma unroll
@@ -1416,6 +1438,11 @@ __device__ __forceinline__ void b_stage_update(int64_t tile_, HeviShapeDev sh, G
         }
       }
     }
+  };
+  {
+    int e = max(ch.e0 - 1, 0);
+    element(e, std::true_type{});
+    for (++e; e < ch.e1; ++e) element(e, std::false_type{});
   }
   if (nonfinite) {
     // count each column once: the first wavefront to flag it wins the exchange
