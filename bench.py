@@ -96,13 +96,28 @@ def oracle_rate(col, qn, qref, budget_cpu_s=15.0):
     t = time.perf_counter()
     oracle.ark_step_batch(sc, tab, 300.0, q0, r0, refine=1, nthreads=threads)
     per_col_cpu = (time.perf_counter() - t) * threads / n0
+    # one core, on a sample of about 2 CPU-s
+    n1 = int(max(4, min(col["z"].shape[1], 2.0 / max(per_col_cpu, 1e-6))))
+    sc1, q1, r1 = sample(n1)
+    t = time.perf_counter()
+    oracle.ark_step_batch(sc1, tab, 300.0, q1, r1, refine=1, nthreads=1)
+    one_core = n1 * 3 / (time.perf_counter() - t)
     n = int(min(col["z"].shape[1], max(n0, budget_cpu_s / max(per_col_cpu, 1e-6))))
     n = max(threads, (n // threads) * threads)
     sc, q0, r0 = sample(n)
     t = time.perf_counter()
     oracle.ark_step_batch(sc, tab, 300.0, q0, r0, refine=1, nthreads=threads)
     wall = time.perf_counter() - t
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": n * 3 / wall, "unit": "column-solves/s", "cores": threads, "kind": "oracle",
+            "single_core_value": one_core, "cpu_model": model,
             "sample": f"{n} of {col['z'].shape[1]} columns (evenly spaced), one ARK3 step each: "
                       f"dense 205x205 GEPP factor, 3 stage solves with one long-double "
                       f"refinement step, 4 dense operator applications; {wall:.2f} s wall, "
@@ -183,6 +198,46 @@ def cfg1_leg(ctx, steps=200):
                    "perturbation); stage_solve_rel_err is the solve of each stage's q^ rebuilt "
                    "from the GPU's own Q_j, S_j")
     return out
+
+
+def share_leg(ctx, ncols=10800, steps=200, warmup=20):
+    """One GPU's share of the ne=30 batch on 8 GPUs (about 10,800 columns, same
+    geometry): FP64 ARK3 steps."""
+    import torch
+    from paper_2311_11425_amd import inputs
+    from paper_2311_11425_amd.driver import ArkStepper, ColumnBatch
+    col = inputs.config2(ncols=ncols)
+    qn, qref = inputs.perturbed_state(col)
+    B = ColumnBatch(ctx, col)
+    qd, qrd = torch.from_numpy(qn).cuda(), torch.from_numpy(qref).cuda()
+    st = ArkStepper(ctx, B, "ARK3", 300.0, precision=0, refine=(0, 1e-13, 0))
+    out = B.empty_state()
+    for _ in range(warmup):
+        st.step(qd, qrd, out)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        st.step(qd, qrd, out)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1e3 / steps
+    return {"columns": ncols, "ms_per_step": ms, "column_solves_per_s": 3 * ncols / (ms * 1e-3),
+            "note": "ne=30 column count split over 8 GPUs (86,402 / 8): one GPU's share, FP64"}
+
+
+def copy_ceiling(nbytes=1 << 30, reps=20):
+    """Device-to-device copy bandwidth (read + write bytes / time) of torch's copy."""
+    import torch
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    return 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
 
 
 def uneven_leg(ctx, scale=1.0, steps=5, reps=2):
@@ -442,7 +497,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="CPU-seconds for the oracle")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the config-1 accuracy, uneven-batch and serving legs")
-    ap.add_argument("--leg", choices=["config1", "uneven", "serve"],
+    ap.add_argument("--leg", choices=["config1", "share", "uneven", "serve"],
                     help="run only this extra leg (for profiling) and print its JSON")
     ap.add_argument("--uneven-scale", type=float, default=1.0)
     ap.add_argument("--serve-scale", type=float, default=1.0)
@@ -461,7 +516,7 @@ def main():
 
     if args.leg:
         ctx = hevi.Context(0)
-        leg = {"config1": lambda: cfg1_leg(ctx),
+        leg = {"config1": lambda: cfg1_leg(ctx), "share": lambda: share_leg(ctx),
                "uneven": lambda: uneven_leg(ctx, scale=args.uneven_scale),
                "serve": lambda: serve_leg(ctx, scale=args.serve_scale)}[args.leg]()
         torch.cuda.synchronize()
@@ -506,6 +561,7 @@ def main():
         res_paths[name] = d
         log(f"{name}: {ms_step:.3f} ms/step, stage solve {stage_ms:.3f} ms, factor {fac_ms:.3f} ms")
 
+    copy_gbs = copy_ceiling()
     if args.copy_calibration:
         src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
@@ -550,6 +606,7 @@ def main():
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "kernel": "hevi_stage_solve (k_stage_rhs + k_stage_bsolve + k_stage_update)",
                      "algorithmic_bytes_per_column": per_col,
+                     "measured_copy_GBps": copy_gbs,
                      "launch_columns": ncols,
                      "paper_layout_band_factor_bytes_per_column": sz["paper_band"],
                      "factor_bytes_per_column": sz["factors"]},
@@ -563,6 +620,8 @@ def main():
         torch.cuda.empty_cache()
         log("config-1 accuracy leg ...")
         res["config1_ark2_accuracy"] = cfg1_leg(ctx)
+        log("one-GPU share leg ...")
+        res["one_gpu_share_of_8"] = share_leg(ctx)
         log("uneven-batch leg ...")
         res["uneven_batch"] = uneven_leg(ctx, scale=args.uneven_scale)
         torch.cuda.empty_cache()

@@ -325,3 +325,44 @@ def test_nonfinite_rhs_reported(ctx):
     inf = ctx.stage_solve(f, [dev(b)], [1.0], [], [], x, info=True)
     assert inf["status"] == "HEVI_E_NONFINITE" and inf["first_bad_col"] == 58
     assert inf["n_bad_cols"] == 1
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_long_run_checkpoints(ctx, prec):
+    """100 ARK3 steps of a config-2 sample (200 columns) on the GPU.  At steps 1, 2, 50
+    and 100 the oracle takes one step from the GPU's own state and the GPU's stage
+    increments and update are compared with it (tolerance as in test_ark_step_parity);
+    the GPU trajectory's deviation from the reference after 100 steps is compared
+    with the oracle's own 100-step trajectory (bound: 100 x the per-step tolerance,
+    errors of a stable linear recurrence adding at most linearly)."""
+    from paper_2311_11425_amd.driver import ArkStepper, ColumnBatch
+    col = inputs.config2(ncols=200)
+    tab, dt = tableaux.as_float(tableaux.ark3()), 300.0
+    print(f"long run prec={prec}", flush=True)
+    B = ColumnBatch(ctx, col)
+    st = ArkStepper(ctx, B, "ARK3", dt, precision=prec)
+    qn, qref = inputs.perturbed_state(col)
+    q, qr = dev(qn), dev(qref)
+    bar = TOL64 if prec == 0 else TOLMIX
+    tol1 = None
+    bufs = [B.empty_state(), B.empty_state()]
+    for n in range(1, 101):
+        qh = host(q)
+        out = bufs[n % 2]
+        st.step(q, qr, out)
+        if n in (1, 2, 50, 100):
+            qo_next, Qo, _ = oracle.ark_step_batch(col, tab, dt, qh, qref, refine=1,
+                                                   want_stages=True)
+            tol = step_tolerance(oracle, col, tab, dt, qh, qref, Qo, bar)
+            tol1 = tol1 or tol
+            errs = [relerr_cols(host(st.Q[i]) - qh, Qo[i] - qh) for i in range(1, st.s)]
+            errs.append(relerr_cols(host(out) - qh, qo_next - qh))
+            print(f"step {n}: max err {max(errs):.2e} (tolerance {tol:.2e})", flush=True)
+            assert max(errs) < tol, (n, errs)
+        q = out
+    qo = qn.copy()
+    for n in range(100):
+        qo = oracle.ark_step_batch(col, tab, dt, qo, qref, refine=1)
+    dev100 = relerr_cols(host(q) - qref, qo - qref)
+    print(f"100-step trajectory deviation {dev100:.2e} (bound {100 * tol1:.2e})", flush=True)
+    assert dev100 < 100 * tol1
