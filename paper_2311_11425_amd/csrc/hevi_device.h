@@ -411,9 +411,18 @@ __device__ __forceinline__ void b_factor_assemble(int64_t tile_, HeviShapeDev sh
   }
 }
 
-// Band LU with partial pivoting of S over a (2N+1) x (4N+1) register window
-// (one lane per column).  Window row t, column s holds A(j+t, j+s) at step j;
-// the S rows entering the window are prefetched PFL rows ahead.
+// Band LU with partial pivoting of S, per column.  At step j the active window
+// holds rows j..j+2N and columns j..j+4N of the partly eliminated matrix (the
+// U rows fill in up to 4N right of the diagonal).  Step j picks the largest
+// |entry| of column j among rows j..j+2N (lowest row on ties), exchanges it
+// with row j, stores U row j, the 2N multipliers and the pivot offset, and
+// eliminates column j from the rows below; then the window moves one row down
+// and one column right and row j+2N+1 of S enters at the bottom.  The window
+// starts empty at j = -(2N+1), the first 2N+1 steps only shift rows 0..2N in
+// (their loads go through the same prefetch ring as every later row).  Two
+// implementations: a register window split over a lane pair (N <= 4,
+// b_factor_lu2) and an LDS window (N >= 5, b_factor_lu_lds); they store the
+// same factors.
 template <int N>
 __device__ __forceinline__ double s_fix(int r, int nz, int s, double raw) {
   // entry (r, r - 2N + s) of S from the stored -lambda^2 K value: identity rows
@@ -426,32 +435,42 @@ __device__ __forceinline__ double s_fix(int r, int nz, int s, double raw) {
   return raw + (s == B ? 1.0 : 0.0);
 }
 
+// exchange a value with the other lane of an even/odd lane pair (DPP quad_perm [1,0,3,2])
+__device__ __forceinline__ int pair_swap(int v) { return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false); }
+__device__ __forceinline__ double pair_swap(double v) {
+  const int lo = pair_swap(__double2loint(v)), hi = pair_swap(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
+// The same band LU with each column's window split over a lane pair: the even
+// lane holds window columns 0..2N, the odd lane columns 2N+1..4N (and one
+// always-zero pad column), 81 doubles each at N = 4 instead of 153, so the
+// window stays in VGPRs.  The pair exchanges the pivot index, the multipliers
+// and the column crossing the split with DPP moves.  A wavefront handles 32
+// columns: half `half` of a 64-column tile.
 template <int N, typename FT>
-__device__ __forceinline__ void b_factor_lu(int64_t tile_, HeviShapeDev sh, const double* sbuf,
-                                                  FT* Ub,  // may alias sbuf (FP64)
-                                                  FT* __restrict__ Lb, uint8_t* __restrict__ piv,
-                                                  HeviDevInfo* info) {
-  constexpr int B = 2 * N, W = 4 * N + 1, PFL = 2;
-  const int lane = threadIdx.x;
-  const int64_t tile = tile_;
+__device__ __forceinline__ void b_factor_lu2(int64_t tile, int half, HeviShapeDev sh,
+                                             const double* sbuf, FT* Ub, FT* __restrict__ Lb,
+                                             uint8_t* __restrict__ piv, HeviDevInfo* info) {
+  constexpr int B = 2 * N, W = 4 * N + 1, H = 2 * N + 1, PFL = 2;
+  const int h = threadIdx.x & 1;                 // window half of this lane
+  const int lane = half * 32 + (threadIdx.x >> 1);  // the column's lane in its tile
   const int64_t c = tile * T + lane;
   const bool valid = c < sh.ncols;
   const int nz = sh.nz;
-  // active window: Wn[t][s] = entry (j + t, j + s) of the partly eliminated S.
-  // It starts empty at j = -(2N+1); the first 2N+1 steps only shift rows
-  // 0..2N in through the prefetch ring (the loads of a row are in flight
-  // together), the elimination starts at j = 0.
-  double Wn[B + 1][W];
+  const int s0 = h * H;                          // first window column of this lane
+  // Wn[t][m] = entry (j + t, j + s0 + m); empty at j = -(2N+1), rows shifted in
+  double Wn[B + 1][H];
 #pragma unroll
   for (int t = 0; t <= B; ++t)
 #pragma unroll
-    for (int s = 0; s < W; ++s) Wn[t][s] = 0.0;
-  double ring[PFL][W];
+    for (int m = 0; m < H; ++m) Wn[t][m] = 0.0;
+  double ring[PFL][H];
 #pragma unroll
   for (int d = 0; d < PFL; ++d) {
     const int r = min(d, nz - 1);
 #pragma unroll
-    for (int s = 0; s < W; ++s) ring[d][s] = sbuf[tix(tile, nz, r, W, s, lane)];
+    for (int m = 0; m < H; ++m) ring[d][m] = sbuf[tix(tile, nz, r, W, min(s0 + m, W - 1), lane)];
   }
   bool singular = false;
   for (int j0 = -(B + 1); j0 < nz; j0 += PFL) {
@@ -460,6 +479,7 @@ __device__ __forceinline__ void b_factor_lu(int64_t tile_, HeviShapeDev sh, cons
       const int j = j0 + d;
       if (j < nz) {
         if (j >= 0) {  // elimination step j (rows 0..2N are only shifted in)
+          // pivot search on window column 0 (even lane); the odd lane takes its result
           int p = 0;
           double best = fabs(Wn[0][0]);
 #pragma unroll
@@ -467,63 +487,78 @@ __device__ __forceinline__ void b_factor_lu(int64_t tile_, HeviShapeDev sh, cons
             const double v = fabs(Wn[t][0]);
             if (j + t < nz && v > best) { best = v; p = t; }
           }
-          if (!(best > 0.0)) { singular = true; Wn[0][0] = 1.0; p = 0; }
-          // Most rows need no exchange in any column of the tile: skip the
-          // selects then (a wave-uniform branch); otherwise each lane selects
-          // its own pivot row.
+          if (h == 0 && !(best > 0.0)) { singular = true; Wn[0][0] = 1.0; p = 0; }
+          const int pp = pair_swap(p);
+          p = h == 0 ? p : pp;
           if (__ballot(p != 0) != 0) {
 #pragma unroll
-            for (int s = 0; s < W; ++s) {
-              const double v0 = Wn[0][s];
+            for (int m = 0; m < H; ++m) {
+              const double v0 = Wn[0][m];
               double vp = v0;
 #pragma unroll
-              for (int t = 1; t <= B; ++t) vp = (p == t) ? Wn[t][s] : vp;
-              Wn[0][s] = vp;
+              for (int t = 1; t <= B; ++t) vp = (p == t) ? Wn[t][m] : vp;
+              Wn[0][m] = vp;
 #pragma unroll
-              for (int t = 1; t <= B; ++t) Wn[t][s] = (p == t) ? v0 : Wn[t][s];
+              for (int t = 1; t <= B; ++t) Wn[t][m] = (p == t) ? v0 : Wn[t][m];
             }
           }
-          piv[tix(tile, nz, j, 1, 0, lane)] = (uint8_t)p;
           FT* urow = Ub + tix(tile, nz, j, W, 0, lane);
 #pragma unroll
-          for (int s = 0; s < W; ++s) urow[s * T] = (FT)Wn[0][s];
+          for (int m = 0; m < H; ++m)
+            if (s0 + m < W) urow[(s0 + m) * T] = (FT)Wn[0][m];
+          // multipliers from the even lane's column 0
           const double inv = 1.0 / Wn[0][0];
-          FT* lrow = Lb + tix(tile, nz, j, B, 0, lane);
+          double l[B + 1];
 #pragma unroll
           for (int t = 1; t <= B; ++t) {
-            const double l = Wn[t][0] * inv;
-            lrow[(t - 1) * T] = (FT)l;
-#pragma unroll
-            for (int s = 1; s < W; ++s) Wn[t][s] -= l * Wn[0][s];
+            const double own = Wn[t][0] * inv;
+            const double other = pair_swap(own);
+            l[t] = h == 0 ? own : other;
           }
+          if (h == 0) {
+            piv[tix(tile, nz, j, 1, 0, lane)] = (uint8_t)p;
+            FT* lrow = Lb + tix(tile, nz, j, B, 0, lane);
+#pragma unroll
+            for (int t = 1; t <= B; ++t) lrow[(t - 1) * T] = (FT)l[t];
+          }
+#pragma unroll
+          for (int t = 1; t <= B; ++t)
+#pragma unroll
+            for (int m = 0; m < H; ++m) Wn[t][m] -= l[t] * Wn[0][m];
         }
+        // shift the window one row up and one column left; the even lane's last
+        // column comes from the odd lane's first, the odd lane's last is zero
+        double cross[B];
+#pragma unroll
+        for (int t = 0; t < B; ++t) cross[t] = pair_swap(Wn[t + 1][0]);
 #pragma unroll
         for (int t = 0; t < B; ++t) {
 #pragma unroll
-          for (int s = 0; s < W - 1; ++s) Wn[t][s] = Wn[t + 1][s + 1];
-          Wn[t][W - 1] = 0.0;
+          for (int m = 0; m < H - 1; ++m) Wn[t][m] = Wn[t + 1][m + 1];
+          Wn[t][H - 1] = h == 0 ? cross[t] : 0.0;
         }
         // new bottom row j + 2N + 1 from the ring; refill the slot
         const int rn = j + B + 1;
 #pragma unroll
-        for (int s = 0; s < W; ++s) Wn[B][s] = s_fix<N>(rn, nz, s, ring[d][s]);
+        for (int m = 0; m < H; ++m)
+          Wn[B][m] = s0 + m < W ? s_fix<N>(rn, nz, s0 + m, ring[d][m]) : 0.0;
         const int rf = min(rn + PFL, nz - 1);
 #pragma unroll
-        for (int s = 0; s < W; ++s) ring[d][s] = sbuf[tix(tile, nz, rf, W, s, lane)];
+        for (int m = 0; m < H; ++m)
+          ring[d][m] = sbuf[tix(tile, nz, rf, W, min(s0 + m, W - 1), lane)];
       }
     }
   }
   if (singular && valid) flag(info, 5 /*HEVI_E_SINGULAR*/, c);
 }
 
-// The same band LU for orders whose window does not fit in registers: the
+// The band LU for orders whose window does not fit in registers: the
 // (2N+1) x (4N+1) window of each column lives in LDS, indexed circularly (row r
 // in slot r mod (2N+1), column c in slot c mod (4N+1)), so moving the window
 // costs nothing; LPC = 64 / CPW lanes share a column (rows and columns of each
 // step are spread over them).  A workgroup of one wavefront handles CPW
 // columns of a 64-column tile (part `part` of 64 / CPW); rows entering the
-// window are prefetched PFR rows ahead into registers.  Pivot choice, operation
-// order and stored factors are those of b_factor_lu.
+// window are prefetched PFR rows ahead into registers.
 constexpr int kLuLdsMinN = 5;  // orders factored with the LDS window
 
 template <int N>

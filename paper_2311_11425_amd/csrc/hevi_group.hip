@@ -120,7 +120,8 @@ __global__ __launch_bounds__(64) void km_factor_lu(const HeviProbDev* __restrict
           b_factor_lu_lds<NN, FT>(tile, part, P.sh, P.sbuf, (FT*)P.U, (FT*)P.L, P.piv, P.info,
                                   lds);
       } else {
-        b_factor_lu<NN, FT>(tile, P.sh, P.sbuf, (FT*)P.U, (FT*)P.L, P.piv, P.info);
+        for (int half = 0; half < 2; ++half)
+          b_factor_lu2<NN, FT>(tile, half, P.sh, P.sbuf, (FT*)P.U, (FT*)P.L, P.piv, P.info);
       }
     });
   });

@@ -92,11 +92,12 @@ __global__ __launch_bounds__(64) void k_factor_assemble(HeviShapeDev sh, double 
 }
 
 template <int N, typename FT>
-__global__ __launch_bounds__(64) void k_factor_lu(HeviShapeDev sh, const double* sbuf,
-                                                  FT* Ub,  // may alias sbuf (FP64)
-                                                  FT* __restrict__ Lb, uint8_t* __restrict__ piv,
-                                                  HeviDevInfo* info) {
-  b_factor_lu<N, FT>((int64_t)blockIdx.x, sh, sbuf, Ub, Lb, piv, info);
+__global__ __launch_bounds__(64) void k_factor_lu2(HeviShapeDev sh, const double* sbuf, FT* Ub,
+                                                     FT* __restrict__ Lb,
+                                                     uint8_t* __restrict__ piv,
+                                                     HeviDevInfo* info) {
+  b_factor_lu2<N, FT>((int64_t)(blockIdx.x >> 1), (int)(blockIdx.x & 1), sh, sbuf, Ub, Lb, piv,
+                      info);
 }
 
 template <int N, typename FT>
@@ -218,7 +219,7 @@ struct Factor {
                         HeviDevInfo* info, hipStream_t st) {
     const dim3 g((unsigned)sh.ntiles);
     hipLaunchKernelGGL(k_factor_assemble<N>, g, dim3(T * CWF), 0, st, sh, lambda, ops, sbuf);
-    if (N >= kLuLdsMinN) {
+    if constexpr (N >= kLuLdsMinN) {
       // the window does not fit in registers: LDS window, 64 / CPW workgroups per tile
       const dim3 gl((unsigned)(sh.ntiles * (64 / LuLdsShape<N>::CPW)));
       if (fp32)
@@ -227,12 +228,15 @@ struct Factor {
       else
         hipLaunchKernelGGL((k_factor_lu_lds<N, double>), gl, dim3(T), 0, st, sh, sbuf,
                            (double*)Ub, (double*)Lb, piv, info);
-    } else if (fp32) {
-      hipLaunchKernelGGL((k_factor_lu<N, float>), g, dim3(T), 0, st, sh, sbuf, (float*)Ub,
-                         (float*)Lb, piv, info);
     } else {
-      hipLaunchKernelGGL((k_factor_lu<N, double>), g, dim3(T), 0, st, sh, sbuf, (double*)Ub,
-                         (double*)Lb, piv, info);
+      // window split over lane pairs: two workgroups (32 columns each) per tile
+      const dim3 g2((unsigned)(sh.ntiles * 2));
+      if (fp32)
+        hipLaunchKernelGGL((k_factor_lu2<N, float>), g2, dim3(T), 0, st, sh, sbuf, (float*)Ub,
+                           (float*)Lb, piv, info);
+      else
+        hipLaunchKernelGGL((k_factor_lu2<N, double>), g2, dim3(T), 0, st, sh, sbuf, (double*)Ub,
+                           (double*)Lb, piv, info);
     }
     return hipGetLastError();
   }
