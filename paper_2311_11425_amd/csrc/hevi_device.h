@@ -420,8 +420,8 @@ __device__ __forceinline__ void b_factor_assemble(int64_t tile_, HeviShapeDev sh
 // and one column right and row j+2N+1 of S enters at the bottom.  The window
 // starts empty at j = -(2N+1), the first 2N+1 steps only shift rows 0..2N in
 // (their loads go through the same prefetch ring as every later row).  Two
-// implementations: a register window split over a lane pair (N <= 4,
-// b_factor_lu2) and an LDS window (N >= 5, b_factor_lu_lds); they store the
+// implementations: a register window split over LPC lanes (N <= 4,
+// b_factor_lu_split) and an LDS window (N >= 5, b_factor_lu_lds); they store the
 // same factors.
 template <int N>
 __device__ __forceinline__ double s_fix(int r, int nz, int s, double raw) {
@@ -435,30 +435,48 @@ __device__ __forceinline__ double s_fix(int r, int nz, int s, double raw) {
   return raw + (s == B ? 1.0 : 0.0);
 }
 
-// exchange a value with the other lane of an even/odd lane pair (DPP quad_perm [1,0,3,2])
-__device__ __forceinline__ int pair_swap(int v) { return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false); }
-__device__ __forceinline__ double pair_swap(double v) {
-  const int lo = pair_swap(__double2loint(v)), hi = pair_swap(__double2hiint(v));
+// Lane exchanges inside groups of LPC = 2 or 4 consecutive lanes (DPP quad_perm):
+// from_first: every lane gets the group's first lane's value; from_next: lane h
+// gets lane h+1's value (the group's last lane gets its own).
+template <int LPC>
+__device__ __forceinline__ int from_first(int v) {
+  return __builtin_amdgcn_mov_dpp(v, LPC == 2 ? 0xA0 : 0x00, 0xF, 0xF, false);
+}
+template <int LPC>
+__device__ __forceinline__ int from_next(int v) {
+  return __builtin_amdgcn_mov_dpp(v, LPC == 2 ? 0xF5 : 0xF9, 0xF, 0xF, false);
+}
+template <int LPC>
+__device__ __forceinline__ double from_first(double v) {
+  const int lo = from_first<LPC>(__double2loint(v)), hi = from_first<LPC>(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+template <int LPC>
+__device__ __forceinline__ double from_next(double v) {
+  const int lo = from_next<LPC>(__double2loint(v)), hi = from_next<LPC>(__double2hiint(v));
   return __hiloint2double(hi, lo);
 }
 
-// The same band LU with each column's window split over a lane pair: the even
-// lane holds window columns 0..2N, the odd lane columns 2N+1..4N (and one
-// always-zero pad column), 81 doubles each at N = 4 instead of 153, so the
-// window stays in VGPRs.  The pair exchanges the pivot index, the multipliers
-// and the column crossing the split with DPP moves.  A wavefront handles 32
-// columns: half `half` of a 64-column tile.
-template <int N, typename FT>
-__device__ __forceinline__ void b_factor_lu2(int64_t tile, int half, HeviShapeDev sh,
-                                             const double* sbuf, FT* Ub, FT* __restrict__ Lb,
-                                             uint8_t* __restrict__ piv, HeviDevInfo* info) {
-  constexpr int B = 2 * N, W = 4 * N + 1, H = 2 * N + 1, PFL = 2;
-  const int h = threadIdx.x & 1;                 // window half of this lane
-  const int lane = half * 32 + (threadIdx.x >> 1);  // the column's lane in its tile
+// The band LU with each column's window split over LPC consecutive lanes: lane
+// h holds window columns hH .. hH+H-1, H = ceil((4N+1) / LPC) (columns past 4N
+// are always zero), so the window stays in VGPRs.  The group shares the pivot
+// index and the multipliers of its first lane, and passes the column crossing
+// each split to the left with DPP moves.  A wavefront handles 64 / LPC columns:
+// part `part` of a 64-column tile.
+constexpr int kLuLanes = 2;  // lanes per column of the register-window LU
+
+template <int N, typename FT, int LPC>
+__device__ __forceinline__ void b_factor_lu_split(int64_t tile, int part, HeviShapeDev sh,
+                                                  const double* sbuf, FT* Ub,
+                                                  FT* __restrict__ Lb,
+                                                  uint8_t* __restrict__ piv, HeviDevInfo* info) {
+  constexpr int B = 2 * N, W = 4 * N + 1, H = (W + LPC - 1) / LPC, PFL = 2;
+  const int h = threadIdx.x % LPC;                           // window part of this lane
+  const int lane = part * (T / LPC) + (threadIdx.x / LPC);   // the column's lane in its tile
   const int64_t c = tile * T + lane;
   const bool valid = c < sh.ncols;
   const int nz = sh.nz;
-  const int s0 = h * H;                          // first window column of this lane
+  const int s0 = h * H;                                      // first window column of this lane
   // Wn[t][m] = entry (j + t, j + s0 + m); empty at j = -(2N+1), rows shifted in
   double Wn[B + 1][H];
 #pragma unroll
@@ -479,7 +497,7 @@ __device__ __forceinline__ void b_factor_lu2(int64_t tile, int half, HeviShapeDe
       const int j = j0 + d;
       if (j < nz) {
         if (j >= 0) {  // elimination step j (rows 0..2N are only shifted in)
-          // pivot search on window column 0 (even lane); the odd lane takes its result
+          // pivot search on window column 0 (first lane of the group)
           int p = 0;
           double best = fabs(Wn[0][0]);
 #pragma unroll
@@ -488,8 +506,7 @@ __device__ __forceinline__ void b_factor_lu2(int64_t tile, int half, HeviShapeDe
             if (j + t < nz && v > best) { best = v; p = t; }
           }
           if (h == 0 && !(best > 0.0)) { singular = true; Wn[0][0] = 1.0; p = 0; }
-          const int pp = pair_swap(p);
-          p = h == 0 ? p : pp;
+          p = from_first<LPC>(p);
           if (__ballot(p != 0) != 0) {
 #pragma unroll
             for (int m = 0; m < H; ++m) {
@@ -506,15 +523,10 @@ __device__ __forceinline__ void b_factor_lu2(int64_t tile, int half, HeviShapeDe
 #pragma unroll
           for (int m = 0; m < H; ++m)
             if (s0 + m < W) urow[(s0 + m) * T] = (FT)Wn[0][m];
-          // multipliers from the even lane's column 0
           const double inv = 1.0 / Wn[0][0];
           double l[B + 1];
 #pragma unroll
-          for (int t = 1; t <= B; ++t) {
-            const double own = Wn[t][0] * inv;
-            const double other = pair_swap(own);
-            l[t] = h == 0 ? own : other;
-          }
+          for (int t = 1; t <= B; ++t) l[t] = from_first<LPC>(Wn[t][0] * inv);
           if (h == 0) {
             piv[tix(tile, nz, j, 1, 0, lane)] = (uint8_t)p;
             FT* lrow = Lb + tix(tile, nz, j, B, 0, lane);
@@ -526,16 +538,16 @@ __device__ __forceinline__ void b_factor_lu2(int64_t tile, int half, HeviShapeDe
 #pragma unroll
             for (int m = 0; m < H; ++m) Wn[t][m] -= l[t] * Wn[0][m];
         }
-        // shift the window one row up and one column left; the even lane's last
-        // column comes from the odd lane's first, the odd lane's last is zero
+        // move the window one row down and one column right: each lane's last
+        // column comes from the next lane's first, the group's last lane's is zero
         double cross[B];
 #pragma unroll
-        for (int t = 0; t < B; ++t) cross[t] = pair_swap(Wn[t + 1][0]);
+        for (int t = 0; t < B; ++t) cross[t] = from_next<LPC>(Wn[t + 1][0]);
 #pragma unroll
         for (int t = 0; t < B; ++t) {
 #pragma unroll
           for (int m = 0; m < H - 1; ++m) Wn[t][m] = Wn[t + 1][m + 1];
-          Wn[t][H - 1] = h == 0 ? cross[t] : 0.0;
+          Wn[t][H - 1] = h < LPC - 1 ? cross[t] : 0.0;
         }
         // new bottom row j + 2N + 1 from the ring; refill the slot
         const int rn = j + B + 1;

@@ -120,8 +120,9 @@ __global__ __launch_bounds__(64) void km_factor_lu(const HeviProbDev* __restrict
           b_factor_lu_lds<NN, FT>(tile, part, P.sh, P.sbuf, (FT*)P.U, (FT*)P.L, P.piv, P.info,
                                   lds);
       } else {
-        for (int half = 0; half < 2; ++half)
-          b_factor_lu2<NN, FT>(tile, half, P.sh, P.sbuf, (FT*)P.U, (FT*)P.L, P.piv, P.info);
+        for (int part = 0; part < kLuLanes; ++part)
+          b_factor_lu_split<NN, FT, kLuLanes>(tile, part, P.sh, P.sbuf, (FT*)P.U, (FT*)P.L, P.piv,
+                                              P.info);
       }
     });
   });

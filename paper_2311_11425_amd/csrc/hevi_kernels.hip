@@ -92,12 +92,12 @@ __global__ __launch_bounds__(64) void k_factor_assemble(HeviShapeDev sh, double 
 }
 
 template <int N, typename FT>
-__global__ __launch_bounds__(64) void k_factor_lu2(HeviShapeDev sh, const double* sbuf, FT* Ub,
-                                                     FT* __restrict__ Lb,
-                                                     uint8_t* __restrict__ piv,
-                                                     HeviDevInfo* info) {
-  b_factor_lu2<N, FT>((int64_t)(blockIdx.x >> 1), (int)(blockIdx.x & 1), sh, sbuf, Ub, Lb, piv,
-                      info);
+__global__ __launch_bounds__(64) void k_factor_lu_split(HeviShapeDev sh, const double* sbuf,
+                                                        FT* Ub, FT* __restrict__ Lb,
+                                                        uint8_t* __restrict__ piv,
+                                                        HeviDevInfo* info) {
+  b_factor_lu_split<N, FT, kLuLanes>((int64_t)(blockIdx.x / kLuLanes),
+                                     (int)(blockIdx.x % kLuLanes), sh, sbuf, Ub, Lb, piv, info);
 }
 
 template <int N, typename FT>
@@ -229,14 +229,14 @@ struct Factor {
         hipLaunchKernelGGL((k_factor_lu_lds<N, double>), gl, dim3(T), 0, st, sh, sbuf,
                            (double*)Ub, (double*)Lb, piv, info);
     } else {
-      // window split over lane pairs: two workgroups (32 columns each) per tile
-      const dim3 g2((unsigned)(sh.ntiles * 2));
+      // window split over kLuLanes lanes: kLuLanes workgroups per tile
+      const dim3 g2((unsigned)(sh.ntiles * kLuLanes));
       if (fp32)
-        hipLaunchKernelGGL((k_factor_lu2<N, float>), g2, dim3(T), 0, st, sh, sbuf, (float*)Ub,
-                           (float*)Lb, piv, info);
+        hipLaunchKernelGGL((k_factor_lu_split<N, float>), g2, dim3(T), 0, st, sh, sbuf,
+                           (float*)Ub, (float*)Lb, piv, info);
       else
-        hipLaunchKernelGGL((k_factor_lu2<N, double>), g2, dim3(T), 0, st, sh, sbuf, (double*)Ub,
-                           (double*)Lb, piv, info);
+        hipLaunchKernelGGL((k_factor_lu_split<N, double>), g2, dim3(T), 0, st, sh, sbuf,
+                           (double*)Ub, (double*)Lb, piv, info);
     }
     return hipGetLastError();
   }
