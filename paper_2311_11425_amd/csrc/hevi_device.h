@@ -63,8 +63,16 @@ __device__ __forceinline__ void flag(HeviDevInfo* info, int code, int64_t col) {
   atomicAdd((unsigned long long*)&info->n_bad, 1ull);
 }
 
+// Streaming accesses carry the non-temporal hint: state vectors, factors and
+// the factorisation's scratch are each touched once per kernel, so they should
+// not evict the compact operator, which every kernel of a step reads again and
+// which fits in the last-level cache at the production column count.
 template <typename FT>
-__device__ __forceinline__ double ld(const FT* p) { return (double)*p; }
+__device__ __forceinline__ double ld(const FT* p) { return (double)__builtin_nontemporal_load(p); }
+__device__ __forceinline__ double ldn(const double* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ void stn(double* p, double v) { __builtin_nontemporal_store(v, p); }
+template <typename FT>
+__device__ __forceinline__ void stnt(FT* p, FT v) { __builtin_nontemporal_store(v, p); }
 
 // ---------------------------------------------------------------------------
 // Element-streaming helpers.  Node eN is shared by elements e-1 and e; a sum
@@ -229,8 +237,8 @@ __device__ __forceinline__ void b_apply(int64_t tile_, HeviShapeDev sh, Gll<N> t
   OpsView op{ops, tile, nz, lane};
   auto X = [&](int v, int k) {
     const size_t i = cix(nz, nc, v, k, cc);
-    if constexpr (HAS_REF) return x[i] - xref[i];
-    else return x[i];
+    if constexpr (HAS_REF) return ldn(x + i) - ldn(xref + i);
+    else return ldn(x + i);
   };
   double cr = 0.0, ct = 0.0, c0 = 0.0, c1 = 0.0, c2 = 0.0;
   // node eN is shared by elements e-1 and e: its loaded values are carried
@@ -297,7 +305,7 @@ __device__ __forceinline__ void b_apply(int64_t tile_, HeviShapeDev sh, Gll<N> t
       for (int a = 0; a <= N; ++a) {
         if (a <= amax) {
 #pragma unroll
-          for (int v = 0; v < 5; ++v) y[cix(nz, nc, v, e * N + a, c)] = yo[a][v];
+          for (int v = 0; v < 5; ++v) stn(y + cix(nz, nc, v, e * N + a, c), yo[a][v]);
         }
       }
     }
@@ -406,7 +414,7 @@ __device__ __forceinline__ void b_factor_assemble(int64_t tile_, HeviShapeDev sh
       }
       double* row = sbuf + tix(tile, nz, r, W, 0, lane);
 #pragma unroll
-      for (int o = 0; o < W; ++o) row[o * T] = -l2 * acc[o];
+      for (int o = 0; o < W; ++o) stn(row + o * T, -l2 * acc[o]);
     }
   }
 }
@@ -488,7 +496,7 @@ __device__ __forceinline__ void b_factor_lu_split(int64_t tile, int part, HeviSh
   for (int d = 0; d < PFL; ++d) {
     const int r = min(d, nz - 1);
 #pragma unroll
-    for (int m = 0; m < H; ++m) ring[d][m] = sbuf[tix(tile, nz, r, W, min(s0 + m, W - 1), lane)];
+    for (int m = 0; m < H; ++m) ring[d][m] = ldn(sbuf + tix(tile, nz, r, W, min(s0 + m, W - 1), lane));
   }
   bool singular = false;
   for (int j0 = -(B + 1); j0 < nz; j0 += PFL) {
@@ -522,7 +530,7 @@ __device__ __forceinline__ void b_factor_lu_split(int64_t tile, int part, HeviSh
           FT* urow = Ub + tix(tile, nz, j, W, 0, lane);
 #pragma unroll
           for (int m = 0; m < H; ++m)
-            if (s0 + m < W) urow[(s0 + m) * T] = (FT)Wn[0][m];
+            if (s0 + m < W) stnt(urow + (s0 + m) * T, (FT)Wn[0][m]);
           const double inv = 1.0 / Wn[0][0];
           double l[B + 1];
 #pragma unroll
@@ -531,7 +539,7 @@ __device__ __forceinline__ void b_factor_lu_split(int64_t tile, int part, HeviSh
             piv[tix(tile, nz, j, 1, 0, lane)] = (uint8_t)p;
             FT* lrow = Lb + tix(tile, nz, j, B, 0, lane);
 #pragma unroll
-            for (int t = 1; t <= B; ++t) lrow[(t - 1) * T] = (FT)l[t];
+            for (int t = 1; t <= B; ++t) stnt(lrow + (t - 1) * T, (FT)l[t]);
           }
 #pragma unroll
           for (int t = 1; t <= B; ++t)
@@ -557,7 +565,7 @@ __device__ __forceinline__ void b_factor_lu_split(int64_t tile, int part, HeviSh
         const int rf = min(rn + PFL, nz - 1);
 #pragma unroll
         for (int m = 0; m < H; ++m)
-          ring[d][m] = sbuf[tix(tile, nz, rf, W, min(s0 + m, W - 1), lane)];
+          ring[d][m] = ldn(sbuf + tix(tile, nz, rf, W, min(s0 + m, W - 1), lane));
       }
     }
   }
@@ -608,7 +616,7 @@ __device__ __forceinline__ void b_factor_lu_lds(int64_t tile, int part, HeviShap
     const int rr = min(r, nz - 1);
 #pragma unroll
     for (int i = 0; i < CS; ++i)
-      v0[r][i] = sbuf[tix(tile, nz, rr, W, min(k + i * LPC, W - 1), lane)];
+      v0[r][i] = ldn(sbuf + tix(tile, nz, rr, W, min(k + i * LPC, W - 1), lane));
   }
 #pragma unroll
   for (int r = 0; r <= B; ++r) {
@@ -626,7 +634,7 @@ __device__ __forceinline__ void b_factor_lu_lds(int64_t tile, int part, HeviShap
 #pragma unroll
     for (int i = 0; i < CS; ++i) {
       const int off = min(k + i * LPC, W - 1);
-      ring[d][i] = sbuf[tix(tile, nz, rr, W, off, lane)];
+      ring[d][i] = ldn(sbuf + tix(tile, nz, rr, W, off, lane));
     }
   }
   __syncthreads();
@@ -678,7 +686,7 @@ __device__ __forceinline__ void b_factor_lu_lds(int64_t tile, int part, HeviShap
 #pragma unroll
         for (int i = 0; i < CS; ++i) {
           const int s = k + i * LPC;
-          if (s < W) urow[s * T] = (FT)at(j, j + s);
+          if (s < W) stnt(urow + s * T, (FT)at(j, j + s));
         }
         const double inv = 1.0 / at(j, j);
         FT* lrow = Lb + tix(tile, nz, j, B, 0, lane);
@@ -687,7 +695,7 @@ __device__ __forceinline__ void b_factor_lu_lds(int64_t tile, int part, HeviShap
           const int t = 1 + k + i * LPC;
           if (t <= B) {
             const double l = at(j + t, j) * inv;
-            lrow[(t - 1) * T] = (FT)l;
+            stnt(lrow + (t - 1) * T, (FT)l);
 #pragma unroll
             for (int s = 1; s < W; ++s) at(j + t, j + s) -= l * at(j, j + s);
             at(j + t, j) = 0.0;  // this slot becomes column j + 4N + 1 (zero so far)
@@ -706,7 +714,7 @@ __device__ __forceinline__ void b_factor_lu_lds(int64_t tile, int part, HeviShap
 #pragma unroll
         for (int i = 0; i < CS; ++i) {
           const int off = min(k + i * LPC, W - 1);
-          ring[d][i] = sbuf[tix(tile, nz, rf, W, off, lane)];
+          ring[d][i] = ldn(sbuf + tix(tile, nz, rf, W, off, lane));
         }
         __syncthreads();
       }
@@ -1068,7 +1076,7 @@ __device__ __forceinline__ void b_stage_solve(int64_t tile_, HeviShapeDev sh, Gl
 #pragma unroll
       for (int j = 0; j <= N; ++j)
 #pragma unroll
-        for (int v = 0; v < 5; ++v) qE[j][v] += cf * src[cix(nz, nc, v, e * N + j, cc)];
+        for (int v = 0; v < 5; ++v) qE[j][v] += cf * ldn(src + cix(nz, nc, v, e * N + j, cc));
     }
 #pragma unroll
     for (int j = 0; j <= N; ++j)
@@ -1080,7 +1088,7 @@ __device__ __forceinline__ void b_stage_solve(int64_t tile_, HeviShapeDev sh, Gl
 #pragma unroll
       for (int j = 0; j <= N; ++j)
 #pragma unroll
-        for (int v = 0; v < 5; ++v) b[j][v] += cf * src[cix(nz, nc, v, e * N + j, cc)];
+        for (int v = 0; v < 5; ++v) b[j][v] += cf * ldn(src + cix(nz, nc, v, e * N + j, cc));
     }
     double f0[N + 1], f1[N + 1], f2[N + 1];
 #pragma unroll
@@ -1126,11 +1134,11 @@ __device__ __forceinline__ void b_stage_solve(int64_t tile_, HeviShapeDev sh, Gl
         h1 = qE[a][1]; h2 = qE[a][2]; h3 = qE[a][3];
       }
       if (valid) {
-        Qi[cix(nz, nc, 0, k, c)] = qE[a][0];
-        Qi[cix(nz, nc, 1, k, c)] = h1;
-        Qi[cix(nz, nc, 2, k, c)] = h2;
-        Qi[cix(nz, nc, 3, k, c)] = h3;
-        Qi[cix(nz, nc, 4, k, c)] = qE[a][4];
+        stn(Qi + cix(nz, nc, 0, k, c), qE[a][0]);
+        stn(Qi + cix(nz, nc, 1, k, c), h1);
+        stn(Qi + cix(nz, nc, 2, k, c), h2);
+        stn(Qi + cix(nz, nc, 3, k, c), h3);
+        stn(Qi + cix(nz, nc, 4, k, c), qE[a][4]);
       }
     }
   }
@@ -1236,7 +1244,7 @@ __device__ __forceinline__ void b_stage_rhs(int64_t tile_, HeviShapeDev sh, Gll<
 #pragma unroll
       for (int j = FIRST ? 0 : 1; j <= N; ++j)
 #pragma unroll
-        for (int v = 0; v < 5; ++v) qE[j][v] += cf * src[cix(nz, nc, v, e * N + j, cc)];
+        for (int v = 0; v < 5; ++v) qE[j][v] += cf * ldn(src + cix(nz, nc, v, e * N + j, cc));
     }
 #pragma unroll
     for (int j = 0; j <= N; ++j)
@@ -1249,7 +1257,7 @@ __device__ __forceinline__ void b_stage_rhs(int64_t tile_, HeviShapeDev sh, Gll<
 #pragma unroll
       for (int j = FIRST ? 0 : 1; j <= N; ++j)
 #pragma unroll
-        for (int v = 0; v < 5; ++v) b[j][v] += cf * src[cix(nz, nc, v, e * N + j, cc)];
+        for (int v = 0; v < 5; ++v) b[j][v] += cf * ldn(src + cix(nz, nc, v, e * N + j, cc));
     }
     double g0[N + 1], g1[N + 1], g2[N + 1], mi[N + 1], ph[N + 1], f0[N + 1], f1[N + 1], f2[N + 1];
 #pragma unroll
@@ -1301,11 +1309,11 @@ __device__ __forceinline__ void b_stage_rhs(int64_t tile_, HeviShapeDev sh, Gll<
           const int k = e * N + a;
           ws[tix(tile, nz, k, HEVI_NWS, WS_R, lane)] = ro[a];
           if (valid) {
-            Qi[cix(nz, nc, 0, k, c)] = qE[a][0];
-            Qi[cix(nz, nc, 1, k, c)] = ho[a][0];
-            Qi[cix(nz, nc, 2, k, c)] = ho[a][1];
-            Qi[cix(nz, nc, 3, k, c)] = ho[a][2];
-            Qi[cix(nz, nc, 4, k, c)] = qE[a][4];
+            stn(Qi + cix(nz, nc, 0, k, c), qE[a][0]);
+            stn(Qi + cix(nz, nc, 1, k, c), ho[a][0]);
+            stn(Qi + cix(nz, nc, 2, k, c), ho[a][1]);
+            stn(Qi + cix(nz, nc, 3, k, c), ho[a][2]);
+            stn(Qi + cix(nz, nc, 4, k, c), qE[a][4]);
           }
         }
       }
@@ -1408,7 +1416,7 @@ __device__ __forceinline__ void b_stage_update(int64_t tile_, HeviShapeDev sh, G
       g0[j] = op(k, OP_GX); g1[j] = op(k, OP_GY); g2[j] = op(k, OP_GZ);
       mi[j] = op(k, OP_MINV); ph[j] = op(k, OP_PHI); jc[j] = op(k, OP_JCT);
 #pragma unroll
-      for (int v = 0; v < 5; ++v) q[j][v] = Qi[cix(nz, nc, v, k, cc)];
+      for (int v = 0; v < 5; ++v) q[j][v] = ldn(Qi + cix(nz, nc, v, k, cc));
     }
     // node N as loaded (before this element's update) is node 0 of the next
 #pragma unroll
@@ -1479,7 +1487,7 @@ __device__ __forceinline__ void b_stage_update(int64_t tile_, HeviShapeDev sh, G
         if (a <= amax) {
 #pragma unroll
           for (int v = 0; v < 5; ++v) {
-            Qi[cix(nz, nc, v, e * N + a, c)] = q[a][v];
+            stn(Qi + cix(nz, nc, v, e * N + a, c), q[a][v]);
             if (!isfinite(q[a][v])) nonfinite = true;
           }
         }

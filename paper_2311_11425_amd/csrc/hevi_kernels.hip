@@ -158,8 +158,8 @@ __global__ __launch_bounds__(256) void k_combine(int64_t n, HeviTerms V, double*
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     double s = 0.0;
-    for (int t = 0; t < V.n; ++t) s += V.coef[t] * V.v[t][i];
-    out[i] = s;
+    for (int t = 0; t < V.n; ++t) s += V.coef[t] * __builtin_nontemporal_load(V.v[t] + i);
+    __builtin_nontemporal_store(s, out + i);
   }
 }
 
