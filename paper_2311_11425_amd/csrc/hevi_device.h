@@ -1233,12 +1233,19 @@ __device__ __forceinline__ void b_stage_rhs(int64_t tile_, HeviShapeDev sh, Gll<
   auto element = [&](const int e, auto first) {
     constexpr bool FIRST = decltype(first)::value;
     double qE[N + 1][5], b[N + 1][5];
+    // E's first vector (q^n in an ARK stage) is loaded once; a Q term naming the
+    // same vector (Q_1 = q^n) reuses it
+    double e0[N + 1][5];
+#pragma unroll
+    for (int j = FIRST ? 0 : 1; j <= N; ++j)
+#pragma unroll
+      for (int v = 0; v < 5; ++v) e0[j][v] = ldn(E.v[0] + cix(nz, nc, v, e * N + j, cc));
 #pragma unroll
     for (int j = 0; j <= N; ++j)
 #pragma unroll
-      for (int v = 0; v < 5; ++v) qE[j][v] = (!FIRST && j == 0) ? kqE[v] : 0.0;
+      for (int v = 0; v < 5; ++v) qE[j][v] = (!FIRST && j == 0) ? kqE[v] : E.coef[0] * e0[j][v];
 #pragma unroll 2
-    for (int t = 0; t < E.n; ++t) {
+    for (int t = 1; t < E.n; ++t) {
       const double* src = E.v[t];
       const double cf = E.coef[t];
 #pragma unroll
@@ -1250,8 +1257,16 @@ __device__ __forceinline__ void b_stage_rhs(int64_t tile_, HeviShapeDev sh, Gll<
     for (int j = 0; j <= N; ++j)
 #pragma unroll
       for (int v = 0; v < 5; ++v) b[j][v] = (!FIRST && j == 0) ? kb[v] : qE[j][v];
+    const bool alias0 = Q.n > 0 && Q.v[0] == E.v[0];
+    if (alias0) {
+      const double cf = Q.coef[0];
+#pragma unroll
+      for (int j = FIRST ? 0 : 1; j <= N; ++j)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) b[j][v] += cf * e0[j][v];
+    }
 #pragma unroll 2
-    for (int t = 0; t < Q.n; ++t) {
+    for (int t = alias0 ? 1 : 0; t < Q.n; ++t) {
       const double* src = Q.v[t];
       const double cf = Q.coef[t];
 #pragma unroll
