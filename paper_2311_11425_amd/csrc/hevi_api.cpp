@@ -336,12 +336,14 @@ hevi_status hevi_tableau(const char* name, int32_t* s, double* a_exp, double* a_
     const double g = 1767732205903.0 / 4055673282236.0;
     const double E[16] = {0, 0, 0, 0,
                           1767732205903.0 / 2027836641118.0, 0, 0, 0,
-                          5535828885825.0 / 10492691773637.0, 788022342437.0 / 10882634858940.0, 0, 0,
+                          5535828885825.0 / 10492691773637.0,
+                          788022342437.0 / 10882634858940.0, 0, 0,
                           6485989280629.0 / 16251701735622.0, -4246266847089.0 / 9704473918619.0,
                           10755448449292.0 / 10357097424841.0, 0};
     const double I[16] = {0, 0, 0, 0,
                           g, g, 0, 0,
-                          2746238789719.0 / 10658868560708.0, -640167445237.0 / 6845629431997.0, g, 0,
+                          2746238789719.0 / 10658868560708.0,
+                          -640167445237.0 / 6845629431997.0, g, 0,
                           1471266399579.0 / 7840856788654.0, -4482444167858.0 / 7529755066697.0,
                           11266239266428.0 / 11593286722821.0, g};
     *s = 4;

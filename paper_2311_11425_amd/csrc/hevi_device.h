@@ -2,9 +2,8 @@
 // per-tile bodies of every kernel, shared by the single-problem kernels
 // (hevi_kernels.hip) and the multi-problem persistent kernels (hevi_group.hip).
 //
-//
 // Mapping.  One lane owns one vertical column; a 64-lane wavefront owns a tile
-// of 64 consecutive columns.  The caller's arrays are column-fastest
+// of 64 consecutive columns (the LU kernels split a column over several lanes).  The caller's arrays are column-fastest
 // struct-of-arrays, so every per-node access of a wavefront is one coalesced
 // 512-byte FP64 request.  Library-owned arrays (compact operator, factors,
 // scratch) are tile-interleaved: element (tile, node k, field f, lane) sits at
@@ -193,12 +192,14 @@ __device__ void pg_pass(Gll<N> tab, const OpsView& op, int Ne, double* ws, int64
 }
 
 // ---------------------------------------------------------------------------
-// Element-chunked kernels: a 256-thread block owns one 64-column tile; its four
-// wavefronts own contiguous chunks of elements [e0, e1) and the nodes
+// Element-chunked kernels: a block of CW wavefronts owns one 64-column tile;
+// wavefront w owns a contiguous chunk of elements [e0, e1) and the nodes
 // e0*N .. e1*N - 1 (plus the top node for the last chunk).  A node on a chunk
 // boundary also receives a contribution from the last element of the previous
 // chunk; the wavefront recomputes that element's contribution itself instead of
-// exchanging partial sums, so the four wavefronts run independently.
+// exchanging partial sums, so the wavefronts run independently.  One wavefront
+// per tile (CW = 1) measured fastest: the chunk recomputation costs more than
+// the extra wavefronts gain.
 constexpr int CW = 1;  // chunk wavefronts per tile
 
 struct Chunk {
@@ -363,7 +364,8 @@ __device__ __forceinline__ void b_factor_assemble(int64_t tile_, HeviShapeDev sh
 #pragma unroll
       for (int q = 0; q < NC; ++q) DT[i][q] = 0.0;
 #pragma unroll
-      for (int i2 = 0; i2 <= N; ++i2) DT[i][N + i2] += tab.w[i] * tab.D[i * (N + 1) + i2] * Jth[N + i2];
+      for (int i2 = 0; i2 <= N; ++i2)
+        DT[i][N + i2] += tab.w[i] * tab.D[i * (N + 1) + i2] * Jth[N + i2];
       if (i == 0 && e > 0) {
 #pragma unroll
         for (int i2 = 0; i2 <= N; ++i2) DT[0][i2] += tab.w[N] * tab.D[N * (N + 1) + i2] * Jth[i2];
@@ -496,7 +498,8 @@ __device__ __forceinline__ void b_factor_lu_split(int64_t tile, int part, HeviSh
   for (int d = 0; d < PFL; ++d) {
     const int r = min(d, nz - 1);
 #pragma unroll
-    for (int m = 0; m < H; ++m) ring[d][m] = ldn(sbuf + tix(tile, nz, r, W, min(s0 + m, W - 1), lane));
+    for (int m = 0; m < H; ++m)
+      ring[d][m] = ldn(sbuf + tix(tile, nz, r, W, min(s0 + m, W - 1), lane));
   }
   bool singular = false;
   for (int j0 = -(B + 1); j0 < nz; j0 += PFL) {
@@ -734,13 +737,13 @@ enum { WS_R = 0, WS_U = 1, WS_VR = 2, WS_VT = 3, WS_T = 4, WS_D = 5, WS_B = 6, W
        WS_S = 16 };
 
 // solve S x = rhs with the band LU factors (rhs field fi, result field fo).
-// The sweeps are sequential in the row index, so each wavefront keeps the
-// factor rows of the next rows in flight (PF forward, PB backward) (software prefetch into a register
-// ring, refilled as soon as a slot is consumed) while it works on the current one.
+// The sweeps are sequential in the row index, so each wavefront keeps the factor
+// rows of the next rows in flight (PF forward, PB backward) in a register ring,
+// refilled as soon as a slot is consumed, while it works on the current row.
 template <int N, typename FT>
 __device__ __forceinline__ void band_solve(const FT* __restrict__ Ub, const FT* __restrict__ Lb,
-                           const uint8_t* __restrict__ piv, double* ws, int64_t tile, int nz,
-                           int lane, int fi, int fo) {
+                                           const uint8_t* __restrict__ piv, double* ws,
+                                           int64_t tile, int nz, int lane, int fi, int fo) {
   constexpr int B = 2 * N, K = 4 * N, PF = 3, PB = 2;
   // ---- forward: row swaps and unit-lower elimination ----
   double y[B + 1];

@@ -50,7 +50,8 @@ __global__ __launch_bounds__(64) void k_build_ops(HeviShapeDev sh, double R, dou
       }
       double dz = 0.0;
 #pragma unroll
-      for (int j = 0; j <= N; ++j) dz += tab.D[ii * (N + 1) + j] * z[(size_t)(ee * N + j) * nc + cc];
+      for (int j = 0; j <= N; ++j)
+        dz += tab.D[ii * (N + 1) + j] * z[(size_t)(ee * N + j) * nc + cc];
       M += tab.w[ii] * Jk;
       Gn += tab.w[ii] * Jk * g * dz;
     }
@@ -122,7 +123,8 @@ __global__ __launch_bounds__(64) void k_stage_solve(HeviShapeDev sh, double lamb
                                                     int max_sweeps, double rel_target,
                                                     int full_sweeps, HeviDevInfo* info) {
   b_stage_solve<N, FT, FULL>((int64_t)blockIdx.x,
-      sh, Gll<N>{}, lambda, ops, Ub, Lb, piv, ws, E, Q, Qi, max_sweeps, rel_target, full_sweeps, info);
+      sh, Gll<N>{}, lambda, ops, Ub, Lb, piv, ws, E, Q, Qi, max_sweeps, rel_target, full_sweeps,
+      info);
 }
 
 template <int N>
@@ -205,9 +207,11 @@ struct Apply {
   static hipError_t run(const HeviShapeDev& sh, const double* ops,
                         const double* x, const double* xref, double* y, hipStream_t st) {
     if (xref)
-      hipLaunchKernelGGL((k_apply<N, true>), dim3((unsigned)sh.ntiles), dim3(T * CW), 0, st, sh, ops, x, xref, y);
+      hipLaunchKernelGGL((k_apply<N, true>), dim3((unsigned)sh.ntiles), dim3(T * CW), 0, st, sh,
+                         ops, x, xref, y);
     else
-      hipLaunchKernelGGL((k_apply<N, false>), dim3((unsigned)sh.ntiles), dim3(T * CW), 0, st, sh, ops, x, xref, y);
+      hipLaunchKernelGGL((k_apply<N, false>), dim3((unsigned)sh.ntiles), dim3(T * CW), 0, st, sh,
+                         ops, x, xref, y);
     return hipGetLastError();
   }
 };

@@ -101,3 +101,24 @@ def test_serve_and_group_reject_null_handles():
     assert lib.hevi_group_step(None, None, 1, None) == 1
     assert lib.hevi_group_set_plan(None, None, None) == 1
     lib.hevi_group_free(None)
+
+
+def test_kernel_gll_tables_match_oracle():
+    """The kernels' compile-time GLL tables (csrc/hevi_gll.h, correctly rounded from 50-digit
+    values) agree with the oracle's independent double-precision Newton tables to a few ulp,
+    and every row of each differentiation matrix sums to zero to within rounding."""
+    import oracle
+    txt = open(os.path.join(ROOT, "paper_2311_11425_amd", "csrc", "hevi_gll.h")).read()
+    for N in range(1, 9):
+        blk = txt[txt.index(f"struct Gll<{N}>"):]
+        blk = blk[:blk.index("};\n};")]
+        nums = [float.fromhex(t) for t in re.findall(r"-?0x[0-9a-fp.+-]+", blk)]
+        assert len(nums) == (N + 1) + (N + 1) ** 2
+        w = np.array(nums[:N + 1])
+        D = np.array(nums[N + 1:]).reshape(N + 1, N + 1)
+        _, ow, oD = oracle.gll(N)
+        oD = np.asarray(oD).reshape(N + 1, N + 1)
+        assert np.abs(w - ow).max() <= 4e-16 * max(1.0, np.abs(ow).max())
+        assert np.abs(D - oD).max() <= 2e-14 * max(1.0, np.abs(oD).max())
+        assert np.abs(D.sum(axis=1)).max() <= 1e-15 * np.abs(D).max() * (N + 1)
+        assert abs(w.sum() - 2.0) <= 4e-16 * (N + 1)
