@@ -3,7 +3,7 @@
 // (hevi_kernels.hip) and the multi-problem persistent kernels (hevi_group.hip).
 //
 // Mapping.  One lane owns one vertical column; a 64-lane wavefront owns a tile
-// of 64 consecutive columns (the LU kernels split a column over several lanes).  The caller's arrays are column-fastest
+// of 64 consecutive columns (the LU kernels split a column over lanes).  The caller's arrays are column-fastest
 // struct-of-arrays, so every per-node access of a wavefront is one coalesced
 // 512-byte FP64 request.  Library-owned arrays (compact operator, factors,
 // scratch) are tile-interleaved: element (tile, node k, field f, lane) sits at
@@ -740,16 +740,23 @@ enum { WS_R = 0, WS_U = 1, WS_VR = 2, WS_VT = 3, WS_T = 4, WS_D = 5, WS_B = 6, W
 // The sweeps are sequential in the row index, so each wavefront keeps the factor
 // rows of the next rows in flight (PF forward, PB backward) in a register ring,
 // refilled as soon as a slot is consumed, while it works on the current row.
-template <int N, typename FT>
+template <int N, typename FT, bool LDSRU = false>
 __device__ __forceinline__ void band_solve(const FT* __restrict__ Ub, const FT* __restrict__ Lb,
                                            const uint8_t* __restrict__ piv, double* ws,
-                                           int64_t tile, int nz, int lane, int fi, int fo) {
+                                           int64_t tile, int nz, int lane, int fi, int fo,
+                                           double* ru = nullptr) {
+  // right-hand side and solution: scratch fields fi / fo, or (LDSRU) one array
+  // ru[k * 64 + lane] in LDS used in place
+  auto S = [&](int k, int f) -> double& {
+    if constexpr (LDSRU) return ru[k * T + lane];
+    else return ws[tix(tile, nz, k, HEVI_NWS, f, lane)];
+  };
   constexpr int B = 2 * N, K = 4 * N, PF = 3, PB = 2;
   // ---- forward: row swaps and unit-lower elimination ----
   double y[B + 1];
 #pragma unroll
   for (int t = 0; t <= B; ++t) {
-    const double v = ws[tix(tile, nz, min(t, nz - 1), HEVI_NWS, fi, lane)];
+    const double v = S(min(t, nz - 1), fi);
     y[t] = (t < nz) ? v : 0.0;
   }
   double lr[PF][B], rin[PF];
@@ -761,7 +768,7 @@ __device__ __forceinline__ void band_solve(const FT* __restrict__ Ub, const FT* 
 #pragma unroll
     for (int t = 0; t < B; ++t) lr[d][t] = ld(Lb + tix(tile, nz, jj, B, t, lane));
     const int rn = d + B + 1;
-    const double rv = ws[tix(tile, nz, min(rn, nz - 1), HEVI_NWS, fi, lane)];
+    const double rv = S(min(rn, nz - 1), fi);
     rin[d] = (rn < nz) ? rv : 0.0;
   }
   for (int j0 = 0; j0 < nz; j0 += PF) {
@@ -776,7 +783,7 @@ __device__ __forceinline__ void band_solve(const FT* __restrict__ Ub, const FT* 
         for (int t = 1; t <= B; ++t) vp = (p == t) ? y[t] : vp;
 #pragma unroll
         for (int t = 1; t <= B; ++t) y[t] = (p == t) ? v0 : y[t];
-        ws[tix(tile, nz, j, HEVI_NWS, fo, lane)] = vp;
+        S(j, fo) = vp;
 #pragma unroll
         for (int t = 1; t <= B; ++t) y[t] -= lr[d][t - 1] * vp;
 #pragma unroll
@@ -789,7 +796,7 @@ __device__ __forceinline__ void band_solve(const FT* __restrict__ Ub, const FT* 
 #pragma unroll
         for (int t = 0; t < B; ++t) lr[d][t] = ld(Lb + tix(tile, nz, jj, B, t, lane));
         const int rn = jn + B + 1;
-        const double rv = ws[tix(tile, nz, min(rn, nz - 1), HEVI_NWS, fi, lane)];
+        const double rv = S(min(rn, nz - 1), fi);
         rin[d] = (rn < nz) ? rv : 0.0;
       }
     }
@@ -805,7 +812,7 @@ __device__ __forceinline__ void band_solve(const FT* __restrict__ Ub, const FT* 
     const int jj = jr >= 0 ? jr : 0;
 #pragma unroll
     for (int t = 0; t <= K; ++t) ur[d][t] = ld(Ub + tix(tile, nz, jj, K + 1, t, lane));
-    yin[d] = ws[tix(tile, nz, jj, HEVI_NWS, fo, lane)];
+    yin[d] = S(jj, fo);
   }
   for (int j0 = nz - 1; j0 >= 0; j0 -= PB) {
 #pragma unroll
@@ -816,7 +823,7 @@ __device__ __forceinline__ void band_solve(const FT* __restrict__ Ub, const FT* 
 #pragma unroll
         for (int t = 1; t <= K; ++t) s -= ur[d][t] * xw[t];
         const double xj = s / ur[d][0];
-        ws[tix(tile, nz, j, HEVI_NWS, fo, lane)] = xj;
+        S(j, fo) = xj;
 #pragma unroll
         for (int t = K; t >= 2; --t) xw[t] = xw[t - 1];
         xw[1] = xj;
@@ -825,7 +832,7 @@ __device__ __forceinline__ void band_solve(const FT* __restrict__ Ub, const FT* 
         const int jj = jr >= 0 ? jr : 0;
 #pragma unroll
         for (int t = 0; t <= K; ++t) ur[d][t] = ld(Ub + tix(tile, nz, jj, K + 1, t, lane));
-        yin[d] = ws[tix(tile, nz, jj, HEVI_NWS, fo, lane)];
+        yin[d] = S(jj, fo);
       }
     }
   }
@@ -1212,11 +1219,12 @@ __device__ __forceinline__ void b_stage_solve(int64_t tile_, HeviShapeDev sh, Gl
 // (at the lid: Q_U <- q^E_U - n (n . q^_U)) and the reduced right-hand side
 // r = grad(zeta).(q^_U + lambda (PG q^_Theta - Phi' grad(zeta) q^_rho)) (0 at the lid).
 // The term loop is outermost so that each term issues (N+1)*5 independent loads.
-template <int N>
+template <int N, bool LDSRU = false>
 __device__ __forceinline__ void b_stage_rhs(int64_t tile_, HeviShapeDev sh, Gll<N> tab,
                                             double lambda, const double* __restrict__ ops,
                                             double* __restrict__ ws, const HeviTerms& E,
-                                            const HeviTerms& Q, double* __restrict__ Qi) {
+                                            const HeviTerms& Q, double* __restrict__ Qi,
+                                            double* ru = nullptr) {
   const int Ne = sh.Ne, nz = sh.nz;
   const Chunk ch = chunk_of(Ne, tile_);
   if (ch.e0 >= ch.e1) return;
@@ -1325,7 +1333,8 @@ __device__ __forceinline__ void b_stage_rhs(int64_t tile_, HeviShapeDev sh, Gll<
       for (int a = 0; a <= N; ++a) {
         if (a <= amax) {
           const int k = e * N + a;
-          ws[tix(tile, nz, k, HEVI_NWS, WS_R, lane)] = ro[a];
+          if constexpr (LDSRU) ru[k * T + lane] = ro[a];
+          else ws[tix(tile, nz, k, HEVI_NWS, WS_R, lane)] = ro[a];
           if (valid) {
             stn(Qi + cix(nz, nc, 0, k, c), qE[a][0]);
             stn(Qi + cix(nz, nc, 1, k, c), ho[a][0]);
@@ -1380,11 +1389,11 @@ __device__ __forceinline__ void b_stage_bsolve(int64_t tile_, HeviShapeDev sh, G
 // lambda^2 (PG v_Th - Phi' grad(zeta) v_rho) [interior], lambda v_Th).
 // An element needs u on its neighbours too (the DSS of Drho u, DTh u at its end
 // nodes), so each iteration loads u and the operator on nodes (e-1)N .. (e+2)N.
-template <int N>
+template <int N, bool LDSRU = false>
 __device__ __forceinline__ void b_stage_update(int64_t tile_, HeviShapeDev sh, Gll<N> tab,
                                                double lambda, const double* __restrict__ ops,
                                                double* __restrict__ ws, double* __restrict__ Qi,
-                                               HeviDevInfo* info) {
+                                               HeviDevInfo* info, double* ru = nullptr) {
   constexpr int NC = 3 * N + 1;
   const int Ne = sh.Ne, nz = sh.nz;
   const Chunk ch = chunk_of(Ne, tile_);
@@ -1416,7 +1425,7 @@ __device__ __forceinline__ void b_stage_update(int64_t tile_, HeviShapeDev sh, G
       }
       const int k = (e - 1) * N + q;
       const int kk = min(max(k, 0), nz - 1);
-      const double u = ws[tix(tile, nz, kk, HEVI_NWS, WS_U, lane)];
+      const double u = LDSRU ? ru[kk * T + lane] : ws[tix(tile, nz, kk, HEVI_NWS, WS_U, lane)];
       const double in = (k >= 0 && k < nz) ? 1.0 : 0.0;
       Ju[q] = in * op(kk, OP_J) * u;
       Jtu[q] = in * op(kk, OP_JTH) * u;

@@ -127,6 +127,27 @@ __global__ __launch_bounds__(64) void k_stage_solve(HeviShapeDev sh, double lamb
       info);
 }
 
+// The FP64 stage solve in one kernel: the three passes run back to back in the
+// wavefront that owns the tile, with the reduced right-hand side r and the
+// solution u (one array, used in place) in LDS instead of the global scratch.
+template <int N>
+__global__ __launch_bounds__(64, 2) void k_stage_fused(HeviShapeDev sh, double lambda,
+                                                     const double* __restrict__ ops,
+                                                     const double* __restrict__ Ub,
+                                                     const double* __restrict__ Lb,
+                                                     const uint8_t* __restrict__ piv,
+                                                     double* __restrict__ ws, HeviTerms E,
+                                                     HeviTerms Q, double* __restrict__ Qi,
+                                                     HeviDevInfo* info) {
+  extern __shared__ double ru[];  // [n_z][64]
+  const int64_t tile = blockIdx.x;
+  b_stage_rhs<N, true>(tile, sh, Gll<N>{}, lambda, ops, ws, E, Q, Qi, ru);
+  __syncthreads();
+  band_solve<N, double, true>(Ub, Lb, piv, ws, tile, sh.nz, (int)threadIdx.x, WS_R, WS_U, ru);
+  __syncthreads();
+  b_stage_update<N, true>(tile, sh, Gll<N>{}, lambda, ops, ws, Qi, info, ru);
+}
+
 template <int N>
 __global__ __launch_bounds__(64, 2) void k_stage_rhs(HeviShapeDev sh, double lambda,
                                                      const double* __restrict__ ops,
@@ -246,6 +267,8 @@ struct Factor {
   }
 };
 
+constexpr int kFusedMaxNz = 128;  // r/u of a tile in LDS: n_z * 512 bytes <= 64 KiB
+
 template <int N>
 struct StageSolve {
   static hipError_t run(const HeviShapeDev& sh, double lambda, int fp32,
@@ -264,6 +287,12 @@ struct StageSolve {
         hipLaunchKernelGGL((k_stage_solve<N, double, true>), g, b, 0, st, sh, lambda, ops,
                            (const double*)Ub, (const double*)Lb, piv, ws, E, Q, Qi, 0, rel_target,
                            full_sweeps, info);
+      return hipGetLastError();
+    }
+    if (!fp32 && CW == 1 && sh.nz <= kFusedMaxNz) {
+      hipLaunchKernelGGL(k_stage_fused<N>, g, b, (size_t)sh.nz * T * sizeof(double), st, sh,
+                         lambda, ops, (const double*)Ub, (const double*)Lb, piv, ws, E, Q, Qi,
+                         info);
       return hipGetLastError();
     }
     hipLaunchKernelGGL(k_stage_rhs<N>, g, b4, 0, st, sh, lambda, ops, ws, E, Q, Qi);
