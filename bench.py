@@ -604,7 +604,7 @@ def main():
         "paths": res_paths,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
-                     "kernel": "hevi_stage_solve (k_stage_rhs + k_stage_bsolve + k_stage_update)",
+                     "kernel": "hevi_stage_solve (k_stage_fused; FP32 factors: k_stage_rhs + k_stage_bsolve + k_stage_update)",
                      "algorithmic_bytes_per_column": per_col,
                      "measured_copy_GBps": copy_gbs,
                      "launch_columns": ncols,
