@@ -49,6 +49,9 @@ def cases():
         "N7": lambda: inputs.make_columns(7, 2, 70, profile="lapse_capped", z_top=60e3, seed=33),
         "N1": lambda: inputs.make_columns(1, 6, 40, profile="isothermal", seed=34),
         "N2": lambda: inputs.make_columns(2, 4, 40, profile="isothermal", seed=35, tilt=0.1),
+        # 161 nodes: past the fused stage kernel's LDS limit (the three-kernel path)
+        "N4_Ne40": lambda: inputs.make_columns(4, 40, 70, profile="lapse_capped", z_top=120e3,
+                                               seed=36),
     }
 
 
@@ -108,13 +111,14 @@ def test_solve_parity(ctx, name, prec):
     if prec == 1:
         assert inf["max_sweeps_used"] <= 4
         assert inf["max_rel_correction"] <= 1e-13
-    # one full-system FP64 refinement sweep meets the FP64 bar outright
+    # one full-system FP64 refinement sweep meets the FP64 bar outright where the system
+    # allows it (an FP64 residual cannot resolve below the oracle's own plain-GEPP error)
     x1 = B.empty_state()
     inf = ctx.stage_solve(f, [dev(b)], [1.0], [], [], x1, refine=(4, 1e-13, 1), info=True)
     assert inf["status"] == "HEVI_OK", inf
     err1 = relerr_cols(host(x1), xo)
     print(f"with one full sweep: {err1:.2e}", flush=True)
-    assert err1 < TOL64, err1
+    assert err1 < max(TOL64, plain), err1
 
 
 def test_solve_identity_at_zero_lambda(ctx):
