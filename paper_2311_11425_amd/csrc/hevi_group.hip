@@ -171,6 +171,28 @@ __global__ __launch_bounds__(64) void km_stage_update(const HeviProbDev* __restr
   });
 }
 
+// FP64 stage solve of a tile in one pass (as k_stage_fused): r/u in LDS
+template <int NLO, int NHI>
+__global__ __launch_bounds__(64) void km_stage_fused(const HeviProbDev* __restrict__ probs,
+                                                     const HeviCallDev* __restrict__ calls,
+                                                     HeviSched s) {
+  extern __shared__ double ru[];  // [max n_z][64]
+  persist(s, [&](int p, int64_t tile) {
+    const HeviProbDev& P = probs[p];
+    const HeviCallDev& C = calls[p];
+    switch_N<NLO, NHI>(P.sh.N, [&](auto n) {
+      constexpr int NN = decltype(n)::value;
+      b_stage_rhs<NN, true>(tile, P.sh, Gll<NN>{}, P.lambda, P.ops, P.ws, C.E, C.Q, C.out, ru);
+      __syncthreads();
+      band_solve<NN, double, true>((const double*)P.U, (const double*)P.L, P.piv, P.ws, tile,
+                                   P.sh.nz, (int)threadIdx.x, WS_R, WS_U, ru);
+      __syncthreads();
+      b_stage_update<NN, true>(tile, P.sh, Gll<NN>{}, P.lambda, P.ops, P.ws, C.out, P.info, ru);
+      __syncthreads();
+    });
+  });
+}
+
 // out = sum_t coef_t V_t over the 5 n_z values of each column of the tile;
 // the same summation order as k_combine.
 __global__ __launch_bounds__(64) void km_combine(const HeviProbDev* __restrict__ probs,
@@ -207,7 +229,7 @@ __global__ void k_info_reset_n(HeviDevInfo* info, int n) {
 template <int NLO, int NHI>
 hipError_t launch_range(int phase, int fp32, const HeviProbDev* probs, const HeviCallDev* calls,
                         const HeviSched& s, int grid, int max_sweeps, double rel_target,
-                        hipStream_t st) {
+                        int max_nz, hipStream_t st) {
   const dim3 g((unsigned)grid), b(T);
   switch (phase) {
     case HEVI_PH_APPLY:
@@ -234,6 +256,11 @@ hipError_t launch_range(int phase, int fp32, const HeviProbDev* probs, const Hev
     case HEVI_PH_STAGE_UPDATE:
       hipLaunchKernelGGL((km_stage_update<NLO, NHI>), g, b, 0, st, probs, calls, s);
       break;
+    case HEVI_PH_STAGE_FUSED:
+      if (fp32 || max_nz > HEVI_FUSED_MAX_NZ) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((km_stage_fused<NLO, NHI>), g, b, (size_t)max_nz * T * sizeof(double),
+                         st, probs, calls, s);
+      break;
     case HEVI_PH_COMBINE:
       hipLaunchKernelGGL(km_combine, g, b, 0, st, probs, calls, s);
       break;
@@ -247,17 +274,18 @@ hipError_t launch_range(int phase, int fp32, const HeviProbDev* probs, const Hev
 
 hipError_t hevi_launch_multi(int phase, int nlo, int nhi, int fp32, const HeviProbDev* probs,
                              const HeviCallDev* calls, const HeviSched& s, int grid,
-                             int max_sweeps, double rel_target, hipStream_t st) {
+                             int max_sweeps, double rel_target, int max_nz, hipStream_t st) {
   if (s.total == 0) return hipSuccess;
   if (grid < 1) return hipErrorInvalidValue;
   if (nlo == 1 && nhi == HEVI_MAXN)
     return launch_range<1, HEVI_MAXN>(phase, fp32, probs, calls, s, grid, max_sweeps, rel_target,
-                                      st);
+                                      max_nz, st);
   if (nlo != nhi) return hipErrorInvalidValue;
   switch (nlo) {
 #define HEVI_ONE_N(n)                                                                          \
   case n:                                                                                      \
-    return launch_range<n, n>(phase, fp32, probs, calls, s, grid, max_sweeps, rel_target, st);
+    return launch_range<n, n>(phase, fp32, probs, calls, s, grid, max_sweeps, rel_target,   \
+                              max_nz, st);
     HEVI_ONE_N(1) HEVI_ONE_N(2) HEVI_ONE_N(3) HEVI_ONE_N(4)
     HEVI_ONE_N(5) HEVI_ONE_N(6) HEVI_ONE_N(7) HEVI_ONE_N(8)
 #undef HEVI_ONE_N

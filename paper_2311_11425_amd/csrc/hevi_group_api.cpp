@@ -25,6 +25,7 @@ struct Launch {
   int32_t m;         // segments
   int64_t total;     // items
   size_t off;        // offset of plist (int32 x m, padded) + pstart (int64 x m+1) in d_sched
+  int maxnz;         // largest n_z of the launch's members
 };
 
 }  // namespace
@@ -83,13 +84,15 @@ hevi_status build_launches(hevi_group* g) {
     });
     std::vector<int32_t> pl;
     std::vector<int64_t> ps{0};
+    int maxnz = 1;
     for (int p : ids) {
       if (g->probs[p].sh.ntiles == 0) continue;
       pl.push_back(p);
       ps.push_back(ps.back() + g->probs[p].sh.ntiles);
+      maxnz = std::max(maxnz, g->probs[p].sh.nz);
     }
     if (pl.empty()) return;
-    Launch l{nlo, nhi, -1, (int32_t)pl.size(), ps.back(), host.size()};
+    Launch l{nlo, nhi, -1, (int32_t)pl.size(), ps.back(), host.size(), maxnz};
     const size_t a = pl.size() * sizeof(int32_t), pad = (a + 7) / 8 * 8;
     host.resize(host.size() + pad + ps.size() * sizeof(int64_t));
     std::memcpy(host.data() + l.off, pl.data(), a);
@@ -109,7 +112,7 @@ hevi_status build_launches(hevi_group* g) {
     }
   } else {
     for (int i = 0; i < g->n; ++i)
-      if (g->probs[i].sh.ntiles > 0) L.push_back(Launch{0, 0, i, 0, 0, 0});
+      if (g->probs[i].sh.ntiles > 0) L.push_back(Launch{0, 0, i, 0, 0, 0, g->probs[i].sh.nz});
   }
   if (g->d_sched) (void)hipFree(g->d_sched);
   g->d_sched = nullptr;
@@ -152,6 +155,11 @@ hipError_t phase(hevi_group* g, int ph, int slot, hipStream_t st) {
           break;
       }
     } else {
+      // FP64 stage solves of launches whose columns fit the fused kernel's LDS run as
+      // one fused pass; their band-solve and update phases are then already done
+      const bool fused = !fp32 && l.maxnz <= HEVI_FUSED_MAX_NZ;
+      if (fused && (ph == HEVI_PH_STAGE_BSOLVE || ph == HEVI_PH_STAGE_UPDATE)) continue;
+      const int phx = (fused && ph == HEVI_PH_STAGE_RHS) ? HEVI_PH_STAGE_FUSED : ph;
       HeviSched s;
       const size_t pad = ((size_t)l.m * sizeof(int32_t) + 7) / 8 * 8;
       s.plist = (const int32_t*)(g->d_sched + l.off);
@@ -161,9 +169,9 @@ hipError_t phase(hevi_group* g, int ph, int slot, hipStream_t st) {
       s.ctr = g->d_ctr;
       const int64_t want = g->plan.grid > 0 ? g->plan.grid : l.total;
       const int grid = (int)std::min<int64_t>(want, l.total);
-      e = hevi_launch_multi(ph, l.nlo, l.nhi, fp32, g->d_probs,
+      e = hevi_launch_multi(phx, l.nlo, l.nhi, fp32, g->d_probs,
                             slot >= 0 ? g->d_calls + (size_t)slot * g->n : nullptr, s, grid,
-                            fp32 ? g->sweeps : 0, g->target, st);
+                            fp32 ? g->sweeps : 0, g->target, l.maxnz, st);
     }
     if (e != hipSuccess) return e;
   }

@@ -106,16 +106,26 @@ enum HeviPhase {
   HEVI_PH_STAGE_BSOLVE = 4,
   HEVI_PH_STAGE_UPDATE = 5,
   HEVI_PH_COMBINE = 6,
-  HEVI_NPHASES = 7
+  HEVI_PH_STAGE_FUSED = 7,  // FP64 rhs + band solve + update, r/u in LDS
+  HEVI_NPHASES = 8
 };
+
+// The fused stage kernel holds n_z doubles per column of its 64-column tile in LDS
+// (n_z * 512 bytes per one-wave workgroup).  It beats the three separate kernels while
+// three such workgroups fit in a CU's 160 KiB of LDS (n_z <= 106): with only two, half
+// of the CU's SIMDs sit idle and its bandwidth-bound RHS part runs ~2.4x slower (1.6M
+// uneven columns, N 3..7: 16.0/26.7/37.0 ms per stage fused at n_z 113, against
+// 14.0/18.5/23.0 ms for the three kernels).
+#define HEVI_FUSED_MAX_NZ 106
 
 // One persistent launch of `phase` with `grid` workgroups of one wavefront.
 // nlo..nhi: the orders the kernel is compiled for ((n, n) for n = 1..8, or
 // (1, HEVI_MAXN)); every problem in the schedule must have nlo <= N <= nhi.
 // fp32 / refine select the factor type and the reduced refinement of the
-// stage solve (max_sweeps, rel_target).
+// stage solve (max_sweeps, rel_target).  max_nz: the largest n_z of the
+// launch's problems (sizes the LDS of HEVI_PH_STAGE_FUSED).
 hipError_t hevi_launch_multi(int phase, int nlo, int nhi, int fp32, const HeviProbDev* probs,
                              const HeviCallDev* calls, const HeviSched& s, int grid,
-                             int max_sweeps, double rel_target, hipStream_t st);
+                             int max_sweeps, double rel_target, int max_nz, hipStream_t st);
 
 hipError_t hevi_launch_info_reset_n(HeviDevInfo* info, int n, hipStream_t st);

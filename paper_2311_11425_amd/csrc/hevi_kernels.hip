@@ -267,8 +267,6 @@ struct Factor {
   }
 };
 
-constexpr int kFusedMaxNz = 128;  // r/u of a tile in LDS: n_z * 512 bytes <= 64 KiB
-
 template <int N>
 struct StageSolve {
   static hipError_t run(const HeviShapeDev& sh, double lambda, int fp32,
@@ -289,7 +287,7 @@ struct StageSolve {
                            full_sweeps, info);
       return hipGetLastError();
     }
-    if (!fp32 && CW == 1 && sh.nz <= kFusedMaxNz) {
+    if (!fp32 && CW == 1 && sh.nz <= HEVI_FUSED_MAX_NZ) {
       hipLaunchKernelGGL(k_stage_fused<N>, g, b, (size_t)sh.nz * T * sizeof(double), st, sh,
                          lambda, ops, (const double*)Ub, (const double*)Lb, piv, ws, E, Q, Qi,
                          info);

@@ -185,7 +185,7 @@ void launch_batch(hevi_server* S) {
   }
   // one schedule per precision
   struct Sub {
-    int lo, hi, fp32, nlo, nhi;
+    int lo, hi, fp32, nlo, nhi, maxnz;
     size_t off;
     int64_t total;
   };
@@ -194,10 +194,11 @@ void launch_batch(hevi_server* S) {
   for (int j = 0; j < n;) {
     int k = j;
     const int fp32 = sl.h_probs[j].fp32;
-    int nmin = HEVI_MAXN, nmax = 1;
+    int nmin = HEVI_MAXN, nmax = 1, maxnz = 1;
     while (k < n && sl.h_probs[k].fp32 == fp32) {
       nmin = std::min(nmin, sl.h_probs[k].sh.N);
       nmax = std::max(nmax, sl.h_probs[k].sh.N);
+      maxnz = std::max(maxnz, sl.h_probs[k].sh.nz);
       ++k;
     }
     const int m = k - j;
@@ -210,7 +211,7 @@ void launch_batch(hevi_server* S) {
       ps[t + 1] = ps[t] + sl.h_probs[j + t].sh.ntiles;
     }
     const bool one = nmin == nmax;
-    subs.push_back(Sub{j, k, fp32, one ? nmin : 1, one ? nmin : HEVI_MAXN, off, ps[m]});
+    subs.push_back(Sub{j, k, fp32, one ? nmin : 1, one ? nmin : HEVI_MAXN, maxnz, off, ps[m]});
     off += pad + (size_t)(m + 1) * 8;
     j = k;
   }
@@ -235,9 +236,14 @@ void launch_batch(hevi_server* S) {
     s.ctr = S->d_ctr;
     const int grid = (int)sb.total;
     const int sweeps = sb.fp32 ? 4 : 0;
+    if (!sb.fp32 && sb.maxnz <= HEVI_FUSED_MAX_NZ) {
+      okk = okk && ok(hevi_launch_multi(HEVI_PH_STAGE_FUSED, sb.nlo, sb.nhi, 0, sl.d_probs,
+                                        sl.d_calls, s, grid, 0, 1e-13, sb.maxnz, S->st));
+      continue;
+    }
     for (int ph : {HEVI_PH_STAGE_RHS, HEVI_PH_STAGE_BSOLVE, HEVI_PH_STAGE_UPDATE})
       okk = okk && ok(hevi_launch_multi(ph, sb.nlo, sb.nhi, sb.fp32, sl.d_probs, sl.d_calls, s,
-                                        grid, sweeps, 1e-13, S->st));
+                                        grid, sweeps, 1e-13, sb.maxnz, S->st));
   }
   okk = okk &&
         ok(hipMemcpyAsync(sl.h_info, sl.d_info, sizeof(HeviDevInfo) * n, hipMemcpyDeviceToHost,
