@@ -327,6 +327,53 @@ __device__ __forceinline__ void b_apply(int64_t tile_, HeviShapeDev sh, Gll<N> t
 // j+1..j+2N; pivot offset p in 0..2N (row j was swapped with row j+p).
 // sbuf holds, during assembly, row r of -lambda^2 K at band offset c - r + 2N.
 
+// Row a (node r = eN + a) of element e's part of K as band offsets o = column - r +
+// 2N.  The pressure gradient of DTh u contributes
+//   sum_i P_ai DTh_iq,  P_ai = -M^-1_r w_a D_ai (J c_Theta)_i grad(zeta)_r . grad(zeta)_i,
+// where DTh row i (node eN + i) is -M^-1_i C_iq (J theta0)_q over the nodes
+// q = (e-1)N .. (e+2)N: C = w_i D_i(q-eN) for the element's own nodes, plus the
+// neighbours' terms at the shared end nodes (element e-1's row N into node eN when
+// `left`, element e+1's row 0 into node (e+1)N when `right`).  Every DTh entry is
+// proportional to (J theta0)_q, so the row is acc_q = (J theta0)_q sum_i Pm_i C_iq
+// with Pm_i = -P_ai M^-1_i.  Gravity adds -Phi'_r |grad zeta_r|^2 M^-1_r times Drho
+// row a.  Jth[q] is J theta0 at node (e-1)N + q (zero outside the column); mi, gx,
+// gy, gz, jc, jn and ph are MINV, GX, GY, GZ, JCT, J and PHI at nodes eN .. eN+N.
+template <int N>
+__device__ __forceinline__ void k_row(Gll<N> tab, int a, bool left, bool right,
+                                      const double (&Jth)[3 * N + 1], const double (&mi)[N + 1],
+                                      const double (&gx)[N + 1], const double (&gy)[N + 1],
+                                      const double (&gz)[N + 1], const double (&jc)[N + 1],
+                                      const double (&jn)[N + 1], const double (&ph)[N + 1],
+                                      double (&acc)[4 * N + 1]) {
+  // every product and sum rounded on its own: the assembly kernel and the fused
+  // factorisation then produce the same bits whatever the surrounding code
+#pragma clang fp contract(off)
+  constexpr int B = 2 * N, W = 4 * N + 1, NC = 3 * N + 1;
+  const double mr = mi[a];
+  double Pm[N + 1];
+#pragma unroll
+  for (int i = 0; i <= N; ++i) {
+    const double dot = gx[a] * gx[i] + gy[a] * gy[i] + gz[a] * gz[i];
+    Pm[i] = mr * tab.w[a] * tab.D[a * (N + 1) + i] * jc[i] * dot * mi[i];
+  }
+#pragma unroll
+  for (int o = 0; o < W; ++o) acc[o] = 0.0;
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    double sq = 0.0;
+    if (q >= N && q <= B) {
+#pragma unroll
+      for (int i = 0; i <= N; ++i) sq += Pm[i] * (tab.w[i] * tab.D[i * (N + 1) + q - N]);
+    }
+    if (q <= N && left) sq += Pm[0] * (tab.w[N] * tab.D[N * (N + 1) + q]);
+    if (q >= B && right) sq += Pm[N] * (tab.w[0] * tab.D[q - B]);
+    acc[q + N - a] = sq * Jth[q];
+  }
+  const double gr = -ph[a] * (gx[a] * gx[a] + gy[a] * gy[a] + gz[a] * gz[a]) * mr;
+#pragma unroll
+  for (int i2 = 0; i2 <= N; ++i2) acc[B + i2 - a] += gr * tab.w[i2] * tab.D[i2 * (N + 1) + a] * jn[i2];
+}
+
 // Assembly of -lambda^2 K (element-chunked, see Chunk): row r of the band is
 // written once, by the wavefront owning node r.
 constexpr int CWF = 1;  // chunk wavefronts of the assembly kernel
@@ -336,7 +383,7 @@ __device__ __forceinline__ void b_factor_assemble(int64_t tile_, HeviShapeDev sh
                                                   Gll<N> tab, double lambda,
                                                   const double* __restrict__ ops,
                                                   double* __restrict__ sbuf) {
-  constexpr int B = 2 * N;          // half-bandwidth of S (kl = ku)
+#pragma clang fp contract(off)
   constexpr int W = 4 * N + 1;      // S band width = U row width kl + ku + 1
   constexpr int NC = 3 * N + 1;     // columns touched by DTh rows of one element
   const int Ne = sh.Ne, nz = sh.nz;
@@ -350,9 +397,7 @@ __device__ __forceinline__ void b_factor_assemble(int64_t tile_, HeviShapeDev sh
 #pragma unroll
   for (int o = 0; o < W; ++o) carry[o] = 0.0;
   for (int e = max(ch.e0 - 1, 0); e < ch.e1; ++e) {
-    // DTh rows of the element's nodes over columns (e-1)N .. (e+2)N
-    double DT[N + 1][NC];
-    double Jth[NC];
+    double Jth[NC], mi[N + 1], gx[N + 1], gy[N + 1], gz[N + 1], jc[N + 1], jn[N + 1], ph[N + 1];
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
       const int k = (e - 1) * N + q;
@@ -361,50 +406,16 @@ __device__ __forceinline__ void b_factor_assemble(int64_t tile_, HeviShapeDev sh
     }
 #pragma unroll
     for (int i = 0; i <= N; ++i) {
-#pragma unroll
-      for (int q = 0; q < NC; ++q) DT[i][q] = 0.0;
-#pragma unroll
-      for (int i2 = 0; i2 <= N; ++i2)
-        DT[i][N + i2] += tab.w[i] * tab.D[i * (N + 1) + i2] * Jth[N + i2];
-      if (i == 0 && e > 0) {
-#pragma unroll
-        for (int i2 = 0; i2 <= N; ++i2) DT[0][i2] += tab.w[N] * tab.D[N * (N + 1) + i2] * Jth[i2];
-      }
-      if (i == N && e < Ne - 1) {
-#pragma unroll
-        for (int i2 = 0; i2 <= N; ++i2)
-          DT[N][2 * N + i2] += tab.w[0] * tab.D[0 * (N + 1) + i2] * Jth[2 * N + i2];
-      }
-      const double mi = op(e * N + i, OP_MINV);
-#pragma unroll
-      for (int q = 0; q < NC; ++q) DT[i][q] *= -mi;
-    }
-    double gxj[N + 1], gyj[N + 1], gzj[N + 1], jct[N + 1], jj[N + 1];
-#pragma unroll
-    for (int i = 0; i <= N; ++i) {
       const int k = e * N + i;
-      gxj[i] = op(k, OP_GX); gyj[i] = op(k, OP_GY); gzj[i] = op(k, OP_GZ);
-      jct[i] = op(k, OP_JCT); jj[i] = op(k, OP_J);
+      mi[i] = op(k, OP_MINV); gx[i] = op(k, OP_GX); gy[i] = op(k, OP_GY); gz[i] = op(k, OP_GZ);
+      jc[i] = op(k, OP_JCT); jn[i] = op(k, OP_J); ph[i] = op(k, OP_PHI);
     }
 #pragma unroll
     for (int a = 0; a <= N; ++a) {
       if (e < ch.e0 && a < N) continue;  // only the boundary row of the recomputed element
       const int r = e * N + a;
-      const double mr = op(r, OP_MINV), ph = op(r, OP_PHI);
       double acc[W];
-#pragma unroll
-      for (int o = 0; o < W; ++o) acc[o] = 0.0;
-#pragma unroll
-      for (int i = 0; i <= N; ++i) {
-        const double dot = gxj[a] * gxj[i] + gyj[a] * gyj[i] + gzj[a] * gzj[i];
-        const double P = -mr * tab.w[a] * tab.D[a * (N + 1) + i] * jct[i] * dot;
-#pragma unroll
-        for (int q = 0; q < NC; ++q) acc[q + N - a] += P * DT[i][q];
-      }
-      const double gr = -ph * (gxj[a] * gxj[a] + gyj[a] * gyj[a] + gzj[a] * gzj[a]) * mr;
-#pragma unroll
-      for (int i2 = 0; i2 <= N; ++i2)
-        acc[B + i2 - a] += gr * tab.w[i2] * tab.D[i2 * (N + 1) + a] * jj[i2];
+      k_row<N>(tab, a, e > 0, e < Ne - 1, Jth, mi, gx, gy, gz, jc, jn, ph, acc);
       if (a == 0) {
 #pragma unroll
         for (int o = 0; o < W; ++o) acc[o] += carry[o];
@@ -475,6 +486,70 @@ __device__ __forceinline__ double from_next(double v) {
 // part `part` of a 64-column tile.
 constexpr int kLuLanes = 2;  // lanes per column of the register-window LU
 
+// One step of the split-window LU: elimination step j (if j >= 0), then the
+// window moves one row down and one column right.  Its bottom row is left for
+// the caller to fill with row j + 2N + 1.
+template <int N, typename FT, int LPC>
+__device__ __forceinline__ void split_step(double (&Wn)[2 * N + 1][(4 * N + LPC) / LPC], int j,
+                                           int nz, int h, int s0, int64_t tile, int lane,
+                                           FT* Ub, FT* __restrict__ Lb,
+                                           uint8_t* __restrict__ piv, bool& singular) {
+  constexpr int B = 2 * N, W = 4 * N + 1, H = (W + LPC - 1) / LPC;
+  if (j >= 0) {  // elimination step j (rows 0..2N are only shifted in)
+    // pivot search on window column 0 (first lane of the group)
+    int p = 0;
+    double best = fabs(Wn[0][0]);
+#pragma unroll
+    for (int t = 1; t <= B; ++t) {
+      const double v = fabs(Wn[t][0]);
+      if (j + t < nz && v > best) { best = v; p = t; }
+    }
+    if (h == 0 && !(best > 0.0)) { singular = true; Wn[0][0] = 1.0; p = 0; }
+    p = from_first<LPC>(p);
+    if (__ballot(p != 0) != 0) {
+#pragma unroll
+      for (int m = 0; m < H; ++m) {
+        const double v0 = Wn[0][m];
+        double vp = v0;
+#pragma unroll
+        for (int t = 1; t <= B; ++t) vp = (p == t) ? Wn[t][m] : vp;
+        Wn[0][m] = vp;
+#pragma unroll
+        for (int t = 1; t <= B; ++t) Wn[t][m] = (p == t) ? v0 : Wn[t][m];
+      }
+    }
+    FT* urow = Ub + tix(tile, nz, j, W, 0, lane);
+#pragma unroll
+    for (int m = 0; m < H; ++m)
+      if (s0 + m < W) stnt(urow + (s0 + m) * T, (FT)Wn[0][m]);
+    const double inv = 1.0 / Wn[0][0];
+    double l[B + 1];
+#pragma unroll
+    for (int t = 1; t <= B; ++t) l[t] = from_first<LPC>(Wn[t][0] * inv);
+    if (h == 0) {
+      piv[tix(tile, nz, j, 1, 0, lane)] = (uint8_t)p;
+      FT* lrow = Lb + tix(tile, nz, j, B, 0, lane);
+#pragma unroll
+      for (int t = 1; t <= B; ++t) stnt(lrow + (t - 1) * T, (FT)l[t]);
+    }
+#pragma unroll
+    for (int t = 1; t <= B; ++t)
+#pragma unroll
+      for (int m = 0; m < H; ++m) Wn[t][m] -= l[t] * Wn[0][m];
+  }
+  // move the window one row down and one column right: each lane's last
+  // column comes from the next lane's first, the group's last lane's is zero
+  double cross[B];
+#pragma unroll
+  for (int t = 0; t < B; ++t) cross[t] = from_next<LPC>(Wn[t + 1][0]);
+#pragma unroll
+  for (int t = 0; t < B; ++t) {
+#pragma unroll
+    for (int m = 0; m < H - 1; ++m) Wn[t][m] = Wn[t + 1][m + 1];
+    Wn[t][H - 1] = h < LPC - 1 ? cross[t] : 0.0;
+  }
+}
+
 template <int N, typename FT, int LPC>
 __device__ __forceinline__ void b_factor_lu_split(int64_t tile, int part, HeviShapeDev sh,
                                                   const double* sbuf, FT* Ub,
@@ -507,59 +582,7 @@ __device__ __forceinline__ void b_factor_lu_split(int64_t tile, int part, HeviSh
     for (int d = 0; d < PFL; ++d) {
       const int j = j0 + d;
       if (j < nz) {
-        if (j >= 0) {  // elimination step j (rows 0..2N are only shifted in)
-          // pivot search on window column 0 (first lane of the group)
-          int p = 0;
-          double best = fabs(Wn[0][0]);
-#pragma unroll
-          for (int t = 1; t <= B; ++t) {
-            const double v = fabs(Wn[t][0]);
-            if (j + t < nz && v > best) { best = v; p = t; }
-          }
-          if (h == 0 && !(best > 0.0)) { singular = true; Wn[0][0] = 1.0; p = 0; }
-          p = from_first<LPC>(p);
-          if (__ballot(p != 0) != 0) {
-#pragma unroll
-            for (int m = 0; m < H; ++m) {
-              const double v0 = Wn[0][m];
-              double vp = v0;
-#pragma unroll
-              for (int t = 1; t <= B; ++t) vp = (p == t) ? Wn[t][m] : vp;
-              Wn[0][m] = vp;
-#pragma unroll
-              for (int t = 1; t <= B; ++t) Wn[t][m] = (p == t) ? v0 : Wn[t][m];
-            }
-          }
-          FT* urow = Ub + tix(tile, nz, j, W, 0, lane);
-#pragma unroll
-          for (int m = 0; m < H; ++m)
-            if (s0 + m < W) stnt(urow + (s0 + m) * T, (FT)Wn[0][m]);
-          const double inv = 1.0 / Wn[0][0];
-          double l[B + 1];
-#pragma unroll
-          for (int t = 1; t <= B; ++t) l[t] = from_first<LPC>(Wn[t][0] * inv);
-          if (h == 0) {
-            piv[tix(tile, nz, j, 1, 0, lane)] = (uint8_t)p;
-            FT* lrow = Lb + tix(tile, nz, j, B, 0, lane);
-#pragma unroll
-            for (int t = 1; t <= B; ++t) stnt(lrow + (t - 1) * T, (FT)l[t]);
-          }
-#pragma unroll
-          for (int t = 1; t <= B; ++t)
-#pragma unroll
-            for (int m = 0; m < H; ++m) Wn[t][m] -= l[t] * Wn[0][m];
-        }
-        // move the window one row down and one column right: each lane's last
-        // column comes from the next lane's first, the group's last lane's is zero
-        double cross[B];
-#pragma unroll
-        for (int t = 0; t < B; ++t) cross[t] = from_next<LPC>(Wn[t + 1][0]);
-#pragma unroll
-        for (int t = 0; t < B; ++t) {
-#pragma unroll
-          for (int m = 0; m < H - 1; ++m) Wn[t][m] = Wn[t + 1][m + 1];
-          Wn[t][H - 1] = h < LPC - 1 ? cross[t] : 0.0;
-        }
+        split_step<N, FT, LPC>(Wn, j, nz, h, s0, tile, lane, Ub, Lb, piv, singular);
         // new bottom row j + 2N + 1 from the ring; refill the slot
         const int rn = j + B + 1;
 #pragma unroll
@@ -571,6 +594,127 @@ __device__ __forceinline__ void b_factor_lu_split(int64_t tile, int part, HeviSh
           ring[d][m] = ldn(sbuf + tix(tile, nz, rf, W, min(s0 + m, W - 1), lane));
       }
     }
+  }
+  if (singular && valid) flag(info, 5 /*HEVI_E_SINGULAR*/, c);
+}
+
+// Assembly and split-window LU in one pass (N <= 4): the wavefront computes each
+// element's rows of S itself (k_row, as b_factor_assemble does), keeps
+// this lane's part of them in LDS until they enter the window, and loads the
+// operator fields of the next element while they do.  S never goes through
+// memory: per column the pass reads the compact operator and writes the factors.
+// lds holds fused_lds_doubles<N>(LPC) doubles: (N + 1) rows of H per lane.
+template <int N>
+constexpr int fused_lds_doubles(int lpc) {
+  return (N + 1) * ((4 * N + lpc) / lpc) * 64;
+}
+
+template <int N, typename FT, int LPC>
+__device__ __forceinline__ void b_factor_fused_split(int64_t tile, int part, HeviShapeDev sh,
+                                                     Gll<N> tab, double lambda,
+                                                     const double* __restrict__ ops,
+                                                     FT* __restrict__ Ub, FT* __restrict__ Lb,
+                                                     uint8_t* __restrict__ piv,
+                                                     HeviDevInfo* info, double* lds) {
+  constexpr int B = 2 * N, W = 4 * N + 1, H = (W + LPC - 1) / LPC, NC = 3 * N + 1;
+  const int h = threadIdx.x % LPC;
+  const int lane = part * (T / LPC) + (threadIdx.x / LPC);
+  const int64_t c = tile * T + lane;
+  const bool valid = c < sh.ncols;
+  const int nz = sh.nz, Ne = sh.Ne;
+  const int s0 = h * H;
+  const OpsView op{ops, tile, nz, lane};
+  const double l2 = lambda * lambda;
+  double* slot = lds + threadIdx.x;  // row a, window column m of this lane: slot[(a * H + m) * T]
+  double Wn[B + 1][H];
+#pragma unroll
+  for (int t = 0; t <= B; ++t)
+#pragma unroll
+    for (int m = 0; m < H; ++m) Wn[t][m] = 0.0;
+  // operator fields of element e: J theta0 at nodes (e-1)N .. (e+2)N (zero outside
+  // the column), the others at nodes eN .. eN+N
+  auto jth_at = [&](int k) {
+    const double v = op(min(max(k, 0), nz - 1), OP_JTH);
+    return (k >= 0 && k < nz) ? v : 0.0;
+  };
+  double jth[NC], mi[N + 1], gx[N + 1], gy[N + 1], gz[N + 1], jc[N + 1], jn[N + 1], ph[N + 1];
+#pragma unroll
+  for (int q = 0; q < NC; ++q) jth[q] = jth_at(q - N);
+#pragma unroll
+  for (int i = 0; i <= N; ++i) {
+    const int k = min(i, nz - 1);
+    mi[i] = op(k, OP_MINV); gx[i] = op(k, OP_GX); gy[i] = op(k, OP_GY); gz[i] = op(k, OP_GZ);
+    jc[i] = op(k, OP_JCT); jn[i] = op(k, OP_J); ph[i] = op(k, OP_PHI);
+  }
+  double carry[H];  // this lane's part of row N of the previous element
+#pragma unroll
+  for (int m = 0; m < H; ++m) carry[m] = 0.0;
+  bool singular = false;
+  int j = -(B + 1);  // the step whose window takes in the next row
+  for (int e = 0; e < Ne; ++e) {
+    // rows eN .. eN+N-1 of S (and the top row after the last element) into LDS,
+    // rounded as the assembly kernel and the LU's s_fix round them
+#pragma unroll
+    for (int a = 0; a <= N; ++a) {
+#pragma clang fp contract(off)
+      double acc[W];
+      k_row<N>(tab, a, e > 0, e < Ne - 1, jth, mi, gx, gy, gz, jc, jn, ph, acc);
+      double x[H];
+#pragma unroll
+      for (int m = 0; m < H; ++m) {
+        double v = acc[m];
+#pragma unroll
+        for (int hh = 1; hh < LPC; ++hh)
+          if (h == hh) v = hh * H + m < W ? acc[hh * H + m] : 0.0;
+        x[m] = a == 0 ? v + carry[m] : v;
+      }
+      if (a == N && e < Ne - 1) {
+#pragma unroll
+        for (int m = 0; m < H; ++m) carry[m] = x[m];
+      } else {
+        const int r = e * N + a;
+#pragma unroll
+        for (int m = 0; m < H; ++m)
+          slot[(a * H + m) * T] = s0 + m < W ? s_fix<N>(r, nz, s0 + m, -l2 * x[m]) : 0.0;
+      }
+    }
+    // the next element's new operator fields, in flight while the rows enter
+    double pj[N], pmi[N], pgx[N], pgy[N], pgz[N], pjc[N], pjn[N], pph[N];
+#pragma unroll
+    for (int t = 0; t < N; ++t) {
+      pj[t] = jth_at((e + 2) * N + 1 + t);
+      const int k = min((e + 1) * N + 1 + t, nz - 1);
+      pmi[t] = op(k, OP_MINV); pgx[t] = op(k, OP_GX); pgy[t] = op(k, OP_GY);
+      pgz[t] = op(k, OP_GZ); pjc[t] = op(k, OP_JCT); pjn[t] = op(k, OP_J); pph[t] = op(k, OP_PHI);
+    }
+    const int na = e == Ne - 1 ? N + 1 : N;
+#pragma unroll
+    for (int a = 0; a <= N; ++a) {
+      if (a < na) {
+        split_step<N, FT, LPC>(Wn, j, nz, h, s0, tile, lane, Ub, Lb, piv, singular);
+#pragma unroll
+        for (int m = 0; m < H; ++m) Wn[B][m] = slot[(a * H + m) * T];
+        ++j;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q <= B; ++q) jth[q] = jth[q + N];
+#pragma unroll
+    for (int t = 0; t < N; ++t) jth[B + 1 + t] = pj[t];
+    mi[0] = mi[N]; gx[0] = gx[N]; gy[0] = gy[N]; gz[0] = gz[N];
+    jc[0] = jc[N]; jn[0] = jn[N]; ph[0] = ph[N];
+#pragma unroll
+    for (int t = 0; t < N; ++t) {
+      mi[1 + t] = pmi[t]; gx[1 + t] = pgx[t]; gy[1 + t] = pgy[t]; gz[1 + t] = pgz[t];
+      jc[1 + t] = pjc[t]; jn[1 + t] = pjn[t]; ph[1 + t] = pph[t];
+    }
+  }
+  // rows past the top are zero
+  while (j < nz) {
+    split_step<N, FT, LPC>(Wn, j, nz, h, s0, tile, lane, Ub, Lb, piv, singular);
+#pragma unroll
+    for (int m = 0; m < H; ++m) Wn[B][m] = 0.0;
+    ++j;
   }
   if (singular && valid) flag(info, 5 /*HEVI_E_SINGULAR*/, c);
 }

@@ -102,6 +102,18 @@ __global__ __launch_bounds__(64) void k_factor_lu_split(HeviShapeDev sh, const d
 }
 
 template <int N, typename FT>
+__global__ __launch_bounds__(64) void k_factor_fused(HeviShapeDev sh, double lambda,
+                                                     const double* __restrict__ ops,
+                                                     FT* __restrict__ Ub, FT* __restrict__ Lb,
+                                                     uint8_t* __restrict__ piv,
+                                                     HeviDevInfo* info) {
+  __shared__ double lds[fused_lds_doubles<N>(kLuLanes)];
+  b_factor_fused_split<N, FT, kLuLanes>((int64_t)(blockIdx.x / kLuLanes),
+                                        (int)(blockIdx.x % kLuLanes), sh, Gll<N>{}, lambda, ops,
+                                        Ub, Lb, piv, info, lds);
+}
+
+template <int N, typename FT>
 __global__ __launch_bounds__(64) void k_factor_lu_lds(HeviShapeDev sh, const double* sbuf, FT* Ub,
                                                       FT* __restrict__ Lb,
                                                       uint8_t* __restrict__ piv,
@@ -242,10 +254,11 @@ struct Factor {
   static hipError_t run(const HeviShapeDev& sh, double lambda, int fp32,
                         const double* ops, double* sbuf, void* Ub, void* Lb, uint8_t* piv,
                         HeviDevInfo* info, hipStream_t st) {
-    const dim3 g((unsigned)sh.ntiles);
-    hipLaunchKernelGGL(k_factor_assemble<N>, g, dim3(T * CWF), 0, st, sh, lambda, ops, sbuf);
     if constexpr (N >= kLuLdsMinN) {
-      // the window does not fit in registers: LDS window, 64 / CPW workgroups per tile
+      // the window does not fit in registers: assembly into sbuf, then the LDS
+      // window LU, 64 / CPW workgroups per tile
+      const dim3 g((unsigned)sh.ntiles);
+      hipLaunchKernelGGL(k_factor_assemble<N>, g, dim3(T * CWF), 0, st, sh, lambda, ops, sbuf);
       const dim3 gl((unsigned)(sh.ntiles * (64 / LuLdsShape<N>::CPW)));
       if (fp32)
         hipLaunchKernelGGL((k_factor_lu_lds<N, float>), gl, dim3(T), 0, st, sh, sbuf, (float*)Ub,
@@ -254,13 +267,15 @@ struct Factor {
         hipLaunchKernelGGL((k_factor_lu_lds<N, double>), gl, dim3(T), 0, st, sh, sbuf,
                            (double*)Ub, (double*)Lb, piv, info);
     } else {
-      // window split over kLuLanes lanes: kLuLanes workgroups per tile
+      // assembly and LU in one pass, the window split over kLuLanes lanes:
+      // kLuLanes workgroups per tile
+      (void)sbuf;
       const dim3 g2((unsigned)(sh.ntiles * kLuLanes));
       if (fp32)
-        hipLaunchKernelGGL((k_factor_lu_split<N, float>), g2, dim3(T), 0, st, sh, sbuf,
+        hipLaunchKernelGGL((k_factor_fused<N, float>), g2, dim3(T), 0, st, sh, lambda, ops,
                            (float*)Ub, (float*)Lb, piv, info);
       else
-        hipLaunchKernelGGL((k_factor_lu_split<N, double>), g2, dim3(T), 0, st, sh, sbuf,
+        hipLaunchKernelGGL((k_factor_fused<N, double>), g2, dim3(T), 0, st, sh, lambda, ops,
                            (double*)Ub, (double*)Lb, piv, info);
     }
     return hipGetLastError();
