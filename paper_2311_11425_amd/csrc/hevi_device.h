@@ -202,6 +202,12 @@ __device__ void pg_pass(Gll<N> tab, const OpsView& op, int Ne, double* ws, int64
 // the extra wavefronts gain.
 constexpr int CW = 1;  // chunk wavefronts per tile
 
+// Waves per SIMD the streaming kernels (apply, stage passes) are compiled for: two
+// up to N = 4, whose element working set fits in 256 VGPRs; one above, where a
+// 256-VGPR cap spilled hundreds of bytes per lane to scratch.
+template <int N>
+constexpr int kStreamWaves = N <= 4 ? 2 : 1;
+
 struct Chunk {
   int lane, e0, e1;
   int64_t tile;

@@ -78,7 +78,7 @@ __global__ __launch_bounds__(64) void k_build_ops(HeviShapeDev sh, double R, dou
 // Single-problem kernels: tile = blockIdx.x
 
 template <int N, bool HAS_REF>
-__global__ __launch_bounds__(64, 2) void k_apply(HeviShapeDev sh, const double* __restrict__ ops,
+__global__ __launch_bounds__(64, kStreamWaves<N>) void k_apply(HeviShapeDev sh, const double* __restrict__ ops,
                                               const double* __restrict__ x,
                                               const double* __restrict__ xref,
                                               double* __restrict__ y) {
@@ -143,7 +143,7 @@ __global__ __launch_bounds__(64) void k_stage_solve(HeviShapeDev sh, double lamb
 // wavefront that owns the tile, with the reduced right-hand side r and the
 // solution u (one array, used in place) in LDS instead of the global scratch.
 template <int N>
-__global__ __launch_bounds__(64, 2) void k_stage_fused(HeviShapeDev sh, double lambda,
+__global__ __launch_bounds__(64, kStreamWaves<N>) void k_stage_fused(HeviShapeDev sh, double lambda,
                                                      const double* __restrict__ ops,
                                                      const double* __restrict__ Ub,
                                                      const double* __restrict__ Lb,
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(64, 2) void k_stage_fused(HeviShapeDev sh, double l
 }
 
 template <int N>
-__global__ __launch_bounds__(64, 2) void k_stage_rhs(HeviShapeDev sh, double lambda,
+__global__ __launch_bounds__(64, kStreamWaves<N>) void k_stage_rhs(HeviShapeDev sh, double lambda,
                                                      const double* __restrict__ ops,
                                                      double* __restrict__ ws, HeviTerms E,
                                                      HeviTerms Q, double* __restrict__ Qi) {
@@ -169,7 +169,7 @@ __global__ __launch_bounds__(64, 2) void k_stage_rhs(HeviShapeDev sh, double lam
 }
 
 template <int N, typename FT, bool REFINE>
-__global__ __launch_bounds__(64, 2) void k_stage_bsolve(HeviShapeDev sh, double lambda,
+__global__ __launch_bounds__(64, kStreamWaves<N>) void k_stage_bsolve(HeviShapeDev sh, double lambda,
                                                         const double* __restrict__ ops,
                                                         const FT* __restrict__ Ub,
                                                         const FT* __restrict__ Lb,
@@ -181,7 +181,7 @@ __global__ __launch_bounds__(64, 2) void k_stage_bsolve(HeviShapeDev sh, double 
 }
 
 template <int N>
-__global__ __launch_bounds__(64, 2) void k_stage_update(HeviShapeDev sh, double lambda,
+__global__ __launch_bounds__(64, kStreamWaves<N>) void k_stage_update(HeviShapeDev sh, double lambda,
                                                      const double* __restrict__ ops,
                                                      double* __restrict__ ws,
                                                      double* __restrict__ Qi, HeviDevInfo* info) {
