@@ -71,11 +71,60 @@ def measured_traffic(path):
     return float(v) if v else None
 
 
-def oracle_rate(col, qn, qref, budget_cpu_s=15.0):
-    """The oracle's ARK3 step on a bounded sample of the same columns, on the host
-    cores; column-solves/s (sampling by column is exact: columns are independent)."""
+def sample_columns(col, idx):
+    """The column batch restricted to the columns idx (host arrays)."""
+    sc = dict(col)
+    for k in ("z", "J", "rho0", "Theta0"):
+        sc[k] = np.ascontiguousarray(col[k][:, idx])
+    sc["gz"] = np.ascontiguousarray(col["gz"][:, :, idx])
+    sc["ncols"] = len(idx)
+    return sc
+
+
+class OracleChecks:
+    """Comparisons with the oracle, queued by the GPU legs as plain host arrays and
+    carried out only by cpu_baseline_leg (the one part of this file that runs the
+    oracle).  Each result is written into the dict it was queued for."""
+
+    def __init__(self):
+        self.jobs = []
+
+    def stage_solves(self, target, key, sc, lam, pairs, combine="list"):
+        """pairs: per stage (q^, x_gpu) on the sampled columns sc, x = Q_i + P.
+        combine="list": target[key] = per-stage max errors; "max": running max."""
+        self.jobs.append(("stage", target, key, sc, lam, pairs, combine))
+
+    def ark_step(self, target, key, col, tableau, dt, qn, qref, gpu):
+        """gpu: {"Q2": .., "Q3": .., "q_next": ..}; the increments against q^n are
+        compared with the oracle's step of the same columns."""
+        self.jobs.append(("ark", target, key, col, tableau, dt, qn, qref, gpu))
+
+
+def cpu_baseline_leg(checks, col=None, qn=None, qref=None, budget_cpu_s=15.0):
+    """Runs the oracle on the host cores: first the comparisons queued in `checks`,
+    then, if `col` is given, the cpu_baseline figure -- the oracle's ARK3 step timed
+    on a bounded sample of the same columns, in column-solves/s (sampling by column
+    is exact: columns are independent)."""
     import oracle
     from oracle import tableaux
+    for job in checks.jobs:
+        if job[0] == "stage":
+            _, target, key, sc, lam, pairs, combine = job
+            errs = [relerr_max(xg, oracle.solve_batch(sc, lam, rhs, refine=1)) for rhs, xg in pairs]
+            if combine == "list":
+                target[key] = errs
+            else:
+                target[key] = max(target.get(key, 0.0), max(errs))
+        else:
+            _, target, key, c, tname, dt, q0, r0, gpu = job
+            tab = tableaux.as_float(getattr(tableaux, tname)())
+            qo, Qo, _ = oracle.ark_step_batch(c, tab, dt, q0, r0, refine=1, want_stages=True)
+            target[key] = {"Q2": relerr_max(gpu["Q2"] - q0, Qo[1] - q0),
+                           "Q3": relerr_max(gpu["Q3"] - q0, Qo[2] - q0),
+                           "q_next": relerr_max(gpu["q_next"] - q0, qo - q0)}
+    checks.jobs = []
+    if col is None:
+        return None
     tab = tableaux.as_float(tableaux.ark3())
     try:
         threads = len(os.sched_getaffinity(0))
@@ -85,11 +134,8 @@ def oracle_rate(col, qn, qref, budget_cpu_s=15.0):
 
     def sample(n):
         idx = np.linspace(0, col["z"].shape[1] - 1, n).astype(np.int64)
-        sc = dict(col)
-        for k in ("z", "J", "rho0", "Theta0"):
-            sc[k] = np.ascontiguousarray(col[k][:, idx])
-        sc["gz"] = np.ascontiguousarray(col["gz"][:, :, idx])
-        return sc, np.ascontiguousarray(qn[..., idx]), np.ascontiguousarray(qref[..., idx])
+        return (sample_columns(col, idx), np.ascontiguousarray(qn[..., idx]),
+                np.ascontiguousarray(qref[..., idx]))
 
     n0 = threads * 16
     sc, q0, r0 = sample(n0)
@@ -124,30 +170,21 @@ def oracle_rate(col, qn, qref, budget_cpu_s=15.0):
                       f"{wall * threads:.1f} CPU-s on {threads} threads"}
 
 
-def stage_errors(st, col, qn, idx):
-    """Max relative L2 error per (column, variable) of each stage solve on sampled
-    columns: q^ rebuilt from the GPU's own Q_j, S_j and solved by the oracle."""
+def queue_stage_errors(checks, target, key, st, col, qn, idx):
+    """Queue the check of each stage solve of the stepper's last step on the sampled
+    columns: q^ rebuilt from the GPU's own Q_j, S_j, solved by the oracle later."""
     import torch
-    import oracle
     qs = np.ascontiguousarray(qn[..., idx])
-    sc = dict(col)
-    for k in ("z", "J", "rho0", "Theta0"):
-        sc[k] = np.ascontiguousarray(col[k][:, idx])
-    sc["gz"] = np.ascontiguousarray(col["gz"][:, :, idx])
     torch.cuda.synchronize()
     Q = [t.cpu().numpy()[..., idx] for t in st.Q]
     S = [t.cpu().numpy()[..., idx] for t in st.S]
-    out = []
+    pairs = []
     for i in range(1, st.s):
         c = st.coeffs(i)
         qE = qs + sum(st.dt * st.Aexp[i][j] * S[j] for j in range(i))
         P = sum(c[j] * Q[j] for j in range(i))
-        xo = oracle.solve_batch(sc, st.lam, qE + P, refine=1)
-        xg = Q[i] + P
-        num = np.sqrt(((xg - xo) ** 2).sum(axis=1))
-        den = np.sqrt((xo ** 2).sum(axis=1))
-        out.append(float((num / np.where(den > 0, den, 1.0)).max()))
-    return out
+        pairs.append((qE + P, Q[i] + P))
+    checks.stage_solves(target, key, sample_columns(col, idx), st.lam, pairs)
 
 
 def relerr_max(a, ref):
@@ -158,33 +195,29 @@ def relerr_max(a, ref):
     return float((num / den).max()) if num.size else 0.0
 
 
-def cfg1_leg(ctx, steps=200):
+def cfg1_leg(ctx, checks, steps=200):
     """Config 1 shape (256 columns, N=4, Ne=8, isothermal, ARK2, dt=30 s): per-stage
     and end-of-step error of the mixed (FP32 factors + FP64 refinement) and FP64
-    paths against the oracle, and the step time (the batch fits in the caches)."""
+    paths against the oracle (queued in `checks`), and the step time (the batch
+    fits in the caches)."""
     import torch
-    import oracle
-    from oracle import tableaux
     from paper_2311_11425_amd import inputs
     from paper_2311_11425_amd.driver import ArkStepper, ColumnBatch
     col = inputs.config1()
     qn, qref = inputs.perturbed_state(col)
     B = ColumnBatch(ctx, col)
     qd, qrd = torch.from_numpy(qn).cuda(), torch.from_numpy(qref).cuda()
-    qo, Qo, _ = oracle.ark_step_batch(col, tableaux.as_float(tableaux.ark2()), 30.0, qn, qref,
-                                      refine=1, want_stages=True)
     out = {}
     for name, prec, refine in (("mixed", 1, (4, 1e-13, 0)), ("fp64", 0, (0, 1e-13, 0))):
         st = ArkStepper(ctx, B, "ARK2", 30.0, precision=prec, refine=refine)
         o = B.empty_state()
         infos = st.step(qd, qrd, o, info=True)
         Q = [t.cpu().numpy() for t in st.Q]
-        res = {"stage_solve_rel_err": stage_errors(st, col, qn, np.arange(col["ncols"])),
-               "increment_rel_err": {
-                   "Q2": relerr_max(Q[1] - qn, Qo[1] - qn),
-                   "Q3": relerr_max(Q[2] - qn, Qo[2] - qn),
-                   "q_next": relerr_max(o.cpu().numpy() - qn, qo - qn)},
-               "max_refinement_sweeps": max(i["max_sweeps_used"] for i in infos)}
+        res = {"max_refinement_sweeps": max(i["max_sweeps_used"] for i in infos)}
+        queue_stage_errors(checks, res, "stage_solve_rel_err", st, col, qn,
+                           np.arange(col["ncols"]))
+        checks.ark_step(res, "increment_rel_err", col, "ark2", 30.0, qn, qref,
+                        {"Q2": Q[1], "Q3": Q[2], "q_next": o.cpu().numpy()})
         for _ in range(10):
             st.step(qd, qrd, o)
         torch.cuda.synchronize()
@@ -240,12 +273,12 @@ def copy_ceiling(nbytes=1 << 30, reps=20):
     return 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
 
 
-def uneven_leg(ctx, scale=1.0, steps=5, reps=2):
+def uneven_leg(ctx, checks, scale=1.0, steps=5, reps=2):
     """Uneven batch: 64 problems, N ~ U{3..7}, Ne ~ U{8..16}, 1k-50k columns each
     (seed 40), isothermal 300 K, 30 km; one ARK3 step (dt = 300 s) of every problem
-    per group step, each phase one persistent launch; autotuned plan."""
+    per group step, each phase one persistent launch; autotuned plan.  Stage solves
+    of sampled columns of 4 members are queued in `checks`."""
     import torch
-    import oracle
     from paper_2311_11425_amd import hevi, inputs
     from paper_2311_11425_amd.driver import ColumnBatch
     specs = inputs.uneven_problems(scale=scale)
@@ -297,26 +330,22 @@ def uneven_leg(ctx, scale=1.0, steps=5, reps=2):
              "max_refinement_sweeps": max(i["max_sweeps_used"] for i in infos),
              "max_rel_correction": max(i["max_rel_correction"] for i in infos),
              "autotune": tune}
-        # stage solves of sampled columns of 4 members against the oracle
-        errs = []
+        # stage solves of sampled columns of 4 members, for the oracle
         tab = hevi.tableau("ARK3")
+        lam = tab["Aimp"][1][1] * 300.0
         for p, (col, qn, idx) in host_q.items():
             m = members[p]
-            sc = dict(col)
-            for k in ("z", "J", "rho0", "Theta0"):
-                sc[k] = np.ascontiguousarray(col[k][:, idx])
-            sc["gz"] = np.ascontiguousarray(col["gz"][:, :, idx])
             qs = np.ascontiguousarray(qn[..., idx])
             Q = [qs] + [t.cpu().numpy()[..., idx] for t in m["Q"][1:]]
             S = [t.cpu().numpy()[..., idx] for t in m["S"]]
-            lam = tab["Aimp"][1][1] * 300.0
+            pairs = []
             for i in range(1, 4):
                 c = [(tab["Aimp"][i][j] - tab["Aexp"][i][j]) / tab["Aimp"][i][i] for j in range(i)]
                 qE = qs + sum(300.0 * tab["Aexp"][i][j] * S[j] for j in range(i))
                 P = sum(c[j] * Q[j] for j in range(i))
-                xo = oracle.solve_batch(sc, lam, qE + P, refine=1)
-                errs.append(relerr_max(Q[i] + P, xo))
-        d["stage_rel_err_vs_oracle_max"] = max(errs)
+                pairs.append((qE + P, Q[i] + P))
+            checks.stage_solves(d, "stage_rel_err_vs_oracle_max", sample_columns(col, idx), lam,
+                                pairs, combine="max")
         d["oracle_sample"] = f"{len(host_q)} members (incl. the highest order) x 12 columns x 3 stages"
         res[name] = d
         log(f"uneven {name}: {ms:.2f} ms/step, plan {best}, per-member {per_member:.2f} ms")
@@ -324,13 +353,16 @@ def uneven_leg(ctx, scale=1.0, steps=5, reps=2):
     return res
 
 
-def serve_leg(ctx, rates=(0.25, 0.5, 0.75, 1.0, 1.2), per_rate=300, scale=1.0, seed=9):
+def serve_leg(ctx, checks, rates=(0.25, 0.5, 0.75, 1.0, 1.2), per_rate=300, scale=1.0,
+              seed=9):
     """Serving: 16 simulations (tops 30/60/120 km, Ne ~ U{10..40}, N = 4, 5k-86,402
     columns, seed 50) registered with a server; each request is the ARK3
-    second-stage solve of one simulation (FP64).  Saturation = completed
-    requests/s of a burst of 8 requests per simulation; then Poisson arrivals of
-    uniformly chosen simulations at fractions of it, latency p50/p99 from the
-    server's submit-to-completion clock."""
+    second-stage solve of one simulation.  Run once with FP64 factors and once with
+    FP32 factors + FP64 refinement, each on a server of its own.  Saturation =
+    completed requests/s of a burst of 8 requests per simulation; then Poisson
+    arrivals of uniformly chosen simulations at fractions of it, latency p50/p99
+    from the server's submit-to-completion clock.  The served results of 3
+    simulations (12 sampled columns each) are queued in `checks`."""
     import threading
     import ctypes
     import torch
@@ -340,7 +372,6 @@ def serve_leg(ctx, rates=(0.25, 0.5, 0.75, 1.0, 1.2), per_rate=300, scale=1.0, s
     dt = 300.0
     lam = tab["Aimp"][1][1] * dt
     specs = inputs.serving_simulations(scale=scale)
-    budget = 0
     sims = []
     t0 = time.perf_counter()
     for sp in specs:
@@ -351,88 +382,108 @@ def serve_leg(ctx, rates=(0.25, 0.5, 0.75, 1.0, 1.2), per_rate=300, scale=1.0, s
         S1 = B.empty_state()
         ctx.apply_op(B.ops, qd, S1, xref=qrd)
         Qi = B.empty_state()
-        sims.append({"B": B, "qn": qd, "S1": S1, "Qi": Qi, "ncols": sp["ncols"],
+        sims.append({"B": B, "qn": qd, "S1": S1, "Qi": Qi, "ncols": sp["ncols"], "col": col,
+                     "nz": col["nz"],
                      "Ep": hevi._ptr_array([qd, S1]),
                      "ep": hevi._dbl_array([1.0, dt * tab["Aexp"][1][0]]),
                      "Qp": hevi._ptr_array([qd]), "cp": hevi._dbl_array([-1.0]),
                      "out": ctypes.c_void_p(Qi.data_ptr())})
-        budget += hevi.sizes(4, sp["Ne"], sp["ncols"])["factors"] * sp["ncols"]
     torch.cuda.synchronize()
     log(f"serve: {len(specs)} simulations ready in {time.perf_counter() - t0:.1f} s")
-    srv = hevi.Server(ctx, 1 << 40, max_inflight=1 << 16)
-    for sm in sims:
-        sm["id"] = srv.register(sm["B"].ops, lam)
-    torch.cuda.synchronize()
-
-    def submit(k):
-        sm = sims[k]
-        while True:
-            code, t = srv.submit_raw(sm["id"], sm["Ep"], sm["ep"], 2, sm["Qp"], sm["cp"], 1,
-                                     sm["out"])
-            if code == 0:
-                return t
-            if code != 7:
-                raise hevi.HeviError(code, "hevi_serve_submit")
-
-    # warm up, then saturation from a burst
-    for t in [submit(k) for k in range(len(sims))]:
-        srv.wait(t)
-    burst = [k for _ in range(8) for k in range(len(sims))]
-    t = time.perf_counter()
-    tickets = [submit(k) for k in burst]
-    for tk in tickets:
-        srv.wait(tk)
-    sat_s = time.perf_counter() - t
-    sat = len(burst) / sat_s
-    cols_per_req = float(np.mean([sm["ncols"] for sm in sims]))
+    check = sorted({0, len(sims) // 2, len(sims) - 1})
     out = {"simulations": len(sims), "columns": [sm["ncols"] for sm in sims],
-           "saturation_requests_per_s": sat,
-           "saturation_column_solves_per_s": sum(sims[k]["ncols"] for k in burst) / sat_s,
-           "rates": []}
-    rng = np.random.default_rng(seed)
-    for frac in rates:
-        rate = frac * sat
-        gaps = rng.exponential(1.0 / rate, per_rate)
-        which = rng.integers(0, len(sims), per_rate)
-        tickets = [None] * per_rate
-        ready = threading.Semaphore(0)
+           "mean_columns_per_request": float(np.mean([sm["ncols"] for sm in sims])),
+           "requests_per_rate": per_rate,
+           "request": "ARK3 stage 2 solve of one simulation (q^n, S_1 -> Q_2)"}
+    for pname, prec in (("fp64", hevi.HEVI_FP64), ("mixed", hevi.HEVI_FP32_REFINE)):
+        srv = hevi.Server(ctx, 1 << 40, max_inflight=1 << 16)
+        for sm in sims:
+            sm["id"] = srv.register(sm["B"].ops, lam, precision=prec)
+        torch.cuda.synchronize()
 
-        def producer():
-            t_next = time.perf_counter()
-            for i in range(per_rate):
-                t_next += gaps[i]
-                while True:
-                    d = t_next - time.perf_counter()
-                    if d <= 0:
-                        break
-                    if d > 0.002:
-                        time.sleep(d - 0.001)
-                tickets[i] = submit(int(which[i]))
-                ready.release()
+        def submit(k):
+            sm = sims[k]
+            while True:
+                code, t = srv.submit_raw(sm["id"], sm["Ep"], sm["ep"], 2, sm["Qp"], sm["cp"], 1,
+                                         sm["out"])
+                if code == 0:
+                    return t
+                if code != 7:
+                    raise hevi.HeviError(code, "hevi_serve_submit")
 
-        lat = []
-        th = threading.Thread(target=producer)
+        # warm up, then saturation from a burst
+        for t in [submit(k) for k in range(len(sims))]:
+            srv.wait(t)
+        burst = [k for _ in range(8) for k in range(len(sims))]
         t = time.perf_counter()
-        th.start()
-        for i in range(per_rate):
-            ready.acquire()
-            inf, l = srv.wait(tickets[i])
-            if inf["status"] != "HEVI_OK":
-                raise SystemExit(f"serve: request reported {inf}")
-            lat.append(l)
-        th.join()
-        wall = time.perf_counter() - t
-        done_cols = float(sum(sims[int(k)]["ncols"] for k in which))
-        out["rates"].append({"offered_fraction_of_saturation": frac,
-                             "offered_requests_per_s": rate,
-                             "achieved_requests_per_s": per_rate / wall,
-                             "column_solves_per_s": done_cols / wall,
-                             "latency_ms": {"p50": 1e3 * pct(lat, 50), "p99": 1e3 * pct(lat, 99),
-                                            "mean": 1e3 * float(np.mean(lat))}})
-        log(f"serve {frac:.2f}x: p50 {1e3 * pct(lat, 50):.2f} ms, p99 {1e3 * pct(lat, 99):.2f} ms")
-    out["mean_columns_per_request"] = cols_per_req
-    out["requests_per_rate"] = per_rate
-    srv.close()
+        tickets = [submit(k) for k in burst]
+        infos = [srv.wait(tk)[0] for tk in tickets]
+        sat_s = time.perf_counter() - t
+        sat = len(burst) / sat_s
+        sat_cols = sum(sims[k]["ncols"] for k in burst) / sat_s
+        d = {"saturation_requests_per_s": sat,
+             "saturation_column_solves_per_s": sat_cols,
+             "saturation_unknowns_per_s": sum(sims[k]["ncols"] * 5 * sims[k]["nz"]
+                                              for k in burst) / sat_s,
+             "max_refinement_sweeps": max(i["max_sweeps_used"] for i in infos),
+             "rates": []}
+        rng = np.random.default_rng(seed)
+        for frac in rates:
+            rate = frac * sat
+            gaps = rng.exponential(1.0 / rate, per_rate)
+            which = rng.integers(0, len(sims), per_rate)
+            tickets = [None] * per_rate
+            ready = threading.Semaphore(0)
+
+            def producer():
+                t_next = time.perf_counter()
+                for i in range(per_rate):
+                    t_next += gaps[i]
+                    while True:
+                        dl = t_next - time.perf_counter()
+                        if dl <= 0:
+                            break
+                        if dl > 0.002:
+                            time.sleep(dl - 0.001)
+                    tickets[i] = submit(int(which[i]))
+                    ready.release()
+
+            lat = []
+            th = threading.Thread(target=producer)
+            t = time.perf_counter()
+            th.start()
+            for i in range(per_rate):
+                ready.acquire()
+                inf, lt = srv.wait(tickets[i])
+                if inf["status"] != "HEVI_OK":
+                    raise SystemExit(f"serve: request reported {inf}")
+                lat.append(lt)
+            th.join()
+            wall = time.perf_counter() - t
+            done_cols = float(sum(sims[int(k)]["ncols"] for k in which))
+            d["rates"].append({"offered_fraction_of_saturation": frac,
+                               "offered_requests_per_s": rate,
+                               "achieved_requests_per_s": per_rate / wall,
+                               "column_solves_per_s": done_cols / wall,
+                               "latency_ms": {"p50": 1e3 * pct(lat, 50),
+                                              "p99": 1e3 * pct(lat, 99),
+                                              "mean": 1e3 * float(np.mean(lat))}})
+            log(f"serve {pname} {frac:.2f}x: p50 {1e3 * pct(lat, 50):.2f} ms, "
+                f"p99 {1e3 * pct(lat, 99):.2f} ms")
+        srv.close()
+        torch.cuda.synchronize()
+        # the served Q_2 of sampled columns, for the oracle
+        for k in check:
+            sm = sims[k]
+            idx = np.unique(np.linspace(0, sm["ncols"] - 1, 12).astype(np.int64))
+            qs = sm["qn"].cpu().numpy()[..., idx]
+            qE = qs + dt * tab["Aexp"][1][0] * sm["S1"].cpu().numpy()[..., idx]
+            xg = sm["Qi"].cpu().numpy()[..., idx] - qs
+            checks.stage_solves(d, "stage_rel_err_vs_oracle_max",
+                                sample_columns(sm["col"], idx), lam, [(qE - qs, xg)],
+                                combine="max")
+        d["oracle_sample"] = f"{len(check)} simulations x 12 columns"
+        out[pname] = d
     return out
 
 
@@ -514,13 +565,16 @@ def main():
     from paper_2311_11425_amd import hevi, inputs
     from paper_2311_11425_amd.driver import ColumnBatch
 
+    checks = OracleChecks()
     if args.leg:
         ctx = hevi.Context(0)
-        leg = {"config1": lambda: cfg1_leg(ctx), "share": lambda: share_leg(ctx),
-               "uneven": lambda: uneven_leg(ctx, scale=args.uneven_scale),
-               "serve": lambda: serve_leg(ctx, scale=args.serve_scale)}[args.leg]()
+        leg = {"config1": lambda: cfg1_leg(ctx, checks), "share": lambda: share_leg(ctx),
+               "uneven": lambda: uneven_leg(ctx, checks, scale=args.uneven_scale),
+               "serve": lambda: serve_leg(ctx, checks, scale=args.serve_scale)}[args.leg]()
         torch.cuda.synchronize()
         ctx.close()
+        if not args.no_error_check:
+            cpu_baseline_leg(checks)
         print(json.dumps({"leg": args.leg, "result": leg}), flush=True)
         return
     t0 = time.perf_counter()
@@ -556,8 +610,7 @@ def main():
              "factor_ms": fac_ms, "apply_op_ms": app_ms,
              "combine_ms": float(np.mean(r["combine_ms"])),
              "factor_plus_stages_column_solves_per_s": 3 * ncols / ((fac_ms + 3 * stage_ms) * 1e-3)}
-        if not args.no_error_check:
-            d["stage_rel_err_vs_oracle"] = stage_errors(st, col, qn, idx)
+        queue_stage_errors(checks, d, "stage_rel_err_vs_oracle", st, col, qn, idx)
         res_paths[name] = d
         log(f"{name}: {ms_step:.3f} ms/step, stage solve {stage_ms:.3f} ms, factor {fac_ms:.3f} ms")
 
@@ -611,22 +664,29 @@ def main():
                      "paper_layout_band_factor_bytes_per_column": sz["paper_band"],
                      "factor_bytes_per_column": sz["factors"]},
     }
-    if not args.no_cpu_baseline:
-        log("oracle CPU baseline ...")
-        res["cpu_baseline"] = oracle_rate(col, qn, qref, args.cpu_budget)
     if not args.no_extra:
         del B, st
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
         log("config-1 accuracy leg ...")
-        res["config1_ark2_accuracy"] = cfg1_leg(ctx)
+        res["config1_ark2_accuracy"] = cfg1_leg(ctx, checks)
         log("one-GPU share leg ...")
         res["one_gpu_share_of_8"] = share_leg(ctx)
         log("uneven-batch leg ...")
-        res["uneven_batch"] = uneven_leg(ctx, scale=args.uneven_scale)
+        res["uneven_batch"] = uneven_leg(ctx, checks, scale=args.uneven_scale)
         torch.cuda.empty_cache()
         log("serving leg ...")
-        res["serving"] = serve_leg(ctx, scale=args.serve_scale)
+        res["serving"] = serve_leg(ctx, checks, scale=args.serve_scale)
+    # the oracle, on the host cores only: the queued comparisons with the GPU's
+    # results, then the timed CPU baseline
+    if args.no_error_check:
+        checks.jobs = []
+    if not args.no_cpu_baseline:
+        log("oracle: error checks and CPU baseline ...")
+        res["cpu_baseline"] = cpu_baseline_leg(checks, col, qn, qref, args.cpu_budget)
+    elif checks.jobs:
+        log("oracle: error checks ...")
+        cpu_baseline_leg(checks)
     res["paper_context"] = {
         "note": "whole-model 10-day baroclinic-instability time-to-solution on 512 AMD EPYC "
                 "Rome cores (CPU); context only, not this metric",
