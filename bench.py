@@ -396,7 +396,8 @@ def serve_leg(ctx, checks, rates=(0.25, 0.5, 0.75, 1.0, 1.2), per_rate=300, scal
            "requests_per_rate": per_rate,
            "request": "ARK3 stage 2 solve of one simulation (q^n, S_1 -> Q_2)"}
     for pname, prec in (("fp64", hevi.HEVI_FP64), ("mixed", hevi.HEVI_FP32_REFINE)):
-        srv = hevi.Server(ctx, 1 << 40, max_inflight=1 << 16)
+        # FP32 factors of the tallest columns (161 nodes) contract more slowly: 8 sweeps
+        srv = hevi.Server(ctx, 1 << 40, max_inflight=1 << 16, refine=(8, 1e-13))
         for sm in sims:
             sm["id"] = srv.register(sm["B"].ops, lam, precision=prec)
         torch.cuda.synchronize()

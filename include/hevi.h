@@ -296,11 +296,12 @@ void hevi_group_free(hevi_group *g);
  * one persistent launch per kernel phase over the tiles of all its requests
  * (FP64 and FP32-factor simulations in separate launches), on the server's own
  * stream, with up to 3 batches in flight.  Requests of one simulation run in
- * submission order.  FP32-factor simulations use the refinement {4, 1e-13}.
+ * submission order.
  *
  * hevi_serve_create: hbm_budget_bytes bounds the library-owned memory of all
  *   registered simulations (factors and scratch); max_inflight bounds the
- *   requests submitted and not yet completed.
+ *   requests submitted and not yet completed; `refine` (NULL = {4, 1e-13, 0};
+ *   full_sweeps must be 0) is the refinement of every FP32-factor simulation.
  * hevi_serve_register: factor A = I - lambda L_z of `ops` (enqueued on the
  *   server's stream) and return a simulation id.  HEVI_E_NOMEM: not admitted
  *   now (the budget is used up; release a simulation and retry).  `ops` must
@@ -321,7 +322,7 @@ void hevi_group_free(hevi_group *g);
  * All server calls are thread-safe.  If the device fails, pending and later
  * tickets complete with status HEVI_E_DEVICE. */
 hevi_status hevi_serve_create(hevi_ctx *ctx, size_t hbm_budget_bytes, int32_t max_inflight,
-                              hevi_server **out);
+                              const hevi_refine *refine, hevi_server **out);
 hevi_status hevi_serve_register(hevi_server *srv, const hevi_ops *ops, double lambda,
                                 hevi_precision prec, int32_t *sim_id);
 hevi_status hevi_serve_submit(hevi_server *srv, int32_t sim_id, int32_t n_e,

@@ -81,6 +81,8 @@ struct hevi_server {
   hevi_ctx* ctx = nullptr;
   size_t budget = 0, used = 0;
   int32_t max_inflight = 0;
+  int sweeps = 4;        // refinement of FP32-factor simulations
+  double target = 1e-13;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::map<int32_t, Sim> sims;
@@ -235,7 +237,7 @@ void launch_batch(hevi_server* S) {
     s.total = sb.total;
     s.ctr = S->d_ctr;
     const int grid = (int)sb.total;
-    const int sweeps = sb.fp32 ? 4 : 0;
+    const int sweeps = sb.fp32 ? S->sweeps : 0;
     if (!sb.fp32 && sb.maxnz <= HEVI_FUSED_MAX_NZ) {
       okk = okk && ok(hevi_launch_multi(HEVI_PH_STAGE_FUSED, sb.nlo, sb.nhi, 0, sl.d_probs,
                                         sl.d_calls, s, grid, 0, 1e-13, sb.maxnz, S->st));
@@ -243,7 +245,7 @@ void launch_batch(hevi_server* S) {
     }
     for (int ph : {HEVI_PH_STAGE_RHS, HEVI_PH_STAGE_BSOLVE, HEVI_PH_STAGE_UPDATE})
       okk = okk && ok(hevi_launch_multi(ph, sb.nlo, sb.nhi, sb.fp32, sl.d_probs, sl.d_calls, s,
-                                        grid, sweeps, 1e-13, sb.maxnz, S->st));
+                                        grid, sweeps, S->target, sb.maxnz, S->st));
   }
   okk = okk &&
         ok(hipMemcpyAsync(sl.h_info, sl.d_info, sizeof(HeviDevInfo) * n, hipMemcpyDeviceToHost,
@@ -296,15 +298,22 @@ hevi_status retire(hevi_server* S, uint64_t ticket, hevi_info* info, double* lat
 extern "C" {
 
 hevi_status hevi_serve_create(hevi_ctx* ctx, size_t hbm_budget_bytes, int32_t max_inflight,
-                              hevi_server** out) {
+                              const hevi_refine* refine, hevi_server** out) {
   if (!ctx || !out || max_inflight < 1) return HEVI_E_INVALID;
   *out = nullptr;
+  if (refine && (refine->max_sweeps < 0 || refine->max_sweeps > 64 ||
+                 !(refine->rel_residual_target >= 0) || refine->full_sweeps != 0))
+    return HEVI_E_INVALID;
   if (!ok(hipSetDevice(ctx->device))) return HEVI_E_DEVICE;
   hevi_server* S = new (std::nothrow) hevi_server;
   if (!S) return HEVI_E_NOMEM;
   S->ctx = ctx;
   S->budget = hbm_budget_bytes;
   S->max_inflight = max_inflight;
+  if (refine) {
+    S->sweeps = refine->max_sweeps;
+    S->target = refine->rel_residual_target;
+  }
   bool good = ok(hipStreamCreate(&S->st)) && !dev_alloc(&S->d_ctr, 2 * sizeof(uint32_t)) &&
               ok(hipMemset(S->d_ctr, 0, 2 * sizeof(uint32_t)));
   for (Slot& sl : S->slots) {

@@ -130,7 +130,7 @@ def load():
         "hevi_group_autotune": ([_vp, _vp, i32, ctypes.POINTER(TuneResult), i32,
                                  ctypes.POINTER(i32), _vp], ctypes.c_int),
         "hevi_group_free": ([_vp], None),
-        "hevi_serve_create": ([_vp, ctypes.c_size_t, i32, pp], ctypes.c_int),
+        "hevi_serve_create": ([_vp, ctypes.c_size_t, i32, _vp, pp], ctypes.c_int),
         "hevi_serve_register": ([_vp, _vp, dbl, ctypes.c_int, ctypes.POINTER(i32)], ctypes.c_int),
         "hevi_serve_submit": ([_vp, i32, i32, pp, pd, i32, pp, pd, _vp,
                                ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
@@ -391,11 +391,15 @@ class Server:
     """Continuous-batching stage-solve server (hevi_serve_*, see include/hevi.h).
     Calls are thread-safe; ctypes releases the GIL while the library waits."""
 
-    def __init__(self, ctx, hbm_budget_bytes, max_inflight=1024):
+    def __init__(self, ctx, hbm_budget_bytes, max_inflight=1024, refine=None):
+        """refine: (max_sweeps, rel_target) of the FP32-factor simulations (None:
+        the library default)."""
         self.ctx = ctx
         self.lib = load()
         h = ctypes.c_void_p()
+        ref = None if refine is None else Refine(*(tuple(refine) + (0,) * (3 - len(refine))))
         _check(self.lib.hevi_serve_create(ctx.handle, int(hbm_budget_bytes), int(max_inflight),
+                                          ctypes.byref(ref) if ref is not None else None,
                                           ctypes.byref(h)), "hevi_serve_create")
         self.handle = h
 

@@ -86,7 +86,7 @@ def test_serve_and_group_reject_null_handles():
     import ctypes
     lib = hevi.load()
     out = ctypes.c_void_p()
-    assert lib.hevi_serve_create(None, 1 << 20, 4, ctypes.byref(out)) == 1
+    assert lib.hevi_serve_create(None, 1 << 20, 4, None, ctypes.byref(out)) == 1
     sid = ctypes.c_int32(0)
     assert lib.hevi_serve_register(None, None, 1.0, 0, ctypes.byref(sid)) == 1
     t = ctypes.c_uint64(0)

@@ -121,6 +121,10 @@ def test_serve_admission_busy_closed(ctx):
     from paper_2311_11425_amd import hevi
     a, b = SimData(ctx, SPECS[0]), SimData(ctx, SPECS[1])
     sz_a = hevi.sizes(4, 12, 300)
+    for bad in ((4, 1e-13, 1), (-1, 1e-13), (65, 1e-13), (4, -1.0)):
+        with pytest.raises(hevi.HeviError) as e:
+            hevi.Server(ctx, 1 << 20, refine=bad)
+        assert e.value.code == 1
     srv = hevi.Server(ctx, 1, max_inflight=2)  # a 1-byte budget admits nothing
     with pytest.raises(hevi.HeviError) as e:
         srv.register(a.B.ops, LAM)
