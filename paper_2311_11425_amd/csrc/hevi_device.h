@@ -446,10 +446,9 @@ __device__ __forceinline__ void b_factor_assemble(int64_t tile_, HeviShapeDev sh
 // eliminates column j from the rows below; then the window moves one row down
 // and one column right and row j+2N+1 of S enters at the bottom.  The window
 // starts empty at j = -(2N+1), the first 2N+1 steps only shift rows 0..2N in
-// (their loads go through the same prefetch ring as every later row).  Two
-// implementations: a register window split over LPC lanes (N <= 4,
-// b_factor_lu_split) and an LDS window (N >= 5, b_factor_lu_lds); they store the
-// same factors.
+// (their loads go through the same prefetch ring as every later row).  The
+// window is kept in registers, split over the lanes of a group
+// (b_factor_lu_split, and b_factor_fused_split with the assembly folded in).
 template <int N>
 __device__ __forceinline__ double s_fix(int r, int nz, int s, double raw) {
   // entry (r, r - 2N + s) of S from the stored -lambda^2 K value: identity rows
@@ -490,7 +489,12 @@ __device__ __forceinline__ double from_next(double v) {
 // index and the multipliers of its first lane, and passes the column crossing
 // each split to the left with DPP moves.  A wavefront handles 64 / LPC columns:
 // part `part` of a 64-column tile.
-constexpr int kLuLanes = 2;  // lanes per column of the register-window LU
+constexpr int kLuLanes = 2;  // lanes per column of the register-window LU, N <= 4
+
+// Lanes per column of the register-window LU by order: 2 up to N = 4, 4 above,
+// where a two-lane window would not fit in registers.
+template <int N>
+constexpr int kSplitLanes = N <= 4 ? kLuLanes : 4;
 
 // One step of the split-window LU: elimination step j (if j >= 0), then the
 // window moves one row down and one column right.  Its bottom row is left for
@@ -723,157 +727,6 @@ __device__ __forceinline__ void b_factor_fused_split(int64_t tile, int part, Hev
     ++j;
   }
   if (singular && valid) flag(info, 5 /*HEVI_E_SINGULAR*/, c);
-}
-
-// The band LU for orders whose window does not fit in registers: the
-// (2N+1) x (4N+1) window of each column lives in LDS, indexed circularly (row r
-// in slot r mod (2N+1), column c in slot c mod (4N+1)), so moving the window
-// costs nothing; LPC = 64 / CPW lanes share a column (rows and columns of each
-// step are spread over them).  A workgroup of one wavefront handles CPW
-// columns of a 64-column tile (part `part` of 64 / CPW); rows entering the
-// window are prefetched PFR rows ahead into registers.
-constexpr int kLuLdsMinN = 5;  // orders factored with the LDS window
-
-template <int N>
-struct LuLdsShape {
-  static constexpr int CPW = N >= 7 ? 8 : 16;  // columns per workgroup
-  static constexpr int LPC = 64 / CPW;         // lanes per column
-  static constexpr int R = 2 * N + 1, W = 4 * N + 1;
-  static constexpr int LDS = CPW * R * W;      // doubles
-};
-
-template <int N, typename FT>
-__device__ __forceinline__ void b_factor_lu_lds(int64_t tile, int part, HeviShapeDev sh,
-                                                const double* sbuf, FT* Ub,
-                                                FT* __restrict__ Lb, uint8_t* __restrict__ piv,
-                                                HeviDevInfo* info, double* lds) {
-  using L = LuLdsShape<N>;
-  constexpr int B = 2 * N, R = L::R, W = L::W, LPC = L::LPC, PFR = 3;
-  constexpr int CS = (W + LPC - 1) / LPC;        // columns of a row per lane
-  constexpr int RS = (B + LPC - 1) / LPC;        // rows below the pivot per lane
-  const int k = threadIdx.x % LPC;               // lane within the column
-  const int cl = threadIdx.x / LPC;              // column within the workgroup
-  const int lane = part * L::CPW + cl;           // lane index of the column in its tile
-  const int64_t c = tile * T + lane;
-  const bool valid = c < sh.ncols;
-  const int nz = sh.nz;
-  double* w = lds + cl * R * W;                  // this column's window
-  auto at = [&](int r, int col) -> double& { return w[(r % R) * W + (col % W)]; };
-  for (int i = k; i < R * W; i += LPC) w[i] = 0.0;
-  __syncthreads();
-  // rows 0..2N: entry (r, c) = band offset c - r + 2N of sbuf row r, columns c >= 0
-  // (unconditional loads from clamped offsets, all in flight together)
-  double v0[R][CS];
-#pragma unroll
-  for (int r = 0; r <= B; ++r) {
-    const int rr = min(r, nz - 1);
-#pragma unroll
-    for (int i = 0; i < CS; ++i)
-      v0[r][i] = ldn(sbuf + tix(tile, nz, rr, W, min(k + i * LPC, W - 1), lane));
-  }
-#pragma unroll
-  for (int r = 0; r <= B; ++r) {
-#pragma unroll
-    for (int i = 0; i < CS; ++i) {
-      const int off = k + i * LPC, col = r - B + off;
-      if (off < W && col >= 0) at(r, col) = s_fix<N>(r, nz, off, v0[r][i]);
-    }
-  }
-  // prefetch ring: rows B+1 .. B+PFR (band offsets k + i LPC of each)
-  double ring[PFR][CS];
-#pragma unroll
-  for (int d = 0; d < PFR; ++d) {
-    const int rr = min(B + 1 + d, nz - 1);
-#pragma unroll
-    for (int i = 0; i < CS; ++i) {
-      const int off = min(k + i * LPC, W - 1);
-      ring[d][i] = ldn(sbuf + tix(tile, nz, rr, W, off, lane));
-    }
-  }
-  __syncthreads();
-  bool singular = false;
-  for (int j0 = 0; j0 < nz; j0 += PFR) {
-#pragma unroll
-    for (int d = 0; d < PFR; ++d) {
-      const int j = j0 + d;
-      if (j < nz) {
-        // pivot: largest |entry| in column j among rows j..j+2N (lowest row on ties)
-        double best = -1.0;
-        int p = 0;
-#pragma unroll
-        for (int i = 0; i < (R + LPC - 1) / LPC; ++i) {
-          const int t = k + i * LPC;
-          if (t <= B && j + t < nz) {
-            const double v = fabs(at(j + t, j));
-            if (v > best) { best = v; p = t; }
-          }
-        }
-#pragma unroll
-        for (int m = 1; m < LPC; m <<= 1) {
-          const double ob = __shfl_xor(best, m, LPC);
-          const int op = __shfl_xor(p, m, LPC);
-          if (ob > best || (ob == best && op < p)) { best = ob; p = op; }
-        }
-        if (!(best > 0.0)) {
-          singular = true;
-          p = 0;
-          if (k == 0) at(j, j) = 1.0;
-        }
-        __syncthreads();
-        if (p != 0) {
-#pragma unroll
-          for (int i = 0; i < CS; ++i) {
-            const int s = k + i * LPC;
-            if (s < W) {
-              double& a = at(j, j + s);
-              double& b = at(j + p, j + s);
-              const double v = a;
-              a = b;
-              b = v;
-            }
-          }
-        }
-        __syncthreads();
-        if (k == 0) piv[tix(tile, nz, j, 1, 0, lane)] = (uint8_t)p;
-        FT* urow = Ub + tix(tile, nz, j, W, 0, lane);
-#pragma unroll
-        for (int i = 0; i < CS; ++i) {
-          const int s = k + i * LPC;
-          if (s < W) stnt(urow + s * T, (FT)at(j, j + s));
-        }
-        const double inv = 1.0 / at(j, j);
-        FT* lrow = Lb + tix(tile, nz, j, B, 0, lane);
-#pragma unroll
-        for (int i = 0; i < RS; ++i) {
-          const int t = 1 + k + i * LPC;
-          if (t <= B) {
-            const double l = at(j + t, j) * inv;
-            stnt(lrow + (t - 1) * T, (FT)l);
-#pragma unroll
-            for (int s = 1; s < W; ++s) at(j + t, j + s) -= l * at(j, j + s);
-            at(j + t, j) = 0.0;  // this slot becomes column j + 4N + 1 (zero so far)
-          }
-        }
-        __syncthreads();
-        // row j's slot takes row j + 2N + 1: band offsets 0..4N are its columns
-        // j + 1 .. j + 4N + 1
-        const int rn = j + B + 1;
-#pragma unroll
-        for (int i = 0; i < CS; ++i) {
-          const int off = k + i * LPC;
-          if (off < W) at(rn, j + 1 + off) = s_fix<N>(rn, nz, off, ring[d][i]);
-        }
-        const int rf = min(rn + PFR, nz - 1);
-#pragma unroll
-        for (int i = 0; i < CS; ++i) {
-          const int off = min(k + i * LPC, W - 1);
-          ring[d][i] = ldn(sbuf + tix(tile, nz, rf, W, off, lane));
-        }
-        __syncthreads();
-      }
-    }
-  }
-  if (singular && valid && k == 0) flag(info, 5 /*HEVI_E_SINGULAR*/, c);
 }
 
 // ---------------------------------------------------------------------------

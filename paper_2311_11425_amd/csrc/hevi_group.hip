@@ -96,34 +96,16 @@ __global__ __launch_bounds__(64) void km_factor_assemble(const HeviProbDev* __re
 }
 
 // LDS doubles needed by the LDS-window LU of the orders NLO..NHI (at least 1)
-template <int NLO, int NHI>
-constexpr int lu_lds_max() {
-  int m = 1;
-  if constexpr (NLO <= NHI) {
-    if constexpr (NLO >= kLuLdsMinN) m = LuLdsShape<NLO>::LDS;
-    const int rest = lu_lds_max<NLO + 1, NHI>();
-    m = m > rest ? m : rest;
-  }
-  return m;
-}
-
 template <int NLO, int NHI, typename FT>
 __global__ __launch_bounds__(64) void km_factor_lu(const HeviProbDev* __restrict__ probs,
                                                    HeviSched s) {
-  __shared__ double lds[lu_lds_max<NLO, NHI>()];
   persist(s, [&](int p, int64_t tile) {
     const HeviProbDev& P = probs[p];
     switch_N<NLO, NHI>(P.sh.N, [&](auto n) {
       constexpr int NN = decltype(n)::value;
-      if constexpr (NN >= kLuLdsMinN) {
-        for (int part = 0; part < 64 / LuLdsShape<NN>::CPW; ++part)
-          b_factor_lu_lds<NN, FT>(tile, part, P.sh, P.sbuf, (FT*)P.U, (FT*)P.L, P.piv, P.info,
-                                  lds);
-      } else {
-        for (int part = 0; part < kLuLanes; ++part)
-          b_factor_lu_split<NN, FT, kLuLanes>(tile, part, P.sh, P.sbuf, (FT*)P.U, (FT*)P.L, P.piv,
-                                              P.info);
-      }
+      for (int part = 0; part < kSplitLanes<NN>; ++part)
+        b_factor_lu_split<NN, FT, kSplitLanes<NN>>(tile, part, P.sh, P.sbuf, (FT*)P.U, (FT*)P.L,
+                                                   P.piv, P.info);
     });
   });
 }

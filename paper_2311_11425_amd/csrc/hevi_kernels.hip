@@ -97,8 +97,9 @@ __global__ __launch_bounds__(64) void k_factor_lu_split(HeviShapeDev sh, const d
                                                         FT* Ub, FT* __restrict__ Lb,
                                                         uint8_t* __restrict__ piv,
                                                         HeviDevInfo* info) {
-  b_factor_lu_split<N, FT, kLuLanes>((int64_t)(blockIdx.x / kLuLanes),
-                                     (int)(blockIdx.x % kLuLanes), sh, sbuf, Ub, Lb, piv, info);
+  b_factor_lu_split<N, FT, kSplitLanes<N>>((int64_t)(blockIdx.x / kSplitLanes<N>),
+                                           (int)(blockIdx.x % kSplitLanes<N>), sh, sbuf, Ub, Lb,
+                                           piv, info);
 }
 
 template <int N, typename FT>
@@ -111,17 +112,6 @@ __global__ __launch_bounds__(64) void k_factor_fused(HeviShapeDev sh, double lam
   b_factor_fused_split<N, FT, kLuLanes>((int64_t)(blockIdx.x / kLuLanes),
                                         (int)(blockIdx.x % kLuLanes), sh, Gll<N>{}, lambda, ops,
                                         Ub, Lb, piv, info, lds);
-}
-
-template <int N, typename FT>
-__global__ __launch_bounds__(64) void k_factor_lu_lds(HeviShapeDev sh, const double* sbuf, FT* Ub,
-                                                      FT* __restrict__ Lb,
-                                                      uint8_t* __restrict__ piv,
-                                                      HeviDevInfo* info) {
-  __shared__ double lds[LuLdsShape<N>::LDS];
-  constexpr int P = 64 / LuLdsShape<N>::CPW;  // workgroups per tile
-  b_factor_lu_lds<N, FT>((int64_t)(blockIdx.x / P), (int)(blockIdx.x % P), sh, sbuf, Ub, Lb, piv,
-                         info, lds);
 }
 
 template <int N, typename FT, bool FULL>
@@ -254,17 +244,17 @@ struct Factor {
   static hipError_t run(const HeviShapeDev& sh, double lambda, int fp32,
                         const double* ops, double* sbuf, void* Ub, void* Lb, uint8_t* piv,
                         HeviDevInfo* info, hipStream_t st) {
-    if constexpr (N >= kLuLdsMinN) {
-      // the window does not fit in registers: assembly into sbuf, then the LDS
-      // window LU, 64 / CPW workgroups per tile
+    if constexpr (N > 4) {
+      // assembly into sbuf, then the register-window LU split over kSplitLanes<N>
+      // lanes: kSplitLanes<N> workgroups per tile
       const dim3 g((unsigned)sh.ntiles);
       hipLaunchKernelGGL(k_factor_assemble<N>, g, dim3(T * CWF), 0, st, sh, lambda, ops, sbuf);
-      const dim3 gl((unsigned)(sh.ntiles * (64 / LuLdsShape<N>::CPW)));
+      const dim3 g4((unsigned)(sh.ntiles * kSplitLanes<N>));
       if (fp32)
-        hipLaunchKernelGGL((k_factor_lu_lds<N, float>), gl, dim3(T), 0, st, sh, sbuf, (float*)Ub,
-                           (float*)Lb, piv, info);
+        hipLaunchKernelGGL((k_factor_lu_split<N, float>), g4, dim3(T), 0, st, sh, sbuf,
+                           (float*)Ub, (float*)Lb, piv, info);
       else
-        hipLaunchKernelGGL((k_factor_lu_lds<N, double>), gl, dim3(T), 0, st, sh, sbuf,
+        hipLaunchKernelGGL((k_factor_lu_split<N, double>), g4, dim3(T), 0, st, sh, sbuf,
                            (double*)Ub, (double*)Lb, piv, info);
     } else {
       // assembly and LU in one pass, the window split over kLuLanes lanes:
