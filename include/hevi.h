@@ -294,8 +294,9 @@ void hevi_group_free(hevi_group *g);
  * gathers the queued requests into batches -- at most one request per
  * simulation per batch, first come first served -- and runs each batch as
  * one persistent launch per kernel phase over the tiles of all its requests
- * (FP64 and FP32-factor simulations in separate launches), on the server's own
- * stream, with up to 3 batches in flight.  Requests of one simulation run in
+ * (FP64 simulations of at most 106 nodes per column, which take the fused stage
+ * kernel, other FP64 simulations and FP32-factor simulations in separate
+ * launches), on the server's own stream, with up to 3 batches in flight.  Requests of one simulation run in
  * submission order.
  *
  * hevi_serve_create: hbm_budget_bytes bounds the library-owned memory of all

@@ -169,13 +169,17 @@ void launch_batch(hevi_server* S) {
     pick.push_back(*it);
     it = S->queue.erase(it);
   }
-  // FP64 requests first, then FP32-factor requests; most expensive tiles first
+  // launch classes: FP64 requests whose columns fit the fused stage kernel, other
+  // FP64 requests, FP32-factor requests; most expensive tiles first within a class
+  auto cls = [&](const HeviProbDev& d) {
+    return d.fp32 ? 2 : (d.sh.nz <= HEVI_FUSED_MAX_NZ ? 0 : 1);
+  };
   auto cost = [&](const Req& r) {
     const HeviShapeDev& sh = S->sims[r.sim].desc.sh;
     return (double)sh.nz * (sh.N + 1);
   };
   std::stable_sort(pick.begin(), pick.end(), [&](const Req& a, const Req& b) {
-    const int pa = S->sims[a.sim].desc.fp32, pb = S->sims[b.sim].desc.fp32;
+    const int pa = cls(S->sims[a.sim].desc), pb = cls(S->sims[b.sim].desc);
     if (pa != pb) return pa < pb;
     return cost(a) > cost(b);
   });
@@ -185,7 +189,7 @@ void launch_batch(hevi_server* S) {
     sl.h_probs[j].info = sl.d_info + j;
     sl.h_calls[j] = pick[j].call;
   }
-  // one schedule per precision
+  // one schedule per launch class
   struct Sub {
     int lo, hi, fp32, nlo, nhi, maxnz;
     size_t off;
@@ -195,9 +199,9 @@ void launch_batch(hevi_server* S) {
   size_t off = 0;
   for (int j = 0; j < n;) {
     int k = j;
-    const int fp32 = sl.h_probs[j].fp32;
+    const int fp32 = sl.h_probs[j].fp32, c = cls(sl.h_probs[j]);
     int nmin = HEVI_MAXN, nmax = 1, maxnz = 1;
-    while (k < n && sl.h_probs[k].fp32 == fp32) {
+    while (k < n && cls(sl.h_probs[k]) == c) {
       nmin = std::min(nmin, sl.h_probs[k].sh.N);
       nmax = std::max(nmax, sl.h_probs[k].sh.N);
       maxnz = std::max(maxnz, sl.h_probs[k].sh.nz);
