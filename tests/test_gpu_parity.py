@@ -47,6 +47,10 @@ def cases():
                                                     surface_max=1500.0, tilt=0.2, deep=True),
         "N5": lambda: inputs.make_columns(5, 3, 65, profile="isothermal", seed=32),
         "N7": lambda: inputs.make_columns(7, 2, 70, profile="lapse_capped", z_top=60e3, seed=33),
+        "N6": lambda: inputs.make_columns(6, 3, 70, profile="lapse", seed=37),
+        "N8": lambda: inputs.make_columns(8, 2, 66, profile="isothermal", seed=38),
+        # one element: the column is shorter than the LU window
+        "N4_Ne1": lambda: inputs.make_columns(4, 1, 65, profile="isothermal", seed=39),
         "N1": lambda: inputs.make_columns(1, 6, 40, profile="isothermal", seed=34),
         "N2": lambda: inputs.make_columns(2, 4, 40, profile="isothermal", seed=35, tilt=0.1),
         # 161 nodes: past the fused stage kernel's LDS limit (the three-kernel path)
