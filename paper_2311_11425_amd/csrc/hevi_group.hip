@@ -239,9 +239,14 @@ hipError_t launch_range(int phase, int fp32, const HeviProbDev* probs, const Hev
       hipLaunchKernelGGL((km_stage_update<NLO, NHI>), g, b, 0, st, probs, calls, s);
       break;
     case HEVI_PH_STAGE_FUSED:
-      if (fp32 || max_nz > HEVI_FUSED_MAX_NZ) return hipErrorInvalidValue;
-      hipLaunchKernelGGL((km_stage_fused<NLO, NHI>), g, b, (size_t)max_nz * T * sizeof(double),
-                         st, probs, calls, s);
+      // single-order launches only (see the callers)
+      if constexpr (NLO != NHI) {
+        return hipErrorInvalidValue;
+      } else {
+        if (fp32 || max_nz > HEVI_FUSED_MAX_NZ) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((km_stage_fused<NLO, NHI>), g, b, (size_t)max_nz * T * sizeof(double),
+                           st, probs, calls, s);
+      }
       break;
     case HEVI_PH_COMBINE:
       hipLaunchKernelGGL(km_combine, g, b, 0, st, probs, calls, s);

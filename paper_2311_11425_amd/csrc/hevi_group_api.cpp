@@ -155,9 +155,11 @@ hipError_t phase(hevi_group* g, int ph, int slot, hipStream_t st) {
           break;
       }
     } else {
-      // FP64 stage solves of launches whose columns fit the fused kernel's LDS run as
-      // one fused pass; their band-solve and update phases are then already done
-      const bool fused = !fp32 && l.maxnz <= HEVI_FUSED_MAX_NZ;
+      // FP64 stage solves of single-order launches whose columns fit the fused
+      // kernel's LDS run as one fused pass; their band-solve and update phases are
+      // then already done.  (A fused kernel over every order would need the
+      // registers of the largest and spill.)
+      const bool fused = !fp32 && l.nlo == l.nhi && l.maxnz <= HEVI_FUSED_MAX_NZ;
       if (fused && (ph == HEVI_PH_STAGE_BSOLVE || ph == HEVI_PH_STAGE_UPDATE)) continue;
       const int phx = (fused && ph == HEVI_PH_STAGE_RHS) ? HEVI_PH_STAGE_FUSED : ph;
       HeviSched s;

@@ -242,7 +242,7 @@ void launch_batch(hevi_server* S) {
     s.ctr = S->d_ctr;
     const int grid = (int)sb.total;
     const int sweeps = sb.fp32 ? S->sweeps : 0;
-    if (!sb.fp32 && sb.maxnz <= HEVI_FUSED_MAX_NZ) {
+    if (!sb.fp32 && sb.nlo == sb.nhi && sb.maxnz <= HEVI_FUSED_MAX_NZ) {
       okk = okk && ok(hevi_launch_multi(HEVI_PH_STAGE_FUSED, sb.nlo, sb.nhi, 0, sl.d_probs,
                                         sl.d_calls, s, grid, 0, 1e-13, sb.maxnz, S->st));
       continue;
