@@ -223,7 +223,8 @@ hevi_status hevi_sizes(const hevi_shape *shape, hevi_precision prec, size_t *ops
  * Each phase of the step is one persistent launch over the 64-column tiles of
  * all members (HEVI_LAUNCH_ONE), one per distinct order (HEVI_LAUNCH_PER_ORDER)
  * or one plain launch per member (HEVI_LAUNCH_PER_MEMBER); the tiles are handed
- * out most expensive first.  Results do not depend on the plan.
+ * out most expensive first.  The refactor runs one launch per distinct order in
+ * both multi-problem plans.  Results do not depend on the plan.
  * Buffers: per member, caller-owned device state vectors [v][k][c] of the
  * member's shape.  d_Q[1..s-1] receive Q_2..Q_s (d_Q[0] is ignored: Q_1 = q^n),
  * d_S[0..s-1] receive S_1..S_s, d_out receives q^{n+1}; none may alias another

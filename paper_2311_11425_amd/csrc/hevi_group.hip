@@ -110,6 +110,21 @@ __global__ __launch_bounds__(64) void km_factor_lu(const HeviProbDev* __restrict
   });
 }
 
+// Assembly and LU in one pass for one order N <= HEVI_FUSED_FACTOR_MAX_N (launched
+// per order only): the parts of each tile in turn, each lane's LDS rows reused.
+template <int N, typename FT>
+__global__ __launch_bounds__(64) void km_factor_fused(const HeviProbDev* __restrict__ probs,
+                                                      HeviSched s) {
+  constexpr int LPC = kSplitLanes<N>;
+  __shared__ double lds[fused_lds_doubles<N>(LPC)];
+  persist(s, [&](int p, int64_t tile) {
+    const HeviProbDev& P = probs[p];
+    for (int part = 0; part < LPC; ++part)
+      b_factor_fused_split<N, FT, LPC>(tile, part, P.sh, Gll<N>{}, P.lambda, P.ops, (FT*)P.U,
+                                       (FT*)P.L, P.piv, P.info, lds);
+  });
+}
+
 template <int NLO, int NHI>
 __global__ __launch_bounds__(64) void km_stage_rhs(const HeviProbDev* __restrict__ probs,
                                                    const HeviCallDev* __restrict__ calls,
@@ -217,12 +232,25 @@ hipError_t launch_range(int phase, int fp32, const HeviProbDev* probs, const Hev
     case HEVI_PH_APPLY:
       hipLaunchKernelGGL((km_apply<NLO, NHI>), g, b, 0, st, probs, calls, s);
       break;
-    case HEVI_PH_FACTOR_ASSEMBLE:
-      hipLaunchKernelGGL((km_factor_assemble<NLO, NHI>), g, b, 0, st, probs, s);
+    case HEVI_PH_FACTOR_ASSEMBLE:  // the factor phases run per order only
+      if constexpr (NLO != NHI) return hipErrorInvalidValue;
+      else hipLaunchKernelGGL((km_factor_assemble<NLO, NHI>), g, b, 0, st, probs, s);
       break;
     case HEVI_PH_FACTOR_LU:
-      if (fp32) hipLaunchKernelGGL((km_factor_lu<NLO, NHI, float>), g, b, 0, st, probs, s);
-      else hipLaunchKernelGGL((km_factor_lu<NLO, NHI, double>), g, b, 0, st, probs, s);
+      if constexpr (NLO != NHI) {
+        return hipErrorInvalidValue;
+      } else {
+        if (fp32) hipLaunchKernelGGL((km_factor_lu<NLO, NHI, float>), g, b, 0, st, probs, s);
+        else hipLaunchKernelGGL((km_factor_lu<NLO, NHI, double>), g, b, 0, st, probs, s);
+      }
+      break;
+    case HEVI_PH_FACTOR_FUSED:
+      if constexpr (NLO != NHI || NHI > HEVI_FUSED_FACTOR_MAX_N) {
+        return hipErrorInvalidValue;
+      } else {
+        if (fp32) hipLaunchKernelGGL((km_factor_fused<NHI, float>), g, b, 0, st, probs, s);
+        else hipLaunchKernelGGL((km_factor_fused<NHI, double>), g, b, 0, st, probs, s);
+      }
       break;
     case HEVI_PH_STAGE_RHS:
       hipLaunchKernelGGL((km_stage_rhs<NLO, NHI>), g, b, 0, st, probs, calls, s);

@@ -50,6 +50,7 @@ struct hevi_group {
   uint32_t* d_ctr = nullptr;
   hevi_group_plan plan = {HEVI_LAUNCH_ONE, 0, 0};
   std::vector<Launch> launches;
+  std::vector<Launch> factor_launches;  // per order, whatever the plan (not per-member)
   char* d_sched = nullptr;
   hipStream_t cap = nullptr;
   hipGraphExec_t graph[2] = {nullptr, nullptr};
@@ -76,9 +77,9 @@ double tile_cost(const HeviShapeDev& sh) { return (double)sh.nz * (sh.N + 1); }
 // may still be read by queued work, so the device is drained first
 hevi_status build_launches(hevi_group* g) {
   if (!ok(hipDeviceSynchronize())) return HEVI_E_DEVICE;
-  std::vector<Launch> L;
+  std::vector<Launch> L, FL;
   std::vector<char> host;
-  auto add = [&](int nlo, int nhi, std::vector<int> ids) {
+  auto add_to = [&](std::vector<Launch>& out, int nlo, int nhi, std::vector<int> ids) {
     std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) {
       return tile_cost(g->probs[a].sh) > tile_cost(g->probs[b].sh);
     });
@@ -97,23 +98,31 @@ hevi_status build_launches(hevi_group* g) {
     host.resize(host.size() + pad + ps.size() * sizeof(int64_t));
     std::memcpy(host.data() + l.off, pl.data(), a);
     std::memcpy(host.data() + l.off + pad, ps.data(), ps.size() * sizeof(int64_t));
-    L.push_back(l);
+    out.push_back(l);
+  };
+  auto add = [&](int nlo, int nhi, std::vector<int> ids) { add_to(L, nlo, nhi, ids); };
+  auto per_order = [&](std::vector<Launch>& out) {
+    for (int N = HEVI_MAXN; N >= 1; --N) {
+      std::vector<int> ids;
+      for (int i = 0; i < g->n; ++i)
+        if (g->probs[i].sh.N == N) ids.push_back(i);
+      if (!ids.empty()) add_to(out, N, N, ids);
+    }
   };
   if (g->plan.mode == HEVI_LAUNCH_ONE) {
     std::vector<int> all(g->n);
     for (int i = 0; i < g->n; ++i) all[i] = i;
     add(1, HEVI_MAXN, all);
   } else if (g->plan.mode == HEVI_LAUNCH_PER_ORDER) {
-    for (int N = HEVI_MAXN; N >= 1; --N) {
-      std::vector<int> ids;
-      for (int i = 0; i < g->n; ++i)
-        if (g->probs[i].sh.N == N) ids.push_back(i);
-      if (!ids.empty()) add(N, N, ids);
-    }
+    per_order(L);
   } else {
     for (int i = 0; i < g->n; ++i)
       if (g->probs[i].sh.ntiles > 0) L.push_back(Launch{0, 0, i, 0, 0, 0, g->probs[i].sh.nz});
   }
+  // the factorisation runs per order in every multi-problem plan: one pass for the
+  // orders up to HEVI_FUSED_FACTOR_MAX_N, and no kernel compiled for every order
+  // (whose LU would need the registers of the largest)
+  if (g->plan.mode != HEVI_LAUNCH_PER_MEMBER) per_order(FL);
   if (g->d_sched) (void)hipFree(g->d_sched);
   g->d_sched = nullptr;
   if (!host.empty()) {
@@ -123,7 +132,25 @@ hevi_status build_launches(hevi_group* g) {
       return HEVI_E_DEVICE;
   }
   g->launches = L;
+  g->factor_launches = FL;
   return HEVI_OK;
+}
+
+// One persistent multi-problem launch of phase ph over the members of l.
+hipError_t multi(hevi_group* g, const Launch& l, int ph, int slot, hipStream_t st) {
+  const int fp32 = g->prec == HEVI_FP32_REFINE;
+  HeviSched s;
+  const size_t pad = ((size_t)l.m * sizeof(int32_t) + 7) / 8 * 8;
+  s.plist = (const int32_t*)(g->d_sched + l.off);
+  s.pstart = (const int64_t*)(g->d_sched + l.off + pad);
+  s.m = l.m;
+  s.total = l.total;
+  s.ctr = g->d_ctr;
+  const int64_t want = g->plan.grid > 0 ? g->plan.grid : l.total;
+  const int grid = (int)std::min<int64_t>(want, l.total);
+  return hevi_launch_multi(ph, l.nlo, l.nhi, fp32, g->d_probs,
+                           slot >= 0 ? g->d_calls + (size_t)slot * g->n : nullptr, s, grid,
+                           fp32 ? g->sweeps : 0, g->target, l.maxnz, st);
 }
 
 hipError_t phase(hevi_group* g, int ph, int slot, hipStream_t st) {
@@ -162,18 +189,24 @@ hipError_t phase(hevi_group* g, int ph, int slot, hipStream_t st) {
       const bool fused = !fp32 && l.nlo == l.nhi && l.maxnz <= HEVI_FUSED_MAX_NZ;
       if (fused && (ph == HEVI_PH_STAGE_BSOLVE || ph == HEVI_PH_STAGE_UPDATE)) continue;
       const int phx = (fused && ph == HEVI_PH_STAGE_RHS) ? HEVI_PH_STAGE_FUSED : ph;
-      HeviSched s;
-      const size_t pad = ((size_t)l.m * sizeof(int32_t) + 7) / 8 * 8;
-      s.plist = (const int32_t*)(g->d_sched + l.off);
-      s.pstart = (const int64_t*)(g->d_sched + l.off + pad);
-      s.m = l.m;
-      s.total = l.total;
-      s.ctr = g->d_ctr;
-      const int64_t want = g->plan.grid > 0 ? g->plan.grid : l.total;
-      const int grid = (int)std::min<int64_t>(want, l.total);
-      e = hevi_launch_multi(phx, l.nlo, l.nhi, fp32, g->d_probs,
-                            slot >= 0 ? g->d_calls + (size_t)slot * g->n : nullptr, s, grid,
-                            fp32 ? g->sweeps : 0, g->target, l.maxnz, st);
+      e = multi(g, l, phx, slot, st);
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// The factorisation of every member: per member in the per-member plan, else one
+// launch per order (one pass up to HEVI_FUSED_FACTOR_MAX_N, assembly + LU above).
+hipError_t factor(hevi_group* g, hipStream_t st) {
+  if (g->plan.mode == HEVI_LAUNCH_PER_MEMBER) return phase(g, HEVI_PH_FACTOR_ASSEMBLE, -1, st);
+  for (const Launch& l : g->factor_launches) {
+    hipError_t e;
+    if (l.nlo <= HEVI_FUSED_FACTOR_MAX_N) {
+      e = multi(g, l, HEVI_PH_FACTOR_FUSED, -1, st);
+    } else {
+      e = multi(g, l, HEVI_PH_FACTOR_ASSEMBLE, -1, st);
+      if (e == hipSuccess) e = multi(g, l, HEVI_PH_FACTOR_LU, -1, st);
     }
     if (e != hipSuccess) return e;
   }
@@ -182,10 +215,7 @@ hipError_t phase(hevi_group* g, int ph, int slot, hipStream_t st) {
 
 hipError_t enqueue_step(hevi_group* g, int refactor, hipStream_t st) {
   hipError_t e;
-  if (refactor) {
-    if ((e = phase(g, HEVI_PH_FACTOR_ASSEMBLE, -1, st)) != hipSuccess) return e;
-    if ((e = phase(g, HEVI_PH_FACTOR_LU, -1, st)) != hipSuccess) return e;
-  }
+  if (refactor && (e = factor(g, st)) != hipSuccess) return e;
   if ((e = phase(g, HEVI_PH_APPLY, slot_apply(g, 0), st)) != hipSuccess) return e;
   for (int i = 1; i < g->s; ++i) {
     if ((e = phase(g, HEVI_PH_STAGE_RHS, slot_stage(g, i), st)) != hipSuccess) return e;

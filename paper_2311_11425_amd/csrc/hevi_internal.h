@@ -106,8 +106,9 @@ enum HeviPhase {
   HEVI_PH_STAGE_BSOLVE = 4,
   HEVI_PH_STAGE_UPDATE = 5,
   HEVI_PH_COMBINE = 6,
-  HEVI_PH_STAGE_FUSED = 7,  // FP64 rhs + band solve + update, r/u in LDS
-  HEVI_NPHASES = 8
+  HEVI_PH_STAGE_FUSED = 7,   // FP64 rhs + band solve + update, r/u in LDS
+  HEVI_PH_FACTOR_FUSED = 8,  // assembly + LU in one pass (N <= HEVI_FUSED_FACTOR_MAX_N)
+  HEVI_NPHASES = 9
 };
 
 // The fused stage kernel holds n_z doubles per column of its 64-column tile in LDS
@@ -117,6 +118,11 @@ enum HeviPhase {
 // uneven columns, N 3..7: 16.0/26.7/37.0 ms per stage fused at n_z 113, against
 // 14.0/18.5/23.0 ms for the three kernels).
 #define HEVI_FUSED_MAX_NZ 106
+
+// Orders whose factorisation runs as one pass (assembly into LDS inside the LU
+// wavefront); above, the element data would not fit beside the LU window and
+// the assembly is a kernel of its own.
+#define HEVI_FUSED_FACTOR_MAX_N 6
 
 // One persistent launch of `phase` with `grid` workgroups of one wavefront.
 // nlo..nhi: the orders the kernel is compiled for ((n, n) for n = 1..8, or

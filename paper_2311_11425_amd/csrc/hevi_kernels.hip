@@ -108,10 +108,10 @@ __global__ __launch_bounds__(64) void k_factor_fused(HeviShapeDev sh, double lam
                                                      FT* __restrict__ Ub, FT* __restrict__ Lb,
                                                      uint8_t* __restrict__ piv,
                                                      HeviDevInfo* info) {
-  __shared__ double lds[fused_lds_doubles<N>(kLuLanes)];
-  b_factor_fused_split<N, FT, kLuLanes>((int64_t)(blockIdx.x / kLuLanes),
-                                        (int)(blockIdx.x % kLuLanes), sh, Gll<N>{}, lambda, ops,
-                                        Ub, Lb, piv, info, lds);
+  constexpr int LPC = kSplitLanes<N>;
+  __shared__ double lds[fused_lds_doubles<N>(LPC)];
+  b_factor_fused_split<N, FT, LPC>((int64_t)(blockIdx.x / LPC), (int)(blockIdx.x % LPC), sh,
+                                   Gll<N>{}, lambda, ops, Ub, Lb, piv, info, lds);
 }
 
 template <int N, typename FT, bool FULL>
@@ -244,7 +244,7 @@ struct Factor {
   static hipError_t run(const HeviShapeDev& sh, double lambda, int fp32,
                         const double* ops, double* sbuf, void* Ub, void* Lb, uint8_t* piv,
                         HeviDevInfo* info, hipStream_t st) {
-    if constexpr (N > 4) {
+    if constexpr (N > HEVI_FUSED_FACTOR_MAX_N) {
       // assembly into sbuf, then the register-window LU split over kSplitLanes<N>
       // lanes: kSplitLanes<N> workgroups per tile
       const dim3 g((unsigned)sh.ntiles);
@@ -257,10 +257,10 @@ struct Factor {
         hipLaunchKernelGGL((k_factor_lu_split<N, double>), g4, dim3(T), 0, st, sh, sbuf,
                            (double*)Ub, (double*)Lb, piv, info);
     } else {
-      // assembly and LU in one pass, the window split over kLuLanes lanes:
-      // kLuLanes workgroups per tile
+      // assembly and LU in one pass, the window split over kSplitLanes<N> lanes:
+      // kSplitLanes<N> workgroups per tile
       (void)sbuf;
-      const dim3 g2((unsigned)(sh.ntiles * kLuLanes));
+      const dim3 g2((unsigned)(sh.ntiles * kSplitLanes<N>));
       if (fp32)
         hipLaunchKernelGGL((k_factor_fused<N, float>), g2, dim3(T), 0, st, sh, lambda, ops,
                            (float*)Ub, (float*)Lb, piv, info);
