@@ -611,6 +611,7 @@ def main():
              "factor_ms": fac_ms, "apply_op_ms": app_ms,
              "combine_ms": float(np.mean(r["combine_ms"])),
              "factor_plus_stages_column_solves_per_s": 3 * ncols / ((fac_ms + 3 * stage_ms) * 1e-3)}
+        d["factor_u_entries_per_column"] = st.factors.band_entries() / ncols
         queue_stage_errors(checks, d, "stage_rel_err_vs_oracle", st, col, qn, idx)
         res_paths[name] = d
         log(f"{name}: {ms_step:.3f} ms/step, stage solve {stage_ms:.3f} ms, factor {fac_ms:.3f} ms")
@@ -627,10 +628,15 @@ def main():
     prec = PATHS[args.precision][0]
     sz = hevi.sizes(4, 10, precision=prec)
     vec = 5 * nz * 8
+    # factor bytes a solve reads: U rows up to their last nonzero entry (the rest
+    # are exact zeros, not read), all 2N multipliers per node, 2 bytes per node
+    # (pivot and U extent)
+    fsz = 8 if prec == 0 else 4
+    fac_read = (main_path["factor_u_entries_per_column"] + 2 * col["N"] * nz) * fsz + 2 * nz
     # algorithmic bytes of one stage solve, averaged over the 3 stages: the input
     # vectors (q^n, S_1..S_{i-1}, Q_1..Q_{i-1}), the output Q_i, the factors and
     # the compact operator, each once
-    per_col = float(np.mean([(2 * i + 1 + 1) * vec + sz["factors"] + sz["ops"] for i in (1, 2, 3)]))
+    per_col = float(np.mean([(2 * i + 1 + 1) * vec + fac_read + sz["ops"] for i in (1, 2, 3)]))
     stage_s = main_path["stage_solve_ms"]["avg"] * 1e-3
     achieved = per_col * ncols / stage_s / 1e9
     traffic = measured_traffic(args.precision)
@@ -663,7 +669,8 @@ def main():
                      "measured_copy_GBps": copy_gbs,
                      "launch_columns": ncols,
                      "paper_layout_band_factor_bytes_per_column": sz["paper_band"],
-                     "factor_bytes_per_column": sz["factors"]},
+                     "factor_bytes_per_column_stored": sz["factors"],
+                     "factor_bytes_per_column_read": fac_read},
     }
     if not args.no_extra:
         del B, st

@@ -162,6 +162,13 @@ hevi_status hevi_apply_op(hevi_ctx *ctx, const hevi_ops *ops, const double *d_x,
 hevi_status hevi_factor(hevi_ctx *ctx, const hevi_ops *ops, double lambda,
                         hevi_precision prec, hevi_factors **out, hipStream_t stream);
 hevi_status hevi_refactor(hevi_ctx *ctx, hevi_factors *f, double lambda, hipStream_t stream);
+/* U entries the solves read, summed over the valid columns: each U row up to its
+ * last nonzero entry, pivot included (the rest of the 4N + 1 band entries are
+ * exact zeros, which the factorisation records and the solves skip; L is read in
+ * full).  Waits for the stream and copies one byte per node to the host (a
+ * diagnostic, not for the stepping loop). */
+hevi_status hevi_factors_band_entries(hevi_ctx *ctx, const hevi_factors *f, int64_t *u_entries,
+                                      hipStream_t stream);
 hevi_status hevi_factors_check(hevi_ctx *ctx, const hevi_factors *f, hevi_info *info,
                                hipStream_t stream);
 void hevi_factors_free(hevi_factors *f);

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <limits>
 #include <new>
+#include <vector>
 
 #include "hevi.h"
 #include "hevi_internal.h"
@@ -63,7 +64,8 @@ hevi_status read_info(HeviDevInfo* d_info, hipStream_t st, hevi_info* out, bool 
 size_t factor_storage_bytes(const HeviShapeDev& sh, hevi_precision prec) {
   const size_t tn = tiles_nodes(sh);
   const size_t fs = prec == HEVI_FP64 ? sizeof(double) : sizeof(float);
-  size_t b = tn * (4 * sh.N + 1) * fs + tn * 2 * sh.N * fs + tn + tn * HEVI_NWS * sizeof(double);
+  // U, L, two byte planes (pivots, U row extents), stage scratch
+  size_t b = tn * (4 * sh.N + 1) * fs + tn * 2 * sh.N * fs + 2 * tn + tn * HEVI_NWS * sizeof(double);
   if (prec != HEVI_FP64) b += tn * (4 * sh.N + 1) * sizeof(double);
   return b;
 }
@@ -206,7 +208,8 @@ hevi_status hevi_factor(hevi_ctx* ctx, const hevi_ops* ops, double lambda, hevi_
   const int N = sh.N;
   hevi_status s;
   if ((s = dev_alloc(&f->U, tn * (4 * N + 1) * fs)) || (s = dev_alloc(&f->L, tn * 2 * N * fs)) ||
-      (s = dev_alloc(&f->piv, tn)) || (s = dev_alloc(&f->ws, tn * HEVI_NWS * sizeof(double))) ||
+      (s = dev_alloc(&f->piv, 2 * tn)) ||
+      (s = dev_alloc(&f->ws, tn * HEVI_NWS * sizeof(double))) ||
       (s = dev_alloc(&f->d_info, sizeof(HeviDevInfo)))) {
     hevi_factors_free(f);
     return s;
@@ -245,6 +248,27 @@ hevi_status hevi_factors_check(hevi_ctx* ctx, const hevi_factors* f, hevi_info* 
                                hipStream_t stream) {
   if (!ctx || !f) return HEVI_E_INVALID;
   return read_info(f->d_info, stream, info, true);
+}
+
+hevi_status hevi_factors_band_entries(hevi_ctx* ctx, const hevi_factors* f, int64_t* u_entries,
+                                      hipStream_t stream) {
+  if (!ctx || !f || !u_entries) return HEVI_E_INVALID;
+  if (!ok(hipSetDevice(ctx->device))) return HEVI_E_DEVICE;
+  const HeviShapeDev& sh = f->ops->sh;
+  const size_t tn = tiles_nodes(sh);
+  *u_entries = 0;
+  if (tn == 0) return HEVI_OK;
+  std::vector<uint8_t> h(tn);
+  if (!ok(hipStreamSynchronize(stream)) ||
+      !ok(hipMemcpy(h.data(), f->piv + tn, tn, hipMemcpyDeviceToHost)))
+    return HEVI_E_DEVICE;
+  int64_t u = 0;
+  for (int64_t t = 0; t < sh.ntiles; ++t)
+    for (int k = 0; k < sh.nz; ++k)
+      for (int c = 0; c < HEVI_TILE; ++c)
+        if (t * HEVI_TILE + c < sh.ncols) u += h[((size_t)t * sh.nz + k) * HEVI_TILE + c] + 1;
+  *u_entries = u;
+  return HEVI_OK;
 }
 
 void hevi_factors_free(hevi_factors* f) {
@@ -364,7 +388,7 @@ hevi_status hevi_sizes(const hevi_shape* shape, hevi_precision prec, size_t* ops
   const size_t nz = (size_t)shape->n_elem * N + 1;
   const size_t fsz = prec == HEVI_FP64 ? 8 : 4;
   if (ops_bytes) *ops_bytes = nz * HEVI_NOPS * sizeof(double);
-  if (factor_bytes) *factor_bytes = nz * ((4 * N + 1) + 2 * N) * fsz + nz;
+  if (factor_bytes) *factor_bytes = nz * ((4 * N + 1) + 2 * N) * fsz + 2 * nz;
   if (paper_bytes) {
     const size_t n = 5 * nz;
     const size_t ldab = 3 * 5 * (N + 1) - 2;

@@ -482,6 +482,21 @@ __device__ __forceinline__ double from_next(double v) {
   const int lo = from_next<LPC>(__double2loint(v)), hi = from_next<LPC>(__double2hiint(v));
   return __hiloint2double(hi, lo);
 }
+// maximum over the LPC = 2 or 4 lanes of the group (DPP quad_perm swaps)
+template <int LPC>
+__device__ __forceinline__ int group_max(int v) {
+  v = max(v, __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false));  // lanes 1,0,3,2
+  if constexpr (LPC == 4) v = max(v, __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false));
+  return v;
+}
+
+// The pivot array holds two byte planes of plane_size(sh) bytes each, laid out
+// like the factors: the pivot offset of step j, and the band offset of the last
+// nonzero entry of U row j.  U entries beyond it are exact zeros, which the
+// solves do not read (about half of each row at N = 4).
+__device__ __forceinline__ size_t plane_size(const HeviShapeDev& sh) {
+  return (size_t)sh.ntiles * sh.nz * T;
+}
 
 // The band LU with each column's window split over LPC consecutive lanes: lane
 // h holds window columns hH .. hH+H-1, H = ceil((4N+1) / LPC) (columns past 4N
@@ -503,7 +518,8 @@ template <int N, typename FT, int LPC>
 __device__ __forceinline__ void split_step(double (&Wn)[2 * N + 1][(4 * N + LPC) / LPC], int j,
                                            int nz, int h, int s0, int64_t tile, int lane,
                                            FT* Ub, FT* __restrict__ Lb,
-                                           uint8_t* __restrict__ piv, bool& singular) {
+                                           uint8_t* __restrict__ piv, size_t plane,
+                                           bool& singular) {
   constexpr int B = 2 * N, W = 4 * N + 1, H = (W + LPC - 1) / LPC;
   if (j >= 0) {  // elimination step j (rows 0..2N are only shifted in)
     // pivot search on window column 0 (first lane of the group)
@@ -528,6 +544,12 @@ __device__ __forceinline__ void split_step(double (&Wn)[2 * N + 1][(4 * N + LPC)
         for (int t = 1; t <= B; ++t) Wn[t][m] = (p == t) ? v0 : Wn[t][m];
       }
     }
+    // the last nonzero entry of U row j (the pivot itself is nonzero)
+    int ue = 0;
+#pragma unroll
+    for (int m = 0; m < H; ++m)
+      if (s0 + m < W && Wn[0][m] != 0.0) ue = s0 + m;
+    ue = group_max<LPC>(ue);
     FT* urow = Ub + tix(tile, nz, j, W, 0, lane);
 #pragma unroll
     for (int m = 0; m < H; ++m)
@@ -537,7 +559,9 @@ __device__ __forceinline__ void split_step(double (&Wn)[2 * N + 1][(4 * N + LPC)
 #pragma unroll
     for (int t = 1; t <= B; ++t) l[t] = from_first<LPC>(Wn[t][0] * inv);
     if (h == 0) {
-      piv[tix(tile, nz, j, 1, 0, lane)] = (uint8_t)p;
+      const size_t pi = tix(tile, nz, j, 1, 0, lane);
+      piv[pi] = (uint8_t)p;
+      piv[plane + pi] = (uint8_t)ue;
       FT* lrow = Lb + tix(tile, nz, j, B, 0, lane);
 #pragma unroll
       for (int t = 1; t <= B; ++t) stnt(lrow + (t - 1) * T, (FT)l[t]);
@@ -592,7 +616,8 @@ __device__ __forceinline__ void b_factor_lu_split(int64_t tile, int part, HeviSh
     for (int d = 0; d < PFL; ++d) {
       const int j = j0 + d;
       if (j < nz) {
-        split_step<N, FT, LPC>(Wn, j, nz, h, s0, tile, lane, Ub, Lb, piv, singular);
+        split_step<N, FT, LPC>(Wn, j, nz, h, s0, tile, lane, Ub, Lb, piv, plane_size(sh),
+                               singular);
         // new bottom row j + 2N + 1 from the ring; refill the slot
         const int rn = j + B + 1;
 #pragma unroll
@@ -635,6 +660,7 @@ __device__ __forceinline__ void b_factor_fused_split(int64_t tile, int part, Hev
   const int s0 = h * H;
   const OpsView op{ops, tile, nz, lane};
   const double l2 = lambda * lambda;
+  const size_t plane = plane_size(sh);
   double* slot = lds + threadIdx.x;  // row a, window column m of this lane: slot[(a * H + m) * T]
   double Wn[B + 1][H];
 #pragma unroll
@@ -701,7 +727,7 @@ __device__ __forceinline__ void b_factor_fused_split(int64_t tile, int part, Hev
 #pragma unroll
     for (int a = 0; a <= N; ++a) {
       if (a < na) {
-        split_step<N, FT, LPC>(Wn, j, nz, h, s0, tile, lane, Ub, Lb, piv, singular);
+        split_step<N, FT, LPC>(Wn, j, nz, h, s0, tile, lane, Ub, Lb, piv, plane, singular);
 #pragma unroll
         for (int m = 0; m < H; ++m) Wn[B][m] = slot[(a * H + m) * T];
         ++j;
@@ -721,7 +747,7 @@ __device__ __forceinline__ void b_factor_fused_split(int64_t tile, int part, Hev
   }
   // rows past the top are zero
   while (j < nz) {
-    split_step<N, FT, LPC>(Wn, j, nz, h, s0, tile, lane, Ub, Lb, piv, singular);
+    split_step<N, FT, LPC>(Wn, j, nz, h, s0, tile, lane, Ub, Lb, piv, plane, singular);
 #pragma unroll
     for (int m = 0; m < H; ++m) Wn[B][m] = 0.0;
     ++j;
@@ -745,9 +771,9 @@ enum { WS_R = 0, WS_U = 1, WS_VR = 2, WS_VT = 3, WS_T = 4, WS_D = 5, WS_B = 6, W
 // refilled as soon as a slot is consumed, while it works on the current row.
 template <int N, typename FT, bool LDSRU = false>
 __device__ __forceinline__ void band_solve(const FT* __restrict__ Ub, const FT* __restrict__ Lb,
-                                           const uint8_t* __restrict__ piv, double* ws,
-                                           int64_t tile, int nz, int lane, int fi, int fo,
-                                           double* ru = nullptr) {
+                                           const uint8_t* __restrict__ piv, size_t plane,
+                                           double* ws, int64_t tile, int nz, int lane, int fi,
+                                           int fo, double* ru = nullptr) {
   // right-hand side and solution: scratch fields fi / fo, or (LDSRU) one array
   // ru[k * 64 + lane] in LDS used in place
   auto S = [&](int k, int f) -> double& {
@@ -755,6 +781,10 @@ __device__ __forceinline__ void band_solve(const FT* __restrict__ Ub, const FT* 
     else return ws[tix(tile, nz, k, HEVI_NWS, f, lane)];
   };
   constexpr int B = 2 * N, K = 4 * N, PF = 3, PB = 2;
+  // U row extents (see plane_size): entries past them are zeros and are not
+  // loaded; each ring slot knows the extent of the row it loads next
+  const uint8_t* ue_p = piv + plane;
+  auto pidx = [&](int k) { return tix(tile, nz, k, 1, 0, lane); };
   // ---- forward: row swaps and unit-lower elimination ----
   double y[B + 1];
 #pragma unroll
@@ -767,7 +797,7 @@ __device__ __forceinline__ void band_solve(const FT* __restrict__ Ub, const FT* 
 #pragma unroll
   for (int d = 0; d < PF; ++d) {
     const int jj = d < nz ? d : nz - 1;
-    pv[d] = piv[tix(tile, nz, jj, 1, 0, lane)];
+    pv[d] = piv[pidx(jj)];
 #pragma unroll
     for (int t = 0; t < B; ++t) lr[d][t] = ld(Lb + tix(tile, nz, jj, B, t, lane));
     const int rn = d + B + 1;
@@ -795,7 +825,7 @@ __device__ __forceinline__ void band_solve(const FT* __restrict__ Ub, const FT* 
         // refill the consumed slot with row j + PF
         const int jn = j + PF;
         const int jj = jn < nz ? jn : nz - 1;
-        pv[d] = piv[tix(tile, nz, jj, 1, 0, lane)];
+        pv[d] = piv[pidx(jj)];
 #pragma unroll
         for (int t = 0; t < B; ++t) lr[d][t] = ld(Lb + tix(tile, nz, jj, B, t, lane));
         const int rn = jn + B + 1;
@@ -809,12 +839,19 @@ __device__ __forceinline__ void band_solve(const FT* __restrict__ Ub, const FT* 
 #pragma unroll
   for (int t = 0; t <= K; ++t) xw[t] = 0.0;
   double ur[PB][K + 1], yin[PB];
+  int unext[PB];
 #pragma unroll
   for (int d = 0; d < PB; ++d) {
     const int jr = nz - 1 - d;
     const int jj = jr >= 0 ? jr : 0;
+    const int ue = ue_p[pidx(jj)];
 #pragma unroll
-    for (int t = 0; t <= K; ++t) ur[d][t] = ld(Ub + tix(tile, nz, jj, K + 1, t, lane));
+    for (int t = 0; t <= K; ++t) {
+      double v = 0.0;
+      if (t <= ue) v = ld(Ub + tix(tile, nz, jj, K + 1, t, lane));
+      ur[d][t] = v;
+    }
+    unext[d] = ue_p[pidx(max(jr - PB, 0))];
     yin[d] = S(jj, fo);
   }
   for (int j0 = nz - 1; j0 >= 0; j0 -= PB) {
@@ -833,8 +870,14 @@ __device__ __forceinline__ void band_solve(const FT* __restrict__ Ub, const FT* 
         // refill the consumed slot with row j - PB
         const int jr = j - PB;
         const int jj = jr >= 0 ? jr : 0;
+        const int ue = unext[d];
 #pragma unroll
-        for (int t = 0; t <= K; ++t) ur[d][t] = ld(Ub + tix(tile, nz, jj, K + 1, t, lane));
+        for (int t = 0; t <= K; ++t) {
+          double v = 0.0;
+          if (t <= ue) v = ld(Ub + tix(tile, nz, jj, K + 1, t, lane));
+          ur[d][t] = v;
+        }
+        unext[d] = ue_p[pidx(max(jr - PB, 0))];
         yin[d] = S(jj, fo);
       }
     }
@@ -850,8 +893,8 @@ template <int N, typename FT>
 __device__ void reduced_refine(Gll<N> tab, const OpsView& op, int Ne, double* ws,
                                int64_t tile, int lane, bool valid, double lambda,
                                const FT* __restrict__ Ub, const FT* __restrict__ Lb,
-                               const uint8_t* __restrict__ piv, int max_sweeps, double rel_target,
-                               int* sweeps_out, double* corr_out) {
+                               const uint8_t* __restrict__ piv, size_t plane, int max_sweeps,
+                               double rel_target, int* sweeps_out, double* corr_out) {
   const int nz = op.nz;
   int sweeps = 0;
   double corr = INFINITY;
@@ -869,7 +912,7 @@ __device__ void reduced_refine(Gll<N> tab, const OpsView& op, int Ne, double* ws
       const double Su = (k == 0 || k == nz - 1) ? u : u - l2 * Ku;
       ws[tix(tile, nz, k, HEVI_NWS, WS_T, lane)] = ws[tix(tile, nz, k, HEVI_NWS, WS_R, lane)] - Su;
     }
-    band_solve<N, FT>(Ub, Lb, piv, ws, tile, nz, lane, WS_T, WS_D);
+    band_solve<N, FT>(Ub, Lb, piv, plane, ws, tile, nz, lane, WS_T, WS_D);
     if (need) {
       double d2 = 0.0, u2 = 0.0;
       for (int k = 0; k < nz; ++k) {
@@ -1157,11 +1200,12 @@ __device__ __forceinline__ void b_stage_solve(int64_t tile_, HeviShapeDev sh, Gl
   }
 
   // ---- pass 2: S u = r (+ reduced FP64 refinement when the factors are FP32) ----
-  band_solve<N, FT>(Ub, Lb, piv, ws, tile, nz, lane, WS_R, WS_U);
+  band_solve<N, FT>(Ub, Lb, piv, plane_size(sh), ws, tile, nz, lane, WS_R, WS_U);
   int sweeps = 0;
   double relres = 0.0;
   if (max_sweeps > 0)
-    reduced_refine<N, FT>(tab, op, Ne, ws, tile, lane, valid, lambda, Ub, Lb, piv, max_sweeps,
+    reduced_refine<N, FT>(tab, op, Ne, ws, tile, lane, valid, lambda, Ub, Lb, piv,
+                          plane_size(sh), max_sweeps,
                           rel_target, &sweeps, &relres);
 
   if constexpr (!FULL) {
@@ -1175,12 +1219,13 @@ __device__ __forceinline__ void b_stage_solve(int64_t tile_, HeviShapeDev sh, Gl
     for (int it = 0; it < full_sweeps; ++it) {
       residual_pass<N>(tab, op, Ne, ws, tile, lane, lambda, WS_B, WS_X, WS_S);
       reduced_rhs_pass<N>(tab, op, Ne, ws, tile, lane, lambda, WS_S);
-      band_solve<N, FT>(Ub, Lb, piv, ws, tile, nz, lane, WS_R, WS_U);
+      band_solve<N, FT>(Ub, Lb, piv, plane_size(sh), ws, tile, nz, lane, WS_R, WS_U);
       if (max_sweeps > 0) {
         // the correction only needs the accuracy of the outer sweep
         int sw = 0;
         double cr = 0.0;
-        reduced_refine<N, FT>(tab, op, Ne, ws, tile, lane, valid, lambda, Ub, Lb, piv, 1,
+        reduced_refine<N, FT>(tab, op, Ne, ws, tile, lane, valid, lambda, Ub, Lb, piv,
+                              plane_size(sh), 1,
                               rel_target, &sw, &cr);
         sweeps += sw;
       }
@@ -1371,12 +1416,13 @@ __device__ __forceinline__ void b_stage_bsolve(int64_t tile_, HeviShapeDev sh, G
   const int64_t c = tile * T + lane;
   const bool valid = c < sh.ncols;
   const int nz = sh.nz;
-  band_solve<N, FT>(Ub, Lb, piv, ws, tile, nz, lane, WS_R, WS_U);
+  band_solve<N, FT>(Ub, Lb, piv, plane_size(sh), ws, tile, nz, lane, WS_R, WS_U);
   if (REFINE && max_sweeps > 0) {
     OpsView op{ops, tile, nz, lane};
     int sweeps = 0;
     double corr = 0.0;
-    reduced_refine<N, FT>(tab, op, sh.Ne, ws, tile, lane, valid, lambda, Ub, Lb, piv, max_sweeps,
+    reduced_refine<N, FT>(tab, op, sh.Ne, ws, tile, lane, valid, lambda, Ub, Lb, piv,
+                          plane_size(sh), max_sweeps,
                           rel_target, &sweeps, &corr);
     if (valid) {
       if (!(corr <= rel_target)) flag(info, 6 /*HEVI_E_NOT_CONVERGED*/, c);

@@ -181,7 +181,8 @@ __global__ __launch_bounds__(64) void km_stage_fused(const HeviProbDev* __restri
       constexpr int NN = decltype(n)::value;
       b_stage_rhs<NN, true>(tile, P.sh, Gll<NN>{}, P.lambda, P.ops, P.ws, C.E, C.Q, C.out, ru);
       __syncthreads();
-      band_solve<NN, double, true>((const double*)P.U, (const double*)P.L, P.piv, P.ws, tile,
+      band_solve<NN, double, true>((const double*)P.U, (const double*)P.L, P.piv,
+                                   plane_size(P.sh), P.ws, tile,
                                    P.sh.nz, (int)threadIdx.x, WS_R, WS_U, ru);
       __syncthreads();
       b_stage_update<NN, true>(tile, P.sh, Gll<NN>{}, P.lambda, P.ops, P.ws, C.out, P.info, ru);

@@ -145,7 +145,8 @@ __global__ __launch_bounds__(64, kStreamWaves<N>) void k_stage_fused(HeviShapeDe
   const int64_t tile = blockIdx.x;
   b_stage_rhs<N, true>(tile, sh, Gll<N>{}, lambda, ops, ws, E, Q, Qi, ru);
   __syncthreads();
-  band_solve<N, double, true>(Ub, Lb, piv, ws, tile, sh.nz, (int)threadIdx.x, WS_R, WS_U, ru);
+  band_solve<N, double, true>(Ub, Lb, piv, plane_size(sh), ws, tile, sh.nz, (int)threadIdx.x, WS_R,
+                              WS_U, ru);
   __syncthreads();
   b_stage_update<N, true>(tile, sh, Gll<N>{}, lambda, ops, ws, Qi, info, ru);
 }

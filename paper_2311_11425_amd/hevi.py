@@ -23,7 +23,8 @@ STATUS = {0: "HEVI_OK", 1: "HEVI_E_INVALID", 2: "HEVI_E_SHAPE", 3: "HEVI_E_NOMEM
 # every symbol include/hevi.h declares
 EXPORTS = ["hevi_create", "hevi_destroy", "hevi_status_str", "hevi_build_column_ops",
            "hevi_ops_check", "hevi_ops_free", "hevi_apply_op", "hevi_factor", "hevi_refactor",
-           "hevi_factors_check", "hevi_factors_free", "hevi_stage_solve", "hevi_combine",
+           "hevi_factors_check", "hevi_factors_band_entries", "hevi_factors_free",
+           "hevi_stage_solve", "hevi_combine",
            "hevi_tableau", "hevi_sizes", "hevi_group_create", "hevi_group_set_plan",
            "hevi_group_get_plan", "hevi_group_step", "hevi_group_check", "hevi_group_autotune",
            "hevi_group_free", "hevi_serve_create", "hevi_serve_register", "hevi_serve_submit",
@@ -113,6 +114,8 @@ def load():
         "hevi_factor": ([_vp, _vp, dbl, ctypes.c_int, pp, _vp], ctypes.c_int),
         "hevi_refactor": ([_vp, _vp, dbl, _vp], ctypes.c_int),
         "hevi_factors_check": ([_vp, _vp, ctypes.POINTER(Info), _vp], ctypes.c_int),
+        "hevi_factors_band_entries": ([_vp, _vp, ctypes.POINTER(ctypes.c_int64), _vp],
+                                      ctypes.c_int),
         "hevi_factors_free": ([_vp], None),
         "hevi_stage_solve": ([_vp, _vp, i32, pp, pd, i32, pp, pd, _vp, ctypes.POINTER(Refine),
                               ctypes.POINTER(Info), _vp], ctypes.c_int),
@@ -233,6 +236,14 @@ class Factors:
         code = load().hevi_factors_check(self.ctx.handle, self.handle, ctypes.byref(inf),
                                          _stream(stream))
         return code, inf.as_dict()
+
+    def band_entries(self, stream=None):
+        """U entries the solves read (each row up to its last nonzero), summed over
+        the columns (see hevi_factors_band_entries)."""
+        u = ctypes.c_int64(0)
+        _check(load().hevi_factors_band_entries(self.ctx.handle, self.handle, ctypes.byref(u),
+                                                _stream(stream)), "hevi_factors_band_entries")
+        return u.value
 
     def free(self):
         if self.handle:

@@ -65,8 +65,8 @@ def test_sizes():
     s = hevi.sizes(4, 10)
     nz = 41
     assert s["ops"] == nz * 8 * 8
-    assert s["factors"] == nz * (17 + 8) * 8 + nz
-    assert hevi.sizes(4, 10, precision=1)["factors"] == nz * 25 * 4 + nz
+    assert s["factors"] == nz * (17 + 8) * 8 + 2 * nz
+    assert hevi.sizes(4, 10, precision=1)["factors"] == nz * 25 * 4 + 2 * nz
     # paper layout: LAPACK band with kl = ku = 5(N+1)-1, ldab = 2kl+ku+1 rows
     n = 5 * nz
     kl = 5 * 5 - 1

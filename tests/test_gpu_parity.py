@@ -279,6 +279,21 @@ def test_single_element_single_order(ctx):
         assert relerr_cols(host(x), oracle.solve_batch(col, 17.0, b, refine=1)) < 1e-14
 
 
+def test_factor_band_entries(ctx):
+    """The U row extents the LU records: every row holds its pivot and no row holds
+    more than the band; at this shape about half the band is exact zeros."""
+    from paper_2311_11425_amd.driver import ColumnBatch
+    col = cases()["cfg2_ragged300"]()
+    B = ColumnBatch(ctx, col)
+    nc, nz, N = col["z"].shape[1], col["nz"], col["N"]
+    for prec in (0, 1):
+        f = ctx.factor(B.ops, lam_for(col), prec)
+        u = f.band_entries()
+        assert nc * nz <= u <= nc * nz * (4 * N + 1)
+        assert u < 0.6 * nc * nz * (4 * N + 1)
+        f.free()
+
+
 def test_zero_columns(ctx):
     col = inputs.make_columns(4, 8, 1, seed=42)
     from paper_2311_11425_amd import hevi
