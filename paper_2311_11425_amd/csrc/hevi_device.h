@@ -781,8 +781,12 @@ __device__ __forceinline__ void band_solve(const FT* __restrict__ Ub, const FT* 
     else return ws[tix(tile, nz, k, HEVI_NWS, f, lane)];
   };
   constexpr int B = 2 * N, K = 4 * N, PF = 3, PB = 2;
-  // U row extents (see plane_size): entries past them are zeros and are not
-  // loaded; each ring slot knows the extent of the row it loads next
+  // U row extents (see plane_size): entries past them are zeros and, with FP64
+  // factors, are not loaded; each ring slot knows the extent of the row it loads
+  // next.  The FP32-factor solves run inside refinement sweeps, where the extra
+  // code of the skipping pushed the kernel into scratch spills: they load the
+  // full rows.
+  constexpr bool SKIP = std::is_same<FT, double>::value;
   const uint8_t* ue_p = piv + plane;
   auto pidx = [&](int k) { return tix(tile, nz, k, 1, 0, lane); };
   // ---- forward: row swaps and unit-lower elimination ----
@@ -844,14 +848,14 @@ __device__ __forceinline__ void band_solve(const FT* __restrict__ Ub, const FT* 
   for (int d = 0; d < PB; ++d) {
     const int jr = nz - 1 - d;
     const int jj = jr >= 0 ? jr : 0;
-    const int ue = ue_p[pidx(jj)];
+    const int ue = SKIP ? ue_p[pidx(jj)] : K;
 #pragma unroll
     for (int t = 0; t <= K; ++t) {
       double v = 0.0;
-      if (t <= ue) v = ld(Ub + tix(tile, nz, jj, K + 1, t, lane));
+      if (!SKIP || t <= ue) v = ld(Ub + tix(tile, nz, jj, K + 1, t, lane));
       ur[d][t] = v;
     }
-    unext[d] = ue_p[pidx(max(jr - PB, 0))];
+    unext[d] = SKIP ? ue_p[pidx(max(jr - PB, 0))] : K;
     yin[d] = S(jj, fo);
   }
   for (int j0 = nz - 1; j0 >= 0; j0 -= PB) {
@@ -874,10 +878,10 @@ __device__ __forceinline__ void band_solve(const FT* __restrict__ Ub, const FT* 
 #pragma unroll
         for (int t = 0; t <= K; ++t) {
           double v = 0.0;
-          if (t <= ue) v = ld(Ub + tix(tile, nz, jj, K + 1, t, lane));
+          if (!SKIP || t <= ue) v = ld(Ub + tix(tile, nz, jj, K + 1, t, lane));
           ur[d][t] = v;
         }
-        unext[d] = ue_p[pidx(max(jr - PB, 0))];
+        if constexpr (SKIP) unext[d] = ue_p[pidx(max(jr - PB, 0))];
         yin[d] = S(jj, fo);
       }
     }
