@@ -13,6 +13,14 @@ first stage, constant diagonal a~_ii, b = b~ to conserve linear invariants).
   the observed third-order convergence on a linear column (tests).  Parity of
   the coefficient values themselves is unpinned by the paper.
 
+* ARS343 = ARS(3,4,3) of Ascher, Ruuth & Spiteri (1997), one of the further
+  integrators the paper lists (Sec. 5; coefficients not printed there).  The
+  implicit part is the L-stable three-stage DIRK with gamma the root in (1/3, 1/2)
+  of 6 g^3 - 18 g^2 + 9 g - 1 = 0; the explicit coefficients are the published
+  10-digit values, with a_31 and a_41 taken from the row sums so that c = c~
+  holds exactly.  Its order conditions then hold to the published digits
+  (about 1e-10); pinned by those and by observed third-order convergence.
+
 Values are exact: rationals as fractions.Fraction, sqrt(2)-based entries as
 mpmath numbers at 50 digits; ``as_float`` converts to float64 arrays.
 """
@@ -58,6 +66,20 @@ def ark3():
     b = [F(1471266399579, 7840856788654), F(-4482444167858, 7529755066697),
          F(11266239266428, 11593286722821), g]
     return {"name": "ARK3", "Aexp": Aexp, "Aimp": Aimp, "b": b, "order": 3}
+
+
+def ars343():
+    g = mp.findroot(lambda x: 6 * x ** 3 - 18 * x ** 2 + 9 * x - 1, mp.mpf("0.4358665215"))
+    b1 = -3 * g ** 2 / 2 + 4 * g - mp.mpf(1) / 4
+    b2 = 3 * g ** 2 / 2 - 5 * g + mp.mpf(5) / 4
+    c3 = (1 + g) / 2
+    a32 = mp.mpf("0.3966543747")
+    a42 = a43 = mp.mpf("0.5529291479")
+    z = mp.mpf(0)
+    Aexp = [[z, z, z, z], [g, z, z, z], [c3 - a32, a32, z, z], [1 - a42 - a43, a42, a43, z]]
+    Aimp = [[z, z, z, z], [z, g, z, z], [z, (1 - g) / 2, g, z], [z, b1, b2, g]]
+    b = [z, b1, b2, g]
+    return {"name": "ARS343", "Aexp": Aexp, "Aimp": Aimp, "b": b, "order": 3}
 
 
 def as_float(tab):

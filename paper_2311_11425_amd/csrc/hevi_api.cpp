@@ -355,6 +355,28 @@ hevi_status hevi_tableau(const char* name, int32_t* s, double* a_exp, double* a_
     b[0] = dl; b[1] = dl; b[2] = gm;
     return HEVI_OK;
   }
+  if (!std::strcmp(name, "ARS343")) {
+    // ARS(3,4,3) (Ascher, Ruuth and Spiteri, 1997): gamma is the root in (1/3, 1/2)
+    // of 6 g^3 - 18 g^2 + 9 g - 1; the last implicit row is b = (0, b1, b2, gamma)
+    // with b1 = -3 g^2 / 2 + 4 g - 1/4, b2 = 3 g^2 / 2 - 5 g + 5/4; the explicit
+    // coefficients are the published 10-digit values, a_31 = c_3 - a_32 and
+    // a_41 = 1 - a_42 - a_43 (row sums equal to the implicit ones).  Doubles are
+    // the correctly rounded values.
+    const double g = 0.435866521508459, b1 = 1.20849664917601, b2 = -0.644363170684469;
+    const double E[16] = {0, 0, 0, 0,
+                          g, 0, 0, 0,
+                          0.3212788860542295, 0.3966543747, 0, 0,
+                          -0.1058582958, 0.5529291479, 0.5529291479, 0};
+    const double I[16] = {0, 0, 0, 0,
+                          0, g, 0, 0,
+                          0, 0.2820667392457705, g, 0,
+                          0, b1, b2, g};
+    *s = 4;
+    std::memcpy(a_exp, E, sizeof(E));
+    std::memcpy(a_imp, I, sizeof(I));
+    b[0] = 0.0; b[1] = b1; b[2] = b2; b[3] = g;
+    return HEVI_OK;
+  }
   if (!std::strcmp(name, "ARK3")) {
     // ARK3(2)4L[2]SA (Kennedy and Carpenter, 2003)
     const double g = 1767732205903.0 / 4055673282236.0;

@@ -46,7 +46,8 @@ def test_create_rejects_missing_device():
 
 
 @pytest.mark.parametrize("name,ref", [("ARK2", otab.ark2("b")), ("ARK2b", otab.ark2("b")),
-                                      ("ARK2a", otab.ark2("a")), ("ARK3", otab.ark3())])
+                                      ("ARK2a", otab.ark2("a")), ("ARK3", otab.ark3()),
+                                      ("ARS343", otab.ars343())])
 def test_tableau_matches_independent_transcription(name, ref):
     t = hevi.tableau(name)
     r = otab.as_float(ref)

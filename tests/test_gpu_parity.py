@@ -142,7 +142,7 @@ def test_solve_identity_at_zero_lambda(ctx):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("which", ["ARK2_cfg1", "ARK3_cfg2_sample"])
+@pytest.mark.parametrize("which", ["ARK2_cfg1", "ARK3_cfg2_sample", "ARS343_cfg1"])
 def test_ark_step_parity(ctx, which, prec):
     """Stage increments Q_i - q^n and q^{n+1} - q^n against the oracle's ARK step.
 
@@ -154,6 +154,9 @@ def test_ark_step_parity(ctx, which, prec):
     if which == "ARK2_cfg1":
         col, tabname, tab, dt, nsteps = inputs.config1(heterogeneous=True), "ARK2", \
             tableaux.as_float(tableaux.ark2("b")), 30.0, 2
+    elif which == "ARS343_cfg1":
+        col, tabname, tab, dt, nsteps = inputs.config1(heterogeneous=True), "ARS343", \
+            tableaux.as_float(tableaux.ars343()), 30.0, 2
     else:
         col, tabname, tab, dt, nsteps = inputs.config2(ncols=200), "ARK3", \
             tableaux.as_float(tableaux.ark3()), 300.0, 2
@@ -190,7 +193,7 @@ MODES = {  # name: (precision, refine, bar)
 
 
 @pytest.mark.parametrize("mode", list(MODES))
-@pytest.mark.parametrize("which", ["ARK2_cfg1", "ARK3_cfg2_sample"])
+@pytest.mark.parametrize("which", ["ARK2_cfg1", "ARK3_cfg2_sample", "ARS343_cfg1"])
 def test_ark_stagewise_parity(ctx, which, mode):
     """Each stage solve of a GPU ARK step: q^ is rebuilt on the host from the GPU's
     own Q_j and S_j, solved by the oracle, and compared with the GPU's
@@ -207,6 +210,8 @@ def test_ark_stagewise_parity(ctx, which, mode):
     from paper_2311_11425_amd.driver import ArkStepper, ColumnBatch
     if which == "ARK2_cfg1":
         col, tabname, dt = inputs.config1(heterogeneous=True), "ARK2", 30.0
+    elif which == "ARS343_cfg1":
+        col, tabname, dt = inputs.config1(heterogeneous=True), "ARS343", 30.0
     else:
         col, tabname, dt = inputs.config2(ncols=200), "ARK3", 300.0
     prec, refine, bar = MODES[mode]

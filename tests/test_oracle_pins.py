@@ -434,11 +434,14 @@ def _conds(tab):
     return out
 
 
-@pytest.mark.parametrize("tab", [tableaux.ark2("b"), tableaux.ark2("a"), tableaux.ark3()])
+@pytest.mark.parametrize("tab", [tableaux.ark2("b"), tableaux.ark2("a"), tableaux.ark3(),
+                                 tableaux.ars343()])
 def test_p13_order_conditions(tab):
     mp.mp.dps = 50
+    # ARS(3,4,3)'s explicit coefficients are published to 10 digits
+    tol = 1e-9 if tab["name"] == "ARS343" else 1e-11
     for k, v in _conds(tab).items():
-        assert abs(float(v)) < 1e-11, (tab["name"], k, float(v))
+        assert abs(float(v)) < tol, (tab["name"], k, float(v))
     s = len(tab["b"])
     # ESDIRK structure: explicit first stage, constant diagonal, b = last implicit row
     assert all(tab["Aimp"][0][j] == 0 for j in range(s))
@@ -464,11 +467,12 @@ def test_ark2_lhevi_coefficients_and_paper_a32():
 # ---------------------------------------------------------------------------
 # P12: ARK order on a linear column against the matrix exponential
 
-@pytest.mark.parametrize("tabname,order", [("ARK2b", 2), ("ARK3", 3)])
+@pytest.mark.parametrize("tabname,order", [("ARK2b", 2), ("ARK3", 3), ("ARS343", 3)])
 def test_p12_ark_order(tabname, order):
     """Observed order of the oracle's LHEVI ARK recipe with an explicit Coriolis term
     (catches a wrong c_j, a wrong q^E or a wrong final update)."""
-    tab = tableaux.as_float(tableaux.ark2("b") if tabname == "ARK2b" else tableaux.ark3())
+    tab = tableaux.as_float({"ARK2b": lambda: tableaux.ark2("b"), "ARK3": tableaux.ark3,
+                             "ARS343": tableaux.ars343}[tabname]())
     col = inputs.make_columns(4, 8, 1, z_top=30e3, profile="isothermal", seed=21)
     qn, qref = inputs.smooth_state(col, modes=(1, 2))
     omega = 2e-3
