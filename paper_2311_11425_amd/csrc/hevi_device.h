@@ -504,7 +504,7 @@ __device__ __forceinline__ size_t plane_size(const HeviShapeDev& sh) {
 // index and the multipliers of its first lane, and passes the column crossing
 // each split to the left with DPP moves.  A wavefront handles 64 / LPC columns:
 // part `part` of a 64-column tile.
-constexpr int kLuLanes = 2;  // lanes per column of the register-window LU, N <= 4
+constexpr int kLuLanes = 2;  // lanes per column of the register-window LU up to N = 4
 
 // Lanes per column of the register-window LU by order: 2 up to N = 4, 4 above,
 // where a two-lane window would not fit in registers.
@@ -633,9 +633,9 @@ __device__ __forceinline__ void b_factor_lu_split(int64_t tile, int part, HeviSh
   if (singular && valid) flag(info, 5 /*HEVI_E_SINGULAR*/, c);
 }
 
-// Assembly and split-window LU in one pass (N <= 4): the wavefront computes each
-// element's rows of S itself (k_row, as b_factor_assemble does), keeps
-// this lane's part of them in LDS until they enter the window, and loads the
+// Assembly and split-window LU in one pass (N <= HEVI_FUSED_FACTOR_MAX_N): the
+// wavefront computes each element's rows of S itself (k_row, as b_factor_assemble
+// does), keeps this lane's part of them in LDS until they enter the window, and loads the
 // operator fields of the next element while they do.  S never goes through
 // memory: per column the pass reads the compact operator and writes the factors.
 // lds holds fused_lds_doubles<N>(LPC) doubles: (N + 1) rows of H per lane.

@@ -95,7 +95,7 @@ __global__ __launch_bounds__(64) void km_factor_assemble(const HeviProbDev* __re
   });
 }
 
-// LDS doubles needed by the LDS-window LU of the orders NLO..NHI (at least 1)
+// The band LU of one order (launched per order only), the parts of each tile in turn.
 template <int NLO, int NHI, typename FT>
 __global__ __launch_bounds__(64) void km_factor_lu(const HeviProbDev* __restrict__ probs,
                                                    HeviSched s) {
