@@ -76,12 +76,12 @@ def snapshot(members):
             for m in members]
 
 
-def single_path(ctx, members, prec, refine):
+def single_path(ctx, members, prec, refine, tab=TAB, dt=DT):
     """Reference: the single-problem kernels through ArkStepper, member by member."""
     from paper_2311_11425_amd.driver import ArkStepper
     ref = []
     for m in members:
-        st = ArkStepper(ctx, m["batch"], TAB, DT, precision=prec, refine=refine)
+        st = ArkStepper(ctx, m["batch"], tab, dt, precision=prec, refine=refine)
         out = m["batch"].empty_state()
         st.step(m["qn"], m["qref"], out)
         torch.cuda.synchronize()
@@ -119,6 +119,24 @@ def test_group_plans_match_single_path(ctx, prec):
             assert_same(snapshot(members), ref, (mode, grid, graph, rep))
         code, infos = g.check()
         assert code == 0, infos
+    g.free()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_group_ars343_matches_single_path(ctx, prec):
+    """Another tableau (ARS(3,4,3), an explicit first stage and a zero first
+    implicit column) through the group: the same bits as the single-problem path."""
+    from paper_2311_11425_amd import hevi
+    refine = (4, 1e-13, 0)
+    members = make_members(ctx, SPECS, 4)
+    ref = single_path(ctx, members, prec, refine, tab="ARS343", dt=30.0)
+    g = hevi.Group(ctx, members, "ARS343", 30.0, precision=prec, refine=refine)
+    for mode, grid, graph in (("one", 0, False), ("per_order", 2, True)):
+        g.set_plan(mode, grid, graph)
+        g.step(refactor=True)
+        assert_same(snapshot(members), ref, ("ARS343", mode, grid, graph))
+    code, infos = g.check()
+    assert code == 0, infos
     g.free()
 
 
