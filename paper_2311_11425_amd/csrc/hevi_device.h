@@ -768,7 +768,9 @@ enum { WS_R = 0, WS_U = 1, WS_VR = 2, WS_VT = 3, WS_T = 4, WS_D = 5, WS_B = 6, W
 // solve S x = rhs with the band LU factors (rhs field fi, result field fo).
 // The sweeps are sequential in the row index, so each wavefront keeps the factor
 // rows of the next rows in flight (PF forward, PB backward) in a register ring,
-// refilled as soon as a slot is consumed, while it works on the current row.
+// refilled as soon as a slot is consumed, while it works on the current row.  The
+// fused stage kernels (LDSRU) hold r/u in LDS and have the registers for a third
+// backward slot; the others spill with it.
 template <int N, typename FT, bool LDSRU = false>
 __device__ __forceinline__ void band_solve(const FT* __restrict__ Ub, const FT* __restrict__ Lb,
                                            const uint8_t* __restrict__ piv, size_t plane,
@@ -780,7 +782,7 @@ __device__ __forceinline__ void band_solve(const FT* __restrict__ Ub, const FT* 
     if constexpr (LDSRU) return ru[k * T + lane];
     else return ws[tix(tile, nz, k, HEVI_NWS, f, lane)];
   };
-  constexpr int B = 2 * N, K = 4 * N, PF = 3, PB = 2;
+  constexpr int B = 2 * N, K = 4 * N, PF = 3, PB = LDSRU ? 3 : 2;
   // U row extents (see plane_size): entries past them are zeros and, with FP64
   // factors, are not loaded; each ring slot knows the extent of the row it loads
   // next.  The FP32-factor solves run inside refinement sweeps, where the extra
