@@ -201,8 +201,9 @@ hevi_status hevi_combine(hevi_ctx *ctx, const hevi_ops *ops, int32_t n_v,
 /* ---- tableaux ---------------------------------------------------------------
  * IMEX ARK tableaux of the paper's integrators (Sec. 5): "ARK2" / "ARK2b" =
  * ARK(2,3,2) with a_32 = 1/2, "ARK2a" with a_32 = (3 + 2 sqrt 2)/6 (Sec. 4.1),
- * "ARK3" = ARK3(2)4L[2]SA of Kennedy and Carpenter, "ARS343" = ARS(3,4,3) of
- * Ascher, Ruuth and Spiteri (further integrators of Sec. 5).  Writes s and the
+ * "ARK3" = ARK3(2)4L[2]SA and "ARK4" = ARK4(3)6L[2]SA of Kennedy and Carpenter,
+ * "ARS343" = ARS(3,4,3) of Ascher, Ruuth and Spiteri (further integrators of
+ * Sec. 5).  Writes s and the
  * row-major s x s explicit / implicit matrices and weights (capacity 8 stages).
  * Returns HEVI_E_INVALID for an unknown name. */
 hevi_status hevi_tableau(const char *name, int32_t *s, double *a_exp, double *a_imp,

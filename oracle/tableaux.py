@@ -1,6 +1,6 @@
 """IMEX ARK tableaux for the oracle's LHEVI stage recipe (test infrastructure).
 
-Both methods are ESDIRK/ERK pairs with b = b~ and c = c~ (Sec. 4.1: explicit
+All methods are ESDIRK/ERK pairs with b = b~ and c = c~ (Sec. 4.1: explicit
 first stage, constant diagonal a~_ii, b = b~ to conserve linear invariants).
 
 * ARK2 = ARK(2,3,2) of Giraldo, Kelly & Constantinescu (2013), the method the
@@ -20,6 +20,13 @@ first stage, constant diagonal a~_ii, b = b~ to conserve linear invariants).
   10-digit values, with a_31 and a_41 taken from the row sums so that c = c~
   holds exactly.  Its order conditions then hold to the published digits
   (about 1e-10); pinned by those and by observed third-order convergence.
+
+* ARK4 = ARK4(3)6L[2]SA of Kennedy & Carpenter (2003), the paper's ARK4, the
+  six-stage ARK(5,6,4) (Sec. 5; coefficients not printed there).  gamma = 1/4 and
+  c = (0, 1/2, 83/250, 31/50, 17/20, 1); the implicit coefficients are exact
+  rationals, the explicit ones the published rational approximations.  Pinned by
+  the fourth-order conditions (exact row sums for the implicit part, about 1e-12
+  for the explicit one) and by observed fourth-order convergence.
 
 Values are exact: rationals as fractions.Fraction, sqrt(2)-based entries as
 mpmath numbers at 50 digits; ``as_float`` converts to float64 arrays.
@@ -80,6 +87,33 @@ def ars343():
     Aimp = [[z, z, z, z], [z, g, z, z], [z, (1 - g) / 2, g, z], [z, b1, b2, g]]
     b = [z, b1, b2, g]
     return {"name": "ARS343", "Aexp": Aexp, "Aimp": Aimp, "b": b, "order": 3}
+
+
+def ark4():
+    q = F(1, 4)
+    z = F(0)
+    Aexp = [
+        [z] * 6,
+        [F(1, 2), z, z, z, z, z],
+        [F(13861, 62500), F(6889, 62500), z, z, z, z],
+        [F(-116923316275, 2393684061468), F(-2731218467317, 15368042101831),
+         F(9408046702089, 11113171139209), z, z, z],
+        [F(-451086348788, 2902428689909), F(-2682348792572, 7519795681897),
+         F(12662868775082, 11960479115383), F(3355817975965, 11060851509271), z, z],
+        [F(647845179188, 3216320057751), F(73281519250, 8382639484533),
+         F(552539513391, 3454668386233), F(3354512671639, 8306763924573), F(4040, 17871), z],
+    ]
+    b = [F(82889, 524892), z, F(15625, 83664), F(69875, 102672), F(-2260, 8211), q]
+    Aimp = [
+        [z] * 6,
+        [q, q, z, z, z, z],
+        [F(8611, 62500), F(-1743, 31250), q, z, z, z],
+        [F(5012029, 34652500), F(-654441, 2922500), F(174375, 388108), q, z, z],
+        [F(15267082809, 155376265600), F(-71443401, 120774400), F(730878875, 902184768),
+         F(2285395, 8070912), q, z],
+        list(b),
+    ]
+    return {"name": "ARK4", "Aexp": Aexp, "Aimp": Aimp, "b": b, "order": 4}
 
 
 def as_float(tab):

@@ -377,6 +377,35 @@ hevi_status hevi_tableau(const char* name, int32_t* s, double* a_exp, double* a_
     b[0] = 0.0; b[1] = b1; b[2] = b2; b[3] = g;
     return HEVI_OK;
   }
+  if (!std::strcmp(name, "ARK4")) {
+    // ARK4(3)6L[2]SA (Kennedy and Carpenter, 2003), the six-stage ARK(5,6,4):
+    // gamma = 1/4, c = (0, 1/2, 83/250, 31/50, 17/20, 1), b = last implicit row
+    const double q = 0.25;
+    const double E[36] = {
+        0, 0, 0, 0, 0, 0,
+        0.5, 0, 0, 0, 0, 0,
+        13861.0 / 62500.0, 6889.0 / 62500.0, 0, 0, 0, 0,
+        -116923316275.0 / 2393684061468.0, -2731218467317.0 / 15368042101831.0,
+        9408046702089.0 / 11113171139209.0, 0, 0, 0,
+        -451086348788.0 / 2902428689909.0, -2682348792572.0 / 7519795681897.0,
+        12662868775082.0 / 11960479115383.0, 3355817975965.0 / 11060851509271.0, 0, 0,
+        647845179188.0 / 3216320057751.0, 73281519250.0 / 8382639484533.0,
+        552539513391.0 / 3454668386233.0, 3354512671639.0 / 8306763924573.0,
+        4040.0 / 17871.0, 0};
+    const double I[36] = {
+        0, 0, 0, 0, 0, 0,
+        q, q, 0, 0, 0, 0,
+        8611.0 / 62500.0, -1743.0 / 31250.0, q, 0, 0, 0,
+        5012029.0 / 34652500.0, -654441.0 / 2922500.0, 174375.0 / 388108.0, q, 0, 0,
+        15267082809.0 / 155376265600.0, -71443401.0 / 120774400.0,
+        730878875.0 / 902184768.0, 2285395.0 / 8070912.0, q, 0,
+        82889.0 / 524892.0, 0, 15625.0 / 83664.0, 69875.0 / 102672.0, -2260.0 / 8211.0, q};
+    *s = 6;
+    std::memcpy(a_exp, E, sizeof(E));
+    std::memcpy(a_imp, I, sizeof(I));
+    for (int i = 0; i < 6; ++i) b[i] = I[30 + i];
+    return HEVI_OK;
+  }
   if (!std::strcmp(name, "ARK3")) {
     // ARK3(2)4L[2]SA (Kennedy and Carpenter, 2003)
     const double g = 1767732205903.0 / 4055673282236.0;

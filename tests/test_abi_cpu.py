@@ -47,7 +47,7 @@ def test_create_rejects_missing_device():
 
 @pytest.mark.parametrize("name,ref", [("ARK2", otab.ark2("b")), ("ARK2b", otab.ark2("b")),
                                       ("ARK2a", otab.ark2("a")), ("ARK3", otab.ark3()),
-                                      ("ARS343", otab.ars343())])
+                                      ("ARS343", otab.ars343()), ("ARK4", otab.ark4())])
 def test_tableau_matches_independent_transcription(name, ref):
     t = hevi.tableau(name)
     r = otab.as_float(ref)

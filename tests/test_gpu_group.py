@@ -123,18 +123,20 @@ def test_group_plans_match_single_path(ctx, prec):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-def test_group_ars343_matches_single_path(ctx, prec):
-    """Another tableau (ARS(3,4,3), an explicit first stage and a zero first
-    implicit column) through the group: the same bits as the single-problem path."""
+@pytest.mark.parametrize("tab", ["ARS343", "ARK4"])
+def test_group_other_tableaux_match_single_path(ctx, tab, prec):
+    """Other tableaux through the group: ARS(3,4,3) (an explicit first stage and a
+    zero first implicit column) and the six-stage ARK4 (five previous stages per
+    solve).  The same bits as the single-problem path."""
     from paper_2311_11425_amd import hevi
     refine = (4, 1e-13, 0)
-    members = make_members(ctx, SPECS, 4)
-    ref = single_path(ctx, members, prec, refine, tab="ARS343", dt=30.0)
-    g = hevi.Group(ctx, members, "ARS343", 30.0, precision=prec, refine=refine)
+    members = make_members(ctx, SPECS, hevi.tableau(tab)["s"])
+    ref = single_path(ctx, members, prec, refine, tab=tab, dt=30.0)
+    g = hevi.Group(ctx, members, tab, 30.0, precision=prec, refine=refine)
     for mode, grid, graph in (("one", 0, False), ("per_order", 2, True)):
         g.set_plan(mode, grid, graph)
         g.step(refactor=True)
-        assert_same(snapshot(members), ref, ("ARS343", mode, grid, graph))
+        assert_same(snapshot(members), ref, (tab, mode, grid, graph))
     code, infos = g.check()
     assert code == 0, infos
     g.free()

@@ -142,7 +142,8 @@ def test_solve_identity_at_zero_lambda(ctx):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("which", ["ARK2_cfg1", "ARK3_cfg2_sample", "ARS343_cfg1"])
+@pytest.mark.parametrize("which", ["ARK2_cfg1", "ARK3_cfg2_sample", "ARS343_cfg1",
+                                   "ARK4_cfg1"])
 def test_ark_step_parity(ctx, which, prec):
     """Stage increments Q_i - q^n and q^{n+1} - q^n against the oracle's ARK step.
 
@@ -157,6 +158,9 @@ def test_ark_step_parity(ctx, which, prec):
     elif which == "ARS343_cfg1":
         col, tabname, tab, dt, nsteps = inputs.config1(heterogeneous=True), "ARS343", \
             tableaux.as_float(tableaux.ars343()), 30.0, 2
+    elif which == "ARK4_cfg1":
+        col, tabname, tab, dt, nsteps = inputs.config1(heterogeneous=True), "ARK4", \
+            tableaux.as_float(tableaux.ark4()), 30.0, 2
     else:
         col, tabname, tab, dt, nsteps = inputs.config2(ncols=200), "ARK3", \
             tableaux.as_float(tableaux.ark3()), 300.0, 2
@@ -193,7 +197,8 @@ MODES = {  # name: (precision, refine, bar)
 
 
 @pytest.mark.parametrize("mode", list(MODES))
-@pytest.mark.parametrize("which", ["ARK2_cfg1", "ARK3_cfg2_sample", "ARS343_cfg1"])
+@pytest.mark.parametrize("which", ["ARK2_cfg1", "ARK3_cfg2_sample", "ARS343_cfg1",
+                                   "ARK4_cfg1"])
 def test_ark_stagewise_parity(ctx, which, mode):
     """Each stage solve of a GPU ARK step: q^ is rebuilt on the host from the GPU's
     own Q_j and S_j, solved by the oracle, and compared with the GPU's
@@ -212,6 +217,8 @@ def test_ark_stagewise_parity(ctx, which, mode):
         col, tabname, dt = inputs.config1(heterogeneous=True), "ARK2", 30.0
     elif which == "ARS343_cfg1":
         col, tabname, dt = inputs.config1(heterogeneous=True), "ARS343", 30.0
+    elif which == "ARK4_cfg1":
+        col, tabname, dt = inputs.config1(heterogeneous=True), "ARK4", 30.0
     else:
         col, tabname, dt = inputs.config2(ncols=200), "ARK3", 300.0
     prec, refine, bar = MODES[mode]

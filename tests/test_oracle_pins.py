@@ -431,15 +431,30 @@ def _conds(tab):
         out["bAtc"] = sum(b[i] * At[i][j] * c[j] for i in range(s) for j in range(s)) - sixth
         out["bAct"] = sum(b[i] * A[i][j] * ct[j] for i in range(s) for j in range(s)) - sixth
         out["bAtct"] = sum(b[i] * At[i][j] * ct[j] for i in range(s) for j in range(s)) - sixth
+    if tab["order"] >= 4:
+        # with b = b~ and c = c~ the additive fourth-order conditions are those of
+        # the four order-4 trees with every inner vertex taking A or A~ (1 + 2 + 2 + 4)
+        Ms = {"E": A, "I": At}
+        out["b_c3"] = sum(b[i] * c[i] ** 3 for i in range(s)) - mp.mpf(1) / 4
+        for xn, X in Ms.items():
+            out[f"bc{xn}c"] = sum(b[i] * c[i] * X[i][j] * c[j]
+                                  for i in range(s) for j in range(s)) - mp.mpf(1) / 8
+            out[f"b{xn}c2"] = sum(b[i] * X[i][j] * c[j] ** 2
+                                  for i in range(s) for j in range(s)) - mp.mpf(1) / 12
+            for yn, Y in Ms.items():
+                out[f"b{xn}{yn}c"] = sum(b[i] * X[i][j] * Y[j][k] * c[k] for i in range(s)
+                                         for j in range(s) for k in range(s)) - mp.mpf(1) / 24
     return out
 
 
 @pytest.mark.parametrize("tab", [tableaux.ark2("b"), tableaux.ark2("a"), tableaux.ark3(),
-                                 tableaux.ars343()])
+                                 tableaux.ars343(), tableaux.ark4()])
 def test_p13_order_conditions(tab):
     mp.mp.dps = 50
-    # ARS(3,4,3)'s explicit coefficients are published to 10 digits
-    tol = 1e-9 if tab["name"] == "ARS343" else 1e-11
+    # ARS(3,4,3)'s explicit coefficients are published to 10 digits; ARK4's
+    # published rationals meet every condition to about 1e-26, so a slip in the
+    # last digit of one of its 13-digit numerators (about 1e-13) must fail
+    tol = {"ARS343": 1e-9, "ARK4": 1e-20}.get(tab["name"], 1e-11)
     for k, v in _conds(tab).items():
         assert abs(float(v)) < tol, (tab["name"], k, float(v))
     s = len(tab["b"])
@@ -467,12 +482,13 @@ def test_ark2_lhevi_coefficients_and_paper_a32():
 # ---------------------------------------------------------------------------
 # P12: ARK order on a linear column against the matrix exponential
 
-@pytest.mark.parametrize("tabname,order", [("ARK2b", 2), ("ARK3", 3), ("ARS343", 3)])
+@pytest.mark.parametrize("tabname,order", [("ARK2b", 2), ("ARK3", 3), ("ARS343", 3),
+                                            ("ARK4", 4)])
 def test_p12_ark_order(tabname, order):
     """Observed order of the oracle's LHEVI ARK recipe with an explicit Coriolis term
     (catches a wrong c_j, a wrong q^E or a wrong final update)."""
     tab = tableaux.as_float({"ARK2b": lambda: tableaux.ark2("b"), "ARK3": tableaux.ark3,
-                             "ARS343": tableaux.ars343}[tabname]())
+                             "ARS343": tableaux.ars343, "ARK4": tableaux.ark4}[tabname]())
     col = inputs.make_columns(4, 8, 1, z_top=30e3, profile="isothermal", seed=21)
     qn, qref = inputs.smooth_state(col, modes=(1, 2))
     omega = 2e-3
