@@ -3,6 +3,8 @@
 * A request's result is bit-identical to hevi_stage_solve of the same operands,
   whether it runs alone or batched with requests of other simulations, and it
   matches the FP64 oracle.
+* A whole six-stage ARK4 step driven request by request through the server
+  gives the single-problem step's bits.
 * Admission within the HBM budget, backpressure (HEVI_E_BUSY), unknown and
   retired ids (HEVI_E_CLOSED), release, and submits from several threads.
 """
@@ -112,6 +114,58 @@ def test_serve_alone_and_mixed_match_stage_solve(ctx, prec):
                                             x_or))
         print(f"N={sd.col['N']} Ne={sd.col['Ne']}: {err:.2e} (tol {tol:.2e})", flush=True)
         assert err < tol
+    for sid in ids:
+        srv.release(sid)
+    srv.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_serve_ark4_step_matches_stepper(ctx, prec):
+    """A whole ARK4 step (six stages, so up to five previous stages per request)
+    driven through the server for two simulations whose requests share launches:
+    every Q_i, S_i and q^{n+1} carries the same bits as the single-problem step."""
+    from paper_2311_11425_amd import hevi
+    from paper_2311_11425_amd.driver import ArkStepper
+    dt = 30.0
+    sims = [SimData(ctx, sp) for sp in (SPECS[0], SPECS[2])]
+    steps, refs = [], []
+    for sd in sims:
+        st = ArkStepper(ctx, sd.B, "ARK4", dt, precision=prec, refine=(4, 1e-13, 0))
+        out = sd.B.empty_state()
+        for inf in st.step(sd.qn, sd.qref, out, info=True):
+            assert inf["status"] == "HEVI_OK", inf
+        torch.cuda.synchronize()
+        steps.append(st)
+        refs.append(([t.cpu() for t in st.Q[1:]], [t.cpu() for t in st.S], out.cpu()))
+    srv = hevi.Server(ctx, 1 << 34, max_inflight=16)
+    ids = [srv.register(sd.B.ops, st.lam, prec) for sd, st in zip(sims, steps)]
+    Q = [[sd.qn] + [sd.out() for _ in range(1, st.s)] for sd, st in zip(sims, steps)]
+    S = [[sd.B.empty_state() for _ in range(st.s)] for sd, st in zip(sims, steps)]
+    for sd, S_ in zip(sims, S):
+        ctx.apply_op(sd.B.ops, sd.qn, S_[0], xref=sd.qref)
+    s = steps[0].s
+    assert s == 6
+    for i in range(1, s):
+        tickets = []
+        for k, (sd, st, sid) in enumerate(zip(sims, steps, ids)):
+            e = [1.0] + [dt * st.Aexp[i][j] for j in range(i)]
+            tickets.append(srv.submit(sid, [sd.qn] + S[k][:i], e, Q[k][:i], st.coeffs(i),
+                                      Q[k][i]))
+        for t in tickets:
+            inf, _ = srv.wait(t)
+            assert inf["status"] == "HEVI_OK", inf
+        for k, sd in enumerate(sims):
+            ctx.apply_op(sd.B.ops, Q[k][i], S[k][i], xref=sd.qref)
+    for k, (sd, st) in enumerate(zip(sims, steps)):
+        out = sd.out()
+        ctx.combine(sd.B.ops, [sd.qn] + S[k], [1.0] + [dt * bi for bi in st.b], out)
+        torch.cuda.synchronize()
+        rQ, rS, rout = refs[k]
+        for i in range(1, s):
+            assert torch.equal(Q[k][i].cpu(), rQ[i - 1]), (k, "Q", i)
+        for i in range(s):
+            assert torch.equal(S[k][i].cpu(), rS[i]), (k, "S", i)
+        assert torch.equal(out.cpu(), rout), (k, "out")
     for sid in ids:
         srv.release(sid)
     srv.close()
