@@ -521,3 +521,67 @@ def test_p12_ark_order(tabname, order):
     rates = [np.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
     assert rates[-1] > order - 0.25, (errs, rates)
     assert rates[-1] < order + 0.6, (errs, rates)
+
+
+def _explicit_linear_order(tab):
+    """Largest p with b A^(k-1) 1 = 1/k! for k = 1..p over the explicit tableau:
+    the order of its stability polynomial (to 1e-9: ARS(3,4,3) is published to
+    10 digits)."""
+    cv = lambda v: mp.mpf(v.numerator) / v.denominator if isinstance(v, Fr) else mp.mpf(v)
+    A = mp.matrix([[cv(v) for v in row] for row in tab["Aexp"]])
+    b = mp.matrix([cv(v) for v in tab["b"]])
+    v = mp.matrix([1] * len(tab["b"]))
+    p = 0
+    while abs((b.T * v)[0] - 1 / mp.factorial(p + 1)) < 1e-9:
+        p += 1
+        v = A * v
+    return p
+
+
+@pytest.mark.parametrize("tabname", ["ARK2b", "ARK3", "ARS343", "ARK4"])
+def test_p12b_explicit_part_order(tabname):
+    """Observed order of the explicit part alone.  An inertial oscillation
+    (horizontal momentum perpendicular to n^, which L_z leaves untouched) is
+    turned only by the Coriolis term, explicit in the stage recipe, so the
+    implicit part plays no role and the rate must be the linear order of the
+    explicit tableau: 2, 3, 4 (ARS(3,4,3)'s explicit part also meets
+    b A^3 1 = 1/24) and 4.  Catches a wrong explicit coefficient or a wrong q^E
+    that the implicit-dominated test above cannot see: ARK3 and ARS(3,4,3) share
+    their implicit stability function and agree there to ten digits."""
+    mp.mp.dps = 50
+    t = {"ARK2b": lambda: tableaux.ark2("b"), "ARK3": tableaux.ark3,
+         "ARS343": tableaux.ars343, "ARK4": tableaux.ark4}[tabname]()
+    p = _explicit_linear_order(t)
+    assert p == {"ARK2b": 2, "ARK3": 3, "ARS343": 4, "ARK4": 4}[tabname]
+    tab = tableaux.as_float(t)
+    col = inputs.make_columns(4, 8, 1, z_top=30e3, profile="isothermal", seed=21)
+    _, qref = inputs.smooth_state(col, modes=(1,))
+    z, J, gz, r0, T0 = oracle.column_of(col, 0)
+    L = oracle.column_L(4, 8, CONSTS, z, J, gz, r0, T0)
+    nz = col["nz"]
+    n = col["nhat"][0]
+    e1 = np.cross(n, [0.0, 0.0, 1.0])
+    e1 /= np.linalg.norm(e1)
+    prof = np.sin(np.pi * (z - z[0]) / (z[-1] - z[0]))
+    q0 = np.zeros(5 * nz)
+    for k in range(nz):
+        q0[5 * k + 1:5 * k + 4] = 0.1 * prof[k] * r0[k] * e1
+    assert np.linalg.norm(L @ q0) < 1e-14 * np.linalg.norm(q0)
+    omega = 5e-3
+    X = np.array([[0, -n[2], n[1]], [n[2], 0, -n[0]], [-n[1], n[0], 0]])
+    C = np.zeros_like(L)
+    for k in range(nz):
+        C[5 * k + 1:5 * k + 4, 5 * k + 1:5 * k + 4] = -2 * omega * X
+    T = 600.0
+    exact = sla.expm((L + C) * T) @ q0
+    qstart = qref.copy()
+    for v in range(5):
+        qstart[v, :, 0] += q0[v::5]
+    errs = []
+    for dt in (60.0, 30.0, 15.0, 7.5):
+        q = qstart.copy()
+        for _ in range(int(round(T / dt))):
+            q = oracle.ark_step_batch(col, tab, dt, q, qref, refine=1, omega=omega)
+        errs.append(np.linalg.norm(oracle.vec_of(q - qref, 0) - exact) / np.linalg.norm(exact))
+    rates = [np.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    assert abs(rates[-1] - p) < 0.15, (errs, rates)
