@@ -563,8 +563,9 @@ def main():
                     help="also run plain 1 GiB device copies (scale for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on exactly one GPU; --gpus {args.gpus} is not "
-              "supported (columns shard across GPUs with no exchange step; see DESIGN.md)",
+        print(f"bench.py: the benchmark runs on one GPU only; --gpus {args.gpus} is not "
+              "supported (the columns are independent, so each GPU would take a share of "
+              "them with no exchange step; a multi-GPU run is not implemented)",
               file=sys.stderr)
         sys.exit(2)
 
