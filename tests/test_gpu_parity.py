@@ -142,8 +142,8 @@ def test_solve_identity_at_zero_lambda(ctx):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("which", ["ARK2_cfg1", "ARK3_cfg2_sample", "ARS343_cfg1",
-                                   "ARK4_cfg1"])
+@pytest.mark.parametrize("which", ["ARK2_cfg1", "ARK2a_cfg1", "ARK3_cfg2_sample",
+                                   "ARS343_cfg1", "ARK4_cfg1"])
 def test_ark_step_parity(ctx, which, prec):
     """Stage increments Q_i - q^n and q^{n+1} - q^n against the oracle's ARK step.
 
@@ -161,6 +161,9 @@ def test_ark_step_parity(ctx, which, prec):
     elif which == "ARK4_cfg1":
         col, tabname, tab, dt, nsteps = inputs.config1(heterogeneous=True), "ARK4", \
             tableaux.as_float(tableaux.ark4()), 30.0, 2
+    elif which == "ARK2a_cfg1":
+        col, tabname, tab, dt, nsteps = inputs.config1(heterogeneous=True), "ARK2a", \
+            tableaux.as_float(tableaux.ark2("a")), 30.0, 2
     else:
         col, tabname, tab, dt, nsteps = inputs.config2(ncols=200), "ARK3", \
             tableaux.as_float(tableaux.ark3()), 300.0, 2

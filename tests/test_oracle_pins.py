@@ -482,12 +482,13 @@ def test_ark2_lhevi_coefficients_and_paper_a32():
 # ---------------------------------------------------------------------------
 # P12: ARK order on a linear column against the matrix exponential
 
-@pytest.mark.parametrize("tabname,order", [("ARK2b", 2), ("ARK3", 3), ("ARS343", 3),
-                                            ("ARK4", 4)])
+@pytest.mark.parametrize("tabname,order", [("ARK2b", 2), ("ARK2a", 2), ("ARK3", 3),
+                                            ("ARS343", 3), ("ARK4", 4)])
 def test_p12_ark_order(tabname, order):
     """Observed order of the oracle's LHEVI ARK recipe with an explicit Coriolis term
     (catches a wrong c_j, a wrong q^E or a wrong final update)."""
-    tab = tableaux.as_float({"ARK2b": lambda: tableaux.ark2("b"), "ARK3": tableaux.ark3,
+    tab = tableaux.as_float({"ARK2b": lambda: tableaux.ark2("b"),
+                             "ARK2a": lambda: tableaux.ark2("a"), "ARK3": tableaux.ark3,
                              "ARS343": tableaux.ars343, "ARK4": tableaux.ark4}[tabname]())
     col = inputs.make_columns(4, 8, 1, z_top=30e3, profile="isothermal", seed=21)
     qn, qref = inputs.smooth_state(col, modes=(1, 2))
@@ -538,21 +539,22 @@ def _explicit_linear_order(tab):
     return p
 
 
-@pytest.mark.parametrize("tabname", ["ARK2b", "ARK3", "ARS343", "ARK4"])
+@pytest.mark.parametrize("tabname", ["ARK2b", "ARK2a", "ARK3", "ARS343", "ARK4"])
 def test_p12b_explicit_part_order(tabname):
     """Observed order of the explicit part alone.  An inertial oscillation
     (horizontal momentum perpendicular to n^, which L_z leaves untouched) is
     turned only by the Coriolis term, explicit in the stage recipe, so the
     implicit part plays no role and the rate must be the linear order of the
-    explicit tableau: 2, 3, 4 (ARS(3,4,3)'s explicit part also meets
-    b A^3 1 = 1/24) and 4.  Catches a wrong explicit coefficient or a wrong q^E
+    explicit tableau: 2, 3 for ARK2a (its a_32 gives b A c = 1/6), 3, 4
+    (ARS(3,4,3)'s explicit part also meets b A^3 1 = 1/24) and 4.  Catches a wrong explicit coefficient or a wrong q^E
     that the implicit-dominated test above cannot see: ARK3 and ARS(3,4,3) share
     their implicit stability function and agree there to ten digits."""
     mp.mp.dps = 50
-    t = {"ARK2b": lambda: tableaux.ark2("b"), "ARK3": tableaux.ark3,
+    t = {"ARK2b": lambda: tableaux.ark2("b"), "ARK2a": lambda: tableaux.ark2("a"),
+         "ARK3": tableaux.ark3,
          "ARS343": tableaux.ars343, "ARK4": tableaux.ark4}[tabname]()
     p = _explicit_linear_order(t)
-    assert p == {"ARK2b": 2, "ARK3": 3, "ARS343": 4, "ARK4": 4}[tabname]
+    assert p == {"ARK2b": 2, "ARK2a": 3, "ARK3": 3, "ARS343": 4, "ARK4": 4}[tabname]
     tab = tableaux.as_float(t)
     col = inputs.make_columns(4, 8, 1, z_top=30e3, profile="isothermal", seed=21)
     _, qref = inputs.smooth_state(col, modes=(1,))
