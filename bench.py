@@ -38,6 +38,10 @@ PATHS = {  # name: (precision, refine=(max_sweeps, rel_target, full_sweeps))
     "mixed": (1, (4, 1e-13, 0)),
     "fp64_full1": (0, (0, 1e-13, 1)),
 }
+# relative-error bars against the oracle: FP64 factors 1e-12, FP32 factors +
+# FP64 refinement 1e-10 (each raised to 4 x a stage's rounding floor where that
+# is larger)
+BARS = {"fp64": 1e-12, "fp64_full1": 1e-12, "mixed": 1e-10}
 
 
 def log(*a):
@@ -95,10 +99,12 @@ class OracleChecks:
     def __init__(self):
         self.jobs = []
 
-    def stage_solves(self, target, key, sc, lam, pairs, combine="list"):
-        """pairs: per stage (q^, x_gpu) on the sampled columns sc, x = Q_i + P.
-        combine="list": target[key] = per-stage max errors; "max": running max."""
-        self.jobs.append(("stage", target, key, sc, lam, pairs, combine))
+    def stage_solves(self, target, key, sc, lam, parts, bar, combine="list"):
+        """parts: per stage (q^E, P, Q_i) on the sampled columns sc (q^ = q^E + P,
+        the GPU's q_tt = Q_i + P).  combine="list": target[key] = per-stage max
+        errors; "max": running max.  target["meets_bar"]: every error within
+        max(bar, 4 x the stage's rounding floor) (stage_floor)."""
+        self.jobs.append(("stage", target, key, sc, lam, parts, bar, combine))
 
     def ark_step(self, target, key, col, tableau, dt, qn, qref, gpu):
         """gpu: {"Q2": .., "Q3": .., "q_next": ..}; the increments against q^n are
@@ -113,14 +119,37 @@ def cpu_baseline_leg(checks, col=None, qn=None, qref=None, budget_cpu_s=15.0):
     is exact: columns are independent)."""
     import oracle
     from oracle import tableaux
+
+    def stage_floor(col, lam, qE, P, Qi, x, seed=2):
+        """Rounding floor of comparing a stage solve whose input q^ = q^E + P and
+        output q_tt = Q_i + P are formed from reference-sized terms that cancel: the
+        change of the oracle's solution when q^ moves by one ulp of |q^E| + |P|, plus
+        one ulp of |Q_i| + |P| on the output (two correct FP64 implementations may
+        differ by this much)."""
+        rng = np.random.default_rng(seed)
+        eps = 2.0 ** -52
+        noise_in = eps * (np.abs(qE) + np.abs(P)) * rng.uniform(-1, 1, qE.shape)
+        x_in = oracle.solve_batch(col, lam, qE + P + noise_in, refine=1)
+        noise_out = eps * (np.abs(Qi) + np.abs(P)) * rng.uniform(-1, 1, Qi.shape)
+        return relerr_max(x_in, x) + relerr_max(x + noise_out, x)
+
     for job in checks.jobs:
         if job[0] == "stage":
-            _, target, key, sc, lam, pairs, combine = job
-            errs = [relerr_max(xg, oracle.solve_batch(sc, lam, rhs, refine=1)) for rhs, xg in pairs]
+            _, target, key, sc, lam, parts, bar, combine = job
+            errs, floors = [], []
+            for qE, P, Qi in parts:
+                xo = oracle.solve_batch(sc, lam, qE + P, refine=1)
+                errs.append(relerr_max(Qi + P, xo))
+                floors.append(stage_floor(sc, lam, qE, P, Qi, xo))
+            ok = all(e <= max(bar, 4 * f) for e, f in zip(errs, floors))
             if combine == "list":
                 target[key] = errs
+                target[key + "_floor"] = floors
             else:
                 target[key] = max(target.get(key, 0.0), max(errs))
+                target[key + "_floor"] = max(target.get(key + "_floor", 0.0), max(floors))
+            target["bar"] = bar
+            target["meets_bar"] = bool(target.get("meets_bar", True) and ok)
         else:
             _, target, key, c, tname, dt, q0, r0, gpu = job
             tab = tableaux.as_float(getattr(tableaux, tname)())
@@ -133,10 +162,13 @@ def cpu_baseline_leg(checks, col=None, qn=None, qref=None, budget_cpu_s=15.0):
         return None
     tab = tableaux.as_float(tableaux.ark3())
     try:
-        threads = len(os.sched_getaffinity(0))
+        affinity = len(os.sched_getaffinity(0))
     except AttributeError:
-        threads = os.cpu_count() or 1
-    threads = max(1, min(threads, 16))
+        affinity = os.cpu_count() or 1
+    # every core this process may run on, up to the host's CPU share for one GPU
+    # (OMP_NUM_THREADS where the host sets it)
+    share = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    threads = max(1, min(affinity, share) if share > 0 else affinity)
 
     def sample(n):
         idx = np.linspace(0, col["z"].shape[1] - 1, n).astype(np.int64)
@@ -169,14 +201,15 @@ def cpu_baseline_leg(checks, col=None, qn=None, qref=None, budget_cpu_s=15.0):
     except OSError:
         pass
     return {"value": n * 3 / wall, "unit": "column-solves/s", "cores": threads, "kind": "oracle",
-            "single_core_value": one_core, "cpu_model": model,
+            "single_core_value": one_core, "cpu_model": model, "nproc": os.cpu_count(),
+            "affinity_cpus": affinity, "omp_num_threads": share or None,
             "sample": f"{n} of {col['z'].shape[1]} columns (evenly spaced), one ARK3 step each: "
                       f"dense 205x205 GEPP factor, 3 stage solves with one long-double "
                       f"refinement step, 4 dense operator applications; {wall:.2f} s wall, "
                       f"{wall * threads:.1f} CPU-s on {threads} threads"}
 
 
-def queue_stage_errors(checks, target, key, st, col, qn, idx):
+def queue_stage_errors(checks, target, key, st, col, qn, idx, bar):
     """Queue the check of each stage solve of the stepper's last step on the sampled
     columns: q^ rebuilt from the GPU's own Q_j, S_j, solved by the oracle later."""
     import torch
@@ -184,13 +217,13 @@ def queue_stage_errors(checks, target, key, st, col, qn, idx):
     torch.cuda.synchronize()
     Q = [t.cpu().numpy()[..., idx] for t in st.Q]
     S = [t.cpu().numpy()[..., idx] for t in st.S]
-    pairs = []
+    parts = []
     for i in range(1, st.s):
         c = st.coeffs(i)
         qE = qs + sum(st.dt * st.Aexp[i][j] * S[j] for j in range(i))
         P = sum(c[j] * Q[j] for j in range(i))
-        pairs.append((qE + P, Q[i] + P))
-    checks.stage_solves(target, key, sample_columns(col, idx), st.lam, pairs)
+        parts.append((qE, P, Q[i]))
+    checks.stage_solves(target, key, sample_columns(col, idx), st.lam, parts, bar)
 
 
 def relerr_max(a, ref):
@@ -221,7 +254,7 @@ def cfg1_leg(ctx, checks, steps=200):
         Q = [t.cpu().numpy() for t in st.Q]
         res = {"max_refinement_sweeps": max(i["max_sweeps_used"] for i in infos)}
         queue_stage_errors(checks, res, "stage_solve_rel_err", st, col, qn,
-                           np.arange(col["ncols"]))
+                           np.arange(col["ncols"]), BARS[name])
         checks.ark_step(res, "increment_rel_err", col, "ark2", 30.0, qn, qref,
                         {"Q2": Q[1], "Q3": Q[2], "q_next": o.cpu().numpy()})
         for _ in range(10):
@@ -344,14 +377,14 @@ def uneven_leg(ctx, checks, scale=1.0, steps=5, reps=2):
             qs = np.ascontiguousarray(qn[..., idx])
             Q = [qs] + [t.cpu().numpy()[..., idx] for t in m["Q"][1:]]
             S = [t.cpu().numpy()[..., idx] for t in m["S"]]
-            pairs = []
+            parts = []
             for i in range(1, 4):
                 c = [(tab["Aimp"][i][j] - tab["Aexp"][i][j]) / tab["Aimp"][i][i] for j in range(i)]
                 qE = qs + sum(300.0 * tab["Aexp"][i][j] * S[j] for j in range(i))
                 P = sum(c[j] * Q[j] for j in range(i))
-                pairs.append((qE + P, Q[i] + P))
+                parts.append((qE, P, Q[i]))
             checks.stage_solves(d, "stage_rel_err_vs_oracle_max", sample_columns(col, idx), lam,
-                                pairs, combine="max")
+                                parts, BARS[name], combine="max")
         d["oracle_sample"] = f"{len(host_q)} members (incl. the highest order) x 12 columns x 3 stages"
         res[name] = d
         log(f"uneven {name}: {ms:.2f} ms/step, plan {best}, per-member {per_member:.2f} ms")
@@ -485,10 +518,10 @@ def serve_leg(ctx, checks, rates=(0.25, 0.5, 0.75, 1.0, 1.2), per_rate=300, scal
             idx = np.unique(np.linspace(0, sm["ncols"] - 1, 12).astype(np.int64))
             qs = sm["qn"].cpu().numpy()[..., idx]
             qE = qs + dt * tab["Aexp"][1][0] * sm["S1"].cpu().numpy()[..., idx]
-            xg = sm["Qi"].cpu().numpy()[..., idx] - qs
+            Qi = sm["Qi"].cpu().numpy()[..., idx]
             checks.stage_solves(d, "stage_rel_err_vs_oracle_max",
-                                sample_columns(sm["col"], idx), lam, [(qE - qs, xg)],
-                                combine="max")
+                                sample_columns(sm["col"], idx), lam, [(qE, -qs, Qi)],
+                                BARS[pname], combine="max")
         d["oracle_sample"] = f"{len(check)} simulations x 12 columns"
         out[pname] = d
     return out
@@ -619,7 +652,7 @@ def main():
              "combine_ms": float(np.mean(r["combine_ms"])),
              "factor_plus_stages_column_solves_per_s": 3 * ncols / ((fac_ms + 3 * stage_ms) * 1e-3)}
         d["factor_u_entries_per_column"] = st.factors.band_entries() / ncols
-        queue_stage_errors(checks, d, "stage_rel_err_vs_oracle", st, col, qn, idx)
+        queue_stage_errors(checks, d, "stage_rel_err_vs_oracle", st, col, qn, idx, BARS[name])
         res_paths[name] = d
         log(f"{name}: {ms_step:.3f} ms/step, stage solve {stage_ms:.3f} ms, factor {fac_ms:.3f} ms")
 
@@ -639,11 +672,17 @@ def main():
     # are exact zeros, not read), all 2N multipliers per node, 2 bytes per node
     # (pivot and U extent)
     fsz = 8 if prec == 0 else 4
-    fac_read = (main_path["factor_u_entries_per_column"] + 2 * col["N"] * nz) * fsz + 2 * nz
-    # algorithmic bytes of one stage solve, averaged over the 3 stages: the input
-    # vectors (q^n, S_1..S_{i-1}, Q_1..Q_{i-1}), the output Q_i, the factors and
-    # the compact operator, each once
-    per_col = float(np.mean([(2 * i + 1 + 1) * vec + fac_read + sz["ops"] for i in (1, 2, 3)]))
+    # byte planes a solve reads: pivot offsets and row scales, and (FP64 factors)
+    # the U row extents
+    fac_read = ((main_path["factor_u_entries_per_column"] + 2 * col["N"] * nz) * fsz
+                + (3 if prec == 0 else 2) * nz)
+    # algorithmic bytes of stage i (i = 2..4) of one column: the input vectors
+    # q^n, S_1..S_{i-1}, Q_2..Q_{i-1} (Q_1 is q^n, read once), the output Q_i,
+    # the factors as read and the compact operator, each once; averaged over the
+    # three stages.  The workload's own count of a column-solve's bytes takes q^n
+    # and Q_1 as two vectors (one more per stage): reported beside it.
+    per_col = float(np.mean([(2 * i + 1) * vec + fac_read + sz["ops"] for i in (1, 2, 3)]))
+    per_col_wl = per_col + vec
     stage_s = main_path["stage_solve_ms"]["avg"] * 1e-3
     achieved = per_col * ncols / stage_s / 1e9
     traffic = measured_traffic(args.precision)
@@ -673,10 +712,13 @@ def main():
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "kernel": "hevi_stage_solve (k_stage_fused; FP32 factors: k_stage_rhs + k_stage_bsolve + k_stage_update)",
                      "algorithmic_bytes_per_column": per_col,
+                     "workload_count_bytes_per_column": per_col_wl,
+                     "workload_count_frac": per_col_wl * ncols / stage_s / 1e9 / PEAK_HBM_GBS,
                      "measured_copy_GBps": copy_gbs,
                      "launch_columns": ncols,
                      "paper_layout_band_factor_bytes_per_column": sz["paper_band"],
                      "factor_bytes_per_column_stored": sz["factors"],
+                     "resident_bytes_per_column": sz["resident"],
                      "factor_bytes_per_column_read": fac_read},
     }
     if not args.no_extra:
@@ -702,12 +744,22 @@ def main():
     elif checks.jobs:
         log("oracle: error checks ...")
         cpu_baseline_leg(checks)
+    # the headline is valid only where its stage errors were checked and met the bar
+    main_checked = "meets_bar" in main_path
+    res["bar_check"] = {"checked": main_checked,
+                        "meets_bar": bool(main_path.get("meets_bar", False)),
+                        "bar": BARS[args.precision],
+                        "rule": "max over sampled columns, variables and stages of the relative "
+                                "L2 error vs the oracle <= max(bar, 4 x the stage's rounding floor)"}
     res["paper_context"] = {
         "note": "whole-model 10-day baroclinic-instability time-to-solution on 512 AMD EPYC "
                 "Rome cores (CPU); context only, not this metric",
         "LHEVI_ARK2_s": 163, "NHEVI_LU_ARK2_s": 502, "NHEVI_GMRES_ARK2_s": 1793}
     ctx.close()
     print(json.dumps(res), flush=True)
+    if main_checked and not res["bar_check"]["meets_bar"]:
+        log(f"bench.py: the {args.precision} path missed its error bar; the headline is invalid")
+        sys.exit(3)
 
 
 if __name__ == "__main__":

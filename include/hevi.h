@@ -88,10 +88,10 @@ typedef struct { int32_t order_N, n_elem; int64_t n_cols; } hevi_shape;
  *   matrix-free, correction d from the FP32 factors, u += d) until the last
  *   correction satisfies ||d|| <= rel_residual_target ||u||.
  * full_sweeps: either precision -- sweeps of iterative refinement of the full
- *   system with the FP64 residual q^ - A q_tt formed on offset-free vectors.  A
- *   plain FP64 solve of a right-hand side ~100x larger than its solution (the
- *   later ARK stages) loses about two digits in any FP64 factorisation; one
- *   full sweep restores them. */
+ *   system with the FP64 residual q^ - A q_tt formed on offset-free vectors, in
+ *   a slower kernel that keeps every vector in scratch (an accuracy reference;
+ *   the default path already solves the row-equilibrated reduced system and
+ *   recovers the momentum from u without differencing large terms). */
 typedef struct { int32_t max_sweeps; double rel_residual_target; int32_t full_sweeps; } hevi_refine;
 
 typedef struct {
@@ -126,7 +126,10 @@ const char *hevi_status_str(hevi_status s);
  * density d_rho0 (> 0) and density potential temperature d_Theta0 (> 0);
  * d_gz = grad(zeta) ([m][k][c], nonzero).  The result is a library-owned
  * compact per-node operator (8 FP64 per node).  Invalid per-node values are
- * reported by hevi_ops_check. */
+ * reported by hevi_ops_check.  The call waits for `stream` once: whether every
+ * column's grad(zeta) is one vector along the column (straight columns, whose
+ * pressure gradient has no part tangential to grad(zeta)) selects the stage-solve
+ * kernels used with these ops. */
 hevi_status hevi_build_column_ops(hevi_ctx *ctx, const hevi_shape *shape,
                                   const hevi_consts *consts, const double *d_z,
                                   const double *d_J, const double *d_gz,
@@ -152,10 +155,12 @@ hevi_status hevi_apply_op(hevi_ctx *ctx, const hevi_ops *ops, const double *d_x,
  * Representation: the exact block elimination of rho, Theta and the tangential
  * momentum (their diagonal blocks are identities) leaves a band system of
  * half-bandwidth 2N in the contravariant vertical momentum u = grad(zeta).U;
- * that system is LU-factored with partial pivoting (largest magnitude in the
- * pivot column, lowest row on ties), the same band LU the paper uses through
- * LAPACK (Sec. 4.2.2) applied to the reduced matrix.  Factors are FP64, or
- * FP32 for HEVI_FP32_REFINE (elimination in FP64, then rounded).  lambda >= 0.
+ * that system is row-equilibrated by powers of two (each row scaled by the
+ * binary exponent of its largest entry, exactly) and LU-factored with partial
+ * pivoting (largest magnitude in the pivot column, lowest row on ties): the
+ * band LU the paper uses through LAPACK (Sec. 4.2.2), applied to the reduced
+ * matrix with LAPACK-style row equilibration.  Factors are FP64, or FP32 for
+ * HEVI_FP32_REFINE (elimination in FP64, then rounded).  lambda >= 0.
  * hevi_factor allocates; hevi_refactor reuses the storage of `f` for a new
  * lambda (no allocation).  A zero pivot is reported as HEVI_E_SINGULAR by
  * hevi_factors_check. */
@@ -210,12 +215,17 @@ hevi_status hevi_tableau(const char *name, int32_t *s, double *a_exp, double *a_
                          double *b);
 
 /* ---- introspection ---------------------------------------------------------- */
-/* Bytes of the compact operator and of the factors actually stored per column
- * (FP64 or FP32 factors incl. pivots), and the bytes the paper's LAPACK band
- * layout would need (ldab = 3 * 5 (N+1) - 2 rows of 8-byte entries per
- * unknown plus a 4-byte pivot). */
+/* Bytes per column of: the compact operator; the factors (FP64 or FP32 U and L
+ * entries plus three byte planes: pivot offsets, U row extents, row-scale
+ * exponents); the paper's LAPACK band layout (ldab = 3 * 5 (N+1) - 2 rows of
+ * 8-byte entries per unknown plus a 4-byte pivot, Sec. 4.2.2); and everything a
+ * factor object holds resident (factors, the stage solve's FP64 scratch and, for
+ * FP32 factors of order N > 6, an FP64 assembly buffer): the figure the server
+ * charges against its HBM budget, per column of the 64-column tiles it
+ * allocates.  Any output pointer may be NULL. */
 hevi_status hevi_sizes(const hevi_shape *shape, hevi_precision prec, size_t *ops_bytes_per_col,
-                       size_t *factor_bytes_per_col, size_t *paper_band_bytes_per_col);
+                       size_t *factor_bytes_per_col, size_t *paper_band_bytes_per_col,
+                       size_t *resident_bytes_per_col);
 
 /* ---- groups: one ARK step for many column batches ---------------------------
  * A group advances n member problems -- column batches with their own

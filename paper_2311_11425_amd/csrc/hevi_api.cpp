@@ -64,9 +64,12 @@ hevi_status read_info(HeviDevInfo* d_info, hipStream_t st, hevi_info* out, bool 
 size_t factor_storage_bytes(const HeviShapeDev& sh, hevi_precision prec) {
   const size_t tn = tiles_nodes(sh);
   const size_t fs = prec == HEVI_FP64 ? sizeof(double) : sizeof(float);
-  // U, L, two byte planes (pivots, U row extents), stage scratch
-  size_t b = tn * (4 * sh.N + 1) * fs + tn * 2 * sh.N * fs + 2 * tn + tn * HEVI_NWS * sizeof(double);
-  if (prec != HEVI_FP64) b += tn * (4 * sh.N + 1) * sizeof(double);
+  // U, L, three byte planes (pivots, U row extents, row scales), stage scratch,
+  // and for FP32 factors of orders without the fused factorisation an FP64
+  // assembly buffer
+  size_t b = tn * (4 * sh.N + 1) * fs + tn * 2 * sh.N * fs + kFactorPlanes * tn +
+             tn * HEVI_NWS * sizeof(double);
+  if (needs_sbuf(sh, prec)) b += tn * (4 * sh.N + 1) * sizeof(double);
   return b;
 }
 
@@ -146,17 +149,27 @@ hevi_status hevi_build_column_ops(hevi_ctx* ctx, const hevi_shape* shape, const 
   o->sh = dev_shape(*shape);
   o->d_ops = nullptr;
   o->d_info = nullptr;
+  o->d_tilt = nullptr;
+  o->tilted = 0;
   if ((s = dev_alloc(&o->d_ops, tiles_nodes(o->sh) * HEVI_NOPS * sizeof(double))) ||
-      (s = dev_alloc(&o->d_info, sizeof(HeviDevInfo)))) {
+      (s = dev_alloc(&o->d_info, sizeof(HeviDevInfo))) ||
+      (s = dev_alloc(&o->d_tilt, sizeof(int32_t)))) {
     hevi_ops_free(o);
     return s;
   }
-  if (!ok(hevi_launch_info_reset(o->d_info, stream)) ||
+  // the geometry class (straight columns or not) selects the stage kernels, so it
+  // is read back here, once
+  int32_t tilt = 0;
+  if (!ok(hipMemcpyAsync(o->d_tilt, &tilt, sizeof(tilt), hipMemcpyHostToDevice, stream)) ||
+      !ok(hevi_launch_info_reset(o->d_info, stream)) ||
       !ok(hevi_launch_build_ops(o->sh, k->R, k->cp, k->g, k->p_A, d_z, d_J, d_gz, d_rho0,
-                                d_Theta0, o->d_ops, o->d_info, stream))) {
+                                d_Theta0, o->d_ops, o->d_info, o->d_tilt, stream)) ||
+      !ok(hipMemcpyAsync(&tilt, o->d_tilt, sizeof(tilt), hipMemcpyDeviceToHost, stream)) ||
+      !ok(hipStreamSynchronize(stream))) {
     hevi_ops_free(o);
     return HEVI_E_DEVICE;
   }
+  o->tilted = tilt != 0;
   *out = o;
   return HEVI_OK;
 }
@@ -174,6 +187,7 @@ void hevi_ops_free(hevi_ops* ops) {
   if (!ops) return;
   if (ops->d_ops) (void)hipFree(ops->d_ops);
   if (ops->d_info) (void)hipFree(ops->d_info);
+  if (ops->d_tilt) (void)hipFree(ops->d_tilt);
   delete ops;
 }
 
@@ -208,14 +222,15 @@ hevi_status hevi_factor(hevi_ctx* ctx, const hevi_ops* ops, double lambda, hevi_
   const int N = sh.N;
   hevi_status s;
   if ((s = dev_alloc(&f->U, tn * (4 * N + 1) * fs)) || (s = dev_alloc(&f->L, tn * 2 * N * fs)) ||
-      (s = dev_alloc(&f->piv, 2 * tn)) ||
+      (s = dev_alloc(&f->piv, kFactorPlanes * tn)) ||
       (s = dev_alloc(&f->ws, tn * HEVI_NWS * sizeof(double))) ||
       (s = dev_alloc(&f->d_info, sizeof(HeviDevInfo)))) {
     hevi_factors_free(f);
     return s;
   }
-  if (prec == HEVI_FP64) {
-    f->sbuf = (double*)f->U;
+  if (!needs_sbuf(sh, prec)) {
+    // FP64 factors assemble in place of U; the fused factorisation needs no buffer
+    f->sbuf = prec == HEVI_FP64 ? (double*)f->U : nullptr;
   } else if ((s = dev_alloc(&f->sbuf, tn * (4 * N + 1) * sizeof(double)))) {
     hevi_factors_free(f);
     return s;
@@ -313,7 +328,8 @@ hevi_status hevi_stage_solve(hevi_ctx* ctx, const hevi_factors* f, int32_t n_e,
   if (f->prec == HEVI_FP64) sweeps = 0;
   if (!ok(hipSetDevice(ctx->device))) return HEVI_E_DEVICE;
   if (h_info && !ok(hevi_launch_info_reset(f->d_info, stream))) return HEVI_E_DEVICE;
-  if (!ok(hevi_launch_stage_solve(o->sh, f->lambda, f->prec == HEVI_FP32_REFINE, o->d_ops,
+  if (!ok(hevi_launch_stage_solve(o->sh, f->lambda, o->tilted, f->prec == HEVI_FP32_REFINE,
+                                  o->d_ops,
                                   f->U, f->L, f->piv, f->ws, E, Q, d_Qi, sweeps, target, full,
                                   f->d_info, stream)))
     return HEVI_E_DEVICE;
@@ -431,7 +447,7 @@ hevi_status hevi_tableau(const char* name, int32_t* s, double* a_exp, double* a_
 }
 
 hevi_status hevi_sizes(const hevi_shape* shape, hevi_precision prec, size_t* ops_bytes,
-                       size_t* factor_bytes, size_t* paper_bytes) {
+                       size_t* factor_bytes, size_t* paper_bytes, size_t* resident_bytes) {
   hevi_status s = check_shape(shape);
   if (s) return s;
   if (prec != HEVI_FP64 && prec != HEVI_FP32_REFINE) return HEVI_E_INVALID;
@@ -439,7 +455,18 @@ hevi_status hevi_sizes(const hevi_shape* shape, hevi_precision prec, size_t* ops
   const size_t nz = (size_t)shape->n_elem * N + 1;
   const size_t fsz = prec == HEVI_FP64 ? 8 : 4;
   if (ops_bytes) *ops_bytes = nz * HEVI_NOPS * sizeof(double);
-  if (factor_bytes) *factor_bytes = nz * ((4 * N + 1) + 2 * N) * fsz + 2 * nz;
+  if (factor_bytes) *factor_bytes = nz * ((4 * N + 1) + 2 * N) * fsz + kFactorPlanes * nz;
+  if (resident_bytes) {
+    // what a factor object holds per column (factor_storage_bytes of a one-tile
+    // shape over its 64 columns): factors, byte planes, scratch, assembly buffer
+    HeviShapeDev one{};
+    one.N = N;
+    one.Ne = shape->n_elem;
+    one.nz = (int32_t)nz;
+    one.ncols = HEVI_TILE;
+    one.ntiles = 1;
+    *resident_bytes = factor_storage_bytes(one, prec) / HEVI_TILE;
+  }
   if (paper_bytes) {
     const size_t n = 5 * nz;
     const size_t ldab = 3 * 5 * (N + 1) - 2;

@@ -124,13 +124,10 @@ __device__ void div_pass(Gll<N> tab, const OpsView& op, int Ne, double* ws, int6
 
 // Pressure gradient + gravity of (v_rho, v_Th) (fields fr, ft):
 //   G_k = -M^-1 sum_e w_i sum_j D_ij (J c_Theta grad zeta)_j v_Th,j - Phi'_k grad(zeta)_k v_rho,k
-// MODE 0: write grad(zeta)_k . G_k into field fo (zero at the rigid-lid nodes).
-// MODE 1: final stage update Q_i = stored + lambda v (rho, Theta) and
-//         Q_U = stored + lambda^2 G (interior nodes) in the caller's Qi.
-template <int N, int MODE>
+// writes grad(zeta)_k . G_k into field fo (zero at the rigid-lid nodes).
+template <int N>
 __device__ void pg_pass(Gll<N> tab, const OpsView& op, int Ne, double* ws, int64_t tile,
-                        int lane, int fr, int ft, int fo, double lambda, double* Qi,
-                        int64_t ncols, int64_t c, bool valid, bool* nonfinite) {
+                        int lane, int fr, int ft, int fo) {
   const int nz = op.nz;
   double c0 = 0.0, c1 = 0.0, c2 = 0.0;
   for (int e = 0; e < Ne; ++e) {
@@ -164,29 +161,7 @@ __device__ void pg_pass(Gll<N> tab, const OpsView& op, int Ne, double* ws, int64
       const double G0 = -mi * s0 - ph * gx * vr;
       const double G1 = -mi * s1 - ph * gy * vr;
       const double G2 = -mi * s2 - ph * gzz * vr;
-      if (MODE == 0) {
-        ws[tix(tile, nz, k, HEVI_NWS, fo, lane)] = lid ? 0.0 : gx * G0 + gy * G1 + gzz * G2;
-      } else {
-        const double vt = ws[tix(tile, nz, k, HEVI_NWS, ft, lane)];
-        if (valid) {
-          double* q = Qi;
-          const size_t i0 = cix(nz, ncols, 0, k, c), i4 = cix(nz, ncols, 4, k, c);
-          const double qr = q[i0] + lambda * vr;
-          const double qt = q[i4] + lambda * vt;
-          q[i0] = qr;
-          q[i4] = qt;
-          bool fin = isfinite(qr) && isfinite(qt);
-          if (!lid) {
-            const double l2 = lambda * lambda;
-            const size_t i1 = cix(nz, ncols, 1, k, c), i2 = cix(nz, ncols, 2, k, c),
-                         i3 = cix(nz, ncols, 3, k, c);
-            const double q1 = q[i1] + l2 * G0, q2 = q[i2] + l2 * G1, q3 = q[i3] + l2 * G2;
-            q[i1] = q1; q[i2] = q2; q[i3] = q3;
-            fin = fin && isfinite(q1) && isfinite(q2) && isfinite(q3);
-          }
-          if (!fin) *nonfinite = true;
-        }
-      }
+      ws[tix(tile, nz, k, HEVI_NWS, fo, lane)] = lid ? 0.0 : gx * G0 + gy * G1 + gzz * G2;
     }
   }
 }
@@ -490,12 +465,38 @@ __device__ __forceinline__ int group_max(int v) {
   return v;
 }
 
-// The pivot array holds two byte planes of plane_size(sh) bytes each, laid out
-// like the factors: the pivot offset of step j, and the band offset of the last
-// nonzero entry of U row j.  U entries beyond it are exact zeros, which the
-// solves do not read (about half of each row at N = 4).
+// The pivot array holds three byte planes of plane_size(sh) bytes each, laid out
+// like the factors: the pivot offset of step j; the band offset of the last
+// nonzero entry of U row j (U entries beyond it are exact zeros, which the
+// solves do not read: about half of each row at N = 4); and the binary exponent
+// e_r of row r's scale 2^-e_r (signed byte, see scale_row).
 __device__ __forceinline__ size_t plane_size(const HeviShapeDev& sh) {
   return (size_t)sh.ntiles * sh.nz * T;
+}
+constexpr int kPlanes = 3;
+
+// Row equilibration of S by powers of two (LAPACK's row scaling of the band
+// system before the LU, with the scale rounded to a power of two so that
+// scaling is exact).  Row r is multiplied by 2^-e_r, e_r the binary exponent of
+// its largest |entry| (the group's lanes share the row), before it enters the
+// LU window, and the solves multiply r_r by the same 2^-e_r.  Pivoting then
+// compares entries relative to their rows' size.  Rows of S near element
+// boundaries, where the GLL spacing is smallest, are up to ~10x larger than the
+// others; without the scaling they win pivot searches they should not, and
+// the reduced solution loses about two digits at the ne = 30 shape.
+template <int LPC, int H>
+__device__ __forceinline__ void scale_row(double (&row)[H], int r, int nz, int h, int64_t tile,
+                                          int lane, uint8_t* __restrict__ piv, size_t plane) {
+  double m = 0.0;
+#pragma unroll
+  for (int i = 0; i < H; ++i) m = fmax(m, fabs(row[i]));
+  int ex = -4096;  // a lane whose part of the row is zero does not count
+  if (m > 0.0) (void)frexp(m, &ex);
+  ex = group_max<LPC>(ex);
+  ex = ex == -4096 ? 0 : min(max(ex, -120), 120);  // a zero row keeps scale 1
+#pragma unroll
+  for (int i = 0; i < H; ++i) row[i] = ldexp(row[i], -ex);
+  if (h == 0 && r < nz) piv[2 * plane + tix(tile, nz, r, 1, 0, lane)] = (uint8_t)(int8_t)ex;
 }
 
 // The band LU with each column's window split over LPC consecutive lanes: lane
@@ -623,6 +624,7 @@ __device__ __forceinline__ void b_factor_lu_split(int64_t tile, int part, HeviSh
 #pragma unroll
         for (int m = 0; m < H; ++m)
           Wn[B][m] = s0 + m < W ? s_fix<N>(rn, nz, s0 + m, ring[d][m]) : 0.0;
+        scale_row<LPC, H>(Wn[B], rn, nz, h, tile, lane, piv, plane_size(sh));
         const int rf = min(rn + PFL, nz - 1);
 #pragma unroll
         for (int m = 0; m < H; ++m)
@@ -730,6 +732,7 @@ __device__ __forceinline__ void b_factor_fused_split(int64_t tile, int part, Hev
         split_step<N, FT, LPC>(Wn, j, nz, h, s0, tile, lane, Ub, Lb, piv, plane, singular);
 #pragma unroll
         for (int m = 0; m < H; ++m) Wn[B][m] = slot[(a * H + m) * T];
+        scale_row<LPC, H>(Wn[B], j + B + 1, nz, h, tile, lane, piv, plane);
         ++j;
       }
     }
@@ -791,13 +794,16 @@ __device__ __forceinline__ void band_solve(const FT* __restrict__ Ub, const FT* 
   constexpr bool SKIP = std::is_same<FT, double>::value;
   const uint8_t* ue_p = piv + plane;
   auto pidx = [&](int k) { return tix(tile, nz, k, 1, 0, lane); };
+  // right-hand side entry k times its row's scale 2^-e_k (see scale_row)
+  auto rhs = [&](int k) {
+    const int kk = min(k, nz - 1);
+    const int ex = (int)(int8_t)piv[2 * plane + pidx(kk)];
+    return k < nz ? ldexp(S(kk, fi), -ex) : 0.0;
+  };
   // ---- forward: row swaps and unit-lower elimination ----
   double y[B + 1];
 #pragma unroll
-  for (int t = 0; t <= B; ++t) {
-    const double v = S(min(t, nz - 1), fi);
-    y[t] = (t < nz) ? v : 0.0;
-  }
+  for (int t = 0; t <= B; ++t) y[t] = rhs(t);
   double lr[PF][B], rin[PF];
   int pv[PF];
 #pragma unroll
@@ -806,9 +812,7 @@ __device__ __forceinline__ void band_solve(const FT* __restrict__ Ub, const FT* 
     pv[d] = piv[pidx(jj)];
 #pragma unroll
     for (int t = 0; t < B; ++t) lr[d][t] = ld(Lb + tix(tile, nz, jj, B, t, lane));
-    const int rn = d + B + 1;
-    const double rv = S(min(rn, nz - 1), fi);
-    rin[d] = (rn < nz) ? rv : 0.0;
+    rin[d] = rhs(d + B + 1);
   }
   for (int j0 = 0; j0 < nz; j0 += PF) {
 #pragma unroll
@@ -834,9 +838,7 @@ __device__ __forceinline__ void band_solve(const FT* __restrict__ Ub, const FT* 
         pv[d] = piv[pidx(jj)];
 #pragma unroll
         for (int t = 0; t < B; ++t) lr[d][t] = ld(Lb + tix(tile, nz, jj, B, t, lane));
-        const int rn = jn + B + 1;
-        const double rv = S(min(rn, nz - 1), fi);
-        rin[d] = (rn < nz) ? rv : 0.0;
+        rin[d] = rhs(jn + B + 1);
       }
     }
   }
@@ -908,9 +910,7 @@ __device__ void reduced_refine(Gll<N> tab, const OpsView& op, int Ne, double* ws
     const bool need = !(corr <= rel_target) && sweeps < max_sweeps;
     if (!__any(valid && need)) break;
     div_pass<N>(tab, op, Ne, ws, tile, lane, WS_U, WS_VR, WS_VT);
-    bool dummy = false;
-    pg_pass<N, 0>(tab, op, Ne, ws, tile, lane, WS_VR, WS_VT, WS_T, 0.0, nullptr, 0, 0, false,
-                  &dummy);
+    pg_pass<N>(tab, op, Ne, ws, tile, lane, WS_VR, WS_VT, WS_T);
     const double l2 = lambda * lambda;
     for (int k = 0; k < nz; ++k) {
       const double u = ws[tix(tile, nz, k, HEVI_NWS, WS_U, lane)];
@@ -1032,6 +1032,10 @@ __device__ void recover_pass(Gll<N> tab, const OpsView& op, int Ne, double* ws,
         d1 = b1 + lambda * (-mi * s0 - ph * gx * dr);
         d2 = b2 + lambda * (-mi * s1 - ph * gy * dr);
         d3 = b3 + lambda * (-mi * s2 - ph * gzz * dr);
+        // normal part from grad(zeta).d_U = u (see b_stage_update)
+        const double tn = (W(k, WS_U) - (gx * d1 + gy * d2 + gzz * d3)) /
+                          (gx * gx + gy * gy + gzz * gzz);
+        d1 += gx * tn; d2 += gy * tn; d3 += gzz * tn;
       }
       if (accumulate) {
         W(k, fx + 0) += dr; W(k, fx + 1) += d1; W(k, fx + 2) += d2; W(k, fx + 3) += d3;
@@ -1102,7 +1106,9 @@ __device__ void residual_pass(Gll<N> tab, const OpsView& op, int Ne, double* ws,
   }
 }
 
-template <int N, typename FT, bool FULL>
+// Stage solve with full-system FP64 iterative refinement (accuracy mode,
+// hevi_refine.full_sweeps > 0), one lane per column, every field in scratch.
+template <int N, typename FT>
 __device__ __forceinline__ void b_stage_solve(int64_t tile_, HeviShapeDev sh, Gll<N> tab,
                                               double lambda, const double* __restrict__ ops,
                                               const FT* __restrict__ Ub, const FT* __restrict__ Lb,
@@ -1120,7 +1126,6 @@ __device__ __forceinline__ void b_stage_solve(int64_t tile_, HeviShapeDev sh, Gl
   const int64_t nc = sh.ncols;
   OpsView op{ops, tile, nz, lane};
   bool nonfinite = false;
-  const bool full = FULL;
 
   // ---- pass 1: q^E, q^ = q^E + sum c_j Q_j, reduced right-hand side r ----
   double c0 = 0.0, c1 = 0.0, c2 = 0.0;
@@ -1172,35 +1177,21 @@ __device__ __forceinline__ void b_stage_solve(int64_t tile_, HeviShapeDev sh, Gl
       if (a == N && e < Ne - 1) { c0 = s0; c1 = s1; c2 = s2; continue; }
       const int k = e * N + a;
       const double gx = op(k, OP_GX), gy = op(k, OP_GY), gzz = op(k, OP_GZ);
-      double h1, h2, h3, r;
-      if (k == 0 || k == nz - 1) {
-        // rigid lid: Q_U = q^E_U - n (n . b_U), u = 0
-        const double inv = 1.0 / sqrt(gx * gx + gy * gy + gzz * gzz);
-        const double n0 = gx * inv, n1 = gy * inv, n2 = gzz * inv;
-        const double d = n0 * b[a][1] + n1 * b[a][2] + n2 * b[a][3];
-        h1 = qE[a][1] - n0 * d; h2 = qE[a][2] - n1 * d; h3 = qE[a][3] - n2 * d;
-        r = 0.0;
-      } else {
+      double r = 0.0;  // u = 0 at the rigid lid
+      if (k != 0 && k != nz - 1) {
         const double mi = op(k, OP_MINV), ph = op(k, OP_PHI);
         const double g1 = lambda * (-mi * s0 - ph * gx * b[a][0]);
         const double g2 = lambda * (-mi * s1 - ph * gy * b[a][0]);
         const double g3 = lambda * (-mi * s2 - ph * gzz * b[a][0]);
-        h1 = qE[a][1] + g1; h2 = qE[a][2] + g2; h3 = qE[a][3] + g3;
         r = gx * (b[a][1] + g1) + gy * (b[a][2] + g2) + gzz * (b[a][3] + g3);
       }
       ws[tix(tile, nz, k, HEVI_NWS, WS_R, lane)] = r;
-      if (full) {
-        // keep q^ (offset-free) for the full-system residual; Q_i holds q^E
+      // keep q^ (offset-free) for the full-system residual; Q_i holds q^E
 #pragma unroll
-        for (int v = 0; v < 5; ++v) ws[tix(tile, nz, k, HEVI_NWS, WS_B + v, lane)] = b[a][v];
-        h1 = qE[a][1]; h2 = qE[a][2]; h3 = qE[a][3];
-      }
+      for (int v = 0; v < 5; ++v) ws[tix(tile, nz, k, HEVI_NWS, WS_B + v, lane)] = b[a][v];
       if (valid) {
-        stn(Qi + cix(nz, nc, 0, k, c), qE[a][0]);
-        stn(Qi + cix(nz, nc, 1, k, c), h1);
-        stn(Qi + cix(nz, nc, 2, k, c), h2);
-        stn(Qi + cix(nz, nc, 3, k, c), h3);
-        stn(Qi + cix(nz, nc, 4, k, c), qE[a][4]);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) stn(Qi + cix(nz, nc, v, k, c), qE[a][v]);
       }
     }
   }
@@ -1214,12 +1205,7 @@ __device__ __forceinline__ void b_stage_solve(int64_t tile_, HeviShapeDev sh, Gl
                           plane_size(sh), max_sweeps,
                           rel_target, &sweeps, &relres);
 
-  if constexpr (!FULL) {
-    // ---- pass 3: recover rho, Theta and momentum; Q_i = q^E + lambda L_z x ----
-    div_pass<N>(tab, op, Ne, ws, tile, lane, WS_U, WS_VR, WS_VT);
-    pg_pass<N, 1>(tab, op, Ne, ws, tile, lane, WS_VR, WS_VT, 0, lambda, Qi, nc, c, valid,
-                  &nonfinite);
-  } else {
+  {
     // ---- full-system FP64 iterative refinement on x = q_tt (offset-free) ----
     recover_pass<N>(tab, op, Ne, ws, tile, lane, lambda, WS_B, WS_X, false);
     for (int it = 0; it < full_sweeps; ++it) {
@@ -1265,15 +1251,74 @@ __device__ __forceinline__ void b_stage_solve(int64_t tile_, HeviShapeDev sh, Gl
 }
 
 // ---------------------------------------------------------------------------
+// Momentum of the stage solution.  With u known, x_U = b_U + lambda G(x),
+// G = PG x_Theta - Phi' grad(zeta) x_rho, splits into its part along
+// grad(zeta), fixed by grad(zeta).x_U = u, and the tangential part of
+// lambda PG x_Theta (gravity acts along grad(zeta) only):
+//   x_U = P_t b_U + lambda (PG x_Theta)_t + grad(zeta) u / |grad(zeta)|^2.
+// The stage passes evaluate PG x_Theta as PG b_Theta (pass 1) plus
+// lambda PG DTh u (pass 3): two vectors ~|b_Theta| / |x_Theta| (about 100 at
+// the later ARK stages) larger than their sum, each the derivative of a large
+// field.  Taken whole, their rounding would swamp x_U.  Their tangential parts
+// are formed term by term from the tangential part of each grad(zeta)_j at the
+// output node k, which is exactly zero where grad(zeta)_j equals grad(zeta)_k
+// (straight columns): pg_tangent returns
+//   t_a = w_a sum_j D_aj p_j (|g_a|^2 g_j - (g_a . g_j) g_a) / |g_a|^2,
+// g_j = grad(zeta) at node j of the element, p_j = (J c_Theta)_j Theta_j, so that
+// (PG Theta)_t at node a is -M^-1 (sum of t_a over the elements containing it).
+template <int N>
+__device__ __forceinline__ double gdot(const double (&g0)[N + 1], const double (&g1)[N + 1],
+                                       const double (&g2)[N + 1], int a, int j) {
+#pragma clang fp contract(off)
+  return g0[a] * g0[j] + g1[a] * g1[j] + g2[a] * g2[j];
+}
+
+// True if grad(zeta) is the same vector at every node of the element in every
+// column of the wavefront (then every t_a is exactly zero).
+template <int N>
+__device__ __forceinline__ bool wave_straight(const double (&g0)[N + 1], const double (&g1)[N + 1],
+                                              const double (&g2)[N + 1]) {
+  bool same = true;
+#pragma unroll
+  for (int j = 1; j <= N; ++j)
+    same = same && g0[j] == g0[0] && g1[j] == g1[0] && g2[j] == g2[0];
+  return __all(same);
+}
+
+template <int N>
+__device__ __forceinline__ void pg_tangent(Gll<N> tab, int a, const double (&p)[N + 1],
+                                           const double (&g0)[N + 1], const double (&g1)[N + 1],
+                                           const double (&g2)[N + 1], double& t0, double& t1,
+                                           double& t2) {
+  // products rounded on their own: |g_a|^2 g_j - (g_a . g_j) g_a is then exactly
+  // zero whenever g_j == g_a
+#pragma clang fp contract(off)
+  const double gga = gdot<N>(g0, g1, g2, a, a);
+  t0 = 0.0; t1 = 0.0; t2 = 0.0;
+#pragma unroll
+  for (int j = 0; j <= N; ++j) {
+    if (j == a) continue;  // its tangential part is zero
+    const double dj = gdot<N>(g0, g1, g2, a, j);
+    const double dp = tab.D[a * (N + 1) + j] * p[j];
+    t0 += dp * (gga * g0[j] - dj * g0[a]);
+    t1 += dp * (gga * g1[j] - dj * g1[a]);
+    t2 += dp * (gga * g2[j] - dj * g2[a]);
+  }
+  const double sc = tab.w[a] / gga;
+  t0 *= sc; t1 *= sc; t2 *= sc;
+}
+
+// ---------------------------------------------------------------------------
 // Fast stage solve as three kernels: k_stage_rhs (element-chunked),
 // k_stage_bsolve (one lane per column), k_stage_update (element-chunked).
 
 // pass 1: q^E = sum e_t E_t and q^ = q^E + sum c_j Q_j at the owned nodes; writes
-// Q_i <- (q^E_rho, q^E_U + lambda (PG q^_Theta - Phi' grad(zeta) q^_rho), q^E_Theta)
-// (at the lid: Q_U <- q^E_U - n (n . q^_U)) and the reduced right-hand side
-// r = grad(zeta).(q^_U + lambda (PG q^_Theta - Phi' grad(zeta) q^_rho)) (0 at the lid).
+// the reduced right-hand side r = grad(zeta).(q^_U + lambda (PG q^_Theta - Phi'
+// grad(zeta) q^_rho)) (0 at the lid) and
+// Q_i <- (q^E_rho, q^E_U - n (n . q^_U) + lambda (PG q^_Theta)_t [interior], q^E_Theta)
+// with n = grad(zeta)/|grad(zeta)| and ( )_t the tangential part (see pg_tangent).
 // The term loop is outermost so that each term issues (N+1)*5 independent loads.
-template <int N, bool LDSRU = false>
+template <int N, bool LDSRU, bool TILT>
 __device__ __forceinline__ void b_stage_rhs(int64_t tile_, HeviShapeDev sh, Gll<N> tab,
                                             double lambda, const double* __restrict__ ops,
                                             double* __restrict__ ws, const HeviTerms& E,
@@ -1290,11 +1335,11 @@ __device__ __forceinline__ void b_stage_rhs(int64_t tile_, HeviShapeDev sh, Gll<
   const int64_t nc = sh.ncols;
   OpsView op{ops, tile, nz, lane};
   if (ch.e0 == 0) ws[tix(tile, nz, 0, HEVI_NWS, WS_T, lane)] = 0.0;  // per-column flag
-  double c0 = 0.0, c1 = 0.0, c2 = 0.0;
+  double c0 = 0.0, c1 = 0.0, c2 = 0.0, d0 = 0.0, d1 = 0.0, d2 = 0.0;
   // node eN is shared by elements e-1 and e: its sums and operator values are
   // carried over instead of being loaded again (the first element loads all)
   double kqE[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, kb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  double kg0 = 0.0, kg1 = 0.0, kg2 = 0.0, kmi = 0.0, kph = 0.0, kf0 = 0.0, kf1 = 0.0, kf2 = 0.0;
+  double kg0 = 0.0, kg1 = 0.0, kg2 = 0.0, kmi = 0.0, kph = 0.0, kpt = 0.0;
   auto element = [&](const int e, auto first) {
     constexpr bool FIRST = decltype(first)::value;
     double qE[N + 1][5], b[N + 1][5];
@@ -1339,46 +1384,53 @@ __device__ __forceinline__ void b_stage_rhs(int64_t tile_, HeviShapeDev sh, Gll<
 #pragma unroll
         for (int v = 0; v < 5; ++v) b[j][v] += cf * ldn(src + cix(nz, nc, v, e * N + j, cc));
     }
-    double g0[N + 1], g1[N + 1], g2[N + 1], mi[N + 1], ph[N + 1], f0[N + 1], f1[N + 1], f2[N + 1];
+    double g0[N + 1], g1[N + 1], g2[N + 1], mi[N + 1], ph[N + 1], pt[N + 1];
 #pragma unroll
     for (int j = 0; j <= N; ++j) {
       if (!FIRST && j == 0) {
-        g0[0] = kg0; g1[0] = kg1; g2[0] = kg2; mi[0] = kmi; ph[0] = kph;
-        f0[0] = kf0; f1[0] = kf1; f2[0] = kf2;
+        g0[0] = kg0; g1[0] = kg1; g2[0] = kg2; mi[0] = kmi; ph[0] = kph; pt[0] = kpt;
         continue;
       }
       const int k = e * N + j;
       g0[j] = op(k, OP_GX); g1[j] = op(k, OP_GY); g2[j] = op(k, OP_GZ);
       mi[j] = op(k, OP_MINV); ph[j] = op(k, OP_PHI);
-      const double p = op(k, OP_JCT) * b[j][4];
-      f0[j] = p * g0[j]; f1[j] = p * g1[j]; f2[j] = p * g2[j];
+      pt[j] = op(k, OP_JCT) * b[j][4];
     }
+    // TILT: some column's grad(zeta) varies; elsewhere every tangential term is zero
+    const bool straight = !TILT || wave_straight<N>(g0, g1, g2);
     double ro[N + 1], ho[N + 1][3];
 #pragma unroll
     for (int a = 0; a <= N; ++a) {
       double s0 = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll
       for (int j = 0; j <= N; ++j) {
-        const double d = tab.D[a * (N + 1) + j];
-        s0 += d * f0[j]; s1 += d * f1[j]; s2 += d * f2[j];
+        const double d = tab.D[a * (N + 1) + j] * pt[j];
+        s0 += d * g0[j]; s1 += d * g1[j]; s2 += d * g2[j];
       }
       s0 *= tab.w[a]; s1 *= tab.w[a]; s2 *= tab.w[a];
-      if (a == 0) { s0 += c0; s1 += c1; s2 += c2; }
-      if (a == N) { c0 = s0; c1 = s1; c2 = s2; }
+      double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+      if constexpr (TILT) {
+        if (!straight) pg_tangent<N>(tab, a, pt, g0, g1, g2, t0, t1, t2);
+      }
+      if (a == 0) { s0 += c0; s1 += c1; s2 += c2; t0 += d0; t1 += d1; t2 += d2; }
+      if (a == N) { c0 = s0; c1 = s1; c2 = s2; d0 = t0; d1 = t1; d2 = t2; }
       const int k = e * N + a;
       const double gx = g0[a], gy = g1[a], gzz = g2[a];
+      // normal part of q^_U removed (lid: the rigid-lid projection; interior: pass 3
+      // adds the normal part of the solution, grad(zeta) u / |grad(zeta)|^2)
+      const double gg = gx * gx + gy * gy + gzz * gzz;
+      const double bn = (gx * b[a][1] + gy * b[a][2] + gzz * b[a][3]) / gg;
+      ho[a][0] = qE[a][1] - gx * bn; ho[a][1] = qE[a][2] - gy * bn; ho[a][2] = qE[a][3] - gzz * bn;
       if (k == 0 || k == nz - 1) {
-        const double inv = 1.0 / sqrt(gx * gx + gy * gy + gzz * gzz);
-        const double n0 = gx * inv, n1 = gy * inv, n2 = gzz * inv;
-        const double d = n0 * b[a][1] + n1 * b[a][2] + n2 * b[a][3];
-        ho[a][0] = qE[a][1] - n0 * d; ho[a][1] = qE[a][2] - n1 * d; ho[a][2] = qE[a][3] - n2 * d;
         ro[a] = 0.0;
       } else {
         const double q1 = lambda * (-mi[a] * s0 - ph[a] * gx * b[a][0]);
         const double q2 = lambda * (-mi[a] * s1 - ph[a] * gy * b[a][0]);
         const double q3 = lambda * (-mi[a] * s2 - ph[a] * gzz * b[a][0]);
-        ho[a][0] = qE[a][1] + q1; ho[a][1] = qE[a][2] + q2; ho[a][2] = qE[a][3] + q3;
         ro[a] = gx * (b[a][1] + q1) + gy * (b[a][2] + q2) + gzz * (b[a][3] + q3);
+        // tangential part of lambda PG q^_Theta
+        const double lm = lambda * mi[a];
+        ho[a][0] -= lm * t0; ho[a][1] -= lm * t1; ho[a][2] -= lm * t2;
       }
     }
     if (e >= ch.e0) {
@@ -1401,8 +1453,7 @@ __device__ __forceinline__ void b_stage_rhs(int64_t tile_, HeviShapeDev sh, Gll<
     }
 #pragma unroll
     for (int v = 0; v < 5; ++v) { kqE[v] = qE[N][v]; kb[v] = b[N][v]; }
-    kg0 = g0[N]; kg1 = g1[N]; kg2 = g2[N]; kmi = mi[N]; kph = ph[N];
-    kf0 = f0[N]; kf1 = f1[N]; kf2 = f2[N];
+    kg0 = g0[N]; kg1 = g1[N]; kg2 = g2[N]; kmi = mi[N]; kph = ph[N]; kpt = pt[N];
   };
   int e = max(ch.e0 - 1, 0);
   element(e, std::true_type{});
@@ -1440,11 +1491,11 @@ __device__ __forceinline__ void b_stage_bsolve(int64_t tile_, HeviShapeDev sh, G
   }
 }
 
-// pass 3: v_rho = Drho u, v_Th = DTh u; Q_i += (lambda v_rho,
-// lambda^2 (PG v_Th - Phi' grad(zeta) v_rho) [interior], lambda v_Th).
+// pass 3: v_rho = Drho u, v_Th = DTh u; Q_i += (lambda v_rho, lambda^2 (PG v_Th)_t +
+// grad(zeta) u / |grad(zeta)|^2 [interior], lambda v_Th), ( )_t the tangential part.
 // An element needs u on its neighbours too (the DSS of Drho u, DTh u at its end
 // nodes), so each iteration loads u and the operator on nodes (e-1)N .. (e+2)N.
-template <int N, bool LDSRU = false>
+template <int N, bool LDSRU, bool TILT>
 __device__ __forceinline__ void b_stage_update(int64_t tile_, HeviShapeDev sh, Gll<N> tab,
                                                double lambda, const double* __restrict__ ops,
                                                double* __restrict__ ws, double* __restrict__ Qi,
@@ -1466,7 +1517,7 @@ __device__ __forceinline__ void b_stage_update(int64_t tile_, HeviShapeDev sh, G
   // consecutive elements share nodes eN .. (e+2)N of the u window and node eN of
   // the operator and Q_i: those values are carried over instead of loaded again
   double kJu[2 * N + 1], kJtu[2 * N + 1], kq[5];
-  double kg0 = 0.0, kg1 = 0.0, kg2 = 0.0, kmi = 0.0, kph = 0.0, kjc = 0.0;
+  double kg0 = 0.0, kg1 = 0.0, kg2 = 0.0, kmi = 0.0, kjc = 0.0;
   auto element = [&](const int e, auto first) {
     constexpr bool FIRST = decltype(first)::value;
     // ---- loads: u, J, J theta0 on nodes (e-1)N .. (e+2)N; operator and Q_i on the element
@@ -1485,25 +1536,25 @@ __device__ __forceinline__ void b_stage_update(int64_t tile_, HeviShapeDev sh, G
       Ju[q] = in * op(kk, OP_J) * u;
       Jtu[q] = in * op(kk, OP_JTH) * u;
     }
-    double g0[N + 1], g1[N + 1], g2[N + 1], mi[N + 1], ph[N + 1], jc[N + 1], q[N + 1][5];
+    double g0[N + 1], g1[N + 1], g2[N + 1], mi[N + 1], jc[N + 1], q[N + 1][5];
 #pragma unroll
     for (int j = 0; j <= N; ++j) {
       if (!FIRST && j == 0) {
-        g0[0] = kg0; g1[0] = kg1; g2[0] = kg2; mi[0] = kmi; ph[0] = kph; jc[0] = kjc;
+        g0[0] = kg0; g1[0] = kg1; g2[0] = kg2; mi[0] = kmi; jc[0] = kjc;
 #pragma unroll
         for (int v = 0; v < 5; ++v) q[0][v] = kq[v];
         continue;
       }
       const int k = e * N + j;
       g0[j] = op(k, OP_GX); g1[j] = op(k, OP_GY); g2[j] = op(k, OP_GZ);
-      mi[j] = op(k, OP_MINV); ph[j] = op(k, OP_PHI); jc[j] = op(k, OP_JCT);
+      mi[j] = op(k, OP_MINV); jc[j] = op(k, OP_JCT);
 #pragma unroll
       for (int v = 0; v < 5; ++v) q[j][v] = ldn(Qi + cix(nz, nc, v, k, cc));
     }
     // node N as loaded (before this element's update) is node 0 of the next
 #pragma unroll
     for (int v = 0; v < 5; ++v) kq[v] = q[N][v];
-    kg0 = g0[N]; kg1 = g1[N]; kg2 = g2[N]; kmi = mi[N]; kph = ph[N]; kjc = jc[N];
+    kg0 = g0[N]; kg1 = g1[N]; kg2 = g2[N]; kmi = mi[N]; kjc = jc[N];
 #pragma unroll
     for (int t = 0; t <= 2 * N; ++t) { kJu[t] = Ju[N + t]; kJtu[t] = Jtu[N + t]; }
     // ---- v_rho, v_Th at the element's nodes (contributions of elements e-1, e, e+1)
@@ -1532,34 +1583,37 @@ __device__ __forceinline__ void b_stage_update(int64_t tile_, HeviShapeDev sh, G
       sr[0] += r0; st[0] += tab.w[N] * t0;
       sr[N] += rN; st[N] += tab.w[0] * tN;
     }
-    double vr[N + 1], vt[N + 1], f0[N + 1], f1[N + 1], f2[N + 1];
+    double vr[N + 1], vt[N + 1], pt[N + 1];
 #pragma unroll
     for (int j = 0; j <= N; ++j) {
       vr[j] = mi[j] * sr[j];
       vt[j] = -mi[j] * st[j];
-      const double p = jc[j] * vt[j];
-      f0[j] = p * g0[j]; f1[j] = p * g1[j]; f2[j] = p * g2[j];
+      pt[j] = jc[j] * vt[j];
     }
-    // ---- pressure gradient and gravity, stage update
+    // ---- stage update: rho and Theta; momentum = the tangential part of
+    // lambda^2 PG v_Th plus the normal part grad(zeta) u / |grad(zeta)|^2 (see
+    // pg_tangent; pass 1 left q^E_U with q^_U's normal part removed)
+    // TILT: some column's grad(zeta) varies; elsewhere every tangential term is zero
+    const bool straight = !TILT || wave_straight<N>(g0, g1, g2);
 #pragma unroll
     for (int a = 0; a <= N; ++a) {
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-#pragma unroll
-      for (int j = 0; j <= N; ++j) {
-        const double d = tab.D[a * (N + 1) + j];
-        s0 += d * f0[j]; s1 += d * f1[j]; s2 += d * f2[j];
+      double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+      if constexpr (TILT) {
+        if (!straight) pg_tangent<N>(tab, a, pt, g0, g1, g2, t0, t1, t2);
       }
-      s0 *= tab.w[a]; s1 *= tab.w[a]; s2 *= tab.w[a];
-      if (a == 0) { s0 += c0; s1 += c1; s2 += c2; }
-      if (a == N) { c0 = s0; c1 = s1; c2 = s2; }
+      if (a == 0) { t0 += c0; t1 += c1; t2 += c2; }
+      if (a == N) { c0 = t0; c1 = t1; c2 = t2; }
       const int k = e * N + a;
       const bool lid = (k == 0) || (k == nz - 1);
       q[a][0] += lambda * vr[a];
       q[a][4] += lambda * vt[a];
       if (!lid) {
-        q[a][1] += l2 * (-mi[a] * s0 - ph[a] * g0[a] * vr[a]);
-        q[a][2] += l2 * (-mi[a] * s1 - ph[a] * g1[a] * vr[a]);
-        q[a][3] += l2 * (-mi[a] * s2 - ph[a] * g2[a] * vr[a]);
+        const double uk = LDSRU ? ru[k * T + lane] : ws[tix(tile, nz, k, HEVI_NWS, WS_U, lane)];
+        const double un = uk / (g0[a] * g0[a] + g1[a] * g1[a] + g2[a] * g2[a]);
+        const double lm = l2 * mi[a];
+        q[a][1] += g0[a] * un - lm * t0;
+        q[a][2] += g1[a] * un - lm * t1;
+        q[a][3] += g2[a] * un - lm * t2;
       }
     }
     if (e >= ch.e0 && valid) {

@@ -125,7 +125,7 @@ __global__ __launch_bounds__(64) void km_factor_fused(const HeviProbDev* __restr
   });
 }
 
-template <int NLO, int NHI>
+template <int NLO, int NHI, bool TILT>
 __global__ __launch_bounds__(64) void km_stage_rhs(const HeviProbDev* __restrict__ probs,
                                                    const HeviCallDev* __restrict__ calls,
                                                    HeviSched s) {
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(64) void km_stage_rhs(const HeviProbDev* __restrict
     const HeviCallDev& C = calls[p];
     switch_N<NLO, NHI>(P.sh.N, [&](auto n) {
       constexpr int NN = decltype(n)::value;
-      b_stage_rhs<NN>(tile, P.sh, Gll<NN>{}, P.lambda, P.ops, P.ws, C.E, C.Q, C.out);
+      b_stage_rhs<NN, false, TILT>(tile, P.sh, Gll<NN>{}, P.lambda, P.ops, P.ws, C.E, C.Q, C.out);
     });
   });
 }
@@ -154,7 +154,7 @@ __global__ __launch_bounds__(64) void km_stage_bsolve(const HeviProbDev* __restr
   });
 }
 
-template <int NLO, int NHI>
+template <int NLO, int NHI, bool TILT>
 __global__ __launch_bounds__(64) void km_stage_update(const HeviProbDev* __restrict__ probs,
                                                       const HeviCallDev* __restrict__ calls,
                                                       HeviSched s) {
@@ -163,13 +163,13 @@ __global__ __launch_bounds__(64) void km_stage_update(const HeviProbDev* __restr
     const HeviCallDev& C = calls[p];
     switch_N<NLO, NHI>(P.sh.N, [&](auto n) {
       constexpr int NN = decltype(n)::value;
-      b_stage_update<NN>(tile, P.sh, Gll<NN>{}, P.lambda, P.ops, P.ws, C.out, P.info);
+      b_stage_update<NN, false, TILT>(tile, P.sh, Gll<NN>{}, P.lambda, P.ops, P.ws, C.out, P.info);
     });
   });
 }
 
 // FP64 stage solve of a tile in one pass (as k_stage_fused): r/u in LDS
-template <int NLO, int NHI>
+template <int NLO, int NHI, bool TILT>
 __global__ __launch_bounds__(64) void km_stage_fused(const HeviProbDev* __restrict__ probs,
                                                      const HeviCallDev* __restrict__ calls,
                                                      HeviSched s) {
@@ -179,13 +179,15 @@ __global__ __launch_bounds__(64) void km_stage_fused(const HeviProbDev* __restri
     const HeviCallDev& C = calls[p];
     switch_N<NLO, NHI>(P.sh.N, [&](auto n) {
       constexpr int NN = decltype(n)::value;
-      b_stage_rhs<NN, true>(tile, P.sh, Gll<NN>{}, P.lambda, P.ops, P.ws, C.E, C.Q, C.out, ru);
+      b_stage_rhs<NN, true, TILT>(tile, P.sh, Gll<NN>{}, P.lambda, P.ops, P.ws, C.E, C.Q, C.out,
+                                  ru);
       __syncthreads();
       band_solve<NN, double, true>((const double*)P.U, (const double*)P.L, P.piv,
                                    plane_size(P.sh), P.ws, tile,
                                    P.sh.nz, (int)threadIdx.x, WS_R, WS_U, ru);
       __syncthreads();
-      b_stage_update<NN, true>(tile, P.sh, Gll<NN>{}, P.lambda, P.ops, P.ws, C.out, P.info, ru);
+      b_stage_update<NN, true, TILT>(tile, P.sh, Gll<NN>{}, P.lambda, P.ops, P.ws, C.out, P.info,
+                                     ru);
       __syncthreads();
     });
   });
@@ -225,7 +227,8 @@ __global__ void k_info_reset_n(HeviDevInfo* info, int n) {
 }
 
 template <int NLO, int NHI>
-hipError_t launch_range(int phase, int fp32, const HeviProbDev* probs, const HeviCallDev* calls,
+hipError_t launch_range(int phase, int fp32, int tilt, const HeviProbDev* probs,
+                        const HeviCallDev* calls,
                         const HeviSched& s, int grid, int max_sweeps, double rel_target,
                         int max_nz, hipStream_t st) {
   const dim3 g((unsigned)grid), b(T);
@@ -254,7 +257,8 @@ hipError_t launch_range(int phase, int fp32, const HeviProbDev* probs, const Hev
       }
       break;
     case HEVI_PH_STAGE_RHS:
-      hipLaunchKernelGGL((km_stage_rhs<NLO, NHI>), g, b, 0, st, probs, calls, s);
+      if (tilt) hipLaunchKernelGGL((km_stage_rhs<NLO, NHI, true>), g, b, 0, st, probs, calls, s);
+      else hipLaunchKernelGGL((km_stage_rhs<NLO, NHI, false>), g, b, 0, st, probs, calls, s);
       break;
     case HEVI_PH_STAGE_BSOLVE:
       if (fp32)
@@ -265,7 +269,10 @@ hipError_t launch_range(int phase, int fp32, const HeviProbDev* probs, const Hev
                            rel_target);
       break;
     case HEVI_PH_STAGE_UPDATE:
-      hipLaunchKernelGGL((km_stage_update<NLO, NHI>), g, b, 0, st, probs, calls, s);
+      if (tilt)
+        hipLaunchKernelGGL((km_stage_update<NLO, NHI, true>), g, b, 0, st, probs, calls, s);
+      else
+        hipLaunchKernelGGL((km_stage_update<NLO, NHI, false>), g, b, 0, st, probs, calls, s);
       break;
     case HEVI_PH_STAGE_FUSED:
       // single-order launches only (see the callers)
@@ -273,8 +280,11 @@ hipError_t launch_range(int phase, int fp32, const HeviProbDev* probs, const Hev
         return hipErrorInvalidValue;
       } else {
         if (fp32 || max_nz > HEVI_FUSED_MAX_NZ) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((km_stage_fused<NLO, NHI>), g, b, (size_t)max_nz * T * sizeof(double),
-                           st, probs, calls, s);
+        const size_t lds = (size_t)max_nz * T * sizeof(double);
+        if (tilt)
+          hipLaunchKernelGGL((km_stage_fused<NLO, NHI, true>), g, b, lds, st, probs, calls, s);
+        else
+          hipLaunchKernelGGL((km_stage_fused<NLO, NHI, false>), g, b, lds, st, probs, calls, s);
       }
       break;
     case HEVI_PH_COMBINE:
@@ -288,20 +298,21 @@ hipError_t launch_range(int phase, int fp32, const HeviProbDev* probs, const Hev
 
 }  // namespace
 
-hipError_t hevi_launch_multi(int phase, int nlo, int nhi, int fp32, const HeviProbDev* probs,
-                             const HeviCallDev* calls, const HeviSched& s, int grid,
-                             int max_sweeps, double rel_target, int max_nz, hipStream_t st) {
+hipError_t hevi_launch_multi(int phase, int nlo, int nhi, int fp32, int tilt,
+                             const HeviProbDev* probs, const HeviCallDev* calls,
+                             const HeviSched& s, int grid, int max_sweeps, double rel_target,
+                             int max_nz, hipStream_t st) {
   if (s.total == 0) return hipSuccess;
   if (grid < 1) return hipErrorInvalidValue;
   if (nlo == 1 && nhi == HEVI_MAXN)
-    return launch_range<1, HEVI_MAXN>(phase, fp32, probs, calls, s, grid, max_sweeps, rel_target,
-                                      max_nz, st);
+    return launch_range<1, HEVI_MAXN>(phase, fp32, tilt, probs, calls, s, grid, max_sweeps,
+                                      rel_target, max_nz, st);
   if (nlo != nhi) return hipErrorInvalidValue;
   switch (nlo) {
 #define HEVI_ONE_N(n)                                                                          \
   case n:                                                                                      \
-    return launch_range<n, n>(phase, fp32, probs, calls, s, grid, max_sweeps, rel_target,   \
-                              max_nz, st);
+    return launch_range<n, n>(phase, fp32, tilt, probs, calls, s, grid, max_sweeps,        \
+                              rel_target, max_nz, st);
     HEVI_ONE_N(1) HEVI_ONE_N(2) HEVI_ONE_N(3) HEVI_ONE_N(4)
     HEVI_ONE_N(5) HEVI_ONE_N(6) HEVI_ONE_N(7) HEVI_ONE_N(8)
 #undef HEVI_ONE_N

@@ -26,6 +26,7 @@ struct Launch {
   int64_t total;     // items
   size_t off;        // offset of plist (int32 x m, padded) + pstart (int64 x m+1) in d_sched
   int maxnz;         // largest n_z of the launch's members
+  int tilt;          // some member's columns are not straight
 };
 
 }  // namespace
@@ -85,15 +86,16 @@ hevi_status build_launches(hevi_group* g) {
     });
     std::vector<int32_t> pl;
     std::vector<int64_t> ps{0};
-    int maxnz = 1;
+    int maxnz = 1, tilt = 0;
     for (int p : ids) {
       if (g->probs[p].sh.ntiles == 0) continue;
       pl.push_back(p);
       ps.push_back(ps.back() + g->probs[p].sh.ntiles);
       maxnz = std::max(maxnz, g->probs[p].sh.nz);
+      tilt |= g->probs[p].tilt;
     }
     if (pl.empty()) return;
-    Launch l{nlo, nhi, -1, (int32_t)pl.size(), ps.back(), host.size(), maxnz};
+    Launch l{nlo, nhi, -1, (int32_t)pl.size(), ps.back(), host.size(), maxnz, tilt};
     const size_t a = pl.size() * sizeof(int32_t), pad = (a + 7) / 8 * 8;
     host.resize(host.size() + pad + ps.size() * sizeof(int64_t));
     std::memcpy(host.data() + l.off, pl.data(), a);
@@ -117,7 +119,8 @@ hevi_status build_launches(hevi_group* g) {
     per_order(L);
   } else {
     for (int i = 0; i < g->n; ++i)
-      if (g->probs[i].sh.ntiles > 0) L.push_back(Launch{0, 0, i, 0, 0, 0, g->probs[i].sh.nz});
+      if (g->probs[i].sh.ntiles > 0)
+        L.push_back(Launch{0, 0, i, 0, 0, 0, g->probs[i].sh.nz, g->probs[i].tilt});
   }
   // the factorisation runs per order in every multi-problem plan: one pass for the
   // orders up to HEVI_FUSED_FACTOR_MAX_N, and no kernel compiled for every order
@@ -148,7 +151,7 @@ hipError_t multi(hevi_group* g, const Launch& l, int ph, int slot, hipStream_t s
   s.ctr = g->d_ctr;
   const int64_t want = g->plan.grid > 0 ? g->plan.grid : l.total;
   const int grid = (int)std::min<int64_t>(want, l.total);
-  return hevi_launch_multi(ph, l.nlo, l.nhi, fp32, g->d_probs,
+  return hevi_launch_multi(ph, l.nlo, l.nhi, fp32, l.tilt, g->d_probs,
                            slot >= 0 ? g->d_calls + (size_t)slot * g->n : nullptr, s, grid,
                            fp32 ? g->sweeps : 0, g->target, l.maxnz, st);
 }
@@ -171,7 +174,7 @@ hipError_t phase(hevi_group* g, int ph, int slot, hipStream_t st) {
                                  P.info, st);
           break;
         case HEVI_PH_STAGE_RHS:
-          e = hevi_launch_stage_solve(P.sh, P.lambda, fp32, P.ops, P.U, P.L, P.piv, P.ws,
+          e = hevi_launch_stage_solve(P.sh, P.lambda, P.tilt, fp32, P.ops, P.U, P.L, P.piv, P.ws,
                                       C->E, C->Q, C->out, fp32 ? g->sweeps : 0, g->target, 0,
                                       P.info, st);
           break;
@@ -311,6 +314,7 @@ hevi_status hevi_group_create(hevi_ctx* ctx, int32_t n, const hevi_group_member*
     std::memset(&P, 0, sizeof(P));
     P.sh = o->sh;
     P.fp32 = prec == HEVI_FP32_REFINE;
+    P.tilt = o->tilted;
     P.lambda = g->lambda;
     P.ops = o->d_ops;
     P.sbuf = f->sbuf;

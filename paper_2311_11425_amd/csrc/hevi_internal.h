@@ -35,10 +35,14 @@ struct HeviShapeDev {
   int64_t ncols, ntiles;
 };
 
+// *tilted becomes nonzero if grad(zeta) is not the same vector (bitwise) at every
+// node of some column: the stage solves then need the tangential part of the
+// pressure gradient (the TILT kernels)
 hipError_t hevi_launch_build_ops(const HeviShapeDev& sh, double R, double cp,
                                  double g, double pA, const double* z, const double* J,
                                  const double* gz, const double* rho0, const double* Th0,
-                                 double* ops, HeviDevInfo* info, hipStream_t st);
+                                 double* ops, HeviDevInfo* info, int32_t* tilted,
+                                 hipStream_t st);
 
 hipError_t hevi_launch_apply(const HeviShapeDev& sh, const double* ops,
                              const double* x, const double* xref, double* y, hipStream_t st);
@@ -49,7 +53,8 @@ hipError_t hevi_launch_factor(const HeviShapeDev& sh, double lambda, int fp32,
                               const double* ops, double* sbuf, void* Ub, void* Lb, uint8_t* piv,
                               HeviDevInfo* info, hipStream_t st);
 
-hipError_t hevi_launch_stage_solve(const HeviShapeDev& sh, double lambda,
+// tilt: the operator's columns are not all straight (see hevi_launch_build_ops)
+hipError_t hevi_launch_stage_solve(const HeviShapeDev& sh, double lambda, int tilt,
                                    int fp32, const double* ops, const void* Ub, const void* Lb,
                                    const uint8_t* piv, double* ws, const HeviTerms& E,
                                    const HeviTerms& Q, double* Qi, int max_sweeps,
@@ -69,6 +74,7 @@ hipError_t hevi_launch_info_reset(HeviDevInfo* info, hipStream_t st);
 struct HeviProbDev {
   HeviShapeDev sh;
   int32_t fp32;           // factors stored in FP32
+  int32_t tilt;           // host use: the operator has columns that are not straight
   double lambda;
   const double* ops;
   double* sbuf;           // FP64 assembly buffer (aliases U for FP64 factors)
@@ -128,10 +134,13 @@ enum HeviPhase {
 // nlo..nhi: the orders the kernel is compiled for ((n, n) for n = 1..8, or
 // (1, HEVI_MAXN)); every problem in the schedule must have nlo <= N <= nhi.
 // fp32 / refine select the factor type and the reduced refinement of the
-// stage solve (max_sweeps, rel_target).  max_nz: the largest n_z of the
-// launch's problems (sizes the LDS of HEVI_PH_STAGE_FUSED).
-hipError_t hevi_launch_multi(int phase, int nlo, int nhi, int fp32, const HeviProbDev* probs,
-                             const HeviCallDev* calls, const HeviSched& s, int grid,
-                             int max_sweeps, double rel_target, int max_nz, hipStream_t st);
+// stage solve (max_sweeps, rel_target).  tilt: some problem of the launch has
+// columns that are not straight (the stage phases then use the TILT kernels).
+// max_nz: the largest n_z of the launch's problems (sizes the LDS of
+// HEVI_PH_STAGE_FUSED).
+hipError_t hevi_launch_multi(int phase, int nlo, int nhi, int fp32, int tilt,
+                             const HeviProbDev* probs, const HeviCallDev* calls,
+                             const HeviSched& s, int grid, int max_sweeps, double rel_target,
+                             int max_nz, hipStream_t st);
 
 hipError_t hevi_launch_info_reset_n(HeviDevInfo* info, int n, hipStream_t st);

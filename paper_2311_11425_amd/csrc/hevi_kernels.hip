@@ -14,7 +14,8 @@ __global__ __launch_bounds__(64) void k_build_ops(HeviShapeDev sh, double R, dou
                                                   const double* __restrict__ gzeta,
                                                   const double* __restrict__ rho0,
                                                   const double* __restrict__ Th0,
-                                                  double* __restrict__ ops, HeviDevInfo* info) {
+                                                  double* __restrict__ ops, HeviDevInfo* info,
+                                                  int32_t* tilted) {
   const Gll<N> tab{};
   const int lane = threadIdx.x;
   const int64_t tile = blockIdx.x;
@@ -25,6 +26,8 @@ __global__ __launch_bounds__(64) void k_build_ops(HeviShapeDev sh, double R, dou
   const int64_t nc = sh.ncols;
   const double gam = cp / (cp - R);
   bool bad = false;
+  bool bent = false;  // grad(zeta) not the same vector at every node of the column
+  double pg0 = 0.0, pg1 = 0.0, pg2 = 0.0;
   for (int k = 0; k < nz; ++k) {
     const double Jk = J[(size_t)k * nc + cc];
     const double r0 = rho0[(size_t)k * nc + cc];
@@ -32,6 +35,8 @@ __global__ __launch_bounds__(64) void k_build_ops(HeviShapeDev sh, double R, dou
     const double g0 = gzeta[cix(nz, nc, 0, k, cc)];
     const double g1 = gzeta[cix(nz, nc, 1, k, cc)];
     const double g2 = gzeta[cix(nz, nc, 2, k, cc)];
+    if (k > 0) bent = bent || g0 != pg0 || g1 != pg1 || g2 != pg2;
+    pg0 = g0; pg1 = g1; pg2 = g2;
     // lumped mass and gravity numerator, summed over the (one or two)
     // elements that contain node k
     double M = 0.0, Gn = 0.0;
@@ -72,6 +77,7 @@ __global__ __launch_bounds__(64) void k_build_ops(HeviShapeDev sh, double R, dou
     o[OP_PHI * T] = Gn / M;
   }
   if (bad && valid) flag(info, 1 /*HEVI_E_INVALID*/, c);
+  if (__any(bent && valid) && lane == 0) atomicOr(tilted, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -114,7 +120,7 @@ __global__ __launch_bounds__(64) void k_factor_fused(HeviShapeDev sh, double lam
                                    Gll<N>{}, lambda, ops, Ub, Lb, piv, info, lds);
 }
 
-template <int N, typename FT, bool FULL>
+template <int N, typename FT>
 __global__ __launch_bounds__(64) void k_stage_solve(HeviShapeDev sh, double lambda,
                                                     const double* __restrict__ ops,
                                                     const FT* __restrict__ Ub,
@@ -124,7 +130,7 @@ __global__ __launch_bounds__(64) void k_stage_solve(HeviShapeDev sh, double lamb
                                                     HeviTerms Q, double* __restrict__ Qi,
                                                     int max_sweeps, double rel_target,
                                                     int full_sweeps, HeviDevInfo* info) {
-  b_stage_solve<N, FT, FULL>((int64_t)blockIdx.x,
+  b_stage_solve<N, FT>((int64_t)blockIdx.x,
       sh, Gll<N>{}, lambda, ops, Ub, Lb, piv, ws, E, Q, Qi, max_sweeps, rel_target, full_sweeps,
       info);
 }
@@ -132,7 +138,7 @@ __global__ __launch_bounds__(64) void k_stage_solve(HeviShapeDev sh, double lamb
 // The FP64 stage solve in one kernel: the three passes run back to back in the
 // wavefront that owns the tile, with the reduced right-hand side r and the
 // solution u (one array, used in place) in LDS instead of the global scratch.
-template <int N>
+template <int N, bool TILT>
 __global__ __launch_bounds__(64, kStreamWaves<N>) void k_stage_fused(HeviShapeDev sh, double lambda,
                                                      const double* __restrict__ ops,
                                                      const double* __restrict__ Ub,
@@ -143,20 +149,20 @@ __global__ __launch_bounds__(64, kStreamWaves<N>) void k_stage_fused(HeviShapeDe
                                                      HeviDevInfo* info) {
   extern __shared__ double ru[];  // [n_z][64]
   const int64_t tile = blockIdx.x;
-  b_stage_rhs<N, true>(tile, sh, Gll<N>{}, lambda, ops, ws, E, Q, Qi, ru);
+  b_stage_rhs<N, true, TILT>(tile, sh, Gll<N>{}, lambda, ops, ws, E, Q, Qi, ru);
   __syncthreads();
   band_solve<N, double, true>(Ub, Lb, piv, plane_size(sh), ws, tile, sh.nz, (int)threadIdx.x, WS_R,
                               WS_U, ru);
   __syncthreads();
-  b_stage_update<N, true>(tile, sh, Gll<N>{}, lambda, ops, ws, Qi, info, ru);
+  b_stage_update<N, true, TILT>(tile, sh, Gll<N>{}, lambda, ops, ws, Qi, info, ru);
 }
 
-template <int N>
+template <int N, bool TILT>
 __global__ __launch_bounds__(64, kStreamWaves<N>) void k_stage_rhs(HeviShapeDev sh, double lambda,
                                                      const double* __restrict__ ops,
                                                      double* __restrict__ ws, HeviTerms E,
                                                      HeviTerms Q, double* __restrict__ Qi) {
-  b_stage_rhs<N>((int64_t)blockIdx.x, sh, Gll<N>{}, lambda, ops, ws, E, Q, Qi);
+  b_stage_rhs<N, false, TILT>((int64_t)blockIdx.x, sh, Gll<N>{}, lambda, ops, ws, E, Q, Qi);
 }
 
 template <int N, typename FT, bool REFINE>
@@ -171,12 +177,12 @@ __global__ __launch_bounds__(64, kStreamWaves<N>) void k_stage_bsolve(HeviShapeD
       sh, Gll<N>{}, lambda, ops, Ub, Lb, piv, ws, max_sweeps, rel_target, info);
 }
 
-template <int N>
+template <int N, bool TILT>
 __global__ __launch_bounds__(64, kStreamWaves<N>) void k_stage_update(HeviShapeDev sh, double lambda,
                                                      const double* __restrict__ ops,
                                                      double* __restrict__ ws,
                                                      double* __restrict__ Qi, HeviDevInfo* info) {
-  b_stage_update<N>((int64_t)blockIdx.x, sh, Gll<N>{}, lambda, ops, ws, Qi, info);
+  b_stage_update<N, false, TILT>((int64_t)blockIdx.x, sh, Gll<N>{}, lambda, ops, ws, Qi, info);
 }
 
 // ---------------------------------------------------------------------------
@@ -219,9 +225,9 @@ struct BuildOps {
   static hipError_t run(const HeviShapeDev& sh, double R, double cp, double g,
                         double pA, const double* z, const double* J, const double* gz,
                         const double* rho0, const double* Th0, double* ops, HeviDevInfo* info,
-                        hipStream_t st) {
+                        int32_t* tilted, hipStream_t st) {
     hipLaunchKernelGGL(k_build_ops<N>, dim3((unsigned)sh.ntiles), dim3(T), 0, st, sh, R, cp,
-                       g, pA, z, J, gz, rho0, Th0, ops, info);
+                       g, pA, z, J, gz, rho0, Th0, ops, info, tilted);
     return hipGetLastError();
   }
 };
@@ -275,7 +281,7 @@ struct Factor {
 
 template <int N>
 struct StageSolve {
-  static hipError_t run(const HeviShapeDev& sh, double lambda, int fp32,
+  static hipError_t run(const HeviShapeDev& sh, double lambda, int tilt, int fp32,
                         const double* ops, const void* Ub, const void* Lb, const uint8_t* piv,
                         double* ws, const HeviTerms& E, const HeviTerms& Q, double* Qi,
                         int max_sweeps, double rel_target, int full_sweeps, HeviDevInfo* info,
@@ -284,29 +290,31 @@ struct StageSolve {
     if (full_sweeps > 0) {
       // accuracy mode: one kernel with the full-system refinement sweeps
       if (fp32)
-        hipLaunchKernelGGL((k_stage_solve<N, float, true>), g, b, 0, st, sh, lambda, ops,
+        hipLaunchKernelGGL((k_stage_solve<N, float>), g, b, 0, st, sh, lambda, ops,
                            (const float*)Ub, (const float*)Lb, piv, ws, E, Q, Qi, max_sweeps,
                            rel_target, full_sweeps, info);
       else
-        hipLaunchKernelGGL((k_stage_solve<N, double, true>), g, b, 0, st, sh, lambda, ops,
+        hipLaunchKernelGGL((k_stage_solve<N, double>), g, b, 0, st, sh, lambda, ops,
                            (const double*)Ub, (const double*)Lb, piv, ws, E, Q, Qi, 0, rel_target,
                            full_sweeps, info);
       return hipGetLastError();
     }
     if (!fp32 && CW == 1 && sh.nz <= HEVI_FUSED_MAX_NZ) {
-      hipLaunchKernelGGL(k_stage_fused<N>, g, b, (size_t)sh.nz * T * sizeof(double), st, sh,
-                         lambda, ops, (const double*)Ub, (const double*)Lb, piv, ws, E, Q, Qi,
-                         info);
+      hipLaunchKernelGGL((tilt ? k_stage_fused<N, true> : k_stage_fused<N, false>), g, b,
+                         (size_t)sh.nz * T * sizeof(double), st, sh, lambda, ops,
+                         (const double*)Ub, (const double*)Lb, piv, ws, E, Q, Qi, info);
       return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_stage_rhs<N>, g, b4, 0, st, sh, lambda, ops, ws, E, Q, Qi);
+    hipLaunchKernelGGL((tilt ? k_stage_rhs<N, true> : k_stage_rhs<N, false>), g, b4, 0, st, sh,
+                       lambda, ops, ws, E, Q, Qi);
     if (fp32)
       hipLaunchKernelGGL((k_stage_bsolve<N, float, true>), g, b, 0, st, sh, lambda, ops,
                          (const float*)Ub, (const float*)Lb, piv, ws, max_sweeps, rel_target, info);
     else
       hipLaunchKernelGGL((k_stage_bsolve<N, double, false>), g, b, 0, st, sh, lambda, ops,
                          (const double*)Ub, (const double*)Lb, piv, ws, 0, rel_target, info);
-    hipLaunchKernelGGL(k_stage_update<N>, g, b4, 0, st, sh, lambda, ops, ws, Qi, info);
+    hipLaunchKernelGGL((tilt ? k_stage_update<N, true> : k_stage_update<N, false>), g, b4, 0, st,
+                       sh, lambda, ops, ws, Qi, info);
     return hipGetLastError();
   }
 };
@@ -316,9 +324,11 @@ struct StageSolve {
 hipError_t hevi_launch_build_ops(const HeviShapeDev& sh, double R, double cp,
                                  double g, double pA, const double* z, const double* J,
                                  const double* gz, const double* rho0, const double* Th0,
-                                 double* ops, HeviDevInfo* info, hipStream_t st) {
+                                 double* ops, HeviDevInfo* info, int32_t* tilted,
+                                 hipStream_t st) {
   if (sh.ntiles == 0) return hipSuccess;
-  return dispatch_N<BuildOps>(sh.N, sh, R, cp, g, pA, z, J, gz, rho0, Th0, ops, info, st);
+  return dispatch_N<BuildOps>(sh.N, sh, R, cp, g, pA, z, J, gz, rho0, Th0, ops, info, tilted,
+                              st);
 }
 
 hipError_t hevi_launch_apply(const HeviShapeDev& sh, const double* ops,
@@ -334,14 +344,14 @@ hipError_t hevi_launch_factor(const HeviShapeDev& sh, double lambda, int fp32,
   return dispatch_N<Factor>(sh.N, sh, lambda, fp32, ops, sbuf, Ub, Lb, piv, info, st);
 }
 
-hipError_t hevi_launch_stage_solve(const HeviShapeDev& sh, double lambda,
+hipError_t hevi_launch_stage_solve(const HeviShapeDev& sh, double lambda, int tilt,
                                    int fp32, const double* ops, const void* Ub, const void* Lb,
                                    const uint8_t* piv, double* ws, const HeviTerms& E,
                                    const HeviTerms& Q, double* Qi, int max_sweeps,
                                    double rel_target, int full_sweeps, HeviDevInfo* info,
                                    hipStream_t st) {
   if (sh.ntiles == 0) return hipSuccess;
-  return dispatch_N<StageSolve>(sh.N, sh, lambda, fp32, ops, Ub, Lb, piv, ws, E, Q, Qi,
+  return dispatch_N<StageSolve>(sh.N, sh, lambda, tilt, fp32, ops, Ub, Lb, piv, ws, E, Q, Qi,
                                 max_sweeps, rel_target, full_sweeps, info, st);
 }
 

@@ -21,6 +21,8 @@ struct hevi_ops {
   HeviShapeDev sh;
   double* d_ops;
   HeviDevInfo* d_info;
+  int32_t* d_tilt;  // device flag set by the ops build
+  int tilted;       // its value: some column's grad(zeta) is not one vector along it
 };
 
 struct hevi_factors {
@@ -58,6 +60,13 @@ void info_to_host(const HeviDevInfo& h, hevi_info* out);
 // validated linear-combination terms (lo = minimum count; empty = no columns)
 hevi_status terms(int32_t n, const double* const* v, const double* coef, int lo, bool empty,
                   HeviTerms* t);
+// byte planes beside the factors: pivot offsets, U row extents, row-scale exponents
+constexpr size_t kFactorPlanes = 3;
+// FP32 factors of orders without the fused assembly + LU need an FP64 assembly
+// buffer (FP64 factors assemble in place of U)
+inline bool needs_sbuf(const HeviShapeDev& sh, hevi_precision prec) {
+  return prec != HEVI_FP64 && sh.N > HEVI_FUSED_FACTOR_MAX_N;
+}
 // bytes of the library-owned storage of one factor object
 size_t factor_storage_bytes(const HeviShapeDev& sh, hevi_precision prec);
 

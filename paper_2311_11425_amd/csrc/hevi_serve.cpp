@@ -191,7 +191,7 @@ void launch_batch(hevi_server* S) {
   }
   // one schedule per launch class
   struct Sub {
-    int lo, hi, fp32, nlo, nhi, maxnz;
+    int lo, hi, fp32, nlo, nhi, maxnz, tilt;
     size_t off;
     int64_t total;
   };
@@ -200,11 +200,12 @@ void launch_batch(hevi_server* S) {
   for (int j = 0; j < n;) {
     int k = j;
     const int fp32 = sl.h_probs[j].fp32, c = cls(sl.h_probs[j]);
-    int nmin = HEVI_MAXN, nmax = 1, maxnz = 1;
+    int nmin = HEVI_MAXN, nmax = 1, maxnz = 1, tilt = 0;
     while (k < n && cls(sl.h_probs[k]) == c) {
       nmin = std::min(nmin, sl.h_probs[k].sh.N);
       nmax = std::max(nmax, sl.h_probs[k].sh.N);
       maxnz = std::max(maxnz, sl.h_probs[k].sh.nz);
+      tilt |= sl.h_probs[k].tilt;
       ++k;
     }
     const int m = k - j;
@@ -217,7 +218,8 @@ void launch_batch(hevi_server* S) {
       ps[t + 1] = ps[t] + sl.h_probs[j + t].sh.ntiles;
     }
     const bool one = nmin == nmax;
-    subs.push_back(Sub{j, k, fp32, one ? nmin : 1, one ? nmin : HEVI_MAXN, maxnz, off, ps[m]});
+    subs.push_back(
+        Sub{j, k, fp32, one ? nmin : 1, one ? nmin : HEVI_MAXN, maxnz, tilt, off, ps[m]});
     off += pad + (size_t)(m + 1) * 8;
     j = k;
   }
@@ -243,13 +245,15 @@ void launch_batch(hevi_server* S) {
     const int grid = (int)sb.total;
     const int sweeps = sb.fp32 ? S->sweeps : 0;
     if (!sb.fp32 && sb.nlo == sb.nhi && sb.maxnz <= HEVI_FUSED_MAX_NZ) {
-      okk = okk && ok(hevi_launch_multi(HEVI_PH_STAGE_FUSED, sb.nlo, sb.nhi, 0, sl.d_probs,
-                                        sl.d_calls, s, grid, 0, 1e-13, sb.maxnz, S->st));
+      okk = okk && ok(hevi_launch_multi(HEVI_PH_STAGE_FUSED, sb.nlo, sb.nhi, 0, sb.tilt,
+                                        sl.d_probs, sl.d_calls, s, grid, 0, 1e-13, sb.maxnz,
+                                        S->st));
       continue;
     }
     for (int ph : {HEVI_PH_STAGE_RHS, HEVI_PH_STAGE_BSOLVE, HEVI_PH_STAGE_UPDATE})
-      okk = okk && ok(hevi_launch_multi(ph, sb.nlo, sb.nhi, sb.fp32, sl.d_probs, sl.d_calls, s,
-                                        grid, sweeps, S->target, sb.maxnz, S->st));
+      okk = okk && ok(hevi_launch_multi(ph, sb.nlo, sb.nhi, sb.fp32, sb.tilt, sl.d_probs,
+                                        sl.d_calls, s, grid, sweeps, S->target, sb.maxnz,
+                                        S->st));
   }
   okk = okk &&
         ok(hipMemcpyAsync(sl.h_info, sl.d_info, sizeof(HeviDevInfo) * n, hipMemcpyDeviceToHost,
@@ -373,6 +377,7 @@ hevi_status hevi_serve_register(hevi_server* S, const hevi_ops* ops, double lamb
   std::memset(&sim.desc, 0, sizeof(sim.desc));
   sim.desc.sh = ops->sh;
   sim.desc.fp32 = prec == HEVI_FP32_REFINE;
+  sim.desc.tilt = ops->tilted;
   sim.desc.lambda = lambda;
   sim.desc.ops = ops->d_ops;
   sim.desc.sbuf = f->sbuf;

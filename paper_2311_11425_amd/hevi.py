@@ -122,7 +122,8 @@ def load():
         "hevi_combine": ([_vp, _vp, i32, pp, pd, _vp, _vp], ctypes.c_int),
         "hevi_tableau": ([ctypes.c_char_p, ctypes.POINTER(i32), pd, pd, pd], ctypes.c_int),
         "hevi_sizes": ([ctypes.POINTER(Shape), ctypes.c_int, ctypes.POINTER(ctypes.c_size_t),
-                        ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)],
+                        ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
+                        ctypes.POINTER(ctypes.c_size_t)],
                        ctypes.c_int),
         "hevi_group_create": ([_vp, i32, ctypes.POINTER(GroupMember), ctypes.c_char_p, dbl,
                                ctypes.c_int, ctypes.POINTER(Refine), pp, _vp], ctypes.c_int),
@@ -200,10 +201,10 @@ def tableau(name):
 def sizes(N, Ne, ncols=1, precision=HEVI_FP64):
     lib = load()
     sh = Shape(N, Ne, ncols)
-    o, f, p = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    o, f, p, r = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
     _check(lib.hevi_sizes(ctypes.byref(sh), precision, ctypes.byref(o), ctypes.byref(f),
-                          ctypes.byref(p)), "sizes")
-    return {"ops": o.value, "factors": f.value, "paper_band": p.value}
+                          ctypes.byref(p), ctypes.byref(r)), "sizes")
+    return {"ops": o.value, "factors": f.value, "paper_band": p.value, "resident": r.value}
 
 
 class Ops:

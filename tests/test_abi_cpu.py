@@ -66,8 +66,17 @@ def test_sizes():
     s = hevi.sizes(4, 10)
     nz = 41
     assert s["ops"] == nz * 8 * 8
-    assert s["factors"] == nz * (17 + 8) * 8 + 2 * nz
-    assert hevi.sizes(4, 10, precision=1)["factors"] == nz * 25 * 4 + 2 * nz
+    # U (4N+1) and L (2N) entries plus three byte planes (pivots, U extents, row scales)
+    assert s["factors"] == nz * (17 + 8) * 8 + 3 * nz
+    s32 = hevi.sizes(4, 10, precision=1)
+    assert s32["factors"] == nz * 25 * 4 + 3 * nz
+    # resident: factors + 21 FP64 scratch fields per node; FP32 factors of orders with
+    # the fused factorisation hold no FP64 assembly buffer
+    assert s["resident"] == s["factors"] + nz * 21 * 8
+    assert s32["resident"] == s32["factors"] + nz * 21 * 8
+    s7 = hevi.sizes(7, 10, precision=1)
+    nz7 = 71
+    assert s7["resident"] == s7["factors"] + nz7 * 21 * 8 + nz7 * 29 * 8
     # paper layout: LAPACK band with kl = ku = 5(N+1)-1, ldab = 2kl+ku+1 rows
     n = 5 * nz
     kl = 5 * 5 - 1

@@ -169,9 +169,6 @@ def test_group_stagewise_oracle(ctx, prec):
             x_or = oracle.solve_batch(col, lam, qE + P, refine=1)
             err = relerr_cols(Q[i] + P, x_or)
             tol = max(bar, 4 * stage_floor(oracle, col, lam, qE, P, Q[i], x_or))
-            if prec == 0:
-                plain = relerr_cols(oracle.solve_batch(col, lam, qE + P, refine=0), x_or)
-                tol = max(tol, 10 * plain)
             print(f"member {p} N={col['N']} stage {i + 1}: {err:.2e} (tol {tol:.2e})", flush=True)
             assert err < tol, (p, i, err, tol)
             assert relerr_cols(S[i], oracle.apply_batch(col, Q[i], qref)) < 1e-12

@@ -106,23 +106,21 @@ def test_solve_parity(ctx, name, prec):
     assert inf["status"] == "HEVI_OK", inf
     xo = oracle.solve_batch(col, lam, b, refine=1)
     err = relerr_cols(host(x), xo)
-    # an unrefined FP64 solve is held to 10 x the error of the oracle's own plain
-    # FP64 Gaussian elimination of the same system where that exceeds the bar
     plain = relerr_cols(oracle.solve_batch(col, lam, b, refine=0), xo)
-    tol = max(TOL64, 10 * plain) if prec == 0 else TOLMIX
-    print(f"rel err {err:.2e} (plain FP64 GEPP {plain:.2e}, tol {tol:.2e}) info {inf}", flush=True)
+    tol = TOL64 if prec == 0 else TOLMIX
+    print(f"rel err {err:.2e} (the oracle's own plain FP64 GEPP: {plain:.2e}, tol {tol:.2e}) "
+          f"info {inf}", flush=True)
     assert err < tol, err
     if prec == 1:
         assert inf["max_sweeps_used"] <= 4
         assert inf["max_rel_correction"] <= 1e-13
-    # one full-system FP64 refinement sweep meets the FP64 bar outright where the system
-    # allows it (an FP64 residual cannot resolve below the oracle's own plain-GEPP error)
+    # one full-system FP64 refinement sweep: the FP64 bar for either factor precision
     x1 = B.empty_state()
     inf = ctx.stage_solve(f, [dev(b)], [1.0], [], [], x1, refine=(4, 1e-13, 1), info=True)
     assert inf["status"] == "HEVI_OK", inf
     err1 = relerr_cols(host(x1), xo)
     print(f"with one full sweep: {err1:.2e}", flush=True)
-    assert err1 < max(TOL64, plain), err1
+    assert err1 < TOL64, err1
 
 
 def test_solve_identity_at_zero_lambda(ctx):
@@ -135,9 +133,12 @@ def test_solve_identity_at_zero_lambda(ctx):
     ctx.stage_solve(f, [dev(b)], [1.0], [], [], x)
     xo = oracle.solve_batch(col, 0.0, b, refine=0)
     xg = host(x)
-    # interior nodes and scalars are copied exactly; the lid projection may round differently
-    assert np.array_equal(xg[:, 1:-1, :], b[:, 1:-1, :])
+    # rho and Theta are copied exactly; the momentum is rebuilt from its parts
+    # tangential and normal to grad(zeta) (and projected at the lid), each rounded
+    # once: within a few ulp of |b_U| per node
     assert np.array_equal(xg[[0, 4]], b[[0, 4]])
+    bu = np.sqrt((b[1:4] ** 2).sum(axis=0))
+    assert np.all(np.abs(xg[1:4, 1:-1] - b[1:4, 1:-1]) <= 4 * np.finfo(float).eps * bu[1:-1])
     assert relerr_cols(xg, xo) < 1e-15
 
 
@@ -209,11 +210,7 @@ def test_ark_stagewise_parity(ctx, which, mode):
 
     Bar: 1e-12 (FP64, and FP32 factors with a full-system refinement sweep) or
     1e-10 (FP32 factors, reduced refinement), or 4 x the rounding floor of forming
-    q^ and q_tt from reference-sized terms where that is larger (stage_floor).  The
-    unrefined FP64 solve is held to 10 x the error of a plain FP64 LU solve of the
-    same q^ instead: the later stages' right-hand sides are ~100 x larger than their
-    solutions, which costs about two digits in any FP64 factorisation; one
-    full-system sweep (fp64_full1) restores the 1e-12 bar.
+    q^ and q_tt from reference-sized terms where that is larger (stage_floor).
     S_i = L_z (Q_i - q_ref) is checked against the oracle on the same Q_i."""
     from paper_2311_11425_amd.driver import ArkStepper, ColumnBatch
     if which == "ARK2_cfg1":
@@ -242,8 +239,6 @@ def test_ark_stagewise_parity(ctx, which, mode):
         err = relerr_cols(Q[i] + P, x_or)
         plain = relerr_cols(oracle.solve_batch(col, st.lam, qE + P, refine=0), x_or)
         tol = max(bar, 4 * stage_floor(oracle, col, st.lam, qE, P, Q[i], x_or))
-        if mode == "fp64":
-            tol = max(tol, 10 * plain)
         print(f"stage {i + 1}: solve rel err {err:.2e} (plain FP64 LU {plain:.2e}, "
               f"tolerance {tol:.2e})", flush=True)
         assert err < tol, (i, err, tol)
