@@ -66,7 +66,9 @@ typedef enum {
   HEVI_E_NOT_CONVERGED = 6, /* mixed path: refinement target not reached           */
   HEVI_E_BUSY = 7,          /* server: no slot or memory free right now            */
   HEVI_E_CLOSED = 8,        /* server: shut down or unknown id                     */
-  HEVI_E_NONFINITE = 9      /* a kernel produced or read a non-finite value        */
+  HEVI_E_NONFINITE = 9,     /* a kernel produced or read a non-finite value        */
+  HEVI_E_SCRATCH = 10       /* hevi_solve_noalloc: the shape needs more than its
+                               fixed scratch (HEVI_NOALLOC_SCRATCH_BYTES)             */
 } hevi_status;
 
 typedef enum {
@@ -195,6 +197,29 @@ hevi_status hevi_stage_solve(hevi_ctx *ctx, const hevi_factors *f, int32_t n_e,
                              const double *const *h_dE, const double *h_e, int32_t n_prev,
                              const double *const *h_dQprev, const double *h_c, double *d_Qi,
                              const hevi_refine *refine, hevi_info *h_info, hipStream_t stream);
+
+/* ---- allocation-free stage solve -------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  One call factors
+ * A = I - lambda L_z of `ops` (as hevi_factor with precision `prec`) and runs
+ * one stage solve with those factors (arguments and results as in
+ * hevi_stage_solve; zero pivots are reported through h_info as well).  It calls
+ * no hipMalloc, hipFree or other allocating routine: the factors, the stage
+ * solve's scratch and the kernel report live in a fixed device array of
+ * HEVI_NOALLOC_SCRATCH_BYTES per GPU, set up by hevi_create and held until the
+ * process ends.  A shape that needs more (about 15.5 KB per column at order 4
+ * with 41 nodes in FP64, so up to ~8,600 such columns) returns HEVI_E_SCRATCH
+ * before any work is enqueued.  Every call on one GPU uses that GPU's one
+ * array: calls that overlap in time on one GPU (several streams, several host
+ * threads, several contexts) race and must be serialised by the caller.  The
+ * results equal those of hevi_factor + hevi_stage_solve bit for bit. */
+#define HEVI_NOALLOC_SCRATCH_BYTES (128u << 20)
+hevi_status hevi_solve_noalloc(hevi_ctx *ctx, const hevi_ops *ops, double lambda,
+                               hevi_precision prec, int32_t n_e, const double *const *h_dE,
+                               const double *h_e, int32_t n_prev,
+                               const double *const *h_dQprev, const double *h_c, double *d_Qi,
+                               const hevi_refine *refine, hevi_info *h_info,
+                               hipStream_t stream);
 
 /* ---- linear combination (end of step, a6) ---------------------------------
  * out = sum_t coef[t] V_t over n_v state vectors (n_v in [1, 16]), e.g. the

@@ -11,8 +11,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhevi.so")
-SOURCES = ["hevi_kernels.hip", "hevi_group.hip", "hevi_api.cpp", "hevi_group_api.cpp",
-           "hevi_serve.cpp"]
+SOURCES = ["hevi_kernels.hip", "hevi_group.hip", "hevi_noalloc.hip", "hevi_api.cpp",
+           "hevi_group_api.cpp", "hevi_serve.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

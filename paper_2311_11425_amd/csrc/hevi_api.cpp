@@ -106,6 +106,7 @@ const char* hevi_status_str(hevi_status s) {
     case HEVI_E_BUSY: return "busy";
     case HEVI_E_CLOSED: return "closed";
     case HEVI_E_NONFINITE: return "non-finite value";
+    case HEVI_E_SCRATCH: return "shape exceeds the fixed scratch of hevi_solve_noalloc";
   }
   return "unknown status";
 }
@@ -119,6 +120,7 @@ hevi_status hevi_create(int device, hevi_ctx** out) {
   if (!ok(hipGetDeviceProperties(&prop, device))) return HEVI_E_DEVICE;
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return HEVI_E_DEVICE;
   if (!ok(hipSetDevice(device))) return HEVI_E_DEVICE;
+  if (hevi_noalloc_init(device) != HEVI_OK) return HEVI_E_DEVICE;
   hevi_ctx* c = new (std::nothrow) hevi_ctx;
   if (!c) return HEVI_E_NOMEM;
   c->device = device;

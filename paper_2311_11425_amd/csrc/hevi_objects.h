@@ -67,6 +67,9 @@ constexpr size_t kFactorPlanes = 3;
 inline bool needs_sbuf(const HeviShapeDev& sh, hevi_precision prec) {
   return prec != HEVI_FP64 && sh.N > HEVI_FUSED_FACTOR_MAX_N;
 }
+// address of the allocation-free entry point's device array on `device` (current),
+// taken once per device (hevi_create)
+hevi_status hevi_noalloc_init(int device);
 // bytes of the library-owned storage of one factor object
 size_t factor_storage_bytes(const HeviShapeDev& sh, hevi_precision prec);
 

@@ -18,13 +18,13 @@ HEVI_FP32_REFINE = 1
 
 STATUS = {0: "HEVI_OK", 1: "HEVI_E_INVALID", 2: "HEVI_E_SHAPE", 3: "HEVI_E_NOMEM",
           4: "HEVI_E_DEVICE", 5: "HEVI_E_SINGULAR", 6: "HEVI_E_NOT_CONVERGED", 7: "HEVI_E_BUSY",
-          8: "HEVI_E_CLOSED", 9: "HEVI_E_NONFINITE"}
+          8: "HEVI_E_CLOSED", 9: "HEVI_E_NONFINITE", 10: "HEVI_E_SCRATCH"}
 
 # every symbol include/hevi.h declares
 EXPORTS = ["hevi_create", "hevi_destroy", "hevi_status_str", "hevi_build_column_ops",
            "hevi_ops_check", "hevi_ops_free", "hevi_apply_op", "hevi_factor", "hevi_refactor",
            "hevi_factors_check", "hevi_factors_band_entries", "hevi_factors_free",
-           "hevi_stage_solve", "hevi_combine",
+           "hevi_stage_solve", "hevi_solve_noalloc", "hevi_combine",
            "hevi_tableau", "hevi_sizes", "hevi_group_create", "hevi_group_set_plan",
            "hevi_group_get_plan", "hevi_group_step", "hevi_group_check", "hevi_group_autotune",
            "hevi_group_free", "hevi_serve_create", "hevi_serve_register", "hevi_serve_submit",
@@ -119,6 +119,8 @@ def load():
         "hevi_factors_free": ([_vp], None),
         "hevi_stage_solve": ([_vp, _vp, i32, pp, pd, i32, pp, pd, _vp, ctypes.POINTER(Refine),
                               ctypes.POINTER(Info), _vp], ctypes.c_int),
+        "hevi_solve_noalloc": ([_vp, _vp, dbl, ctypes.c_int, i32, pp, pd, i32, pp, pd, _vp,
+                                ctypes.POINTER(Refine), ctypes.POINTER(Info), _vp], ctypes.c_int),
         "hevi_combine": ([_vp, _vp, i32, pp, pd, _vp, _vp], ctypes.c_int),
         "hevi_tableau": ([ctypes.c_char_p, ctypes.POINTER(i32), pd, pd, pd], ctypes.c_int),
         "hevi_sizes": ([ctypes.POINTER(Shape), ctypes.c_int, ctypes.POINTER(ctypes.c_size_t),
@@ -313,6 +315,24 @@ class Context:
                                          _ptr(Qi), ctypes.byref(ref) if ref else None,
                                          ctypes.byref(inf) if inf else None, _stream(stream)),
                "hevi_stage_solve")
+        return inf.as_dict() if inf else None
+
+    def solve_noalloc(self, ops, lam, precision, E, e, Qprev, c, Qi, refine=None, info=False,
+                      stream=None):
+        """hevi_solve_noalloc: factor A = I - lam L_z and one stage solve, with the
+        library's fixed per-GPU scratch (no allocation); arguments as stage_solve."""
+        Ep, ep = _ptr_array(E), _dbl_array(e)
+        Qp, cp = _ptr_array(Qprev), _dbl_array(c)
+        ref = None
+        if refine is not None:
+            r = tuple(refine) + (0,) * (3 - len(refine))
+            ref = Refine(int(r[0]), float(r[1]), int(r[2]))
+        inf = Info() if info else None
+        _check(self.lib.hevi_solve_noalloc(self.handle, ops.handle, ctypes.c_double(lam),
+                                           int(precision), len(E), Ep, ep, len(Qprev), Qp, cp,
+                                           _ptr(Qi), ctypes.byref(ref) if ref else None,
+                                           ctypes.byref(inf) if inf else None, _stream(stream)),
+               "hevi_solve_noalloc")
         return inf.as_dict() if inf else None
 
     def combine(self, ops, V, coef, out, stream=None):
