@@ -524,7 +524,111 @@ def serve_leg(ctx, checks, rates=(0.25, 0.5, 0.75, 1.0, 1.2), per_rate=300, scal
                                 BARS[pname], combine="max")
         d["oracle_sample"] = f"{len(check)} simulations x 12 columns"
         out[pname] = d
+    out["admission"] = serve_admission(ctx, sims, lam, out["fp64"]["saturation_requests_per_s"],
+                                       per_rate, seed)
     return out
+
+
+def serve_admission(ctx, sims, lam, sat, n_req, seed, budget_frac=0.5, load=0.5):
+    """Serving under memory pressure: an HBM budget of `budget_frac` of the 16
+    simulations' resident footprint (FP64 factors), Poisson arrivals at `load` x
+    the FP64 saturation rate over uniformly chosen simulations.  A request for a
+    simulation that is not registered registers it; when the server refuses
+    (HEVI_E_NOMEM) the least recently used simulation is released and the
+    registration retried.  Latency is arrival to completion (registration
+    included); warm requests (simulation resident) and cold ones are reported
+    apart."""
+    import threading
+    from paper_2311_11425_amd import hevi
+    sizes = [hevi.sizes(4, sm["col"]["Ne"], sm["ncols"], precision=0)["resident"] * 64 *
+             ((sm["ncols"] + 63) // 64) for sm in sims]
+    budget = int(budget_frac * sum(sizes))
+    srv = hevi.Server(ctx, budget, max_inflight=1 << 16, refine=(8, 1e-13))
+    active = {}              # simulation index -> server id, least recently used first
+    stats = {"registrations": 0, "refused_registrations": 0, "evictions": 0}
+    reg_s = []
+
+    def ensure(k):
+        if k in active:
+            active[k] = active.pop(k)
+            return False
+        t = time.perf_counter()
+        while True:
+            try:
+                sid = srv.register(sims[k]["B"].ops, lam, precision=0)
+                break
+            except hevi.HeviError as err:
+                if err.code != 3 or not active:
+                    raise
+                stats["refused_registrations"] += 1
+                victim = next(iter(active))
+                srv.release(active.pop(victim))
+                stats["evictions"] += 1
+        active[k] = sid
+        stats["registrations"] += 1
+        reg_s.append(time.perf_counter() - t)
+        return True
+
+    def submit(k):
+        sm = sims[k]
+        while True:
+            code, t = srv.submit_raw(active[k], sm["Ep"], sm["ep"], 2, sm["Qp"], sm["cp"], 1,
+                                     sm["out"])
+            if code == 0:
+                return t
+            if code != 7:
+                raise hevi.HeviError(code, "hevi_serve_submit")
+
+    rng = np.random.default_rng(seed + 1)
+    gaps = rng.exponential(1.0 / (load * sat), n_req)
+    which = rng.integers(0, len(sims), n_req)
+    arrivals, tickets, cold = [0.0] * n_req, [None] * n_req, [False] * n_req
+    ready = threading.Semaphore(0)
+
+    def producer():
+        t_next = time.perf_counter()
+        for i in range(n_req):
+            t_next += gaps[i]
+            while True:
+                dl = t_next - time.perf_counter()
+                if dl <= 0:
+                    break
+                if dl > 0.002:
+                    time.sleep(dl - 0.001)
+            arrivals[i] = t_next
+            cold[i] = ensure(int(which[i]))
+            tickets[i] = submit(int(which[i]))
+            ready.release()
+
+    lat = []
+    t0 = time.perf_counter()
+    th = threading.Thread(target=producer)
+    th.start()
+    for i in range(n_req):
+        ready.acquire()
+        inf, _ = srv.wait(tickets[i])
+        if inf["status"] != "HEVI_OK":
+            raise SystemExit(f"serve admission: request reported {inf}")
+        lat.append(time.perf_counter() - arrivals[i])
+    th.join()
+    wall = time.perf_counter() - t0
+    srv.close()
+    warm = [l for l, c in zip(lat, cold) if not c]
+    cold_l = [l for l, c in zip(lat, cold) if c]
+    ms = lambda v, p: 1e3 * pct(v, p)
+    log(f"serve admission: budget {budget / 1e9:.1f} GB of {sum(sizes) / 1e9:.1f} GB, "
+        f"{stats['registrations']} registrations, {stats['evictions']} evictions")
+    return dict(stats, **{
+        "budget_bytes": budget, "footprint_all_bytes": int(sum(sizes)),
+        "offered_requests_per_s": load * sat, "achieved_requests_per_s": n_req / wall,
+        "requests": n_req, "cold_requests": int(sum(cold)),
+        "latency_ms": {"p50": ms(lat, 50), "p99": ms(lat, 99)},
+        "warm_latency_ms": {"p50": ms(warm, 50), "p99": ms(warm, 99)},
+        "cold_latency_ms": {"p50": ms(cold_l, 50), "p99": ms(cold_l, 99)},
+        "registration_ms": {"p50": ms(reg_s, 50), "p99": ms(reg_s, 99)},
+        "policy": "register on first request; on HEVI_E_NOMEM release the least recently "
+                  "used simulation (after its pending requests) and retry; latency from "
+                  "arrival to completion, registration included"})
 
 
 def run_path(ctx, B, name, qd, qrd, steps, warmup):

@@ -206,8 +206,32 @@ hevi_status hevi_apply_op(hevi_ctx* ctx, const hevi_ops* ops, const double* d_x,
   return HEVI_OK;
 }
 
+}  // extern "C"
+
+namespace hevi_host {
+
+hevi_status factor_impl(hevi_ctx* ctx, const hevi_ops* ops, double lambda, hevi_precision prec,
+                        hevi_factors** out, hipStream_t stream, bool stream_ordered);
+
+hevi_status factor_stream_ordered(hevi_ctx* ctx, const hevi_ops* ops, double lambda,
+                                  hevi_precision prec, hevi_factors** out, hipStream_t stream) {
+  return factor_impl(ctx, ops, lambda, prec, out, stream, true);
+}
+
+}  // namespace hevi_host
+
+extern "C" {
+
 hevi_status hevi_factor(hevi_ctx* ctx, const hevi_ops* ops, double lambda, hevi_precision prec,
                         hevi_factors** out, hipStream_t stream) {
+  return factor_impl(ctx, ops, lambda, prec, out, stream, false);
+}
+
+}  // extern "C"
+
+hevi_status hevi_host::factor_impl(hevi_ctx* ctx, const hevi_ops* ops, double lambda,
+                                   hevi_precision prec, hevi_factors** out, hipStream_t stream,
+                                   bool stream_ordered) {
   if (!ctx || !ops || !out) return HEVI_E_INVALID;
   *out = nullptr;
   if (prec != HEVI_FP64 && prec != HEVI_FP32_REFINE) return HEVI_E_INVALID;
@@ -218,22 +242,27 @@ hevi_status hevi_factor(hevi_ctx* ctx, const hevi_ops* ops, double lambda, hevi_
   std::memset(f, 0, sizeof(*f));
   f->ops = ops;
   f->prec = prec;
+  f->stream_ordered = stream_ordered;
+  f->alloc_stream = stream;
   const HeviShapeDev& sh = ops->sh;
   const size_t tn = tiles_nodes(sh);
   const size_t fs = prec == HEVI_FP64 ? sizeof(double) : sizeof(float);
   const int N = sh.N;
+  auto alloc = [&](auto** p, size_t bytes) {
+    return stream_ordered ? dev_alloc_on(p, bytes, stream) : dev_alloc(p, bytes);
+  };
   hevi_status s;
-  if ((s = dev_alloc(&f->U, tn * (4 * N + 1) * fs)) || (s = dev_alloc(&f->L, tn * 2 * N * fs)) ||
-      (s = dev_alloc(&f->piv, kFactorPlanes * tn)) ||
-      (s = dev_alloc(&f->ws, tn * HEVI_NWS * sizeof(double))) ||
-      (s = dev_alloc(&f->d_info, sizeof(HeviDevInfo)))) {
+  if ((s = alloc(&f->U, tn * (4 * N + 1) * fs)) || (s = alloc(&f->L, tn * 2 * N * fs)) ||
+      (s = alloc(&f->piv, kFactorPlanes * tn)) ||
+      (s = alloc(&f->ws, tn * HEVI_NWS * sizeof(double))) ||
+      (s = alloc(&f->d_info, sizeof(HeviDevInfo)))) {
     hevi_factors_free(f);
     return s;
   }
   if (!needs_sbuf(sh, prec)) {
     // FP64 factors assemble in place of U; the fused factorisation needs no buffer
     f->sbuf = prec == HEVI_FP64 ? (double*)f->U : nullptr;
-  } else if ((s = dev_alloc(&f->sbuf, tn * (4 * N + 1) * sizeof(double)))) {
+  } else if ((s = alloc(&f->sbuf, tn * (4 * N + 1) * sizeof(double)))) {
     hevi_factors_free(f);
     return s;
   }
@@ -248,6 +277,8 @@ hevi_status hevi_factor(hevi_ctx* ctx, const hevi_ops* ops, double lambda, hevi_
   *out = f;
   return HEVI_OK;
 }
+
+extern "C" {
 
 hevi_status hevi_refactor(hevi_ctx* ctx, hevi_factors* f, double lambda, hipStream_t stream) {
   if (!ctx || !f) return HEVI_E_INVALID;
@@ -290,12 +321,17 @@ hevi_status hevi_factors_band_entries(hevi_ctx* ctx, const hevi_factors* f, int6
 
 void hevi_factors_free(hevi_factors* f) {
   if (!f) return;
-  if (f->sbuf && f->sbuf != (double*)f->U) (void)hipFree(f->sbuf);
-  if (f->U) (void)hipFree(f->U);
-  if (f->L) (void)hipFree(f->L);
-  if (f->piv) (void)hipFree(f->piv);
-  if (f->ws) (void)hipFree(f->ws);
-  if (f->d_info) (void)hipFree(f->d_info);
+  auto fr = [&](void* p) {
+    if (!p) return;
+    if (f->stream_ordered) (void)hipFreeAsync(p, f->alloc_stream);
+    else (void)hipFree(p);
+  };
+  if (f->sbuf != (double*)f->U) fr(f->sbuf);
+  fr(f->U);
+  fr(f->L);
+  fr(f->piv);
+  fr(f->ws);
+  fr(f->d_info);
   delete f;
 }
 

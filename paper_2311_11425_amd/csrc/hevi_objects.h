@@ -35,6 +35,8 @@ struct hevi_factors {
   double* sbuf;  // FP64 assembly buffer (aliases U for FP64 factors)
   double* ws;    // per-node FP64 scratch of the stage solve
   HeviDevInfo* d_info;
+  hipStream_t alloc_stream;  // buffers allocated stream-ordered on it (server), or 0
+  bool stream_ordered;
 };
 
 namespace hevi_host {
@@ -50,6 +52,24 @@ hevi_status dev_alloc(P** p, size_t bytes) {
   *p = (P*)v;
   return HEVI_OK;
 }
+
+// stream-ordered allocation on `st` (freed with hipFreeAsync on the same stream):
+// neither call waits for the device
+template <typename P>
+hevi_status dev_alloc_on(P** p, size_t bytes, hipStream_t st) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 256;
+  void* v = nullptr;
+  if (!ok(hipMallocAsync(&v, bytes, st))) return HEVI_E_NOMEM;
+  *p = (P*)v;
+  return HEVI_OK;
+}
+
+// hevi_factor with the factor object's buffers allocated stream-ordered on
+// `stream` (and freed the same way by hevi_factors_free): the server's
+// registrations and releases then never wait for the whole device
+hevi_status factor_stream_ordered(hevi_ctx* ctx, const hevi_ops* ops, double lambda,
+                                  hevi_precision prec, hevi_factors** out, hipStream_t stream);
 
 HeviShapeDev dev_shape(const hevi_shape& s);
 hevi_status check_shape(const hevi_shape* s);

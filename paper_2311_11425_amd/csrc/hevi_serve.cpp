@@ -368,7 +368,7 @@ hevi_status hevi_serve_register(hevi_server* S, const hevi_ops* ops, double lamb
   if (S->used + bytes > S->budget) return HEVI_E_NOMEM;
   if (!ok(hipSetDevice(S->ctx->device))) return HEVI_E_DEVICE;
   hevi_factors* f = nullptr;
-  hevi_status s = hevi_factor(S->ctx, ops, lambda, prec, &f, S->st);
+  hevi_status s = factor_stream_ordered(S->ctx, ops, lambda, prec, &f, S->st);
   if (s) return s;
   Sim sim;
   sim.ops = ops;
@@ -464,11 +464,11 @@ hevi_status hevi_serve_release(hevi_server* S, int32_t sim_id) {
   S->sims.erase(sim_id);
   S->used -= sim.bytes;
   lk.unlock();
-  // the stream may still hold the simulation's last batch: wait for it
+  // its requests have completed; the buffers go back stream-ordered on the
+  // server's stream (after everything queued there), so nothing waits here
   (void)hipSetDevice(S->ctx->device);
-  const bool good = ok(hipStreamSynchronize(S->st));
   hevi_factors_free(sim.fac);
-  return good ? HEVI_OK : HEVI_E_DEVICE;
+  return HEVI_OK;
 }
 
 void hevi_serve_destroy(hevi_server* S) {
@@ -482,6 +482,7 @@ void hevi_serve_destroy(hevi_server* S) {
   (void)hipSetDevice(S->ctx->device);
   (void)hipStreamSynchronize(S->st);
   for (auto& kv : S->sims) hevi_factors_free(kv.second.fac);
+  (void)hipStreamSynchronize(S->st);  // the stream-ordered frees, before the stream goes
   free_slots(S);
   if (S->d_ctr) (void)hipFree(S->d_ctr);
   if (S->st) (void)hipStreamDestroy(S->st);

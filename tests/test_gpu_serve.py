@@ -168,10 +168,17 @@ def test_serve_ark4_step_matches_stepper(ctx, prec):
     srv.close()
 
 
+def resident_bytes(spec, prec):
+    """What the server charges for a simulation: hevi_sizes' resident bytes per
+    column over the 64-column tiles it allocates."""
+    from paper_2311_11425_amd import hevi
+    per_col = hevi.sizes(spec["N"], spec["Ne"], spec["ncols"], precision=prec)["resident"]
+    return per_col * 64 * ((spec["ncols"] + 63) // 64)
+
+
 def test_serve_admission_busy_closed(ctx):
     from paper_2311_11425_amd import hevi
     a, b = SimData(ctx, SPECS[0]), SimData(ctx, SPECS[1])
-    sz_a = hevi.sizes(4, 12, 300)
     for bad in ((4, 1e-13, 1), (-1, 1e-13), (65, 1e-13), (4, -1.0)):
         with pytest.raises(hevi.HeviError) as e:
             hevi.Server(ctx, 1 << 20, refine=bad)
@@ -181,16 +188,14 @@ def test_serve_admission_busy_closed(ctx):
         srv.register(a.B.ops, LAM)
     assert e.value.code == 3
     srv.close()
-    # budget for one simulation: the second waits for a release
-    srv = hevi.Server(ctx, 64 << 20, max_inflight=2)
+    # a budget one byte short of both simulations: a fits, b is refused until a is
+    # released, then admitted
+    ra, rb = resident_bytes(SPECS[0], 0), resident_bytes(SPECS[1], 0)
+    srv = hevi.Server(ctx, ra + rb - 1, max_inflight=2)
     sa = srv.register(a.B.ops, LAM)
-    try:
+    with pytest.raises(hevi.HeviError) as e:
         srv.register(b.B.ops, LAM)
-        admitted_both = True
-    except hevi.HeviError as err:
-        assert err.code == 3
-        admitted_both = False
-    assert sz_a["factors"] > 0
+    assert e.value.code == 3
     # backpressure: a burst beyond max_inflight sees HEVI_E_BUSY
     outs = [a.out() for _ in range(40)]
     tickets, busy = [], 0
@@ -210,14 +215,25 @@ def test_serve_admission_busy_closed(ctx):
     with pytest.raises(hevi.HeviError) as e:
         srv.submit(12345, a.E, a.e, a.Qp, a.c, outs[0])
     assert e.value.code == 8
+    # a request still queued when its simulation is released completes first and
+    # its ticket can be waited for afterwards
+    t_last = srv.submit(sa, a.E, a.e, a.Qp, a.c, outs[0])
     srv.release(sa)
+    inf, _ = srv.wait(t_last)
+    assert inf["status"] == "HEVI_OK"
     with pytest.raises(hevi.HeviError) as e:
         srv.submit(sa, a.E, a.e, a.Qp, a.c, outs[0])
     assert e.value.code == 8
-    if not admitted_both:
-        sb = srv.register(b.B.ops, LAM)  # fits after the release
-        srv.release(sb)
+    sb = srv.register(b.B.ops, LAM)  # fits after the release
+    srv.release(sb)
     srv.close()
+    # exactly both fit
+    srv = hevi.Server(ctx, ra + rb, max_inflight=2)
+    ids = [srv.register(a.B.ops, LAM), srv.register(b.B.ops, LAM)]
+    for sid in ids:
+        srv.release(sid)
+    srv.close()
+
 
 
 def test_serve_threads(ctx):
