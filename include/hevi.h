@@ -12,7 +12,7 @@
  * hydrostatic reference state at rest and discretised on the Gauss-Lobatto-
  * Legendre points of each column (Sec. 3; Appendix A.3), with a rigid lid at
  * the bottom and top nodes.  The matrix is factored once and the factors are
- * reused by every implicit stage (Sec. 4.4: the forward reduction is paid when
+ * reused by every implicit stage (Sec. 5.3: the forward reduction is paid when
  * the operator is rebuilt, the back-substitution once per stage).
  *
  * Conventions shared by every entry point
@@ -160,7 +160,7 @@ hevi_status hevi_apply_op(hevi_ctx *ctx, const hevi_ops *ops, const double *d_x,
  * that system is row-equilibrated by powers of two (each row scaled by the
  * binary exponent of its largest entry, exactly) and LU-factored with partial
  * pivoting (largest magnitude in the pivot column, lowest row on ties): the
- * band LU the paper uses through LAPACK (Sec. 4.2.2), applied to the reduced
+ * band LU the paper uses through LAPACK (Sec. 4.2.3), applied to the reduced
  * matrix with LAPACK-style row equilibration.  Factors are FP64, or FP32 for
  * HEVI_FP32_REFINE (elimination in FP64, then rounded).  lambda >= 0.
  * hevi_factor allocates; hevi_refactor reuses the storage of `f` for a new
@@ -229,11 +229,11 @@ hevi_status hevi_combine(hevi_ctx *ctx, const hevi_ops *ops, int32_t n_v,
                          hipStream_t stream);
 
 /* ---- tableaux ---------------------------------------------------------------
- * IMEX ARK tableaux of the paper's integrators (Sec. 5): "ARK2" / "ARK2b" =
+ * IMEX ARK tableaux of the paper's integrators (Sec. 6): "ARK2" / "ARK2b" =
  * ARK(2,3,2) with a_32 = 1/2, "ARK2a" with a_32 = (3 + 2 sqrt 2)/6 (Sec. 4.1),
  * "ARK3" = ARK3(2)4L[2]SA and "ARK4" = ARK4(3)6L[2]SA of Kennedy and Carpenter,
  * "ARS343" = ARS(3,4,3) of Ascher, Ruuth and Spiteri (further integrators of
- * Sec. 5).  Writes s and the
+ * Sec. 6).  Writes s and the
  * row-major s x s explicit / implicit matrices and weights (capacity 8 stages).
  * Returns HEVI_E_INVALID for an unknown name. */
 hevi_status hevi_tableau(const char *name, int32_t *s, double *a_exp, double *a_imp,
@@ -243,7 +243,7 @@ hevi_status hevi_tableau(const char *name, int32_t *s, double *a_exp, double *a_
 /* Bytes per column of: the compact operator; the factors (FP64 or FP32 U and L
  * entries plus three byte planes: pivot offsets, U row extents, row-scale
  * exponents); the paper's LAPACK band layout (ldab = 3 * 5 (N+1) - 2 rows of
- * 8-byte entries per unknown plus a 4-byte pivot, Sec. 4.2.2); and everything a
+ * 8-byte entries per unknown plus a 4-byte pivot, Sec. 4.2.3); and everything a
  * factor object holds resident (factors, the stage solve's FP64 scratch and, for
  * FP32 factors of order N > 6, an FP64 assembly buffer): the figure the server
  * charges against its HBM budget, per column of the 64-column tiles it

@@ -15,7 +15,7 @@
  *     (Appendix A.2) linearised about a reference state at rest, discretised with
  *     the strong/weak differentiation matrices of Appendix A.3, multiplied by the
  *     quadrature weight w_i J_i, direct-stiffness-summed along the column and
- *     divided by the lumped mass (Sec. 3 eq. mass matrix, Sec. 4.2.2 global
+ *     divided by the lumped mass (Sec. 3 eq. mass matrix, Sec. 4.2.3 global
  *     assembly), with rigid-lid rows at the bottom and top nodes;
  *   - x = (I - Lambda L_z)^{-1} b by dense Gaussian elimination with partial
  *     pivoting (Sec. 4.3 eq. lhevi-ark-final-2), optionally followed by
@@ -130,7 +130,7 @@ void ho_reference(int nz, const double *rho0, const double *Theta0, double R,
  * rows, with Phi = g z (Sec. 2.1).
  *
  * Per element e (nodes k = eN+i), multiplied by the quadrature weight w_i J_i
- * (Sec. 4.2.2, "applying numerical integration ... and DSS"):
+ * (Sec. 4.2.3, "applying numerical integration ... and DSS"):
  *   strong form (Appendix A.3 eq. differentiation_matrix/strong):
  *     B[(k_i,a),(k_j,b)] += w_i D_ij J_{k_j} K_{k_j}[a][b]
  *   weak form (eq. differentiation_matrix/weak):
@@ -138,7 +138,7 @@ void ho_reference(int nz, const double *rho0, const double *Theta0, double R,
  *   gravity: B[(k_i,U_m),(k_i,rho)] += w_i J_{k_i} (dPhi/dzeta)_i gz_m(k_i),
  *     (dPhi/dzeta)_i = g sum_j D_ij z_{k_j} within the element;
  *   mass M_k += w_i J_k (Sec. 3, lumped mass and DSS).
- * L_z = -M^{-1} B.  rho row weak (the continuity choice of Sec. 4.2.2) unless
+ * L_z = -M^{-1} B.  rho row weak (the continuity choice of Sec. 4.2.3) unless
  * rho_weak == 0; Theta row strong unless theta_weak != 0; momentum rows strong.
  * Rigid lid: momentum rows of the bottom (k=0) and top (k=nz-1) nodes are zero.
  * Parity pinned: closed-form isothermal acoustic-gravity eigenvalues, mass and
@@ -219,7 +219,7 @@ void ho_form_A(int n, double lambda, const double *L, double *A) {
  * pivot is the row i >= k of largest |a_ik|, the lowest such row on ties; the
  * multipliers overwrite the strictly lower part.  Returns 0, or 1 + k for an
  * exactly zero pivot at step k.  Plain Gaussian elimination as used by the
- * LU-based HEVI solvers (Sec. 4.2.2; LHEVI reuses it, Sec. 4.3).
+ * LU-based HEVI solvers (Sec. 4.2.3; LHEVI reuses it, Sec. 4.3).
  * Parity pinned: exact rational brute force, scipy LAPACK band solve, mpmath. */
 int ho_lu_factor(int n, double *A, int *piv) {
   for (int k = 0; k < n; ++k) {

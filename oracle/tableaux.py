@@ -4,17 +4,17 @@ All methods are ESDIRK/ERK pairs with b = b~ and c = c~ (Sec. 4.1: explicit
 first stage, constant diagonal a~_ii, b = b~ to conserve linear invariants).
 
 * ARK2 = ARK(2,3,2) of Giraldo, Kelly & Constantinescu (2013), the method the
-  paper calls ARK2 (Sec. 5).  gamma = 1 - 1/sqrt(2), delta = 1/(2 sqrt(2)),
+  paper calls ARK2 (Sec. 6).  gamma = 1 - 1/sqrt(2), delta = 1/(2 sqrt(2)),
   and the free explicit coefficient a_32 = 1/2 for variant "b" (the de facto
   NUMA choice) or (3 + 2 sqrt(2))/6 for variant "a" (Sec. 4.1 text).
 * ARK3 = ARK3(2)4L[2]SA of Kennedy & Carpenter (2003), the paper's ARK3
-  (Sec. 5).  The paper does not print these coefficients; they are transcribed
+  (Sec. 6).  The paper does not print these coefficients; they are transcribed
   from the cited publication and pinned only by their order conditions and by
   the observed third-order convergence on a linear column (tests).  Parity of
   the coefficient values themselves is unpinned by the paper.
 
 * ARS343 = ARS(3,4,3) of Ascher, Ruuth & Spiteri (1997), one of the further
-  integrators the paper lists (Sec. 5; coefficients not printed there).  The
+  integrators the paper lists (Sec. 6; coefficients not printed there).  The
   implicit part is the L-stable three-stage DIRK with gamma the root in (1/3, 1/2)
   of 6 g^3 - 18 g^2 + 9 g - 1 = 0; the explicit coefficients are the published
   10-digit values, with a_31 and a_41 taken from the row sums so that c = c~
@@ -22,7 +22,7 @@ first stage, constant diagonal a~_ii, b = b~ to conserve linear invariants).
   (about 1e-10); pinned by those and by observed third-order convergence.
 
 * ARK4 = ARK4(3)6L[2]SA of Kennedy & Carpenter (2003), the paper's ARK4, the
-  six-stage ARK(5,6,4) (Sec. 5; coefficients not printed there).  gamma = 1/4 and
+  six-stage ARK(5,6,4) (Sec. 6; coefficients not printed there).  gamma = 1/4 and
   c = (0, 1/2, 83/250, 31/50, 17/20, 1); the implicit coefficients are exact
   rationals, the explicit ones the published rational approximations.  Pinned by
   the fourth-order conditions (exact row sums for the implicit part, about 1e-12

@@ -393,7 +393,7 @@ hevi_status hevi_combine(hevi_ctx* ctx, const hevi_ops* ops, int32_t n_v,
   return HEVI_OK;
 }
 
-// ---- ARK tableaux (Sec. 5) ---------------------------------------------------
+// ---- ARK tableaux (Sec. 6) ---------------------------------------------------
 hevi_status hevi_tableau(const char* name, int32_t* s, double* a_exp, double* a_imp, double* b) {
   if (!name || !s || !a_exp || !a_imp || !b) return HEVI_E_INVALID;
   if (!std::strcmp(name, "ARK2") || !std::strcmp(name, "ARK2b") || !std::strcmp(name, "ARK2a")) {

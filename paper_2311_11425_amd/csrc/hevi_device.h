@@ -25,14 +25,14 @@
 //                 - Phi'_k grad(zeta)_k rho_k                 (interior nodes)
 // The rho-rho and Theta-Theta blocks of A = I - Lambda L_z are identities, so
 // eliminating rho, Theta and the tangential momentum exactly leaves
-//   S u = r,  S = I - Lambda^2 grad(zeta).(PG DTh + Phi' grad(zeta) Drho),
+//   S u = r,  S = I - Lambda^2 grad(zeta).(PG DTh - Phi' grad(zeta) Drho),
 //   r = grad(zeta).(b_U + Lambda (PG b_Theta - Phi' grad(zeta) b_rho)),
 // a band matrix of half-bandwidth 2N in u (identity rows at the rigid-lid
 // nodes, where u = 0).  Back-substitution recovers
 //   x_rho = b_rho + Lambda Drho u,  x_Theta = b_Theta + Lambda DTh u,
 //   x_U   = b_U + Lambda (PG x_Theta - Phi' grad(zeta) x_rho).
 // S is LU-factored with partial pivoting (band LU, the paper's LAPACK scheme
-// of Sec. 4.2.2 applied to the reduced matrix).
+// of Sec. 4.2.3 applied to the reduced matrix).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <math.h>

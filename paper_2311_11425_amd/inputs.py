@@ -4,7 +4,7 @@ This module holds no arithmetic of the method: it only builds grids, reference
 atmospheres and perturbations (the inputs of the column solve).  Neither the
 oracle nor the HIP library import it; both receive the arrays it produces.
 
-Recipes (the paper's baroclinic-instability and gravity-wave set-ups, Sec. 5,
+Recipes (the paper's baroclinic-instability and gravity-wave set-ups, Sec. 7,
 are stood in for by their vertical structure: 30 km model top, order-4 GLL
 elements, hydrostatic stratified reference):
 

@@ -503,7 +503,7 @@ def test_p12_ark_order(tabname, order):
         C[5 * k + 1:5 * k + 4, 5 * k + 1:5 * k + 4] = -2 * omega * X
     T = 600.0
     # keep the slow modes only (|lambda| < 0.06 s^-1): the fast acoustic modes are damped
-    # by the implicit part at these step sizes and hide the asymptotic order (Sec. 5.2)
+    # by the implicit part at these step sizes and hide the asymptotic order (stability regions, Sec. 6)
     lam_, V = np.linalg.eig(L + C)
     a = np.linalg.solve(V, oracle.vec_of(qn - qref, 0).astype(complex))
     slow = np.abs(lam_) < 0.06
