@@ -167,15 +167,18 @@ __device__ void pg_pass(Gll<N> tab, const OpsView& op, int Ne, double* ws, int64
 }
 
 // ---------------------------------------------------------------------------
-// Element-chunked kernels: a block of CW wavefronts owns one 64-column tile;
+// Element-chunked kernels: a block of cw wavefronts owns one 64-column tile;
 // wavefront w owns a contiguous chunk of elements [e0, e1) and the nodes
 // e0*N .. e1*N - 1 (plus the top node for the last chunk).  A node on a chunk
 // boundary also receives a contribution from the last element of the previous
 // chunk; the wavefront recomputes that element's contribution itself instead of
-// exchanging partial sums, so the wavefronts run independently.  One wavefront
-// per tile (CW = 1) measured fastest: the chunk recomputation costs more than
-// the extra wavefronts gain.
-constexpr int CW = 1;  // chunk wavefronts per tile
+// exchanging partial sums, so the wavefronts run independently.  With enough
+// tiles to fill the chip one wavefront per tile measured fastest (the chunk
+// recomputation costs more than the extra wavefronts gain); a launch of few
+// tiles is bound by one tile's latency along its elements instead, and the
+// single-problem launchers then split tiles into up to kMaxChunks chunks
+// (chunks_for).
+constexpr int kMaxChunks = 4;
 
 // Waves per SIMD the streaming kernels (apply, stage passes) are compiled for: two
 // up to N = 4, whose element working set fits in 256 VGPRs; one above, where a
@@ -188,13 +191,15 @@ struct Chunk {
   int64_t tile;
 };
 
-__device__ __forceinline__ Chunk chunk_of(int Ne, int64_t tile) {
+// chunk of wavefront threadIdx.x / 64 among cw wavefronts: elements split as evenly
+// as integers allow (the first Ne % cw chunks take one more)
+__device__ __forceinline__ Chunk chunk_of(int Ne, int64_t tile, int cw = 1) {
   Chunk ch;
   ch.lane = threadIdx.x & (T - 1);
   const int wv = threadIdx.x / T;
-  const int ce = (Ne + CW - 1) / CW;
-  ch.e0 = wv * ce;
-  ch.e1 = min(Ne, ch.e0 + ce);
+  const int q = Ne / cw, r = Ne % cw;
+  ch.e0 = wv * q + min(wv, r);
+  ch.e1 = ch.e0 + q + (wv < r ? 1 : 0);
   ch.tile = tile;
   return ch;
 }
@@ -206,9 +211,10 @@ template <int N, bool HAS_REF>
 __device__ __forceinline__ void b_apply(int64_t tile_, HeviShapeDev sh, Gll<N> tab,
                                         const double* __restrict__ ops,
                                         const double* __restrict__ x,
-                                        const double* __restrict__ xref, double* __restrict__ y) {
+                                        const double* __restrict__ xref, double* __restrict__ y,
+                                        int cw = 1) {
   const int Ne = sh.Ne, nz = sh.nz;
-  const Chunk ch = chunk_of(Ne, tile_);
+  const Chunk ch = chunk_of(Ne, tile_, cw);
   if (ch.e0 >= ch.e1) return;
   const int lane = ch.lane;
   const int64_t tile = ch.tile;
@@ -1323,9 +1329,9 @@ __device__ __forceinline__ void b_stage_rhs(int64_t tile_, HeviShapeDev sh, Gll<
                                             double lambda, const double* __restrict__ ops,
                                             double* __restrict__ ws, const HeviTerms& E,
                                             const HeviTerms& Q, double* __restrict__ Qi,
-                                            double* ru = nullptr) {
+                                            double* ru = nullptr, int cw = 1) {
   const int Ne = sh.Ne, nz = sh.nz;
-  const Chunk ch = chunk_of(Ne, tile_);
+  const Chunk ch = chunk_of(Ne, tile_, cw);
   if (ch.e0 >= ch.e1) return;
   const int lane = ch.lane;
   const int64_t tile = ch.tile;
@@ -1499,10 +1505,11 @@ template <int N, bool LDSRU, bool TILT>
 __device__ __forceinline__ void b_stage_update(int64_t tile_, HeviShapeDev sh, Gll<N> tab,
                                                double lambda, const double* __restrict__ ops,
                                                double* __restrict__ ws, double* __restrict__ Qi,
-                                               HeviDevInfo* info, double* ru = nullptr) {
+                                               HeviDevInfo* info, double* ru = nullptr,
+                                               int cw = 1) {
   constexpr int NC = 3 * N + 1;
   const int Ne = sh.Ne, nz = sh.nz;
-  const Chunk ch = chunk_of(Ne, tile_);
+  const Chunk ch = chunk_of(Ne, tile_, cw);
   if (ch.e0 >= ch.e1) return;
   const int lane = ch.lane;
   const int64_t tile = ch.tile;

@@ -83,12 +83,15 @@ __global__ __launch_bounds__(64) void k_build_ops(HeviShapeDev sh, double R, dou
 // ---------------------------------------------------------------------------
 // Single-problem kernels: tile = blockIdx.x
 
-template <int N, bool HAS_REF>
-__global__ __launch_bounds__(64, kStreamWaves<N>) void k_apply(HeviShapeDev sh, const double* __restrict__ ops,
-                                              const double* __restrict__ x,
-                                              const double* __restrict__ xref,
-                                              double* __restrict__ y) {
-  b_apply<N, HAS_REF>((int64_t)blockIdx.x, sh, Gll<N>{}, ops, x, xref, y);
+// Streaming kernels take blocks of cw wavefronts (element chunks of one tile,
+// cw <= kMaxChunks; see chunks_for).
+// CHUNKED instances take the chunk count at run time (a kernel with cw fixed at 1
+// keeps the element bounds as constants and needs fewer registers).
+template <int N, bool HAS_REF, bool CHUNKED>
+__global__ __launch_bounds__(CHUNKED ? 64 * kMaxChunks : 64, kStreamWaves<N>) void k_apply(
+    HeviShapeDev sh, const double* __restrict__ ops, const double* __restrict__ x,
+    const double* __restrict__ xref, double* __restrict__ y, int cw) {
+  b_apply<N, HAS_REF>((int64_t)blockIdx.x, sh, Gll<N>{}, ops, x, xref, y, CHUNKED ? cw : 1);
 }
 
 template <int N>
@@ -138,31 +141,32 @@ __global__ __launch_bounds__(64) void k_stage_solve(HeviShapeDev sh, double lamb
 // The FP64 stage solve in one kernel: the three passes run back to back in the
 // wavefront that owns the tile, with the reduced right-hand side r and the
 // solution u (one array, used in place) in LDS instead of the global scratch.
-template <int N, bool TILT>
-__global__ __launch_bounds__(64, kStreamWaves<N>) void k_stage_fused(HeviShapeDev sh, double lambda,
-                                                     const double* __restrict__ ops,
-                                                     const double* __restrict__ Ub,
-                                                     const double* __restrict__ Lb,
-                                                     const uint8_t* __restrict__ piv,
-                                                     double* __restrict__ ws, HeviTerms E,
-                                                     HeviTerms Q, double* __restrict__ Qi,
-                                                     HeviDevInfo* info) {
+// The element chunks of the tile's cw wavefronts write and read the one r/u array;
+// the band solve runs in the first wavefront between the two barriers.
+template <int N, bool TILT, bool CHUNKED>
+__global__ __launch_bounds__(CHUNKED ? 64 * kMaxChunks : 64, kStreamWaves<N>) void k_stage_fused(
+    HeviShapeDev sh, double lambda, const double* __restrict__ ops,
+    const double* __restrict__ Ub, const double* __restrict__ Lb,
+    const uint8_t* __restrict__ piv, double* __restrict__ ws, HeviTerms E, HeviTerms Q,
+    double* __restrict__ Qi, HeviDevInfo* info, int cw_) {
   extern __shared__ double ru[];  // [n_z][64]
   const int64_t tile = blockIdx.x;
-  b_stage_rhs<N, true, TILT>(tile, sh, Gll<N>{}, lambda, ops, ws, E, Q, Qi, ru);
+  const int cw = CHUNKED ? cw_ : 1;
+  b_stage_rhs<N, true, TILT>(tile, sh, Gll<N>{}, lambda, ops, ws, E, Q, Qi, ru, cw);
   __syncthreads();
-  band_solve<N, double, true>(Ub, Lb, piv, plane_size(sh), ws, tile, sh.nz, (int)threadIdx.x, WS_R,
-                              WS_U, ru);
+  if (threadIdx.x < T)
+    band_solve<N, double, true>(Ub, Lb, piv, plane_size(sh), ws, tile, sh.nz, (int)threadIdx.x,
+                                WS_R, WS_U, ru);
   __syncthreads();
-  b_stage_update<N, true, TILT>(tile, sh, Gll<N>{}, lambda, ops, ws, Qi, info, ru);
+  b_stage_update<N, true, TILT>(tile, sh, Gll<N>{}, lambda, ops, ws, Qi, info, ru, cw);
 }
 
-template <int N, bool TILT>
-__global__ __launch_bounds__(64, kStreamWaves<N>) void k_stage_rhs(HeviShapeDev sh, double lambda,
-                                                     const double* __restrict__ ops,
-                                                     double* __restrict__ ws, HeviTerms E,
-                                                     HeviTerms Q, double* __restrict__ Qi) {
-  b_stage_rhs<N, false, TILT>((int64_t)blockIdx.x, sh, Gll<N>{}, lambda, ops, ws, E, Q, Qi);
+template <int N, bool TILT, bool CHUNKED>
+__global__ __launch_bounds__(CHUNKED ? 64 * kMaxChunks : 64, kStreamWaves<N>) void k_stage_rhs(
+    HeviShapeDev sh, double lambda, const double* __restrict__ ops, double* __restrict__ ws,
+    HeviTerms E, HeviTerms Q, double* __restrict__ Qi, int cw) {
+  b_stage_rhs<N, false, TILT>((int64_t)blockIdx.x, sh, Gll<N>{}, lambda, ops, ws, E, Q, Qi,
+                              nullptr, CHUNKED ? cw : 1);
 }
 
 template <int N, typename FT, bool REFINE>
@@ -177,12 +181,12 @@ __global__ __launch_bounds__(64, kStreamWaves<N>) void k_stage_bsolve(HeviShapeD
       sh, Gll<N>{}, lambda, ops, Ub, Lb, piv, ws, max_sweeps, rel_target, info);
 }
 
-template <int N, bool TILT>
-__global__ __launch_bounds__(64, kStreamWaves<N>) void k_stage_update(HeviShapeDev sh, double lambda,
-                                                     const double* __restrict__ ops,
-                                                     double* __restrict__ ws,
-                                                     double* __restrict__ Qi, HeviDevInfo* info) {
-  b_stage_update<N, false, TILT>((int64_t)blockIdx.x, sh, Gll<N>{}, lambda, ops, ws, Qi, info);
+template <int N, bool TILT, bool CHUNKED>
+__global__ __launch_bounds__(CHUNKED ? 64 * kMaxChunks : 64, kStreamWaves<N>) void k_stage_update(
+    HeviShapeDev sh, double lambda, const double* __restrict__ ops, double* __restrict__ ws,
+    double* __restrict__ Qi, HeviDevInfo* info, int cw) {
+  b_stage_update<N, false, TILT>((int64_t)blockIdx.x, sh, Gll<N>{}, lambda, ops, ws, Qi, info,
+                                 nullptr, CHUNKED ? cw : 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -232,16 +236,28 @@ struct BuildOps {
   }
 };
 
+// Element chunks per tile of the streaming kernels.  A launch of few tiles is bound
+// by each tile's latency along its elements: below 512 tiles (two per CU) each
+// tile is split into up to kMaxChunks wavefronts, never more than it has elements.
+// (10,800 columns, 169 tiles: see the design notes for the measured effect.)
+int chunks_for(const HeviShapeDev& sh) {
+  if (sh.ntiles >= 512) return 1;
+  return sh.Ne < kMaxChunks ? sh.Ne : kMaxChunks;
+}
+
 template <int N>
 struct Apply {
   static hipError_t run(const HeviShapeDev& sh, const double* ops,
                         const double* x, const double* xref, double* y, hipStream_t st) {
-    if (xref)
-      hipLaunchKernelGGL((k_apply<N, true>), dim3((unsigned)sh.ntiles), dim3(T * CW), 0, st, sh,
-                         ops, x, xref, y);
+    const int cw = chunks_for(sh);
+    const dim3 g((unsigned)sh.ntiles), b(T * cw);
+    if (xref && cw > 1)
+      hipLaunchKernelGGL((k_apply<N, true, true>), g, b, 0, st, sh, ops, x, xref, y, cw);
+    else if (xref)
+      hipLaunchKernelGGL((k_apply<N, true, false>), g, b, 0, st, sh, ops, x, xref, y, 1);
     else
-      hipLaunchKernelGGL((k_apply<N, false>), dim3((unsigned)sh.ntiles), dim3(T * CW), 0, st, sh,
-                         ops, x, xref, y);
+      hipLaunchKernelGGL((k_apply<N, false, false>), dim3((unsigned)sh.ntiles), dim3(T), 0, st,
+                         sh, ops, x, xref, y, 1);
     return hipGetLastError();
   }
 };
@@ -286,7 +302,10 @@ struct StageSolve {
                         double* ws, const HeviTerms& E, const HeviTerms& Q, double* Qi,
                         int max_sweeps, double rel_target, int full_sweeps, HeviDevInfo* info,
                         hipStream_t st) {
-    const dim3 g((unsigned)sh.ntiles), b(T), b4(T * CW);
+    // element chunks for launches of few tiles (straight columns; the TILT kernels run
+    // one wavefront per tile)
+    const int cw = tilt ? 1 : chunks_for(sh);
+    const dim3 g((unsigned)sh.ntiles), b(T), b4(T * cw);
     if (full_sweeps > 0) {
       // accuracy mode: one kernel with the full-system refinement sweeps
       if (fp32)
@@ -299,22 +318,26 @@ struct StageSolve {
                            full_sweeps, info);
       return hipGetLastError();
     }
-    if (!fp32 && CW == 1 && sh.nz <= HEVI_FUSED_MAX_NZ) {
-      hipLaunchKernelGGL((tilt ? k_stage_fused<N, true> : k_stage_fused<N, false>), g, b,
-                         (size_t)sh.nz * T * sizeof(double), st, sh, lambda, ops,
-                         (const double*)Ub, (const double*)Lb, piv, ws, E, Q, Qi, info);
+    if (!fp32 && sh.nz <= HEVI_FUSED_MAX_NZ) {
+      hipLaunchKernelGGL((tilt ? k_stage_fused<N, true, false>
+                               : cw > 1 ? k_stage_fused<N, false, true> : k_stage_fused<N, false, false>),
+                         g, b4, (size_t)sh.nz * T * sizeof(double), st, sh, lambda, ops,
+                         (const double*)Ub, (const double*)Lb, piv, ws, E, Q, Qi, info, cw);
       return hipGetLastError();
     }
-    hipLaunchKernelGGL((tilt ? k_stage_rhs<N, true> : k_stage_rhs<N, false>), g, b4, 0, st, sh,
-                       lambda, ops, ws, E, Q, Qi);
+    hipLaunchKernelGGL((tilt ? k_stage_rhs<N, true, false>
+                             : cw > 1 ? k_stage_rhs<N, false, true> : k_stage_rhs<N, false, false>),
+                       g, b4, 0, st, sh, lambda, ops, ws, E, Q, Qi, cw);
     if (fp32)
       hipLaunchKernelGGL((k_stage_bsolve<N, float, true>), g, b, 0, st, sh, lambda, ops,
                          (const float*)Ub, (const float*)Lb, piv, ws, max_sweeps, rel_target, info);
     else
       hipLaunchKernelGGL((k_stage_bsolve<N, double, false>), g, b, 0, st, sh, lambda, ops,
                          (const double*)Ub, (const double*)Lb, piv, ws, 0, rel_target, info);
-    hipLaunchKernelGGL((tilt ? k_stage_update<N, true> : k_stage_update<N, false>), g, b4, 0, st,
-                       sh, lambda, ops, ws, Qi, info);
+    hipLaunchKernelGGL((tilt ? k_stage_update<N, true, false>
+                             : cw > 1 ? k_stage_update<N, false, true>
+                                      : k_stage_update<N, false, false>),
+                       g, b4, 0, st, sh, lambda, ops, ws, Qi, info, cw);
     return hipGetLastError();
   }
 };
