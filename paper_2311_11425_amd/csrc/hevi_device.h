@@ -178,7 +178,7 @@ __device__ void pg_pass(Gll<N> tab, const OpsView& op, int Ne, double* ws, int64
 // tiles is bound by one tile's latency along its elements instead, and the
 // single-problem launchers then split tiles into up to kMaxChunks chunks
 // (chunks_for).
-constexpr int kMaxChunks = 4;
+constexpr int kMaxChunks = 8;
 
 // Waves per SIMD the streaming kernels (apply, stage passes) are compiled for: two
 // up to N = 4, whose element working set fits in 256 VGPRs; one above, where a

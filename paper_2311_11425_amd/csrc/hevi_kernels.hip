@@ -239,7 +239,8 @@ struct BuildOps {
 // Element chunks per tile of the streaming kernels.  A launch of few tiles is bound
 // by each tile's latency along its elements: below 512 tiles (two per CU) each
 // tile is split into up to kMaxChunks wavefronts, never more than it has elements.
-// (10,800 columns, 169 tiles: see the design notes for the measured effect.)
+// At 10,800 columns (169 tiles of 10 elements) one step took 0.957 ms with one
+// wavefront per tile, 0.726 ms with 4 and 0.675 ms with 8.
 int chunks_for(const HeviShapeDev& sh) {
   if (sh.ntiles >= 512) return 1;
   return sh.Ne < kMaxChunks ? sh.Ne : kMaxChunks;
