@@ -9,7 +9,10 @@ The arithmetic lives in ``hevi_oracle.c`` (plain C, built with gcc into
 ``libhevi_oracle.so`` next to this file); this module only marshals numpy
 arrays.  Array layout matches the batched convention used throughout: a per-node
 field is ``[k][c]`` (column index fastest), a state vector ``[v][k][c]`` with
-``v = (rho, rho u, rho v, rho w, rho theta)``, ``grad(zeta)`` is ``[m][k][c]``.
+``v = (rho, rho u, rho v, rho w, q_T)`` with ``q_T`` the thermodynamic variable of
+the equation set (``Theta = rho theta`` for set 2C, the total energy ``E`` for
+set 3C), ``grad(zeta)`` is ``[m][k][c]``.  A column batch names its set in
+``col["eqset"]`` ("2C" when absent); a set-3C batch carries ``E0``.
 
 Parity status per function is documented in ``hevi_oracle.c``; every function
 has at least one pin in ``tests/test_oracle_pins.py``.  The ARK tableaux in
@@ -55,8 +58,11 @@ def _load():
         lib.ho_reference.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double, ctypes.c_double,
                                      ctypes.c_double, _dp, _dp]
         lib.ho_reference.restype = None
+        lib.ho_reference_3c.argtypes = [ctypes.c_int, _dp, _dp, _dp, ctypes.c_double,
+                                        ctypes.c_double, ctypes.c_double, _dp, _dp, _dp]
+        lib.ho_reference_3c.restype = None
         lib.ho_assemble_L.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp, _dp,
-                                      _dp, _dp, ctypes.c_int, ctypes.c_int, _dp]
+                                      _dp, _dp, _dp, ctypes.c_int, ctypes.c_int, _dp]
         lib.ho_assemble_L.restype = ctypes.c_int
         lib.ho_bc_project.argtypes = [ctypes.c_int, _dp, _dp]
         lib.ho_bc_project.restype = None
@@ -72,14 +78,15 @@ def _load():
         common = [ctypes.c_int, ctypes.c_int, ctypes.c_long, ctypes.c_int, _dp, _dp, _dp, _dp, _dp,
                   _dp]
         lib.ho_solve_batch.argtypes = common + [ctypes.c_double, _dp, _dp, ctypes.c_int,
-                                                ctypes.c_int, ctypes.POINTER(ctypes.c_long)]
+                                                ctypes.c_int, ctypes.c_int,
+                                                ctypes.POINTER(ctypes.c_long)]
         lib.ho_solve_batch.restype = ctypes.c_int
-        lib.ho_apply_batch.argtypes = common + [_dp, _dp, _dp, ctypes.c_int,
+        lib.ho_apply_batch.argtypes = common + [_dp, _dp, _dp, ctypes.c_int, ctypes.c_int,
                                                 ctypes.POINTER(ctypes.c_long)]
         lib.ho_apply_batch.restype = ctypes.c_int
         lib.ho_ark_step_batch.argtypes = common + [ctypes.c_int, _dp, _dp, _dp, ctypes.c_double,
                                                    ctypes.c_double, _dp, _dp, _dp, _dp, _dp,
-                                                   ctypes.c_int,
+                                                   ctypes.c_int, ctypes.c_int,
                                                    ctypes.c_int, ctypes.POINTER(ctypes.c_long)]
         lib.ho_ark_step_batch.restype = ctypes.c_int
         _lib = lib
@@ -120,22 +127,42 @@ def reference(rho0, Theta0, consts):
     return th, cT
 
 
-def assemble_L(N, Ne, g, z, J, gz_k3, theta0, cTheta, rho_weak=True, theta_weak=False):
-    """Dense L_z of ONE column.  gz_k3 is [k][3]; returns (5nz x 5nz)."""
+def reference_3c(rho0, E0, z, consts):
+    """Set-3C coefficients at rest: h = (E0 + P0)/rho0, dP/dE, dP/drho."""
+    lib = _load()
+    rho0, E0, z = _f64(rho0), _f64(E0), _f64(z)
+    hE, dPdE, dPdr = (np.zeros_like(rho0) for _ in range(3))
+    R, cp, g, pA = consts
+    lib.ho_reference_3c(rho0.size, _p(rho0), _p(E0), _p(z), R, cp, g, _p(hE), _p(dPdE),
+                        _p(dPdr))
+    return hE, dPdE, dPdr
+
+
+def assemble_L(N, Ne, g, z, J, gz_k3, hq, cq, pr=None, rho_weak=True, theta_weak=False):
+    """Dense L_z of ONE column.  gz_k3 is [k][3]; hq, cq, pr are the flux
+    coefficient, dP/dq_T and dP/drho per node (pr None: zero, set 2C).
+    Returns (5nz x 5nz)."""
     lib = _load()
     nz = Ne * N + 1
     L = np.zeros((5 * nz, 5 * nz))
-    args = [_f64(a) for a in (z, J, gz_k3, theta0, cTheta)]
-    rc = lib.ho_assemble_L(N, Ne, g, *[_p(a) for a in args], int(rho_weak), int(theta_weak),
-                           _p(L))
+    args = [_f64(a) for a in (z, J, gz_k3, hq, cq)]
+    prp = _f64(pr) if pr is not None else None
+    rc = lib.ho_assemble_L(N, Ne, g, *[_p(a) for a in args], _p(prp), int(rho_weak),
+                           int(theta_weak), _p(L))
     if rc:
         raise ValueError("assemble failed")
     return L
 
 
-def column_L(N, Ne, consts, z, J, gz_k3, rho0, Theta0, rho_weak=True, theta_weak=False):
-    th, cT = reference(rho0, Theta0, consts)
-    return assemble_L(N, Ne, consts[2], z, J, gz_k3, th, cT, rho_weak, theta_weak)
+def column_L(N, Ne, consts, z, J, gz_k3, rho0, thermo0, rho_weak=True, theta_weak=False,
+             eqset="2C"):
+    """Dense L_z of one column of set ``eqset``; thermo0 is Theta0 (2C) or E0 (3C)."""
+    if eqset == "3C":
+        hq, cq, pr = reference_3c(rho0, thermo0, z, consts)
+    else:
+        hq, cq = reference(rho0, thermo0, consts)
+        pr = None
+    return assemble_L(N, Ne, consts[2], z, J, gz_k3, hq, cq, pr, rho_weak, theta_weak)
 
 
 def bc_project(nz, gz_k3, b):
@@ -173,8 +200,17 @@ def lu_solve_dense(A, b, refine=0):
 # --------------------------------------------------------------------------
 # batched drivers (columns stored column-fastest)
 
+def _eqset(col):
+    """0 for set 2C, 1 for set 3C."""
+    return 1 if col.get("eqset", "2C") == "3C" else 0
+
+
+def _thermo_key(col):
+    return "E0" if _eqset(col) else "Theta0"
+
+
 def _geom_args(col):
-    return [_f64(col[k]) for k in ("z", "J", "gz", "rho0", "Theta0")]
+    return [_f64(col[k]) for k in ("z", "J", "gz", "rho0", _thermo_key(col))]
 
 
 def solve_batch(col, lam, b, refine=1, rho_weak=True, nthreads=None):
@@ -189,7 +225,7 @@ def solve_batch(col, lam, b, refine=1, rho_weak=True, nthreads=None):
     consts = _f64(col["consts"])
     rc = lib.ho_solve_batch(N, Ne, ncols, nthreads or os.cpu_count() or 1, _p(consts),
                             *[_p(a) for a in g], lam, _p(b), _p(x), refine, int(rho_weak),
-                            ctypes.byref(bad))
+                            _eqset(col), ctypes.byref(bad))
     if rc:
         raise RuntimeError(f"oracle solve failed ({rc}) at column {bad.value}")
     return x
@@ -208,7 +244,7 @@ def apply_batch(col, x, xref=None, rho_weak=True, nthreads=None):
     consts = _f64(col["consts"])
     rc = lib.ho_apply_batch(N, Ne, ncols, nthreads or os.cpu_count() or 1, _p(consts),
                             *[_p(a) for a in g], _p(x), _p(xr), _p(y), int(rho_weak),
-                            ctypes.byref(bad))
+                            _eqset(col), ctypes.byref(bad))
     if rc:
         raise RuntimeError(f"oracle apply failed ({rc}) at column {bad.value}")
     return y
@@ -240,7 +276,7 @@ def ark_step_batch(col, tab, dt, qn, qref, refine=1, rho_weak=True, nthreads=Non
                                *[_p(a) for a in g], s, _p(Aexp), _p(Aimp), _p(bw), dt, omega,
                                _p(qn),
                                _p(qref), _p(qnp1), _p(Q), _p(S), refine, int(rho_weak),
-                               ctypes.byref(bad))
+                               _eqset(col), ctypes.byref(bad))
     if rc:
         raise RuntimeError(f"oracle ARK step failed ({rc}) at column {bad.value}")
     if want_stages:
@@ -249,10 +285,12 @@ def ark_step_batch(col, tab, dt, qn, qref, refine=1, rho_weak=True, nthreads=Non
 
 
 def column_of(col, c):
-    """Per-column arrays of column c: z, J, gz [k][3], rho0, Theta0."""
+    """Per-column arrays of column c: z, J, gz [k][3], rho0 and the set's
+    thermodynamic reference (Theta0 for 2C, E0 for 3C)."""
     gz = np.ascontiguousarray(col["gz"][:, :, c].T)
     return (np.ascontiguousarray(col["z"][:, c]), np.ascontiguousarray(col["J"][:, c]), gz,
-            np.ascontiguousarray(col["rho0"][:, c]), np.ascontiguousarray(col["Theta0"][:, c]))
+            np.ascontiguousarray(col["rho0"][:, c]),
+            np.ascontiguousarray(col[_thermo_key(col)][:, c]))
 
 
 def vec_of(v, c):

@@ -10,8 +10,10 @@
  *   - 1D Gauss-Lobatto-Legendre nodes, weights and differentiation matrix
  *     (Sec. 3, basis and collocated Lobatto quadrature);
  *   - the reference coefficients theta0 = Theta0/rho0 and c_Theta = dP/dTheta
- *     from the set-2C equation of state (Appendix A.1, eq. set2c_pressure);
- *   - the dense vertical operator L_z: the set-2C vertical operator V
+ *     from the set-2C equation of state (Appendix A.1, eq. set2c_pressure), or
+ *     for set 3C (total energy E, Appendix A.1 eq. set3c) h = (E0 + P0)/rho0,
+ *     dP/dE and dP/drho from eq. set3c_pressure;
+ *   - the dense vertical operator L_z: the set-2C or set-3C vertical operator V
  *     (Appendix A.2) linearised about a reference state at rest, discretised with
  *     the strong/weak differentiation matrices of Appendix A.3, multiplied by the
  *     quadrature weight w_i J_i, direct-stiffness-summed along the column and
@@ -114,20 +116,47 @@ void ho_reference(int nz, const double *rho0, const double *Theta0, double R,
   }
 }
 
+/* Reference coefficients of set 3C at rest (Appendix A.1, eq. set3c_pressure with
+ * U = 0): P0 = (gamma - 1)(E0 - rho0 Phi), Phi = g z (Sec. 2.1), and the entries of
+ * the flux Jacobian K_3C (Appendix A.3, eq. set3c_jacobian) that survive at U = 0:
+ *   hE    = (E0 + P0) / rho0          (E row, momentum columns, times grad zeta)
+ *   dPdE  = dP/dE   = gamma - 1       (momentum rows, E column)
+ *   dPdrho = dP/drho = -(gamma - 1) Phi (momentum rows, rho column; the kinetic
+ *                                        part U.U/(2 rho^2) vanishes at rest)
+ * Parity pinned: the momentum rows equal set 2C's under the linearised change of
+ * variables E' = c_Theta Theta'/(gamma-1) + Phi rho' (exact), the E row converges to
+ * it, total-energy conservation, isothermal acoustic-gravity eigenvalues (tests). */
+void ho_reference_3c(int nz, const double *rho0, const double *E0, const double *z, double R,
+                     double cp, double g, double *hE, double *dPdE, double *dPdrho) {
+  double gm1 = cp / (cp - R) - 1.0;
+  for (int k = 0; k < nz; ++k) {
+    double phi = g * z[k];
+    double P0 = gm1 * (E0[k] - rho0[k] * phi);
+    hE[k] = (E0[k] + P0) / rho0[k];
+    dPdE[k] = gm1;
+    dPdrho[k] = -gm1 * phi;
+  }
+}
+
 /* ------------------------------------------------------------------------- */
 /* Dense vertical operator L_z (n x n, row-major, n = 5 nz) of one column.
- * Unknown (node k, variable v) sits at 5k+v, v = (rho, rho u, rho v, rho w,
- * rho theta).  Inputs per node k: height z[k], metric Jacobian J[k],
- * contravariant metric grad(zeta) gz[3k+m], theta0[k], cTheta[k]; gravity g.
+ * Unknown (node k, variable v) sits at 5k+v, v = (rho, rho u, rho v, rho w, q_T)
+ * with q_T the thermodynamic variable of the equation set (Theta = rho theta for
+ * set 2C, the total energy E for set 3C).  Inputs per node k: height z[k], metric
+ * Jacobian J[k], contravariant metric grad(zeta) gz[3k+m], the flux coefficient
+ * hq[k] (theta0 for 2C, (E0 + P0)/rho0 for 3C), cq[k] = dP/dq_T (c_Theta for 2C,
+ * gamma - 1 for 3C) and pr[k] = dP/drho (NULL: zero, as in set 2C); gravity g.
  *
- * The set-2C vertical fluxes F_rho = U.gz, F_U = (UU/rho + P I).gz,
- * F_Theta = Theta U.gz / rho (Appendix A.2) linearised about a state at rest
+ * The vertical fluxes F_rho = U.gz, F_U = (UU/rho + P I).gz and F_T = Theta U.gz/rho
+ * (2C) or (E + P) U.gz/rho (3C) (Appendix A.2) linearised about a state at rest
  * (U0 = 0) give the flux Jacobian K_j with nonzeros
- *   K[rho][U_m] = gz_m,  K[U_m][Theta] = gz_m c_Theta,  K[Theta][U_m] = gz_m theta0
- * (Appendix A.3, eq. set2c_jacobian, evaluated at U = 0 and with dP/dTheta in
- * place of the garbled dP/dE entry), and the gravity term rho dPhi/dzeta gz
- * (Appendix A.2) is linear in rho, so it enters the rho column of the momentum
- * rows, with Phi = g z (Sec. 2.1).
+ *   K[rho][U_m] = gz_m,  K[U_m][rho] = gz_m dP/drho,  K[U_m][T] = gz_m dP/dq_T,
+ *   K[T][U_m] = gz_m hq
+ * (Appendix A.3, eqs. set2c_jacobian and set3c_jacobian at U = 0, reading the
+ * pressure column as gz_m dP/dq_T: the extra 1/rho printed there does not follow
+ * from differentiating P I.gz, and for 2C the printed dP/dE stands for dP/dTheta),
+ * and the gravity term rho dPhi/dzeta gz (Appendix A.2) is linear in rho, so it
+ * enters the rho column of the momentum rows, with Phi = g z (Sec. 2.1).
  *
  * Per element e (nodes k = eN+i), multiplied by the quadrature weight w_i J_i
  * (Sec. 4.2.3, "applying numerical integration ... and DSS"):
@@ -139,14 +168,14 @@ void ho_reference(int nz, const double *rho0, const double *Theta0, double R,
  *     (dPhi/dzeta)_i = g sum_j D_ij z_{k_j} within the element;
  *   mass M_k += w_i J_k (Sec. 3, lumped mass and DSS).
  * L_z = -M^{-1} B.  rho row weak (the continuity choice of Sec. 4.2.3) unless
- * rho_weak == 0; Theta row strong unless theta_weak != 0; momentum rows strong.
+ * rho_weak == 0; q_T row strong unless theta_weak != 0; momentum rows strong.
  * Rigid lid: momentum rows of the bottom (k=0) and top (k=nz-1) nodes are zero.
  * Parity pinned: closed-form isothermal acoustic-gravity eigenvalues, mass and
  * rho-theta conservation, weak/strong equivalence, tangential momentum,
  * hydrostatic null vectors, rotation equivariance, exact rational brute force
  * (tests). */
 int ho_assemble_L(int N, int Ne, double g, const double *z, const double *J,
-                  const double *gz, const double *theta0, const double *cTheta,
+                  const double *gz, const double *hq, const double *cq, const double *pr,
                   int rho_weak, int theta_weak, double *L) {
   if (N < 1 || N > 16 || Ne < 1) return 1;
   int nz = Ne * N + 1, n = 5 * nz, np1 = N + 1;
@@ -171,8 +200,9 @@ int ho_assemble_L(int N, int Ne, double g, const double *z, const double *J,
         for (int m = 0; m < 3; ++m) {
           double zm = gz[3 * kj + m];
           L[(size_t)(5 * ki + 0) * n + 5 * kj + 1 + m] += (rho_weak ? weak : strong) * zm;
-          L[(size_t)(5 * ki + 1 + m) * n + 5 * kj + 4] += strong * zm * cTheta[kj];
-          L[(size_t)(5 * ki + 4) * n + 5 * kj + 1 + m] += (theta_weak ? weak : strong) * zm * theta0[kj];
+          L[(size_t)(5 * ki + 1 + m) * n + 5 * kj + 4] += strong * zm * cq[kj];
+          if (pr) L[(size_t)(5 * ki + 1 + m) * n + 5 * kj + 0] += strong * zm * pr[kj];
+          L[(size_t)(5 * ki + 4) * n + 5 * kj + 1 + m] += (theta_weak ? weak : strong) * zm * hq[kj];
         }
       }
     }
@@ -308,6 +338,7 @@ typedef struct {
   /* mode 0: solve, 1: apply, 2: ARK step */
   int mode;
   int rho_weak, refine;
+  int eqset; /* 0: set 2C (Theta0 input), 1: set 3C (E0 input) */
   double lambda;
   const double *in; /* solve: b; apply: x */
   const double *in_ref; /* apply: optional x_ref subtracted first */
@@ -370,7 +401,7 @@ static void *worker(void *arg) {
   double *z = malloc(sizeof(double) * nz), *J = malloc(sizeof(double) * nz),
          *gz = malloc(sizeof(double) * 3 * nz), *rho0 = malloc(sizeof(double) * nz),
          *Th0 = malloc(sizeof(double) * nz), *th0 = malloc(sizeof(double) * nz),
-         *cT = malloc(sizeof(double) * nz);
+         *cT = malloc(sizeof(double) * nz), *pr = malloc(sizeof(double) * nz);
   int nv = 8 + 2 * (s > 0 ? s : 1);
   double *vb = malloc(sizeof(double) * n * nv);
   double *b = vb, *x = vb + n, *work = vb + 2 * n, *qn = vb + 3 * n, *qref = vb + 4 * n,
@@ -380,8 +411,13 @@ static void *worker(void *arg) {
   jb->bad_col = -1;
   for (long c = jb->c0; c < jb->c1; ++c) {
     gather_col(jb, c, z, J, gz, rho0, Th0);
-    ho_reference(nz, rho0, Th0, jb->R, jb->cp, jb->pA, th0, cT);
-    if (ho_assemble_L(jb->N, jb->Ne, jb->g, z, J, gz, th0, cT, jb->rho_weak, 0, L)) {
+    /* Th0 holds the set's thermodynamic reference: Theta0 (2C) or E0 (3C) */
+    if (jb->eqset == 1)
+      ho_reference_3c(nz, rho0, Th0, z, jb->R, jb->cp, jb->g, th0, cT, pr);
+    else
+      ho_reference(nz, rho0, Th0, jb->R, jb->cp, jb->pA, th0, cT);
+    if (ho_assemble_L(jb->N, jb->Ne, jb->g, z, J, gz, th0, cT, jb->eqset == 1 ? pr : NULL,
+                      jb->rho_weak, 0, L)) {
       jb->status = 1; jb->bad_col = c; break;
     }
     if (jb->mode == 1) {
@@ -467,7 +503,7 @@ static void *worker(void *arg) {
         put_vec(jb->Sout + (size_t)i * 5 * nz * jb->ncols, jb->ncols, nz, c, &S[(size_t)i * n]);
   }
   free(L); free(A); free(LU); free(piv); free(z); free(J); free(gz); free(rho0);
-  free(Th0); free(th0); free(cT); free(vb);
+  free(Th0); free(th0); free(cT); free(pr); free(vb);
   return NULL;
 }
 
@@ -504,16 +540,17 @@ static void fill_common(job_t *jb, int N, int Ne, long ncols, const double *cons
 }
 
 /* x = (I - lambda L_z)^{-1} P(b) per column, P the rigid-lid projection.
- * consts = {R, c_p, g, P_A}.  Returns 0 or an error code; *bad_col names the
- * first failing column. */
+ * consts = {R, c_p, g, P_A}; eqset 0 (set 2C: Theta0 is rho0 theta0) or 1 (set
+ * 3C: Theta0 holds the total energy E0).  Returns 0 or an error code; *bad_col
+ * names the first failing column. */
 int ho_solve_batch(int N, int Ne, long ncols, int nthreads, const double *consts,
                    const double *z, const double *J, const double *gz, const double *rho0,
                    const double *Theta0, double lambda, const double *b, double *x,
-                   int refine, int rho_weak, long *bad_col) {
+                   int refine, int rho_weak, int eqset, long *bad_col) {
   job_t jb;
   fill_common(&jb, N, Ne, ncols, consts, z, J, gz, rho0, Theta0);
   jb.mode = 0; jb.lambda = lambda; jb.in = b; jb.out = x; jb.refine = refine;
-  jb.rho_weak = rho_weak;
+  jb.rho_weak = rho_weak; jb.eqset = eqset;
   return run_jobs(&jb, nthreads, bad_col);
 }
 
@@ -521,10 +558,11 @@ int ho_solve_batch(int N, int Ne, long ncols, int nthreads, const double *consts
 int ho_apply_batch(int N, int Ne, long ncols, int nthreads, const double *consts,
                    const double *z, const double *J, const double *gz, const double *rho0,
                    const double *Theta0, const double *x, const double *xref, double *y,
-                   int rho_weak, long *bad_col) {
+                   int rho_weak, int eqset, long *bad_col) {
   job_t jb;
   fill_common(&jb, N, Ne, ncols, consts, z, J, gz, rho0, Theta0);
   jb.mode = 1; jb.in = x; jb.in_ref = xref; jb.out = y; jb.rho_weak = rho_weak;
+  jb.eqset = eqset;
   return run_jobs(&jb, nthreads, bad_col);
 }
 
@@ -537,13 +575,13 @@ int ho_ark_step_batch(int N, int Ne, long ncols, int nthreads, const double *con
                       const double *Theta0, int s, const double *Aexp, const double *Aimp,
                       const double *bw, double dt, double omega, const double *qn,
                       const double *qref, double *qnp1, double *Qout, double *Sout, int refine,
-                      int rho_weak, long *bad_col) {
+                      int rho_weak, int eqset, long *bad_col) {
   if (s < 2) return 1;
   job_t jb;
   fill_common(&jb, N, Ne, ncols, consts, z, J, gz, rho0, Theta0);
   jb.mode = 2; jb.s = s; jb.Aexp = Aexp; jb.Aimp = Aimp; jb.bw = bw; jb.dt = dt;
   jb.omega = omega;
   jb.qn = qn; jb.qref = qref; jb.qnp1 = qnp1; jb.Qout = Qout; jb.Sout = Sout;
-  jb.refine = refine; jb.rho_weak = rho_weak;
+  jb.refine = refine; jb.rho_weak = rho_weak; jb.eqset = eqset;
   return run_jobs(&jb, nthreads, bad_col);
 }

@@ -17,8 +17,9 @@ elements, hydrostatic stratified reference):
   general per-node metric inputs.
 * reference state: hydrostatic p(z) for an isothermal or piecewise lapse-rate
   temperature profile (closed forms), rho0 = p/(R T),
-  Theta0 = rho0 T (P_A/p)^(R/c_p), at rest.
-* perturbation: drho = 1e-3 rho0 xi, dTheta = 1e-3 Theta0 xi,
+  Theta0 = rho0 T (P_A/p)^(R/c_p), at rest; for set 3C (total energy) the same
+  atmosphere as E0 = rho0 c_v T + rho0 g z (internal plus potential energy).
+* perturbation: drho = 1e-3 rho0 xi, dq_T = 1e-3 q_T0 xi (q_T = Theta or E),
   dU = 1e-3 rho0 c0 xi_vec with c0 = sqrt(gamma R T) and xi ~ U(-1, 1); the
   normal momentum at the bottom and top nodes is removed.
 """
@@ -116,18 +117,34 @@ def make_columns(N, Ne, ncols, *, z_top=30.0e3, z_s=None, profile="isothermal", 
     rho0 = p / (R_DRY * T)
     theta = T * (P_A / p) ** (R_DRY / CP_DRY)
     Theta0 = rho0 * theta
+    E0 = rho0 * (CP_DRY - R_DRY) * T + rho0 * GRAV * z
     return {"N": N, "Ne": Ne, "nz": nz, "ncols": ncols, "consts": np.array(CONSTS),
             "z": np.ascontiguousarray(z), "J": np.ascontiguousarray(J),
             "gz": np.ascontiguousarray(gz), "rho0": np.ascontiguousarray(rho0),
-            "Theta0": np.ascontiguousarray(Theta0), "T": T, "nhat": nhat,
-            "profile": profile, "z_top": z_top}
+            "Theta0": np.ascontiguousarray(Theta0), "E0": np.ascontiguousarray(E0), "T": T,
+            "nhat": nhat, "profile": profile, "z_top": z_top, "eqset": "2C"}
+
+
+def as_set(col, eqset):
+    """The same batch with its equation set switched ("2C": state (rho, U, Theta);
+    "3C": state (rho, U, E))."""
+    if eqset not in ("2C", "3C"):
+        raise ValueError(eqset)
+    out = dict(col)
+    out["eqset"] = eqset
+    return out
+
+
+def thermo0(col):
+    """The reference of the set's thermodynamic variable: Theta0 (2C) or E0 (3C)."""
+    return col["E0"] if col.get("eqset", "2C") == "3C" else col["Theta0"]
 
 
 def reference_vector(col):
-    """q_ref = (rho0, 0, 0, 0, Theta0) as [v][k][c]."""
+    """q_ref = (rho0, 0, 0, 0, Theta0 or E0) as [v][k][c]."""
     q = np.zeros((5,) + col["rho0"].shape)
     q[0] = col["rho0"]
-    q[4] = col["Theta0"]
+    q[4] = thermo0(col)
     return q
 
 
@@ -151,7 +168,7 @@ def perturbed_state(col, seed=3, amp=1.0e-3):
     q[0] += amp * col["rho0"] * rng.uniform(-1, 1, shape)
     for m in range(3):
         q[1 + m] += amp * col["rho0"] * c0 * rng.uniform(-1, 1, shape)
-    q[4] += amp * col["Theta0"] * rng.uniform(-1, 1, shape)
+    q[4] += amp * thermo0(col) * rng.uniform(-1, 1, shape)
     return _remove_boundary_normal(col, q), qref
 
 
@@ -167,7 +184,7 @@ def smooth_state(col, amp=1.0e-3, modes=(1, 2)):
     cshape = sum(np.cos(m * np.pi * s) / m for m in modes)
     q = qref.copy()
     q[0] += amp * col["rho0"] * cshape
-    q[4] += amp * col["Theta0"] * 0.5 * cshape
+    q[4] += amp * thermo0(col) * 0.5 * cshape
     nh = col["nhat"].T[:, None, :]
     q[1:4] += amp * col["rho0"] * c0 * shape * nh
     return _remove_boundary_normal(col, q), qref

@@ -125,8 +125,9 @@ def _rational_gll(N):
     raise ValueError
 
 
-def _rational_solve(N, Ne, g, z, J, gz, th0, cT, lam, b):
-    """Exact (Fraction) assembly of I - lam L and Gauss-Jordan solve."""
+def _rational_solve(N, Ne, g, z, J, gz, th0, cT, lam, b, pr=None):
+    """Exact (Fraction) assembly of I - lam L and Gauss-Jordan solve (pr: the
+    dP/drho column of set 3C, None for set 2C)."""
     w, D = _rational_gll(N)
     nz = Ne * N + 1
     n = 5 * nz
@@ -144,6 +145,8 @@ def _rational_solve(N, Ne, g, z, J, gz, th0, cT, lam, b):
                 for m in range(3):
                     B[5 * ki][5 * kj + 1 + m] += -w[j] * D[j][i] * J[kj] * gz[kj][m]
                     B[5 * ki + 1 + m][5 * kj + 4] += w[i] * D[i][j] * J[kj] * gz[kj][m] * cT[kj]
+                    if pr is not None:
+                        B[5 * ki + 1 + m][5 * kj] += w[i] * D[i][j] * J[kj] * gz[kj][m] * pr[kj]
                     B[5 * ki + 4][5 * kj + 1 + m] += w[i] * D[i][j] * J[kj] * gz[kj][m] * th0[kj]
     A = [[(Fr(1) if r == c else Fr(0)) + lam * B[r][c] / M[r // 5] for c in range(n)]
          for r in range(n)]
@@ -164,10 +167,12 @@ def _rational_solve(N, Ne, g, z, J, gz, th0, cT, lam, b):
     return [Ab[r][n] for r in range(n)]
 
 
-@pytest.mark.parametrize("N,Ne", [(1, 2), (2, 2), (2, 1)])
-def test_p1_rational_brute_force(N, Ne):
+@pytest.mark.parametrize("N,Ne,with_pr", [(1, 2, False), (2, 2, False), (2, 1, False),
+                                          (2, 2, True), (1, 3, True)])
+def test_p1_rational_brute_force(N, Ne, with_pr):
     """Oracle solve vs exact rational arithmetic; n = (3/5, 0, 4/5) so the boundary
-    projection is exact (catches index, sign and pivoting bugs in assembly and GE)."""
+    projection is exact (catches index, sign and pivoting bugs in assembly and GE).
+    with_pr adds the set-3C dP/drho column of the momentum rows."""
     nz = Ne * N + 1
     h = Fr(3000)
     nh = (Fr(3, 5), Fr(0), Fr(4, 5))
@@ -189,10 +194,12 @@ def test_p1_rational_brute_force(N, Ne):
         d = sum(a * c for a, c in zip(bu, nh))
         for m in range(3):
             b[5 * k + 1 + m] = bu[m] - nh[m] * d
-    x_exact = np.array([float(v) for v in _rational_solve(N, Ne, g, z, J, gz, th0, cT, lam, b)])
+    pr = [-Fr(2, 5) * g * zz for zz in z] if with_pr else None
+    x_exact = np.array([float(v) for v in _rational_solve(N, Ne, g, z, J, gz, th0, cT, lam, b,
+                                                          pr)])
     f = lambda a: np.array([float(v) for v in a])
     L = oracle.assemble_L(N, Ne, float(g), f(z), f(J), np.array([[float(v) for v in r] for r in gz]),
-                          f(th0), f(cT))
+                          f(th0), f(cT), f(pr) if with_pr else None)
     A = oracle.form_A(L, float(lam))
     x = oracle.lu_solve_dense(A, f(b), refine=0)
     assert np.linalg.norm(x - x_exact) / np.linalg.norm(x_exact) < 1e-14
@@ -587,3 +594,196 @@ def test_p12b_explicit_part_order(tabname):
         errs.append(np.linalg.norm(oracle.vec_of(q - qref, 0) - exact) / np.linalg.norm(exact))
     rates = [np.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
     assert abs(rates[-1] - p) < 0.15, (errs, rates)
+
+
+# ---------------------------------------------------------------------------
+# Set 3C (total energy; Appendix A.1 eq. set3c, Appendix A.3 eq. set3c_jacobian)
+
+def _to_3c(col, c, v2):
+    """The set-2C perturbation v2 = (rho', U', Theta') of column c as set-3C
+    variables (rho', U', E'): linearising E = P/(gamma-1) + U.U/(2 rho) + rho Phi
+    (eq. set3c_pressure) at rest with P' = c_Theta Theta' (eq. set2c_pressure) gives
+    E' = c_Theta Theta'/(gamma - 1) + Phi rho', Phi = g z."""
+    z, J, gz, r0, T0 = oracle.column_of(col, c)
+    _, cT = oracle.reference(r0, T0, CONSTS)
+    v = v2.copy()
+    v[4::5] = cT * v2[4::5] / (GAM - 1) + G * z * v2[0::5]
+    return v
+
+
+def _L_both(col, c):
+    z, J, gz, r0, T0 = oracle.column_of(col, c)
+    N, Ne = col["N"], col["Ne"]
+    L2 = oracle.column_L(N, Ne, CONSTS, z, J, gz, r0, T0)
+    L3 = oracle.column_L(N, Ne, CONSTS, z, J, gz, r0, col["E0"][:, c], eqset="3C")
+    return L2, L3
+
+
+def test_3c_reference_ideal_gas():
+    """For the ideal-gas reference E0 = rho0 c_v T + rho0 g z: P0 = rho0 R T, so
+    dP/dE (h - Phi) = (gamma-1) c_p T = gamma R T = c^2, and dP/drho = -(gamma-1) g z
+    (catches E0/rho0 in place of (E0+P0)/rho0, a dropped Phi or a wrong gamma)."""
+    col = inputs.config2(ncols=3)
+    z = col["z"].ravel()
+    hE, dPdE, dPdr = oracle.reference_3c(col["rho0"].ravel(), col["E0"].ravel(), z, CONSTS)
+    T = col["T"].ravel()
+    assert np.allclose(dPdE * (hE - G * z), GAM * R * T, rtol=1e-12)
+    assert np.allclose(dPdr, -(GAM - 1) * G * z, rtol=1e-15, atol=0)
+    assert np.all(dPdE == GAM - 1)
+
+
+@pytest.mark.parametrize("profile", ["isothermal", "lapse"])
+def test_3c_momentum_rows_equal_2c(profile):
+    """Under E' = c_Theta Theta'/(gamma-1) + Phi rho' the linearised pressure of set
+    3C, (gamma-1)(E' - Phi rho'), is set 2C's c_Theta Theta' node by node, and the
+    continuity rows are the same: so the rho and momentum rows of L_3C T v and
+    T L_2C v agree to rounding at any resolution.  Catches a wrong sign or a
+    missing dP/drho entry, a dP/dE other than gamma-1 or the pressure column put in
+    the wrong place."""
+    col = inputs.make_columns(4, 6, 2, profile=profile, seed=3, surface_max=1e3, tilt=0.05)
+    qn, qref = inputs.perturbed_state(col)
+    for c in range(2):
+        L2, L3 = _L_both(col, c)
+        v2 = oracle.vec_of(qn - qref, c)
+        a = L3 @ _to_3c(col, c, v2)
+        b = _to_3c(col, c, L2 @ v2)
+        assert np.array_equal(a[0::5], b[0::5])
+        for v in (1, 2, 3):
+            assert np.linalg.norm(a[v::5] - b[v::5]) <= 1e-13 * np.linalg.norm(b[v::5])
+
+
+@pytest.mark.parametrize("profile", ["isothermal", "lapse"])
+def test_3c_energy_row_converges_to_2c(profile):
+    """The energy rows of L_3C T v and T L_2C v differ only by the discrete product
+    rule (h = (gamma-1)^-1 c_Theta theta0 + Phi up to the hydrostatic balance of the
+    reference), so their difference falls at the spectral rate, by about 2^(N) per
+    halving of the element size for N = 4, for a smooth perturbation.  Catches a
+    wrong energy flux coefficient (an O(1) difference that does not converge) or a
+    transposed derivative in the energy row."""
+    errs = []
+    for Ne in (4, 8, 16):
+        col = inputs.make_columns(4, Ne, 1, profile=profile, seed=3, surface_max=1e3)
+        qn, qref = inputs.smooth_state(col)
+        L2, L3 = _L_both(col, 0)
+        v2 = oracle.vec_of(qn - qref, 0)
+        a = L3 @ _to_3c(col, 0, v2)
+        b = _to_3c(col, 0, L2 @ v2)
+        errs.append(np.linalg.norm(a[4::5] - b[4::5]) / np.linalg.norm(a[4::5]))
+    assert errs[-1] < 2e-6, errs
+    assert errs[0] / errs[1] > 10 and errs[1] / errs[2] > 10, errs
+
+
+@pytest.mark.parametrize("Ne,tols", [(8, (1e-10, 1e-8, 1e-6)), (16, (1e-12, 1e-10, 1e-8))])
+def test_3c_acoustic_eigenvalues(Ne, tols):
+    """The isothermal rigid-lid column in set 3C has the same acoustic-gravity
+    frequencies as in set 2C (the linear dynamics do not depend on the choice of
+    thermodynamic variable): catches a wrong energy flux, a wrong dP/dE or dP/drho."""
+    H = 30.0e3
+    col = inputs.as_set(flat_column(4, Ne, H=H, nhat=(0.36, 0.48, 0.8)), "3C")
+    L = oracle.column_L(4, Ne, CONSTS, *oracle.column_of(col, 0), eqset="3C")
+    ev = np.linalg.eigvals(L)
+    for m, tol in zip((1, 2, 3), tols):
+        w = _omega(m, H)
+        best = ev[np.argmin(np.abs(ev - 1j * w))]
+        assert abs(best - 1j * w) / w < tol, (m, best, w)
+        assert abs(best.real) < tol * w
+    assert np.abs(ev.real).max() < 0.03 * np.abs(ev).max()
+
+
+@pytest.mark.parametrize("hetero", [False, True])
+def test_3c_mass_and_total_energy_conservation(hetero):
+    """Set 3C conserves mass and total energy (Sec. 3 and the Appendix A.1
+    remarks): sum_k M_k x_k = sum_k M_k b_k for rho and E under the rigid lid
+    (catches a transposed derivative or a wrong DSS in the energy row)."""
+    col = inputs.make_columns(4, 8, 4, profile="lapse", seed=4,
+                              surface_max=2e3 if hetero else 0.0, deep=hetero)
+    col = inputs.as_set(col, "3C")
+    qn, qref = inputs.perturbed_state(col)
+    b = qn - qref
+    lam = 0.4358665215 * 300
+    x = oracle.solve_batch(col, lam, b, refine=1)
+    w = np.array([float(v) for v in GLL_CLOSED[4][1]])
+    for c in range(4):
+        M = np.zeros(col["nz"])
+        for e in range(col["Ne"]):
+            for i in range(5):
+                M[4 * e + i] += w[i] * col["J"][4 * e + i, c]
+        for v in (0, 4):
+            lhs = np.dot(M, x[v, :, c])
+            rhs = np.dot(M, b[v, :, c])
+            assert abs(lhs - rhs) <= 1e-13 * np.dot(M, np.abs(b[v, :, c]))
+
+
+def test_3c_hydrostatic_null_vector():
+    """The set-2C hydrostatic null vector (rho' balancing the pressure gradient of
+    Theta') mapped to (rho', 0, E') is a null vector of L_3C, so x = b for every
+    Lambda (catches a gravity or dP/drho term that does not cancel)."""
+    col = inputs.config1(heterogeneous=True, ncols=1)
+    rng = np.random.default_rng(4)
+    z, J, gz, r0, T0 = oracle.column_of(col, 0)
+    nz = col["nz"]
+    L2, L3 = _L_both(col, 0)
+    v = np.zeros(5 * nz)
+    v[4::5] = 1e-2 * T0 * rng.uniform(-1, 1, nz)
+    p = L2 @ v
+    n = col["nhat"][0]
+    for k in range(1, nz - 1):
+        v[5 * k] = (n @ p[5 * k + 1:5 * k + 4]) / G
+    v3 = _to_3c(col, 0, v)
+    assert np.linalg.norm(L3 @ v3) <= 1e-13 * np.linalg.norm(L3, 2) * np.linalg.norm(v3)
+    for lam in (10.0, 1000.0):
+        x = oracle.lu_solve_dense(oracle.form_A(L3, lam), v3, refine=1)
+        assert relerr_per_var(x, v3) < 1e-12
+
+
+def test_3c_lapack_band_and_mpmath():
+    """Set-3C solve at the ne=30 shape against the LAPACK band solver (the paper's
+    solver, Sec. 4.2.2) and 30-digit elimination (the oracle+ mode)."""
+    mp.mp.dps = 30
+    col = inputs.as_set(inputs.config2(ncols=1), "3C")
+    N, Ne = col["N"], col["Ne"]
+    lam = 0.4358665215 * 300
+    qn, qref = inputs.perturbed_state(col)
+    z, J, gz, r0, E0 = oracle.column_of(col, 0)
+    L = oracle.column_L(N, Ne, CONSTS, z, J, gz, r0, E0, eqset="3C")
+    A = oracle.form_A(L, lam)
+    n = A.shape[0]
+    kl = ku = 5 * (N + 1) - 1
+    ii, jj = np.nonzero(A)
+    assert np.abs(ii - jj).max() <= kl
+    ab = np.zeros((kl + ku + 1, n))
+    for j in range(n):
+        for i in range(max(0, j - ku), min(n, j + kl + 1)):
+            ab[ku + i - j, j] = A[i, j]
+    b = oracle.bc_project(col["nz"], gz, oracle.vec_of(qn - qref, 0))
+    xl = sla.solve_banded((kl, ku), ab, b)
+    xm = np.array([float(v) for v in mp.lu_solve(mp.matrix(A.tolist()), mp.matrix(b.tolist()))])
+    x1 = oracle.lu_solve_dense(A, b, refine=1)
+    assert relerr_per_var(x1, xm) < 1e-15
+    assert relerr_per_var(x1, xl) < 5e-12
+    # the batched driver runs the same definition
+    xb = oracle.solve_batch(col, lam, qn - qref, refine=1)
+    assert relerr_per_var(oracle.vec_of(xb, 0), x1) < 1e-15
+
+
+@pytest.mark.parametrize("eqset", ["2C", "3C"])
+def test_3c_rotation_and_tangential(eqset):
+    """Rotation equivariance and untouched tangential momentum hold for both sets."""
+    col = inputs.as_set(inputs.config1(heterogeneous=True, ncols=3), eqset)
+    qn, qref = inputs.perturbed_state(col)
+    b = qn - qref
+    lam = 25.0
+    x = oracle.solve_batch(col, lam, b, refine=1)
+    Q = sla.expm(np.array([[0, -0.3, 0.5], [0.3, 0, -0.7], [-0.5, 0.7, 0]]))
+    col2 = dict(col)
+    col2["gz"] = np.einsum("ij,jkc->ikc", Q, col["gz"])
+    b2 = b.copy()
+    b2[1:4] = np.einsum("ij,jkc->ikc", Q, b[1:4])
+    x2 = oracle.solve_batch(col2, lam, b2, refine=1)
+    xr = x.copy()
+    xr[1:4] = np.einsum("ij,jkc->ikc", Q, x[1:4])
+    for c in range(3):
+        assert relerr_per_var(oracle.vec_of(x2, c), oracle.vec_of(xr, c)) < 1e-13
+        n = col["nhat"][c]
+        P = np.eye(3) - np.outer(n, n)
+        assert np.abs(P @ x[1:4, :, c] - P @ b[1:4, :, c]).max() <= 1e-13 * np.abs(b[1:4]).max()
