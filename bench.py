@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0       # MI355X HBM3E, published
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage_solve_ne30_traffic.txt")
 KERNEL_SRC = [os.path.join(ROOT, "paper_2311_11425_amd", "csrc", f)
-              for f in ("hevi_kernels.hip", "hevi_device.h", "hevi_gll.h")]
+              for f in ("hevi_kernels.hip", "hevi_kernels_impl.h", "hevi_device.h", "hevi_gll.h")]
 
 PATHS = {  # name: (precision, refine=(max_sweeps, rel_target, full_sweeps))
     "fp64": (0, (0, 1e-13, 0)),
@@ -84,8 +84,9 @@ def measured_traffic(path):
 def sample_columns(col, idx):
     """The column batch restricted to the columns idx (host arrays)."""
     sc = dict(col)
-    for k in ("z", "J", "rho0", "Theta0"):
-        sc[k] = np.ascontiguousarray(col[k][:, idx])
+    for k in ("z", "J", "rho0", "Theta0", "E0"):
+        if k in col:
+            sc[k] = np.ascontiguousarray(col[k][:, idx])
     sc["gz"] = np.ascontiguousarray(col["gz"][:, :, idx])
     sc["ncols"] = len(idx)
     return sc
@@ -294,6 +295,34 @@ def share_leg(ctx, ncols=10800, steps=200, warmup=20):
     ms = (time.perf_counter() - t) * 1e3 / steps
     return {"columns": ncols, "ms_per_step": ms, "column_solves_per_s": 3 * ncols / (ms * 1e-3),
             "note": "ne=30 column count split over 8 GPUs (86,402 / 8): one GPU's share, FP64"}
+
+
+def set3c_leg(ctx, checks, ncols=86402, steps=100, warmup=10):
+    """The same ne=30 workload in set 3C (total energy E as the fifth variable, its
+    operator with the dP/drho column): FP64 and FP32-factor ARK3 steps, stage solves
+    checked against the oracle on sampled columns (queued in `checks`)."""
+    import torch
+    from paper_2311_11425_amd import inputs
+    from paper_2311_11425_amd.driver import ColumnBatch
+    col = inputs.as_set(inputs.config2(ncols=ncols), "3C")
+    qn, qref = inputs.perturbed_state(col)
+    B = ColumnBatch(ctx, col)
+    qd, qrd = torch.from_numpy(qn).cuda(), torch.from_numpy(qref).cuda()
+    rng = np.random.default_rng(6)
+    idx = np.unique(np.concatenate([rng.choice(ncols, min(ncols, 64) - 3, replace=False),
+                                    [0, ncols - 1, min(64, ncols - 1)]]))
+    out = {"columns": ncols, "eqset": "3C"}
+    for name in ("fp64", "mixed"):
+        st, r = run_path(ctx, B, name, qd, qrd, steps, warmup)
+        ms = r["wall_s"] * 1e3 / steps
+        d = {"ms_per_step": ms, "column_solves_per_s": 3 * ncols / (ms * 1e-3),
+             "stage_solve_ms": float(np.mean(r["stage_ms"])),
+             "factor_ms": float(np.mean(r["factor_ms"])),
+             "apply_op_ms": float(np.mean(r["apply_ms"]))}
+        queue_stage_errors(checks, d, "stage_rel_err_vs_oracle", st, col, qn, idx, BARS[name])
+        out[name] = d
+        del st
+    return out
 
 
 def copy_ceiling(nbytes=1 << 30, reps=20):
@@ -691,8 +720,8 @@ def main():
     ap.add_argument("--no-error-check", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="CPU-seconds for the oracle")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the config-1 accuracy, uneven-batch and serving legs")
-    ap.add_argument("--leg", choices=["config1", "share", "uneven", "serve"],
+                    help="skip the set-3C, config-1 accuracy, uneven-batch and serving legs")
+    ap.add_argument("--leg", choices=["config1", "share", "uneven", "serve", "set3c"],
                     help="run only this extra leg (for profiling) and print its JSON")
     ap.add_argument("--uneven-scale", type=float, default=1.0)
     ap.add_argument("--serve-scale", type=float, default=1.0)
@@ -715,7 +744,8 @@ def main():
         ctx = hevi.Context(0)
         leg = {"config1": lambda: cfg1_leg(ctx, checks), "share": lambda: share_leg(ctx),
                "uneven": lambda: uneven_leg(ctx, checks, scale=args.uneven_scale),
-               "serve": lambda: serve_leg(ctx, checks, scale=args.serve_scale)}[args.leg]()
+               "serve": lambda: serve_leg(ctx, checks, scale=args.serve_scale),
+               "set3c": lambda: set3c_leg(ctx, checks)}[args.leg]()
         torch.cuda.synchronize()
         ctx.close()
         if not args.no_error_check:
@@ -828,6 +858,9 @@ def main():
     if not args.no_extra:
         del B, st
         torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        log("set-3C leg ...")
+        res["set3c"] = set3c_leg(ctx, checks)
         torch.cuda.empty_cache()
         log("config-1 accuracy leg ...")
         res["config1_ark2_accuracy"] = cfg1_leg(ctx, checks)

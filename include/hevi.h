@@ -137,6 +137,30 @@ hevi_status hevi_build_column_ops(hevi_ctx *ctx, const hevi_shape *shape,
                                   const double *d_J, const double *d_gz,
                                   const double *d_rho0, const double *d_Theta0,
                                   hevi_ops **out, hipStream_t stream);
+
+/* Equation sets (Appendix A.1): set 2C carries Theta = rho theta, set 3C the total
+ * energy E = rho (c_v T + u.u/2 + Phi) as the fifth state variable. */
+typedef enum {
+  HEVI_SET_2C = 0,
+  HEVI_SET_3C = 1
+} hevi_eqset;
+
+/* hevi_build_column_ops for either equation set; HEVI_SET_2C is exactly
+ * hevi_build_column_ops.  For HEVI_SET_3C, d_q0 is the reference total energy E0
+ * ([k][c]) and the operator is the set-3C vertical operator linearised at rest
+ * (Appendix A.3, eq. set3c_jacobian at U = 0): pressure P0 = (gamma - 1)(E0 -
+ * rho0 Phi) with Phi = g z (eq. set3c_pressure; must be > 0), energy flux
+ * coefficient (E0 + P0)/rho0, dP/dE = gamma - 1 and dP/drho = -(gamma - 1) Phi,
+ * whose rho column joins the pressure gradient of the momentum rows (the reduced
+ * system keeps its band, see hevi_factor).  Every state vector handed to calls on
+ * these ops is then (rho, U, E).  A set-3C operator holds 9 FP64 per node.  Group
+ * steps and the server take set-2C operators only (HEVI_E_INVALID). */
+hevi_status hevi_build_column_ops_set(hevi_ctx *ctx, const hevi_shape *shape,
+                                      const hevi_consts *consts, hevi_eqset eqset,
+                                      const double *d_z, const double *d_J,
+                                      const double *d_gz, const double *d_rho0,
+                                      const double *d_q0, hevi_ops **out,
+                                      hipStream_t stream);
 /* Waits for `stream` and reports the first column whose inputs were invalid
  * (non-positive J/rho0/Theta0, zero grad(zeta), non-finite values). */
 hevi_status hevi_ops_check(hevi_ctx *ctx, const hevi_ops *ops, int64_t *first_bad_col,

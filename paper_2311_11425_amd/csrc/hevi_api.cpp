@@ -134,7 +134,17 @@ hevi_status hevi_build_column_ops(hevi_ctx* ctx, const hevi_shape* shape, const 
                                   const double* d_z, const double* d_J, const double* d_gz,
                                   const double* d_rho0, const double* d_Theta0, hevi_ops** out,
                                   hipStream_t stream) {
+  return hevi_build_column_ops_set(ctx, shape, k, HEVI_SET_2C, d_z, d_J, d_gz, d_rho0, d_Theta0,
+                                   out, stream);
+}
+
+hevi_status hevi_build_column_ops_set(hevi_ctx* ctx, const hevi_shape* shape,
+                                      const hevi_consts* k, hevi_eqset eqset, const double* d_z,
+                                      const double* d_J, const double* d_gz,
+                                      const double* d_rho0, const double* d_Theta0,
+                                      hevi_ops** out, hipStream_t stream) {
   if (!ctx || !out || !k) return HEVI_E_INVALID;
+  if (eqset != HEVI_SET_2C && eqset != HEVI_SET_3C) return HEVI_E_INVALID;
   *out = nullptr;
   hevi_status s = check_shape(shape);
   if (s) return s;
@@ -153,7 +163,9 @@ hevi_status hevi_build_column_ops(hevi_ctx* ctx, const hevi_shape* shape, const 
   o->d_info = nullptr;
   o->d_tilt = nullptr;
   o->tilted = 0;
-  if ((s = dev_alloc(&o->d_ops, tiles_nodes(o->sh) * HEVI_NOPS * sizeof(double))) ||
+  o->s3 = eqset == HEVI_SET_3C;
+  // set 3C: one more per-node field (J dP/drho) after the tile-interleaved eight
+  if ((s = dev_alloc(&o->d_ops, tiles_nodes(o->sh) * (HEVI_NOPS + o->s3) * sizeof(double))) ||
       (s = dev_alloc(&o->d_info, sizeof(HeviDevInfo))) ||
       (s = dev_alloc(&o->d_tilt, sizeof(int32_t)))) {
     hevi_ops_free(o);
@@ -164,7 +176,7 @@ hevi_status hevi_build_column_ops(hevi_ctx* ctx, const hevi_shape* shape, const 
   int32_t tilt = 0;
   if (!ok(hipMemcpyAsync(o->d_tilt, &tilt, sizeof(tilt), hipMemcpyHostToDevice, stream)) ||
       !ok(hevi_launch_info_reset(o->d_info, stream)) ||
-      !ok(hevi_launch_build_ops(o->sh, k->R, k->cp, k->g, k->p_A, d_z, d_J, d_gz, d_rho0,
+      !ok(hevi_launch_build_ops(o->sh, o->s3, k->R, k->cp, k->g, k->p_A, d_z, d_J, d_gz, d_rho0,
                                 d_Theta0, o->d_ops, o->d_info, o->d_tilt, stream)) ||
       !ok(hipMemcpyAsync(&tilt, o->d_tilt, sizeof(tilt), hipMemcpyDeviceToHost, stream)) ||
       !ok(hipStreamSynchronize(stream))) {
@@ -201,7 +213,7 @@ hevi_status hevi_apply_op(hevi_ctx* ctx, const hevi_ops* ops, const double* d_x,
     if (d_y == d_x || (d_xref && d_y == d_xref)) return HEVI_E_INVALID;
   }
   if (!ok(hipSetDevice(ctx->device))) return HEVI_E_DEVICE;
-  if (!ok(hevi_launch_apply(ops->sh, ops->d_ops, d_x, d_xref, d_y, stream)))
+  if (!ok(hevi_launch_apply(ops->sh, ops->s3, ops->d_ops, d_x, d_xref, d_y, stream)))
     return HEVI_E_DEVICE;
   return HEVI_OK;
 }
@@ -286,7 +298,7 @@ hevi_status hevi_refactor(hevi_ctx* ctx, hevi_factors* f, double lambda, hipStre
   if (!ok(hipSetDevice(ctx->device))) return HEVI_E_DEVICE;
   f->lambda = lambda;
   const hevi_ops* o = f->ops;
-  if (!ok(hevi_launch_factor(o->sh, lambda, f->prec == HEVI_FP32_REFINE, o->d_ops,
+  if (!ok(hevi_launch_factor(o->sh, o->s3, lambda, f->prec == HEVI_FP32_REFINE, o->d_ops,
                              f->sbuf, f->U, f->L, f->piv, f->d_info, stream)))
     return HEVI_E_DEVICE;
   return HEVI_OK;
@@ -366,7 +378,7 @@ hevi_status hevi_stage_solve(hevi_ctx* ctx, const hevi_factors* f, int32_t n_e,
   if (f->prec == HEVI_FP64) sweeps = 0;
   if (!ok(hipSetDevice(ctx->device))) return HEVI_E_DEVICE;
   if (h_info && !ok(hevi_launch_info_reset(f->d_info, stream))) return HEVI_E_DEVICE;
-  if (!ok(hevi_launch_stage_solve(o->sh, f->lambda, o->tilted, f->prec == HEVI_FP32_REFINE,
+  if (!ok(hevi_launch_stage_solve(o->sh, o->s3, f->lambda, o->tilted, f->prec == HEVI_FP32_REFINE,
                                   o->d_ops,
                                   f->U, f->L, f->piv, f->ws, E, Q, d_Qi, sweeps, target, full,
                                   f->d_info, stream)))

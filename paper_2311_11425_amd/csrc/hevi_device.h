@@ -33,6 +33,17 @@
 //   x_U   = b_U + Lambda (PG x_Theta - Phi' grad(zeta) x_rho).
 // S is LU-factored with partial pivoting (band LU, the paper's LAPACK scheme
 // of Sec. 4.2.3 applied to the reduced matrix).
+//
+// Set 3C (total energy E in place of Theta; Appendix A.1 eq. set3c and the
+// Jacobian eq. set3c_jacobian at rest) has the same structure: its E row is DTh
+// with (J theta0) replaced by J (E0 + P0)/rho0, and its linearised pressure
+// (gamma-1)(E - Phi rho) adds dP/drho = -(gamma-1) Phi, a rho column in the pressure
+// gradient: (L x)_U = PG(x_E) + PGr(x_rho) - Phi' grad(zeta) x_rho, PGr the
+// pressure gradient with (J dP/drho) in place of (J c_Theta), so
+//   S = I - Lambda^2 grad(zeta).(PG DTh + PGr Drho - Phi' grad(zeta) Drho),
+// the same band.  The bodies take a template flag S3; with S3 the operator holds
+// the extra per-node field J dP/drho as a plane of its own after the eight
+// tile-interleaved fields (pr_plane).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -82,10 +93,22 @@ struct OpsView {
   const double* ops;
   int64_t tile;
   int nz, lane;
+  const double* pr = nullptr;  // set 3C: J dP/drho plane (pr_plane), else unused
   __device__ __forceinline__ double operator()(int k, int f) const {
     return ops[tix(tile, nz, k, HEVI_NOPS, f, lane)];
   }
+  // J dP/drho at node k (set 3C only)
+  __device__ __forceinline__ double jpr(int k) const { return pr[((size_t)tile * nz + k) * T + lane]; }
 };
+
+// Set 3C: the ninth per-node operator field J dP/drho, stored [tile][k][lane]
+// after the eight tile-interleaved fields of the compact operator.
+__device__ __forceinline__ size_t pr_offset(const HeviShapeDev& sh) {
+  return (size_t)sh.ntiles * sh.nz * HEVI_NOPS * T;
+}
+__device__ __forceinline__ const double* pr_plane(const double* ops, const HeviShapeDev& sh) {
+  return ops + pr_offset(sh);
+}
 
 // v_rho = Drho u and v_Th = DTh u for all nodes; u read from scratch field
 // fu, results written to fields fr, ft.
@@ -124,8 +147,9 @@ __device__ void div_pass(Gll<N> tab, const OpsView& op, int Ne, double* ws, int6
 
 // Pressure gradient + gravity of (v_rho, v_Th) (fields fr, ft):
 //   G_k = -M^-1 sum_e w_i sum_j D_ij (J c_Theta grad zeta)_j v_Th,j - Phi'_k grad(zeta)_k v_rho,k
-// writes grad(zeta)_k . G_k into field fo (zero at the rigid-lid nodes).
-template <int N>
+// (S3: the pressure is J (c v_Th + dP/drho v_rho)); writes grad(zeta)_k . G_k into
+// field fo (zero at the rigid-lid nodes).
+template <int N, bool S3 = false>
 __device__ void pg_pass(Gll<N> tab, const OpsView& op, int Ne, double* ws, int64_t tile,
                         int lane, int fr, int ft, int fo) {
   const int nz = op.nz;
@@ -135,7 +159,8 @@ __device__ void pg_pass(Gll<N> tab, const OpsView& op, int Ne, double* ws, int64
 #pragma unroll
     for (int j = 0; j <= N; ++j) {
       const int k = e * N + j;
-      const double v = op(k, OP_JCT) * ws[tix(tile, nz, k, HEVI_NWS, ft, lane)];
+      double v = op(k, OP_JCT) * ws[tix(tile, nz, k, HEVI_NWS, ft, lane)];
+      if constexpr (S3) v += op.jpr(k) * ws[tix(tile, nz, k, HEVI_NWS, fr, lane)];
       f0[j] = v * op(k, OP_GX);
       f1[j] = v * op(k, OP_GY);
       f2[j] = v * op(k, OP_GZ);
@@ -207,7 +232,7 @@ __device__ __forceinline__ Chunk chunk_of(int Ne, int64_t tile, int cw = 1) {
 // a0: y = L_z (x - x_ref).  Each element iteration loads everything it needs
 // unconditionally (clamped indices), computes, then stores the owned nodes, so
 // the loads of an element are in flight together.
-template <int N, bool HAS_REF>
+template <int N, bool HAS_REF, bool S3 = false>
 __device__ __forceinline__ void b_apply(int64_t tile_, HeviShapeDev sh, Gll<N> tab,
                                         const double* __restrict__ ops,
                                         const double* __restrict__ x,
@@ -222,46 +247,46 @@ __device__ __forceinline__ void b_apply(int64_t tile_, HeviShapeDev sh, Gll<N> t
   const bool valid = c < sh.ncols;
   const int64_t cc = valid ? c : sh.ncols - 1;
   const int64_t nc = sh.ncols;
-  OpsView op{ops, tile, nz, lane};
+  OpsView op{ops, tile, nz, lane, S3 ? pr_plane(ops, sh) : nullptr};
   auto X = [&](int v, int k) {
     const size_t i = cix(nz, nc, v, k, cc);
     if constexpr (HAS_REF) return ldn(x + i) - ldn(xref + i);
     else return ldn(x + i);
   };
   double cr = 0.0, ct = 0.0, c0 = 0.0, c1 = 0.0, c2 = 0.0;
-  // node eN is shared by elements e-1 and e: its loaded values are carried
-  // over instead of being loaded again (the first element loads all N+1 nodes)
-  double kg0 = 0.0, kg1 = 0.0, kg2 = 0.0, kJn = 0.0, kJt = 0.0, kJc = 0.0, kmi = 0.0, kph = 0.0;
-  double kxr = 0.0, kxu0 = 0.0, kxu1 = 0.0, kxu2 = 0.0, kxt = 0.0;
+  // node eN is shared by elements e-1 and e: its values are carried over instead
+  // of being loaded again (the first element loads all N+1 nodes).  Each node's
+  // loads are reduced at once to what the element sums use (u times J and J theta0,
+  // the pressure J (c x_T [+ dP/drho x_rho])), so few values stay live.
+  double kg0 = 0.0, kg1 = 0.0, kg2 = 0.0, kmi = 0.0, kph = 0.0, kxr = 0.0;
+  double kJu = 0.0, kJtu = 0.0, kp = 0.0;
   auto element = [&](const int e, auto first) {
     constexpr bool FIRST = decltype(first)::value;
     // ---- loads ----
-    double g0[N + 1], g1[N + 1], g2[N + 1], Jn[N + 1], Jt[N + 1], Jc[N + 1], mi[N + 1], ph[N + 1];
-    double xr[N + 1], xu[N + 1][3], xt[N + 1];
+    double g0[N + 1], g1[N + 1], g2[N + 1], mi[N + 1], ph[N + 1], xr[N + 1];
+    double Ju[N + 1], Jtu[N + 1], pp[N + 1];
 #pragma unroll
     for (int j = 0; j <= N; ++j) {
       if (!FIRST && j == 0) {
-        g0[0] = kg0; g1[0] = kg1; g2[0] = kg2; Jn[0] = kJn; Jt[0] = kJt; Jc[0] = kJc;
-        mi[0] = kmi; ph[0] = kph;
-        xr[0] = kxr; xu[0][0] = kxu0; xu[0][1] = kxu1; xu[0][2] = kxu2; xt[0] = kxt;
+        g0[0] = kg0; g1[0] = kg1; g2[0] = kg2; mi[0] = kmi; ph[0] = kph; xr[0] = kxr;
+        Ju[0] = kJu; Jtu[0] = kJtu; pp[0] = kp;
         continue;
       }
       const int k = e * N + j;
       g0[j] = op(k, OP_GX); g1[j] = op(k, OP_GY); g2[j] = op(k, OP_GZ);
-      Jn[j] = op(k, OP_J); Jt[j] = op(k, OP_JTH); Jc[j] = op(k, OP_JCT);
       mi[j] = op(k, OP_MINV); ph[j] = op(k, OP_PHI);
-      xr[j] = X(0, k); xu[j][0] = X(1, k); xu[j][1] = X(2, k); xu[j][2] = X(3, k);
-      xt[j] = X(4, k);
+      xr[j] = X(0, k);
+      const double u = g0[j] * X(1, k) + g1[j] * X(2, k) + g2[j] * X(3, k);
+      Ju[j] = op(k, OP_J) * u;
+      Jtu[j] = op(k, OP_JTH) * u;
+      pp[j] = op(k, OP_JCT) * X(4, k);
+      if constexpr (S3) pp[j] += op.jpr(k) * xr[j];
     }
     // ---- element sums ----
-    double Ju[N + 1], Jtu[N + 1], f0[N + 1], f1[N + 1], f2[N + 1];
+    double f0[N + 1], f1[N + 1], f2[N + 1];
 #pragma unroll
     for (int j = 0; j <= N; ++j) {
-      const double u = g0[j] * xu[j][0] + g1[j] * xu[j][1] + g2[j] * xu[j][2];
-      Ju[j] = Jn[j] * u;
-      Jtu[j] = Jt[j] * u;
-      const double p = Jc[j] * xt[j];
-      f0[j] = p * g0[j]; f1[j] = p * g1[j]; f2[j] = p * g2[j];
+      f0[j] = pp[j] * g0[j]; f1[j] = pp[j] * g1[j]; f2[j] = pp[j] * g2[j];
     }
     double yo[N + 1][5];
 #pragma unroll
@@ -297,9 +322,8 @@ __device__ __forceinline__ void b_apply(int64_t tile_, HeviShapeDev sh, Gll<N> t
         }
       }
     }
-    kg0 = g0[N]; kg1 = g1[N]; kg2 = g2[N]; kJn = Jn[N]; kJt = Jt[N]; kJc = Jc[N];
-    kmi = mi[N]; kph = ph[N];
-    kxr = xr[N]; kxu0 = xu[N][0]; kxu1 = xu[N][1]; kxu2 = xu[N][2]; kxt = xt[N];
+    kg0 = g0[N]; kg1 = g1[N]; kg2 = g2[N]; kmi = mi[N]; kph = ph[N]; kxr = xr[N];
+    kJu = Ju[N]; kJtu = Jtu[N]; kp = pp[N];
   };
   int e = max(ch.e0 - 1, 0);
   element(e, std::true_type{});
@@ -361,11 +385,46 @@ __device__ __forceinline__ void k_row(Gll<N> tab, int a, bool left, bool right,
   for (int i2 = 0; i2 <= N; ++i2) acc[B + i2 - a] += gr * tab.w[i2] * tab.D[i2 * (N + 1) + a] * jn[i2];
 }
 
+// Set 3C: the rho column of the pressure adds to row a the term
+//   sum_i Pr_ai Drho_iq,  Pr_ai = -M^-1_r w_a D_ai (J dP/drho)_i grad(zeta)_r . grad(zeta)_i,
+// where Drho row i (node eN + i) is M^-1_i C'_iq J_q: C' = w_q D_(q-eN)i for the
+// element's own nodes, element e-1's w_q D_qN at node eN when `left`, element e+1's
+// w_(q-2N) D_(q-2N)0 at node (e+1)N when `right` (the weak form).  So
+// acc_q -= J_q sum_i Prm_i C'_iq with Prm_i = -Pr_ai M^-1_i.  Jq[q] is J at node
+// (e-1)N + q (zero outside the column), jp J dP/drho at nodes eN .. eN+N.
+template <int N>
+__device__ __forceinline__ void k_row_pr(Gll<N> tab, int a, bool left, bool right,
+                                         const double (&Jq)[3 * N + 1], const double (&mi)[N + 1],
+                                         const double (&gx)[N + 1], const double (&gy)[N + 1],
+                                         const double (&gz)[N + 1], const double (&jp)[N + 1],
+                                         double (&acc)[4 * N + 1]) {
+#pragma clang fp contract(off)
+  constexpr int B = 2 * N, NC = 3 * N + 1;
+  const double mr = mi[a];
+  double Pm[N + 1];
+#pragma unroll
+  for (int i = 0; i <= N; ++i) {
+    const double dot = gx[a] * gx[i] + gy[a] * gy[i] + gz[a] * gz[i];
+    Pm[i] = mr * tab.w[a] * tab.D[a * (N + 1) + i] * jp[i] * dot * mi[i];
+  }
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    double sq = 0.0;
+    if (q >= N && q <= B) {
+#pragma unroll
+      for (int i = 0; i <= N; ++i) sq += Pm[i] * (tab.w[q - N] * tab.D[(q - N) * (N + 1) + i]);
+    }
+    if (q <= N && left) sq += Pm[0] * (tab.w[q] * tab.D[q * (N + 1) + N]);
+    if (q >= B && right) sq += Pm[N] * (tab.w[q - B] * tab.D[(q - B) * (N + 1)]);
+    acc[q + N - a] -= sq * Jq[q];
+  }
+}
+
 // Assembly of -lambda^2 K (element-chunked, see Chunk): row r of the band is
 // written once, by the wavefront owning node r.
 constexpr int CWF = 1;  // chunk wavefronts of the assembly kernel
 
-template <int N>
+template <int N, bool S3 = false>
 __device__ __forceinline__ void b_factor_assemble(int64_t tile_, HeviShapeDev sh,
                                                   Gll<N> tab, double lambda,
                                                   const double* __restrict__ ops,
@@ -378,24 +437,30 @@ __device__ __forceinline__ void b_factor_assemble(int64_t tile_, HeviShapeDev sh
   if (ch.e0 >= ch.e1) return;
   const int lane = ch.lane;
   const int64_t tile = ch.tile;
-  OpsView op{ops, tile, nz, lane};
+  OpsView op{ops, tile, nz, lane, S3 ? pr_plane(ops, sh) : nullptr};
   const double l2 = lambda * lambda;
   double carry[W];
 #pragma unroll
   for (int o = 0; o < W; ++o) carry[o] = 0.0;
   for (int e = max(ch.e0 - 1, 0); e < ch.e1; ++e) {
     double Jth[NC], mi[N + 1], gx[N + 1], gy[N + 1], gz[N + 1], jc[N + 1], jn[N + 1], ph[N + 1];
+    double Jq[NC], jp[N + 1];
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
       const int k = (e - 1) * N + q;
       const double v = op(min(max(k, 0), nz - 1), OP_JTH);
       Jth[q] = (k >= 0 && k < nz) ? v : 0.0;
+      if constexpr (S3) {
+        const double vj = op(min(max(k, 0), nz - 1), OP_J);
+        Jq[q] = (k >= 0 && k < nz) ? vj : 0.0;
+      }
     }
 #pragma unroll
     for (int i = 0; i <= N; ++i) {
       const int k = e * N + i;
       mi[i] = op(k, OP_MINV); gx[i] = op(k, OP_GX); gy[i] = op(k, OP_GY); gz[i] = op(k, OP_GZ);
       jc[i] = op(k, OP_JCT); jn[i] = op(k, OP_J); ph[i] = op(k, OP_PHI);
+      if constexpr (S3) jp[i] = op.jpr(k);
     }
 #pragma unroll
     for (int a = 0; a <= N; ++a) {
@@ -403,6 +468,7 @@ __device__ __forceinline__ void b_factor_assemble(int64_t tile_, HeviShapeDev sh
       const int r = e * N + a;
       double acc[W];
       k_row<N>(tab, a, e > 0, e < Ne - 1, Jth, mi, gx, gy, gz, jc, jn, ph, acc);
+      if constexpr (S3) k_row_pr<N>(tab, a, e > 0, e < Ne - 1, Jq, mi, gx, gy, gz, jp, acc);
       if (a == 0) {
 #pragma unroll
         for (int o = 0; o < W; ++o) acc[o] += carry[o];
@@ -652,7 +718,7 @@ constexpr int fused_lds_doubles(int lpc) {
   return (N + 1) * ((4 * N + lpc) / lpc) * 64;
 }
 
-template <int N, typename FT, int LPC>
+template <int N, typename FT, int LPC, bool S3 = false>
 __device__ __forceinline__ void b_factor_fused_split(int64_t tile, int part, HeviShapeDev sh,
                                                      Gll<N> tab, double lambda,
                                                      const double* __restrict__ ops,
@@ -666,7 +732,7 @@ __device__ __forceinline__ void b_factor_fused_split(int64_t tile, int part, Hev
   const bool valid = c < sh.ncols;
   const int nz = sh.nz, Ne = sh.Ne;
   const int s0 = h * H;
-  const OpsView op{ops, tile, nz, lane};
+  const OpsView op{ops, tile, nz, lane, S3 ? pr_plane(ops, sh) : nullptr};
   const double l2 = lambda * lambda;
   const size_t plane = plane_size(sh);
   double* slot = lds + threadIdx.x;  // row a, window column m of this lane: slot[(a * H + m) * T]
@@ -681,14 +747,23 @@ __device__ __forceinline__ void b_factor_fused_split(int64_t tile, int part, Hev
     const double v = op(min(max(k, 0), nz - 1), OP_JTH);
     return (k >= 0 && k < nz) ? v : 0.0;
   };
+  auto j_at = [&](int k) {
+    const double v = op(min(max(k, 0), nz - 1), OP_J);
+    return (k >= 0 && k < nz) ? v : 0.0;
+  };
   double jth[NC], mi[N + 1], gx[N + 1], gy[N + 1], gz[N + 1], jc[N + 1], jn[N + 1], ph[N + 1];
+  double jq[NC], jp[N + 1];  // set 3C: J at the nodes of jth, J dP/drho
 #pragma unroll
-  for (int q = 0; q < NC; ++q) jth[q] = jth_at(q - N);
+  for (int q = 0; q < NC; ++q) {
+    jth[q] = jth_at(q - N);
+    if constexpr (S3) jq[q] = j_at(q - N);
+  }
 #pragma unroll
   for (int i = 0; i <= N; ++i) {
     const int k = min(i, nz - 1);
     mi[i] = op(k, OP_MINV); gx[i] = op(k, OP_GX); gy[i] = op(k, OP_GY); gz[i] = op(k, OP_GZ);
     jc[i] = op(k, OP_JCT); jn[i] = op(k, OP_J); ph[i] = op(k, OP_PHI);
+    if constexpr (S3) jp[i] = op.jpr(k);
   }
   double carry[H];  // this lane's part of row N of the previous element
 #pragma unroll
@@ -703,6 +778,7 @@ __device__ __forceinline__ void b_factor_fused_split(int64_t tile, int part, Hev
 #pragma clang fp contract(off)
       double acc[W];
       k_row<N>(tab, a, e > 0, e < Ne - 1, jth, mi, gx, gy, gz, jc, jn, ph, acc);
+      if constexpr (S3) k_row_pr<N>(tab, a, e > 0, e < Ne - 1, jq, mi, gx, gy, gz, jp, acc);
       double x[H];
 #pragma unroll
       for (int m = 0; m < H; ++m) {
@@ -723,13 +799,17 @@ __device__ __forceinline__ void b_factor_fused_split(int64_t tile, int part, Hev
       }
     }
     // the next element's new operator fields, in flight while the rows enter
-    double pj[N], pmi[N], pgx[N], pgy[N], pgz[N], pjc[N], pjn[N], pph[N];
+    double pj[N], pmi[N], pgx[N], pgy[N], pgz[N], pjc[N], pjn[N], pph[N], pjq[N], pjp[N];
 #pragma unroll
     for (int t = 0; t < N; ++t) {
       pj[t] = jth_at((e + 2) * N + 1 + t);
       const int k = min((e + 1) * N + 1 + t, nz - 1);
       pmi[t] = op(k, OP_MINV); pgx[t] = op(k, OP_GX); pgy[t] = op(k, OP_GY);
       pgz[t] = op(k, OP_GZ); pjc[t] = op(k, OP_JCT); pjn[t] = op(k, OP_J); pph[t] = op(k, OP_PHI);
+      if constexpr (S3) {
+        pjq[t] = j_at((e + 2) * N + 1 + t);
+        pjp[t] = op.jpr(k);
+      }
     }
     const int na = e == Ne - 1 ? N + 1 : N;
 #pragma unroll
@@ -752,6 +832,16 @@ __device__ __forceinline__ void b_factor_fused_split(int64_t tile, int part, Hev
     for (int t = 0; t < N; ++t) {
       mi[1 + t] = pmi[t]; gx[1 + t] = pgx[t]; gy[1 + t] = pgy[t]; gz[1 + t] = pgz[t];
       jc[1 + t] = pjc[t]; jn[1 + t] = pjn[t]; ph[1 + t] = pph[t];
+    }
+    if constexpr (S3) {
+#pragma unroll
+      for (int q = 0; q <= B; ++q) jq[q] = jq[q + N];
+      jp[0] = jp[N];
+#pragma unroll
+      for (int t = 0; t < N; ++t) {
+        jq[B + 1 + t] = pjq[t];
+        jp[1 + t] = pjp[t];
+      }
     }
   }
   // rows past the top are zero
@@ -903,7 +993,7 @@ __device__ __forceinline__ void band_solve(const FT* __restrict__ Ub, const FT* 
 // correction is small, ||delta|| <= target ||u|| (a residual test would stop
 // early: ||u_err|| can exceed ||d|| / ||r|| by the condition number of S), or
 // max_sweeps.  Per column; the wavefront sweeps while any column needs one.
-template <int N, typename FT>
+template <int N, typename FT, bool S3 = false>
 __device__ void reduced_refine(Gll<N> tab, const OpsView& op, int Ne, double* ws,
                                int64_t tile, int lane, bool valid, double lambda,
                                const FT* __restrict__ Ub, const FT* __restrict__ Lb,
@@ -916,7 +1006,7 @@ __device__ void reduced_refine(Gll<N> tab, const OpsView& op, int Ne, double* ws
     const bool need = !(corr <= rel_target) && sweeps < max_sweeps;
     if (!__any(valid && need)) break;
     div_pass<N>(tab, op, Ne, ws, tile, lane, WS_U, WS_VR, WS_VT);
-    pg_pass<N>(tab, op, Ne, ws, tile, lane, WS_VR, WS_VT, WS_T);
+    pg_pass<N, S3>(tab, op, Ne, ws, tile, lane, WS_VR, WS_VT, WS_T);
     const double l2 = lambda * lambda;
     for (int k = 0; k < nz; ++k) {
       const double u = ws[tix(tile, nz, k, HEVI_NWS, WS_U, lane)];
@@ -945,7 +1035,7 @@ __device__ void reduced_refine(Gll<N> tab, const OpsView& op, int Ne, double* ws
 
 // Reduced right-hand side r = grad(zeta).(b_U + lambda (PG b_Theta - Phi' grad(zeta) b_rho))
 // of a 5-field vector b stored in scratch fields fb..fb+4 (zero at the lid nodes).
-template <int N>
+template <int N, bool S3 = false>
 __device__ double reduced_rhs_pass(Gll<N> tab, const OpsView& op, int Ne, double* ws,
                                    int64_t tile, int lane, double lambda, int fb) {
   const int nz = op.nz;
@@ -955,7 +1045,8 @@ __device__ double reduced_rhs_pass(Gll<N> tab, const OpsView& op, int Ne, double
 #pragma unroll
     for (int j = 0; j <= N; ++j) {
       const int k = e * N + j;
-      const double p = op(k, OP_JCT) * ws[tix(tile, nz, k, HEVI_NWS, fb + 4, lane)];
+      double p = op(k, OP_JCT) * ws[tix(tile, nz, k, HEVI_NWS, fb + 4, lane)];
+      if constexpr (S3) p += op.jpr(k) * ws[tix(tile, nz, k, HEVI_NWS, fb + 0, lane)];
       f0[j] = p * op(k, OP_GX); f1[j] = p * op(k, OP_GY); f2[j] = p * op(k, OP_GZ);
     }
 #pragma unroll
@@ -994,7 +1085,7 @@ __device__ double reduced_rhs_pass(Gll<N> tab, const OpsView& op, int Ne, double
 // d_Th = b_Th + lambda DTh u, d_U = b_U + lambda (PG d_Th - Phi' grad(zeta) d_rho)
 // (interior), d_U = P(b_U) at the lid (P removes the normal component).
 // Writes d into fields fx.. or adds it to them (accumulate).
-template <int N>
+template <int N, bool S3 = false>
 __device__ void recover_pass(Gll<N> tab, const OpsView& op, int Ne, double* ws,
                              int64_t tile, int lane, double lambda, int fb, int fx,
                              bool accumulate) {
@@ -1008,7 +1099,8 @@ __device__ void recover_pass(Gll<N> tab, const OpsView& op, int Ne, double* ws,
     for (int j = 0; j <= N; ++j) {
       const int k = e * N + j;
       const double dth = W(k, fb + 4) + lambda * W(k, WS_VT);
-      const double p = op(k, OP_JCT) * dth;
+      double p = op(k, OP_JCT) * dth;
+      if constexpr (S3) p += op.jpr(k) * (W(k, fb + 0) + lambda * W(k, WS_VR));
       f0[j] = p * op(k, OP_GX); f1[j] = p * op(k, OP_GY); f2[j] = p * op(k, OP_GZ);
     }
 #pragma unroll
@@ -1057,7 +1149,7 @@ __device__ void recover_pass(Gll<N> tab, const OpsView& op, int Ne, double* ws,
 // Full-system residual s = P(b) - A x = P(b) - x + lambda L_z x in FP64 for the
 // vectors b (fields fb..) and x (fields fx..); rigid-lid momentum rows of A are
 // identity rows, so there s_U = P(b_U) - x_U.  Writes fields fs..
-template <int N>
+template <int N, bool S3 = false>
 __device__ void residual_pass(Gll<N> tab, const OpsView& op, int Ne, double* ws,
                               int64_t tile, int lane, double lambda, int fb, int fx, int fs) {
   const int nz = op.nz;
@@ -1072,7 +1164,8 @@ __device__ void residual_pass(Gll<N> tab, const OpsView& op, int Ne, double* ws,
       const double u = gx * W(k, fx + 1) + gy * W(k, fx + 2) + gzz * W(k, fx + 3);
       Ju[j] = op(k, OP_J) * u;
       Jtu[j] = op(k, OP_JTH) * u;
-      const double p = op(k, OP_JCT) * W(k, fx + 4);
+      double p = op(k, OP_JCT) * W(k, fx + 4);
+      if constexpr (S3) p += op.jpr(k) * W(k, fx + 0);
       f0[j] = p * gx; f1[j] = p * gy; f2[j] = p * gzz;
     }
 #pragma unroll
@@ -1114,7 +1207,7 @@ __device__ void residual_pass(Gll<N> tab, const OpsView& op, int Ne, double* ws,
 
 // Stage solve with full-system FP64 iterative refinement (accuracy mode,
 // hevi_refine.full_sweeps > 0), one lane per column, every field in scratch.
-template <int N, typename FT>
+template <int N, typename FT, bool S3 = false>
 __device__ __forceinline__ void b_stage_solve(int64_t tile_, HeviShapeDev sh, Gll<N> tab,
                                               double lambda, const double* __restrict__ ops,
                                               const FT* __restrict__ Ub, const FT* __restrict__ Lb,
@@ -1130,7 +1223,7 @@ __device__ __forceinline__ void b_stage_solve(int64_t tile_, HeviShapeDev sh, Gl
   const int64_t cc = valid ? c : sh.ncols - 1;
   const int nz = sh.nz, Ne = sh.Ne;
   const int64_t nc = sh.ncols;
-  OpsView op{ops, tile, nz, lane};
+  OpsView op{ops, tile, nz, lane, S3 ? pr_plane(ops, sh) : nullptr};
   bool nonfinite = false;
 
   // ---- pass 1: q^E, q^ = q^E + sum c_j Q_j, reduced right-hand side r ----
@@ -1167,7 +1260,8 @@ __device__ __forceinline__ void b_stage_solve(int64_t tile_, HeviShapeDev sh, Gl
 #pragma unroll
     for (int j = 0; j <= N; ++j) {
       const int k = e * N + j;
-      const double p = op(k, OP_JCT) * b[j][4];
+      double p = op(k, OP_JCT) * b[j][4];
+      if constexpr (S3) p += op.jpr(k) * b[j][0];
       f0[j] = p * op(k, OP_GX); f1[j] = p * op(k, OP_GY); f2[j] = p * op(k, OP_GZ);
     }
 #pragma unroll
@@ -1207,27 +1301,27 @@ __device__ __forceinline__ void b_stage_solve(int64_t tile_, HeviShapeDev sh, Gl
   int sweeps = 0;
   double relres = 0.0;
   if (max_sweeps > 0)
-    reduced_refine<N, FT>(tab, op, Ne, ws, tile, lane, valid, lambda, Ub, Lb, piv,
-                          plane_size(sh), max_sweeps,
-                          rel_target, &sweeps, &relres);
+    reduced_refine<N, FT, S3>(tab, op, Ne, ws, tile, lane, valid, lambda, Ub, Lb, piv,
+                              plane_size(sh), max_sweeps,
+                              rel_target, &sweeps, &relres);
 
   {
     // ---- full-system FP64 iterative refinement on x = q_tt (offset-free) ----
-    recover_pass<N>(tab, op, Ne, ws, tile, lane, lambda, WS_B, WS_X, false);
+    recover_pass<N, S3>(tab, op, Ne, ws, tile, lane, lambda, WS_B, WS_X, false);
     for (int it = 0; it < full_sweeps; ++it) {
-      residual_pass<N>(tab, op, Ne, ws, tile, lane, lambda, WS_B, WS_X, WS_S);
-      reduced_rhs_pass<N>(tab, op, Ne, ws, tile, lane, lambda, WS_S);
+      residual_pass<N, S3>(tab, op, Ne, ws, tile, lane, lambda, WS_B, WS_X, WS_S);
+      reduced_rhs_pass<N, S3>(tab, op, Ne, ws, tile, lane, lambda, WS_S);
       band_solve<N, FT>(Ub, Lb, piv, plane_size(sh), ws, tile, nz, lane, WS_R, WS_U);
       if (max_sweeps > 0) {
         // the correction only needs the accuracy of the outer sweep
         int sw = 0;
         double cr = 0.0;
-        reduced_refine<N, FT>(tab, op, Ne, ws, tile, lane, valid, lambda, Ub, Lb, piv,
-                              plane_size(sh), 1,
-                              rel_target, &sw, &cr);
+        reduced_refine<N, FT, S3>(tab, op, Ne, ws, tile, lane, valid, lambda, Ub, Lb, piv,
+                                  plane_size(sh), 1,
+                                  rel_target, &sw, &cr);
         sweeps += sw;
       }
-      recover_pass<N>(tab, op, Ne, ws, tile, lane, lambda, WS_S, WS_X, true);
+      recover_pass<N, S3>(tab, op, Ne, ws, tile, lane, lambda, WS_S, WS_X, true);
     }
     // Q_i = q_tt - sum_j c_j Q_j = q^E + x - q^
     if (valid) {
@@ -1324,7 +1418,7 @@ __device__ __forceinline__ void pg_tangent(Gll<N> tab, int a, const double (&p)[
 // Q_i <- (q^E_rho, q^E_U - n (n . q^_U) + lambda (PG q^_Theta)_t [interior], q^E_Theta)
 // with n = grad(zeta)/|grad(zeta)| and ( )_t the tangential part (see pg_tangent).
 // The term loop is outermost so that each term issues (N+1)*5 independent loads.
-template <int N, bool LDSRU, bool TILT>
+template <int N, bool LDSRU, bool TILT, bool S3 = false>
 __device__ __forceinline__ void b_stage_rhs(int64_t tile_, HeviShapeDev sh, Gll<N> tab,
                                             double lambda, const double* __restrict__ ops,
                                             double* __restrict__ ws, const HeviTerms& E,
@@ -1339,7 +1433,7 @@ __device__ __forceinline__ void b_stage_rhs(int64_t tile_, HeviShapeDev sh, Gll<
   const bool valid = c < sh.ncols;
   const int64_t cc = valid ? c : sh.ncols - 1;
   const int64_t nc = sh.ncols;
-  OpsView op{ops, tile, nz, lane};
+  OpsView op{ops, tile, nz, lane, S3 ? pr_plane(ops, sh) : nullptr};
   if (ch.e0 == 0) ws[tix(tile, nz, 0, HEVI_NWS, WS_T, lane)] = 0.0;  // per-column flag
   double c0 = 0.0, c1 = 0.0, c2 = 0.0, d0 = 0.0, d1 = 0.0, d2 = 0.0;
   // node eN is shared by elements e-1 and e: its sums and operator values are
@@ -1401,6 +1495,7 @@ __device__ __forceinline__ void b_stage_rhs(int64_t tile_, HeviShapeDev sh, Gll<
       g0[j] = op(k, OP_GX); g1[j] = op(k, OP_GY); g2[j] = op(k, OP_GZ);
       mi[j] = op(k, OP_MINV); ph[j] = op(k, OP_PHI);
       pt[j] = op(k, OP_JCT) * b[j][4];
+      if constexpr (S3) pt[j] += op.jpr(k) * b[j][0];
     }
     // TILT: some column's grad(zeta) varies; elsewhere every tangential term is zero
     const bool straight = !TILT || wave_straight<N>(g0, g1, g2);
@@ -1467,7 +1562,7 @@ __device__ __forceinline__ void b_stage_rhs(int64_t tile_, HeviShapeDev sh, Gll<
 }
 
 // pass 2: S u = r, one lane per column (+ reduced FP64 refinement for FP32 factors)
-template <int N, typename FT, bool REFINE>
+template <int N, typename FT, bool REFINE, bool S3 = false>
 __device__ __forceinline__ void b_stage_bsolve(int64_t tile_, HeviShapeDev sh, Gll<N> tab,
                                                double lambda, const double* __restrict__ ops,
                                                const FT* __restrict__ Ub, const FT* __restrict__ Lb,
@@ -1481,12 +1576,12 @@ __device__ __forceinline__ void b_stage_bsolve(int64_t tile_, HeviShapeDev sh, G
   const int nz = sh.nz;
   band_solve<N, FT>(Ub, Lb, piv, plane_size(sh), ws, tile, nz, lane, WS_R, WS_U);
   if (REFINE && max_sweeps > 0) {
-    OpsView op{ops, tile, nz, lane};
+    OpsView op{ops, tile, nz, lane, S3 ? pr_plane(ops, sh) : nullptr};
     int sweeps = 0;
     double corr = 0.0;
-    reduced_refine<N, FT>(tab, op, sh.Ne, ws, tile, lane, valid, lambda, Ub, Lb, piv,
-                          plane_size(sh), max_sweeps,
-                          rel_target, &sweeps, &corr);
+    reduced_refine<N, FT, S3>(tab, op, sh.Ne, ws, tile, lane, valid, lambda, Ub, Lb, piv,
+                              plane_size(sh), max_sweeps,
+                              rel_target, &sweeps, &corr);
     if (valid) {
       if (!(corr <= rel_target)) flag(info, 6 /*HEVI_E_NOT_CONVERGED*/, c);
       atomicMax(&info->max_sweeps, sweeps);
@@ -1501,7 +1596,7 @@ __device__ __forceinline__ void b_stage_bsolve(int64_t tile_, HeviShapeDev sh, G
 // grad(zeta) u / |grad(zeta)|^2 [interior], lambda v_Th), ( )_t the tangential part.
 // An element needs u on its neighbours too (the DSS of Drho u, DTh u at its end
 // nodes), so each iteration loads u and the operator on nodes (e-1)N .. (e+2)N.
-template <int N, bool LDSRU, bool TILT>
+template <int N, bool LDSRU, bool TILT, bool S3 = false>
 __device__ __forceinline__ void b_stage_update(int64_t tile_, HeviShapeDev sh, Gll<N> tab,
                                                double lambda, const double* __restrict__ ops,
                                                double* __restrict__ ws, double* __restrict__ Qi,
@@ -1517,14 +1612,14 @@ __device__ __forceinline__ void b_stage_update(int64_t tile_, HeviShapeDev sh, G
   const bool valid = c < sh.ncols;
   const int64_t cc = valid ? c : sh.ncols - 1;
   const int64_t nc = sh.ncols;
-  OpsView op{ops, tile, nz, lane};
+  OpsView op{ops, tile, nz, lane, S3 ? pr_plane(ops, sh) : nullptr};
   const double l2 = lambda * lambda;
   bool nonfinite = false;
   double c0 = 0.0, c1 = 0.0, c2 = 0.0;
   // consecutive elements share nodes eN .. (e+2)N of the u window and node eN of
   // the operator and Q_i: those values are carried over instead of loaded again
   double kJu[2 * N + 1], kJtu[2 * N + 1], kq[5];
-  double kg0 = 0.0, kg1 = 0.0, kg2 = 0.0, kmi = 0.0, kjc = 0.0;
+  double kg0 = 0.0, kg1 = 0.0, kg2 = 0.0, kmi = 0.0, kjc = 0.0, kjp = 0.0;
   auto element = [&](const int e, auto first) {
     constexpr bool FIRST = decltype(first)::value;
     // ---- loads: u, J, J theta0 on nodes (e-1)N .. (e+2)N; operator and Q_i on the element
@@ -1543,11 +1638,11 @@ __device__ __forceinline__ void b_stage_update(int64_t tile_, HeviShapeDev sh, G
       Ju[q] = in * op(kk, OP_J) * u;
       Jtu[q] = in * op(kk, OP_JTH) * u;
     }
-    double g0[N + 1], g1[N + 1], g2[N + 1], mi[N + 1], jc[N + 1], q[N + 1][5];
+    double g0[N + 1], g1[N + 1], g2[N + 1], mi[N + 1], jc[N + 1], jp[N + 1], q[N + 1][5];
 #pragma unroll
     for (int j = 0; j <= N; ++j) {
       if (!FIRST && j == 0) {
-        g0[0] = kg0; g1[0] = kg1; g2[0] = kg2; mi[0] = kmi; jc[0] = kjc;
+        g0[0] = kg0; g1[0] = kg1; g2[0] = kg2; mi[0] = kmi; jc[0] = kjc; jp[0] = kjp;
 #pragma unroll
         for (int v = 0; v < 5; ++v) q[0][v] = kq[v];
         continue;
@@ -1555,13 +1650,14 @@ __device__ __forceinline__ void b_stage_update(int64_t tile_, HeviShapeDev sh, G
       const int k = e * N + j;
       g0[j] = op(k, OP_GX); g1[j] = op(k, OP_GY); g2[j] = op(k, OP_GZ);
       mi[j] = op(k, OP_MINV); jc[j] = op(k, OP_JCT);
+      jp[j] = S3 ? op.jpr(k) : 0.0;
 #pragma unroll
       for (int v = 0; v < 5; ++v) q[j][v] = ldn(Qi + cix(nz, nc, v, k, cc));
     }
     // node N as loaded (before this element's update) is node 0 of the next
 #pragma unroll
     for (int v = 0; v < 5; ++v) kq[v] = q[N][v];
-    kg0 = g0[N]; kg1 = g1[N]; kg2 = g2[N]; kmi = mi[N]; kjc = jc[N];
+    kg0 = g0[N]; kg1 = g1[N]; kg2 = g2[N]; kmi = mi[N]; kjc = jc[N]; kjp = jp[N];
 #pragma unroll
     for (int t = 0; t <= 2 * N; ++t) { kJu[t] = Ju[N + t]; kJtu[t] = Jtu[N + t]; }
     // ---- v_rho, v_Th at the element's nodes (contributions of elements e-1, e, e+1)
@@ -1596,6 +1692,7 @@ __device__ __forceinline__ void b_stage_update(int64_t tile_, HeviShapeDev sh, G
       vr[j] = mi[j] * sr[j];
       vt[j] = -mi[j] * st[j];
       pt[j] = jc[j] * vt[j];
+      if constexpr (S3) pt[j] += jp[j] * vr[j];
     }
     // ---- stage update: rho and Theta; momentum = the tangential part of
     // lambda^2 PG v_Th plus the normal part grad(zeta) u / |grad(zeta)|^2 (see

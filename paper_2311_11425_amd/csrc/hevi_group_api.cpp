@@ -167,14 +167,14 @@ hipError_t phase(hevi_group* g, int ph, int slot, hipStream_t st) {
       const HeviCallDev* C = slot >= 0 ? &g->calls[(size_t)slot * g->n + p] : nullptr;
       switch (ph) {
         case HEVI_PH_APPLY:
-          e = hevi_launch_apply(P.sh, P.ops, C->x, C->xref, C->out, st);
+          e = hevi_launch_apply(P.sh, 0, P.ops, C->x, C->xref, C->out, st);
           break;
         case HEVI_PH_FACTOR_ASSEMBLE:
-          e = hevi_launch_factor(P.sh, P.lambda, fp32, P.ops, P.sbuf, P.U, P.L, P.piv,
+          e = hevi_launch_factor(P.sh, 0, P.lambda, fp32, P.ops, P.sbuf, P.U, P.L, P.piv,
                                  P.info, st);
           break;
         case HEVI_PH_STAGE_RHS:
-          e = hevi_launch_stage_solve(P.sh, P.lambda, P.tilt, fp32, P.ops, P.U, P.L, P.piv, P.ws,
+          e = hevi_launch_stage_solve(P.sh, 0, P.lambda, P.tilt, fp32, P.ops, P.U, P.L, P.piv, P.ws,
                                       C->E, C->Q, C->out, fp32 ? g->sweeps : 0, g->target, 0,
                                       P.info, st);
           break;
@@ -264,6 +264,7 @@ hevi_status hevi_group_create(hevi_ctx* ctx, int32_t n, const hevi_group_member*
   for (int p = 0; p < n; ++p) {
     const hevi_group_member& m = members[p];
     if (!m.ops || m.ops->ctx->device != ctx->device) return HEVI_E_INVALID;
+    if (m.ops->s3) return HEVI_E_INVALID;  // the group kernels are set-2C instances
     if (m.ops->sh.ncols == 0) continue;
     std::vector<const void*> outs{m.d_out};
     for (int i = 1; i < s; ++i) outs.push_back(m.d_Q[i]);

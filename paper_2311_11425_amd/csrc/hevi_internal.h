@@ -37,29 +37,44 @@ struct HeviShapeDev {
 
 // *tilted becomes nonzero if grad(zeta) is not the same vector (bitwise) at every
 // node of some column: the stage solves then need the tangential part of the
-// pressure gradient (the TILT kernels)
-hipError_t hevi_launch_build_ops(const HeviShapeDev& sh, double R, double cp,
+// pressure gradient (the TILT kernels).  s3: set 3C (Th0 holds the total energy
+// E0; ops then has room for the extra J dP/drho plane, HEVI_NOPS + 1 fields per node).
+hipError_t hevi_launch_build_ops(const HeviShapeDev& sh, int s3, double R, double cp,
                                  double g, double pA, const double* z, const double* J,
                                  const double* gz, const double* rho0, const double* Th0,
                                  double* ops, HeviDevInfo* info, int32_t* tilted,
                                  hipStream_t st);
 
-hipError_t hevi_launch_apply(const HeviShapeDev& sh, const double* ops,
+// s3: the operator is of set 3C (instances in hevi_kernels3c.hip)
+hipError_t hevi_launch_apply(const HeviShapeDev& sh, int s3, const double* ops,
                              const double* x, const double* xref, double* y, hipStream_t st);
 
 // fp32 != 0 selects FP32 factor storage.  sbuf: FP64 assembly buffer of
 // (4N+1) entries per node (may alias Ub when FP64).
-hipError_t hevi_launch_factor(const HeviShapeDev& sh, double lambda, int fp32,
+hipError_t hevi_launch_factor(const HeviShapeDev& sh, int s3, double lambda, int fp32,
                               const double* ops, double* sbuf, void* Ub, void* Lb, uint8_t* piv,
                               HeviDevInfo* info, hipStream_t st);
 
 // tilt: the operator's columns are not all straight (see hevi_launch_build_ops)
-hipError_t hevi_launch_stage_solve(const HeviShapeDev& sh, double lambda, int tilt,
+hipError_t hevi_launch_stage_solve(const HeviShapeDev& sh, int s3, double lambda, int tilt,
                                    int fp32, const double* ops, const void* Ub, const void* Lb,
                                    const uint8_t* piv, double* ws, const HeviTerms& E,
                                    const HeviTerms& Q, double* Qi, int max_sweeps,
                                    double rel_target, int full_sweeps, HeviDevInfo* info,
                                    hipStream_t st);
+
+// the set-3C instances (hevi_kernels3c.hip)
+hipError_t hevi_launch_apply_3c(const HeviShapeDev& sh, const double* ops, const double* x,
+                                const double* xref, double* y, hipStream_t st);
+hipError_t hevi_launch_factor_3c(const HeviShapeDev& sh, double lambda, int fp32,
+                                 const double* ops, double* sbuf, void* Ub, void* Lb,
+                                 uint8_t* piv, HeviDevInfo* info, hipStream_t st);
+hipError_t hevi_launch_stage_solve_3c(const HeviShapeDev& sh, double lambda, int tilt, int fp32,
+                                      const double* ops, const void* Ub, const void* Lb,
+                                      const uint8_t* piv, double* ws, const HeviTerms& E,
+                                      const HeviTerms& Q, double* Qi, int max_sweeps,
+                                      double rel_target, int full_sweeps, HeviDevInfo* info,
+                                      hipStream_t st);
 
 hipError_t hevi_launch_combine(int64_t n, const HeviTerms& V, double* out, hipStream_t st);
 

@@ -1,12 +1,19 @@
-// hevi_kernels.hip -- single-problem gfx950 kernels of the batched LHEVI column
-// solver (one workgroup = one wavefront = one 64-column tile) and their launchers.
-// The per-tile bodies and the method are described in hevi_device.h.
-#include "hevi_device.h"
+// hevi_kernels.hip -- launchers of the single-problem gfx950 kernels of the
+// batched LHEVI column solver: the operator build, the set-2C instances of the
+// kernels of hevi_kernels_impl.h (set 3C: hevi_kernels3c.hip), the linear
+// combination and the report reset.  The per-tile bodies and the method are
+// described in hevi_device.h.
+#include "hevi_kernels_impl.h"
 
 namespace {
 
 // ---------------------------------------------------------------------------
-// a1: compact per-node operator
+// a1: compact per-node operator.  Set 2C (s3 == 0): Th0 is Theta0, the flux
+// coefficient theta0 = Theta0/rho0 and c_Theta = dP/dTheta from P = P_A (R Theta /
+// P_A)^gamma (Appendix A.1, eq. set2c_pressure).  Set 3C: Th0 is the total energy
+// E0; at rest P0 = (gamma-1)(E0 - rho0 Phi), Phi = g z (eq. set3c_pressure), the
+// flux coefficient is (E0 + P0)/rho0, dP/dE = gamma - 1 and the extra plane
+// holds J dP/drho = -J (gamma-1) Phi (eq. set3c_jacobian at U = 0).
 template <int N>
 __global__ __launch_bounds__(64) void k_build_ops(HeviShapeDev sh, double R, double cp, double g,
                                                   double pA, const double* __restrict__ z,
@@ -15,7 +22,7 @@ __global__ __launch_bounds__(64) void k_build_ops(HeviShapeDev sh, double R, dou
                                                   const double* __restrict__ rho0,
                                                   const double* __restrict__ Th0,
                                                   double* __restrict__ ops, HeviDevInfo* info,
-                                                  int32_t* tilted) {
+                                                  int32_t* tilted, int s3) {
   const Gll<N> tab{};
   const int lane = threadIdx.x;
   const int64_t tile = blockIdx.x;
@@ -60,12 +67,22 @@ __global__ __launch_bounds__(64) void k_build_ops(HeviShapeDev sh, double R, dou
       M += tab.w[ii] * Jk;
       Gn += tab.w[ii] * Jk * g * dz;
     }
-    const double P0 = pA * pow(R * T0 / pA, gam);
-    const double th0 = T0 / r0;
-    const double cT = gam * P0 / T0;
+    double th0, cT, P0;
+    if (s3) {
+      const double phi = g * z[(size_t)k * nc + cc];
+      P0 = (gam - 1.0) * (T0 - r0 * phi);
+      th0 = (T0 + P0) / r0;
+      cT = gam - 1.0;
+      ops[pr_offset(sh) + ((size_t)tile * nz + k) * T + lane] = -Jk * cT * phi;
+    } else {
+      P0 = pA * pow(R * T0 / pA, gam);
+      th0 = T0 / r0;
+      cT = gam * P0 / T0;
+    }
     const double gg = g0 * g0 + g1 * g1 + g2 * g2;
-    bad |= !(Jk > 0.0) || !(r0 > 0.0) || !(T0 > 0.0) || !(gg > 0.0) || !isfinite(Jk) ||
-           !isfinite(r0) || !isfinite(T0) || !isfinite(gg) || !isfinite(Gn) || !isfinite(cT);
+    bad |= !(Jk > 0.0) || !(r0 > 0.0) || !(T0 > 0.0) || !(P0 > 0.0) || !(gg > 0.0) ||
+           !isfinite(Jk) || !isfinite(r0) || !isfinite(T0) || !isfinite(gg) || !isfinite(Gn) ||
+           !isfinite(cT) || !isfinite(th0);
     double* o = ops + tix(tile, nz, k, HEVI_NOPS, 0, lane);
     o[OP_MINV * T] = 1.0 / M;
     o[OP_J * T] = Jk;
@@ -78,115 +95,6 @@ __global__ __launch_bounds__(64) void k_build_ops(HeviShapeDev sh, double R, dou
   }
   if (bad && valid) flag(info, 1 /*HEVI_E_INVALID*/, c);
   if (__any(bent && valid) && lane == 0) atomicOr(tilted, 1);
-}
-
-// ---------------------------------------------------------------------------
-// Single-problem kernels: tile = blockIdx.x
-
-// Streaming kernels take blocks of cw wavefronts (element chunks of one tile,
-// cw <= kMaxChunks; see chunks_for).
-// CHUNKED instances take the chunk count at run time (a kernel with cw fixed at 1
-// keeps the element bounds as constants and needs fewer registers).
-template <int N, bool HAS_REF, bool CHUNKED>
-__global__ __launch_bounds__(CHUNKED ? 64 * kMaxChunks : 64, kStreamWaves<N>) void k_apply(
-    HeviShapeDev sh, const double* __restrict__ ops, const double* __restrict__ x,
-    const double* __restrict__ xref, double* __restrict__ y, int cw) {
-  b_apply<N, HAS_REF>((int64_t)blockIdx.x, sh, Gll<N>{}, ops, x, xref, y, CHUNKED ? cw : 1);
-}
-
-template <int N>
-__global__ __launch_bounds__(64) void k_factor_assemble(HeviShapeDev sh, double lambda,
-                                                        const double* __restrict__ ops,
-                                                        double* __restrict__ sbuf) {
-  b_factor_assemble<N>((int64_t)blockIdx.x, sh, Gll<N>{}, lambda, ops, sbuf);
-}
-
-template <int N, typename FT>
-__global__ __launch_bounds__(64) void k_factor_lu_split(HeviShapeDev sh, const double* sbuf,
-                                                        FT* Ub, FT* __restrict__ Lb,
-                                                        uint8_t* __restrict__ piv,
-                                                        HeviDevInfo* info) {
-  b_factor_lu_split<N, FT, kSplitLanes<N>>((int64_t)(blockIdx.x / kSplitLanes<N>),
-                                           (int)(blockIdx.x % kSplitLanes<N>), sh, sbuf, Ub, Lb,
-                                           piv, info);
-}
-
-template <int N, typename FT>
-__global__ __launch_bounds__(64) void k_factor_fused(HeviShapeDev sh, double lambda,
-                                                     const double* __restrict__ ops,
-                                                     FT* __restrict__ Ub, FT* __restrict__ Lb,
-                                                     uint8_t* __restrict__ piv,
-                                                     HeviDevInfo* info) {
-  constexpr int LPC = kSplitLanes<N>;
-  __shared__ double lds[fused_lds_doubles<N>(LPC)];
-  b_factor_fused_split<N, FT, LPC>((int64_t)(blockIdx.x / LPC), (int)(blockIdx.x % LPC), sh,
-                                   Gll<N>{}, lambda, ops, Ub, Lb, piv, info, lds);
-}
-
-template <int N, typename FT>
-__global__ __launch_bounds__(64) void k_stage_solve(HeviShapeDev sh, double lambda,
-                                                    const double* __restrict__ ops,
-                                                    const FT* __restrict__ Ub,
-                                                    const FT* __restrict__ Lb,
-                                                    const uint8_t* __restrict__ piv,
-                                                    double* __restrict__ ws, HeviTerms E,
-                                                    HeviTerms Q, double* __restrict__ Qi,
-                                                    int max_sweeps, double rel_target,
-                                                    int full_sweeps, HeviDevInfo* info) {
-  b_stage_solve<N, FT>((int64_t)blockIdx.x,
-      sh, Gll<N>{}, lambda, ops, Ub, Lb, piv, ws, E, Q, Qi, max_sweeps, rel_target, full_sweeps,
-      info);
-}
-
-// The FP64 stage solve in one kernel: the three passes run back to back in the
-// wavefront that owns the tile, with the reduced right-hand side r and the
-// solution u (one array, used in place) in LDS instead of the global scratch.
-// The element chunks of the tile's cw wavefronts write and read the one r/u array;
-// the band solve runs in the first wavefront between the two barriers.
-template <int N, bool TILT, bool CHUNKED>
-__global__ __launch_bounds__(CHUNKED ? 64 * kMaxChunks : 64, kStreamWaves<N>) void k_stage_fused(
-    HeviShapeDev sh, double lambda, const double* __restrict__ ops,
-    const double* __restrict__ Ub, const double* __restrict__ Lb,
-    const uint8_t* __restrict__ piv, double* __restrict__ ws, HeviTerms E, HeviTerms Q,
-    double* __restrict__ Qi, HeviDevInfo* info, int cw_) {
-  extern __shared__ double ru[];  // [n_z][64]
-  const int64_t tile = blockIdx.x;
-  const int cw = CHUNKED ? cw_ : 1;
-  b_stage_rhs<N, true, TILT>(tile, sh, Gll<N>{}, lambda, ops, ws, E, Q, Qi, ru, cw);
-  __syncthreads();
-  if (threadIdx.x < T)
-    band_solve<N, double, true>(Ub, Lb, piv, plane_size(sh), ws, tile, sh.nz, (int)threadIdx.x,
-                                WS_R, WS_U, ru);
-  __syncthreads();
-  b_stage_update<N, true, TILT>(tile, sh, Gll<N>{}, lambda, ops, ws, Qi, info, ru, cw);
-}
-
-template <int N, bool TILT, bool CHUNKED>
-__global__ __launch_bounds__(CHUNKED ? 64 * kMaxChunks : 64, kStreamWaves<N>) void k_stage_rhs(
-    HeviShapeDev sh, double lambda, const double* __restrict__ ops, double* __restrict__ ws,
-    HeviTerms E, HeviTerms Q, double* __restrict__ Qi, int cw) {
-  b_stage_rhs<N, false, TILT>((int64_t)blockIdx.x, sh, Gll<N>{}, lambda, ops, ws, E, Q, Qi,
-                              nullptr, CHUNKED ? cw : 1);
-}
-
-template <int N, typename FT, bool REFINE>
-__global__ __launch_bounds__(64, kStreamWaves<N>) void k_stage_bsolve(HeviShapeDev sh, double lambda,
-                                                        const double* __restrict__ ops,
-                                                        const FT* __restrict__ Ub,
-                                                        const FT* __restrict__ Lb,
-                                                        const uint8_t* __restrict__ piv,
-                                                        double* __restrict__ ws, int max_sweeps,
-                                                        double rel_target, HeviDevInfo* info) {
-  b_stage_bsolve<N, FT, REFINE>((int64_t)blockIdx.x,
-      sh, Gll<N>{}, lambda, ops, Ub, Lb, piv, ws, max_sweeps, rel_target, info);
-}
-
-template <int N, bool TILT, bool CHUNKED>
-__global__ __launch_bounds__(CHUNKED ? 64 * kMaxChunks : 64, kStreamWaves<N>) void k_stage_update(
-    HeviShapeDev sh, double lambda, const double* __restrict__ ops, double* __restrict__ ws,
-    double* __restrict__ Qi, HeviDevInfo* info, int cw) {
-  b_stage_update<N, false, TILT>((int64_t)blockIdx.x, sh, Gll<N>{}, lambda, ops, ws, Qi, info,
-                                 nullptr, CHUNKED ? cw : 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -229,154 +137,52 @@ struct BuildOps {
   static hipError_t run(const HeviShapeDev& sh, double R, double cp, double g,
                         double pA, const double* z, const double* J, const double* gz,
                         const double* rho0, const double* Th0, double* ops, HeviDevInfo* info,
-                        int32_t* tilted, hipStream_t st) {
+                        int32_t* tilted, int s3, hipStream_t st) {
     hipLaunchKernelGGL(k_build_ops<N>, dim3((unsigned)sh.ntiles), dim3(T), 0, st, sh, R, cp,
-                       g, pA, z, J, gz, rho0, Th0, ops, info, tilted);
-    return hipGetLastError();
-  }
-};
-
-// Element chunks per tile of the streaming kernels.  A launch of few tiles is bound
-// by each tile's latency along its elements: below 512 tiles (two per CU) each
-// tile is split into up to kMaxChunks wavefronts, never more than it has elements.
-// At 10,800 columns (169 tiles of 10 elements) one step took 0.957 ms with one
-// wavefront per tile, 0.726 ms with 4 and 0.675 ms with 8.
-int chunks_for(const HeviShapeDev& sh) {
-  if (sh.ntiles >= 512) return 1;
-  return sh.Ne < kMaxChunks ? sh.Ne : kMaxChunks;
-}
-
-template <int N>
-struct Apply {
-  static hipError_t run(const HeviShapeDev& sh, const double* ops,
-                        const double* x, const double* xref, double* y, hipStream_t st) {
-    const int cw = chunks_for(sh);
-    const dim3 g((unsigned)sh.ntiles), b(T * cw);
-    if (xref && cw > 1)
-      hipLaunchKernelGGL((k_apply<N, true, true>), g, b, 0, st, sh, ops, x, xref, y, cw);
-    else if (xref)
-      hipLaunchKernelGGL((k_apply<N, true, false>), g, b, 0, st, sh, ops, x, xref, y, 1);
-    else
-      hipLaunchKernelGGL((k_apply<N, false, false>), dim3((unsigned)sh.ntiles), dim3(T), 0, st,
-                         sh, ops, x, xref, y, 1);
-    return hipGetLastError();
-  }
-};
-
-template <int N>
-struct Factor {
-  static hipError_t run(const HeviShapeDev& sh, double lambda, int fp32,
-                        const double* ops, double* sbuf, void* Ub, void* Lb, uint8_t* piv,
-                        HeviDevInfo* info, hipStream_t st) {
-    if constexpr (N > HEVI_FUSED_FACTOR_MAX_N) {
-      // assembly into sbuf, then the register-window LU split over kSplitLanes<N>
-      // lanes: kSplitLanes<N> workgroups per tile
-      const dim3 g((unsigned)sh.ntiles);
-      hipLaunchKernelGGL(k_factor_assemble<N>, g, dim3(T * CWF), 0, st, sh, lambda, ops, sbuf);
-      const dim3 g4((unsigned)(sh.ntiles * kSplitLanes<N>));
-      if (fp32)
-        hipLaunchKernelGGL((k_factor_lu_split<N, float>), g4, dim3(T), 0, st, sh, sbuf,
-                           (float*)Ub, (float*)Lb, piv, info);
-      else
-        hipLaunchKernelGGL((k_factor_lu_split<N, double>), g4, dim3(T), 0, st, sh, sbuf,
-                           (double*)Ub, (double*)Lb, piv, info);
-    } else {
-      // assembly and LU in one pass, the window split over kSplitLanes<N> lanes:
-      // kSplitLanes<N> workgroups per tile
-      (void)sbuf;
-      const dim3 g2((unsigned)(sh.ntiles * kSplitLanes<N>));
-      if (fp32)
-        hipLaunchKernelGGL((k_factor_fused<N, float>), g2, dim3(T), 0, st, sh, lambda, ops,
-                           (float*)Ub, (float*)Lb, piv, info);
-      else
-        hipLaunchKernelGGL((k_factor_fused<N, double>), g2, dim3(T), 0, st, sh, lambda, ops,
-                           (double*)Ub, (double*)Lb, piv, info);
-    }
-    return hipGetLastError();
-  }
-};
-
-template <int N>
-struct StageSolve {
-  static hipError_t run(const HeviShapeDev& sh, double lambda, int tilt, int fp32,
-                        const double* ops, const void* Ub, const void* Lb, const uint8_t* piv,
-                        double* ws, const HeviTerms& E, const HeviTerms& Q, double* Qi,
-                        int max_sweeps, double rel_target, int full_sweeps, HeviDevInfo* info,
-                        hipStream_t st) {
-    // element chunks for launches of few tiles (straight columns; the TILT kernels run
-    // one wavefront per tile)
-    const int cw = tilt ? 1 : chunks_for(sh);
-    const dim3 g((unsigned)sh.ntiles), b(T), b4(T * cw);
-    if (full_sweeps > 0) {
-      // accuracy mode: one kernel with the full-system refinement sweeps
-      if (fp32)
-        hipLaunchKernelGGL((k_stage_solve<N, float>), g, b, 0, st, sh, lambda, ops,
-                           (const float*)Ub, (const float*)Lb, piv, ws, E, Q, Qi, max_sweeps,
-                           rel_target, full_sweeps, info);
-      else
-        hipLaunchKernelGGL((k_stage_solve<N, double>), g, b, 0, st, sh, lambda, ops,
-                           (const double*)Ub, (const double*)Lb, piv, ws, E, Q, Qi, 0, rel_target,
-                           full_sweeps, info);
-      return hipGetLastError();
-    }
-    if (!fp32 && sh.nz <= HEVI_FUSED_MAX_NZ) {
-      hipLaunchKernelGGL((tilt ? k_stage_fused<N, true, false>
-                               : cw > 1 ? k_stage_fused<N, false, true> : k_stage_fused<N, false, false>),
-                         g, b4, (size_t)sh.nz * T * sizeof(double), st, sh, lambda, ops,
-                         (const double*)Ub, (const double*)Lb, piv, ws, E, Q, Qi, info, cw);
-      return hipGetLastError();
-    }
-    hipLaunchKernelGGL((tilt ? k_stage_rhs<N, true, false>
-                             : cw > 1 ? k_stage_rhs<N, false, true> : k_stage_rhs<N, false, false>),
-                       g, b4, 0, st, sh, lambda, ops, ws, E, Q, Qi, cw);
-    if (fp32)
-      hipLaunchKernelGGL((k_stage_bsolve<N, float, true>), g, b, 0, st, sh, lambda, ops,
-                         (const float*)Ub, (const float*)Lb, piv, ws, max_sweeps, rel_target, info);
-    else
-      hipLaunchKernelGGL((k_stage_bsolve<N, double, false>), g, b, 0, st, sh, lambda, ops,
-                         (const double*)Ub, (const double*)Lb, piv, ws, 0, rel_target, info);
-    hipLaunchKernelGGL((tilt ? k_stage_update<N, true, false>
-                             : cw > 1 ? k_stage_update<N, false, true>
-                                      : k_stage_update<N, false, false>),
-                       g, b4, 0, st, sh, lambda, ops, ws, Qi, info, cw);
+                       g, pA, z, J, gz, rho0, Th0, ops, info, tilted, s3);
     return hipGetLastError();
   }
 };
 
 }  // namespace
 
-hipError_t hevi_launch_build_ops(const HeviShapeDev& sh, double R, double cp,
+hipError_t hevi_launch_build_ops(const HeviShapeDev& sh, int s3, double R, double cp,
                                  double g, double pA, const double* z, const double* J,
                                  const double* gz, const double* rho0, const double* Th0,
                                  double* ops, HeviDevInfo* info, int32_t* tilted,
                                  hipStream_t st) {
   if (sh.ntiles == 0) return hipSuccess;
   return dispatch_N<BuildOps>(sh.N, sh, R, cp, g, pA, z, J, gz, rho0, Th0, ops, info, tilted,
-                              st);
+                              s3, st);
 }
 
-hipError_t hevi_launch_apply(const HeviShapeDev& sh, const double* ops,
+hipError_t hevi_launch_apply(const HeviShapeDev& sh, int s3, const double* ops,
                              const double* x, const double* xref, double* y, hipStream_t st) {
   if (sh.ntiles == 0) return hipSuccess;
-  return dispatch_N<Apply>(sh.N, sh, ops, x, xref, y, st);
+  if (s3) return hevi_launch_apply_3c(sh, ops, x, xref, y, st);
+  return dispatch_NS<Apply, false>(sh.N, sh, ops, x, xref, y, st);
 }
 
-hipError_t hevi_launch_factor(const HeviShapeDev& sh, double lambda, int fp32,
+hipError_t hevi_launch_factor(const HeviShapeDev& sh, int s3, double lambda, int fp32,
                               const double* ops, double* sbuf, void* Ub, void* Lb, uint8_t* piv,
                               HeviDevInfo* info, hipStream_t st) {
   if (sh.ntiles == 0) return hipSuccess;
-  return dispatch_N<Factor>(sh.N, sh, lambda, fp32, ops, sbuf, Ub, Lb, piv, info, st);
+  if (s3) return hevi_launch_factor_3c(sh, lambda, fp32, ops, sbuf, Ub, Lb, piv, info, st);
+  return dispatch_NS<Factor, false>(sh.N, sh, lambda, fp32, ops, sbuf, Ub, Lb, piv, info, st);
 }
 
-hipError_t hevi_launch_stage_solve(const HeviShapeDev& sh, double lambda, int tilt,
+hipError_t hevi_launch_stage_solve(const HeviShapeDev& sh, int s3, double lambda, int tilt,
                                    int fp32, const double* ops, const void* Ub, const void* Lb,
                                    const uint8_t* piv, double* ws, const HeviTerms& E,
                                    const HeviTerms& Q, double* Qi, int max_sweeps,
                                    double rel_target, int full_sweeps, HeviDevInfo* info,
                                    hipStream_t st) {
   if (sh.ntiles == 0) return hipSuccess;
-  return dispatch_N<StageSolve>(sh.N, sh, lambda, tilt, fp32, ops, Ub, Lb, piv, ws, E, Q, Qi,
-                                max_sweeps, rel_target, full_sweeps, info, st);
+  if (s3)
+    return hevi_launch_stage_solve_3c(sh, lambda, tilt, fp32, ops, Ub, Lb, piv, ws, E, Q, Qi,
+                                      max_sweeps, rel_target, full_sweeps, info, st);
+  return dispatch_NS<StageSolve, false>(sh.N, sh, lambda, tilt, fp32, ops, Ub, Lb, piv, ws, E,
+                                        Q, Qi, max_sweeps, rel_target, full_sweeps, info, st);
 }
 
 hipError_t hevi_launch_combine(int64_t n, const HeviTerms& V, double* out, hipStream_t st) {

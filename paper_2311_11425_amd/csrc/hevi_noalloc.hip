@@ -121,9 +121,9 @@ hevi_status hevi_solve_noalloc(hevi_ctx* ctx, const hevi_ops* ops, double lambda
   // the report starts at zero (a kernel, not a memset); every factor and scratch
   // entry the kernels read is written by this call's kernels first
   if (!ok(hevi_launch_info_reset(info, stream)) ||
-      !ok(hevi_launch_factor(sh, lambda, prec == HEVI_FP32_REFINE, ops->d_ops, sbuf, U, L, piv,
+      !ok(hevi_launch_factor(sh, ops->s3, lambda, prec == HEVI_FP32_REFINE, ops->d_ops, sbuf, U, L, piv,
                              info, stream)) ||
-      !ok(hevi_launch_stage_solve(sh, lambda, ops->tilted, prec == HEVI_FP32_REFINE, ops->d_ops,
+      !ok(hevi_launch_stage_solve(sh, ops->s3, lambda, ops->tilted, prec == HEVI_FP32_REFINE, ops->d_ops,
                                   U, L, piv, ws, E, Q, d_Qi, sweeps, target, full, info,
                                   stream)))
     return HEVI_E_DEVICE;

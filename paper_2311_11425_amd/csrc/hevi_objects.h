@@ -23,6 +23,7 @@ struct hevi_ops {
   HeviDevInfo* d_info;
   int32_t* d_tilt;  // device flag set by the ops build
   int tilted;       // its value: some column's grad(zeta) is not one vector along it
+  int s3;           // set 3C (state (rho, U, E); ops hold the J dP/drho plane)
 };
 
 struct hevi_factors {

@@ -38,9 +38,12 @@ class ColumnBatch:
         self.J = to_dev(col["J"], device)
         self.gz = to_dev(col["gz"], device)
         self.rho0 = to_dev(col["rho0"], device)
-        self.Theta0 = to_dev(col["Theta0"], device)
+        # the set's thermodynamic reference: Theta0 (set 2C) or the total energy E0 (3C)
+        self.eqset = col.get("eqset", "2C")
+        self.Theta0 = to_dev(col["E0"] if self.eqset == "3C" else col["Theta0"], device)
         self.ops = ctx.build_column_ops(self.N, self.Ne, self.ncols, self.consts, self.z, self.J,
-                                        self.gz, self.rho0, self.Theta0, stream=stream)
+                                        self.gz, self.rho0, self.Theta0, stream=stream,
+                                        eqset=self.eqset)
         self.device = device
 
     def empty_state(self):

@@ -15,6 +15,9 @@ LIB_PATH = os.path.join(HERE, "libhevi.so")
 
 HEVI_FP64 = 0
 HEVI_FP32_REFINE = 1
+HEVI_SET_2C = 0
+HEVI_SET_3C = 1
+EQSETS = {"2C": HEVI_SET_2C, "3C": HEVI_SET_3C}
 
 STATUS = {0: "HEVI_OK", 1: "HEVI_E_INVALID", 2: "HEVI_E_SHAPE", 3: "HEVI_E_NOMEM",
           4: "HEVI_E_DEVICE", 5: "HEVI_E_SINGULAR", 6: "HEVI_E_NOT_CONVERGED", 7: "HEVI_E_BUSY",
@@ -22,6 +25,7 @@ STATUS = {0: "HEVI_OK", 1: "HEVI_E_INVALID", 2: "HEVI_E_SHAPE", 3: "HEVI_E_NOMEM
 
 # every symbol include/hevi.h declares
 EXPORTS = ["hevi_create", "hevi_destroy", "hevi_status_str", "hevi_build_column_ops",
+           "hevi_build_column_ops_set",
            "hevi_ops_check", "hevi_ops_free", "hevi_apply_op", "hevi_factor", "hevi_refactor",
            "hevi_factors_check", "hevi_factors_band_entries", "hevi_factors_free",
            "hevi_stage_solve", "hevi_solve_noalloc", "hevi_combine",
@@ -108,6 +112,9 @@ def load():
         "hevi_status_str": ([ctypes.c_int], ctypes.c_char_p),
         "hevi_build_column_ops": ([_vp, ctypes.POINTER(Shape), ctypes.POINTER(Consts), _vp, _vp, _vp,
                                    _vp, _vp, pp, _vp], ctypes.c_int),
+        "hevi_build_column_ops_set": ([_vp, ctypes.POINTER(Shape), ctypes.POINTER(Consts),
+                                       ctypes.c_int, _vp, _vp, _vp, _vp, _vp, pp, _vp],
+                                      ctypes.c_int),
         "hevi_ops_check": ([_vp, _vp, ctypes.POINTER(i64), _vp], ctypes.c_int),
         "hevi_ops_free": ([_vp], None),
         "hevi_apply_op": ([_vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
@@ -275,14 +282,26 @@ class Context:
             self.lib.hevi_destroy(self.handle)
             self.handle = None
 
-    def build_column_ops(self, N, Ne, ncols, consts, z, J, gz, rho0, Theta0, stream=None):
+    def build_column_ops(self, N, Ne, ncols, consts, z, J, gz, rho0, Theta0, stream=None,
+                         eqset="2C"):
+        """Column operator of set ``eqset``: "2C" (Theta0 is rho0 theta0) or "3C"
+        (the argument is the reference total energy E0)."""
         sh = Shape(N, Ne, ncols)
         k = Consts(*consts)
         out = ctypes.c_void_p()
-        _check(self.lib.hevi_build_column_ops(self.handle, ctypes.byref(sh), ctypes.byref(k), _ptr(z),
-                                              _ptr(J), _ptr(gz), _ptr(rho0), _ptr(Theta0),
-                                              ctypes.byref(out), _stream(stream)),
-               "hevi_build_column_ops")
+        if eqset == "2C":
+            _check(self.lib.hevi_build_column_ops(self.handle, ctypes.byref(sh), ctypes.byref(k),
+                                                  _ptr(z), _ptr(J), _ptr(gz), _ptr(rho0),
+                                                  _ptr(Theta0), ctypes.byref(out),
+                                                  _stream(stream)),
+                   "hevi_build_column_ops")
+        else:
+            _check(self.lib.hevi_build_column_ops_set(self.handle, ctypes.byref(sh),
+                                                      ctypes.byref(k), EQSETS[eqset], _ptr(z),
+                                                      _ptr(J), _ptr(gz), _ptr(rho0),
+                                                      _ptr(Theta0), ctypes.byref(out),
+                                                      _stream(stream)),
+                   "hevi_build_column_ops_set")
         return Ops(self, out, (N, Ne, ncols), None)
 
     def apply_op(self, ops, x, y, xref=None, stream=None):

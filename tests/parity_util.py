@@ -22,8 +22,9 @@ def relerr_cols(a, ref, floor=0.0):
 def sub_batch(col, idx):
     """The columns idx of a batch as a new batch (columns are independent)."""
     out = dict(col)
-    for k in ("z", "J", "rho0", "Theta0", "T"):
-        out[k] = np.ascontiguousarray(col[k][:, idx])
+    for k in ("z", "J", "rho0", "Theta0", "E0", "T"):
+        if k in col:
+            out[k] = np.ascontiguousarray(col[k][:, idx])
     out["gz"] = np.ascontiguousarray(col["gz"][:, :, idx])
     out["nhat"] = np.ascontiguousarray(col["nhat"][idx])
     out["ncols"] = len(idx)
