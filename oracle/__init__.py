@@ -12,7 +12,9 @@ field is ``[k][c]`` (column index fastest), a state vector ``[v][k][c]`` with
 ``v = (rho, rho u, rho v, rho w, q_T)`` with ``q_T`` the thermodynamic variable of
 the equation set (``Theta = rho theta`` for set 2C, the total energy ``E`` for
 set 3C), ``grad(zeta)`` is ``[m][k][c]``.  A column batch names its set in
-``col["eqset"]`` ("2C" when absent); a set-3C batch carries ``E0``.
+``col["eqset"]`` ("2C" when absent); a set-3C batch carries ``E0``.  A batch with
+``col["U0"]`` (momentum [m][k][c] of a moving linearisation state, set 2C) is solved
+with the LHEVI-PS operator: the Jacobian of the vertical operator at (rho0, U0, Theta0).
 
 Parity status per function is documented in ``hevi_oracle.c``; every function
 has at least one pin in ``tests/test_oracle_pins.py``.  The ARK tableaux in
@@ -64,6 +66,11 @@ def _load():
         lib.ho_assemble_L.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp, _dp,
                                       _dp, _dp, _dp, ctypes.c_int, ctypes.c_int, _dp]
         lib.ho_assemble_L.restype = ctypes.c_int
+        lib.ho_jacobian_2c.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp]
+        lib.ho_jacobian_2c.restype = None
+        lib.ho_assemble_L_K.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp, _dp,
+                                        _dp, ctypes.c_int, _dp]
+        lib.ho_assemble_L_K.restype = ctypes.c_int
         lib.ho_bc_project.argtypes = [ctypes.c_int, _dp, _dp]
         lib.ho_bc_project.restype = None
         lib.ho_form_A.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp]
@@ -78,16 +85,16 @@ def _load():
         common = [ctypes.c_int, ctypes.c_int, ctypes.c_long, ctypes.c_int, _dp, _dp, _dp, _dp, _dp,
                   _dp]
         lib.ho_solve_batch.argtypes = common + [ctypes.c_double, _dp, _dp, ctypes.c_int,
-                                                ctypes.c_int, ctypes.c_int,
+                                                ctypes.c_int, ctypes.c_int, _dp,
                                                 ctypes.POINTER(ctypes.c_long)]
         lib.ho_solve_batch.restype = ctypes.c_int
-        lib.ho_apply_batch.argtypes = common + [_dp, _dp, _dp, ctypes.c_int, ctypes.c_int,
+        lib.ho_apply_batch.argtypes = common + [_dp, _dp, _dp, ctypes.c_int, ctypes.c_int, _dp,
                                                 ctypes.POINTER(ctypes.c_long)]
         lib.ho_apply_batch.restype = ctypes.c_int
         lib.ho_ark_step_batch.argtypes = common + [ctypes.c_int, _dp, _dp, _dp, ctypes.c_double,
                                                    ctypes.c_double, _dp, _dp, _dp, _dp, _dp,
                                                    ctypes.c_int, ctypes.c_int,
-                                                   ctypes.c_int, ctypes.POINTER(ctypes.c_long)]
+                                                   ctypes.c_int, _dp, ctypes.POINTER(ctypes.c_long)]
         lib.ho_ark_step_batch.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -154,9 +161,35 @@ def assemble_L(N, Ne, g, z, J, gz_k3, hq, cq, pr=None, rho_weak=True, theta_weak
     return L
 
 
+def jacobian_2c(gz_k3, rho0, U0_k3, Theta0, cTheta):
+    """Set-2C flux Jacobian at (rho0, U0, Theta0) per node: array [k][5][5]."""
+    lib = _load()
+    nz = len(rho0)
+    K = np.zeros((nz, 5, 5))
+    lib.ho_jacobian_2c(nz, *[_p(_f64(a)) for a in (gz_k3, rho0, U0_k3, Theta0, cTheta)], _p(K))
+    return K
+
+
+def assemble_L_K(N, Ne, g, z, J, gz_k3, K, rho_weak=True):
+    """Dense L_z from per-node flux Jacobians K [k][5][5]."""
+    lib = _load()
+    nz = Ne * N + 1
+    L = np.zeros((5 * nz, 5 * nz))
+    rc = lib.ho_assemble_L_K(N, Ne, g, *[_p(_f64(a)) for a in (z, J, gz_k3, K)], int(rho_weak),
+                             _p(L))
+    if rc:
+        raise ValueError("assemble failed")
+    return L
+
+
 def column_L(N, Ne, consts, z, J, gz_k3, rho0, thermo0, rho_weak=True, theta_weak=False,
-             eqset="2C"):
-    """Dense L_z of one column of set ``eqset``; thermo0 is Theta0 (2C) or E0 (3C)."""
+             eqset="2C", U0_k3=None):
+    """Dense L_z of one column of set ``eqset``; thermo0 is Theta0 (2C) or E0 (3C).
+    U0_k3 ([k][3], set 2C): LHEVI-PS, the Jacobian at (rho0, U0, Theta0)."""
+    if U0_k3 is not None:
+        hq, cq = reference(rho0, thermo0, consts)
+        K = jacobian_2c(gz_k3, rho0, U0_k3, thermo0, cq)
+        return assemble_L_K(N, Ne, consts[2], z, J, gz_k3, K, rho_weak)
     if eqset == "3C":
         hq, cq, pr = reference_3c(rho0, thermo0, z, consts)
     else:
@@ -213,6 +246,11 @@ def _geom_args(col):
     return [_f64(col[k]) for k in ("z", "J", "gz", "rho0", _thermo_key(col))]
 
 
+def _u0(col):
+    """LHEVI-PS linearisation momentum [m][k][c], or None (state at rest)."""
+    return _f64(col["U0"]) if col.get("U0") is not None else None
+
+
 def solve_batch(col, lam, b, refine=1, rho_weak=True, nthreads=None):
     """x = (I - lam L_z)^{-1} P(b) for every column of the batch ``col``."""
     lib = _load()
@@ -225,7 +263,7 @@ def solve_batch(col, lam, b, refine=1, rho_weak=True, nthreads=None):
     consts = _f64(col["consts"])
     rc = lib.ho_solve_batch(N, Ne, ncols, nthreads or os.cpu_count() or 1, _p(consts),
                             *[_p(a) for a in g], lam, _p(b), _p(x), refine, int(rho_weak),
-                            _eqset(col), ctypes.byref(bad))
+                            _eqset(col), _p(_u0(col)), ctypes.byref(bad))
     if rc:
         raise RuntimeError(f"oracle solve failed ({rc}) at column {bad.value}")
     return x
@@ -244,7 +282,7 @@ def apply_batch(col, x, xref=None, rho_weak=True, nthreads=None):
     consts = _f64(col["consts"])
     rc = lib.ho_apply_batch(N, Ne, ncols, nthreads or os.cpu_count() or 1, _p(consts),
                             *[_p(a) for a in g], _p(x), _p(xr), _p(y), int(rho_weak),
-                            _eqset(col), ctypes.byref(bad))
+                            _eqset(col), _p(_u0(col)), ctypes.byref(bad))
     if rc:
         raise RuntimeError(f"oracle apply failed ({rc}) at column {bad.value}")
     return y
@@ -276,12 +314,17 @@ def ark_step_batch(col, tab, dt, qn, qref, refine=1, rho_weak=True, nthreads=Non
                                *[_p(a) for a in g], s, _p(Aexp), _p(Aimp), _p(bw), dt, omega,
                                _p(qn),
                                _p(qref), _p(qnp1), _p(Q), _p(S), refine, int(rho_weak),
-                               _eqset(col), ctypes.byref(bad))
+                               _eqset(col), _p(_u0(col)), ctypes.byref(bad))
     if rc:
         raise RuntimeError(f"oracle ARK step failed ({rc}) at column {bad.value}")
     if want_stages:
         return qnp1, Q, S
     return qnp1
+
+
+def u0_of(col, c):
+    """The LHEVI-PS linearisation momentum of column c as [k][3] (None at rest)."""
+    return None if col.get("U0") is None else np.ascontiguousarray(col["U0"][:, :, c].T)
 
 
 def column_of(col, c):

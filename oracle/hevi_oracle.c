@@ -19,6 +19,10 @@
  *     quadrature weight w_i J_i, direct-stiffness-summed along the column and
  *     divided by the lumped mass (Sec. 3 eq. mass matrix, Sec. 4.2.3 global
  *     assembly), with rigid-lid rows at the bottom and top nodes;
+ *   - for LHEVI-PS (Sec. 4.3.1: the linear operator is the Jacobian of the
+ *     vertical operator at a previous solution q0 = (rho0, U0, Theta0), U0 != 0),
+ *     the set-2C flux Jacobian K(q0) at that state (Appendix A.3, eq.
+ *     set2c_jacobian, re-derived from the fluxes) and the same assembly;
  *   - x = (I - Lambda L_z)^{-1} b by dense Gaussian elimination with partial
  *     pivoting (Sec. 4.3 eq. lhevi-ark-final-2), optionally followed by
  *     iterative refinement with the residual accumulated in long double;
@@ -221,6 +225,94 @@ int ho_assemble_L(int N, int Ne, double g, const double *z, const double *J,
   return 0;
 }
 
+/* Flux Jacobian of set 2C at a general state (LHEVI-PS, Sec. 4.3.1), per node k:
+ * K[25k + 5a + b] = dF_a/dq_b of the contravariant vertical fluxes
+ *   F_rho = U^z,  F_U = U U^z / rho + P grad(zeta),  F_Theta = Theta U^z / rho,
+ *   U^z = grad(zeta).U  (Appendix A.2),  P = P(Theta) of eq. set2c_pressure,
+ * at q0 = (rho0, U0, Theta0): with u = U0/rho0, w = grad(zeta).u, theta0 = Theta0/rho0,
+ *   K[rho][U_m] = gz_m
+ *   K[U_l][rho] = -u_l w,  K[U_l][U_m] = delta_lm w + u_l gz_m,  K[U_l][Theta] = gz_l c_Theta
+ *   K[Theta][rho] = -theta0 w,  K[Theta][U_m] = theta0 gz_m,  K[Theta][Theta] = w
+ * (the printed eq. set2c_jacobian has these entries up to garbled 1/rho factors and a
+ * dropped Theta in K[Theta][rho]; dP/drho = dP/dU = 0 in set 2C).  At U0 = 0 this is
+ * the matrix of ho_assemble_L.  U0 is [3k+m] (momentum), cTheta = dP/dTheta at Theta0.
+ * Parity pinned: centred differences of the nonlinear vertical operator written from
+ * the fluxes (tests), the rest-state limit, conservation. */
+void ho_jacobian_2c(int nz, const double *gz, const double *rho0, const double *U0,
+                    const double *Theta0, const double *cTheta, double *K) {
+  for (int k = 0; k < nz; ++k) {
+    const double *z = &gz[3 * k];
+    double u[3], w = 0.0;
+    for (int m = 0; m < 3; ++m) {
+      u[m] = U0[3 * k + m] / rho0[k];
+      w += z[m] * u[m];
+    }
+    double th = Theta0[k] / rho0[k];
+    double *Kk = &K[25 * (size_t)k];
+    memset(Kk, 0, 25 * sizeof(double));
+    for (int m = 0; m < 3; ++m) Kk[0 * 5 + 1 + m] = z[m];
+    for (int l = 0; l < 3; ++l) {
+      Kk[(1 + l) * 5 + 0] = -u[l] * w;
+      for (int m = 0; m < 3; ++m) Kk[(1 + l) * 5 + 1 + m] = (l == m ? w : 0.0) + u[l] * z[m];
+      Kk[(1 + l) * 5 + 4] = z[l] * cTheta[k];
+    }
+    Kk[4 * 5 + 0] = -th * w;
+    for (int m = 0; m < 3; ++m) Kk[4 * 5 + 1 + m] = th * z[m];
+    Kk[4 * 5 + 4] = w;
+  }
+}
+
+/* Dense L_z from per-node flux Jacobians K (as ho_jacobian_2c), assembled as in
+ * ho_assemble_L: per element, strong rows w_i D_ij J_{k_j} K_{k_j}[a][b] (momentum and
+ * Theta rows), the rho row weak -w_j D_ji J_{k_j} K_{k_j}[0][b] unless rho_weak == 0,
+ * gravity in the rho column of the momentum rows, lumped mass, L = -M^{-1} B, zero
+ * momentum rows at the rigid-lid nodes (Sec. 4.2.3, Appendix A.3).
+ * Parity pinned: equals ho_assemble_L at U0 = 0 (to rounding), finite differences of the
+ * nonlinear operator (tests). */
+int ho_assemble_L_K(int N, int Ne, double g, const double *z, const double *J,
+                    const double *gz, const double *K, int rho_weak, double *L) {
+  if (N < 1 || N > 16 || Ne < 1) return 1;
+  int nz = Ne * N + 1, n = 5 * nz, np1 = N + 1;
+  double xi[17], w[17], D[17 * 17];
+  if (ho_gll(N, xi, w, D)) return 1;
+  double *M = (double *)calloc((size_t)nz, sizeof(double));
+  if (!M) return 2;
+  memset(L, 0, sizeof(double) * (size_t)n * (size_t)n);
+  for (int e = 0; e < Ne; ++e) {
+    for (int i = 0; i <= N; ++i) {
+      int ki = e * N + i;
+      double dphi = 0.0;
+      for (int j = 0; j <= N; ++j) dphi += D[i * np1 + j] * z[e * N + j];
+      dphi *= g;
+      M[ki] += w[i] * J[ki];
+      for (int m = 0; m < 3; ++m)
+        L[(size_t)(5 * ki + 1 + m) * n + 5 * ki + 0] += w[i] * J[ki] * dphi * gz[3 * ki + m];
+      for (int j = 0; j <= N; ++j) {
+        int kj = e * N + j;
+        double strong = w[i] * D[i * np1 + j] * J[kj];
+        double weak = -w[j] * D[j * np1 + i] * J[kj];
+        const double *Kj = &K[25 * (size_t)kj];
+        for (int a = 0; a < 5; ++a) {
+          double f = (a == 0 && rho_weak) ? weak : strong;
+          for (int b = 0; b < 5; ++b)
+            if (Kj[5 * a + b] != 0.0)
+              L[(size_t)(5 * ki + a) * n + 5 * kj + b] += f * Kj[5 * a + b];
+        }
+      }
+    }
+  }
+  for (int r = 0; r < n; ++r) {
+    double s = -1.0 / M[r / 5];
+    for (int c = 0; c < n; ++c) L[(size_t)r * n + c] *= s;
+  }
+  int ends[2] = {0, nz - 1};
+  for (int t = 0; t < 2; ++t)
+    for (int m = 0; m < 3; ++m)
+      memset(&L[(size_t)(5 * ends[t] + 1 + m) * n], 0, sizeof(double) * (size_t)n);
+  free(M);
+  return 0;
+}
+
 /* Rigid-lid projection of a right-hand side: at the bottom and top nodes the
  * momentum loses its component along n = gz/|gz| (no flux through the lid). */
 void ho_bc_project(int nz, const double *gz, double *b) {
@@ -339,6 +431,7 @@ typedef struct {
   int mode;
   int rho_weak, refine;
   int eqset; /* 0: set 2C (Theta0 input), 1: set 3C (E0 input) */
+  const double *U0; /* LHEVI-PS: momentum of the linearisation state [m][k][c], or NULL */
   double lambda;
   const double *in; /* solve: b; apply: x */
   const double *in_ref; /* apply: optional x_ref subtracted first */
@@ -401,7 +494,8 @@ static void *worker(void *arg) {
   double *z = malloc(sizeof(double) * nz), *J = malloc(sizeof(double) * nz),
          *gz = malloc(sizeof(double) * 3 * nz), *rho0 = malloc(sizeof(double) * nz),
          *Th0 = malloc(sizeof(double) * nz), *th0 = malloc(sizeof(double) * nz),
-         *cT = malloc(sizeof(double) * nz), *pr = malloc(sizeof(double) * nz);
+         *cT = malloc(sizeof(double) * nz), *pr = malloc(sizeof(double) * nz),
+         *U0 = malloc(sizeof(double) * 3 * nz), *Kn = malloc(sizeof(double) * 25 * nz);
   int nv = 8 + 2 * (s > 0 ? s : 1);
   double *vb = malloc(sizeof(double) * n * nv);
   double *b = vb, *x = vb + n, *work = vb + 2 * n, *qn = vb + 3 * n, *qref = vb + 4 * n,
@@ -416,8 +510,18 @@ static void *worker(void *arg) {
       ho_reference_3c(nz, rho0, Th0, z, jb->R, jb->cp, jb->g, th0, cT, pr);
     else
       ho_reference(nz, rho0, Th0, jb->R, jb->cp, jb->pA, th0, cT);
-    if (ho_assemble_L(jb->N, jb->Ne, jb->g, z, J, gz, th0, cT, jb->eqset == 1 ? pr : NULL,
-                      jb->rho_weak, 0, L)) {
+    int bad;
+    if (jb->U0) {
+      /* LHEVI-PS: the Jacobian at (rho0, U0, Theta0) */
+      for (int k = 0; k < nz; ++k)
+        for (int m = 0; m < 3; ++m) U0[3 * k + m] = jb->U0[((long)m * nz + k) * jb->ncols + c];
+      ho_jacobian_2c(nz, gz, rho0, U0, Th0, cT, Kn);
+      bad = ho_assemble_L_K(jb->N, jb->Ne, jb->g, z, J, gz, Kn, jb->rho_weak, L);
+    } else {
+      bad = ho_assemble_L(jb->N, jb->Ne, jb->g, z, J, gz, th0, cT, jb->eqset == 1 ? pr : NULL,
+                          jb->rho_weak, 0, L);
+    }
+    if (bad) {
       jb->status = 1; jb->bad_col = c; break;
     }
     if (jb->mode == 1) {
@@ -503,7 +607,7 @@ static void *worker(void *arg) {
         put_vec(jb->Sout + (size_t)i * 5 * nz * jb->ncols, jb->ncols, nz, c, &S[(size_t)i * n]);
   }
   free(L); free(A); free(LU); free(piv); free(z); free(J); free(gz); free(rho0);
-  free(Th0); free(th0); free(cT); free(pr); free(vb);
+  free(Th0); free(th0); free(cT); free(pr); free(U0); free(Kn); free(vb);
   return NULL;
 }
 
@@ -541,16 +645,18 @@ static void fill_common(job_t *jb, int N, int Ne, long ncols, const double *cons
 
 /* x = (I - lambda L_z)^{-1} P(b) per column, P the rigid-lid projection.
  * consts = {R, c_p, g, P_A}; eqset 0 (set 2C: Theta0 is rho0 theta0) or 1 (set
- * 3C: Theta0 holds the total energy E0).  Returns 0 or an error code; *bad_col
- * names the first failing column. */
+ * 3C: Theta0 holds the total energy E0).  U0 non-NULL ([m][k][c], set 2C only):
+ * LHEVI-PS, L_z the Jacobian at (rho0, U0, Theta0).  Returns 0 or an error code;
+ * *bad_col names the first failing column. */
 int ho_solve_batch(int N, int Ne, long ncols, int nthreads, const double *consts,
                    const double *z, const double *J, const double *gz, const double *rho0,
                    const double *Theta0, double lambda, const double *b, double *x,
-                   int refine, int rho_weak, int eqset, long *bad_col) {
+                   int refine, int rho_weak, int eqset, const double *U0, long *bad_col) {
   job_t jb;
+  if (U0 && eqset != 0) return 1;
   fill_common(&jb, N, Ne, ncols, consts, z, J, gz, rho0, Theta0);
   jb.mode = 0; jb.lambda = lambda; jb.in = b; jb.out = x; jb.refine = refine;
-  jb.rho_weak = rho_weak; jb.eqset = eqset;
+  jb.rho_weak = rho_weak; jb.eqset = eqset; jb.U0 = U0;
   return run_jobs(&jb, nthreads, bad_col);
 }
 
@@ -558,11 +664,12 @@ int ho_solve_batch(int N, int Ne, long ncols, int nthreads, const double *consts
 int ho_apply_batch(int N, int Ne, long ncols, int nthreads, const double *consts,
                    const double *z, const double *J, const double *gz, const double *rho0,
                    const double *Theta0, const double *x, const double *xref, double *y,
-                   int rho_weak, int eqset, long *bad_col) {
+                   int rho_weak, int eqset, const double *U0, long *bad_col) {
   job_t jb;
+  if (U0 && eqset != 0) return 1;
   fill_common(&jb, N, Ne, ncols, consts, z, J, gz, rho0, Theta0);
   jb.mode = 1; jb.in = x; jb.in_ref = xref; jb.out = y; jb.rho_weak = rho_weak;
-  jb.eqset = eqset;
+  jb.eqset = eqset; jb.U0 = U0;
   return run_jobs(&jb, nthreads, bad_col);
 }
 
@@ -575,13 +682,13 @@ int ho_ark_step_batch(int N, int Ne, long ncols, int nthreads, const double *con
                       const double *Theta0, int s, const double *Aexp, const double *Aimp,
                       const double *bw, double dt, double omega, const double *qn,
                       const double *qref, double *qnp1, double *Qout, double *Sout, int refine,
-                      int rho_weak, int eqset, long *bad_col) {
-  if (s < 2) return 1;
+                      int rho_weak, int eqset, const double *U0, long *bad_col) {
+  if (s < 2 || (U0 && eqset != 0)) return 1;
   job_t jb;
   fill_common(&jb, N, Ne, ncols, consts, z, J, gz, rho0, Theta0);
   jb.mode = 2; jb.s = s; jb.Aexp = Aexp; jb.Aimp = Aimp; jb.bw = bw; jb.dt = dt;
   jb.omega = omega;
   jb.qn = qn; jb.qref = qref; jb.qnp1 = qnp1; jb.Qout = Qout; jb.Sout = Sout;
-  jb.refine = refine; jb.rho_weak = rho_weak; jb.eqset = eqset;
+  jb.refine = refine; jb.rho_weak = rho_weak; jb.eqset = eqset; jb.U0 = U0;
   return run_jobs(&jb, nthreads, bad_col);
 }

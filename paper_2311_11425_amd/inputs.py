@@ -140,10 +140,37 @@ def thermo0(col):
     return col["E0"] if col.get("eqset", "2C") == "3C" else col["Theta0"]
 
 
+def with_wind(col, u_h=20.0, w0=0.5, seed=13):
+    """The batch with a moving linearisation state (LHEVI-PS, a previous solution):
+    momentum U0 = rho0 (u_t(z) + w(z) n) with a horizontal wind u_t tangential to the
+    column, growing linearly from 0.5 u_h at the bottom to 1.5 u_h at the top in a random
+    tangential direction, and a vertical wind w = w0 sin(pi s) (s the normalised
+    height) that vanishes at the bottom and top nodes, as the rigid lid requires."""
+    rng = np.random.default_rng(seed)
+    out = dict(col)
+    z = col["z"]
+    s = (z - z[:1]) / (z[-1:] - z[:1])
+    nh = col["nhat"]                                           # (c, 3)
+    t = rng.standard_normal(nh.shape)
+    t -= (t * nh).sum(1, keepdims=True) * nh
+    t /= np.linalg.norm(t, axis=1, keepdims=True)
+    w = w0 * np.sin(np.pi * s)
+    w[0] = 0.0
+    w[-1] = 0.0
+    U0 = np.empty((3,) + z.shape)
+    for m in range(3):
+        U0[m] = col["rho0"] * (u_h * (0.5 + s) * t[:, m][None, :] + w * nh[:, m][None, :])
+    out["U0"] = np.ascontiguousarray(U0)
+    return out
+
+
 def reference_vector(col):
-    """q_ref = (rho0, 0, 0, 0, Theta0 or E0) as [v][k][c]."""
+    """q_ref = (rho0, U0 or 0, Theta0 or E0) as [v][k][c] (U0: a moving linearisation
+    state, see with_wind)."""
     q = np.zeros((5,) + col["rho0"].shape)
     q[0] = col["rho0"]
+    if col.get("U0") is not None:
+        q[1:4] = col["U0"]
     q[4] = thermo0(col)
     return q
 

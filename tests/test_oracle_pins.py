@@ -787,3 +787,150 @@ def test_3c_rotation_and_tangential(eqset):
         n = col["nhat"][c]
         P = np.eye(3) - np.outer(n, n)
         assert np.abs(P @ x[1:4, :, c] - P @ b[1:4, :, c]).max() <= 1e-13 * np.abs(b[1:4]).max()
+
+
+# ---------------------------------------------------------------------------
+# LHEVI-PS (Sec. 4.3.1): the Jacobian of the vertical operator at a moving state
+
+def _nonlinear_V(col, c, q):
+    """The set-2C discrete vertical operator V(q) of column c (Appendix A.2), written
+    from its nonlinear fluxes F_rho = J U^z, F_U = J (U U^z/rho + P(Theta) grad zeta),
+    F_Theta = J Theta U^z/rho (U^z = grad(zeta).U) with the same element derivatives,
+    gravity, DSS, mass and rigid lid as the oracle's operator; q interleaved (5k+v)."""
+    N, Ne = col["N"], col["Ne"]
+    nz = Ne * N + 1
+    _, w, D = oracle.gll(N)
+    z, J, gz, _, _ = oracle.column_of(col, c)
+    rho, Th = q[0::5], q[4::5]
+    U = np.stack([q[1::5], q[2::5], q[3::5]], 1)
+    Uz = (gz * U).sum(1)
+    P = PA * (R * Th / PA) ** GAM
+    Fr = J * Uz
+    FU = J[:, None] * (U * (Uz / rho)[:, None] + P[:, None] * gz)
+    FT = J * Th * Uz / rho
+    B = np.zeros((nz, 5))
+    M = np.zeros(nz)
+    for e in range(Ne):
+        for i in range(N + 1):
+            ki = e * N + i
+            M[ki] += w[i] * J[ki]
+            dphi = G * sum(D[i, j] * z[e * N + j] for j in range(N + 1))
+            B[ki, 1:4] += w[i] * J[ki] * dphi * gz[ki] * rho[ki]
+            for j in range(N + 1):
+                kj = e * N + j
+                B[ki, 0] += -w[j] * D[j, i] * Fr[kj]
+                B[ki, 1:4] += w[i] * D[i, j] * FU[kj]
+                B[ki, 4] += w[i] * D[i, j] * FT[kj]
+    V = -B / M[:, None]
+    V[0, 1:4] = 0.0
+    V[-1, 1:4] = 0.0
+    return V.reshape(-1)
+
+
+def _ps_col():
+    return inputs.with_wind(inputs.make_columns(4, 6, 2, profile="lapse", seed=3,
+                                                surface_max=1e3, tilt=0.05))
+
+
+def test_ps_rest_limit():
+    """At U0 = 0 the LHEVI-PS operator is the reference-state operator (catches an entry
+    of the general Jacobian that survives at rest, or an assembly slip of the general
+    path)."""
+    col = _ps_col()
+    z, J, gz, r0, T0 = oracle.column_of(col, 0)
+    Lrs = oracle.column_L(4, 6, CONSTS, z, J, gz, r0, T0)
+    L0 = oracle.column_L(4, 6, CONSTS, z, J, gz, r0, T0, U0_k3=np.zeros((len(z), 3)))
+    assert np.abs(L0 - Lrs).max() <= 1e-15 * np.abs(Lrs).max()
+
+
+def test_ps_jacobian_matches_nonlinear_operator():
+    """L_PS v against centred differences of the nonlinear operator V at q0 = (rho0, U0,
+    Theta0): the second-order error at this step is ~1e-10, while any dropped or
+    mis-signed Jacobian entry (advection of U and Theta, the u_l U^z/rho products, the
+    -Theta U^z/rho^2 term) leaves 1e-4 or more; the rest-state operator misses by 1e-3."""
+    col = _ps_col()
+    qn, qref = inputs.perturbed_state(col)
+    for c in range(2):
+        z, J, gz, r0, T0 = oracle.column_of(col, c)
+        L = oracle.column_L(4, 6, CONSTS, z, J, gz, r0, T0, U0_k3=oracle.u0_of(col, c))
+        Lrs = oracle.column_L(4, 6, CONSTS, z, J, gz, r0, T0)
+        q0 = oracle.vec_of(qref, c)
+        v = oracle.vec_of(qn - qref, c)
+        eps = 1e-2
+        fd = (_nonlinear_V(col, c, q0 + eps * v) - _nonlinear_V(col, c, q0 - eps * v)) / (2 * eps)
+        Lv, Lv_rs = L @ v, Lrs @ v
+        for k in range(5):
+            d = np.linalg.norm(Lv[k::5])
+            assert np.linalg.norm(fd[k::5] - Lv[k::5]) < 1e-9 * d, (c, k)
+        assert max(np.linalg.norm(fd[k::5] - Lv_rs[k::5]) / np.linalg.norm(Lv_rs[k::5])
+                   for k in range(1, 5)) > 1e-4
+
+
+def test_ps_conservation():
+    """Mass and rho-theta stay conserved with the moving linearisation state (flux form;
+    the vertical wind of the state vanishes at the lid)."""
+    col = inputs.with_wind(inputs.make_columns(4, 8, 4, profile="lapse", seed=4,
+                                               surface_max=2e3, deep=True))
+    qn, qref = inputs.perturbed_state(col)
+    b = qn - qref
+    x = oracle.solve_batch(col, 0.4358665215 * 300, b, refine=1)
+    w = np.array([float(v) for v in GLL_CLOSED[4][1]])
+    for c in range(4):
+        M = np.zeros(col["nz"])
+        for e in range(col["Ne"]):
+            for i in range(5):
+                M[4 * e + i] += w[i] * col["J"][4 * e + i, c]
+        for v in (0, 4):
+            assert abs(np.dot(M, x[v, :, c]) - np.dot(M, b[v, :, c])) <= \
+                1e-13 * np.dot(M, np.abs(b[v, :, c]))
+
+
+def test_ps_lapack_band_and_mpmath():
+    """An LHEVI-PS column of the ne=30 shape: the paper's band structure (kl = ku =
+    5(N+1) - 1) holds, the LAPACK band solver and 30-digit elimination agree with the
+    oracle, and the batched driver equals the dense solve."""
+    mp.mp.dps = 30
+    col = inputs.with_wind(inputs.config2(ncols=1))
+    N, Ne = col["N"], col["Ne"]
+    lam = 0.4358665215 * 300
+    qn, qref = inputs.perturbed_state(col)
+    z, J, gz, r0, T0 = oracle.column_of(col, 0)
+    L = oracle.column_L(N, Ne, CONSTS, z, J, gz, r0, T0, U0_k3=oracle.u0_of(col, 0))
+    A = oracle.form_A(L, lam)
+    n = A.shape[0]
+    kl = ku = 5 * (N + 1) - 1
+    ii, jj = np.nonzero(A)
+    assert np.abs(ii - jj).max() <= kl
+    ab = np.zeros((kl + ku + 1, n))
+    for j in range(n):
+        for i in range(max(0, j - ku), min(n, j + kl + 1)):
+            ab[ku + i - j, j] = A[i, j]
+    b = oracle.bc_project(col["nz"], gz, oracle.vec_of(qn - qref, 0))
+    xl = sla.solve_banded((kl, ku), ab, b)
+    xm = np.array([float(v) for v in mp.lu_solve(mp.matrix(A.tolist()), mp.matrix(b.tolist()))])
+    x1 = oracle.lu_solve_dense(A, b, refine=1)
+    assert relerr_per_var(x1, xm) < 1e-15
+    assert relerr_per_var(x1, xl) < 5e-12
+    xb = oracle.solve_batch(col, lam, qn - qref, refine=1)
+    assert relerr_per_var(oracle.vec_of(xb, 0), x1) < 1e-15
+
+
+def test_ps_rotation_equivariance():
+    """Rotating grad(zeta), the state's momentum and the right-hand side's momentum
+    rotates the LHEVI-PS solution."""
+    col = inputs.with_wind(inputs.config1(heterogeneous=True, ncols=3))
+    qn, qref = inputs.perturbed_state(col)
+    b = qn - qref
+    lam = 25.0
+    x = oracle.solve_batch(col, lam, b, refine=1)
+    Q = sla.expm(np.array([[0, -0.3, 0.5], [0.3, 0, -0.7], [-0.5, 0.7, 0]]))
+    col2 = dict(col)
+    col2["gz"] = np.einsum("ij,jkc->ikc", Q, col["gz"])
+    col2["U0"] = np.einsum("ij,jkc->ikc", Q, col["U0"])
+    b2 = b.copy()
+    b2[1:4] = np.einsum("ij,jkc->ikc", Q, b[1:4])
+    x2 = oracle.solve_batch(col2, lam, b2, refine=1)
+    xr = x.copy()
+    xr[1:4] = np.einsum("ij,jkc->ikc", Q, x[1:4])
+    for c in range(3):
+        assert relerr_per_var(oracle.vec_of(x2, c), oracle.vec_of(xr, c)) < 1e-13
