@@ -161,6 +161,35 @@ hevi_status hevi_build_column_ops_set(hevi_ctx *ctx, const hevi_shape *shape,
                                       const double *d_gz, const double *d_rho0,
                                       const double *d_q0, hevi_ops **out,
                                       hipStream_t stream);
+/* LHEVI-PS (Sec. 4.3.1): the linear operator is the Jacobian of the set-2C vertical
+ * operator at a moving state q0 = (rho0, U0, Theta0), a previous solution, instead of a
+ * state at rest: the flux Jacobian K(q0) of Appendix A.3 (eq. set2c_jacobian, re-derived
+ * from the fluxes of Appendix A.2) with u0 = U0/rho0 and w = grad(zeta).u0 gives the
+ * advection entries K[U_l][rho] = -u0_l w, K[U_l][U_m] = delta_lm w + u0_l gz_m,
+ * K[Theta][rho] = -theta0 w, K[Theta][Theta] = w besides the rest-state ones.  d_U0 is
+ * the state's momentum [m][k][c] (its normal part should vanish at the bottom and top
+ * nodes, as the rigid lid requires); the other inputs as hevi_build_column_ops.  The
+ * rho-theta and momentum blocks of I - lambda L_z are then not identities, so these
+ * operators factor the whole 5 n_z band with partial pivoting (the paper's LAPACK band
+ * LU, Sec. 4.2.2; kl = ku = 5(N+1) - 1): hevi_factor / hevi_refactor store U (2 kl + 1
+ * entries per row), the kl multipliers and the pivot offsets per column, FP64 only
+ * (HEVI_FP32_REFINE gives HEVI_E_INVALID), N <= 5 and n_z <= 546 (else HEVI_E_SHAPE);
+ * hevi_stage_solve solves directly (its refine argument is ignored), hevi_apply_op applies
+ * L_z(q0).  hevi_factors_band_entries, hevi_solve_noalloc, groups and the server take
+ * reference-state operators only (HEVI_E_INVALID).  The operator holds 11 FP64 per node. */
+hevi_status hevi_build_column_ops_ps(hevi_ctx *ctx, const hevi_shape *shape,
+                                     const hevi_consts *consts, const double *d_z,
+                                     const double *d_J, const double *d_gz,
+                                     const double *d_rho0, const double *d_U0,
+                                     const double *d_Theta0, hevi_ops **out,
+                                     hipStream_t stream);
+/* New linearisation state for an LHEVI-PS operator, in place (no allocation, no wait):
+ * the state-dependent fields are rewritten from (rho0, U0, Theta0); the geometry stays.
+ * The paper refreshes the state every few steps (5 by default, Sec. 4.3.1); follow it
+ * with hevi_refactor.  Invalid values are reported by hevi_ops_check. */
+hevi_status hevi_ops_relinearize(hevi_ctx *ctx, hevi_ops *ops, const double *d_rho0,
+                                 const double *d_U0, const double *d_Theta0,
+                                 hipStream_t stream);
 /* Waits for `stream` and reports the first column whose inputs were invalid
  * (non-positive J/rho0/Theta0, zero grad(zeta), non-finite values). */
 hevi_status hevi_ops_check(hevi_ctx *ctx, const hevi_ops *ops, int64_t *first_bad_col,

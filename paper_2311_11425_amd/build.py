@@ -11,8 +11,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhevi.so")
-SOURCES = ["hevi_kernels.hip", "hevi_kernels3c.hip", "hevi_group.hip", "hevi_noalloc.hip",
-           "hevi_api.cpp",
+SOURCES = ["hevi_kernels.hip", "hevi_kernels3c.hip", "hevi_ps.hip", "hevi_group.hip",
+           "hevi_noalloc.hip", "hevi_api.cpp",
            "hevi_group_api.cpp", "hevi_serve.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -57,7 +57,7 @@ def build(verbose: bool = False, only_changed: bool = False) -> str:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
 
-    with ThreadPoolExecutor(max_workers=max(1, min(len(jobs), 6))) as ex:
+    with ThreadPoolExecutor(max_workers=max(1, min(len(jobs), 8))) as ex:
         for f in [ex.submit(run, c) for c in jobs]:
             f.result()
     tmp = LIB + ".tmp"

@@ -164,6 +164,7 @@ hevi_status hevi_build_column_ops_set(hevi_ctx* ctx, const hevi_shape* shape,
   o->d_tilt = nullptr;
   o->tilted = 0;
   o->s3 = eqset == HEVI_SET_3C;
+  o->ps = 0;
   // set 3C: one more per-node field (J dP/drho) after the tile-interleaved eight
   if ((s = dev_alloc(&o->d_ops, tiles_nodes(o->sh) * (HEVI_NOPS + o->s3) * sizeof(double))) ||
       (s = dev_alloc(&o->d_info, sizeof(HeviDevInfo))) ||
@@ -185,6 +186,70 @@ hevi_status hevi_build_column_ops_set(hevi_ctx* ctx, const hevi_shape* shape,
   }
   o->tilted = tilt != 0;
   *out = o;
+  return HEVI_OK;
+}
+
+hevi_status hevi_build_column_ops_ps(hevi_ctx* ctx, const hevi_shape* shape,
+                                     const hevi_consts* k, const double* d_z, const double* d_J,
+                                     const double* d_gz, const double* d_rho0,
+                                     const double* d_U0, const double* d_Theta0, hevi_ops** out,
+                                     hipStream_t stream) {
+  if (!ctx || !out || !k) return HEVI_E_INVALID;
+  *out = nullptr;
+  hevi_status s = check_shape(shape);
+  if (s) return s;
+  if (shape->order_N > HEVI_PS_MAXN) return HEVI_E_SHAPE;
+  if (!(k->R > 0) || !(k->cp > k->R) || !(k->g >= 0) || !(k->p_A > 0) || !std::isfinite(k->R) ||
+      !std::isfinite(k->cp) || !std::isfinite(k->g) || !std::isfinite(k->p_A))
+    return HEVI_E_INVALID;
+  if (shape->n_cols > 0 && (!d_z || !d_J || !d_gz || !d_rho0 || !d_U0 || !d_Theta0))
+    return HEVI_E_INVALID;
+  if (!ok(hipSetDevice(ctx->device))) return HEVI_E_DEVICE;
+  hevi_ops* o = new (std::nothrow) hevi_ops;
+  if (!o) return HEVI_E_NOMEM;
+  o->ctx = ctx;
+  o->shape = *shape;
+  o->consts = *k;
+  o->sh = dev_shape(*shape);
+  o->d_ops = nullptr;
+  o->d_info = nullptr;
+  o->d_tilt = nullptr;
+  o->tilted = 0;
+  o->s3 = 0;
+  o->ps = 1;
+  // the eight fields, then the three velocity planes of the linearisation state
+  if ((s = dev_alloc(&o->d_ops, tiles_nodes(o->sh) * (HEVI_NOPS + 3) * sizeof(double))) ||
+      (s = dev_alloc(&o->d_info, sizeof(HeviDevInfo))) ||
+      (s = dev_alloc(&o->d_tilt, sizeof(int32_t)))) {
+    hevi_ops_free(o);
+    return s;
+  }
+  int32_t tilt = 0;
+  if (!ok(hipMemcpyAsync(o->d_tilt, &tilt, sizeof(tilt), hipMemcpyHostToDevice, stream)) ||
+      !ok(hevi_launch_info_reset(o->d_info, stream)) ||
+      !ok(hevi_launch_build_ops(o->sh, 0, k->R, k->cp, k->g, k->p_A, d_z, d_J, d_gz, d_rho0,
+                                d_Theta0, o->d_ops, o->d_info, o->d_tilt, stream)) ||
+      !ok(hevi_launch_ps_state(o->sh, k->R, k->cp, k->p_A, d_rho0, d_U0, d_Theta0, o->d_ops,
+                               o->d_info, stream)) ||
+      !ok(hipMemcpyAsync(&tilt, o->d_tilt, sizeof(tilt), hipMemcpyDeviceToHost, stream)) ||
+      !ok(hipStreamSynchronize(stream))) {
+    hevi_ops_free(o);
+    return HEVI_E_DEVICE;
+  }
+  o->tilted = tilt != 0;
+  *out = o;
+  return HEVI_OK;
+}
+
+hevi_status hevi_ops_relinearize(hevi_ctx* ctx, hevi_ops* ops, const double* d_rho0,
+                                 const double* d_U0, const double* d_Theta0, hipStream_t stream) {
+  if (!ctx || !ops || !ops->ps) return HEVI_E_INVALID;
+  if (ops->sh.ncols > 0 && (!d_rho0 || !d_U0 || !d_Theta0)) return HEVI_E_INVALID;
+  if (!ok(hipSetDevice(ctx->device))) return HEVI_E_DEVICE;
+  const hevi_consts& k = ops->consts;
+  if (!ok(hevi_launch_ps_state(ops->sh, k.R, k.cp, k.p_A, d_rho0, d_U0, d_Theta0, ops->d_ops,
+                               ops->d_info, stream)))
+    return HEVI_E_DEVICE;
   return HEVI_OK;
 }
 
@@ -213,8 +278,10 @@ hevi_status hevi_apply_op(hevi_ctx* ctx, const hevi_ops* ops, const double* d_x,
     if (d_y == d_x || (d_xref && d_y == d_xref)) return HEVI_E_INVALID;
   }
   if (!ok(hipSetDevice(ctx->device))) return HEVI_E_DEVICE;
-  if (!ok(hevi_launch_apply(ops->sh, ops->s3, ops->d_ops, d_x, d_xref, d_y, stream)))
-    return HEVI_E_DEVICE;
+  const hipError_t e = ops->ps ? hevi_launch_apply_ps(ops->sh, ops->d_ops, d_x, d_xref, d_y, stream)
+                               : hevi_launch_apply(ops->sh, ops->s3, ops->d_ops, d_x, d_xref, d_y,
+                                                   stream);
+  if (!ok(e)) return HEVI_E_DEVICE;
   return HEVI_OK;
 }
 
@@ -264,14 +331,27 @@ hevi_status hevi_host::factor_impl(hevi_ctx* ctx, const hevi_ops* ops, double la
     return stream_ordered ? dev_alloc_on(p, bytes, stream) : dev_alloc(p, bytes);
   };
   hevi_status s;
-  if ((s = alloc(&f->U, tn * (4 * N + 1) * fs)) || (s = alloc(&f->L, tn * 2 * N * fs)) ||
+  if (ops->ps) {
+    // LHEVI-PS: the full 5 n_z band in FP64, column-contiguous
+    if (prec != HEVI_FP64) { delete f; return HEVI_E_INVALID; }
+    if (N > HEVI_PS_MAXN || sh.nz > kPsMaxNz) { delete f; return HEVI_E_SHAPE; }
+    const size_t n = 5 * (size_t)sh.nz, nc = (size_t)sh.ncols;
+    if ((s = alloc(&f->U, nc * n * hevi_ps_band_width(N) * sizeof(double))) ||
+        (s = alloc(&f->L, nc * n * hevi_ps_lower_width(N) * sizeof(double))) ||
+        (s = alloc(&f->piv, 2 * nc * n)) || (s = alloc(&f->d_info, sizeof(HeviDevInfo)))) {
+      hevi_factors_free(f);
+      return s;
+    }
+  } else if ((s = alloc(&f->U, tn * (4 * N + 1) * fs)) || (s = alloc(&f->L, tn * 2 * N * fs)) ||
       (s = alloc(&f->piv, kFactorPlanes * tn)) ||
       (s = alloc(&f->ws, tn * HEVI_NWS * sizeof(double))) ||
       (s = alloc(&f->d_info, sizeof(HeviDevInfo)))) {
     hevi_factors_free(f);
     return s;
   }
-  if (!needs_sbuf(sh, prec)) {
+  if (ops->ps) {
+    f->sbuf = nullptr;
+  } else if (!needs_sbuf(sh, prec)) {
     // FP64 factors assemble in place of U; the fused factorisation needs no buffer
     f->sbuf = prec == HEVI_FP64 ? (double*)f->U : nullptr;
   } else if ((s = alloc(&f->sbuf, tn * (4 * N + 1) * sizeof(double)))) {
@@ -298,9 +378,12 @@ hevi_status hevi_refactor(hevi_ctx* ctx, hevi_factors* f, double lambda, hipStre
   if (!ok(hipSetDevice(ctx->device))) return HEVI_E_DEVICE;
   f->lambda = lambda;
   const hevi_ops* o = f->ops;
-  if (!ok(hevi_launch_factor(o->sh, o->s3, lambda, f->prec == HEVI_FP32_REFINE, o->d_ops,
-                             f->sbuf, f->U, f->L, f->piv, f->d_info, stream)))
-    return HEVI_E_DEVICE;
+  const hipError_t e =
+      o->ps ? hevi_launch_ps_factor(o->sh, lambda, o->d_ops, (double*)f->U, (double*)f->L, f->piv,
+                                    f->d_info, stream)
+            : hevi_launch_factor(o->sh, o->s3, lambda, f->prec == HEVI_FP32_REFINE, o->d_ops,
+                                 f->sbuf, f->U, f->L, f->piv, f->d_info, stream);
+  if (!ok(e)) return HEVI_E_DEVICE;
   return HEVI_OK;
 }
 
@@ -312,7 +395,7 @@ hevi_status hevi_factors_check(hevi_ctx* ctx, const hevi_factors* f, hevi_info* 
 
 hevi_status hevi_factors_band_entries(hevi_ctx* ctx, const hevi_factors* f, int64_t* u_entries,
                                       hipStream_t stream) {
-  if (!ctx || !f || !u_entries) return HEVI_E_INVALID;
+  if (!ctx || !f || !u_entries || f->ops->ps) return HEVI_E_INVALID;
   if (!ok(hipSetDevice(ctx->device))) return HEVI_E_DEVICE;
   const HeviShapeDev& sh = f->ops->sh;
   const size_t tn = tiles_nodes(sh);
@@ -378,11 +461,13 @@ hevi_status hevi_stage_solve(hevi_ctx* ctx, const hevi_factors* f, int32_t n_e,
   if (f->prec == HEVI_FP64) sweeps = 0;
   if (!ok(hipSetDevice(ctx->device))) return HEVI_E_DEVICE;
   if (h_info && !ok(hevi_launch_info_reset(f->d_info, stream))) return HEVI_E_DEVICE;
-  if (!ok(hevi_launch_stage_solve(o->sh, o->s3, f->lambda, o->tilted, f->prec == HEVI_FP32_REFINE,
-                                  o->d_ops,
-                                  f->U, f->L, f->piv, f->ws, E, Q, d_Qi, sweeps, target, full,
-                                  f->d_info, stream)))
-    return HEVI_E_DEVICE;
+  const hipError_t e =
+      o->ps ? hevi_launch_ps_stage(o->sh, o->d_ops, (const double*)f->U, (const double*)f->L,
+                                   f->piv, E, Q, d_Qi, f->d_info, stream)
+            : hevi_launch_stage_solve(o->sh, o->s3, f->lambda, o->tilted,
+                                      f->prec == HEVI_FP32_REFINE, o->d_ops, f->U, f->L, f->piv,
+                                      f->ws, E, Q, d_Qi, sweeps, target, full, f->d_info, stream);
+  if (!ok(e)) return HEVI_E_DEVICE;
   if (h_info) {
     std::memset(h_info, 0, sizeof(*h_info));
     hevi_status r = read_info(f->d_info, stream, h_info, true);

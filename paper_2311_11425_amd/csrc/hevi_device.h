@@ -102,12 +102,21 @@ struct OpsView {
 };
 
 // Set 3C: the ninth per-node operator field J dP/drho, stored [tile][k][lane]
-// after the eight tile-interleaved fields of the compact operator.
+// after the eight tile-interleaved fields of the compact operator.  LHEVI-PS
+// operators hold instead three planes there: the velocity u0 = U0/rho0 of the
+// linearisation state (ps_plane(ops, sh, m), m = 0..2).
 __device__ __forceinline__ size_t pr_offset(const HeviShapeDev& sh) {
   return (size_t)sh.ntiles * sh.nz * HEVI_NOPS * T;
 }
 __device__ __forceinline__ const double* pr_plane(const double* ops, const HeviShapeDev& sh) {
   return ops + pr_offset(sh);
+}
+__device__ __forceinline__ size_t plane_elems(const HeviShapeDev& sh) {
+  return (size_t)sh.ntiles * sh.nz * T;
+}
+__device__ __forceinline__ const double* ps_plane(const double* ops, const HeviShapeDev& sh,
+                                                  int m) {
+  return ops + pr_offset(sh) + (size_t)m * plane_elems(sh);
 }
 
 // v_rho = Drho u and v_Th = DTh u for all nodes; u read from scratch field
@@ -232,7 +241,7 @@ __device__ __forceinline__ Chunk chunk_of(int Ne, int64_t tile, int cw = 1) {
 // a0: y = L_z (x - x_ref).  Each element iteration loads everything it needs
 // unconditionally (clamped indices), computes, then stores the owned nodes, so
 // the loads of an element are in flight together.
-template <int N, bool HAS_REF, bool S3 = false>
+template <int N, bool HAS_REF, bool S3 = false, bool PS = false>
 __device__ __forceinline__ void b_apply(int64_t tile_, HeviShapeDev sh, Gll<N> tab,
                                         const double* __restrict__ ops,
                                         const double* __restrict__ x,
@@ -259,34 +268,56 @@ __device__ __forceinline__ void b_apply(int64_t tile_, HeviShapeDev sh, Gll<N> t
   // loads are reduced at once to what the element sums use (u times J and J theta0,
   // the pressure J (c x_T [+ dP/drho x_rho])), so few values stay live.
   double kg0 = 0.0, kg1 = 0.0, kg2 = 0.0, kmi = 0.0, kph = 0.0, kxr = 0.0;
-  double kJu = 0.0, kJtu = 0.0, kp = 0.0;
+  double kJu = 0.0, kJtu = 0.0, kp = 0.0, kf0 = 0.0, kf1 = 0.0, kf2 = 0.0;
+  // LHEVI-PS: the velocity planes of the linearisation state
+  const double* u0p = PS ? ps_plane(ops, sh, 0) : nullptr;
+  const size_t pe = PS ? plane_elems(sh) : 0;
   auto element = [&](const int e, auto first) {
     constexpr bool FIRST = decltype(first)::value;
     // ---- loads ----
     double g0[N + 1], g1[N + 1], g2[N + 1], mi[N + 1], ph[N + 1], xr[N + 1];
-    double Ju[N + 1], Jtu[N + 1], pp[N + 1];
+    double Ju[N + 1], Jtu[N + 1], pp[N + 1], f0[N + 1], f1[N + 1], f2[N + 1];
 #pragma unroll
     for (int j = 0; j <= N; ++j) {
       if (!FIRST && j == 0) {
         g0[0] = kg0; g1[0] = kg1; g2[0] = kg2; mi[0] = kmi; ph[0] = kph; xr[0] = kxr;
         Ju[0] = kJu; Jtu[0] = kJtu; pp[0] = kp;
+        f0[0] = kf0; f1[0] = kf1; f2[0] = kf2;
         continue;
       }
       const int k = e * N + j;
       g0[j] = op(k, OP_GX); g1[j] = op(k, OP_GY); g2[j] = op(k, OP_GZ);
       mi[j] = op(k, OP_MINV); ph[j] = op(k, OP_PHI);
       xr[j] = X(0, k);
-      const double u = g0[j] * X(1, k) + g1[j] * X(2, k) + g2[j] * X(3, k);
+      const double x1 = X(1, k), x2 = X(2, k), x3 = X(3, k), xt = X(4, k);
+      const double u = g0[j] * x1 + g1[j] * x2 + g2[j] * x3;
       Ju[j] = op(k, OP_J) * u;
-      Jtu[j] = op(k, OP_JTH) * u;
-      pp[j] = op(k, OP_JCT) * X(4, k);
-      if constexpr (S3) pp[j] += op.jpr(k) * xr[j];
+      if constexpr (PS) {
+        // fluxes linearised at (rho0, U0, Theta0), u0 = U0/rho0, w = grad(zeta).u0:
+        //   J F_Theta' = J theta0 (u - w rho') + J w Theta'
+        //   J F_U'     = J c_Theta Theta' grad(zeta) + J (w U' + u0 (u - w rho'))
+        const size_t ip = ((size_t)tile * nz + k) * T + lane;
+        const double a0 = u0p[ip], a1 = u0p[ip + pe], a2 = u0p[ip + 2 * pe];
+        const double Jk = op(k, OP_J);
+        const double w = g0[j] * a0 + g1[j] * a1 + g2[j] * a2;
+        const double uw = u - w * xr[j];
+        Jtu[j] = op(k, OP_JTH) * uw + Jk * w * xt;
+        const double pc = op(k, OP_JCT) * xt;
+        f0[j] = pc * g0[j] + Jk * (w * x1 + a0 * uw);
+        f1[j] = pc * g1[j] + Jk * (w * x2 + a1 * uw);
+        f2[j] = pc * g2[j] + Jk * (w * x3 + a2 * uw);
+      } else {
+        Jtu[j] = op(k, OP_JTH) * u;
+        pp[j] = op(k, OP_JCT) * xt;
+        if constexpr (S3) pp[j] += op.jpr(k) * xr[j];
+      }
     }
     // ---- element sums ----
-    double f0[N + 1], f1[N + 1], f2[N + 1];
+    if constexpr (!PS) {
 #pragma unroll
-    for (int j = 0; j <= N; ++j) {
-      f0[j] = pp[j] * g0[j]; f1[j] = pp[j] * g1[j]; f2[j] = pp[j] * g2[j];
+      for (int j = 0; j <= N; ++j) {
+        f0[j] = pp[j] * g0[j]; f1[j] = pp[j] * g1[j]; f2[j] = pp[j] * g2[j];
+      }
     }
     double yo[N + 1][5];
 #pragma unroll
@@ -323,7 +354,9 @@ __device__ __forceinline__ void b_apply(int64_t tile_, HeviShapeDev sh, Gll<N> t
       }
     }
     kg0 = g0[N]; kg1 = g1[N]; kg2 = g2[N]; kmi = mi[N]; kph = ph[N]; kxr = xr[N];
-    kJu = Ju[N]; kJtu = Jtu[N]; kp = pp[N];
+    kJu = Ju[N]; kJtu = Jtu[N];
+    if constexpr (PS) { kf0 = f0[N]; kf1 = f1[N]; kf2 = f2[N]; }
+    else kp = pp[N];
   };
   int e = max(ch.e0 - 1, 0);
   element(e, std::true_type{});

@@ -264,7 +264,7 @@ hevi_status hevi_group_create(hevi_ctx* ctx, int32_t n, const hevi_group_member*
   for (int p = 0; p < n; ++p) {
     const hevi_group_member& m = members[p];
     if (!m.ops || m.ops->ctx->device != ctx->device) return HEVI_E_INVALID;
-    if (m.ops->s3) return HEVI_E_INVALID;  // the group kernels are set-2C instances
+    if (m.ops->s3 || m.ops->ps) return HEVI_E_INVALID;  // the group kernels: set 2C at rest
     if (m.ops->sh.ncols == 0) continue;
     std::vector<const void*> outs{m.d_out};
     for (int i = 1; i < s; ++i) outs.push_back(m.d_Q[i]);

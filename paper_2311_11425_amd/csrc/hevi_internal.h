@@ -76,6 +76,27 @@ hipError_t hevi_launch_stage_solve_3c(const HeviShapeDev& sh, double lambda, int
                                       double rel_target, int full_sweeps, HeviDevInfo* info,
                                       hipStream_t st);
 
+// LHEVI-PS (hevi_ps.hip): the full 5 n_z band, one wavefront per column, N <= 5.
+// Operators hold the velocity planes of the linearisation state after the eight
+// fields (HEVI_NOPS + 3 planes); factors U [ncols][n][W], L [ncols][n][KL], pivot
+// offsets [ncols][n] then row-scale exponents [ncols][n] (bytes), n = 5 n_z,
+// KL = hevi_ps_lower_width(N), W = hevi_ps_band_width(N).
+#define HEVI_PS_MAXN 5
+int hevi_ps_band_width(int N);
+int hevi_ps_lower_width(int N);
+hipError_t hevi_launch_ps_factor(const HeviShapeDev& sh, double lambda, const double* ops,
+                                 double* U, double* L, uint8_t* piv, HeviDevInfo* info,
+                                 hipStream_t st);
+hipError_t hevi_launch_ps_stage(const HeviShapeDev& sh, const double* ops, const double* U,
+                                const double* L, const uint8_t* piv, const HeviTerms& E,
+                                const HeviTerms& Q, double* Qi, HeviDevInfo* info,
+                                hipStream_t st);
+hipError_t hevi_launch_apply_ps(const HeviShapeDev& sh, const double* ops, const double* x,
+                                const double* xref, double* y, hipStream_t st);
+hipError_t hevi_launch_ps_state(const HeviShapeDev& sh, double R, double cp, double pA,
+                                const double* rho0, const double* U0, const double* Th0,
+                                double* ops, HeviDevInfo* info, hipStream_t st);
+
 hipError_t hevi_launch_combine(int64_t n, const HeviTerms& V, double* out, hipStream_t st);
 
 hipError_t hevi_launch_info_reset(HeviDevInfo* info, hipStream_t st);

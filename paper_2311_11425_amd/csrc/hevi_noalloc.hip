@@ -78,7 +78,7 @@ hevi_status hevi_solve_noalloc(hevi_ctx* ctx, const hevi_ops* ops, double lambda
                                const hevi_refine* refine, hevi_info* h_info,
                                hipStream_t stream) {
   using namespace hevi_host;
-  if (!ctx || !ops) return HEVI_E_INVALID;
+  if (!ctx || !ops || ops->ps) return HEVI_E_INVALID;  // LHEVI-PS factors: hevi_factor
   if (prec != HEVI_FP64 && prec != HEVI_FP32_REFINE) return HEVI_E_INVALID;
   if (!(lambda >= 0.0) || !std::isfinite(lambda)) return HEVI_E_INVALID;
   const HeviShapeDev& sh = ops->sh;

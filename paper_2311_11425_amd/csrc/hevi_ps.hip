@@ -1,0 +1,430 @@
+// hevi_ps.hip -- LHEVI-PS column solves (Sec. 4.3.1): the linear operator is the
+// Jacobian of the set-2C vertical operator at a moving state q0 = (rho0, U0, Theta0)
+// (a previous solution), not at a state at rest.
+//
+// With U0 != 0 the flux Jacobian K(q0) (Appendix A.3, eq. set2c_jacobian at a
+// general state) has advection entries w = grad(zeta).u0 on its diagonal blocks,
+// so the rho-theta and momentum blocks of A = I - lambda L_z are no longer
+// identities and the exact elimination of the reference-state path does not
+// apply.  These kernels factor the whole 5 n_z band instead, as the paper does with
+// LAPACK's banded LU (Sec. 4.2.2): unknown (node k, variable v) at 5k + v, KL =
+// 5(N+1) - 1 sub- and super-diagonals, U rows of width W = 2 KL + 1 (partial
+// pivoting fills KL more super-diagonals).
+//
+// Mapping: one wavefront per column.  Lane l holds window column l of the
+// (KL + 1) x W active window of the band LU (rows j..j+KL, columns j..j+W-1) in
+// registers; step j takes the pivot from lane 0's column (largest magnitude, lowest
+// row on ties), broadcasts the multipliers, eliminates, stores U row j (W lanes),
+// the KL multipliers and the pivot offset, and shifts the window one lane to the
+// left, computing the entering row of A on the fly from the compact operator.
+// The stage solve runs the substitutions with the window of the vector in
+// registers and q^E, q^ and the solution of the column in LDS.
+//
+// Rows are equilibrated as they enter the window: each row of A is scaled by 2^-e,
+// e the binary exponent of its largest entry (exact; LAPACK's row equilibration with
+// power-of-two scales).  The rows of A mix variables of very different size (the
+// continuity, momentum and rho-theta rows), and unscaled pivoting on them lost a digit
+// at the ne = 30 shape; the solves scale the right-hand side the same way.
+//
+// Factor storage per column (column-contiguous, the paper's layout of the band):
+// U [n][W], L [n][KL] (multipliers of step j for rows j+1..j+KL), pivot offsets
+// [n] bytes, then (after all columns' offsets) the row exponents e [n] (signed bytes),
+// n = 5 n_z.  At N = 4, n_z = 41: 119,925 bytes per column.
+#include "hevi_device.h"
+
+namespace {
+
+template <int N>
+constexpr int kPsKL = 5 * (N + 1) - 1;
+template <int N>
+constexpr int kPsW = 2 * kPsKL<N> + 1;
+
+__device__ __forceinline__ double bcast(double v, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double sel3(int m, double a, double b, double c) {
+  return m == 0 ? a : (m == 1 ? b : c);
+}
+
+// The operator of one column as the PS kernels read it (lane-dependent nodes).
+struct PsCol {
+  const double* ops;
+  const double* u0;  // velocity planes of the linearisation state
+  size_t pe;         // elements per plane
+  int64_t tile;
+  int nz, Ne, cl;    // cl: the column's lane within its tile
+  __device__ __forceinline__ double op(int k, int f) const {
+    return ops[tix(tile, nz, k, HEVI_NOPS, f, cl)];
+  }
+  __device__ __forceinline__ double u(int k, int m) const {
+    return u0[(size_t)m * pe + ((size_t)tile * nz + k) * T + cl];
+  }
+};
+
+// Entry (r, c) of A = I - lambda L_z (zero outside the matrix or the band):
+//   L_z = -M^-1 B - gravity,  B_(k,a),(kc,b) = sum over the elements e holding both
+//   nodes of  w_i D_ij J_kc K_kc[a][b]  (a > 0, strong)  or  -w_j D_ji J_kc K_kc[0][b]
+//   (the continuity row, weak), i, j the local indices of k, kc in e; the momentum rows
+//   of the bottom and top nodes are identity rows (rigid lid).  K at the state q0,
+//   u0 = U0/rho0, w = grad(zeta).u0:
+//   K[rho][U_m] = g_m;  K[U_l][rho] = -u0_l w, K[U_l][U_m] = delta_lm w + u0_l g_m,
+//   K[U_l][Theta] = g_l c_Theta;  K[Theta][rho] = -theta0 w, K[Theta][U_m] = theta0 g_m,
+//   K[Theta][Theta] = w.
+template <int N>
+__device__ double ps_entry(const PsCol& P, const double* Dsh, const double* wsh,
+                           double lambda, int r, int c) {
+  const int nz = P.nz, n = 5 * nz;
+  if (r < 0 || r >= n || c < 0 || c >= n) return 0.0;
+  const int k = r / 5, a = r - 5 * k, kc = c / 5, b = c - 5 * kc;
+  const double delta = r == c ? 1.0 : 0.0;
+  if (a >= 1 && a <= 3 && (k == 0 || k == nz - 1)) return delta;
+  const int dk = kc - k;
+  if (dk > N || dk < -N) return delta;
+  const double J = P.op(kc, OP_J);
+  const double g0 = P.op(kc, OP_GX), g1 = P.op(kc, OP_GY), g2 = P.op(kc, OP_GZ);
+  const double v0 = P.u(kc, 0), v1 = P.u(kc, 1), v2 = P.u(kc, 2);
+  const double w = g0 * v0 + g1 * v1 + g2 * v2;
+  double JK;
+  if (a == 0) {
+    JK = (b >= 1 && b <= 3) ? J * sel3(b - 1, g0, g1, g2) : 0.0;
+  } else if (a <= 3) {
+    const double ul = sel3(a - 1, v0, v1, v2);
+    if (b == 0) JK = -J * ul * w;
+    else if (b <= 3) JK = J * ((a == b ? w : 0.0) + ul * sel3(b - 1, g0, g1, g2));
+    else JK = sel3(a - 1, g0, g1, g2) * P.op(kc, OP_JCT);
+  } else {
+    const double Jth = P.op(kc, OP_JTH);
+    if (b == 0) JK = -Jth * w;
+    else if (b <= 3) JK = Jth * sel3(b - 1, g0, g1, g2);
+    else JK = J * w;
+  }
+  double Bs = 0.0;
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    // the element in which k is local node N (side 0) or local node < N (side 1)
+    const int e = side == 0 ? ((k % N == 0) ? k / N - 1 : -1) : k / N;
+    if (e < 0 || e >= P.Ne) continue;
+    const int i = k - e * N, j = kc - e * N;
+    if (j < 0 || j > N) continue;
+    const double coef = a == 0 ? -wsh[j] * Dsh[j * (N + 1) + i] : wsh[i] * Dsh[i * (N + 1) + j];
+    Bs += coef * JK;
+  }
+  double L = -P.op(k, OP_MINV) * Bs;
+  if (kc == k && b == 0 && a >= 1 && a <= 3) L -= P.op(k, OP_PHI) * sel3(a - 1, g0, g1, g2);
+  return delta - lambda * L;
+}
+
+// Scales the row held across the lanes (one entry per lane) by 2^-e, e the binary
+// exponent of its largest magnitude (clamped to a signed byte), and returns e.
+__device__ __forceinline__ int ps_scale_row(double& v) {
+  double m = fabs(v);
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  int e = 0;
+  if (m > 0.0 && isfinite(m)) {
+    frexp(m, &e);
+    e = min(max(e, -120), 120);
+  }
+  v = ldexp(v, -e);
+  return e;
+}
+
+template <int N>
+__device__ __forceinline__ void load_tables(double* Dsh, double* wsh) {
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < (N + 1) * (N + 1); ++q) Dsh[q] = Gll<N>::D[q];
+#pragma unroll
+    for (int q = 0; q <= N; ++q) wsh[q] = Gll<N>::w[q];
+  }
+  __syncthreads();
+}
+
+template <int N>
+__global__ __launch_bounds__(64) void k_ps_factor(HeviShapeDev sh, double lambda,
+                                                  const double* __restrict__ ops,
+                                                  double* __restrict__ Ub,
+                                                  double* __restrict__ Lb,
+                                                  uint8_t* __restrict__ piv, HeviDevInfo* info) {
+  constexpr int KL = kPsKL<N>, W = kPsW<N>;
+  static_assert(W <= 64, "one wavefront holds the window");
+  __shared__ double Dsh[(N + 1) * (N + 1)], wsh[N + 1];
+  load_tables<N>(Dsh, wsh);
+  const int lane = threadIdx.x;
+  const int64_t col = blockIdx.x;
+  const int nz = sh.nz, n = 5 * nz;
+  const PsCol P{ops, ps_plane(ops, sh, 0), plane_elems(sh), col / T, nz, sh.Ne, (int)(col % T)};
+  double* Ur = Ub + (size_t)col * n * W;
+  double* Lr = Lb + (size_t)col * n * KL;
+  uint8_t* pr = piv + (size_t)col * n;
+  int8_t* er = (int8_t*)piv + (size_t)sh.ncols * n + (size_t)col * n;
+  double a[KL + 1];
+#pragma unroll
+  for (int i = 0; i <= KL; ++i) {
+    a[i] = lane < W ? ps_entry<N>(P, Dsh, wsh, lambda, i, lane) : 0.0;
+    const int e = ps_scale_row(a[i]);
+    if (lane == 0 && i < n) er[i] = (int8_t)e;
+  }
+  bool singular = false;
+  for (int j = 0; j < n; ++j) {
+    // pivot of column j (lane 0): largest magnitude among rows j..j+KL inside the matrix
+    const int rmax = min(KL, n - 1 - j);
+    double best = fabs(a[0]);
+    int p = 0;
+#pragma unroll
+    for (int i = 1; i <= KL; ++i) {
+      const double v = fabs(a[i]);
+      if (i <= rmax && v > best) { best = v; p = i; }
+    }
+    p = __builtin_amdgcn_readfirstlane(p);
+    if (p != 0) {
+#pragma unroll
+      for (int i = 1; i <= KL; ++i)
+        if (i == p) { const double t = a[0]; a[0] = a[i]; a[i] = t; }
+    }
+    const double pv = bcast(a[0], 0);
+    if (pv == 0.0) singular = true;
+    const double rp = pv != 0.0 ? 1.0 / pv : 0.0;
+    double Lv = 0.0;
+#pragma unroll
+    for (int i = 1; i <= KL; ++i) {
+      const double m = bcast(a[i], 0) * rp;
+      if (lane == i - 1) Lv = m;
+      a[i] -= m * a[0];
+    }
+    if (lane < W) Ur[(size_t)j * W + lane] = a[0];
+    if (lane < KL) Lr[(size_t)j * KL + lane] = Lv;
+    if (lane == 0) pr[j] = (uint8_t)p;
+    // next window: rows j+1..j+1+KL, columns j+1..j+W (lanes >= W hold zeros)
+#pragma unroll
+    for (int i = 0; i < KL; ++i) a[i] = __shfl_down(a[i + 1], 1);
+    a[KL] = lane < W ? ps_entry<N>(P, Dsh, wsh, lambda, j + 1 + KL, j + 1 + lane) : 0.0;
+    const int e = ps_scale_row(a[KL]);
+    if (lane == 0 && j + 1 + KL < n) er[j + 1 + KL] = (int8_t)e;
+  }
+  if (singular && lane == 0) flag(info, 5 /*HEVI_E_SINGULAR*/, col);
+}
+
+// One stage solve: q^E = sum e_t E_t, q^ = q^E + sum c_j Q_j, A x = P(q^) with the
+// band factors (P the rigid-lid projection of the momentum at the bottom and top
+// nodes), Q_i = q^E + (x - q^) (= x - sum c_j Q_j, Sec. 4.3 eq. lhevi-ark-final-3).
+// Dynamic LDS: 3 n doubles (q^, q^E, and P(q^) overwritten by the solution).
+template <int N>
+__global__ __launch_bounds__(64) void k_ps_stage(HeviShapeDev sh, const double* __restrict__ ops,
+                                                 const double* __restrict__ Ub,
+                                                 const double* __restrict__ Lb,
+                                                 const uint8_t* __restrict__ piv, HeviTerms E,
+                                                 HeviTerms Q, double* __restrict__ Qi,
+                                                 HeviDevInfo* info) {
+  constexpr int KL = kPsKL<N>, W = kPsW<N>;
+  extern __shared__ double sm[];
+  const int lane = threadIdx.x;
+  const int64_t col = blockIdx.x;
+  const int nz = sh.nz, n = 5 * nz;
+  const int64_t nc = sh.ncols;
+  double* qh = sm;
+  double* qe = sm + n;
+  double* xs = sm + 2 * n;
+  for (int r = lane; r < n; r += T) {
+    const int k = r / 5, v = r - 5 * k;
+    const size_t ix = cix(nz, nc, v, k, col);
+    double e = 0.0;
+    for (int t = 0; t < E.n; ++t) e += E.coef[t] * E.v[t][ix];
+    double h = e;
+    for (int t = 0; t < Q.n; ++t) h += Q.coef[t] * Q.v[t][ix];
+    qe[r] = e;
+    qh[r] = h;
+    xs[r] = h;
+  }
+  __syncthreads();
+  if (lane < 2) {
+    const int k = lane == 0 ? 0 : nz - 1;
+    const int64_t tile = col / T;
+    const int cl = (int)(col % T);
+    const double g0 = ops[tix(tile, nz, k, HEVI_NOPS, OP_GX, cl)];
+    const double g1 = ops[tix(tile, nz, k, HEVI_NOPS, OP_GY, cl)];
+    const double g2 = ops[tix(tile, nz, k, HEVI_NOPS, OP_GZ, cl)];
+    const double inv = 1.0 / sqrt(g0 * g0 + g1 * g1 + g2 * g2);
+    const double n0 = g0 * inv, n1 = g1 * inv, n2 = g2 * inv;
+    double* b = xs + 5 * k;
+    const double d = n0 * b[1] + n1 * b[2] + n2 * b[3];
+    b[1] -= n0 * d; b[2] -= n1 * d; b[3] -= n2 * d;
+  }
+  __syncthreads();
+  const double* Ur = Ub + (size_t)col * n * W;
+  const double* Lr = Lb + (size_t)col * n * KL;
+  const uint8_t* pr = piv + (size_t)col * n;
+  const int8_t* er = (const int8_t*)piv + (size_t)sh.ncols * n + (size_t)col * n;
+  // forward: the row scales, the row exchanges and L; lane i holds y[j + i], i = 0..KL
+  // (xs[j] is overwritten at step j, after its last read as an entering row)
+  double y = (lane <= KL && lane < n) ? ldexp(xs[lane], -(int)er[lane]) : 0.0;
+  for (int j = 0; j < n; ++j) {
+    const int p = __builtin_amdgcn_readfirstlane((int)pr[j]);
+    if (p != 0) {
+      const double yp = bcast(y, p), y0 = bcast(y, 0);
+      if (lane == 0) y = yp;
+      if (lane == p) y = y0;
+    }
+    const double xj = bcast(y, 0);
+    if (lane >= 1 && lane <= KL) y -= Lr[(size_t)j * KL + lane - 1] * xj;
+    if (lane == 0) xs[j] = xj;
+    y = __shfl_down(y, 1);
+    if (lane == KL) y = j + 1 + KL < n ? ldexp(xs[j + 1 + KL], -(int)er[j + 1 + KL]) : 0.0;
+  }
+  __syncthreads();
+  // backward: U x = y; lane l (1..W-1) holds x[j + l]
+  double z = 0.0;
+  for (int j = n - 1; j >= 0; --j) {
+    const double uv = lane < W ? Ur[(size_t)j * W + lane] : 0.0;
+    double s = (lane >= 1 && lane < W) ? uv * z : 0.0;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+    const double xj = (xs[j] - s) / bcast(uv, 0);
+    z = __shfl_up(z, 1);
+    if (lane == 1) z = xj;
+    // every lane read xs[j] above; instructions of one wavefront reach LDS in order
+    if (lane == 0) xs[j] = xj;
+  }
+  __syncthreads();
+  bool nonfinite = false;
+  for (int r = lane; r < n; r += T) {
+    const int k = r / 5, v = r - 5 * k;
+    const double q = qe[r] + (xs[r] - qh[r]);
+    Qi[cix(nz, nc, v, k, col)] = q;
+    if (!isfinite(q)) nonfinite = true;
+  }
+  if (__any(nonfinite) && lane == 0) flag(info, 9 /*HEVI_E_NONFINITE*/, col);
+}
+
+// New linearisation state for an LHEVI-PS operator (no allocation): theta0 and
+// c_Theta = gamma P(Theta0)/Theta0 (Appendix A.1, eq. set2c_pressure) times J into
+// their fields, the velocity u0 = U0/rho0 into the state planes.
+__global__ __launch_bounds__(64) void k_ps_state(HeviShapeDev sh, double R, double cp,
+                                                 double pA, const double* __restrict__ rho0,
+                                                 const double* __restrict__ U0,
+                                                 const double* __restrict__ Th0,
+                                                 double* __restrict__ ops, HeviDevInfo* info) {
+  const int lane = threadIdx.x;
+  const int64_t tile = blockIdx.x;
+  const int64_t c = tile * T + lane;
+  const bool valid = c < sh.ncols;
+  const int64_t cc = valid ? c : sh.ncols - 1;
+  const int nz = sh.nz;
+  const int64_t nc = sh.ncols;
+  const double gam = cp / (cp - R);
+  const size_t pe = plane_elems(sh);
+  double* u0p = ops + pr_offset(sh);
+  bool bad = false;
+  for (int k = 0; k < nz; ++k) {
+    const double r0 = rho0[(size_t)k * nc + cc];
+    const double T0 = Th0[(size_t)k * nc + cc];
+    double* o = ops + tix(tile, nz, k, HEVI_NOPS, 0, lane);
+    const double Jk = o[OP_J * T];
+    const double P0 = pA * pow(R * T0 / pA, gam);
+    const double th0 = T0 / r0, cT = gam * P0 / T0;
+    o[OP_JTH * T] = Jk * th0;
+    o[OP_JCT * T] = Jk * cT;
+    const size_t ip = ((size_t)tile * nz + k) * T + lane;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      const double v = U0[cix(nz, nc, m, k, cc)] / r0;
+      u0p[(size_t)m * pe + ip] = v;
+      bad |= !isfinite(v);
+    }
+    bad |= !(r0 > 0.0) || !(T0 > 0.0) || !isfinite(r0) || !isfinite(T0) || !isfinite(cT);
+  }
+  if (bad && valid) flag(info, 1 /*HEVI_E_INVALID*/, c);
+}
+
+template <int N, bool HAS_REF>
+__global__ __launch_bounds__(64, kStreamWaves<N>) void k_apply_ps(
+    HeviShapeDev sh, const double* __restrict__ ops, const double* __restrict__ x,
+    const double* __restrict__ xref, double* __restrict__ y) {
+  b_apply<N, HAS_REF, false, true>((int64_t)blockIdx.x, sh, Gll<N>{}, ops, x, xref, y, 1);
+}
+
+template <template <int> class F, typename... A>
+hipError_t dispatch_ps(int N, A&&... a) {
+  switch (N) {
+    case 1: return F<1>::run(a...);
+    case 2: return F<2>::run(a...);
+    case 3: return F<3>::run(a...);
+    case 4: return F<4>::run(a...);
+    case 5: return F<5>::run(a...);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int N>
+struct PsFactor {
+  static hipError_t run(const HeviShapeDev& sh, double lambda, const double* ops, double* U,
+                        double* L, uint8_t* piv, HeviDevInfo* info, hipStream_t st) {
+    hipLaunchKernelGGL(k_ps_factor<N>, dim3((unsigned)sh.ncols), dim3(T), 0, st, sh, lambda,
+                       ops, U, L, piv, info);
+    return hipGetLastError();
+  }
+};
+
+template <int N>
+struct PsStage {
+  static hipError_t run(const HeviShapeDev& sh, const double* ops, const double* U,
+                        const double* L, const uint8_t* piv, const HeviTerms& E,
+                        const HeviTerms& Q, double* Qi, HeviDevInfo* info, hipStream_t st) {
+    hipLaunchKernelGGL(k_ps_stage<N>, dim3((unsigned)sh.ncols), dim3(T),
+                       (size_t)15 * sh.nz * sizeof(double), st, sh, ops, U, L, piv, E, Q, Qi,
+                       info);
+    return hipGetLastError();
+  }
+};
+
+template <int N>
+struct PsApply {
+  static hipError_t run(const HeviShapeDev& sh, const double* ops, const double* x,
+                        const double* xref, double* y, hipStream_t st) {
+    if (xref)
+      hipLaunchKernelGGL((k_apply_ps<N, true>), dim3((unsigned)sh.ntiles), dim3(T), 0, st, sh,
+                         ops, x, xref, y);
+    else
+      hipLaunchKernelGGL((k_apply_ps<N, false>), dim3((unsigned)sh.ntiles), dim3(T), 0, st, sh,
+                         ops, x, xref, y);
+    return hipGetLastError();
+  }
+};
+
+}  // namespace
+
+int hevi_ps_band_width(int N) { return 2 * (5 * (N + 1) - 1) + 1; }
+int hevi_ps_lower_width(int N) { return 5 * (N + 1) - 1; }
+
+hipError_t hevi_launch_ps_factor(const HeviShapeDev& sh, double lambda, const double* ops,
+                                 double* U, double* L, uint8_t* piv, HeviDevInfo* info,
+                                 hipStream_t st) {
+  if (sh.ncols == 0) return hipSuccess;
+  return dispatch_ps<PsFactor>(sh.N, sh, lambda, ops, U, L, piv, info, st);
+}
+
+hipError_t hevi_launch_ps_stage(const HeviShapeDev& sh, const double* ops, const double* U,
+                                const double* L, const uint8_t* piv, const HeviTerms& E,
+                                const HeviTerms& Q, double* Qi, HeviDevInfo* info,
+                                hipStream_t st) {
+  if (sh.ncols == 0) return hipSuccess;
+  return dispatch_ps<PsStage>(sh.N, sh, ops, U, L, piv, E, Q, Qi, info, st);
+}
+
+hipError_t hevi_launch_apply_ps(const HeviShapeDev& sh, const double* ops, const double* x,
+                                const double* xref, double* y, hipStream_t st) {
+  if (sh.ntiles == 0) return hipSuccess;
+  return dispatch_ps<PsApply>(sh.N, sh, ops, x, xref, y, st);
+}
+
+hipError_t hevi_launch_ps_state(const HeviShapeDev& sh, double R, double cp, double pA,
+                                const double* rho0, const double* U0, const double* Th0,
+                                double* ops, HeviDevInfo* info, hipStream_t st) {
+  if (sh.ntiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ps_state, dim3((unsigned)sh.ntiles), dim3(T), 0, st, sh, R, cp, pA, rho0,
+                     U0, Th0, ops, info);
+  return hipGetLastError();
+}

@@ -362,7 +362,7 @@ hevi_status hevi_serve_register(hevi_server* S, const hevi_ops* ops, double lamb
   if (prec != HEVI_FP64 && prec != HEVI_FP32_REFINE) return HEVI_E_INVALID;
   if (!(lambda >= 0.0) || !std::isfinite(lambda)) return HEVI_E_INVALID;
   if (ops->ctx->device != S->ctx->device) return HEVI_E_INVALID;
-  if (ops->s3) return HEVI_E_INVALID;  // batches run the set-2C group kernels
+  if (ops->s3 || ops->ps) return HEVI_E_INVALID;  // batches run the set-2C group kernels
   std::lock_guard<std::mutex> lk(S->mu);
   if (S->stop || S->broken) return HEVI_E_CLOSED;
   const size_t bytes = factor_storage_bytes(ops->sh, prec);

@@ -41,9 +41,16 @@ class ColumnBatch:
         # the set's thermodynamic reference: Theta0 (set 2C) or the total energy E0 (3C)
         self.eqset = col.get("eqset", "2C")
         self.Theta0 = to_dev(col["E0"] if self.eqset == "3C" else col["Theta0"], device)
-        self.ops = ctx.build_column_ops(self.N, self.Ne, self.ncols, self.consts, self.z, self.J,
-                                        self.gz, self.rho0, self.Theta0, stream=stream,
-                                        eqset=self.eqset)
+        if col.get("U0") is not None:
+            # LHEVI-PS: linearised at the moving state (rho0, U0, Theta0)
+            self.U0 = to_dev(col["U0"], device)
+            self.ops = ctx.build_column_ops_ps(self.N, self.Ne, self.ncols, self.consts, self.z,
+                                               self.J, self.gz, self.rho0, self.U0, self.Theta0,
+                                               stream=stream)
+        else:
+            self.ops = ctx.build_column_ops(self.N, self.Ne, self.ncols, self.consts, self.z,
+                                            self.J, self.gz, self.rho0, self.Theta0,
+                                            stream=stream, eqset=self.eqset)
         self.device = device
 
     def empty_state(self):

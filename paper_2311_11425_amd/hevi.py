@@ -25,7 +25,7 @@ STATUS = {0: "HEVI_OK", 1: "HEVI_E_INVALID", 2: "HEVI_E_SHAPE", 3: "HEVI_E_NOMEM
 
 # every symbol include/hevi.h declares
 EXPORTS = ["hevi_create", "hevi_destroy", "hevi_status_str", "hevi_build_column_ops",
-           "hevi_build_column_ops_set",
+           "hevi_build_column_ops_set", "hevi_build_column_ops_ps", "hevi_ops_relinearize",
            "hevi_ops_check", "hevi_ops_free", "hevi_apply_op", "hevi_factor", "hevi_refactor",
            "hevi_factors_check", "hevi_factors_band_entries", "hevi_factors_free",
            "hevi_stage_solve", "hevi_solve_noalloc", "hevi_combine",
@@ -115,6 +115,9 @@ def load():
         "hevi_build_column_ops_set": ([_vp, ctypes.POINTER(Shape), ctypes.POINTER(Consts),
                                        ctypes.c_int, _vp, _vp, _vp, _vp, _vp, pp, _vp],
                                       ctypes.c_int),
+        "hevi_build_column_ops_ps": ([_vp, ctypes.POINTER(Shape), ctypes.POINTER(Consts), _vp,
+                                      _vp, _vp, _vp, _vp, _vp, pp, _vp], ctypes.c_int),
+        "hevi_ops_relinearize": ([_vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
         "hevi_ops_check": ([_vp, _vp, ctypes.POINTER(i64), _vp], ctypes.c_int),
         "hevi_ops_free": ([_vp], None),
         "hevi_apply_op": ([_vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
@@ -303,6 +306,24 @@ class Context:
                                                       _stream(stream)),
                    "hevi_build_column_ops_set")
         return Ops(self, out, (N, Ne, ncols), None)
+
+    def build_column_ops_ps(self, N, Ne, ncols, consts, z, J, gz, rho0, U0, Theta0,
+                            stream=None):
+        """LHEVI-PS operator: the Jacobian at the moving state (rho0, U0, Theta0)."""
+        sh = Shape(N, Ne, ncols)
+        k = Consts(*consts)
+        out = ctypes.c_void_p()
+        _check(self.lib.hevi_build_column_ops_ps(self.handle, ctypes.byref(sh), ctypes.byref(k),
+                                                 _ptr(z), _ptr(J), _ptr(gz), _ptr(rho0),
+                                                 _ptr(U0), _ptr(Theta0), ctypes.byref(out),
+                                                 _stream(stream)),
+               "hevi_build_column_ops_ps")
+        return Ops(self, out, (N, Ne, ncols), None)
+
+    def relinearize(self, ops, rho0, U0, Theta0, stream=None):
+        _check(self.lib.hevi_ops_relinearize(self.handle, ops.handle, _ptr(rho0), _ptr(U0),
+                                             _ptr(Theta0), _stream(stream)),
+               "hevi_ops_relinearize")
 
     def apply_op(self, ops, x, y, xref=None, stream=None):
         _check(self.lib.hevi_apply_op(self.handle, ops.handle, _ptr(x), _ptr(xref), _ptr(y),
