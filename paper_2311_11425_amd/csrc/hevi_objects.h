@@ -84,9 +84,9 @@ hevi_status terms(int32_t n, const double* const* v, const double* coef, int lo,
                   HeviTerms* t);
 // byte planes beside the factors: pivot offsets, U row extents, row-scale exponents
 constexpr size_t kFactorPlanes = 3;
-// LHEVI-PS stage solves hold q^E, q^ and x of one column in LDS (3 n doubles of at
-// most 64 KiB): n_z up to 546
-constexpr int kPsMaxNz = 546;
+// LHEVI-PS stage solves hold q^E, q^ and x of one column in LDS with its pivot offsets
+// and row exponents (26 n bytes of at most 64 KiB): n_z up to 504
+constexpr int kPsMaxNz = 504;
 // FP32 factors of orders without the fused assembly + LU need an FP64 assembly
 // buffer (FP64 factors assemble in place of U)
 inline bool needs_sbuf(const HeviShapeDev& sh, hevi_precision prec) {

@@ -45,10 +45,6 @@ __device__ __forceinline__ double bcast(double v, int src) {
   return __hiloint2double(hi, lo);
 }
 
-__device__ __forceinline__ double sel3(int m, double a, double b, double c) {
-  return m == 0 ? a : (m == 1 ? b : c);
-}
-
 // The operator of one column as the PS kernels read it (lane-dependent nodes).
 struct PsCol {
   const double* ops;
@@ -64,6 +60,40 @@ struct PsCol {
   }
 };
 
+// The operator of one column copied into LDS at the start of the factorisation
+// (field-major, s[f * nz + k]): J, grad(zeta), u0, J c_Theta, J theta0, M^-1, the
+// gravity coefficient and w = grad(zeta).u0 per node.  The entering rows of every step
+// then read LDS instead of memory.
+enum { PN_J = 0, PN_G = 1, PN_U = 4, PN_JCT = 7, PN_JTH = 8, PN_MINV = 9, PN_PHI = 10,
+       PN_W = 11, PN_FIELDS = 12 };
+struct PsNodes {
+  const double* s;
+  int nz;
+  __device__ __forceinline__ double f(int fld, int k) const { return s[fld * nz + k]; }
+};
+
+__device__ void ps_load_nodes(const PsCol& P, double* s) {
+  const int nz = P.nz, lane = threadIdx.x;
+  for (int q = lane; q < (PN_FIELDS - 1) * nz; q += T) {
+    const int fld = q / nz, k = q - fld * nz;
+    double v;
+    if (fld == PN_J) v = P.op(k, OP_J);
+    else if (fld < PN_U) v = P.op(k, OP_GX + (fld - PN_G));
+    else if (fld < PN_JCT) v = P.u(k, fld - PN_U);
+    else if (fld == PN_JCT) v = P.op(k, OP_JCT);
+    else if (fld == PN_JTH) v = P.op(k, OP_JTH);
+    else if (fld == PN_MINV) v = P.op(k, OP_MINV);
+    else v = P.op(k, OP_PHI);
+    s[q] = v;
+  }
+  __syncthreads();
+  for (int k = lane; k < nz; k += T)
+    s[PN_W * nz + k] = s[PN_G * nz + k] * s[PN_U * nz + k] +
+                       s[(PN_G + 1) * nz + k] * s[(PN_U + 1) * nz + k] +
+                       s[(PN_G + 2) * nz + k] * s[(PN_U + 2) * nz + k];
+  __syncthreads();
+}
+
 // Entry (r, c) of A = I - lambda L_z (zero outside the matrix or the band):
 //   L_z = -M^-1 B - gravity,  B_(k,a),(kc,b) = sum over the elements e holding both
 //   nodes of  w_i D_ij J_kc K_kc[a][b]  (a > 0, strong)  or  -w_j D_ji J_kc K_kc[0][b]
@@ -74,7 +104,7 @@ struct PsCol {
 //   K[U_l][Theta] = g_l c_Theta;  K[Theta][rho] = -theta0 w, K[Theta][U_m] = theta0 g_m,
 //   K[Theta][Theta] = w.
 template <int N>
-__device__ double ps_entry(const PsCol& P, const double* Dsh, const double* wsh,
+__device__ double ps_entry(const PsNodes& P, int Ne, const double* Dsh, const double* wsh,
                            double lambda, int r, int c) {
   const int nz = P.nz, n = 5 * nz;
   if (r < 0 || r >= n || c < 0 || c >= n) return 0.0;
@@ -83,22 +113,21 @@ __device__ double ps_entry(const PsCol& P, const double* Dsh, const double* wsh,
   if (a >= 1 && a <= 3 && (k == 0 || k == nz - 1)) return delta;
   const int dk = kc - k;
   if (dk > N || dk < -N) return delta;
-  const double J = P.op(kc, OP_J);
-  const double g0 = P.op(kc, OP_GX), g1 = P.op(kc, OP_GY), g2 = P.op(kc, OP_GZ);
-  const double v0 = P.u(kc, 0), v1 = P.u(kc, 1), v2 = P.u(kc, 2);
-  const double w = g0 * v0 + g1 * v1 + g2 * v2;
+  const double J = P.f(PN_J, kc);
+  const double w = P.f(PN_W, kc);
+  const double gb = (b >= 1 && b <= 3) ? P.f(PN_G + b - 1, kc) : 0.0;
   double JK;
   if (a == 0) {
-    JK = (b >= 1 && b <= 3) ? J * sel3(b - 1, g0, g1, g2) : 0.0;
+    JK = J * gb;
   } else if (a <= 3) {
-    const double ul = sel3(a - 1, v0, v1, v2);
+    const double ul = P.f(PN_U + a - 1, kc);
     if (b == 0) JK = -J * ul * w;
-    else if (b <= 3) JK = J * ((a == b ? w : 0.0) + ul * sel3(b - 1, g0, g1, g2));
-    else JK = sel3(a - 1, g0, g1, g2) * P.op(kc, OP_JCT);
+    else if (b <= 3) JK = J * ((a == b ? w : 0.0) + ul * gb);
+    else JK = P.f(PN_G + a - 1, kc) * P.f(PN_JCT, kc);
   } else {
-    const double Jth = P.op(kc, OP_JTH);
+    const double Jth = P.f(PN_JTH, kc);
     if (b == 0) JK = -Jth * w;
-    else if (b <= 3) JK = Jth * sel3(b - 1, g0, g1, g2);
+    else if (b <= 3) JK = Jth * gb;
     else JK = J * w;
   }
   double Bs = 0.0;
@@ -106,15 +135,30 @@ __device__ double ps_entry(const PsCol& P, const double* Dsh, const double* wsh,
   for (int side = 0; side < 2; ++side) {
     // the element in which k is local node N (side 0) or local node < N (side 1)
     const int e = side == 0 ? ((k % N == 0) ? k / N - 1 : -1) : k / N;
-    if (e < 0 || e >= P.Ne) continue;
+    if (e < 0 || e >= Ne) continue;
     const int i = k - e * N, j = kc - e * N;
     if (j < 0 || j > N) continue;
     const double coef = a == 0 ? -wsh[j] * Dsh[j * (N + 1) + i] : wsh[i] * Dsh[i * (N + 1) + j];
     Bs += coef * JK;
   }
-  double L = -P.op(k, OP_MINV) * Bs;
-  if (kc == k && b == 0 && a >= 1 && a <= 3) L -= P.op(k, OP_PHI) * sel3(a - 1, g0, g1, g2);
+  double L = -P.f(PN_MINV, k) * Bs;
+  if (kc == k && b == 0 && a >= 1 && a <= 3) L -= P.f(PN_PHI, k) * P.f(PN_G + a - 1, k);
   return delta - lambda * L;
+}
+
+// Workgroups are dealt to the 8 XCDs round-robin (workgroup b runs on XCD b mod 8),
+// and each XCD has its own L2.  A wavefront reads its column's entries of the
+// column-fastest caller vectors and of the tile-interleaved operator, 8 bytes of
+// each cache line that 16 (or 64) neighbouring columns share, so neighbouring
+// columns must run on the same XCD: XCD x takes the contiguous columns
+// x*chunk .. x*chunk + chunk - 1 (grid = 8 * chunk, chunk = ceil(ncols / 8)).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t ps_column(int64_t ncols) {
+  const int64_t chunk = (ncols + kXcds - 1) / kXcds;
+  return (int64_t)(blockIdx.x % kXcds) * chunk + blockIdx.x / kXcds;
+}
+__host__ __forceinline__ unsigned ps_grid(int64_t ncols) {
+  return (unsigned)(kXcds * ((ncols + kXcds - 1) / kXcds));
 }
 
 // Scales the row held across the lanes (one entry per lane) by 2^-e, e the binary
@@ -152,11 +196,16 @@ __global__ __launch_bounds__(64) void k_ps_factor(HeviShapeDev sh, double lambda
   constexpr int KL = kPsKL<N>, W = kPsW<N>;
   static_assert(W <= 64, "one wavefront holds the window");
   __shared__ double Dsh[(N + 1) * (N + 1)], wsh[N + 1];
+  extern __shared__ double nodes[];  // PN_FIELDS * n_z
   load_tables<N>(Dsh, wsh);
   const int lane = threadIdx.x;
-  const int64_t col = blockIdx.x;
-  const int nz = sh.nz, n = 5 * nz;
-  const PsCol P{ops, ps_plane(ops, sh, 0), plane_elems(sh), col / T, nz, sh.Ne, (int)(col % T)};
+  const int64_t col = ps_column(sh.ncols);
+  if (col >= sh.ncols) return;
+  const int nz = sh.nz, n = 5 * nz, Ne = sh.Ne;
+  ps_load_nodes(PsCol{ops, ps_plane(ops, sh, 0), plane_elems(sh), col / T, nz, Ne,
+                      (int)(col % T)},
+                nodes);
+  const PsNodes P{nodes, nz};
   double* Ur = Ub + (size_t)col * n * W;
   double* Lr = Lb + (size_t)col * n * KL;
   uint8_t* pr = piv + (size_t)col * n;
@@ -164,7 +213,7 @@ __global__ __launch_bounds__(64) void k_ps_factor(HeviShapeDev sh, double lambda
   double a[KL + 1];
 #pragma unroll
   for (int i = 0; i <= KL; ++i) {
-    a[i] = lane < W ? ps_entry<N>(P, Dsh, wsh, lambda, i, lane) : 0.0;
+    a[i] = lane < W ? ps_entry<N>(P, Ne, Dsh, wsh, lambda, i, lane) : 0.0;
     const int e = ps_scale_row(a[i]);
     if (lane == 0 && i < n) er[i] = (int8_t)e;
   }
@@ -201,7 +250,7 @@ __global__ __launch_bounds__(64) void k_ps_factor(HeviShapeDev sh, double lambda
     // next window: rows j+1..j+1+KL, columns j+1..j+W (lanes >= W hold zeros)
 #pragma unroll
     for (int i = 0; i < KL; ++i) a[i] = __shfl_down(a[i + 1], 1);
-    a[KL] = lane < W ? ps_entry<N>(P, Dsh, wsh, lambda, j + 1 + KL, j + 1 + lane) : 0.0;
+    a[KL] = lane < W ? ps_entry<N>(P, Ne, Dsh, wsh, lambda, j + 1 + KL, j + 1 + lane) : 0.0;
     const int e = ps_scale_row(a[KL]);
     if (lane == 0 && j + 1 + KL < n) er[j + 1 + KL] = (int8_t)e;
   }
@@ -211,7 +260,12 @@ __global__ __launch_bounds__(64) void k_ps_factor(HeviShapeDev sh, double lambda
 // One stage solve: q^E = sum e_t E_t, q^ = q^E + sum c_j Q_j, A x = P(q^) with the
 // band factors (P the rigid-lid projection of the momentum at the bottom and top
 // nodes), Q_i = q^E + (x - q^) (= x - sum c_j Q_j, Sec. 4.3 eq. lhevi-ark-final-3).
-// Dynamic LDS: 3 n doubles (q^, q^E, and P(q^) overwritten by the solution).
+// Dynamic LDS: 3 n doubles (q^, q^E, and P(q^) overwritten by the solution) and the
+// column's pivot offsets and row exponents (2 n bytes).  The factor rows are read
+// kPsRing steps ahead into register rings, so each step's loads are in flight long
+// before the dependent chain of the substitution reaches them.
+constexpr int kPsRing = 8;
+
 template <int N>
 __global__ __launch_bounds__(64) void k_ps_stage(HeviShapeDev sh, const double* __restrict__ ops,
                                                  const double* __restrict__ Ub,
@@ -222,12 +276,23 @@ __global__ __launch_bounds__(64) void k_ps_stage(HeviShapeDev sh, const double* 
   constexpr int KL = kPsKL<N>, W = kPsW<N>;
   extern __shared__ double sm[];
   const int lane = threadIdx.x;
-  const int64_t col = blockIdx.x;
+  const int64_t col = ps_column(sh.ncols);
+  if (col >= sh.ncols) return;
   const int nz = sh.nz, n = 5 * nz;
   const int64_t nc = sh.ncols;
   double* qh = sm;
   double* qe = sm + n;
   double* xs = sm + 2 * n;
+  uint8_t* pl = (uint8_t*)(sm + 3 * n);  // pivot offsets
+  int8_t* el = (int8_t*)(pl + n);        // row exponents
+  {
+    const uint8_t* pr = piv + (size_t)col * n;
+    const int8_t* er = (const int8_t*)piv + (size_t)sh.ncols * n + (size_t)col * n;
+    for (int r = lane; r < n; r += T) {
+      pl[r] = pr[r];
+      el[r] = er[r];
+    }
+  }
   for (int r = lane; r < n; r += T) {
     const int k = r / 5, v = r - 5 * k;
     const size_t ix = cix(nz, nc, v, k, col);
@@ -256,37 +321,59 @@ __global__ __launch_bounds__(64) void k_ps_stage(HeviShapeDev sh, const double* 
   __syncthreads();
   const double* Ur = Ub + (size_t)col * n * W;
   const double* Lr = Lb + (size_t)col * n * KL;
-  const uint8_t* pr = piv + (size_t)col * n;
-  const int8_t* er = (const int8_t*)piv + (size_t)sh.ncols * n + (size_t)col * n;
+  constexpr int D = kPsRing;
   // forward: the row scales, the row exchanges and L; lane i holds y[j + i], i = 0..KL
   // (xs[j] is overwritten at step j, after its last read as an entering row)
-  double y = (lane <= KL && lane < n) ? ldexp(xs[lane], -(int)er[lane]) : 0.0;
-  for (int j = 0; j < n; ++j) {
-    const int p = __builtin_amdgcn_readfirstlane((int)pr[j]);
-    if (p != 0) {
-      const double yp = bcast(y, p), y0 = bcast(y, 0);
-      if (lane == 0) y = yp;
-      if (lane == p) y = y0;
+  const bool lrow = lane >= 1 && lane <= KL;
+  double lr[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) lr[d] = (lrow && d < n) ? Lr[(size_t)d * KL + lane - 1] : 0.0;
+  double y = (lane <= KL && lane < n) ? ldexp(xs[lane], -(int)el[lane]) : 0.0;
+  for (int j0 = 0; j0 < n; j0 += D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int j = j0 + d;
+      if (j >= n) break;
+      const double lv = lr[d];
+      const int jn = j + D;
+      lr[d] = (lrow && jn < n) ? Lr[(size_t)jn * KL + lane - 1] : 0.0;
+      const int p = __builtin_amdgcn_readfirstlane((int)pl[j]);
+      if (p != 0) {
+        const double yp = bcast(y, p), y0 = bcast(y, 0);
+        if (lane == 0) y = yp;
+        if (lane == p) y = y0;
+      }
+      const double xj = bcast(y, 0);
+      if (lrow) y -= lv * xj;
+      if (lane == 0) xs[j] = xj;
+      y = __shfl_down(y, 1);
+      if (lane == KL) y = j + 1 + KL < n ? ldexp(xs[j + 1 + KL], -(int)el[j + 1 + KL]) : 0.0;
     }
-    const double xj = bcast(y, 0);
-    if (lane >= 1 && lane <= KL) y -= Lr[(size_t)j * KL + lane - 1] * xj;
-    if (lane == 0) xs[j] = xj;
-    y = __shfl_down(y, 1);
-    if (lane == KL) y = j + 1 + KL < n ? ldexp(xs[j + 1 + KL], -(int)er[j + 1 + KL]) : 0.0;
   }
   __syncthreads();
   // backward: U x = y; lane l (1..W-1) holds x[j + l]
-  double z = 0.0;
-  for (int j = n - 1; j >= 0; --j) {
-    const double uv = lane < W ? Ur[(size_t)j * W + lane] : 0.0;
-    double s = (lane >= 1 && lane < W) ? uv * z : 0.0;
+  const bool urow = lane < W;
+  double ur[D];
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
-    const double xj = (xs[j] - s) / bcast(uv, 0);
-    z = __shfl_up(z, 1);
-    if (lane == 1) z = xj;
-    // every lane read xs[j] above; instructions of one wavefront reach LDS in order
-    if (lane == 0) xs[j] = xj;
+  for (int d = 0; d < D; ++d) ur[d] = (urow && n - 1 - d >= 0) ? Ur[(size_t)(n - 1 - d) * W + lane] : 0.0;
+  double z = 0.0;
+  for (int j0 = n - 1; j0 >= 0; j0 -= D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int j = j0 - d;
+      if (j < 0) break;
+      const double uv = ur[d];
+      const int jn = j - D;
+      ur[d] = (urow && jn >= 0) ? Ur[(size_t)jn * W + lane] : 0.0;
+      double s = (lane >= 1 && urow) ? uv * z : 0.0;
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+      const double xj = (xs[j] - s) / bcast(uv, 0);
+      z = __shfl_up(z, 1);
+      if (lane == 1) z = xj;
+      // every lane read xs[j] above; instructions of one wavefront reach LDS in order
+      if (lane == 0) xs[j] = xj;
+    }
   }
   __syncthreads();
   bool nonfinite = false;
@@ -362,8 +449,9 @@ template <int N>
 struct PsFactor {
   static hipError_t run(const HeviShapeDev& sh, double lambda, const double* ops, double* U,
                         double* L, uint8_t* piv, HeviDevInfo* info, hipStream_t st) {
-    hipLaunchKernelGGL(k_ps_factor<N>, dim3((unsigned)sh.ncols), dim3(T), 0, st, sh, lambda,
-                       ops, U, L, piv, info);
+    hipLaunchKernelGGL(k_ps_factor<N>, dim3(ps_grid(sh.ncols)), dim3(T),
+                       (size_t)PN_FIELDS * sh.nz * sizeof(double), st, sh, lambda, ops, U, L, piv,
+                       info);
     return hipGetLastError();
   }
 };
@@ -373,9 +461,9 @@ struct PsStage {
   static hipError_t run(const HeviShapeDev& sh, const double* ops, const double* U,
                         const double* L, const uint8_t* piv, const HeviTerms& E,
                         const HeviTerms& Q, double* Qi, HeviDevInfo* info, hipStream_t st) {
-    hipLaunchKernelGGL(k_ps_stage<N>, dim3((unsigned)sh.ncols), dim3(T),
-                       (size_t)15 * sh.nz * sizeof(double), st, sh, ops, U, L, piv, E, Q, Qi,
-                       info);
+    const size_t n = 5 * (size_t)sh.nz;
+    hipLaunchKernelGGL(k_ps_stage<N>, dim3(ps_grid(sh.ncols)), dim3(T),
+                       3 * n * sizeof(double) + 2 * n, st, sh, ops, U, L, piv, E, Q, Qi, info);
     return hipGetLastError();
   }
 };
