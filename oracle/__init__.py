@@ -96,6 +96,14 @@ def _load():
                                                    ctypes.c_int, ctypes.c_int,
                                                    ctypes.c_int, _dp, ctypes.POINTER(ctypes.c_long)]
         lib.ho_ark_step_batch.restype = ctypes.c_int
+        lib.ho_vertical_op.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _dp, _dp,
+                                       ctypes.c_int, _dp]
+        lib.ho_vertical_op.restype = ctypes.c_int
+        lib.ho_nhevi_step_batch.argtypes = common + [ctypes.c_int, _dp, _dp, ctypes.c_double, _dp,
+                                                     ctypes.c_double, ctypes.c_int, _dp, _dp, _dp,
+                                                     ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+                                                     ctypes.c_int, ctypes.POINTER(ctypes.c_long)]
+        lib.ho_nhevi_step_batch.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -339,3 +347,47 @@ def column_of(col, c):
 def vec_of(v, c):
     """Column c of a batched state [v][k][c] as the interleaved vector (5k+v)."""
     return np.ascontiguousarray(v[:, :, c].T).reshape(-1)
+
+
+def vertical_op(N, Ne, consts, z, J, gz_k3, q, rho_weak=True):
+    """Nonlinear set-2C vertical operator V(q) of one column (q interleaved 5k+v)."""
+    lib = _load()
+    q = _f64(q)
+    V = np.zeros_like(q)
+    rc = lib.ho_vertical_op(N, Ne, _p(_f64(consts)), *[_p(_f64(a)) for a in (z, J, gz_k3)],
+                            _p(q), int(rho_weak), _p(V))
+    if rc:
+        raise ValueError("vertical operator failed")
+    return V
+
+
+def nhevi_step_batch(col, tab, dt, qn, tol=1e-12, maxit=8, refine=1, rho_weak=True,
+                     nthreads=None, want_stages=False):
+    """One NHEVI-LU step (Newton per implicit stage with the Jacobian rebuilt at every
+    iterate) of every column; ``tab`` as for ark_step_batch (only Aimp and b are used:
+    there is no explicit operator).  Returns q^{n+1}, the per-column Newton iteration
+    counts and, if requested, the stage values Q and V(Q) as [s][v][k][c]."""
+    lib = _load()
+    N, Ne = col["N"], col["Ne"]
+    ncols = col["z"].shape[1]
+    g = _geom_args(col)
+    Aimp = _f64(tab["Aimp"])
+    bw = _f64(tab["b"])
+    s = bw.size
+    qn = _f64(qn)
+    qnp1 = np.zeros_like(qn)
+    Q = np.zeros((s,) + qn.shape) if want_stages else None
+    V = np.zeros((s,) + qn.shape) if want_stages else None
+    its = np.zeros(ncols, dtype=np.int32)
+    bad = ctypes.c_long(-1)
+    consts = _f64(col["consts"])
+    rc = lib.ho_nhevi_step_batch(N, Ne, ncols, nthreads or os.cpu_count() or 1, _p(consts),
+                                 *[_p(a) for a in g], s, _p(Aimp), _p(bw), dt, _p(qn), tol,
+                                 maxit, _p(qnp1), _p(Q), _p(V),
+                                 its.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), refine,
+                                 int(rho_weak), ctypes.byref(bad))
+    if rc:
+        raise RuntimeError(f"oracle NHEVI step failed ({rc}) at column {bad.value}")
+    if want_stages:
+        return qnp1, its, Q, V
+    return qnp1, its

@@ -23,6 +23,9 @@
  *     vertical operator at a previous solution q0 = (rho0, U0, Theta0), U0 != 0),
  *     the set-2C flux Jacobian K(q0) at that state (Appendix A.3, eq.
  *     set2c_jacobian, re-derived from the fluxes) and the same assembly;
+ *   - for NHEVI-LU (Sec. 4.2.2), the nonlinear set-2C vertical operator V(q) and
+ *     the Newton iteration on F(q) = q - Lambda V(q) - R of each implicit stage, with
+ *     the Jacobian rebuilt (as for LHEVI-PS) and factored at every iterate;
  *   - x = (I - Lambda L_z)^{-1} b by dense Gaussian elimination with partial
  *     pivoting (Sec. 4.3 eq. lhevi-ark-final-2), optionally followed by
  *     iterative refinement with the residual accumulated in long double;
@@ -313,6 +316,61 @@ int ho_assemble_L_K(int N, int Ne, double g, const double *z, const double *J,
   return 0;
 }
 
+/* Nonlinear set-2C vertical operator V(q) of one column, q and V interleaved (5k+v):
+ * the fluxes F_rho = J U^z, F_U = J (U U^z/rho + P(Theta) grad zeta),
+ * F_Theta = J Theta U^z / rho (U^z = grad(zeta).U, P of eq. set2c_pressure) through the
+ * element derivatives of ho_assemble_L (rho row weak unless rho_weak == 0, the others
+ * strong), direct stiffness summation and the lumped mass, the gravity term
+ * -rho Phi' grad(zeta) in the momentum rows, zero momentum rows at the rigid-lid nodes
+ * (Appendix A.2, Sec. 3).  consts = {R, c_p, g, P_A}.
+ * Parity pinned: its centred differences equal the Jacobian ho_jacobian_2c +
+ * ho_assemble_L_K at any state (tests), column mass conservation. */
+int ho_vertical_op(int N, int Ne, const double *consts, const double *z, const double *J,
+                   const double *gz, const double *q, int rho_weak, double *V) {
+  if (N < 1 || N > 16 || Ne < 1) return 1;
+  int nz = Ne * N + 1, np1 = N + 1;
+  double R = consts[0], cp = consts[1], g = consts[2], pA = consts[3];
+  double gam = cp / (cp - R);
+  double xi[17], w[17], D[17 * 17];
+  if (ho_gll(N, xi, w, D)) return 1;
+  double *M = (double *)calloc((size_t)nz, sizeof(double));
+  double *F = (double *)malloc(sizeof(double) * 5 * (size_t)nz);
+  if (!M || !F) { free(M); free(F); return 2; }
+  for (int k = 0; k < nz; ++k) {
+    const double *qk = &q[5 * k], *a = &gz[3 * k];
+    double Uz = a[0] * qk[1] + a[1] * qk[2] + a[2] * qk[3];
+    double P = pA * pow(R * qk[4] / pA, gam);
+    F[5 * k + 0] = J[k] * Uz;
+    for (int m = 0; m < 3; ++m) F[5 * k + 1 + m] = J[k] * (qk[1 + m] * Uz / qk[0] + P * a[m]);
+    F[5 * k + 4] = J[k] * qk[4] * Uz / qk[0];
+  }
+  memset(V, 0, sizeof(double) * 5 * (size_t)nz);
+  for (int e = 0; e < Ne; ++e) {
+    for (int i = 0; i <= N; ++i) {
+      int ki = e * N + i;
+      double dphi = 0.0;
+      for (int j = 0; j <= N; ++j) dphi += D[i * np1 + j] * z[e * N + j];
+      dphi *= g;
+      M[ki] += w[i] * J[ki];
+      for (int m = 0; m < 3; ++m) V[5 * ki + 1 + m] += w[i] * J[ki] * dphi * gz[3 * ki + m] * q[5 * ki];
+      for (int j = 0; j <= N; ++j) {
+        int kj = e * N + j;
+        double strong = w[i] * D[i * np1 + j], weak = -w[j] * D[j * np1 + i];
+        V[5 * ki + 0] += (rho_weak ? weak : strong) * F[5 * kj + 0];
+        for (int v = 1; v < 5; ++v) V[5 * ki + v] += strong * F[5 * kj + v];
+      }
+    }
+  }
+  for (int k = 0; k < nz; ++k)
+    for (int v = 0; v < 5; ++v) V[5 * k + v] *= -1.0 / M[k];
+  for (int m = 0; m < 3; ++m) {
+    V[5 * 0 + 1 + m] = 0.0;
+    V[5 * (nz - 1) + 1 + m] = 0.0;
+  }
+  free(M); free(F);
+  return 0;
+}
+
 /* Rigid-lid projection of a right-hand side: at the bottom and top nodes the
  * momentum loses its component along n = gz/|gz| (no flux through the lid). */
 void ho_bc_project(int nz, const double *gz, double *b) {
@@ -432,6 +490,10 @@ typedef struct {
   int rho_weak, refine;
   int eqset; /* 0: set 2C (Theta0 input), 1: set 3C (E0 input) */
   const double *U0; /* LHEVI-PS: momentum of the linearisation state [m][k][c], or NULL */
+  /* NHEVI-LU (mode 3) */
+  double tol;
+  int maxit;
+  int *iters;
   double lambda;
   const double *in; /* solve: b; apply: x */
   const double *in_ref; /* apply: optional x_ref subtracted first */
@@ -523,6 +585,80 @@ static void *worker(void *arg) {
     }
     if (bad) {
       jb->status = 1; jb->bad_col = c; break;
+    }
+    if (jb->mode == 3) {
+      /* NHEVI-LU step (Sec. 4.2.2): per implicit stage i, Newton on
+       *   F(q) = q - Lambda V(q) - R,  R = q^n + dt sum_{j<i} a~_ij V(Q_j)
+       * (no explicit operator H here), J(q_m) dq = -F(q_m) with J = I - Lambda dV/dq
+       * rebuilt at every iterate (the Jacobian of ho_jacobian_2c / ho_assemble_L_K),
+       * q_{m+1} = q_m + dq, from q_0 = Q_{i-1}, until max_v ||dq_v|| / ||q_{m+1,v} -
+       * q^n_v|| <= tol or maxit iterations; the right-hand side of every Newton solve
+       * gets the rigid-lid projection.  q^{n+1} = q^n + dt sum_i b_i V(Q_i). */
+      int s3 = jb->s, nit = 0;
+      double lam = jb->Aimp[1 * s3 + 1] * jb->dt;
+      const double kc[4] = {jb->R, jb->cp, jb->g, jb->pA};
+      get_vec(jb->qn, jb->ncols, nz, c, qn);
+      memcpy(&Q[0], qn, sizeof(double) * n);
+      if (ho_vertical_op(jb->N, jb->Ne, kc, z, J, gz, &Q[0], jb->rho_weak, &S[0])) {
+        jb->status = 1; jb->bad_col = c; break;
+      }
+      int fail = 0;
+      for (int i = 1; i < s3 && !fail; ++i) {
+        for (int r = 0; r < n; ++r) {
+          double v = qn[r];
+          for (int j = 0; j < i; ++j) v += jb->dt * jb->Aimp[i * s3 + j] * S[(size_t)j * n + r];
+          qE[r] = v;
+        }
+        double *q = &Q[(size_t)i * n];
+        memcpy(q, &Q[(size_t)(i - 1) * n], sizeof(double) * n);
+        for (int m = 0; m < jb->maxit; ++m) {
+          ho_vertical_op(jb->N, jb->Ne, kc, z, J, gz, q, jb->rho_weak, tmp);
+          for (int r = 0; r < n; ++r) b[r] = qE[r] - q[r] + lam * tmp[r];
+          ho_bc_project(nz, gz, b);
+          for (int k = 0; k < nz; ++k) {
+            rho0[k] = q[5 * k];
+            Th0[k] = q[5 * k + 4];
+            for (int mm = 0; mm < 3; ++mm) U0[3 * k + mm] = q[5 * k + 1 + mm];
+          }
+          ho_reference(nz, rho0, Th0, jb->R, jb->cp, jb->pA, th0, cT);
+          ho_jacobian_2c(nz, gz, rho0, U0, Th0, cT, Kn);
+          ho_assemble_L_K(jb->N, jb->Ne, jb->g, z, J, gz, Kn, jb->rho_weak, L);
+          ho_form_A(n, lam, L, A);
+          memcpy(LU, A, sizeof(double) * nn);
+          if (ho_lu_factor(n, LU, piv)) { fail = 5; break; }
+          ho_solve_refined(n, A, LU, piv, b, x, jb->refine, work);
+          double worst = 0.0;
+          for (int v = 0; v < 5; ++v) {
+            double d2 = 0.0, q2 = 0.0;
+            for (int k = 0; k < nz; ++k) {
+              double nq = q[5 * k + v] + x[5 * k + v];
+              d2 += x[5 * k + v] * x[5 * k + v];
+              q2 += (nq - qn[5 * k + v]) * (nq - qn[5 * k + v]);
+            }
+            double rel = q2 > 0.0 ? sqrt(d2 / q2) : (d2 > 0.0 ? INFINITY : 0.0);
+            if (rel > worst) worst = rel;
+          }
+          for (int r = 0; r < n; ++r) q[r] += x[r];
+          if (m + 1 > nit) nit = m + 1;
+          if (worst <= jb->tol) break;
+        }
+        ho_vertical_op(jb->N, jb->Ne, kc, z, J, gz, q, jb->rho_weak, &S[(size_t)i * n]);
+      }
+      if (fail) { jb->status = fail; jb->bad_col = c; break; }
+      for (int r = 0; r < n; ++r) {
+        double v = qn[r];
+        for (int i = 0; i < s3; ++i) v += jb->dt * jb->bw[i] * S[(size_t)i * n + r];
+        x[r] = v;
+      }
+      put_vec(jb->qnp1, jb->ncols, nz, c, x);
+      if (jb->Qout)
+        for (int i = 0; i < s3; ++i)
+          put_vec(jb->Qout + (size_t)i * 5 * nz * jb->ncols, jb->ncols, nz, c, &Q[(size_t)i * n]);
+      if (jb->Sout)
+        for (int i = 0; i < s3; ++i)
+          put_vec(jb->Sout + (size_t)i * 5 * nz * jb->ncols, jb->ncols, nz, c, &S[(size_t)i * n]);
+      if (jb->iters) jb->iters[c] = nit;
+      continue;
     }
     if (jb->mode == 1) {
       get_vec(jb->in, jb->ncols, nz, c, x);
@@ -690,5 +826,24 @@ int ho_ark_step_batch(int N, int Ne, long ncols, int nthreads, const double *con
   jb.omega = omega;
   jb.qn = qn; jb.qref = qref; jb.qnp1 = qnp1; jb.Qout = Qout; jb.Sout = Sout;
   jb.refine = refine; jb.rho_weak = rho_weak; jb.eqset = eqset; jb.U0 = U0;
+  return run_jobs(&jb, nthreads, bad_col);
+}
+
+/* One NHEVI-LU step of every column (see the mode-3 branch of the worker): the
+ * implicit tableau Aimp (s x s, ESDIRK) and weights bw, Newton tolerance tol and at most
+ * maxit iterations per stage; iters (nullable) receives each column's largest Newton
+ * iteration count, Qout / Vout (nullable) the stage values and V(Q_i) [i][v][k][c]. */
+int ho_nhevi_step_batch(int N, int Ne, long ncols, int nthreads, const double *consts,
+                        const double *z, const double *J, const double *gz, const double *rho0,
+                        const double *Theta0, int s, const double *Aimp, const double *bw,
+                        double dt, const double *qn, double tol, int maxit, double *qnp1,
+                        double *Qout, double *Vout, int *iters, int refine, int rho_weak,
+                        long *bad_col) {
+  if (s < 2 || maxit < 1) return 1;
+  job_t jb;
+  fill_common(&jb, N, Ne, ncols, consts, z, J, gz, rho0, Theta0);
+  jb.mode = 3; jb.s = s; jb.Aimp = Aimp; jb.Aexp = Aimp; jb.bw = bw; jb.dt = dt;
+  jb.qn = qn; jb.qnp1 = qnp1; jb.Qout = Qout; jb.Sout = Vout; jb.iters = iters;
+  jb.tol = tol; jb.maxit = maxit; jb.refine = refine; jb.rho_weak = rho_weak;
   return run_jobs(&jb, nthreads, bad_col);
 }

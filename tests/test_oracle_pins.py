@@ -934,3 +934,98 @@ def test_ps_rotation_equivariance():
     xr[1:4] = np.einsum("ij,jkc->ikc", Q, x[1:4])
     for c in range(3):
         assert relerr_per_var(oracle.vec_of(x2, c), oracle.vec_of(xr, c)) < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# NHEVI-LU (Sec. 4.2.2): Newton on F(q) = q - Lambda V(q) - R per implicit stage
+
+def test_nhevi_vertical_op_derivative():
+    """Centred differences of the oracle's nonlinear operator V at a moving state equal
+    the LHEVI-PS Jacobian there (two independent derivations of the same operator), and
+    V conserves column mass (flux form, rigid lid)."""
+    col = _ps_col()
+    qn, qref = inputs.perturbed_state(col)
+    for c in range(2):
+        z, J, gz, r0, T0 = oracle.column_of(col, c)
+        L = oracle.column_L(4, 6, CONSTS, z, J, gz, r0, T0, U0_k3=oracle.u0_of(col, c))
+        q0 = oracle.vec_of(qref, c)
+        v = oracle.vec_of(qn - qref, c)
+        eps = 1e-2
+        fd = (oracle.vertical_op(4, 6, CONSTS, z, J, gz, q0 + eps * v)
+              - oracle.vertical_op(4, 6, CONSTS, z, J, gz, q0 - eps * v)) / (2 * eps)
+        Lv = L @ v
+        for k in range(5):
+            assert np.linalg.norm(fd[k::5] - Lv[k::5]) < 1e-9 * np.linalg.norm(Lv[k::5]), (c, k)
+        # the numpy operator written from the fluxes in this file agrees too
+        assert np.allclose(oracle.vertical_op(4, 6, CONSTS, z, J, gz, q0 + v),
+                           _nonlinear_V(col, c, q0 + v), rtol=1e-12, atol=1e-14 * np.abs(q0).max())
+        _, w, _ = oracle.gll(4)
+        M = np.zeros(len(z))
+        for e in range(6):
+            for i in range(5):
+                M[4 * e + i] += w[i] * J[4 * e + i]
+        V = oracle.vertical_op(4, 6, CONSTS, z, J, gz, q0 + v)
+        assert abs(M @ V[0::5]) <= 1e-13 * (M @ np.abs(V[0::5]))
+
+
+def test_nhevi_newton_converges_quadratically():
+    """Distance to the stage roots after 1, 2, 3 Newton iterations (fixed counts):
+    quadratic convergence (catches a wrong Jacobian, which converges linearly at best,
+    or a wrong sign of the update)."""
+    col = inputs.config1(heterogeneous=True, ncols=2)
+    tab = tableaux.as_float(tableaux.ark2("b"))
+    qn, _ = inputs.perturbed_state(col, amp=1e-2)
+    root, _ = oracle.nhevi_step_batch(col, tab, 30.0, qn, tol=0.0, maxit=10)
+    d = []
+    for m in (1, 2, 3):
+        qm, its = oracle.nhevi_step_batch(col, tab, 30.0, qn, tol=0.0, maxit=m)
+        assert np.all(its == m)
+        d.append(max(np.linalg.norm((qm - root)[v]) / np.linalg.norm((root - qn)[v])
+                     for v in range(5)))
+    assert d[0] < 0.1 and d[1] < 10 * d[0] ** 2 and d[2] < 1e-12, d
+
+
+def test_nhevi_linear_limit():
+    """For a small perturbation of the reference state the NHEVI-LU step's response
+    (the step of q_ref + delta minus that of q_ref) tends to the implicit Runge-Kutta
+    step of the linearised operator L_z applied to delta, written here directly from the
+    tableau; the relative difference falls linearly with the amplitude (the neglected
+    terms are quadratic).  Catches a wrong stage right-hand side R, a wrong final
+    combination or a Newton solve that does not reach the root."""
+    col = inputs.config1(heterogeneous=True, ncols=1)
+    tab = tableaux.as_float(tableaux.ark2("b"))
+    dt = 30.0
+    A, b = np.array(tab["Aimp"]), np.array(tab["b"])
+    z, J, gz, r0, T0 = oracle.column_of(col, 0)
+    L = oracle.column_L(4, 8, CONSTS, z, J, gz, r0, T0)
+    n = L.shape[0]
+    errs = []
+    for amp in (1e-3, 1e-4):
+        qn, qref = inputs.perturbed_state(col, amp=amp)
+        q1, _ = oracle.nhevi_step_batch(col, tab, dt, qn, tol=1e-10, maxit=10)
+        q0, _ = oracle.nhevi_step_batch(col, tab, dt, qref, tol=1e-10, maxit=10)
+        d = oracle.vec_of(qn - qref, 0)
+        Qs = [d]
+        for i in range(1, len(b)):
+            rhs = d + dt * sum(A[i][j] * (L @ Qs[j]) for j in range(i))
+            Qs.append(np.linalg.solve(np.eye(n) - dt * A[i][i] * L, rhs))
+        dl = d + dt * sum(b[i] * (L @ Qs[i]) for i in range(len(b)))
+        dn = oracle.vec_of(q1 - q0, 0)
+        errs.append(max(np.linalg.norm(dn[v::5] - dl[v::5]) / np.linalg.norm(dl[v::5])
+                        for v in range(5)))
+    assert errs[1] < 1e-3 and 5 < errs[0] / errs[1] < 20, errs
+
+
+def test_nhevi_mass_conservation():
+    """The NHEVI-LU step conserves column mass: sum_k M_k rho_k."""
+    col = inputs.config1(heterogeneous=True, ncols=3)
+    tab = tableaux.as_float(tableaux.ark3())
+    qn, _ = inputs.perturbed_state(col, amp=1e-2)
+    q1, _ = oracle.nhevi_step_batch(col, tab, 30.0, qn, tol=1e-10, maxit=8)
+    w = np.array([float(v) for v in GLL_CLOSED[4][1]])
+    for c in range(3):
+        M = np.zeros(col["nz"])
+        for e in range(col["Ne"]):
+            for i in range(5):
+                M[4 * e + i] += w[i] * col["J"][4 * e + i, c]
+        assert abs(M @ q1[0, :, c] - M @ qn[0, :, c]) <= 1e-14 * (M @ qn[0, :, c])
