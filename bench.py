@@ -109,6 +109,11 @@ class OracleChecks:
         max(bar, 4 x the stage's rounding floor) (stage_floor)."""
         self.jobs.append(("stage", target, key, sc, lam, parts, bar, combine))
 
+    def nhevi_step(self, target, key, col, qn, gpu_next, tol):
+        """The GPU's NHEVI-LU ARK3 update q^{n+1} - q^n against the oracle's at the same
+        Newton tolerance."""
+        self.jobs.append(("nhevi", target, key, col, qn, gpu_next, tol))
+
     def ark_step(self, target, key, col, tableau, dt, qn, qref, gpu):
         """gpu: {"Q2": .., "Q3": .., "q_next": ..}; the increments against q^n are
         compared with the oracle's step of the same columns."""
@@ -153,6 +158,11 @@ def cpu_baseline_leg(checks, col=None, qn=None, qref=None, budget_cpu_s=15.0):
                 target[key + "_floor"] = max(target.get(key + "_floor", 0.0), max(floors))
             target["bar"] = bar
             target["meets_bar"] = bool(target.get("meets_bar", True) and ok)
+        elif job[0] == "nhevi":
+            _, target, key, c, q0, gpu_next, ntol = job
+            tab = tableaux.as_float(tableaux.ark3())
+            qo, _ = oracle.nhevi_step_batch(c, tab, 300.0, q0, tol=ntol, maxit=8)
+            target[key] = relerr_max(gpu_next - q0, qo - q0)
         else:
             _, target, key, c, tname, dt, q0, r0, gpu = job
             tab = tableaux.as_float(getattr(tableaux, tname)())
@@ -357,6 +367,40 @@ def ps_leg(ctx, checks, ncols=86402, steps=20, warmup=3, refresh=5):
          # U (2 kl + 1) and L (kl) FP64 entries per row, pivot and scale bytes
          "factor_bytes_per_column": 5 * col["nz"] * ((3 * (5 * (col["N"] + 1) - 1) + 1) * 8 + 2)}
     queue_stage_errors(checks, d, "stage_rel_err_vs_oracle", st, col, qn, idx, BARS["fp64"])
+    del st
+    return d
+
+
+def nhevi_leg(ctx, checks, ncols=86402, steps=3, tol=1e-5):
+    """NHEVI-LU at the ne=30 shape (Sec. 4.2.2): Newton per implicit stage of an ARK3
+    step to the paper's tolerance 1e-5 (Sec. 7.1), the Jacobian rebuilt and factored on
+    the GPU at every iterate (LHEVI-PS band LU); no explicit operator."""
+    import torch
+    from paper_2311_11425_amd import inputs
+    from paper_2311_11425_amd.driver import ColumnBatch, NheviStepper
+    col = inputs.with_wind(inputs.config2(ncols=ncols), u_h=0.0, w0=0.0)
+    qn, _ = inputs.perturbed_state(col)
+    B = ColumnBatch(ctx, col)
+    qd = torch.from_numpy(qn).cuda()
+    st = NheviStepper(ctx, B, "ARK3", 300.0, tol=tol, maxit=8)
+    out = B.empty_state()
+    its, meas = st.step(qd, out)  # warm-up, and the step whose result is checked
+    torch.cuda.synchronize()
+    res = out.cpu().numpy()
+    t = time.perf_counter()
+    for _ in range(steps):
+        its2, _ = st.step(qd, out)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1e3 / steps
+    rng = np.random.default_rng(8)
+    idx = np.unique(np.concatenate([rng.choice(ncols, min(ncols, 32) - 2, replace=False),
+                                    [0, ncols - 1]]))
+    d = {"columns": ncols, "ms_per_step": ms, "column_solves_per_s": 3 * ncols / (ms * 1e-3),
+         "newton_iterations_per_stage": its2, "newton_tolerance": tol,
+         "factorizations_per_step": int(sum(its2)),
+         "last_newton_measure_per_stage": meas}
+    checks.nhevi_step(d, "update_rel_err_vs_oracle", sample_columns(col, idx),
+                      np.ascontiguousarray(qn[..., idx]), np.ascontiguousarray(res[..., idx]), tol)
     del st
     return d
 
@@ -756,9 +800,10 @@ def main():
     ap.add_argument("--no-error-check", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="CPU-seconds for the oracle")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the set-3C, LHEVI-PS, config-1 accuracy, uneven-batch and "
-                         "serving legs")
-    ap.add_argument("--leg", choices=["config1", "share", "uneven", "serve", "set3c", "ps"],
+                    help="skip the set-3C, LHEVI-PS, NHEVI-LU, config-1 accuracy, "
+                         "uneven-batch and serving legs")
+    ap.add_argument("--leg", choices=["config1", "share", "uneven", "serve", "set3c", "ps",
+                                      "nhevi"],
                     help="run only this extra leg (for profiling) and print its JSON")
     ap.add_argument("--uneven-scale", type=float, default=1.0)
     ap.add_argument("--serve-scale", type=float, default=1.0)
@@ -783,7 +828,8 @@ def main():
                "uneven": lambda: uneven_leg(ctx, checks, scale=args.uneven_scale),
                "serve": lambda: serve_leg(ctx, checks, scale=args.serve_scale),
                "set3c": lambda: set3c_leg(ctx, checks),
-               "ps": lambda: ps_leg(ctx, checks)}[args.leg]()
+               "ps": lambda: ps_leg(ctx, checks),
+               "nhevi": lambda: nhevi_leg(ctx, checks)}[args.leg]()
         torch.cuda.synchronize()
         ctx.close()
         if not args.no_error_check:
@@ -902,6 +948,9 @@ def main():
         torch.cuda.empty_cache()
         log("LHEVI-PS leg ...")
         res["lhevi_ps"] = ps_leg(ctx, checks)
+        torch.cuda.empty_cache()
+        log("NHEVI-LU leg ...")
+        res["nhevi_lu"] = nhevi_leg(ctx, checks)
         torch.cuda.empty_cache()
         log("config-1 accuracy leg ...")
         res["config1_ark2_accuracy"] = cfg1_leg(ctx, checks)

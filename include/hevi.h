@@ -190,6 +190,24 @@ hevi_status hevi_build_column_ops_ps(hevi_ctx *ctx, const hevi_shape *shape,
 hevi_status hevi_ops_relinearize(hevi_ctx *ctx, hevi_ops *ops, const double *d_rho0,
                                  const double *d_U0, const double *d_Theta0,
                                  hipStream_t stream);
+/* NHEVI-LU (Sec. 4.2.2): each implicit stage solves F(q) = q - Lambda V(q) - R = 0 by
+ * Newton's method, rebuilding and factoring the Jacobian I - Lambda dV/dq at every
+ * iterate.  hevi_vertical_op evaluates the nonlinear set-2C vertical operator
+ *   V(q) = -(div(J U^z), div(J (U U^z/rho + P(Theta) grad zeta)) + rho Phi' grad zeta,
+ *            div(J Theta U^z/rho)) / J     (Appendix A.2; P of eq. set2c_pressure)
+ * with the discretisation of L_z (continuity row weak, the others strong, DSS, lumped
+ * mass, zero momentum rows at the rigid lid), for any set-2C operator's geometry (the
+ * state is q, [v][k][c]; d_V must not alias d_q).  The Newton step then is
+ * hevi_ops_relinearize(ops, q_rho, q_U, q_Theta) + hevi_refactor + hevi_stage_solve with
+ * E = {R, q, V(q)}, e = {1, -1, Lambda} (the increment, rigid-lid projected) +
+ * hevi_combine.  hevi_newton_increment waits for `stream` and returns the stopping
+ * measure max over columns and variables of ||dq_v|| / ||q_v - q^n_v|| (node norms, q the
+ * updated iterate; the paper stops at 1e-5, Sec. 7.1). */
+hevi_status hevi_vertical_op(hevi_ctx *ctx, const hevi_ops *ops, const double *d_q, double *d_V,
+                             hipStream_t stream);
+hevi_status hevi_newton_increment(hevi_ctx *ctx, const hevi_ops *ops, const double *d_dq,
+                                  const double *d_q, const double *d_qn, double *h_rel,
+                                  hipStream_t stream);
 /* Waits for `stream` and reports the first column whose inputs were invalid
  * (non-positive J/rho0/Theta0, zero grad(zeta), non-finite values). */
 hevi_status hevi_ops_check(hevi_ctx *ctx, const hevi_ops *ops, int64_t *first_bad_col,

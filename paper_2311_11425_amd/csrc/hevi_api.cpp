@@ -162,12 +162,14 @@ hevi_status hevi_build_column_ops_set(hevi_ctx* ctx, const hevi_shape* shape,
   o->d_ops = nullptr;
   o->d_info = nullptr;
   o->d_tilt = nullptr;
+  o->d_aux = nullptr;
   o->tilted = 0;
   o->s3 = eqset == HEVI_SET_3C;
   o->ps = 0;
   // set 3C: one more per-node field (J dP/drho) after the tile-interleaved eight
   if ((s = dev_alloc(&o->d_ops, tiles_nodes(o->sh) * (HEVI_NOPS + o->s3) * sizeof(double))) ||
       (s = dev_alloc(&o->d_info, sizeof(HeviDevInfo))) ||
+      (s = dev_alloc(&o->d_aux, sizeof(HeviDevInfo))) ||
       (s = dev_alloc(&o->d_tilt, sizeof(int32_t)))) {
     hevi_ops_free(o);
     return s;
@@ -214,12 +216,14 @@ hevi_status hevi_build_column_ops_ps(hevi_ctx* ctx, const hevi_shape* shape,
   o->d_ops = nullptr;
   o->d_info = nullptr;
   o->d_tilt = nullptr;
+  o->d_aux = nullptr;
   o->tilted = 0;
   o->s3 = 0;
   o->ps = 1;
   // the eight fields, then the three velocity planes of the linearisation state
   if ((s = dev_alloc(&o->d_ops, tiles_nodes(o->sh) * (HEVI_NOPS + 3) * sizeof(double))) ||
       (s = dev_alloc(&o->d_info, sizeof(HeviDevInfo))) ||
+      (s = dev_alloc(&o->d_aux, sizeof(HeviDevInfo))) ||
       (s = dev_alloc(&o->d_tilt, sizeof(int32_t)))) {
     hevi_ops_free(o);
     return s;
@@ -267,6 +271,7 @@ void hevi_ops_free(hevi_ops* ops) {
   if (ops->d_ops) (void)hipFree(ops->d_ops);
   if (ops->d_info) (void)hipFree(ops->d_info);
   if (ops->d_tilt) (void)hipFree(ops->d_tilt);
+  if (ops->d_aux) (void)hipFree(ops->d_aux);
   delete ops;
 }
 
@@ -487,6 +492,35 @@ hevi_status hevi_combine(hevi_ctx* ctx, const hevi_ops* ops, int32_t n_v,
   if (!ok(hipSetDevice(ctx->device))) return HEVI_E_DEVICE;
   const int64_t n = 5 * (int64_t)ops->sh.nz * ops->sh.ncols;
   if (!ok(hevi_launch_combine(n, V, d_out, stream))) return HEVI_E_DEVICE;
+  return HEVI_OK;
+}
+
+hevi_status hevi_vertical_op(hevi_ctx* ctx, const hevi_ops* ops, const double* d_q, double* d_V,
+                             hipStream_t stream) {
+  if (!ctx || !ops || ops->s3) return HEVI_E_INVALID;
+  if (ops->sh.ncols > 0 && (!d_q || !d_V || d_q == d_V)) return HEVI_E_INVALID;
+  if (!ok(hipSetDevice(ctx->device))) return HEVI_E_DEVICE;
+  const hevi_consts& k = ops->consts;
+  if (!ok(hevi_launch_vertical_op(ops->sh, k.R, k.cp, k.p_A, ops->d_ops, d_q, d_V, stream)))
+    return HEVI_E_DEVICE;
+  return HEVI_OK;
+}
+
+hevi_status hevi_newton_increment(hevi_ctx* ctx, const hevi_ops* ops, const double* d_dq,
+                                  const double* d_q, const double* d_qn, double* h_rel,
+                                  hipStream_t stream) {
+  if (!ctx || !ops || !h_rel) return HEVI_E_INVALID;
+  if (ops->sh.ncols > 0 && (!d_dq || !d_q || !d_qn)) return HEVI_E_INVALID;
+  if (!ok(hipSetDevice(ctx->device))) return HEVI_E_DEVICE;
+  HeviDevInfo h;
+  if (!ok(hevi_launch_info_reset(ops->d_aux, stream)) ||
+      !ok(hevi_launch_newton_rel(ops->sh, d_dq, d_q, d_qn, ops->d_aux, stream)) ||
+      !ok(hipMemcpyAsync(&h, ops->d_aux, sizeof(h), hipMemcpyDeviceToHost, stream)) ||
+      !ok(hipStreamSynchronize(stream)))
+    return HEVI_E_DEVICE;
+  double r;
+  std::memcpy(&r, &h.max_res_bits, sizeof(r));
+  *h_rel = r;
   return HEVI_OK;
 }
 

@@ -97,6 +97,14 @@ hipError_t hevi_launch_ps_state(const HeviShapeDev& sh, double R, double cp, dou
                                 const double* rho0, const double* U0, const double* Th0,
                                 double* ops, HeviDevInfo* info, hipStream_t st);
 
+// NHEVI-LU: the nonlinear set-2C vertical operator V(q) (any order), and the Newton
+// measure max ||dq_v|| / ||q_v - q^n_v|| into info->max_res_bits
+hipError_t hevi_launch_vertical_op(const HeviShapeDev& sh, double R, double cp, double pA,
+                                   const double* ops, const double* q, double* V,
+                                   hipStream_t st);
+hipError_t hevi_launch_newton_rel(const HeviShapeDev& sh, const double* dq, const double* q,
+                                  const double* qn, HeviDevInfo* info, hipStream_t st);
+
 hipError_t hevi_launch_combine(int64_t n, const HeviTerms& V, double* out, hipStream_t st);
 
 hipError_t hevi_launch_info_reset(HeviDevInfo* info, hipStream_t st);

@@ -25,6 +25,7 @@ struct hevi_ops {
   int tilted;       // its value: some column's grad(zeta) is not one vector along it
   int s3;           // set 3C (state (rho, U, E); ops hold the J dP/drho plane)
   int ps;           // LHEVI-PS: linearised at a moving state (ops hold its velocity planes)
+  HeviDevInfo* d_aux;  // reduction slot of hevi_newton_increment
 };
 
 struct hevi_factors {

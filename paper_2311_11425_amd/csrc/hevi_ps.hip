@@ -433,6 +433,109 @@ __global__ __launch_bounds__(64, kStreamWaves<N>) void k_apply_ps(
   b_apply<N, HAS_REF, false, true>((int64_t)blockIdx.x, sh, Gll<N>{}, ops, x, xref, y, 1);
 }
 
+// NHEVI-LU (Sec. 4.2.2): the nonlinear set-2C vertical operator V(q) (Appendix A.2)
+// with the discretisation of the linear one: fluxes F_rho = J U^z, F_U = J (U U^z/rho +
+// P(Theta) grad zeta), F_Theta = J Theta U^z/rho (U^z = grad(zeta).U, P = P_A (R
+// Theta/P_A)^gamma, eq. set2c_pressure), the continuity row weak, the others strong,
+// DSS, lumped mass, gravity -rho Phi' grad(zeta), zero momentum rows at the rigid
+// lid.  One lane per column, elements in order, the sums of a shared node carried.
+template <int N>
+__global__ __launch_bounds__(64) void k_vertical_op(HeviShapeDev sh, double R, double gam,
+                                                    double pA, const double* __restrict__ ops,
+                                                    const double* __restrict__ q,
+                                                    double* __restrict__ V) {
+  const Gll<N> tab{};
+  const int lane = threadIdx.x;
+  const int64_t tile = blockIdx.x;
+  const int64_t c = tile * T + lane;
+  const bool valid = c < sh.ncols;
+  const int64_t cc = valid ? c : sh.ncols - 1;
+  const int nz = sh.nz, Ne = sh.Ne;
+  const int64_t nc = sh.ncols;
+  OpsView op{ops, tile, nz, lane};
+  double cr = 0.0, c0 = 0.0, c1 = 0.0, c2 = 0.0, ct = 0.0;
+  for (int e = 0; e < Ne; ++e) {
+    double Fr[N + 1], F0[N + 1], F1[N + 1], F2[N + 1], Ft[N + 1], rho[N + 1];
+#pragma unroll
+    for (int j = 0; j <= N; ++j) {
+      const int k = e * N + j;
+      const double g0 = op(k, OP_GX), g1 = op(k, OP_GY), g2 = op(k, OP_GZ), Jk = op(k, OP_J);
+      const double r = q[cix(nz, nc, 0, k, cc)];
+      const double u0 = q[cix(nz, nc, 1, k, cc)], u1 = q[cix(nz, nc, 2, k, cc)];
+      const double u2 = q[cix(nz, nc, 3, k, cc)], th = q[cix(nz, nc, 4, k, cc)];
+      const double Uz = g0 * u0 + g1 * u1 + g2 * u2;
+      const double P = pA * pow(R * th / pA, gam);
+      const double a = Uz / r;
+      rho[j] = r;
+      Fr[j] = Jk * Uz;
+      F0[j] = Jk * (u0 * a + P * g0);
+      F1[j] = Jk * (u1 * a + P * g1);
+      F2[j] = Jk * (u2 * a + P * g2);
+      Ft[j] = Jk * th * a;
+    }
+#pragma unroll
+    for (int i = 0; i <= N; ++i) {
+      double sr = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0, st = 0.0;
+#pragma unroll
+      for (int j = 0; j <= N; ++j) {
+        const double d = tab.D[i * (N + 1) + j];
+        sr += tab.w[j] * tab.D[j * (N + 1) + i] * Fr[j];
+        s0 += d * F0[j]; s1 += d * F1[j]; s2 += d * F2[j]; st += d * Ft[j];
+      }
+      const double wi = tab.w[i];
+      s0 *= wi; s1 *= wi; s2 *= wi; st *= wi;
+      if (i == 0) { sr += cr; s0 += c0; s1 += c1; s2 += c2; st += ct; }
+      if (i == N && e < Ne - 1) { cr = sr; c0 = s0; c1 = s1; c2 = s2; ct = st; continue; }
+      const int k = e * N + i;
+      const double mi = op(k, OP_MINV), ph = op(k, OP_PHI);
+      const bool lid = (k == 0) || (k == nz - 1);
+      if (valid) {
+        V[cix(nz, nc, 0, k, c)] = mi * sr;
+        V[cix(nz, nc, 1, k, c)] = lid ? 0.0 : -mi * s0 - ph * op(k, OP_GX) * rho[i];
+        V[cix(nz, nc, 2, k, c)] = lid ? 0.0 : -mi * s1 - ph * op(k, OP_GY) * rho[i];
+        V[cix(nz, nc, 3, k, c)] = lid ? 0.0 : -mi * s2 - ph * op(k, OP_GZ) * rho[i];
+        V[cix(nz, nc, 4, k, c)] = -mi * st;
+      }
+    }
+  }
+}
+
+// Newton stopping measure: max over columns and variables of ||dq_v|| / ||q_v - q^n_v||
+// (norms over the column's nodes; q the updated iterate), reduced into info->max_res_bits.
+__global__ __launch_bounds__(64) void k_newton_rel(HeviShapeDev sh, const double* __restrict__ dq,
+                                                   const double* __restrict__ q,
+                                                   const double* __restrict__ qn,
+                                                   HeviDevInfo* info) {
+  const int64_t c = (int64_t)blockIdx.x * T + threadIdx.x;
+  if (c >= sh.ncols) return;
+  const int nz = sh.nz;
+  const int64_t nc = sh.ncols;
+  double worst = 0.0;
+  for (int v = 0; v < 5; ++v) {
+    double d2 = 0.0, q2 = 0.0;
+    for (int k = 0; k < nz; ++k) {
+      const size_t i = cix(nz, nc, v, k, c);
+      const double d = dq[i], w = q[i] - qn[i];
+      d2 += d * d;
+      q2 += w * w;
+    }
+    const double rel = q2 > 0.0 ? sqrt(d2 / q2) : (d2 > 0.0 ? INFINITY : 0.0);
+    worst = fmax(worst, rel);
+  }
+  if (!isfinite(worst)) worst = 1.0e300;
+  atomicMax((unsigned long long*)&info->max_res_bits, (unsigned long long)__double_as_longlong(worst));
+}
+
+template <int N>
+struct VerticalOp {
+  static hipError_t run(const HeviShapeDev& sh, double R, double gam, double pA,
+                        const double* ops, const double* q, double* V, hipStream_t st) {
+    hipLaunchKernelGGL(k_vertical_op<N>, dim3((unsigned)sh.ntiles), dim3(T), 0, st, sh, R, gam,
+                       pA, ops, q, V);
+    return hipGetLastError();
+  }
+};
+
 template <template <int> class F, typename... A>
 hipError_t dispatch_ps(int N, A&&... a) {
   switch (N) {
@@ -514,5 +617,29 @@ hipError_t hevi_launch_ps_state(const HeviShapeDev& sh, double R, double cp, dou
   if (sh.ntiles == 0) return hipSuccess;
   hipLaunchKernelGGL(k_ps_state, dim3((unsigned)sh.ntiles), dim3(T), 0, st, sh, R, cp, pA, rho0,
                      U0, Th0, ops, info);
+  return hipGetLastError();
+}
+
+hipError_t hevi_launch_vertical_op(const HeviShapeDev& sh, double R, double cp, double pA,
+                                   const double* ops, const double* q, double* V,
+                                   hipStream_t st) {
+  if (sh.ntiles == 0) return hipSuccess;
+  if (sh.N > HEVI_PS_MAXN) {
+    // orders 6..8 share the same body
+    switch (sh.N) {
+      case 6: return VerticalOp<6>::run(sh, R, cp / (cp - R), pA, ops, q, V, st);
+      case 7: return VerticalOp<7>::run(sh, R, cp / (cp - R), pA, ops, q, V, st);
+      case 8: return VerticalOp<8>::run(sh, R, cp / (cp - R), pA, ops, q, V, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  return dispatch_ps<VerticalOp>(sh.N, sh, R, cp / (cp - R), pA, ops, q, V, st);
+}
+
+hipError_t hevi_launch_newton_rel(const HeviShapeDev& sh, const double* dq, const double* q,
+                                  const double* qn, HeviDevInfo* info, hipStream_t st) {
+  if (sh.ncols == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_newton_rel, dim3((unsigned)sh.ntiles), dim3(T), 0, st, sh, dq, q, qn,
+                     info);
   return hipGetLastError();
 }

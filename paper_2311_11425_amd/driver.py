@@ -139,3 +139,65 @@ class ArkStepper:
         ctx.combine(ops, [qn] + self.S, [1.0] + [self.dt * bi for bi in self.b], out,
                     stream=stream)
         return infos
+
+
+class NheviStepper:
+    """One NHEVI-LU time step per call (Sec. 4.2.2).
+
+    Every implicit stage i >= 2 solves F(q) = q - Lambda V(q) - R = 0, R = q^n +
+    dt sum_{j<i} a~_ij V(Q_j), by Newton's method from q = Q_{i-1}: per iteration
+    V(q), the Jacobian rebuilt at q (hevi_ops_relinearize of the batch's LHEVI-PS
+    operator) and factored (hevi_refactor), the increment dq = J^{-1}(R - q + Lambda V(q))
+    (hevi_stage_solve), q += dq (hevi_combine), until the measure of
+    hevi_newton_increment is <= tol or maxit iterations.  There is no explicit operator
+    here; q^{n+1} = q^n + dt sum_i b_i V(Q_i).  The batch's operator is relinearised by
+    every step (it ends at the last stage's iterate)."""
+
+    def __init__(self, ctx: hevi.Context, batch: ColumnBatch, tableau="ARK3", dt=300.0,
+                 tol=1e-5, maxit=8, stream=None):
+        if getattr(batch, "U0", None) is None:
+            raise ValueError("NHEVI-LU needs an LHEVI-PS operator (a batch with U0)")
+        self.ctx, self.batch = ctx, batch
+        tab = hevi.tableau(tableau)
+        self.s = tab["s"]
+        self.Aimp, self.b = tab["Aimp"], tab["b"]
+        self.dt = float(dt)
+        self.lam = self.Aimp[1][1] * self.dt
+        self.tol, self.maxit = float(tol), int(maxit)
+        self.Q = [batch.empty_state() for _ in range(self.s)]
+        self.V = [batch.empty_state() for _ in range(self.s)]
+        self.R, self.Vq, self.dq = batch.empty_state(), batch.empty_state(), batch.empty_state()
+        self.factors = ctx.factor(batch.ops, self.lam, hevi.HEVI_FP64, stream=stream)
+
+    def step(self, qn, out, stream=None):
+        """One step; returns the Newton iterations of each implicit stage and the last
+        stopping measure of each."""
+        ctx, ops, f = self.ctx, self.batch.ops, self.factors
+        self.Q[0] = qn
+        ctx.vertical_op(ops, qn, self.V[0], stream=stream)
+        its, meas = [], []
+        for i in range(1, self.s):
+            ctx.combine(ops, [qn] + self.V[:i],
+                        [1.0] + [self.dt * self.Aimp[i][j] for j in range(i)], self.R,
+                        stream=stream)
+            q = self.Q[i]
+            ctx.combine(ops, [self.Q[i - 1]], [1.0], q, stream=stream)
+            rel = float("inf")
+            m = 0
+            while m < self.maxit:
+                m += 1
+                ctx.vertical_op(ops, q, self.Vq, stream=stream)
+                ctx.relinearize(ops, q[0], q[1:4], q[4], stream=stream)
+                ctx.refactor(f, self.lam, stream=stream)
+                ctx.stage_solve(f, [self.R, q, self.Vq], [1.0, -1.0, self.lam], [], [],
+                                self.dq, stream=stream)
+                ctx.combine(ops, [q, self.dq], [1.0, 1.0], q, stream=stream)
+                rel = ctx.newton_increment(ops, self.dq, q, qn, stream=stream)
+                if rel <= self.tol:
+                    break
+            its.append(m)
+            meas.append(rel)
+            ctx.vertical_op(ops, q, self.V[i], stream=stream)
+        ctx.combine(ops, [qn] + self.V, [1.0] + [self.dt * bi for bi in self.b], out,
+                    stream=stream)
+        return its, meas

@@ -26,6 +26,7 @@ STATUS = {0: "HEVI_OK", 1: "HEVI_E_INVALID", 2: "HEVI_E_SHAPE", 3: "HEVI_E_NOMEM
 # every symbol include/hevi.h declares
 EXPORTS = ["hevi_create", "hevi_destroy", "hevi_status_str", "hevi_build_column_ops",
            "hevi_build_column_ops_set", "hevi_build_column_ops_ps", "hevi_ops_relinearize",
+           "hevi_vertical_op", "hevi_newton_increment",
            "hevi_ops_check", "hevi_ops_free", "hevi_apply_op", "hevi_factor", "hevi_refactor",
            "hevi_factors_check", "hevi_factors_band_entries", "hevi_factors_free",
            "hevi_stage_solve", "hevi_solve_noalloc", "hevi_combine",
@@ -118,6 +119,8 @@ def load():
         "hevi_build_column_ops_ps": ([_vp, ctypes.POINTER(Shape), ctypes.POINTER(Consts), _vp,
                                       _vp, _vp, _vp, _vp, _vp, pp, _vp], ctypes.c_int),
         "hevi_ops_relinearize": ([_vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+        "hevi_vertical_op": ([_vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+        "hevi_newton_increment": ([_vp, _vp, _vp, _vp, _vp, pd, _vp], ctypes.c_int),
         "hevi_ops_check": ([_vp, _vp, ctypes.POINTER(i64), _vp], ctypes.c_int),
         "hevi_ops_free": ([_vp], None),
         "hevi_apply_op": ([_vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
@@ -324,6 +327,17 @@ class Context:
         _check(self.lib.hevi_ops_relinearize(self.handle, ops.handle, _ptr(rho0), _ptr(U0),
                                              _ptr(Theta0), _stream(stream)),
                "hevi_ops_relinearize")
+
+    def vertical_op(self, ops, q, V, stream=None):
+        _check(self.lib.hevi_vertical_op(self.handle, ops.handle, _ptr(q), _ptr(V),
+                                         _stream(stream)), "hevi_vertical_op")
+
+    def newton_increment(self, ops, dq, q, qn, stream=None):
+        r = ctypes.c_double(0.0)
+        _check(self.lib.hevi_newton_increment(self.handle, ops.handle, _ptr(dq), _ptr(q),
+                                              _ptr(qn), ctypes.byref(r), _stream(stream)),
+               "hevi_newton_increment")
+        return r.value
 
     def apply_op(self, ops, x, y, xref=None, stream=None):
         _check(self.lib.hevi_apply_op(self.handle, ops.handle, _ptr(x), _ptr(xref), _ptr(y),
