@@ -93,7 +93,9 @@ typedef struct { int32_t order_N, n_elem; int64_t n_cols; } hevi_shape;
  *   system with the FP64 residual q^ - A q_tt formed on offset-free vectors, in
  *   a slower kernel that keeps every vector in scratch (an accuracy reference;
  *   the default path already solves the row-equilibrated reduced system and
- *   recovers the momentum from u without differencing large terms). */
+ *   recovers the momentum from u without differencing large terms).  The first
+ *   stage solve with full_sweeps > 0 on a factor object allocates that kernel's
+ *   wider scratch (15 more FP64 per node), which the object keeps until freed. */
 typedef struct { int32_t max_sweeps; double rel_residual_target; int32_t full_sweeps; } hevi_refine;
 
 typedef struct {
@@ -315,8 +317,9 @@ hevi_status hevi_tableau(const char *name, int32_t *s, double *a_exp, double *a_
  * entries plus three byte planes: pivot offsets, U row extents, row-scale
  * exponents); the paper's LAPACK band layout (ldab = 3 * 5 (N+1) - 2 rows of
  * 8-byte entries per unknown plus a 4-byte pivot, Sec. 4.2.3); and everything a
- * factor object holds resident (factors, the stage solve's FP64 scratch and, for
- * FP32 factors of order N > 6, an FP64 assembly buffer): the figure the server
+ * factor object holds resident (factors, the stage solve's FP64 scratch of 6 values
+ * per node and, for FP32 factors of order N > 6, an FP64 assembly buffer; not the
+ * full-sweep scratch allocated on demand): the figure the server
  * charges against its HBM budget, per column of the 64-column tiles it
  * allocates.  Any output pointer may be NULL. */
 hevi_status hevi_sizes(const hevi_shape *shape, hevi_precision prec, size_t *ops_bytes_per_col,

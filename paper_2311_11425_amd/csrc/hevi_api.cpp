@@ -431,6 +431,7 @@ void hevi_factors_free(hevi_factors* f) {
   fr(f->L);
   fr(f->piv);
   fr(f->ws);
+  if (f->wsf) (void)hipFree(f->wsf);
   fr(f->d_info);
   delete f;
 }
@@ -465,13 +466,19 @@ hevi_status hevi_stage_solve(hevi_ctx* ctx, const hevi_factors* f, int32_t n_e,
   }
   if (f->prec == HEVI_FP64) sweeps = 0;
   if (!ok(hipSetDevice(ctx->device))) return HEVI_E_DEVICE;
+  if (full > 0 && !o->ps && !f->wsf) {
+    // the accuracy mode's wider scratch, once per factor object (this call allocates)
+    hevi_status a = dev_alloc(&f->wsf, tiles_nodes(o->sh) * HEVI_NWS_FULL * sizeof(double));
+    if (a) return a;
+  }
   if (h_info && !ok(hevi_launch_info_reset(f->d_info, stream))) return HEVI_E_DEVICE;
   const hipError_t e =
       o->ps ? hevi_launch_ps_stage(o->sh, o->d_ops, (const double*)f->U, (const double*)f->L,
                                    f->piv, E, Q, d_Qi, f->d_info, stream)
             : hevi_launch_stage_solve(o->sh, o->s3, f->lambda, o->tilted,
                                       f->prec == HEVI_FP32_REFINE, o->d_ops, f->U, f->L, f->piv,
-                                      f->ws, E, Q, d_Qi, sweeps, target, full, f->d_info, stream);
+                                      full > 0 ? f->wsf : f->ws, E, Q, d_Qi, sweeps, target,
+                                      full, f->d_info, stream);
   if (!ok(e)) return HEVI_E_DEVICE;
   if (h_info) {
     std::memset(h_info, 0, sizeof(*h_info));

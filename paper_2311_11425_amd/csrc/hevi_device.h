@@ -121,7 +121,7 @@ __device__ __forceinline__ const double* ps_plane(const double* ops, const HeviS
 
 // v_rho = Drho u and v_Th = DTh u for all nodes; u read from scratch field
 // fu, results written to fields fr, ft.
-template <int N>
+template <int N, int NWS = HEVI_NWS>
 __device__ void div_pass(Gll<N> tab, const OpsView& op, int Ne, double* ws, int64_t tile,
                          int lane, int fu, int fr, int ft) {
   const int nz = op.nz;
@@ -131,7 +131,7 @@ __device__ void div_pass(Gll<N> tab, const OpsView& op, int Ne, double* ws, int6
 #pragma unroll
     for (int j = 0; j <= N; ++j) {
       const int k = e * N + j;
-      const double u = ws[tix(tile, nz, k, HEVI_NWS, fu, lane)];
+      const double u = ws[tix(tile, nz, k, NWS, fu, lane)];
       Ju[j] = op(k, OP_J) * u;
       Jtu[j] = op(k, OP_JTH) * u;
     }
@@ -148,8 +148,8 @@ __device__ void div_pass(Gll<N> tab, const OpsView& op, int Ne, double* ws, int6
       if (a == N && e < Ne - 1) { cr = sr; ct = st; continue; }
       const int k = e * N + a;
       const double mi = op(k, OP_MINV);
-      ws[tix(tile, nz, k, HEVI_NWS, fr, lane)] = mi * sr;
-      ws[tix(tile, nz, k, HEVI_NWS, ft, lane)] = -mi * st;
+      ws[tix(tile, nz, k, NWS, fr, lane)] = mi * sr;
+      ws[tix(tile, nz, k, NWS, ft, lane)] = -mi * st;
     }
   }
 }
@@ -158,7 +158,7 @@ __device__ void div_pass(Gll<N> tab, const OpsView& op, int Ne, double* ws, int6
 //   G_k = -M^-1 sum_e w_i sum_j D_ij (J c_Theta grad zeta)_j v_Th,j - Phi'_k grad(zeta)_k v_rho,k
 // (S3: the pressure is J (c v_Th + dP/drho v_rho)); writes grad(zeta)_k . G_k into
 // field fo (zero at the rigid-lid nodes).
-template <int N, bool S3 = false>
+template <int N, bool S3 = false, int NWS = HEVI_NWS>
 __device__ void pg_pass(Gll<N> tab, const OpsView& op, int Ne, double* ws, int64_t tile,
                         int lane, int fr, int ft, int fo) {
   const int nz = op.nz;
@@ -168,8 +168,8 @@ __device__ void pg_pass(Gll<N> tab, const OpsView& op, int Ne, double* ws, int64
 #pragma unroll
     for (int j = 0; j <= N; ++j) {
       const int k = e * N + j;
-      double v = op(k, OP_JCT) * ws[tix(tile, nz, k, HEVI_NWS, ft, lane)];
-      if constexpr (S3) v += op.jpr(k) * ws[tix(tile, nz, k, HEVI_NWS, fr, lane)];
+      double v = op(k, OP_JCT) * ws[tix(tile, nz, k, NWS, ft, lane)];
+      if constexpr (S3) v += op.jpr(k) * ws[tix(tile, nz, k, NWS, fr, lane)];
       f0[j] = v * op(k, OP_GX);
       f1[j] = v * op(k, OP_GY);
       f2[j] = v * op(k, OP_GZ);
@@ -191,11 +191,11 @@ __device__ void pg_pass(Gll<N> tab, const OpsView& op, int Ne, double* ws, int64
       const bool lid = (k == 0) || (k == nz - 1);
       const double mi = op(k, OP_MINV), ph = op(k, OP_PHI);
       const double gx = op(k, OP_GX), gy = op(k, OP_GY), gzz = op(k, OP_GZ);
-      const double vr = ws[tix(tile, nz, k, HEVI_NWS, fr, lane)];
+      const double vr = ws[tix(tile, nz, k, NWS, fr, lane)];
       const double G0 = -mi * s0 - ph * gx * vr;
       const double G1 = -mi * s1 - ph * gy * vr;
       const double G2 = -mi * s2 - ph * gzz * vr;
-      ws[tix(tile, nz, k, HEVI_NWS, fo, lane)] = lid ? 0.0 : gx * G0 + gy * G1 + gzz * G2;
+      ws[tix(tile, nz, k, NWS, fo, lane)] = lid ? 0.0 : gx * G0 + gy * G1 + gzz * G2;
     }
   }
 }
@@ -903,7 +903,7 @@ enum { WS_R = 0, WS_U = 1, WS_VR = 2, WS_VT = 3, WS_T = 4, WS_D = 5, WS_B = 6, W
 // refilled as soon as a slot is consumed, while it works on the current row.  The
 // fused stage kernels (LDSRU) hold r/u in LDS and have the registers for a third
 // backward slot; the others spill with it.
-template <int N, typename FT, bool LDSRU = false>
+template <int N, typename FT, bool LDSRU = false, int NWS = HEVI_NWS>
 __device__ __forceinline__ void band_solve(const FT* __restrict__ Ub, const FT* __restrict__ Lb,
                                            const uint8_t* __restrict__ piv, size_t plane,
                                            double* ws, int64_t tile, int nz, int lane, int fi,
@@ -912,7 +912,7 @@ __device__ __forceinline__ void band_solve(const FT* __restrict__ Ub, const FT* 
   // ru[k * 64 + lane] in LDS used in place
   auto S = [&](int k, int f) -> double& {
     if constexpr (LDSRU) return ru[k * T + lane];
-    else return ws[tix(tile, nz, k, HEVI_NWS, f, lane)];
+    else return ws[tix(tile, nz, k, NWS, f, lane)];
   };
   constexpr int B = 2 * N, K = 4 * N, PF = 3, PB = LDSRU ? 3 : 2;
   // U row extents (see plane_size): entries past them are zeros and, with FP64
@@ -1026,7 +1026,7 @@ __device__ __forceinline__ void band_solve(const FT* __restrict__ Ub, const FT* 
 // correction is small, ||delta|| <= target ||u|| (a residual test would stop
 // early: ||u_err|| can exceed ||d|| / ||r|| by the condition number of S), or
 // max_sweeps.  Per column; the wavefront sweeps while any column needs one.
-template <int N, typename FT, bool S3 = false>
+template <int N, typename FT, bool S3 = false, int NWS = HEVI_NWS>
 __device__ void reduced_refine(Gll<N> tab, const OpsView& op, int Ne, double* ws,
                                int64_t tile, int lane, bool valid, double lambda,
                                const FT* __restrict__ Ub, const FT* __restrict__ Lb,
@@ -1038,21 +1038,21 @@ __device__ void reduced_refine(Gll<N> tab, const OpsView& op, int Ne, double* ws
   for (;;) {
     const bool need = !(corr <= rel_target) && sweeps < max_sweeps;
     if (!__any(valid && need)) break;
-    div_pass<N>(tab, op, Ne, ws, tile, lane, WS_U, WS_VR, WS_VT);
-    pg_pass<N, S3>(tab, op, Ne, ws, tile, lane, WS_VR, WS_VT, WS_T);
+    div_pass<N, NWS>(tab, op, Ne, ws, tile, lane, WS_U, WS_VR, WS_VT);
+    pg_pass<N, S3, NWS>(tab, op, Ne, ws, tile, lane, WS_VR, WS_VT, WS_T);
     const double l2 = lambda * lambda;
     for (int k = 0; k < nz; ++k) {
-      const double u = ws[tix(tile, nz, k, HEVI_NWS, WS_U, lane)];
-      const double Ku = ws[tix(tile, nz, k, HEVI_NWS, WS_T, lane)];
+      const double u = ws[tix(tile, nz, k, NWS, WS_U, lane)];
+      const double Ku = ws[tix(tile, nz, k, NWS, WS_T, lane)];
       const double Su = (k == 0 || k == nz - 1) ? u : u - l2 * Ku;
-      ws[tix(tile, nz, k, HEVI_NWS, WS_T, lane)] = ws[tix(tile, nz, k, HEVI_NWS, WS_R, lane)] - Su;
+      ws[tix(tile, nz, k, NWS, WS_T, lane)] = ws[tix(tile, nz, k, NWS, WS_R, lane)] - Su;
     }
-    band_solve<N, FT>(Ub, Lb, piv, plane, ws, tile, nz, lane, WS_T, WS_D);
+    band_solve<N, FT, false, NWS>(Ub, Lb, piv, plane, ws, tile, nz, lane, WS_T, WS_D);
     if (need) {
       double d2 = 0.0, u2 = 0.0;
       for (int k = 0; k < nz; ++k) {
-        const size_t iu = tix(tile, nz, k, HEVI_NWS, WS_U, lane);
-        const double d = ws[tix(tile, nz, k, HEVI_NWS, WS_D, lane)];
+        const size_t iu = tix(tile, nz, k, NWS, WS_U, lane);
+        const double d = ws[tix(tile, nz, k, NWS, WS_D, lane)];
         const double u = ws[iu] + d;
         ws[iu] = u;
         d2 += d * d;
@@ -1068,7 +1068,7 @@ __device__ void reduced_refine(Gll<N> tab, const OpsView& op, int Ne, double* ws
 
 // Reduced right-hand side r = grad(zeta).(b_U + lambda (PG b_Theta - Phi' grad(zeta) b_rho))
 // of a 5-field vector b stored in scratch fields fb..fb+4 (zero at the lid nodes).
-template <int N, bool S3 = false>
+template <int N, bool S3 = false, int NWS = HEVI_NWS>
 __device__ double reduced_rhs_pass(Gll<N> tab, const OpsView& op, int Ne, double* ws,
                                    int64_t tile, int lane, double lambda, int fb) {
   const int nz = op.nz;
@@ -1078,8 +1078,8 @@ __device__ double reduced_rhs_pass(Gll<N> tab, const OpsView& op, int Ne, double
 #pragma unroll
     for (int j = 0; j <= N; ++j) {
       const int k = e * N + j;
-      double p = op(k, OP_JCT) * ws[tix(tile, nz, k, HEVI_NWS, fb + 4, lane)];
-      if constexpr (S3) p += op.jpr(k) * ws[tix(tile, nz, k, HEVI_NWS, fb + 0, lane)];
+      double p = op(k, OP_JCT) * ws[tix(tile, nz, k, NWS, fb + 4, lane)];
+      if constexpr (S3) p += op.jpr(k) * ws[tix(tile, nz, k, NWS, fb + 0, lane)];
       f0[j] = p * op(k, OP_GX); f1[j] = p * op(k, OP_GY); f2[j] = p * op(k, OP_GZ);
     }
 #pragma unroll
@@ -1098,16 +1098,16 @@ __device__ double reduced_rhs_pass(Gll<N> tab, const OpsView& op, int Ne, double
       if (k != 0 && k != nz - 1) {
         const double gx = op(k, OP_GX), gy = op(k, OP_GY), gzz = op(k, OP_GZ);
         const double mi = op(k, OP_MINV), ph = op(k, OP_PHI);
-        const double br = ws[tix(tile, nz, k, HEVI_NWS, fb + 0, lane)];
+        const double br = ws[tix(tile, nz, k, NWS, fb + 0, lane)];
         const double g1 = lambda * (-mi * s0 - ph * gx * br);
         const double g2 = lambda * (-mi * s1 - ph * gy * br);
         const double g3 = lambda * (-mi * s2 - ph * gzz * br);
-        r = gx * (ws[tix(tile, nz, k, HEVI_NWS, fb + 1, lane)] + g1) +
-            gy * (ws[tix(tile, nz, k, HEVI_NWS, fb + 2, lane)] + g2) +
-            gzz * (ws[tix(tile, nz, k, HEVI_NWS, fb + 3, lane)] + g3);
+        r = gx * (ws[tix(tile, nz, k, NWS, fb + 1, lane)] + g1) +
+            gy * (ws[tix(tile, nz, k, NWS, fb + 2, lane)] + g2) +
+            gzz * (ws[tix(tile, nz, k, NWS, fb + 3, lane)] + g3);
       }
       rn2 += r * r;
-      ws[tix(tile, nz, k, HEVI_NWS, WS_R, lane)] = r;
+      ws[tix(tile, nz, k, NWS, WS_R, lane)] = r;
     }
   }
   return rn2;
@@ -1118,13 +1118,13 @@ __device__ double reduced_rhs_pass(Gll<N> tab, const OpsView& op, int Ne, double
 // d_Th = b_Th + lambda DTh u, d_U = b_U + lambda (PG d_Th - Phi' grad(zeta) d_rho)
 // (interior), d_U = P(b_U) at the lid (P removes the normal component).
 // Writes d into fields fx.. or adds it to them (accumulate).
-template <int N, bool S3 = false>
+template <int N, bool S3 = false, int NWS = HEVI_NWS>
 __device__ void recover_pass(Gll<N> tab, const OpsView& op, int Ne, double* ws,
                              int64_t tile, int lane, double lambda, int fb, int fx,
                              bool accumulate) {
   const int nz = op.nz;
-  div_pass<N>(tab, op, Ne, ws, tile, lane, WS_U, WS_VR, WS_VT);
-  auto W = [&](int k, int f) -> double& { return ws[tix(tile, nz, k, HEVI_NWS, f, lane)]; };
+  div_pass<N, NWS>(tab, op, Ne, ws, tile, lane, WS_U, WS_VR, WS_VT);
+  auto W = [&](int k, int f) -> double& { return ws[tix(tile, nz, k, NWS, f, lane)]; };
   double c0 = 0.0, c1 = 0.0, c2 = 0.0;
   for (int e = 0; e < Ne; ++e) {
     double f0[N + 1], f1[N + 1], f2[N + 1];
@@ -1182,11 +1182,11 @@ __device__ void recover_pass(Gll<N> tab, const OpsView& op, int Ne, double* ws,
 // Full-system residual s = P(b) - A x = P(b) - x + lambda L_z x in FP64 for the
 // vectors b (fields fb..) and x (fields fx..); rigid-lid momentum rows of A are
 // identity rows, so there s_U = P(b_U) - x_U.  Writes fields fs..
-template <int N, bool S3 = false>
+template <int N, bool S3 = false, int NWS = HEVI_NWS>
 __device__ void residual_pass(Gll<N> tab, const OpsView& op, int Ne, double* ws,
                               int64_t tile, int lane, double lambda, int fb, int fx, int fs) {
   const int nz = op.nz;
-  auto W = [&](int k, int f) -> double& { return ws[tix(tile, nz, k, HEVI_NWS, f, lane)]; };
+  auto W = [&](int k, int f) -> double& { return ws[tix(tile, nz, k, NWS, f, lane)]; };
   double cr = 0.0, ct = 0.0, c0 = 0.0, c1 = 0.0, c2 = 0.0;
   for (int e = 0; e < Ne; ++e) {
     double Ju[N + 1], Jtu[N + 1], f0[N + 1], f1[N + 1], f2[N + 1];
@@ -1239,7 +1239,8 @@ __device__ void residual_pass(Gll<N> tab, const OpsView& op, int Ne, double* ws,
 }
 
 // Stage solve with full-system FP64 iterative refinement (accuracy mode,
-// hevi_refine.full_sweeps > 0), one lane per column, every field in scratch.
+// hevi_refine.full_sweeps > 0), one lane per column, every field in scratch: the
+// HEVI_NWS_FULL-field scratch of this mode (the other stage kernels use HEVI_NWS).
 template <int N, typename FT, bool S3 = false>
 __device__ __forceinline__ void b_stage_solve(int64_t tile_, HeviShapeDev sh, Gll<N> tab,
                                               double lambda, const double* __restrict__ ops,
@@ -1318,10 +1319,10 @@ __device__ __forceinline__ void b_stage_solve(int64_t tile_, HeviShapeDev sh, Gl
         const double g3 = lambda * (-mi * s2 - ph * gzz * b[a][0]);
         r = gx * (b[a][1] + g1) + gy * (b[a][2] + g2) + gzz * (b[a][3] + g3);
       }
-      ws[tix(tile, nz, k, HEVI_NWS, WS_R, lane)] = r;
+      ws[tix(tile, nz, k, HEVI_NWS_FULL, WS_R, lane)] = r;
       // keep q^ (offset-free) for the full-system residual; Q_i holds q^E
 #pragma unroll
-      for (int v = 0; v < 5; ++v) ws[tix(tile, nz, k, HEVI_NWS, WS_B + v, lane)] = b[a][v];
+      for (int v = 0; v < 5; ++v) ws[tix(tile, nz, k, HEVI_NWS_FULL, WS_B + v, lane)] = b[a][v];
       if (valid) {
 #pragma unroll
         for (int v = 0; v < 5; ++v) stn(Qi + cix(nz, nc, v, k, c), qE[a][v]);
@@ -1330,31 +1331,31 @@ __device__ __forceinline__ void b_stage_solve(int64_t tile_, HeviShapeDev sh, Gl
   }
 
   // ---- pass 2: S u = r (+ reduced FP64 refinement when the factors are FP32) ----
-  band_solve<N, FT>(Ub, Lb, piv, plane_size(sh), ws, tile, nz, lane, WS_R, WS_U);
+  band_solve<N, FT, false, HEVI_NWS_FULL>(Ub, Lb, piv, plane_size(sh), ws, tile, nz, lane, WS_R, WS_U);
   int sweeps = 0;
   double relres = 0.0;
   if (max_sweeps > 0)
-    reduced_refine<N, FT, S3>(tab, op, Ne, ws, tile, lane, valid, lambda, Ub, Lb, piv,
+    reduced_refine<N, FT, S3, HEVI_NWS_FULL>(tab, op, Ne, ws, tile, lane, valid, lambda, Ub, Lb, piv,
                               plane_size(sh), max_sweeps,
                               rel_target, &sweeps, &relres);
 
   {
     // ---- full-system FP64 iterative refinement on x = q_tt (offset-free) ----
-    recover_pass<N, S3>(tab, op, Ne, ws, tile, lane, lambda, WS_B, WS_X, false);
+    recover_pass<N, S3, HEVI_NWS_FULL>(tab, op, Ne, ws, tile, lane, lambda, WS_B, WS_X, false);
     for (int it = 0; it < full_sweeps; ++it) {
-      residual_pass<N, S3>(tab, op, Ne, ws, tile, lane, lambda, WS_B, WS_X, WS_S);
-      reduced_rhs_pass<N, S3>(tab, op, Ne, ws, tile, lane, lambda, WS_S);
-      band_solve<N, FT>(Ub, Lb, piv, plane_size(sh), ws, tile, nz, lane, WS_R, WS_U);
+      residual_pass<N, S3, HEVI_NWS_FULL>(tab, op, Ne, ws, tile, lane, lambda, WS_B, WS_X, WS_S);
+      reduced_rhs_pass<N, S3, HEVI_NWS_FULL>(tab, op, Ne, ws, tile, lane, lambda, WS_S);
+      band_solve<N, FT, false, HEVI_NWS_FULL>(Ub, Lb, piv, plane_size(sh), ws, tile, nz, lane, WS_R, WS_U);
       if (max_sweeps > 0) {
         // the correction only needs the accuracy of the outer sweep
         int sw = 0;
         double cr = 0.0;
-        reduced_refine<N, FT, S3>(tab, op, Ne, ws, tile, lane, valid, lambda, Ub, Lb, piv,
+        reduced_refine<N, FT, S3, HEVI_NWS_FULL>(tab, op, Ne, ws, tile, lane, valid, lambda, Ub, Lb, piv,
                                   plane_size(sh), 1,
                                   rel_target, &sw, &cr);
         sweeps += sw;
       }
-      recover_pass<N, S3>(tab, op, Ne, ws, tile, lane, lambda, WS_S, WS_X, true);
+      recover_pass<N, S3, HEVI_NWS_FULL>(tab, op, Ne, ws, tile, lane, lambda, WS_S, WS_X, true);
     }
     // Q_i = q_tt - sum_j c_j Q_j = q^E + x - q^
     if (valid) {
@@ -1362,8 +1363,8 @@ __device__ __forceinline__ void b_stage_solve(int64_t tile_, HeviShapeDev sh, Gl
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
           const size_t i = cix(nz, nc, v, k, c);
-          const double q = Qi[i] + ws[tix(tile, nz, k, HEVI_NWS, WS_X + v, lane)] -
-                           ws[tix(tile, nz, k, HEVI_NWS, WS_B + v, lane)];
+          const double q = Qi[i] + ws[tix(tile, nz, k, HEVI_NWS_FULL, WS_X + v, lane)] -
+                           ws[tix(tile, nz, k, HEVI_NWS_FULL, WS_B + v, lane)];
           Qi[i] = q;
           if (!isfinite(q)) nonfinite = true;
         }

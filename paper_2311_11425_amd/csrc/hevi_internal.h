@@ -8,7 +8,9 @@
 #define HEVI_MAXN 8       // highest supported polynomial order
 #define HEVI_TILE 64      // columns per wavefront: one lane per column
 #define HEVI_NOPS 8       // compact per-node operator fields
-#define HEVI_NWS 21       // per-node FP64 scratch fields of a stage solve
+#define HEVI_NWS 6        // per-node FP64 scratch fields of a stage solve (r, u, Drho u,
+                          // DTh u, residual, correction)
+#define HEVI_NWS_FULL 21  // ... of the full-system refinement mode (5-field b, x, s added)
 #define HEVI_MAXTERMS 16  // max vectors in a linear combination
 #define HEVI_MAXSTAGES 8  // max stages of an ARK tableau in a group step
 

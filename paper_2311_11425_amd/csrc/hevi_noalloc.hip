@@ -40,7 +40,8 @@ struct Layout {
   size_t info, U, L, piv, ws, sbuf, total;
 };
 
-Layout layout(const HeviShapeDev& sh, hevi_precision prec) {
+// full: the full-system refinement mode (its wider scratch)
+Layout layout(const HeviShapeDev& sh, hevi_precision prec, bool full) {
   const size_t tn = hevi_host::tiles_nodes(sh);
   const size_t fs = prec == HEVI_FP64 ? sizeof(double) : sizeof(float);
   Layout l{};
@@ -49,7 +50,7 @@ Layout layout(const HeviShapeDev& sh, hevi_precision prec) {
   l.U = o;    o += up256(tn * (4 * sh.N + 1) * fs);
   l.L = o;    o += up256(tn * 2 * sh.N * fs);
   l.piv = o;  o += up256(hevi_host::kFactorPlanes * tn);
-  l.ws = o;   o += up256(tn * HEVI_NWS * sizeof(double));
+  l.ws = o;   o += up256(tn * (full ? HEVI_NWS_FULL : HEVI_NWS) * sizeof(double));
   l.sbuf = o;
   if (hevi_host::needs_sbuf(sh, prec)) o += up256(tn * (4 * sh.N + 1) * sizeof(double));
   l.total = o;
@@ -105,7 +106,7 @@ hevi_status hevi_solve_noalloc(hevi_ctx* ctx, const hevi_ops* ops, double lambda
     full = refine->full_sweeps;
   }
   if (prec == HEVI_FP64) sweeps = 0;
-  const Layout l = layout(sh, prec);
+  const Layout l = layout(sh, prec, full > 0);
   if (l.total > (size_t)HEVI_NOALLOC_SCRATCH_BYTES) return HEVI_E_SCRATCH;
   unsigned char* base = scratch_of(ctx->device);
   if (!base) return HEVI_E_DEVICE;

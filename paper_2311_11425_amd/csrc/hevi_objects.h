@@ -36,7 +36,10 @@ struct hevi_factors {
   void* L;
   uint8_t* piv;
   double* sbuf;  // FP64 assembly buffer (aliases U for FP64 factors)
-  double* ws;    // per-node FP64 scratch of the stage solve
+  double* ws;    // per-node FP64 scratch of the stage solve (HEVI_NWS fields)
+  // scratch of the full-system refinement mode (HEVI_NWS_FULL fields), allocated by the
+  // first stage solve that asks for full sweeps
+  mutable double* wsf;
   HeviDevInfo* d_info;
   hipStream_t alloc_stream;  // buffers allocated stream-ordered on it (server), or 0
   bool stream_ordered;
