@@ -39,6 +39,35 @@ constexpr int kPsKL = 5 * (N + 1) - 1;
 template <int N>
 constexpr int kPsW = 2 * kPsKL<N> + 1;
 
+// Whole-wavefront lane shifts by DPP (wave_shl:1 / wave_shr:1, a VALU move): lane i
+// takes lane i+1's value (shift_down1; lane 63 takes 0) or lane i-1's (shift_up1; lane 0
+// takes 0).
+__device__ __forceinline__ double shift_down1(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x130, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x130, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double shift_up1(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x138, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x138, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+
+// Exchange of register a[0] with a[p], p uniform, as one branch to the matching case
+// (a chain of selects over every slot otherwise).
+template <int I, int KL>
+__device__ __forceinline__ void swap_first(double (&a)[KL + 1], int p) {
+  if constexpr (I <= KL) {
+    if (p == I) {
+      const double t = a[0];
+      a[0] = a[I];
+      a[I] = t;
+      return;
+    }
+    swap_first<I + 1, KL>(a, p);
+  }
+}
+
 __device__ __forceinline__ double bcast(double v, int src) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
@@ -196,6 +225,7 @@ __global__ __launch_bounds__(64) void k_ps_factor(HeviShapeDev sh, double lambda
   constexpr int KL = kPsKL<N>, W = kPsW<N>;
   static_assert(W <= 64, "one wavefront holds the window");
   __shared__ double Dsh[(N + 1) * (N + 1)], wsh[N + 1];
+  __shared__ double col0[T];         // the pivot column spread over the lanes
   extern __shared__ double nodes[];  // PN_FIELDS * n_z
   load_tables<N>(Dsh, wsh);
   const int lane = threadIdx.x;
@@ -219,37 +249,42 @@ __global__ __launch_bounds__(64) void k_ps_factor(HeviShapeDev sh, double lambda
   }
   bool singular = false;
   for (int j = 0; j < n; ++j) {
-    // pivot of column j (lane 0): largest magnitude among rows j..j+KL inside the matrix
+    // pivot of column j (lane 0's registers): largest magnitude among rows j..j+KL inside
+    // the matrix, the lowest row on ties.  The column goes across the lanes through LDS;
+    // a wave reduction finds the largest magnitude, a ballot the lowest lane holding it.
     const int rmax = min(KL, n - 1 - j);
-    double best = fabs(a[0]);
-    int p = 0;
+    if (lane == 0) {
 #pragma unroll
-    for (int i = 1; i <= KL; ++i) {
-      const double v = fabs(a[i]);
-      if (i <= rmax && v > best) { best = v; p = i; }
+      for (int i = 0; i <= KL; ++i) col0[i] = a[i];
     }
-    p = __builtin_amdgcn_readfirstlane(p);
-    if (p != 0) {
+    __syncthreads();
+    const double v = lane <= rmax ? fabs(col0[lane]) : -1.0;
+    double vm = v;
 #pragma unroll
-      for (int i = 1; i <= KL; ++i)
-        if (i == p) { const double t = a[0]; a[0] = a[i]; a[i] = t; }
-    }
+    for (int o = 16; o >= 1; o >>= 1) vm = fmax(vm, __shfl_xor(vm, o));  // lanes 0..31
+    vm = bcast(vm, 0);
+    const unsigned long long hit = __ballot(lane <= rmax && v == vm);
+    const int p = hit ? (int)__builtin_ctzll(hit) : 0;
+    __syncthreads();  // col0 is rewritten by the next step
+    if (p != 0) swap_first<1, KL>(a, p);
     const double pv = bcast(a[0], 0);
     if (pv == 0.0) singular = true;
     const double rp = pv != 0.0 ? 1.0 / pv : 0.0;
-    double Lv = 0.0;
+    if (lane < W) Ur[(size_t)j * W + lane] = a[0];
+    if (lane == 0) {
+      // the multipliers are lane 0's column below the pivot
+      pr[j] = (uint8_t)p;
+#pragma unroll
+      for (int i = 1; i <= KL; ++i) Lr[(size_t)j * KL + i - 1] = a[i] * rp;
+    }
 #pragma unroll
     for (int i = 1; i <= KL; ++i) {
       const double m = bcast(a[i], 0) * rp;
-      if (lane == i - 1) Lv = m;
       a[i] -= m * a[0];
     }
-    if (lane < W) Ur[(size_t)j * W + lane] = a[0];
-    if (lane < KL) Lr[(size_t)j * KL + lane] = Lv;
-    if (lane == 0) pr[j] = (uint8_t)p;
     // next window: rows j+1..j+1+KL, columns j+1..j+W (lanes >= W hold zeros)
 #pragma unroll
-    for (int i = 0; i < KL; ++i) a[i] = __shfl_down(a[i + 1], 1);
+    for (int i = 0; i < KL; ++i) a[i] = shift_down1(a[i + 1]);
     a[KL] = lane < W ? ps_entry<N>(P, Ne, Dsh, wsh, lambda, j + 1 + KL, j + 1 + lane) : 0.0;
     const int e = ps_scale_row(a[KL]);
     if (lane == 0 && j + 1 + KL < n) er[j + 1 + KL] = (int8_t)e;
@@ -346,7 +381,7 @@ __global__ __launch_bounds__(64) void k_ps_stage(HeviShapeDev sh, const double* 
       const double xj = bcast(y, 0);
       if (lrow) y -= lv * xj;
       if (lane == 0) xs[j] = xj;
-      y = __shfl_down(y, 1);
+      y = shift_down1(y);
       if (lane == KL) y = j + 1 + KL < n ? ldexp(xs[j + 1 + KL], -(int)el[j + 1 + KL]) : 0.0;
     }
   }
@@ -369,7 +404,7 @@ __global__ __launch_bounds__(64) void k_ps_stage(HeviShapeDev sh, const double* 
 #pragma unroll
       for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
       const double xj = (xs[j] - s) / bcast(uv, 0);
-      z = __shfl_up(z, 1);
+      z = shift_up1(z);
       if (lane == 1) z = xj;
       // every lane read xs[j] above; instructions of one wavefront reach LDS in order
       if (lane == 0) xs[j] = xj;
