@@ -365,7 +365,7 @@ def ps_leg(ctx, checks, ncols=86402, steps=20, warmup=3, refresh=5):
          "stage_solve_ms": float(np.mean(r["stage_ms"])), "factor_ms": fac,
          "apply_op_ms": float(np.mean(r["apply_ms"])),
          # U (2 kl + 1) and L (kl) FP64 entries per row, pivot and scale bytes
-         "factor_bytes_per_column": 5 * col["nz"] * ((3 * (5 * (col["N"] + 1) - 1) + 1) * 8 + 2)}
+         "factor_bytes_per_column": 5 * col["nz"] * ((3 * (5 * (col["N"] + 1) - 1) + 1) * 8 + 4)}
     queue_stage_errors(checks, d, "stage_rel_err_vs_oracle", st, col, qn, idx, BARS["fp64"])
     del st
     return d

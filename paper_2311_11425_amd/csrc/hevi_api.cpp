@@ -337,13 +337,14 @@ hevi_status hevi_host::factor_impl(hevi_ctx* ctx, const hevi_ops* ops, double la
   };
   hevi_status s;
   if (ops->ps) {
-    // LHEVI-PS: the full 5 n_z band in FP64, column-contiguous
+    // LHEVI-PS: the full 5 n_z band in FP64, column-contiguous, and four byte planes
+    // (pivot offsets, row exponents, U column extents, L step extents)
     if (prec != HEVI_FP64) { delete f; return HEVI_E_INVALID; }
     if (N > HEVI_PS_MAXN || sh.nz > kPsMaxNz) { delete f; return HEVI_E_SHAPE; }
     const size_t n = 5 * (size_t)sh.nz, nc = (size_t)sh.ncols;
     if ((s = alloc(&f->U, nc * n * hevi_ps_band_width(N) * sizeof(double))) ||
         (s = alloc(&f->L, nc * n * hevi_ps_lower_width(N) * sizeof(double))) ||
-        (s = alloc(&f->piv, 2 * nc * n)) || (s = alloc(&f->d_info, sizeof(HeviDevInfo)))) {
+        (s = alloc(&f->piv, 4 * nc * n)) || (s = alloc(&f->d_info, sizeof(HeviDevInfo)))) {
       hevi_factors_free(f);
       return s;
     }

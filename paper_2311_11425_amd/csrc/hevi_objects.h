@@ -89,8 +89,8 @@ hevi_status terms(int32_t n, const double* const* v, const double* coef, int lo,
 // byte planes beside the factors: pivot offsets, U row extents, row-scale exponents
 constexpr size_t kFactorPlanes = 3;
 // LHEVI-PS stage solves hold q^E, q^ and x of one column in LDS with its pivot offsets
-// and row exponents (26 n bytes of at most 64 KiB): n_z up to 504
-constexpr int kPsMaxNz = 504;
+// and U and L extents (27 n bytes of at most 64 KiB): n_z up to 485
+constexpr int kPsMaxNz = 485;
 // FP32 factors of orders without the fused assembly + LU need an FP64 assembly
 // buffer (FP64 factors assemble in place of U)
 inline bool needs_sbuf(const HeviShapeDev& sh, hevi_precision prec) {

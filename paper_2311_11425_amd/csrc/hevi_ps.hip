@@ -26,10 +26,13 @@
 // continuity, momentum and rho-theta rows), and unscaled pivoting on them lost a digit
 // at the ne = 30 shape; the solves scale the right-hand side the same way.
 //
-// Factor storage per column (column-contiguous, the paper's layout of the band):
-// U [n][W], L [n][KL] (multipliers of step j for rows j+1..j+KL), pivot offsets
-// [n] bytes, then (after all columns' offsets) the row exponents e [n] (signed bytes),
-// n = 5 n_z.  At N = 4, n_z = 41: 119,925 bytes per column.
+// Factor storage per column (column-contiguous): U by columns of the band, [n][W] with
+// entry (c, l) = U[c - l][c] (what the column-oriented back substitution reads, in order;
+// entries past the column's extent are not written); L [n][KL] (multipliers of step j
+// for rows j+1..j+KL); four byte planes, each [ncols][n]: the pivot offsets, the row
+// exponents e (signed), the extent of each U column (largest offset l of a nonzero
+// entry) and of each step's multipliers (largest i of a nonzero one), n = 5 n_z.  At
+// N = 4, n_z = 41: 120,540 bytes per column.
 #include "hevi_device.h"
 
 namespace {
@@ -216,8 +219,13 @@ __device__ __forceinline__ void load_tables(double* Dsh, double* wsh) {
   __syncthreads();
 }
 
+// Waves per SIMD of the factorisation: its window and multipliers take 80-112 registers
+// (N = 1..5); at N = 4 one register above the limit of 5 waves.
 template <int N>
-__global__ __launch_bounds__(64) void k_ps_factor(HeviShapeDev sh, double lambda,
+constexpr int kPsFactorWaves = N <= 2 ? 6 : N <= 4 ? 5 : 4;
+
+template <int N>
+__global__ __launch_bounds__(64, kPsFactorWaves<N>) void k_ps_factor(HeviShapeDev sh, double lambda,
                                                   const double* __restrict__ ops,
                                                   double* __restrict__ Ub,
                                                   double* __restrict__ Lb,
@@ -226,6 +234,7 @@ __global__ __launch_bounds__(64) void k_ps_factor(HeviShapeDev sh, double lambda
   static_assert(W <= 64, "one wavefront holds the window");
   __shared__ double Dsh[(N + 1) * (N + 1)], wsh[N + 1];
   __shared__ double col0[T];         // the pivot column spread over the lanes
+  __shared__ double ub[8 * W];       // the last 8 rows of U, before they are stored
   extern __shared__ double nodes[];  // PN_FIELDS * n_z
   load_tables<N>(Dsh, wsh);
   const int lane = threadIdx.x;
@@ -236,10 +245,13 @@ __global__ __launch_bounds__(64) void k_ps_factor(HeviShapeDev sh, double lambda
                       (int)(col % T)},
                 nodes);
   const PsNodes P{nodes, nz};
-  double* Ur = Ub + (size_t)col * n * W;
+  double* Uc = Ub + (size_t)col * n * W;
   double* Lr = Lb + (size_t)col * n * KL;
+  const size_t plane = (size_t)sh.ncols * n;
   uint8_t* pr = piv + (size_t)col * n;
-  int8_t* er = (int8_t*)piv + (size_t)sh.ncols * n + (size_t)col * n;
+  int8_t* er = (int8_t*)piv + plane + (size_t)col * n;
+  uint8_t* uxr = piv + 2 * plane + (size_t)col * n;
+  uint8_t* lxr = piv + 3 * plane + (size_t)col * n;
   double a[KL + 1];
 #pragma unroll
   for (int i = 0; i <= KL; ++i) {
@@ -247,6 +259,9 @@ __global__ __launch_bounds__(64) void k_ps_factor(HeviShapeDev sh, double lambda
     const int e = ps_scale_row(a[i]);
     if (lane == 0 && i < n) er[i] = (int8_t)e;
   }
+  // extent of the window column held by this lane: the offset from the diagonal of its
+  // first nonzero U entry, -1 until a row has one (set when that row leaves the window)
+  int xt = -1;
   bool singular = false;
   for (int j = 0; j < n; ++j) {
     // pivot of column j (lane 0's registers): largest magnitude among rows j..j+KL inside
@@ -265,15 +280,38 @@ __global__ __launch_bounds__(64) void k_ps_factor(HeviShapeDev sh, double lambda
     vm = bcast(vm, 0);
     const unsigned long long hit = __ballot(lane <= rmax && v == vm);
     const int p = hit ? (int)__builtin_ctzll(hit) : 0;
+    // the nonzero rows of the column after the exchange; the highest one below the pivot
+    // is the extent of the step's multipliers
+    unsigned long long nzm = __ballot(lane <= rmax && v != 0.0);
+    if (p != 0) {
+      const unsigned long long b0 = nzm & 1ull, bp = (nzm >> p) & 1ull;
+      nzm = (nzm & ~(1ull | (1ull << p))) | bp | (b0 << p);
+    }
+    nzm &= ~1ull;
+    const int lx = nzm ? 63 - __builtin_clzll(nzm) : 0;
     __syncthreads();  // col0 is rewritten by the next step
     if (p != 0) swap_first<1, KL>(a, p);
+    if (xt < 0 && a[0] != 0.0) xt = lane;
     const double pv = bcast(a[0], 0);
     if (pv == 0.0) singular = true;
     const double rp = pv != 0.0 ? 1.0 / pv : 0.0;
-    if (lane < W) Ur[(size_t)j * W + lane] = a[0];
+    // U row j into the column-band layout (entry (j, j+l) at column j+l, offset l), through
+    // LDS: rows are staged for 8 steps, then written as runs of up to 8 consecutive entries
+    // per column (row-by-row stores into that layout would touch W separate cache lines per
+    // step with 8 bytes each)
+    if (lane < W) ub[(j & 7) * W + lane] = a[0];
+    if ((j & 7) == 7 || j == n - 1) {
+      const int r0 = j & ~7, nr = j - r0 + 1;
+      for (int t = lane; t < (W + 7) * 8; t += T) {
+        const int cc = t >> 3, k = t & 7, o = cc - k, c = r0 + cc;
+        if (k < nr && o >= 0 && o < W && c < n) Uc[(size_t)c * W + o] = ub[k * W + o];
+      }
+    }
     if (lane == 0) {
       // the multipliers are lane 0's column below the pivot
       pr[j] = (uint8_t)p;
+      lxr[j] = (uint8_t)lx;
+      uxr[j] = (uint8_t)max(xt, 0);
 #pragma unroll
       for (int i = 1; i <= KL; ++i) Lr[(size_t)j * KL + i - 1] = a[i] * rp;
     }
@@ -285,6 +323,8 @@ __global__ __launch_bounds__(64) void k_ps_factor(HeviShapeDev sh, double lambda
     // next window: rows j+1..j+1+KL, columns j+1..j+W (lanes >= W hold zeros)
 #pragma unroll
     for (int i = 0; i < KL; ++i) a[i] = shift_down1(a[i + 1]);
+    xt = __builtin_amdgcn_mov_dpp(xt, 0x130, 0xF, 0xF, true);
+    if (lane == W - 1) xt = -1;
     a[KL] = lane < W ? ps_entry<N>(P, Ne, Dsh, wsh, lambda, j + 1 + KL, j + 1 + lane) : 0.0;
     const int e = ps_scale_row(a[KL]);
     if (lane == 0 && j + 1 + KL < n) er[j + 1 + KL] = (int8_t)e;
@@ -295,11 +335,21 @@ __global__ __launch_bounds__(64) void k_ps_factor(HeviShapeDev sh, double lambda
 // One stage solve: q^E = sum e_t E_t, q^ = q^E + sum c_j Q_j, A x = P(q^) with the
 // band factors (P the rigid-lid projection of the momentum at the bottom and top
 // nodes), Q_i = q^E + (x - q^) (= x - sum c_j Q_j, Sec. 4.3 eq. lhevi-ark-final-3).
-// Dynamic LDS: 3 n doubles (q^, q^E, and P(q^) overwritten by the solution) and the
-// column's pivot offsets and row exponents (2 n bytes).  The factor rows are read
-// kPsRing steps ahead into register rings, so each step's loads are in flight long
-// before the dependent chain of the substitution reaches them.
+// Dynamic LDS: 3 n doubles (q^, q^E, and P(q^) overwritten by the solution) and 3 n bytes
+// (pivot offsets, U and L extents).  The factor
+// rows are read kPsRing steps ahead into register rings, so each step's loads are in
+// flight long before the dependent chain of the substitution reaches them, and only up
+// to the extents the factorisation recorded: the loads are buffer loads whose lanes past
+// the extent take an offset outside the buffer, which returns zero without a memory
+// access (at ne = 30, 38% of the stored U entries and 56% of L's are nonzero).
 constexpr int kPsRing = 8;
+
+typedef unsigned int PsU2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double ps_bload(__amdgpu_buffer_rsrc_t rs, unsigned off) {
+  const PsU2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
+  return __hiloint2double((int)v.y, (int)v.x);
+}
+constexpr unsigned kPsOff = 0x80000000u;  // beyond any buffer of these kernels
 
 template <int N>
 __global__ __launch_bounds__(64) void k_ps_stage(HeviShapeDev sh, const double* __restrict__ ops,
@@ -318,14 +368,20 @@ __global__ __launch_bounds__(64) void k_ps_stage(HeviShapeDev sh, const double* 
   double* qh = sm;
   double* qe = sm + n;
   double* xs = sm + 2 * n;
-  uint8_t* pl = (uint8_t*)(sm + 3 * n);  // pivot offsets
-  int8_t* el = (int8_t*)(pl + n);        // row exponents
+  // byte planes of the factorisation: pivot offsets, row exponents, U column extents and
+  // L step extents; all but the exponents are copied to LDS (global loads between the
+  // ring loads would make the compiler wait for the whole ring)
+  uint8_t* pr = (uint8_t*)(sm + 3 * n);
+  uint8_t* uxr = pr + n;
+  uint8_t* lxr = uxr + n;
+  const size_t plane = (size_t)nc * n;
+  const int8_t* er = (const int8_t*)piv + plane + (size_t)col * n;
   {
-    const uint8_t* pr = piv + (size_t)col * n;
-    const int8_t* er = (const int8_t*)piv + (size_t)sh.ncols * n + (size_t)col * n;
+    const uint8_t* pg = piv + (size_t)col * n;
     for (int r = lane; r < n; r += T) {
-      pl[r] = pr[r];
-      el[r] = er[r];
+      pr[r] = pg[r];
+      uxr[r] = pg[2 * plane + r];
+      lxr[r] = pg[3 * plane + r];
     }
   }
   for (int r = lane; r < n; r += T) {
@@ -354,61 +410,121 @@ __global__ __launch_bounds__(64) void k_ps_stage(HeviShapeDev sh, const double* 
     b[1] -= n0 * d; b[2] -= n1 * d; b[3] -= n2 * d;
   }
   __syncthreads();
-  const double* Ur = Ub + (size_t)col * n * W;
-  const double* Lr = Lb + (size_t)col * n * KL;
+  // the right-hand side in the scale of the equilibrated rows
+  for (int r = lane; r < n; r += T) xs[r] = ldexp(xs[r], -(int)er[r]);
+  __syncthreads();
   constexpr int D = kPsRing;
-  // forward: the row scales, the row exchanges and L; lane i holds y[j + i], i = 0..KL
-  // (xs[j] is overwritten at step j, after its last read as an entering row)
+  const __amdgpu_buffer_rsrc_t lrs = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(Lb + (size_t)col * n * KL), (short)0, n * KL * (int)sizeof(double), 0x00020000);
+  const __amdgpu_buffer_rsrc_t urs = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(Ub + (size_t)col * n * W), (short)0, n * W * (int)sizeof(double), 0x00020000);
+  // Forward: the row exchanges and L, y[j + i] in lane i (i = 0..KL).  Each block of 64
+  // steps takes its pivot offsets, the extents of the rows its ring loads fetch and the
+  // entering values y[j + 1 + KL] from lane-spread registers (read from LDS once per
+  // block), and collects its results y[j] the same way, so no step waits on LDS.  The ring
+  // loads are unconditional (a guarded load becomes a branch, across which the compiler
+  // waits for every outstanding load, the one just issued included); rows past the last
+  // step have extent 0, so all their lanes read zero.
   const bool lrow = lane >= 1 && lane <= KL;
+  auto loff = [&](int j, int x) -> unsigned {
+    return lane >= 1 && lane <= x ? (unsigned)((j * KL + lane - 1) * (int)sizeof(double)) : kPsOff;
+  };
   double lr[D];
 #pragma unroll
-  for (int d = 0; d < D; ++d) lr[d] = (lrow && d < n) ? Lr[(size_t)d * KL + lane - 1] : 0.0;
-  double y = (lane <= KL && lane < n) ? ldexp(xs[lane], -(int)el[lane]) : 0.0;
-  for (int j0 = 0; j0 < n; j0 += D) {
+  for (int d = 0; d < D; ++d) lr[d] = ps_bload(lrs, loff(d, d < n ? (int)lxr[d] : 0));
+  double y = (lane <= KL && lane < n) ? xs[lane] : 0.0;
+  for (int j0 = 0; j0 < n; j0 += T) {
+    const int pb = j0 + lane < n ? (int)pr[j0 + lane] : 0;
+    const int lx = j0 + lane + D < n ? (int)lxr[j0 + lane + D] : 0;
+    const int je = j0 + lane + KL + 1;
+    const double eb = je < n ? xs[je] : 0.0;
+    double ob = 0.0;
+    const int nb = min(T, n - j0);
+    // whole groups of D steps (a conditional step would again make the compiler wait for
+    // every outstanding load): past the last row every y is zero (no exchange, zero
+    // entering values, no multipliers), so the extra steps have x_j = 0, change nothing,
+    // and their results are not stored
+    for (int d0 = 0; d0 < nb; d0 += D) {
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-      const int j = j0 + d;
-      if (j >= n) break;
-      const double lv = lr[d];
-      const int jn = j + D;
-      lr[d] = (lrow && jn < n) ? Lr[(size_t)jn * KL + lane - 1] : 0.0;
-      const int p = __builtin_amdgcn_readfirstlane((int)pl[j]);
-      if (p != 0) {
-        const double yp = bcast(y, p), y0 = bcast(y, 0);
-        if (lane == 0) y = yp;
-        if (lane == p) y = y0;
+      for (int e = 0; e < D; ++e) {
+        const int d = d0 + e;
+        const int j = j0 + d;
+        const int p = __builtin_amdgcn_readlane(pb, d);
+        if (p != 0) {
+          const double yp = bcast(y, p), y0 = bcast(y, 0);
+          if (lane == 0) y = yp;
+          if (lane == p) y = y0;
+        }
+        const double xj = bcast(y, 0);
+        if (lrow) y -= lr[e] * xj;
+        // the slot's next row, loaded into the register just used (a load into another
+        // register followed by a copy would wait for it here)
+        lr[e] = ps_bload(lrs, loff(j + D, __builtin_amdgcn_readlane(lx, d)));
+        if (lane == d) ob = xj;
+        y = shift_down1(y);
+        const double ent = bcast(eb, d);
+        y = lane == KL ? ent : y;
       }
-      const double xj = bcast(y, 0);
-      if (lrow) y -= lv * xj;
-      if (lane == 0) xs[j] = xj;
-      y = shift_down1(y);
-      if (lane == KL) y = j + 1 + KL < n ? ldexp(xs[j + 1 + KL], -(int)el[j + 1 + KL]) : 0.0;
     }
+    // entries j0..j0+63 of xs are no longer read (the entering values are read up to a block
+    // ahead); a wavefront's LDS accesses complete in order
+    if (lane < nb) xs[j0 + lane] = ob;
   }
   __syncthreads();
-  // backward: U x = y; lane l (1..W-1) holds x[j + l]
-  const bool urow = lane < W;
+  // Backward, column-oriented: lane l holds the partial sum of row j - l (l = 0..W-1);
+  // step j: x_j = r_j / U_jj, then r[j - l] -= U[j - l][j] x_j, one FMA per lane, and the
+  // rows shift one lane down with row j - W entering at lane W-1.  Column j of U is one
+  // contiguous W-vector of the column-band layout, read up to its extent (lanes past it,
+  // lanes l > j among them, read zero).  Lanes >= W read zero and their sums are replaced
+  // by the entering row (lane W-1 takes lane W's) before any use.  The extra steps below
+  // the first row read nothing (extent -1) and are not stored.
+  auto uoff = [&](int j, int x) -> unsigned {
+    return lane <= x ? (unsigned)((j * W + lane) * (int)sizeof(double)) : kPsOff;
+  };
   double ur[D];
 #pragma unroll
-  for (int d = 0; d < D; ++d) ur[d] = (urow && n - 1 - d >= 0) ? Ur[(size_t)(n - 1 - d) * W + lane] : 0.0;
-  double z = 0.0;
-  for (int j0 = n - 1; j0 >= 0; j0 -= D) {
+  for (int d = 0; d < D; ++d) {
+    const int jn = n - 1 - d;
+    ur[d] = ps_bload(urs, uoff(jn, jn >= 0 ? (int)uxr[jn] : -1));
+  }
+  double r = (lane < W && n - 1 - lane >= 0) ? xs[n - 1 - lane] : 0.0;
+  double un = bcast(ur[0], 0);
+  double rn = 1.0 / un;
+  for (int jt = n - 1; jt >= 0; jt -= T) {
+    const int ju = jt - D - lane;
+    const int ux = ju >= 0 ? (int)uxr[ju] : -1;
+    const int jr = jt - W - lane;
+    const double eb = jr >= 0 ? xs[jr] : 0.0;
+    double ob = 0.0;
+    const int nb = min(T, jt + 1);
+    for (int d0 = 0; d0 < nb; d0 += D) {
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-      const int j = j0 - d;
-      if (j < 0) break;
-      const double uv = ur[d];
-      const int jn = j - D;
-      ur[d] = (urow && jn >= 0) ? Ur[(size_t)jn * W + lane] : 0.0;
-      double s = (lane >= 1 && urow) ? uv * z : 0.0;
-#pragma unroll
-      for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
-      const double xj = (xs[j] - s) / bcast(uv, 0);
-      z = shift_up1(z);
-      if (lane == 1) z = xj;
-      // every lane read xs[j] above; instructions of one wavefront reach LDS in order
-      if (lane == 0) xs[j] = xj;
+      for (int e = 0; e < D; ++e) {
+        const int d = d0 + e;
+        const int j = jt - d;
+        // x_j = r_j / U_jj correctly rounded, with only a product and two FMAs on the chain
+        // through r: the reciprocal of U_jj is computed a step ahead, off the chain, and
+        // one residual correction of the product gives the rounded quotient (Markstein's
+        // final step of division with a fused multiply-add)
+        const double u = un, ri = rn;
+        const double r0 = bcast(r, 0);
+        double xj = r0 * ri;
+        xj = fma(fma(-xj, u, r0), ri, xj);
+        r = fma(-ur[e], xj, r);
+        ur[e] = ps_bload(urs, uoff(j - D, __builtin_amdgcn_readlane(ux, d)));
+        un = bcast(ur[(e + 1) % D], 0);  // the next step's U_jj, loaded D - 1 steps ago
+        rn = 1.0 / un;
+        if (lane == d) ob = xj;
+        r = shift_down1(r);
+        const double ent = bcast(eb, d);
+        r = lane == W - 1 ? ent : r;
+        // keep each step's ring load in its step (the scheduler would otherwise gather the
+        // group's loads at its end and shorten the prefetch distance)
+        __builtin_amdgcn_sched_barrier(0);
+      }
     }
+    // xs[jt - 63 .. jt]: read for the last time as entering values a block earlier
+    if (lane < nb) xs[jt - lane] = ob;
   }
   __syncthreads();
   bool nonfinite = false;
@@ -601,7 +717,7 @@ struct PsStage {
                         const HeviTerms& Q, double* Qi, HeviDevInfo* info, hipStream_t st) {
     const size_t n = 5 * (size_t)sh.nz;
     hipLaunchKernelGGL(k_ps_stage<N>, dim3(ps_grid(sh.ncols)), dim3(T),
-                       3 * n * sizeof(double) + 2 * n, st, sh, ops, U, L, piv, E, Q, Qi, info);
+                       3 * n * sizeof(double) + 3 * n, st, sh, ops, U, L, piv, E, Q, Qi, info);
     return hipGetLastError();
   }
 };
