@@ -77,6 +77,28 @@ __device__ __forceinline__ double bcast(double v, int src) {
   return __hiloint2double(hi, lo);
 }
 
+// DPP move of a double within the wavefront (lanes whose source is invalid keep their own
+// value), and the maximum over all 64 lanes by an inclusive scan: row_shr:1,2,4,8 leave
+// each 16-lane row's maximum in its lane 15, row_bcast:15 and row_bcast:31 carry it into
+// the following rows, so lane 63 ends with the maximum of the wavefront.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(v), __double2loint(v), CTRL, ROWS,
+                                             0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(v), __double2hiint(v), CTRL, ROWS,
+                                             0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wave_max(double v) {
+  v = fmax(v, dpp_d<0x111, 0xF>(v));
+  v = fmax(v, dpp_d<0x112, 0xF>(v));
+  v = fmax(v, dpp_d<0x114, 0xF>(v));
+  v = fmax(v, dpp_d<0x118, 0xF>(v));
+  v = fmax(v, dpp_d<0x142, 0xA>(v));
+  v = fmax(v, dpp_d<0x143, 0xC>(v));
+  return bcast(v, 63);
+}
+
 // The operator of one column as the PS kernels read it (lane-dependent nodes).
 struct PsCol {
   const double* ops;
@@ -196,9 +218,7 @@ __host__ __forceinline__ unsigned ps_grid(int64_t ncols) {
 // Scales the row held across the lanes (one entry per lane) by 2^-e, e the binary
 // exponent of its largest magnitude (clamped to a signed byte), and returns e.
 __device__ __forceinline__ int ps_scale_row(double& v) {
-  double m = fabs(v);
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  const double m = wave_max(fabs(v));
   int e = 0;
   if (m > 0.0 && isfinite(m)) {
     frexp(m, &e);
@@ -222,7 +242,7 @@ __device__ __forceinline__ void load_tables(double* Dsh, double* wsh) {
 // Waves per SIMD of the factorisation: its window and multipliers take 80-112 registers
 // (N = 1..5); at N = 4 one register above the limit of 5 waves.
 template <int N>
-constexpr int kPsFactorWaves = N <= 2 ? 6 : N <= 4 ? 5 : 4;
+constexpr int kPsFactorWaves = N <= 2 ? 6 : N <= 4 ? 5 : 3;
 
 template <int N>
 __global__ __launch_bounds__(64, kPsFactorWaves<N>) void k_ps_factor(HeviShapeDev sh, double lambda,
@@ -234,6 +254,7 @@ __global__ __launch_bounds__(64, kPsFactorWaves<N>) void k_ps_factor(HeviShapeDe
   static_assert(W <= 64, "one wavefront holds the window");
   __shared__ double Dsh[(N + 1) * (N + 1)], wsh[N + 1];
   __shared__ double col0[T];         // the pivot column spread over the lanes
+  __shared__ double mb[T];           // the step's multipliers, for their broadcast
   __shared__ double ub[8 * W];       // the last 8 rows of U, before they are stored
   extern __shared__ double nodes[];  // PN_FIELDS * n_z
   load_tables<N>(Dsh, wsh);
@@ -273,11 +294,9 @@ __global__ __launch_bounds__(64, kPsFactorWaves<N>) void k_ps_factor(HeviShapeDe
       for (int i = 0; i <= KL; ++i) col0[i] = a[i];
     }
     __syncthreads();
-    const double v = lane <= rmax ? fabs(col0[lane]) : -1.0;
-    double vm = v;
-#pragma unroll
-    for (int o = 16; o >= 1; o >>= 1) vm = fmax(vm, __shfl_xor(vm, o));  // lanes 0..31
-    vm = bcast(vm, 0);
+    const double cl = lane <= KL ? col0[lane] : 0.0;
+    const double v = lane <= rmax ? fabs(cl) : -1.0;
+    const double vm = wave_max(v);
     const unsigned long long hit = __ballot(lane <= rmax && v == vm);
     const int p = hit ? (int)__builtin_ctzll(hit) : 0;
     // the nonzero rows of the column after the exchange; the highest one below the pivot
@@ -292,9 +311,17 @@ __global__ __launch_bounds__(64, kPsFactorWaves<N>) void k_ps_factor(HeviShapeDe
     __syncthreads();  // col0 is rewritten by the next step
     if (p != 0) swap_first<1, KL>(a, p);
     if (xt < 0 && a[0] != 0.0) xt = lane;
-    const double pv = bcast(a[0], 0);
+    // the pivot column after the exchange, entry i in lane i, and its multipliers: stored
+    // by lanes 1..KL in one coalesced store and broadcast through LDS
+    const double c0 = bcast(cl, 0), pv = bcast(cl, p);
+    const double cs = lane == 0 ? pv : (lane == p ? c0 : cl);
     if (pv == 0.0) singular = true;
     const double rp = pv != 0.0 ? 1.0 / pv : 0.0;
+    const double mv = cs * rp;
+    if (lane >= 1 && lane <= KL) {
+      mb[lane] = mv;
+      Lr[(size_t)j * KL + lane - 1] = mv;
+    }
     // U row j into the column-band layout (entry (j, j+l) at column j+l, offset l), through
     // LDS: rows are staged for 8 steps, then written as runs of up to 8 consecutive entries
     // per column (row-by-row stores into that layout would touch W separate cache lines per
@@ -308,18 +335,14 @@ __global__ __launch_bounds__(64, kPsFactorWaves<N>) void k_ps_factor(HeviShapeDe
       }
     }
     if (lane == 0) {
-      // the multipliers are lane 0's column below the pivot
       pr[j] = (uint8_t)p;
       lxr[j] = (uint8_t)lx;
       uxr[j] = (uint8_t)max(xt, 0);
-#pragma unroll
-      for (int i = 1; i <= KL; ++i) Lr[(size_t)j * KL + i - 1] = a[i] * rp;
     }
+    __syncthreads();
 #pragma unroll
-    for (int i = 1; i <= KL; ++i) {
-      const double m = bcast(a[i], 0) * rp;
-      a[i] -= m * a[0];
-    }
+    for (int i = 1; i <= KL; ++i) a[i] = fma(-mb[i], a[0], a[i]);
+    __syncthreads();  // mb is rewritten by the next step
     // next window: rows j+1..j+1+KL, columns j+1..j+W (lanes >= W hold zeros)
 #pragma unroll
     for (int i = 0; i < KL; ++i) a[i] = shift_down1(a[i + 1]);
