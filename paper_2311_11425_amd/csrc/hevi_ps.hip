@@ -200,6 +200,63 @@ __device__ double ps_entry(const PsNodes& P, int Ne, const double* Dsh, const do
   return delta - lambda * L;
 }
 
+// The five rows of node k (variables a = 0..4) of A at the columns c0 + lane, as
+// ps_entry gives them, with the lane's node lookups and element coefficients shared by
+// the five rows.
+template <int N>
+__device__ void ps_node_rows(const PsNodes& P, int Ne, const double* Dsh, const double* wsh,
+                             double lambda, int k, int c0, double (&row)[5]) {
+  const int nz = P.nz, n = 5 * nz;
+  const int c = c0 + (int)threadIdx.x;
+  const int kc = c / 5, b = c - 5 * kc, dk = kc - k;
+  const bool band = c < n && dk <= N && dk >= -N;
+  const int kq = band ? kc : k;  // an in-range node for the loads
+  const double J = P.f(PN_J, kq), w = P.f(PN_W, kq);
+  const double g[3] = {P.f(PN_G, kq), P.f(PN_G + 1, kq), P.f(PN_G + 2, kq)};
+  const double u[3] = {P.f(PN_U, kq), P.f(PN_U + 1, kq), P.f(PN_U + 2, kq)};
+  const double jct = P.f(PN_JCT, kq), jth = P.f(PN_JTH, kq);
+  const double gb = b == 1 ? g[0] : b == 2 ? g[1] : b == 3 ? g[2] : 0.0;
+  // per element side: the strong (rows a >= 1) and weak (row a = 0) coefficients
+  double cs[2], cw[2];
+  bool on[2];
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const int e = side == 0 ? ((k % N == 0) ? k / N - 1 : -1) : k / N;
+    const int i = k - e * N, jj = kc - e * N;
+    on[side] = band && e >= 0 && e < Ne && jj >= 0 && jj <= N;
+    const int ic = min(max(i, 0), N), jc = min(max(jj, 0), N);
+    cs[side] = wsh[ic] * Dsh[ic * (N + 1) + jc];
+    cw[side] = -wsh[jc] * Dsh[jc * (N + 1) + ic];
+  }
+  const double minv = P.f(PN_MINV, k), phi = P.f(PN_PHI, k);
+#pragma unroll
+  for (int a = 0; a < 5; ++a) {
+    const int r = 5 * k + a;
+    const double delta = r == c ? 1.0 : 0.0;
+    double JK;
+    if (a == 0) {
+      JK = J * gb;
+    } else if (a <= 3) {
+      const double ul = u[a - 1];
+      JK = b == 0 ? -J * ul * w
+                  : b <= 3 ? J * ((a == b ? w : 0.0) + ul * gb) : g[a - 1] * jct;
+    } else {
+      JK = b == 0 ? -jth * w : b <= 3 ? jth * gb : J * w;
+    }
+    double Bs = 0.0;
+#pragma unroll
+    for (int side = 0; side < 2; ++side)
+      if (on[side]) Bs += (a == 0 ? cw[side] : cs[side]) * JK;
+    double L = -minv * Bs;
+    if (a >= 1 && a <= 3 && kc == k && b == 0) L -= phi * P.f(PN_G + a - 1, k);
+    double v;
+    if (r >= n || c >= n) v = 0.0;
+    else if ((a >= 1 && a <= 3 && (k == 0 || k == nz - 1)) || !band) v = delta;  // rigid lid
+    else v = delta - lambda * L;
+    row[a] = v;
+  }
+}
+
 // Workgroups are dealt to the 8 XCDs round-robin (workgroup b runs on XCD b mod 8),
 // and each XCD has its own L2.  A wavefront reads its column's entries of the
 // column-fastest caller vectors and of the tile-interleaved operator, 8 bytes of
@@ -239,10 +296,10 @@ __device__ __forceinline__ void load_tables(double* Dsh, double* wsh) {
   __syncthreads();
 }
 
-// Waves per SIMD of the factorisation: its window and multipliers take 80-112 registers
-// (N = 1..5); at N = 4 one register above the limit of 5 waves.
+// Waves per SIMD of the factorisation (its window, multipliers and the entering node's
+// rows take 96-134 registers for N = 1..5; at N = 4 the limit of 5 waves spills).
 template <int N>
-constexpr int kPsFactorWaves = N <= 2 ? 6 : N <= 4 ? 5 : 3;
+constexpr int kPsFactorWaves = N <= 3 ? 5 : N == 4 ? 4 : 3;
 
 template <int N>
 __global__ __launch_bounds__(64, kPsFactorWaves<N>) void k_ps_factor(HeviShapeDev sh, double lambda,
@@ -283,6 +340,7 @@ __global__ __launch_bounds__(64, kPsFactorWaves<N>) void k_ps_factor(HeviShapeDe
   // extent of the window column held by this lane: the offset from the diagonal of its
   // first nonzero U entry, -1 until a row has one (set when that row leaves the window)
   int xt = -1;
+  double nr[5];  // rows of the node whose rows are entering the window
   bool singular = false;
   for (int j = 0; j < n; ++j) {
     // pivot of column j (lane 0's registers): largest magnitude among rows j..j+KL inside
@@ -348,7 +406,15 @@ __global__ __launch_bounds__(64, kPsFactorWaves<N>) void k_ps_factor(HeviShapeDe
     for (int i = 0; i < KL; ++i) a[i] = shift_down1(a[i + 1]);
     xt = __builtin_amdgcn_mov_dpp(xt, 0x130, 0xF, 0xF, true);
     if (lane == W - 1) xt = -1;
-    a[KL] = lane < W ? ps_entry<N>(P, Ne, Dsh, wsh, lambda, j + 1 + KL, j + 1 + lane) : 0.0;
+    // the entering row j+1+KL = 5 m + (j mod 5): the node's five rows are computed when its
+    // first one enters (at columns j+1+lane) and the later ones shift with the window
+    if (j % 5 == 0) {
+      ps_node_rows<N>(P, Ne, Dsh, wsh, lambda, (j + 1 + KL) / 5, j + 1, nr);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) nr[q] = shift_down1(nr[q + 1]);
+    }
+    a[KL] = lane < W ? nr[0] : 0.0;
     const int e = ps_scale_row(a[KL]);
     if (lane == 0 && j + 1 + KL < n) er[j + 1 + KL] = (int8_t)e;
   }
