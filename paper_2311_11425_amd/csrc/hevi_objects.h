@@ -88,9 +88,10 @@ hevi_status terms(int32_t n, const double* const* v, const double* coef, int lo,
                   HeviTerms* t);
 // byte planes beside the factors: pivot offsets, U row extents, row-scale exponents
 constexpr size_t kFactorPlanes = 3;
-// LHEVI-PS stage solves hold q^E, q^ and x of one column in LDS with its pivot offsets
-// and U and L extents (27 n bytes of at most 64 KiB): n_z up to 485
-constexpr int kPsMaxNz = 485;
+// LHEVI-PS kernels hold one column in LDS, at most 64 KiB: the factorisation 12 operator
+// fields (96 n_z bytes) and ~5 KiB of tables and staging, the stage solve two vectors and
+// three byte planes (19 n = 95 n_z bytes): n_z up to 600
+constexpr int kPsMaxNz = 600;
 // FP32 factors of orders without the fused assembly + LU need an FP64 assembly
 // buffer (FP64 factors assemble in place of U)
 inline bool needs_sbuf(const HeviShapeDev& sh, hevi_precision prec) {

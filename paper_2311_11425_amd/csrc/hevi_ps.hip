@@ -423,8 +423,8 @@ __global__ __launch_bounds__(64, kPsFactorWaves<N>) void k_ps_factor(HeviShapeDe
 
 // One stage solve: q^E = sum e_t E_t, q^ = q^E + sum c_j Q_j, A x = P(q^) with the
 // band factors (P the rigid-lid projection of the momentum at the bottom and top
-// nodes), Q_i = q^E + (x - q^) (= x - sum c_j Q_j, Sec. 4.3 eq. lhevi-ark-final-3).
-// Dynamic LDS: 3 n doubles (q^, q^E, and P(q^) overwritten by the solution) and 3 n bytes
+// nodes), Q_i = x + (q^E - q^) (= x - sum c_j Q_j, Sec. 4.3 eq. lhevi-ark-final-3).
+// Dynamic LDS: 2 n doubles (q^E - q^, and P(q^) overwritten by the solution) and 3 n bytes
 // (pivot offsets, U and L extents).  The factor
 // rows are read kPsRing steps ahead into register rings, so each step's loads are in
 // flight long before the dependent chain of the substitution reaches them, and only up
@@ -440,6 +440,17 @@ __device__ __forceinline__ double ps_bload(__amdgpu_buffer_rsrc_t rs, unsigned o
 }
 constexpr unsigned kPsOff = 0x80000000u;  // beyond any buffer of these kernels
 
+// 1/u from the hardware estimate and two Newton steps y <- y + y (1 - u y) (each
+// doubles the correct bits), within an ulp of the rounded reciprocal for normal u; the
+// quotient correction that follows does not need it rounded.  A zero u (a singular
+// factor, flagged by the factorisation) gives a non-finite result.
+__device__ __forceinline__ double ps_recip(double u) {
+  double y = __builtin_amdgcn_rcp(u);
+  y = fma(y, fma(-u, y, 1.0), y);
+  y = fma(y, fma(-u, y, 1.0), y);
+  return y;
+}
+
 template <int N>
 __global__ __launch_bounds__(64) void k_ps_stage(HeviShapeDev sh, const double* __restrict__ ops,
                                                  const double* __restrict__ Ub,
@@ -454,13 +465,12 @@ __global__ __launch_bounds__(64) void k_ps_stage(HeviShapeDev sh, const double* 
   if (col >= sh.ncols) return;
   const int nz = sh.nz, n = 5 * nz;
   const int64_t nc = sh.ncols;
-  double* qh = sm;
-  double* qe = sm + n;
-  double* xs = sm + 2 * n;
+  double* qd = sm;      // q^E - q^
+  double* xs = sm + n;  // P(q^), then the solution
   // byte planes of the factorisation: pivot offsets, row exponents, U column extents and
   // L step extents; all but the exponents are copied to LDS (global loads between the
   // ring loads would make the compiler wait for the whole ring)
-  uint8_t* pr = (uint8_t*)(sm + 3 * n);
+  uint8_t* pr = (uint8_t*)(sm + 2 * n);
   uint8_t* uxr = pr + n;
   uint8_t* lxr = uxr + n;
   const size_t plane = (size_t)nc * n;
@@ -480,8 +490,7 @@ __global__ __launch_bounds__(64) void k_ps_stage(HeviShapeDev sh, const double* 
     for (int t = 0; t < E.n; ++t) e += E.coef[t] * E.v[t][ix];
     double h = e;
     for (int t = 0; t < Q.n; ++t) h += Q.coef[t] * Q.v[t][ix];
-    qe[r] = e;
-    qh[r] = h;
+    qd[r] = e - h;
     xs[r] = h;
   }
   __syncthreads();
@@ -578,7 +587,7 @@ __global__ __launch_bounds__(64) void k_ps_stage(HeviShapeDev sh, const double* 
   }
   double r = (lane < W && n - 1 - lane >= 0) ? xs[n - 1 - lane] : 0.0;
   double un = bcast(ur[0], 0);
-  double rn = 1.0 / un;
+  double rn = ps_recip(un);
   for (int jt = n - 1; jt >= 0; jt -= T) {
     const int ju = jt - D - lane;
     const int ux = ju >= 0 ? (int)uxr[ju] : -1;
@@ -591,10 +600,10 @@ __global__ __launch_bounds__(64) void k_ps_stage(HeviShapeDev sh, const double* 
       for (int e = 0; e < D; ++e) {
         const int d = d0 + e;
         const int j = jt - d;
-        // x_j = r_j / U_jj correctly rounded, with only a product and two FMAs on the chain
-        // through r: the reciprocal of U_jj is computed a step ahead, off the chain, and
-        // one residual correction of the product gives the rounded quotient (Markstein's
-        // final step of division with a fused multiply-add)
+        // x_j = r_j / U_jj with only a product and two FMAs on the chain through r: the
+        // reciprocal of U_jj is computed a step ahead, off the chain, and one residual
+        // correction of the product (Markstein's final step of division with a fused
+        // multiply-add) gives the rounded quotient but in rare cases of the last bit
         const double u = un, ri = rn;
         const double r0 = bcast(r, 0);
         double xj = r0 * ri;
@@ -602,7 +611,7 @@ __global__ __launch_bounds__(64) void k_ps_stage(HeviShapeDev sh, const double* 
         r = fma(-ur[e], xj, r);
         ur[e] = ps_bload(urs, uoff(j - D, __builtin_amdgcn_readlane(ux, d)));
         un = bcast(ur[(e + 1) % D], 0);  // the next step's U_jj, loaded D - 1 steps ago
-        rn = 1.0 / un;
+        rn = ps_recip(un);
         if (lane == d) ob = xj;
         r = shift_down1(r);
         const double ent = bcast(eb, d);
@@ -619,7 +628,7 @@ __global__ __launch_bounds__(64) void k_ps_stage(HeviShapeDev sh, const double* 
   bool nonfinite = false;
   for (int r = lane; r < n; r += T) {
     const int k = r / 5, v = r - 5 * k;
-    const double q = qe[r] + (xs[r] - qh[r]);
+    const double q = xs[r] + qd[r];
     Qi[cix(nz, nc, v, k, col)] = q;
     if (!isfinite(q)) nonfinite = true;
   }
@@ -806,7 +815,7 @@ struct PsStage {
                         const HeviTerms& Q, double* Qi, HeviDevInfo* info, hipStream_t st) {
     const size_t n = 5 * (size_t)sh.nz;
     hipLaunchKernelGGL(k_ps_stage<N>, dim3(ps_grid(sh.ncols)), dim3(T),
-                       3 * n * sizeof(double) + 3 * n, st, sh, ops, U, L, piv, E, Q, Qi, info);
+                       2 * n * sizeof(double) + 3 * n, st, sh, ops, U, L, piv, E, Q, Qi, info);
     return hipGetLastError();
   }
 };
