@@ -28,7 +28,7 @@
 //
 // Factor storage per column (column-contiguous): U by columns of the band, [n][W] with
 // entry (c, l) = U[c - l][c] (what the column-oriented back substitution reads, in order;
-// entries past the column's extent are not written); L [n][KL] (multipliers of step j
+// the entries above the first row, l > c, are not written); L [n][KL] (multipliers of step j
 // for rows j+1..j+KL); four byte planes, each [ncols][n]: the pivot offsets, the row
 // exponents e (signed), the extent of each U column (largest offset l of a nonzero
 // entry) and of each step's multipliers (largest i of a nonzero one), n = 5 n_z.  At

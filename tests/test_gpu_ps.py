@@ -223,3 +223,39 @@ def test_ps_rest_state_matches_reference_path(ctx):
         ctx.stage_solve(f, [dev(b)], [1.0], [], [], x)
         xs.append(host(x))
     assert relerr_cols(xs[0], xs[1]) < 1e-12
+
+
+@pytest.mark.parametrize("N,Ne", [(4, 149), (5, 119)])
+def test_ps_tall_columns(ctx, N, Ne):
+    """Columns at the largest supported height (n_z <= 600, 2,985 unknowns, 47 blocks of 64
+    substitution steps): the band solve's normwise backward error against the oracle's
+    dense A is at rounding level, and one more element is refused with HEVI_E_SHAPE."""
+    from paper_2311_11425_amd import hevi
+    from paper_2311_11425_amd.driver import ColumnBatch
+    col = W(inputs.make_columns(N, Ne, 2, profile="lapse", seed=43, surface_max=800.0))
+    nz = col["z"].shape[0]
+    print(f"PS tall N={N} Ne={Ne} nz={nz}", flush=True)
+    B = ColumnBatch(ctx, col)
+    lam = 0.4358665215 * 300.0
+    b = rhs(col)
+    f = ctx.factor(B.ops, lam, 0)
+    code, inf = f.check()
+    assert code == 0, inf
+    x = B.empty_state()
+    inf = ctx.stage_solve(f, [dev(b)], [1.0], [], [], x, info=True)
+    assert inf["status"] == "HEVI_OK", inf
+    xg = host(x)
+    for c in range(2):
+        z, J, gz, r0, T0 = oracle.column_of(col, c)
+        A = oracle.form_A(oracle.column_L(N, Ne, inputs.CONSTS, z, J, gz, r0, T0,
+                                          U0_k3=oracle.u0_of(col, c)), lam)
+        bb = oracle.bc_project(nz, gz, oracle.vec_of(b, c))
+        xc = oracle.vec_of(xg, c)
+        res = np.abs(A @ xc - bb).max()
+        berr = res / (np.abs(A).sum(1).max() * np.abs(xc).max() + np.abs(bb).max())
+        print(f"column {c}: backward error {berr:.2e}", flush=True)
+        assert berr < 1e-14, berr
+    with pytest.raises(hevi.HeviError) as ei:
+        B2 = ColumnBatch(ctx, W(inputs.make_columns(N, Ne + (5 if N == 4 else 1), 1)))
+        ctx.factor(B2.ops, lam, 0)
+    assert ei.value.code == 2
