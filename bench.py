@@ -337,6 +337,15 @@ def set3c_leg(ctx, checks, ncols=86402, steps=100, warmup=10):
     return out
 
 
+def ps_factor_bytes(N, nz):
+    """LHEVI-PS factor storage per column: per unknown a U column of 2 kl + 1 and an L row
+    of kl FP64 entries, each padded to whole 128-byte lines, and four bytes (pivot offset,
+    row exponent, U and L extents)."""
+    kl = 5 * (N + 1) - 1
+    pad = lambda w: -(-w // 16) * 16
+    return 5 * nz * ((pad(2 * kl + 1) + pad(kl)) * 8 + 4)
+
+
 def ps_leg(ctx, checks, ncols=86402, steps=20, warmup=3, refresh=5):
     """LHEVI-PS at the ne=30 shape: the operator linearised at a moving state (a
     previous solution with a 10-30 m/s horizontal and 0.5 m/s vertical wind), the whole
@@ -364,8 +373,7 @@ def ps_leg(ctx, checks, ncols=86402, steps=20, warmup=3, refresh=5):
          "column_solves_per_s_refresh_every_%d" % refresh: 3 * ncols / (amort * 1e-3),
          "stage_solve_ms": float(np.mean(r["stage_ms"])), "factor_ms": fac,
          "apply_op_ms": float(np.mean(r["apply_ms"])),
-         # U (2 kl + 1) and L (kl) FP64 entries per row, pivot and scale bytes
-         "factor_bytes_per_column": 5 * col["nz"] * ((3 * (5 * (col["N"] + 1) - 1) + 1) * 8 + 4)}
+         "factor_bytes_per_column": ps_factor_bytes(col["N"], col["nz"])}
     queue_stage_errors(checks, d, "stage_rel_err_vs_oracle", st, col, qn, idx, BARS["fp64"])
     del st
     return d

@@ -80,9 +80,10 @@ hipError_t hevi_launch_stage_solve_3c(const HeviShapeDev& sh, double lambda, int
 
 // LHEVI-PS (hevi_ps.hip): the full 5 n_z band, one wavefront per column, N <= 5.
 // Operators hold the velocity planes of the linearisation state after the eight
-// fields (HEVI_NOPS + 3 planes); factors U [ncols][n][W], L [ncols][n][KL], pivot
-// offsets [ncols][n] then row-scale exponents [ncols][n] (bytes), n = 5 n_z,
-// KL = hevi_ps_lower_width(N), W = hevi_ps_band_width(N).
+// fields (HEVI_NOPS + 3 planes); factors U [ncols][n][WS], L [ncols][n][KLS], then four
+// byte planes [ncols][n] (pivot offsets, row-scale exponents, U and L extents), n = 5 n_z,
+// KLS = hevi_ps_lower_width(N), WS = hevi_ps_band_width(N) (the band widths rounded up to
+// whole 128-byte lines).
 #define HEVI_PS_MAXN 5
 int hevi_ps_band_width(int N);
 int hevi_ps_lower_width(int N);

@@ -26,13 +26,14 @@
 // continuity, momentum and rho-theta rows), and unscaled pivoting on them lost a digit
 // at the ne = 30 shape; the solves scale the right-hand side the same way.
 //
-// Factor storage per column (column-contiguous): U by columns of the band, [n][W] with
+// Factor storage per column (column-contiguous): U by columns of the band, [n][WS] with
 // entry (c, l) = U[c - l][c] (what the column-oriented back substitution reads, in order;
-// the entries above the first row, l > c, are not written); L [n][KL] (multipliers of step j
-// for rows j+1..j+KL); four byte planes, each [ncols][n]: the pivot offsets, the row
-// exponents e (signed), the extent of each U column (largest offset l of a nonzero
-// entry) and of each step's multipliers (largest i of a nonzero one), n = 5 n_z.  At
-// N = 4, n_z = 41: 120,540 bytes per column.
+// the entries above the first row, l > c, and the padding are not written); L [n][KLS]
+// (multipliers of step j for rows j+1..j+KL); WS and KLS are W and KL rounded up to whole
+// 128-byte lines; four byte planes, each [ncols][n]: the pivot offsets, the row exponents
+// e (signed), the extent of each U column (largest offset l of a nonzero entry) and of
+// each step's multipliers (largest i of a nonzero one), n = 5 n_z.  At N = 4, n_z = 41:
+// 158,260 bytes per column.
 #include "hevi_device.h"
 
 namespace {
@@ -41,6 +42,12 @@ template <int N>
 constexpr int kPsKL = 5 * (N + 1) - 1;
 template <int N>
 constexpr int kPsW = 2 * kPsKL<N> + 1;
+// Stored widths: a U column and an L row padded to whole 128-byte cache lines, so that a
+// read up to an extent touches only the lines the extent needs.
+template <int N>
+constexpr int kPsWS = (kPsW<N> + 15) / 16 * 16;
+template <int N>
+constexpr int kPsKLS = (kPsKL<N> + 15) / 16 * 16;
 
 // Whole-wavefront lane shifts by DPP (wave_shl:1 / wave_shr:1, a VALU move): lane i
 // takes lane i+1's value (shift_down1; lane 63 takes 0) or lane i-1's (shift_up1; lane 0
@@ -323,8 +330,9 @@ __global__ __launch_bounds__(64, kPsFactorWaves<N>) void k_ps_factor(HeviShapeDe
                       (int)(col % T)},
                 nodes);
   const PsNodes P{nodes, nz};
-  double* Uc = Ub + (size_t)col * n * W;
-  double* Lr = Lb + (size_t)col * n * KL;
+  constexpr int WS = kPsWS<N>, KLS = kPsKLS<N>;
+  double* Uc = Ub + (size_t)col * n * WS;
+  double* Lr = Lb + (size_t)col * n * KLS;
   const size_t plane = (size_t)sh.ncols * n;
   uint8_t* pr = piv + (size_t)col * n;
   int8_t* er = (int8_t*)piv + plane + (size_t)col * n;
@@ -378,7 +386,7 @@ __global__ __launch_bounds__(64, kPsFactorWaves<N>) void k_ps_factor(HeviShapeDe
     const double mv = cs * rp;
     if (lane >= 1 && lane <= KL) {
       mb[lane] = mv;
-      Lr[(size_t)j * KL + lane - 1] = mv;
+      Lr[(size_t)j * KLS + lane - 1] = mv;
     }
     // U row j into the column-band layout (entry (j, j+l) at column j+l, offset l), through
     // LDS: rows are staged for 8 steps, then written as runs of up to 8 consecutive entries
@@ -389,7 +397,7 @@ __global__ __launch_bounds__(64, kPsFactorWaves<N>) void k_ps_factor(HeviShapeDe
       const int r0 = j & ~7, nr = j - r0 + 1;
       for (int t = lane; t < (W + 7) * 8; t += T) {
         const int cc = t >> 3, k = t & 7, o = cc - k, c = r0 + cc;
-        if (k < nr && o >= 0 && o < W && c < n) Uc[(size_t)c * W + o] = ub[k * W + o];
+        if (k < nr && o >= 0 && o < W && c < n) Uc[(size_t)c * WS + o] = ub[k * W + o];
       }
     }
     if (lane == 0) {
@@ -458,7 +466,7 @@ __global__ __launch_bounds__(64) void k_ps_stage(HeviShapeDev sh, const double* 
                                                  const uint8_t* __restrict__ piv, HeviTerms E,
                                                  HeviTerms Q, double* __restrict__ Qi,
                                                  HeviDevInfo* info) {
-  constexpr int KL = kPsKL<N>, W = kPsW<N>;
+  constexpr int KL = kPsKL<N>, W = kPsW<N>, WS = kPsWS<N>, KLS = kPsKLS<N>;
   extern __shared__ double sm[];
   const int lane = threadIdx.x;
   const int64_t col = ps_column(sh.ncols);
@@ -513,9 +521,9 @@ __global__ __launch_bounds__(64) void k_ps_stage(HeviShapeDev sh, const double* 
   __syncthreads();
   constexpr int D = kPsRing;
   const __amdgpu_buffer_rsrc_t lrs = __builtin_amdgcn_make_buffer_rsrc(
-      (void*)(Lb + (size_t)col * n * KL), (short)0, n * KL * (int)sizeof(double), 0x00020000);
+      (void*)(Lb + (size_t)col * n * KLS), (short)0, n * KLS * (int)sizeof(double), 0x00020000);
   const __amdgpu_buffer_rsrc_t urs = __builtin_amdgcn_make_buffer_rsrc(
-      (void*)(Ub + (size_t)col * n * W), (short)0, n * W * (int)sizeof(double), 0x00020000);
+      (void*)(Ub + (size_t)col * n * WS), (short)0, n * WS * (int)sizeof(double), 0x00020000);
   // Forward: the row exchanges and L, y[j + i] in lane i (i = 0..KL).  Each block of 64
   // steps takes its pivot offsets, the extents of the rows its ring loads fetch and the
   // entering values y[j + 1 + KL] from lane-spread registers (read from LDS once per
@@ -525,7 +533,7 @@ __global__ __launch_bounds__(64) void k_ps_stage(HeviShapeDev sh, const double* 
   // step have extent 0, so all their lanes read zero.
   const bool lrow = lane >= 1 && lane <= KL;
   auto loff = [&](int j, int x) -> unsigned {
-    return lane >= 1 && lane <= x ? (unsigned)((j * KL + lane - 1) * (int)sizeof(double)) : kPsOff;
+    return lane >= 1 && lane <= x ? (unsigned)((j * KLS + lane - 1) * (int)sizeof(double)) : kPsOff;
   };
   double lr[D];
 #pragma unroll
@@ -577,7 +585,7 @@ __global__ __launch_bounds__(64) void k_ps_stage(HeviShapeDev sh, const double* 
   // by the entering row (lane W-1 takes lane W's) before any use.  The extra steps below
   // the first row read nothing (extent -1) and are not stored.
   auto uoff = [&](int j, int x) -> unsigned {
-    return lane <= x ? (unsigned)((j * W + lane) * (int)sizeof(double)) : kPsOff;
+    return lane <= x ? (unsigned)((j * WS + lane) * (int)sizeof(double)) : kPsOff;
   };
   double ur[D];
 #pragma unroll
@@ -836,8 +844,8 @@ struct PsApply {
 
 }  // namespace
 
-int hevi_ps_band_width(int N) { return 2 * (5 * (N + 1) - 1) + 1; }
-int hevi_ps_lower_width(int N) { return 5 * (N + 1) - 1; }
+int hevi_ps_band_width(int N) { return (2 * (5 * (N + 1) - 1) + 1 + 15) / 16 * 16; }
+int hevi_ps_lower_width(int N) { return (5 * (N + 1) - 1 + 15) / 16 * 16; }
 
 hipError_t hevi_launch_ps_factor(const HeviShapeDev& sh, double lambda, const double* ops,
                                  double* U, double* L, uint8_t* piv, HeviDevInfo* info,
