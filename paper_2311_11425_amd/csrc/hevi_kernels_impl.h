@@ -85,8 +85,8 @@ __global__ __launch_bounds__(CHUNKED ? 64 * kMaxChunks : 64, kStreamWaves<N>) vo
   b_stage_rhs<N, true, TILT, S3>(tile, sh, Gll<N>{}, lambda, ops, ws, E, Q, Qi, ru, cw);
   __syncthreads();
   if (threadIdx.x < T)
-    band_solve<N, double, true>(Ub, Lb, piv, plane_size(sh), ws, tile, sh.nz, (int)threadIdx.x,
-                                WS_R, WS_U, ru);
+    band_solve<N, double, true, HEVI_NWS, CHUNKED>(Ub, Lb, piv, plane_size(sh), ws, tile, sh.nz,
+                                                   (int)threadIdx.x, WS_R, WS_U, ru);
   __syncthreads();
   b_stage_update<N, true, TILT, S3>(tile, sh, Gll<N>{}, lambda, ops, ws, Qi, info, ru, cw);
 }
