@@ -897,17 +897,27 @@ __device__ __forceinline__ void b_factor_fused_split(int64_t tile, int part, Hev
 enum { WS_R = 0, WS_U = 1, WS_VR = 2, WS_VT = 3, WS_T = 4, WS_D = 5, WS_B = 6, WS_X = 11,
        WS_S = 16 };
 
-// band_solve for launches of few tiles (the chunked fused stage kernel), where each
-// wavefront's memory latency is exposed: for the ring to stay in flight the loads must be unconditional and nothing may use a
-// value right after loading it: a guarded load (a branch), a step behind a branch, or a
-// load whose value is used at once makes the compiler wait for every outstanding load,
-// the one just issued included.  So the groups of PF (PB) steps always run whole (the
-// steps past the last row compute on clamped rows and store nothing), a row's scale is
-// applied when its entry enters the window, and the FP64 U rows are read by buffer
-// loads whose lanes past the row's extent take an offset outside the buffer (zero
-// returned, no memory access) instead of guarded loads.
-template <int N, typename FT, bool LDSRU, int NWS>
-__device__ __forceinline__ void band_solve_pipe(const FT* __restrict__ Ub, const FT* __restrict__ Lb,
+// solve S x = rhs with the band LU factors (rhs field fi, result field fo).
+// The sweeps are sequential in the row index, so each wavefront keeps the factor
+// rows of the next rows in flight (PF forward, PB backward) in a register ring,
+// refilled as soon as a slot is consumed, while it works on the current row.  The
+// fused stage kernels (LDSRU) hold r/u in LDS and have the registers for a third
+// backward slot; the others spill with it.
+//
+// PIPE (bit 0 forward, bit 1 backward) selects the pipelined form of a sweep, same
+// arithmetic.  For the ring to stay in flight the loads must be unconditional and nothing
+// may use a value right after loading it: a guarded load (a branch), a step behind a
+// branch, or a load whose value is used at once makes the compiler wait for every
+// outstanding load, the one just issued included.  So in the pipelined form the groups of
+// PF (PB) steps always run whole (the steps past the last row compute on clamped rows and
+// store nothing), a row's scale is applied when its entry enters the window, and the
+// FP64 U rows are read by buffer loads whose lanes past the row's extent take an offset
+// outside the buffer (zero returned, no memory access) instead of guarded loads.  In a
+// launch of few tiles each wavefront's memory latency is exposed and the pipelined form
+// is faster (the 10,800-column share: 0.596 against 0.660 ms per step); when the chip is
+// full the guarded form measured faster (0.389 against 0.404 ms per stage solve at ne = 30).
+template <int N, typename FT, bool LDSRU = false, int NWS = HEVI_NWS, int PIPE = 0>
+__device__ __forceinline__ void band_solve(const FT* __restrict__ Ub, const FT* __restrict__ Lb,
                                            const uint8_t* __restrict__ piv, size_t plane,
                                            double* ws, int64_t tile, int nz, int lane, int fi,
                                            int fo, double* ru = nullptr) {
@@ -920,139 +930,8 @@ __device__ __forceinline__ void band_solve_pipe(const FT* __restrict__ Ub, const
   constexpr int B = 2 * N, K = 4 * N, PF = 3, PB = LDSRU ? 3 : 2;
   // U row extents (see plane_size): entries past them are zeros and, with FP64
   // factors, are not fetched; each ring slot knows the extent of the row it loads
-  // next.  The FP32-factor solves run inside refinement sweeps and load the full rows.
-  constexpr bool SKIP = std::is_same<FT, double>::value;
-  const uint8_t* ue_p = piv + plane;
-  auto pidx = [&](int k) { return tix(tile, nz, k, 1, 0, lane); };
-  auto rex = [&](int k) { return (int)(int8_t)piv[2 * plane + pidx(min(k, nz - 1))]; };
-  // right-hand side entry k (zero past the last row) and its row's exponent e_k: the
-  // entry enters the window as r_k 2^-e_k (see scale_row)
-  auto rval = [&](int k) { return k < nz ? S(min(k, nz - 1), fi) : 0.0; };
-  // ---- forward: row swaps and unit-lower elimination ----
-  double y[B + 1];
-#pragma unroll
-  for (int t = 0; t <= B; ++t) y[t] = ldexp(rval(t), -rex(t));
-  double lr[PF][B], rin[PF];
-  int pv[PF], rie[PF];
-#pragma unroll
-  for (int d = 0; d < PF; ++d) {
-    const int jj = d < nz ? d : nz - 1;
-    pv[d] = piv[pidx(jj)];
-#pragma unroll
-    for (int t = 0; t < B; ++t) lr[d][t] = ld(Lb + tix(tile, nz, jj, B, t, lane));
-    rin[d] = rval(d + B + 1);
-    rie[d] = rex(d + B + 1);
-  }
-  for (int j0 = 0; j0 < nz; j0 += PF) {
-#pragma unroll
-    for (int d = 0; d < PF; ++d) {
-      const int j = j0 + d;
-      const int p = pv[d];
-      const double v0 = y[0];
-      double vp = v0;
-#pragma unroll
-      for (int t = 1; t <= B; ++t) vp = (p == t) ? y[t] : vp;
-#pragma unroll
-      for (int t = 1; t <= B; ++t) y[t] = (p == t) ? v0 : y[t];
-      if (j < nz) S(j, fo) = vp;
-#pragma unroll
-      for (int t = 1; t <= B; ++t) y[t] -= lr[d][t - 1] * vp;
-#pragma unroll
-      for (int t = 0; t < B; ++t) y[t] = y[t + 1];
-      y[B] = ldexp(rin[d], -rie[d]);
-      // refill the consumed slot with row j + PF
-      const int jn = j + PF;
-      const int jj = jn < nz ? jn : nz - 1;
-      pv[d] = piv[pidx(jj)];
-#pragma unroll
-      for (int t = 0; t < B; ++t) lr[d][t] = ld(Lb + tix(tile, nz, jj, B, t, lane));
-      rin[d] = rval(jn + B + 1);
-      rie[d] = rex(jn + B + 1);
-    }
-  }
-  // ---- backward: upper-triangular substitution ----
-  double xw[K + 1];
-#pragma unroll
-  for (int t = 0; t <= K; ++t) xw[t] = 0.0;
-  double ur[PB][K + 1], yin[PB];
-  int unext[PB];
-  // FP64 rows: buffer loads over this tile's U block (unused with FP32 factors)
-  const __amdgpu_buffer_rsrc_t urs = __builtin_amdgcn_make_buffer_rsrc(
-      (void*)(Ub + tix(tile, nz, 0, K + 1, 0, 0)), (short)0,
-      (int)((size_t)nz * (K + 1) * T * sizeof(FT)), 0x00020000);
-  auto urow = [&](double (&dst)[K + 1], int jj, int ue) {
-#pragma unroll
-    for (int t = 0; t <= K; ++t) {
-      if constexpr (SKIP) {
-        const unsigned off = t <= ue ? (unsigned)(tix(0, nz, jj, K + 1, t, lane) * sizeof(double))
-                                     : 0x80000000u;
-        dst[t] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(urs, off, 0, 2 /*nt*/));
-      } else {
-        dst[t] = ld(Ub + tix(tile, nz, jj, K + 1, t, lane));
-      }
-    }
-  };
-#pragma unroll
-  for (int d = 0; d < PB; ++d) {
-    const int jr = nz - 1 - d;
-    const int jj = jr >= 0 ? jr : 0;
-    urow(ur[d], jj, SKIP ? (int)ue_p[pidx(jj)] : K);
-    unext[d] = SKIP ? ue_p[pidx(max(jr - PB, 0))] : K;
-    yin[d] = S(jj, fo);
-  }
-  for (int j0 = nz - 1; j0 >= 0; j0 -= PB) {
-#pragma unroll
-    for (int d = 0; d < PB; ++d) {
-      const int j = j0 - d;
-      double s = yin[d];
-#pragma unroll
-      for (int t = 1; t <= K; ++t) s -= ur[d][t] * xw[t];
-      const double xj = s / ur[d][0];
-      if (j >= 0) S(j, fo) = xj;
-#pragma unroll
-      for (int t = K; t >= 2; --t) xw[t] = xw[t - 1];
-      xw[1] = xj;
-      // refill the consumed slot with row j - PB (steps below the first row work on
-      // row 0 again and store nothing)
-      const int jr = j - PB;
-      const int jj = jr >= 0 ? jr : 0;
-      urow(ur[d], jj, unext[d]);
-      if constexpr (SKIP) unext[d] = ue_p[pidx(max(jr - PB, 0))];
-      yin[d] = S(jj, fo);
-    }
-  }
-}
-
-// solve S x = rhs with the band LU factors (rhs field fi, result field fo).
-// The sweeps are sequential in the row index, so each wavefront keeps the factor
-// rows of the next rows in flight (PF forward, PB backward) in a register ring,
-// refilled as soon as a slot is consumed, while it works on the current row.  The
-// fused stage kernels (LDSRU) hold r/u in LDS and have the registers for a third
-// backward slot; the others spill with it.  PIPE: the variant for launches of few tiles
-// (band_solve_pipe), same arithmetic.  When the chip is full the guarded loads of this
-// one measured faster (0.389 against 0.404 ms per stage solve at ne = 30); with 169 tiles
-// the pipelined one is (0.596 against 0.660 ms per step).
-template <int N, typename FT, bool LDSRU = false, int NWS = HEVI_NWS, bool PIPE = false>
-__device__ __forceinline__ void band_solve(const FT* __restrict__ Ub, const FT* __restrict__ Lb,
-                                           const uint8_t* __restrict__ piv, size_t plane,
-                                           double* ws, int64_t tile, int nz, int lane, int fi,
-                                           int fo, double* ru = nullptr) {
-  if constexpr (PIPE) {
-    band_solve_pipe<N, FT, LDSRU, NWS>(Ub, Lb, piv, plane, ws, tile, nz, lane, fi, fo, ru);
-    return;
-  }
-  // right-hand side and solution: scratch fields fi / fo, or (LDSRU) one array
-  // ru[k * 64 + lane] in LDS used in place
-  auto S = [&](int k, int f) -> double& {
-    if constexpr (LDSRU) return ru[k * T + lane];
-    else return ws[tix(tile, nz, k, NWS, f, lane)];
-  };
-  constexpr int B = 2 * N, K = 4 * N, PF = 3, PB = LDSRU ? 3 : 2;
-  // U row extents (see plane_size): entries past them are zeros and, with FP64
-  // factors, are not loaded; each ring slot knows the extent of the row it loads
-  // next.  The FP32-factor solves run inside refinement sweeps, where the extra
-  // code of the skipping pushed the kernel into scratch spills: they load the
-  // full rows.
+  // next.  The FP32-factor solves run inside refinement sweeps, where the extra code of
+  // the skipping pushed the kernel into scratch spills: they load the full rows.
   constexpr bool SKIP = std::is_same<FT, double>::value;
   const uint8_t* ue_p = piv + plane;
   auto pidx = [&](int k) { return tix(tile, nz, k, 1, 0, lane); };
@@ -1062,25 +941,29 @@ __device__ __forceinline__ void band_solve(const FT* __restrict__ Ub, const FT* 
     const int ex = (int)(int8_t)piv[2 * plane + pidx(kk)];
     return k < nz ? ldexp(S(kk, fi), -ex) : 0.0;
   };
-  // ---- forward: row swaps and unit-lower elimination ----
-  double y[B + 1];
+  // the same as two parts: the entry (zero past the last row) and the exponent
+  auto rex = [&](int k) { return (int)(int8_t)piv[2 * plane + pidx(min(k, nz - 1))]; };
+  auto rval = [&](int k) { return k < nz ? S(min(k, nz - 1), fi) : 0.0; };
+  if constexpr ((PIPE & 1) != 0) {
+    // ---- forward: row swaps and unit-lower elimination ----
+    double y[B + 1];
 #pragma unroll
-  for (int t = 0; t <= B; ++t) y[t] = rhs(t);
-  double lr[PF][B], rin[PF];
-  int pv[PF];
-#pragma unroll
-  for (int d = 0; d < PF; ++d) {
-    const int jj = d < nz ? d : nz - 1;
-    pv[d] = piv[pidx(jj)];
-#pragma unroll
-    for (int t = 0; t < B; ++t) lr[d][t] = ld(Lb + tix(tile, nz, jj, B, t, lane));
-    rin[d] = rhs(d + B + 1);
-  }
-  for (int j0 = 0; j0 < nz; j0 += PF) {
+    for (int t = 0; t <= B; ++t) y[t] = ldexp(rval(t), -rex(t));
+    double lr[PF][B], rin[PF];
+    int pv[PF], rie[PF];
 #pragma unroll
     for (int d = 0; d < PF; ++d) {
-      const int j = j0 + d;
-      if (j < nz) {
+      const int jj = d < nz ? d : nz - 1;
+      pv[d] = piv[pidx(jj)];
+#pragma unroll
+      for (int t = 0; t < B; ++t) lr[d][t] = ld(Lb + tix(tile, nz, jj, B, t, lane));
+      rin[d] = rval(d + B + 1);
+      rie[d] = rex(d + B + 1);
+    }
+    for (int j0 = 0; j0 < nz; j0 += PF) {
+#pragma unroll
+      for (int d = 0; d < PF; ++d) {
+        const int j = j0 + d;
         const int p = pv[d];
         const double v0 = y[0];
         double vp = v0;
@@ -1088,67 +971,166 @@ __device__ __forceinline__ void band_solve(const FT* __restrict__ Ub, const FT* 
         for (int t = 1; t <= B; ++t) vp = (p == t) ? y[t] : vp;
 #pragma unroll
         for (int t = 1; t <= B; ++t) y[t] = (p == t) ? v0 : y[t];
-        S(j, fo) = vp;
+        if (j < nz) S(j, fo) = vp;
 #pragma unroll
         for (int t = 1; t <= B; ++t) y[t] -= lr[d][t - 1] * vp;
 #pragma unroll
         for (int t = 0; t < B; ++t) y[t] = y[t + 1];
-        y[B] = rin[d];
+        y[B] = ldexp(rin[d], -rie[d]);
         // refill the consumed slot with row j + PF
         const int jn = j + PF;
         const int jj = jn < nz ? jn : nz - 1;
         pv[d] = piv[pidx(jj)];
 #pragma unroll
         for (int t = 0; t < B; ++t) lr[d][t] = ld(Lb + tix(tile, nz, jj, B, t, lane));
-        rin[d] = rhs(jn + B + 1);
+        rin[d] = rval(jn + B + 1);
+        rie[d] = rex(jn + B + 1);
+      }
+    }
+  } else {
+    // ---- forward: row swaps and unit-lower elimination ----
+    double y[B + 1];
+#pragma unroll
+    for (int t = 0; t <= B; ++t) y[t] = rhs(t);
+    double lr[PF][B], rin[PF];
+    int pv[PF];
+#pragma unroll
+    for (int d = 0; d < PF; ++d) {
+      const int jj = d < nz ? d : nz - 1;
+      pv[d] = piv[pidx(jj)];
+#pragma unroll
+      for (int t = 0; t < B; ++t) lr[d][t] = ld(Lb + tix(tile, nz, jj, B, t, lane));
+      rin[d] = rhs(d + B + 1);
+    }
+    for (int j0 = 0; j0 < nz; j0 += PF) {
+#pragma unroll
+      for (int d = 0; d < PF; ++d) {
+        const int j = j0 + d;
+        if (j < nz) {
+          const int p = pv[d];
+          const double v0 = y[0];
+          double vp = v0;
+#pragma unroll
+          for (int t = 1; t <= B; ++t) vp = (p == t) ? y[t] : vp;
+#pragma unroll
+          for (int t = 1; t <= B; ++t) y[t] = (p == t) ? v0 : y[t];
+          S(j, fo) = vp;
+#pragma unroll
+          for (int t = 1; t <= B; ++t) y[t] -= lr[d][t - 1] * vp;
+#pragma unroll
+          for (int t = 0; t < B; ++t) y[t] = y[t + 1];
+          y[B] = rin[d];
+          // refill the consumed slot with row j + PF
+          const int jn = j + PF;
+          const int jj = jn < nz ? jn : nz - 1;
+          pv[d] = piv[pidx(jj)];
+#pragma unroll
+          for (int t = 0; t < B; ++t) lr[d][t] = ld(Lb + tix(tile, nz, jj, B, t, lane));
+          rin[d] = rhs(jn + B + 1);
+        }
       }
     }
   }
-  // ---- backward: upper-triangular substitution ----
-  double xw[K + 1];
+  if constexpr ((PIPE & 2) != 0) {
+    // ---- backward: upper-triangular substitution ----
+    double xw[K + 1];
 #pragma unroll
-  for (int t = 0; t <= K; ++t) xw[t] = 0.0;
-  double ur[PB][K + 1], yin[PB];
-  int unext[PB];
+    for (int t = 0; t <= K; ++t) xw[t] = 0.0;
+    double ur[PB][K + 1], yin[PB];
+    int unext[PB];
+    // FP64 rows: buffer loads over this tile's U block (unused with FP32 factors)
+    const __amdgpu_buffer_rsrc_t urs = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(Ub + tix(tile, nz, 0, K + 1, 0, 0)), (short)0,
+        (int)((size_t)nz * (K + 1) * T * sizeof(FT)), 0x00020000);
+    auto urow = [&](double (&dst)[K + 1], int jj, int ue) {
 #pragma unroll
-  for (int d = 0; d < PB; ++d) {
-    const int jr = nz - 1 - d;
-    const int jj = jr >= 0 ? jr : 0;
-    const int ue = SKIP ? ue_p[pidx(jj)] : K;
-#pragma unroll
-    for (int t = 0; t <= K; ++t) {
-      double v = 0.0;
-      if (!SKIP || t <= ue) v = ld(Ub + tix(tile, nz, jj, K + 1, t, lane));
-      ur[d][t] = v;
-    }
-    unext[d] = SKIP ? ue_p[pidx(max(jr - PB, 0))] : K;
-    yin[d] = S(jj, fo);
-  }
-  for (int j0 = nz - 1; j0 >= 0; j0 -= PB) {
+      for (int t = 0; t <= K; ++t) {
+        if constexpr (SKIP) {
+          const unsigned off =
+              t <= ue ? (unsigned)(tix(0, nz, jj, K + 1, t, lane) * sizeof(double)) : 0x80000000u;
+          dst[t] = __builtin_bit_cast(double,
+                                      __builtin_amdgcn_raw_buffer_load_b64(urs, off, 0, 2 /*nt*/));
+        } else {
+          dst[t] = ld(Ub + tix(tile, nz, jj, K + 1, t, lane));
+        }
+      }
+    };
 #pragma unroll
     for (int d = 0; d < PB; ++d) {
-      const int j = j0 - d;
-      if (j >= 0) {
+      const int jr = nz - 1 - d;
+      const int jj = jr >= 0 ? jr : 0;
+      urow(ur[d], jj, SKIP ? (int)ue_p[pidx(jj)] : K);
+      unext[d] = SKIP ? ue_p[pidx(max(jr - PB, 0))] : K;
+      yin[d] = S(jj, fo);
+    }
+    for (int j0 = nz - 1; j0 >= 0; j0 -= PB) {
+#pragma unroll
+      for (int d = 0; d < PB; ++d) {
+        const int j = j0 - d;
         double s = yin[d];
 #pragma unroll
         for (int t = 1; t <= K; ++t) s -= ur[d][t] * xw[t];
         const double xj = s / ur[d][0];
-        S(j, fo) = xj;
+        if (j >= 0) S(j, fo) = xj;
 #pragma unroll
         for (int t = K; t >= 2; --t) xw[t] = xw[t - 1];
         xw[1] = xj;
-        // refill the consumed slot with row j - PB
+        // refill the consumed slot with row j - PB (steps below the first row work on
+        // row 0 again and store nothing)
         const int jr = j - PB;
         const int jj = jr >= 0 ? jr : 0;
-        const int ue = unext[d];
-#pragma unroll
-        for (int t = 0; t <= K; ++t) {
-          double v = 0.0;
-          if (!SKIP || t <= ue) v = ld(Ub + tix(tile, nz, jj, K + 1, t, lane));
-          ur[d][t] = v;
-        }
+        urow(ur[d], jj, unext[d]);
         if constexpr (SKIP) unext[d] = ue_p[pidx(max(jr - PB, 0))];
         yin[d] = S(jj, fo);
+      }
+    }
+  } else {
+    // ---- backward: upper-triangular substitution ----
+    double xw[K + 1];
+#pragma unroll
+    for (int t = 0; t <= K; ++t) xw[t] = 0.0;
+    double ur[PB][K + 1], yin[PB];
+    int unext[PB];
+#pragma unroll
+    for (int d = 0; d < PB; ++d) {
+      const int jr = nz - 1 - d;
+      const int jj = jr >= 0 ? jr : 0;
+      const int ue = SKIP ? ue_p[pidx(jj)] : K;
+#pragma unroll
+      for (int t = 0; t <= K; ++t) {
+        double v = 0.0;
+        if (!SKIP || t <= ue) v = ld(Ub + tix(tile, nz, jj, K + 1, t, lane));
+        ur[d][t] = v;
+      }
+      unext[d] = SKIP ? ue_p[pidx(max(jr - PB, 0))] : K;
+      yin[d] = S(jj, fo);
+    }
+    for (int j0 = nz - 1; j0 >= 0; j0 -= PB) {
+#pragma unroll
+      for (int d = 0; d < PB; ++d) {
+        const int j = j0 - d;
+        if (j >= 0) {
+          double s = yin[d];
+#pragma unroll
+          for (int t = 1; t <= K; ++t) s -= ur[d][t] * xw[t];
+          const double xj = s / ur[d][0];
+          S(j, fo) = xj;
+#pragma unroll
+          for (int t = K; t >= 2; --t) xw[t] = xw[t - 1];
+          xw[1] = xj;
+          // refill the consumed slot with row j - PB
+          const int jr = j - PB;
+          const int jj = jr >= 0 ? jr : 0;
+          const int ue = unext[d];
+#pragma unroll
+          for (int t = 0; t <= K; ++t) {
+            double v = 0.0;
+            if (!SKIP || t <= ue) v = ld(Ub + tix(tile, nz, jj, K + 1, t, lane));
+            ur[d][t] = v;
+          }
+          if constexpr (SKIP) unext[d] = ue_p[pidx(max(jr - PB, 0))];
+          yin[d] = S(jj, fo);
+        }
       }
     }
   }

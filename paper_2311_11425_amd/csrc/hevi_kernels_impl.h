@@ -73,6 +73,11 @@ __global__ __launch_bounds__(64) void k_stage_solve(HeviShapeDev sh, double lamb
 // solution u (one array, used in place) in LDS instead of the global scratch.
 // The element chunks of the tile's cw wavefronts write and read the one r/u array;
 // the band solve runs in the first wavefront between the two barriers.
+// The band solve's form in the fused kernel (see band_solve): kChunkedPipe in chunked
+// launches (few tiles), kFusedPipe otherwise.
+constexpr int kChunkedPipe = 3;
+constexpr int kFusedPipe = 1;
+
 template <int N, bool TILT, bool CHUNKED, bool S3>
 __global__ __launch_bounds__(CHUNKED ? 64 * kMaxChunks : 64, kStreamWaves<N>) void k_stage_fused(
     HeviShapeDev sh, double lambda, const double* __restrict__ ops,
@@ -85,8 +90,8 @@ __global__ __launch_bounds__(CHUNKED ? 64 * kMaxChunks : 64, kStreamWaves<N>) vo
   b_stage_rhs<N, true, TILT, S3>(tile, sh, Gll<N>{}, lambda, ops, ws, E, Q, Qi, ru, cw);
   __syncthreads();
   if (threadIdx.x < T)
-    band_solve<N, double, true, HEVI_NWS, CHUNKED>(Ub, Lb, piv, plane_size(sh), ws, tile, sh.nz,
-                                                   (int)threadIdx.x, WS_R, WS_U, ru);
+    band_solve<N, double, true, HEVI_NWS, CHUNKED ? kChunkedPipe : kFusedPipe>(
+        Ub, Lb, piv, plane_size(sh), ws, tile, sh.nz, (int)threadIdx.x, WS_R, WS_U, ru);
   __syncthreads();
   b_stage_update<N, true, TILT, S3>(tile, sh, Gll<N>{}, lambda, ops, ws, Qi, info, ru, cw);
 }
