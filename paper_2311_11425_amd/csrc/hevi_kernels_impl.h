@@ -41,13 +41,12 @@ __global__ __launch_bounds__(64) void k_factor_lu_split(HeviShapeDev sh, const d
                                            piv, info);
 }
 
-template <int N, typename FT, bool S3>
+template <int N, typename FT, bool S3, int LPC = kSplitLanes<N>>
 __global__ __launch_bounds__(64) void k_factor_fused(HeviShapeDev sh, double lambda,
                                                      const double* __restrict__ ops,
                                                      FT* __restrict__ Ub, FT* __restrict__ Lb,
                                                      uint8_t* __restrict__ piv,
                                                      HeviDevInfo* info) {
-  constexpr int LPC = kSplitLanes<N>;
   __shared__ double lds[fused_lds_doubles<N>(LPC)];
   b_factor_fused_split<N, FT, LPC, S3>((int64_t)(blockIdx.x / LPC), (int)(blockIdx.x % LPC),
                                        sh, Gll<N>{}, lambda, ops, Ub, Lb, piv, info, lds);
@@ -144,8 +143,9 @@ hipError_t dispatch_NS(int N, A&&... a) {
 // tile is split into up to kMaxChunks wavefronts, never more than it has elements.
 // At 10,800 columns (169 tiles of 10 elements) one step took 0.957 ms with one
 // wavefront per tile, 0.726 ms with 4 and 0.675 ms with 8.
+constexpr int64_t kChunkTiles = 512;
 int chunks_for(const HeviShapeDev& sh) {
-  if (sh.ntiles >= 512) return 1;
+  if (sh.ntiles >= kChunkTiles) return 1;
   return sh.Ne < kMaxChunks ? sh.Ne : kMaxChunks;
 }
 
@@ -185,9 +185,21 @@ struct Factor {
                            (double*)Ub, (double*)Lb, piv, info);
     } else {
       // assembly and LU in one pass, the window split over kSplitLanes<N> lanes:
-      // kSplitLanes<N> workgroups per tile
+      // kSplitLanes<N> workgroups per tile.  A launch of few tiles (as the streaming
+      // kernels' chunking) splits the window over 4 lanes, for twice the wavefronts.
       (void)sbuf;
-      const dim3 g2((unsigned)(sh.ntiles * kSplitLanes<N>));
+      constexpr int L2 = kSplitLanes<N>;
+      if (L2 < 4 && sh.ntiles < kChunkTiles) {
+        const dim3 g4((unsigned)(sh.ntiles * 4));
+        if (fp32)
+          hipLaunchKernelGGL((k_factor_fused<N, float, S3, 4>), g4, dim3(T), 0, st, sh, lambda,
+                             ops, (float*)Ub, (float*)Lb, piv, info);
+        else
+          hipLaunchKernelGGL((k_factor_fused<N, double, S3, 4>), g4, dim3(T), 0, st, sh, lambda,
+                             ops, (double*)Ub, (double*)Lb, piv, info);
+        return hipGetLastError();
+      }
+      const dim3 g2((unsigned)(sh.ntiles * L2));
       if (fp32)
         hipLaunchKernelGGL((k_factor_fused<N, float, S3>), g2, dim3(T), 0, st, sh, lambda, ops,
                            (float*)Ub, (float*)Lb, piv, info);
