@@ -84,10 +84,18 @@ __device__ __forceinline__ double bcast(double v, int src) {
   return __hiloint2double(hi, lo);
 }
 
-// DPP move of a double within the wavefront (lanes whose source is invalid keep their own
-// value), and the maximum over all 64 lanes by an inclusive scan: row_shr:1,2,4,8 leave
-// each 16-lane row's maximum in its lane 15, row_bcast:15 and row_bcast:31 carry it into
-// the following rows, so lane 63 ends with the maximum of the wavefront.
+// DPP moves of a double within the wavefront: dpp_z fills lanes whose source is invalid
+// with zero (no copy of the old value needed), dpp_d keeps their own value.  The maximum
+// over all 64 lanes of values >= -1 whose maximum is >= 0 (magnitudes, with -1 marking
+// lanes out of the search) by an inclusive scan: row_shr:1,2,4,8 leave each 16-lane row's
+// maximum (or 0) in its lane 15, row_bcast:15 and row_bcast:31 carry it into the following
+// rows, so lane 63 ends with the maximum of the wavefront.
+template <int CTRL>
+__device__ __forceinline__ double dpp_z(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
 template <int CTRL, int ROWS>
 __device__ __forceinline__ double dpp_d(double v) {
   const int lo = __builtin_amdgcn_update_dpp(__double2loint(v), __double2loint(v), CTRL, ROWS,
@@ -97,10 +105,10 @@ __device__ __forceinline__ double dpp_d(double v) {
   return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ double wave_max(double v) {
-  v = fmax(v, dpp_d<0x111, 0xF>(v));
-  v = fmax(v, dpp_d<0x112, 0xF>(v));
-  v = fmax(v, dpp_d<0x114, 0xF>(v));
-  v = fmax(v, dpp_d<0x118, 0xF>(v));
+  v = fmax(v, dpp_z<0x111>(v));
+  v = fmax(v, dpp_z<0x112>(v));
+  v = fmax(v, dpp_z<0x114>(v));
+  v = fmax(v, dpp_z<0x118>(v));
   v = fmax(v, dpp_d<0x142, 0xA>(v));
   v = fmax(v, dpp_d<0x143, 0xC>(v));
   return bcast(v, 63);
