@@ -49,17 +49,11 @@ constexpr int kPsWS = (kPsW<N> + 15) / 16 * 16;
 template <int N>
 constexpr int kPsKLS = (kPsKL<N> + 15) / 16 * 16;
 
-// Whole-wavefront lane shifts by DPP (wave_shl:1 / wave_shr:1, a VALU move): lane i
-// takes lane i+1's value (shift_down1; lane 63 takes 0) or lane i-1's (shift_up1; lane 0
-// takes 0).
+// Whole-wavefront lane shift by DPP (wave_shl:1, a VALU move): lane i takes lane i+1's
+// value, lane 63 takes 0.
 __device__ __forceinline__ double shift_down1(double v) {
   const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x130, 0xF, 0xF, true);
   const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x130, 0xF, 0xF, true);
-  return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ double shift_up1(double v) {
-  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x138, 0xF, 0xF, true);
-  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x138, 0xF, 0xF, true);
   return __hiloint2double(hi, lo);
 }
 
