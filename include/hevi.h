@@ -173,8 +173,10 @@ hevi_status hevi_build_column_ops_set(hevi_ctx *ctx, const hevi_shape *shape,
  * nodes, as the rigid lid requires); the other inputs as hevi_build_column_ops.  The
  * rho-theta and momentum blocks of I - lambda L_z are then not identities, so these
  * operators factor the whole 5 n_z band with partial pivoting (the paper's LAPACK band
- * LU, Sec. 4.2.2; kl = ku = 5(N+1) - 1): hevi_factor / hevi_refactor store U (2 kl + 1
- * entries per row), the kl multipliers and the pivot offsets per column, FP64 only
+ * LU, Sec. 4.2.2; kl = ku = 5(N+1) - 1): hevi_factor / hevi_refactor store U by band
+ * columns (2 kl + 1 entries, padded to whole 128-byte lines), the kl multipliers of each
+ * step (padded likewise), and per unknown the pivot offset, row-scale exponent and the
+ * extents of U's column and L's row (at N = 4, n_z = 41: 158,260 bytes per column), FP64 only
  * (HEVI_FP32_REFINE gives HEVI_E_INVALID), N <= 5 and n_z <= 600 (else HEVI_E_SHAPE);
  * hevi_stage_solve solves directly (its refine argument is ignored), hevi_apply_op applies
  * L_z(q0).  hevi_factors_band_entries, hevi_solve_noalloc, groups and the server take
