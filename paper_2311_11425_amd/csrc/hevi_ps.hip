@@ -408,8 +408,17 @@ __global__ __launch_bounds__(64, kPsFactorWaves<N>) void k_ps_factor(HeviShapeDe
       uxr[j] = (uint8_t)max(xt, 0);
     }
     __syncthreads();
+    // the rank-1 update in tiers of 8 rows; the rows past the step's multiplier extent lx
+    // have zero multipliers (the update would leave them as they are) and are skipped
 #pragma unroll
-    for (int i = 1; i <= KL; ++i) a[i] = fma(-mb[i], a[0], a[i]);
+    for (int t = 0; 8 * t < KL; ++t) {
+      if (t > 0 && lx <= 8 * t) break;
+#pragma unroll
+      for (int q = 1; q <= 8; ++q) {
+        const int i = 8 * t + q;
+        if (i <= KL) a[i] = fma(-mb[i], a[0], a[i]);
+      }
+    }
     __syncthreads();  // mb is rewritten by the next step
     // next window: rows j+1..j+1+KL, columns j+1..j+W (lanes >= W hold zeros)
 #pragma unroll
