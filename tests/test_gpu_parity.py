@@ -276,6 +276,46 @@ def test_full_size_cfg2_sampled(ctx, prec):
     assert err < tol, err
 
 
+@pytest.mark.parametrize("N,Ne", [(2, 12), (6, 5)])
+def test_large_and_small_launch_same_bits(ctx, N, Ne):
+    """A launch of 516 tiles (the full-launch forms: one wavefront per tile, the band
+    solve's forward sweep pipelined, the factorisation window over kSplitLanes lanes) and a
+    launch of 2 tiles of some of its columns (the small-launch forms: element chunks, both
+    sweeps pipelined, a 4-lane window at N <= 4) give the same bits for those columns in
+    one ARK3 step; a few columns are checked against the oracle."""
+    from paper_2311_11425_amd.driver import ArkStepper, ColumnBatch
+    col = inputs.make_columns(N, Ne, 33000, profile="lapse", seed=61, surface_max=1200.0)
+    print(f"large/small launch N={N} Ne={Ne}", flush=True)
+    qn, qref = inputs.perturbed_state(col)
+    B = ColumnBatch(ctx, col)
+    st = ArkStepper(ctx, B, "ARK3", 300.0, precision=0)
+    out = B.empty_state()
+    for inf in st.step(dev(qn), dev(qref), out, info=True):
+        assert inf["status"] == "HEVI_OK", inf
+    big = host(out)
+    bigQ = [host(st.Q[i]) for i in range(1, 4)]
+    rng = np.random.default_rng(62)
+    idx = np.sort(np.concatenate([rng.choice(33000, 97, replace=False), [0, 32999, 64]]))
+    sc = sub_batch(col, idx)
+    Bs = ColumnBatch(ctx, sc)
+    ss = ArkStepper(ctx, Bs, "ARK3", 300.0, precision=0)
+    outs = Bs.empty_state()
+    for inf in ss.step(dev(sub_state(qn, idx)), dev(sub_state(qref, idx)), outs, info=True):
+        assert inf["status"] == "HEVI_OK", inf
+    assert np.array_equal(host(outs), big[..., idx])
+    for i in range(1, 4):
+        assert np.array_equal(host(ss.Q[i]), bigQ[i - 1][..., idx]), i
+    few = idx[:8]
+    sf = sub_batch(col, few)
+    qo_next, Qo, _ = oracle.ark_step_batch(sf, tableaux.as_float(tableaux.ark3()), 300.0,
+                                           sub_state(qn, few), sub_state(qref, few), refine=1,
+                                           want_stages=True)
+    qs = sub_state(qn, few)
+    tol = step_tolerance(oracle, sf, tableaux.as_float(tableaux.ark3()), 300.0, qs,
+                         sub_state(qref, few), Qo, TOL64)
+    assert relerr_cols(big[..., few] - qs, qo_next - qs) < tol
+
+
 def test_single_element_single_order(ctx):
     """N = 1, one element: both nodes are rigid-lid nodes, u = 0, x = P(b)."""
     col = inputs.make_columns(1, 1, 3, profile="isothermal", seed=41)
